@@ -1,0 +1,348 @@
+"""Seeded synthetic aerial bundle-adjustment scenes.
+
+This is the input generator shared by the tests, the benchmark and the smoke
+check.  It flies a block of nadir images over Gaussian-hill terrain, spawns tie
+points in 150x150 px image cells (the patch grid of Sec. 3.1), observes them in
+the overlapping images of the cluster (including images of the adjacent strip,
+Sec. 3.1 / 3.2), adds pixel noise and wrong-match outliers, and perturbs the
+poses into a GNSS/IMU-like initialisation that also serves as pose prior
+(Sec. 3.2: initial T_k^(0), R_k^(0) from navigation data).
+
+It holds only the data-generating process: a forward camera model to synthesise
+measurements and a ray/terrain intersection to place points.  Nothing here
+evaluates residuals, Jacobians or any part of the adjustment.
+
+Conventions (shared by every consumer of a scene):
+  * R[k] is camera->world (columns are the camera x, y, z axes in the world
+    frame), T[k] is the projection centre, so a world point X is seen at
+    X_c = R[k]^T (X - T[k]), with z forward and the image y axis down.
+  * obs_uv are pixel coordinates with the origin at the image corner; the
+    principal point is (cx, cy).
+  * World frame: local ENU metres.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Camera of the workload: 50 MP, 8000 x 6000 px, 3.76 um pixels, f = 50 mm.
+IMG_W = 8000
+IMG_H = 6000
+PIXEL_M = 3.76e-6
+FOCAL_M = 0.050
+F_PX = FOCAL_M / PIXEL_M            # 13297.87 px
+CX = IMG_W / 2.0
+CY = IMG_H / 2.0
+ALTITUDE = 300.0
+CELL_PX = 150                       # patch cell size used to spawn tie points
+FWD_OVERLAP = 0.80
+SIDE_OVERLAP = 0.60
+DEG = math.pi / 180.0
+
+GSD = ALTITUDE / F_PX
+FOOT_ALONG = IMG_H * GSD            # image y axis is the along-track axis
+FOOT_ACROSS = IMG_W * GSD
+BASE = (1.0 - FWD_OVERLAP) * FOOT_ALONG
+STRIP_SPACING = (1.0 - SIDE_OVERLAP) * FOOT_ACROSS
+
+R_NADIR = np.array([[1.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, -1.0]])
+
+
+@dataclasses.dataclass
+class SceneSpec:
+    n_strips: int = 2
+    imgs_per_strip: int = 3
+    n_points: int = 2000
+    # observations per point: ("geom", mean) = 1 + geometric extra observers
+    # with the given mean total; ("tgeom", p, lo, hi) = truncated geometric.
+    obs_model: tuple = ("geom", 3.0)
+    noise_px: float = 0.5
+    outlier_frac: float = 0.03
+    outlier_px: float = 75.0
+    k_true: tuple = (0.0, 0.0)
+    k_init: tuple = (0.0, 0.0)
+    intr_mask: int = 0
+    pos_noise_m: float = 0.5
+    att_noise_deg: float = 0.05
+    point_noise_m: float = 1.0
+    prior_sigma_T: float = 0.5
+    prior_sigma_w_deg: float = 0.05
+    priors: bool = True
+    priors_at_truth: bool = False
+    n_fixed: int = 0
+    sigma_px: float = 0.5
+    huber_delta_px: float = 1.0
+    jitter_deg: float = 1.0
+    n_hills: int = 8
+    first_strip: int = 0
+
+
+def rotvec_to_matrix(w: np.ndarray) -> np.ndarray:
+    """Rotation matrices for rotation vectors w[..., 3] (Rodrigues)."""
+    w = np.asarray(w, dtype=np.float64)
+    th = np.linalg.norm(w, axis=-1, keepdims=True)
+    small = th < 1e-12
+    k = np.where(small, 0.0, w / np.where(small, 1.0, th))
+    K = np.zeros(w.shape[:-1] + (3, 3))
+    K[..., 0, 1], K[..., 0, 2] = -k[..., 2], k[..., 1]
+    K[..., 1, 0], K[..., 1, 2] = k[..., 2], -k[..., 0]
+    K[..., 2, 0], K[..., 2, 1] = -k[..., 1], k[..., 0]
+    th = th[..., None]
+    eye = np.broadcast_to(np.eye(3), K.shape)
+    return eye + np.sin(th) * K + (1.0 - np.cos(th)) * (K @ K)
+
+
+def heading_matrix(psi: float) -> np.ndarray:
+    c, s = math.cos(psi), math.sin(psi)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+class Terrain:
+    """Sum of Gaussian hills: z = sum_i a_i exp(-|xy - c_i|^2 / (2 s_i^2))."""
+
+    def __init__(self, rng: np.random.Generator, lo: np.ndarray, hi: np.ndarray, n: int):
+        self.a = rng.uniform(0.0, 50.0, n)
+        self.s = rng.uniform(50.0, 250.0, n)
+        self.c = rng.uniform(lo, hi, (n, 2))
+
+    def height(self, xy: np.ndarray) -> np.ndarray:
+        d2 = ((xy[:, None, :] - self.c[None, :, :]) ** 2).sum(-1)
+        return (self.a[None, :] * np.exp(-d2 / (2.0 * self.s[None, :] ** 2))).sum(-1)
+
+    def intersect(self, origin: np.ndarray, direction: np.ndarray) -> np.ndarray:
+        """Ray/terrain intersection by fixed-point iteration on the height."""
+        z = np.zeros(origin.shape[0])
+        for _ in range(200):
+            t = (z - origin[:, 2]) / direction[:, 2]
+            p = origin + t[:, None] * direction
+            z_new = self.height(p[:, :2])
+            if np.max(np.abs(z_new - z)) < 1e-9:
+                z = z_new
+                break
+            z = z_new
+        t = (z - origin[:, 2]) / direction[:, 2]
+        return origin + t[:, None] * direction
+
+
+def _distort(a, b, k1, k2):
+    r2 = a * a + b * b
+    d = 1.0 + k1 * r2 + k2 * r2 * r2
+    return a * d, b * d
+
+
+def synth_project(R, T, X, k1, k2):
+    """Data-generating camera: pixel coordinates of X (N,3) in cameras (R,T).
+
+    R: (C,3,3), T: (C,3); returns uv (N,C,2) and depth z (N,C).
+    """
+    d = X[:, None, :] - T[None, :, :]
+    xc = np.einsum("cji,ncj->nci", R, d)
+    z = xc[..., 2]
+    zs = np.where(np.abs(z) < 1e-9, 1e-9, z)
+    a, b = xc[..., 0] / zs, xc[..., 1] / zs
+    ad, bd = _distort(a, b, k1, k2)
+    uv = np.stack([F_PX * ad + CX, F_PX * bd + CY], axis=-1)
+    return uv, z
+
+
+def _undistort(ad, bd, k1, k2):
+    a, b = ad.copy(), bd.copy()
+    for _ in range(20):
+        r2 = a * a + b * b
+        d = 1.0 + k1 * r2 + k2 * r2 * r2
+        a, b = ad / d, bd / d
+    return a, b
+
+
+def flight_poses(spec: SceneSpec, rng: np.random.Generator):
+    """Truth poses of a boustrophedon block, in flight order (strip-major)."""
+    R, T, strip = [], [], []
+    for s in range(spec.n_strips):
+        gs = spec.first_strip + s
+        north = gs % 2 == 0
+        psi = 0.0 if north else math.pi
+        for i in range(spec.imgs_per_strip):
+            y = i * BASE if north else (spec.imgs_per_strip - 1 - i) * BASE
+            T.append([gs * STRIP_SPACING, y, ALTITUDE])
+            jit = rng.normal(0.0, spec.jitter_deg * DEG, 3)
+            R.append(heading_matrix(psi) @ R_NADIR @ rotvec_to_matrix(jit))
+            strip.append(gs)
+    return np.array(R), np.array(T), np.array(strip, dtype=np.int32)
+
+
+def _n_observers(spec: SceneSpec, rng: np.random.Generator, n: int) -> np.ndarray:
+    kind = spec.obs_model[0]
+    if kind == "geom":
+        mean_total = spec.obs_model[1]
+        p = 1.0 / max(mean_total - 1.0, 1e-9)
+        return 1 + rng.geometric(min(p, 1.0), n)
+    if kind == "tgeom":
+        p, lo, hi = spec.obs_model[1], spec.obs_model[2], spec.obs_model[3]
+        ks = np.arange(lo, hi + 1)
+        pk = p * (1.0 - p) ** (ks - lo)
+        pk /= pk.sum()
+        return rng.choice(ks, size=n, p=pk)
+    if kind == "all":
+        return np.full(n, 1 << 30)
+    raise ValueError(kind)
+
+
+def make_scene(spec: SceneSpec, seed: int) -> dict:
+    """Generate one cluster.  Returns a dict of C-contiguous numpy arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R_t, T_t, strip = flight_poses(spec, rng)
+    C = R_t.shape[0]
+    lo = T_t[:, :2].min(0) - np.array([FOOT_ACROSS, FOOT_ALONG])
+    hi = T_t[:, :2].max(0) + np.array([FOOT_ACROSS, FOOT_ALONG])
+    terrain = Terrain(rng, lo, hi, spec.n_hills)
+    k1t, k2t = spec.k_true
+    ncx, ncy = IMG_W // CELL_PX, IMG_H // CELL_PX
+
+    X_list, obs_list = [], []
+    have = 0
+    guard = 0
+    while have < spec.n_points:
+        guard += 1
+        if guard > 200:
+            raise RuntimeError("scene generator could not place enough points")
+        B = max(1024, int(1.6 * (spec.n_points - have)))
+        img = rng.integers(0, C, B)
+        cu = rng.integers(0, ncx, B)
+        cv = rng.integers(0, ncy, B)
+        u = (cu + rng.uniform(0, 1, B)) * CELL_PX
+        v = (cv + rng.uniform(0, 1, B)) * CELL_PX
+        a, b = _undistort((u - CX) / F_PX, (v - CY) / F_PX, k1t, k2t)
+        dirc = np.stack([a, b, np.ones(B)], -1)
+        dirw = np.einsum("nij,nj->ni", R_t[img], dirc)
+        X = terrain.intersect(T_t[img], dirw)
+        uv, z = synth_project(R_t, T_t, X, k1t, k2t)
+        vis = (z > 1.0) & (uv[..., 0] >= 0) & (uv[..., 0] < IMG_W) & (uv[..., 1] >= 0) & (uv[..., 1] < IMG_H)
+        vis[np.arange(B), img] = False
+        want = _n_observers(spec, rng, B) - 1
+        score = rng.uniform(0, 1, (B, C))
+        score[~vis] = np.inf
+        order = np.argsort(score, axis=1)
+        n_extra = np.minimum(want, vis.sum(1))
+        keep = n_extra >= 1
+        for i in np.nonzero(keep)[0]:
+            if have >= spec.n_points:
+                break
+            cams = np.concatenate([[img[i]], order[i, : n_extra[i]]])
+            X_list.append(X[i])
+            obs_list.append((have, np.sort(cams), uv[i, np.sort(cams)]))
+            have += 1
+
+    X_true = np.array(X_list)
+    obs_cam = np.concatenate([o[1] for o in obs_list]).astype(np.int32)
+    obs_pt = np.concatenate([np.full(len(o[1]), o[0]) for o in obs_list]).astype(np.int32)
+    uv_true = np.concatenate([o[2] for o in obs_list])
+    O = obs_cam.shape[0]
+
+    uv = uv_true + rng.normal(0.0, spec.noise_px, (O, 2))
+    n_out = int(round(spec.outlier_frac * O))
+    out_idx = rng.choice(O, n_out, replace=False) if n_out > 0 else np.zeros(0, np.int64)
+    uv[out_idx] = uv_true[out_idx] + rng.uniform(-spec.outlier_px, spec.outlier_px, (n_out, 2))
+
+    perm = rng.permutation(O)
+    obs_cam, obs_pt, uv = obs_cam[perm], obs_pt[perm], uv[perm]
+    is_outlier = np.zeros(O, dtype=bool)
+    is_outlier[out_idx] = True
+    is_outlier = is_outlier[perm]
+
+    R0 = np.einsum("cij,cjk->cik", R_t, rotvec_to_matrix(rng.normal(0.0, spec.att_noise_deg * DEG, (C, 3))))
+    T0 = T_t + rng.normal(0.0, spec.pos_noise_m, (C, 3))
+    X0 = X_true + rng.normal(0.0, spec.point_noise_m, X_true.shape)
+
+    if spec.priors_at_truth:
+        pR, pT = R_t.copy(), T_t.copy()
+    else:
+        pR, pT = R0.copy(), T0.copy()
+    sig = np.zeros((C, 6))
+    if spec.priors:
+        sig[:, :3] = spec.prior_sigma_w_deg * DEG
+        sig[:, 3:] = spec.prior_sigma_T
+    fixed = np.zeros(C, dtype=np.uint8)
+    fixed[: spec.n_fixed] = 1
+
+    c = lambda x, dt=np.float64: np.ascontiguousarray(x, dtype=dt)
+    return {
+        "n_cams": C,
+        "n_points": int(X0.shape[0]),
+        "n_obs": int(O),
+        "R": c(R0),
+        "T": c(T0),
+        "X": c(X0),
+        "k": c(spec.k_init),
+        "prior_R": c(pR),
+        "prior_T": c(pT),
+        "prior_sigma": c(sig),
+        "fixed": c(fixed, np.uint8),
+        "obs_cam": c(obs_cam, np.int32),
+        "obs_pt": c(obs_pt, np.int32),
+        "obs_uv": c(uv),
+        "f": F_PX,
+        "cx": CX,
+        "cy": CY,
+        "intr_mask": int(spec.intr_mask),
+        "sigma_px": float(spec.sigma_px),
+        "huber_delta": float(spec.huber_delta_px),
+        "truth": {
+            "R": c(R_t),
+            "T": c(T_t),
+            "X": c(X_true),
+            "k": c(spec.k_true),
+            "strip": strip,
+            "outlier": is_outlier,
+        },
+    }
+
+
+# ---------------------------------------------------------------------------
+# Workload presets.  Sizes follow the workloads the method is evaluated on.
+
+def spec_tiny() -> SceneSpec:
+    """6 cameras (2 strips x 3), 2,000 points, every image that sees a point
+    observes it (~3.1 observations per point, ~6,200 observations)."""
+    return SceneSpec(n_strips=2, imgs_per_strip=3, n_points=2000, obs_model=("all",))
+
+
+def spec_cluster12() -> SceneSpec:
+    """Paper-scale local cluster: 12 cameras (2 strips x 6), ~20k points,
+    ~85k observations (every image that sees a point observes it), k1/k2
+    radial distortion estimated (truth -0.05, 0.02)."""
+    return SceneSpec(n_strips=2, imgs_per_strip=6, n_points=20000, obs_model=("all",),
+                     k_true=(-0.05, 0.02), k_init=(0.0, 0.0), intr_mask=3)
+
+
+def spec_batched(seed: int) -> SceneSpec:
+    """One cluster of the uneven batch: 6-24 cameras in 2-3 strips, points
+    log-uniform in [5k, 60k], 2-6 observations per point (geometric, p=0.5),
+    5% outliers, pinhole."""
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0x5EED))
+    C = int(rng.integers(6, 25))
+    n_strips = 2 if C < 12 else 3
+    per = int(math.ceil(C / n_strips))
+    P = int(round(math.exp(rng.uniform(math.log(5000), math.log(60000)))))
+    return SceneSpec(n_strips=n_strips, imgs_per_strip=per, n_points=P,
+                     obs_model=("tgeom", 0.5, 2, 6), outlier_frac=0.05)
+
+
+def spec_micro(n_strips=2, imgs_per_strip=2, n_points=40, **kw) -> SceneSpec:
+    """Small scenes for brute-force checks."""
+    kw.setdefault("obs_model", ("geom", 3.0))
+    return SceneSpec(n_strips=n_strips, imgs_per_strip=imgs_per_strip, n_points=n_points, **kw)
+
+
+def scene_tiny(seed: int = 1) -> dict:
+    return make_scene(spec_tiny(), seed)
+
+
+def scene_cluster12(seed: int = 2) -> dict:
+    return make_scene(spec_cluster12(), seed)
+
+
+def scene_batched(index: int) -> dict:
+    seed = 4_000_000 + index
+    return make_scene(spec_batched(seed), seed)
