@@ -1,0 +1,200 @@
+/*
+ * ba.h -- C ABI of the MI355X (gfx950) cluster bundle-adjustment library.
+ *
+ * The library minimises, for one cluster C_l of overlapping images at a time
+ * (Sec. 3.2 of "Real-Time Bundle Adjustment for Ultra-High-Resolution UAV
+ * Imagery Using Adaptive Patch-Based Feature Tracking"), the robust
+ * reprojection cost of Eq. (7)
+ *
+ *     E = 1/2 sum_{k in C_l} sum_{j in J_k} rho( |p_kj - pi(K R_k^T (X_j - T_k))|^2 / sigma^2 )
+ *       + 1/2 sum_{free k} ( |Log(R_prior,k^T R_k)|^2_{sigma_omega} + |T_k - T_prior,k|^2_{sigma_T} )
+ *
+ * with the pinhole projection of Eq. (5) extended by Brown radial terms
+ * k1, k2 on the normalised coordinates, rho the Huber function on the squared
+ * whitened residual norm, and pose priors at the GNSS/IMU-derived initial
+ * poses T_k^(0), R_k^(0) (Sec. 3.2).  Images marked fixed keep their pose
+ * (the first half of the inter-cluster overlap, Sec. 3.2).  The minimiser is
+ * Levenberg-Marquardt: IRLS Gauss-Newton normal equations, Marquardt diagonal
+ * scaling D = clamp(diag H, 1e-6, 1e32), Nielsen's damping update, the damped
+ * system solved by eliminating the points (Schur complement), a Cholesky
+ * factorisation of the reduced camera system in FP64 and point
+ * back-substitution.  All of it runs in HIP kernels on the GPU.
+ *
+ * Conventions
+ *   R_k  camera->world rotation, row-major 3x3 (columns = camera axes in the
+ *        world frame); T_k projection centre.  X_c = R_k^T (X_j - T_k), camera
+ *        z forward, image y down (Eq. 3/5: pi(x, y, z) = (x/z, y/z)).
+ *   obs_uv pixel coordinates, origin at the image corner; principal point
+ *        (cx, cy); focal length f in pixels.
+ *   Rotation update R <- R Exp(d_omega) (right perturbation).
+ *   Any consistent metric world frame (ENU, ECEF); the library shifts all
+ *   coordinates by the mean camera centre internally, in FP64.
+ *
+ * Memory and threads
+ *   Every array passed in is a HOST pointer owned by the caller and is only
+ *   read during the call (submit copies what it needs).  Every output buffer
+ *   is caller-allocated host memory.  The library owns all device memory: one
+ *   arena of hbm_budget_bytes allocated by ba_create, from which each admitted
+ *   cluster takes one block, freed when the cluster is released.
+ *   All functions are thread-safe.  With serve = 1 a runtime thread inside
+ *   the context runs the continuous-batching loop (ba_solve/ba_wait).
+ *   Functions return BA_OK (0) or a negative ba_error; nothing is thrown or
+ *   aborted across the ABI.  ba_last_error gives a message for the last
+ *   failure of the context.
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_ctx ba_ctx;
+typedef int64_t ba_ticket;
+
+enum ba_error {
+  BA_OK = 0,
+  BA_E_ARG = -1,      /* invalid argument: bad index, non-finite value, size limit */
+  BA_E_NOMEM = -2,    /* the cluster can never fit the arena, or device allocation failed */
+  BA_E_AGAIN = -3,    /* queue full, or (ba_step) no slot/memory free right now: retry */
+  BA_E_STATE = -4,    /* operation not valid in the ticket's current state */
+  BA_E_DEVICE = -5,   /* HIP runtime error; the context is unusable afterwards */
+  BA_E_TIMEOUT = -7   /* ba_wait timed out */
+};
+
+enum ba_precision {
+  BA_FP64 = 0,   /* plain: residuals, Jacobians, Schur assembly and solve in FP64 */
+  BA_MIXED = 1   /* residuals, Jacobians, Schur assembly in FP32 (FP32 accumulation);
+                    reduced-system Cholesky, one refinement step of the camera
+                    update, cost reductions and gain ratio in FP64 */
+};
+
+enum ba_solve_status {
+  BA_ST_QUEUED = 0,     /* waiting for a slot / arena memory */
+  BA_ST_RUNNING = 1,    /* admitted, iterations in progress */
+  BA_ST_MAXITER = 2,    /* ran max_iters iterations */
+  BA_ST_CONVERGED = 3,  /* an accepted step decreased E by less than ftol * E */
+  BA_ST_STALLED = 4,    /* damping exceeded 1e32 after rejected steps */
+  BA_ST_BAD_INIT = 5    /* the initial state has a point at non-positive depth */
+};
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal */
+  void* stream;              /* hipStream_t to run on (e.g. torch.cuda.current_stream().cuda_stream);
+                                NULL: the context creates its own stream */
+  size_t hbm_budget_bytes;   /* arena size for cluster state; 0 -> 1 GiB */
+  int32_t max_slots;         /* clusters resident on the device at once; 0 -> 256 */
+  int32_t max_queue;         /* submitted clusters waiting for admission; 0 -> 4096 */
+  int32_t precision;         /* enum ba_precision */
+  int32_t serve;             /* 1: start the continuous-batching runtime thread */
+  int32_t iters_per_tick;    /* LM iterations per serving tick; 0 -> 2 */
+  int32_t chunks_per_wg;     /* 64-observation chunks per workgroup in the assembly
+                                kernels; 0 -> 16 */
+} ba_options;
+
+/* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */
+typedef struct {
+  int32_t n_cams, n_points, n_obs;
+  int32_t intr_mask;            /* bit 0: estimate k1, bit 1: estimate k2 */
+  const double* R;              /* [9C] initial rotations, camera->world, row-major */
+  const double* T;              /* [3C] initial projection centres */
+  const double* X;              /* [3P] initial tie points */
+  const double* k;              /* [2]  initial k1, k2 */
+  const double* prior_R;        /* [9C] GNSS/IMU attitude prior */
+  const double* prior_T;        /* [3C] GNSS/IMU position prior */
+  const double* prior_sigma;    /* [6C] sigma_omega[3] (rad), sigma_T[3] (m); a component
+                                   with sigma <= 0 or non-finite is switched off */
+  const uint8_t* fixed;         /* [C] 1: pose held constant (no unknowns, no prior) */
+  const int32_t* obs_cam;       /* [O] camera index of each observation */
+  const int32_t* obs_pt;        /* [O] point index of each observation */
+  const double* obs_uv;         /* [2O] observed pixel (u, v) */
+  double f, cx, cy;             /* focal length and principal point, pixels */
+  double sigma_px;              /* observation standard deviation, pixels (> 0) */
+  double huber_delta;           /* Huber threshold on |e|, pixels (> 0) */
+  int32_t max_iters;            /* LM iterations (1..4096) */
+  int32_t stop_on_ftol;         /* 1: stop when an accepted step has (E - E') < ftol E */
+  double lambda0;               /* initial damping (clamped to [1e-16, 1e32]) */
+  double ftol;
+} ba_cluster;
+
+/* Results (ba_fetch).  Every pointer may be NULL (not written). */
+typedef struct {
+  double* R;                    /* [9C] */
+  double* T;                    /* [3C] */
+  double* X;                    /* [3P] */
+  double* k;                    /* [2]  */
+  double* cost_log;             /* [max_iters + 1]: E before the first iteration and after each */
+  int32_t status;               /* enum ba_solve_status */
+  int32_t iterations, accepted, rejected;
+  double lambda;                /* damping after the last iteration */
+  double initial_cost, final_cost;
+  double t_submit, t_admit, t_done;   /* seconds on the library's steady clock */
+} ba_result;
+
+/* Limits enforced by ba_submit_cluster (BA_E_ARG beyond them). */
+#define BA_MAX_FREE_CAMS 24     /* free cameras per cluster (reduced system <= 146) */
+#define BA_MAX_CAMS 64          /* cameras per cluster, fixed ones included */
+#define BA_MAX_OBS_PER_POINT 64 /* a point's observations share one 64-lane wavefront */
+
+/* Create a context on options->device.  Allocates the arena.
+ * Errors: BA_E_ARG (bad options), BA_E_NOMEM, BA_E_DEVICE. */
+int ba_create(const ba_options* options, ba_ctx** out);
+
+/* Stop the runtime thread, free all device memory and the context. */
+int ba_destroy(ba_ctx* ctx);
+
+/* Validate and copy one cluster (Eq. 7 problem data, Sec. 3.2), admit it to a
+ * device slot if a slot and arena memory are free, else queue it.  Checks:
+ * indices in range, finite inputs, 1..64 observations per observed point,
+ * no camera twice on one point, <= BA_MAX_FREE_CAMS free cameras.
+ * Errors: BA_E_ARG, BA_E_NOMEM (larger than the whole arena), BA_E_AGAIN
+ * (queue full), BA_E_DEVICE. */
+int ba_submit_cluster(ba_ctx* ctx, const ba_cluster* cluster, ba_ticket* ticket);
+
+/* Run up to n_iters LM iterations of one cluster now, on the calling thread,
+ * reading the LM status back after every iteration (the plain, host-driven
+ * loop).  Admits the cluster first if it is still queued.
+ * Errors: BA_E_ARG (unknown ticket), BA_E_AGAIN (no slot or memory free),
+ * BA_E_STATE (the cluster is owned by the serving loop), BA_E_DEVICE. */
+int ba_step(ba_ctx* ctx, ba_ticket ticket, int32_t n_iters);
+
+/* Solve the given clusters together to termination on the calling thread:
+ * every LM iteration of every cluster is one batched launch series, with LM
+ * control on the device (no host round trip per iteration).  All tickets must
+ * be admitted or admissible at once.  Errors as ba_step. */
+int ba_solve_batch(ba_ctx* ctx, const ba_ticket* tickets, int32_t n);
+
+/* Hand the cluster to the continuous-batching loop (context created with
+ * serve = 1): it is admitted when a slot and memory free up, iterated with
+ * the other resident clusters, and retired on termination.  Returns at once.
+ * Errors: BA_E_ARG, BA_E_STATE (no serving loop, or already solving). */
+int ba_solve(ba_ctx* ctx, ba_ticket ticket);
+
+/* Wait until a cluster handed to ba_solve has terminated.  timeout_s < 0
+ * waits forever.  Errors: BA_E_ARG, BA_E_STATE, BA_E_TIMEOUT. */
+int ba_wait(ba_ctx* ctx, ba_ticket ticket, double timeout_s);
+
+/* Copy the cluster's current (or final) state and statistics into result
+ * (origin shift undone in FP64 on the device).  Errors: BA_E_ARG,
+ * BA_E_STATE (still queued or being solved by the serving loop), BA_E_DEVICE. */
+int ba_fetch(ba_ctx* ctx, ba_ticket ticket, ba_result* result);
+
+/* Forget a ticket and free its slot and arena block.  Errors: BA_E_ARG,
+ * BA_E_STATE (being solved by the serving loop). */
+int ba_release(ba_ctx* ctx, ba_ticket ticket);
+
+/* Bytes of arena the cluster would take once admitted (its admission
+ * footprint), or 0 if the cluster is invalid. */
+size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
+
+const char* ba_strerror(int code);
+const char* ba_last_error(ba_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BA_H */

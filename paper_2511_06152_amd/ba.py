@@ -1,0 +1,200 @@
+"""ctypes binding of libba.so (include/ba.h), with the same names.
+
+Argument marshalling only: every step of the adjustment runs in the HIP
+kernels of libba.so.  Loading fails loudly when the library has not been
+built (paper_2511_06152_amd/build.py) or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libba.so")
+
+BA_OK, BA_E_ARG, BA_E_NOMEM, BA_E_AGAIN, BA_E_STATE, BA_E_DEVICE, BA_E_TIMEOUT = 0, -1, -2, -3, -4, -5, -7
+BA_FP64, BA_MIXED = 0, 1
+BA_ST_QUEUED, BA_ST_RUNNING, BA_ST_MAXITER, BA_ST_CONVERGED, BA_ST_STALLED, BA_ST_BAD_INIT = range(6)
+BA_MAX_FREE_CAMS = 24
+BA_MAX_CAMS = 64
+BA_MAX_OBS_PER_POINT = 64
+
+EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
+            "ba_fetch", "ba_release", "ba_footprint", "ba_strerror", "ba_last_error"]
+
+
+class ba_options(ct.Structure):
+    _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("hbm_budget_bytes", ct.c_size_t),
+                ("max_slots", ct.c_int32), ("max_queue", ct.c_int32), ("precision", ct.c_int32),
+                ("serve", ct.c_int32), ("iters_per_tick", ct.c_int32), ("chunks_per_wg", ct.c_int32)]
+
+
+class ba_cluster(ct.Structure):
+    _fields_ = [("n_cams", ct.c_int32), ("n_points", ct.c_int32), ("n_obs", ct.c_int32), ("intr_mask", ct.c_int32),
+                ("R", ct.c_void_p), ("T", ct.c_void_p), ("X", ct.c_void_p), ("k", ct.c_void_p),
+                ("prior_R", ct.c_void_p), ("prior_T", ct.c_void_p), ("prior_sigma", ct.c_void_p),
+                ("fixed", ct.c_void_p), ("obs_cam", ct.c_void_p), ("obs_pt", ct.c_void_p), ("obs_uv", ct.c_void_p),
+                ("f", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double),
+                ("sigma_px", ct.c_double), ("huber_delta", ct.c_double),
+                ("max_iters", ct.c_int32), ("stop_on_ftol", ct.c_int32),
+                ("lambda0", ct.c_double), ("ftol", ct.c_double)]
+
+
+class ba_result(ct.Structure):
+    _fields_ = [("R", ct.c_void_p), ("T", ct.c_void_p), ("X", ct.c_void_p), ("k", ct.c_void_p),
+                ("cost_log", ct.c_void_p), ("status", ct.c_int32), ("iterations", ct.c_int32),
+                ("accepted", ct.c_int32), ("rejected", ct.c_int32), ("lambda_", ct.c_double),
+                ("initial_cost", ct.c_double), ("final_cost", ct.c_double),
+                ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libba.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libba.so not built ({path}); run paper_2511_06152_amd/build.py")
+    L = ct.CDLL(path)
+    P = ct.c_void_p
+    L.ba_create.argtypes = [ct.POINTER(ba_options), ct.POINTER(P)]
+    L.ba_destroy.argtypes = [P]
+    L.ba_submit_cluster.argtypes = [P, ct.POINTER(ba_cluster), ct.POINTER(ct.c_int64)]
+    L.ba_step.argtypes = [P, ct.c_int64, ct.c_int32]
+    L.ba_solve_batch.argtypes = [P, ct.POINTER(ct.c_int64), ct.c_int32]
+    L.ba_solve.argtypes = [P, ct.c_int64]
+    L.ba_wait.argtypes = [P, ct.c_int64, ct.c_double]
+    L.ba_fetch.argtypes = [P, ct.c_int64, ct.POINTER(ba_result)]
+    L.ba_release.argtypes = [P, ct.c_int64]
+    L.ba_footprint.argtypes = [P, ct.POINTER(ba_cluster)]
+    L.ba_footprint.restype = ct.c_size_t
+    L.ba_strerror.argtypes = [ct.c_int]
+    L.ba_strerror.restype = ct.c_char_p
+    L.ba_last_error.argtypes = [P]
+    L.ba_last_error.restype = ct.c_char_p
+    for name in EXPORTED:
+        if name not in ("ba_footprint", "ba_strerror", "ba_last_error"):
+            getattr(L, name).restype = ct.c_int
+    _lib = L
+    return L
+
+
+class BAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+class Cluster:
+    """Marshals a scene dict into a ba_cluster, keeping the arrays alive."""
+
+    def __init__(self, sc: dict, max_iters: int = 10, lambda0: float = 1e-4, ftol: float = 1e-10,
+                 stop_on_ftol: bool = False):
+        C, P, O = int(sc["n_cams"]), int(sc["n_points"]), int(sc["n_obs"])
+        f64 = lambda x: np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1))
+        self.arrays = {
+            "R": f64(sc["R"]), "T": f64(sc["T"]), "X": f64(sc["X"]) if P else np.zeros(3),
+            "k": f64(sc["k"]), "prior_R": f64(sc["prior_R"]), "prior_T": f64(sc["prior_T"]),
+            "prior_sigma": f64(sc["prior_sigma"]),
+            "fixed": np.ascontiguousarray(np.asarray(sc["fixed"], np.uint8).reshape(-1)),
+            "obs_cam": np.ascontiguousarray(np.asarray(sc["obs_cam"], np.int32).reshape(-1)),
+            "obs_pt": np.ascontiguousarray(np.asarray(sc["obs_pt"], np.int32).reshape(-1)),
+            "obs_uv": f64(sc["obs_uv"]) if O else np.zeros(2),
+        }
+        a = self.arrays
+        self.C, self.P, self.O, self.max_iters = C, P, O, max_iters
+        self.c = ba_cluster(C, P, O, int(sc["intr_mask"]),
+                            _p(a["R"]), _p(a["T"]), _p(a["X"]), _p(a["k"]), _p(a["prior_R"]), _p(a["prior_T"]),
+                            _p(a["prior_sigma"]), _p(a["fixed"]), _p(a["obs_cam"]), _p(a["obs_pt"]), _p(a["obs_uv"]),
+                            float(sc["f"]), float(sc["cx"]), float(sc["cy"]), float(sc["sigma_px"]),
+                            float(sc["huber_delta"]), int(max_iters), 1 if stop_on_ftol else 0,
+                            float(lambda0), float(ftol))
+
+
+class Context:
+    """Owns a ba_ctx.  Methods mirror the C ABI and raise BAError on failure."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256,
+                 max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
+                 chunks_per_wg: int = 16):
+        self.lib = load()
+        opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
+                         iters_per_tick, chunks_per_wg)
+        h = ct.c_void_p()
+        rc = self.lib.ba_create(ct.byref(opt), ct.byref(h))
+        if rc != BA_OK:
+            raise BAError(rc, "ba_create failed: " + self.lib.ba_strerror(rc).decode())
+        self.h = h
+        self.meta = {}
+
+    def _chk(self, rc, what):
+        if rc != BA_OK:
+            raise BAError(rc, f"{what}: {self.lib.ba_strerror(rc).decode()}: {self.lib.ba_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ba_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def ba_submit_cluster(self, cl: Cluster) -> int:
+        t = ct.c_int64()
+        self._chk(self.lib.ba_submit_cluster(self.h, ct.byref(cl.c), ct.byref(t)), "ba_submit_cluster")
+        self.meta[t.value] = (cl.C, cl.P, cl.max_iters)
+        return t.value
+
+    def submit(self, sc: dict, **kw) -> int:
+        return self.ba_submit_cluster(Cluster(sc, **kw))
+
+    def ba_footprint(self, cl: Cluster) -> int:
+        return int(self.lib.ba_footprint(self.h, ct.byref(cl.c)))
+
+    def ba_step(self, t: int, n_iters: int):
+        return self._chk(self.lib.ba_step(self.h, t, n_iters), "ba_step")
+
+    def ba_solve_batch(self, tickets):
+        arr = (ct.c_int64 * len(tickets))(*tickets)
+        return self._chk(self.lib.ba_solve_batch(self.h, arr, len(tickets)), "ba_solve_batch")
+
+    def ba_solve(self, t: int):
+        return self._chk(self.lib.ba_solve(self.h, t), "ba_solve")
+
+    def ba_wait(self, t: int, timeout_s: float = -1.0):
+        return self._chk(self.lib.ba_wait(self.h, t, timeout_s), "ba_wait")
+
+    def ba_release(self, t: int):
+        self.meta.pop(t, None)
+        return self._chk(self.lib.ba_release(self.h, t), "ba_release")
+
+    def ba_fetch(self, t: int) -> dict:
+        C, P, it = self.meta[t]
+        out = {"R": np.zeros((C, 3, 3)), "T": np.zeros((C, 3)), "X": np.zeros((max(P, 1), 3)), "k": np.zeros(2),
+               "cost_log": np.zeros(it + 1)}
+        r = ba_result(_p(out["R"]), _p(out["T"]), _p(out["X"]), _p(out["k"]), _p(out["cost_log"]))
+        self._chk(self.lib.ba_fetch(self.h, t, ct.byref(r)), "ba_fetch")
+        out["X"] = out["X"][:P]
+        n = r.iterations
+        out.update(status=r.status, iterations=n, accepted=r.accepted, rejected=r.rejected, lambda_=r.lambda_,
+                   initial_cost=r.initial_cost, final_cost=r.final_cost, t_submit=r.t_submit, t_admit=r.t_admit,
+                   t_done=r.t_done)
+        out["cost_log"] = out["cost_log"][: n + 1]
+        out["state"] = (out["R"], out["T"], out["X"], out["k"])
+        return out

@@ -1,0 +1,83 @@
+// Internal device-side data layout of the cluster bundle-adjustment library.
+// Shared by the runtime (ba_runtime.cpp) and the kernels (ba_kernels.hip);
+// not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bagpu {
+
+constexpr int kWave = 64;                 // CDNA wavefront
+constexpr int kWG = 256;                  // threads per workgroup of the chunk kernels
+constexpr int kWavesPerWG = kWG / kWave;
+constexpr int kMaxFreeCams = 24;          // reduced system m <= 6*24 + 2 = 146
+constexpr int kMaxCams = 64;              // camera table kept in LDS
+constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
+constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
+constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
+constexpr int kPtVals = 12;               // per point: Q (6 packed symmetric), g (3), D (3)
+
+enum SlotStatus { ST_QUEUED = 0, ST_RUNNING = 1, ST_MAXITER = 2, ST_CONVERGED = 3, ST_STALLED = 4, ST_BAD_INIT = 5 };
+
+// Read-only description of one resident cluster; written once at admission.
+struct SlotDesc {
+  int C, P, L, n_chunks, n_wg, cpw;       // cameras, points, lanes, 64-lane chunks, workgroups, chunks/WG
+  int m, n_free, kcol0, kcol1;            // reduced system size, free cameras, intrinsic columns (-1: fixed)
+  int psize, pstride;                     // packed m(m+1)/2, partial stride (Real elements)
+  int max_iters, stop_on_ftol, mixed, pad0;
+  double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
+  // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
+  const int* lane_pt;                     // [L] point index, -1 for padding
+  const int* lane_cam;                    // [L] camera index
+  const int* lane_seg;                    // [L] (first lane of the point's segment in the chunk << 8) | length
+  double* lane_uv64;                      // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
+  float* lane_uv32;                       // [2L]
+  // cameras
+  double* cam[2];                         // [C][12] state buffers
+  double* prior;                          // [C][18]
+  const int* cam_col;                     // [C] first reduced-system column, -1 if fixed
+  const double* raw_cam;                  // [C][30] R (9), T (3), R_prior (9), T_prior (3), sigma (6)
+  // points
+  double* X[2];                           // [P][3] state buffers (origin-shifted)
+  float* X32[2];                          // [P][3] FP32 shadows of X
+  void* ptv;                              // [P][12] Real: Q, g, D from the last assembly
+  // reduced camera system
+  void* partial;                          // [n_wg][pstride] Real: per-workgroup S, g, bS, diag U
+  double* Sg;                             // [pstride] reduced: packed S_acc (psize), g, bS, diag U (m each)
+  double* Sd;                             // [psize] damped S, kept for the refinement step
+  double* dc;                             // [m] camera / intrinsic update
+  double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
+  int* bad_part;                          // [n_wg] trial observations at non-positive depth
+  double* cost_log;                       // [max_iters + 1]
+  double* out;                            // [12C + 3P + 2] export staging
+};
+
+// Levenberg-Marquardt control of one cluster, updated on the device.
+struct SlotCtl {
+  double origin[3];
+  double k[2][2];                         // intrinsics per state buffer
+  double lambda, nu, E, E_prior_trial, pred_c, E0;
+  int cur, status, iter, accepted, rejected, solve_ok, point_fail, bad_init;
+};
+
+// Launch helpers (ba_kernels.hip).  `act` lists the slots of the batch,
+// `wg_off` the prefix sums of their chunk-kernel workgroup counts.
+struct Batch {
+  const SlotDesc* desc;
+  SlotCtl* ctl;
+  const int* act;
+  const int* wg_off;
+  int n_act;
+  int total_wg;                           // wg_off[n_act]
+  int max_m, max_C, max_pstride;
+};
+
+hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st);
+hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st);
+hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
+
+size_t real_size(bool mixed);
+
+}  // namespace bagpu

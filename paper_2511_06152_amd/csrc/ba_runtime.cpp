@@ -1,0 +1,833 @@
+// Host runtime of the cluster bundle-adjustment library: the C ABI of ba.h,
+// validation and observation layout at submission, the HBM arena and its
+// admission control, resident-cluster slots, batched launch series, and the
+// continuous-batching serving thread.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_device.h"
+
+using namespace bagpu;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- arena: first-fit free list with coalescing -------------------------------------
+
+class Arena {
+ public:
+  void init(size_t size) { free_.clear(); free_[0] = size; size_ = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) { it->second += nx->second; free_.erase(nx); }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) { pv->second += it->second; free_.erase(it); }
+    }
+  }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0, used_ = 0;
+};
+
+// ---- a submitted cluster, laid out for the device ------------------------------------
+
+struct Staged {
+  int C = 0, P = 0, O = 0, L = 0, n_chunks = 0, m = 0, n_free = 0, kcol0 = -1, kcol1 = -1;
+  int max_iters = 0, stop_on_ftol = 0;
+  double f = 0, cx = 0, cy = 0, sigma = 1, delta = 1, lambda0 = 1e-4, ftol = 0, k[2] = {0, 0};
+  std::vector<double> raw_cam;   // [C][30]
+  std::vector<double> X;         // [3P]
+  std::vector<int> cam_col;      // [C]
+  std::vector<int> lane_pt, lane_cam, lane_seg;
+  std::vector<double> lane_uv;   // [2L]
+};
+
+struct Layout {                  // byte offsets inside a slot block
+  size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv,
+      partial, Sg, Sd, dc, cost_part, bad_part, cost_log, out, total;
+  int n_wg, psize, pstride;
+};
+
+Layout make_layout(const Staged& s, bool mixed, int cpw) {
+  Layout l{};
+  const size_t rs = real_size(mixed);
+  l.n_wg = (s.n_chunks + cpw - 1) / cpw;
+  l.psize = s.m * (s.m + 1) / 2;
+  l.pstride = (int)align_up((size_t)l.psize + 3 * (size_t)s.m, 4);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
+  l.lane_pt = take(4 * (size_t)s.L);
+  l.lane_cam = take(4 * (size_t)s.L);
+  l.lane_seg = take(4 * (size_t)s.L);
+  l.uv64 = take(16 * (size_t)s.L);
+  l.uv32 = take(8 * (size_t)s.L);
+  l.cam0 = take(8 * (size_t)kCamVals * s.C);
+  l.cam1 = take(8 * (size_t)kCamVals * s.C);
+  l.prior = take(8 * (size_t)kPriorVals * s.C);
+  l.cam_col = take(4 * (size_t)s.C);
+  l.raw_cam = take(8 * 30 * (size_t)s.C);
+  l.X0 = take(24 * (size_t)s.P);
+  l.X1 = take(24 * (size_t)s.P);
+  l.X320 = take(12 * (size_t)s.P);
+  l.X321 = take(12 * (size_t)s.P);
+  l.ptv = take(rs * kPtVals * (size_t)s.P);
+  l.partial = take(rs * (size_t)l.pstride * l.n_wg);
+  l.Sg = take(8 * (size_t)l.pstride);
+  l.Sd = take(8 * (size_t)l.psize);
+  l.dc = take(8 * (size_t)s.m);
+  l.cost_part = take(16 * (size_t)l.n_wg);
+  l.bad_part = take(4 * (size_t)l.n_wg);
+  l.cost_log = take(8 * ((size_t)s.max_iters + 1));
+  l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 2));
+  l.total = o;
+  return l;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Validates the cluster and builds the lane layout: observations sorted by
+// (point, camera), packed greedily into 64-lane chunks so that no point's
+// observations straddle a chunk.  Integer bookkeeping only.
+int stage(const ba_cluster* c, Staged& s, std::string& err) {
+  if (!c) { err = "cluster is NULL"; return BA_E_ARG; }
+  const int C = c->n_cams, P = c->n_points, O = c->n_obs;
+  if (C < 1 || C > kMaxCams || P < 0 || O < 0) { err = "sizes out of range (1 <= n_cams <= 64)"; return BA_E_ARG; }
+  if (!c->R || !c->T || !c->k || !c->prior_R || !c->prior_T || !c->prior_sigma || !c->fixed ||
+      (P > 0 && !c->X) || (O > 0 && (!c->obs_cam || !c->obs_pt || !c->obs_uv))) {
+    err = "missing input array"; return BA_E_ARG;
+  }
+  if (c->max_iters < 1 || c->max_iters > 4096) { err = "max_iters must be in 1..4096"; return BA_E_ARG; }
+  if (!(c->sigma_px > 0) || !(c->huber_delta > 0) || !std::isfinite(c->sigma_px) || !std::isfinite(c->huber_delta) ||
+      !std::isfinite(c->f) || !std::isfinite(c->cx) || !std::isfinite(c->cy) || !(c->f > 0)) {
+    err = "bad camera or noise parameters"; return BA_E_ARG;
+  }
+  if (!finite_all(c->R, 9 * (size_t)C) || !finite_all(c->T, 3 * (size_t)C) || !finite_all(c->k, 2) ||
+      !finite_all(c->prior_R, 9 * (size_t)C) || !finite_all(c->prior_T, 3 * (size_t)C) ||
+      (P > 0 && !finite_all(c->X, 3 * (size_t)P)) || (O > 0 && !finite_all(c->obs_uv, 2 * (size_t)O))) {
+    err = "non-finite input"; return BA_E_ARG;
+  }
+  for (size_t i = 0; i < 6 * (size_t)C; ++i)
+    if (std::isnan(c->prior_sigma[i])) { err = "NaN prior sigma"; return BA_E_ARG; }
+  s = Staged();
+  s.C = C; s.P = P; s.O = O;
+  s.max_iters = c->max_iters; s.stop_on_ftol = c->stop_on_ftol;
+  s.f = c->f; s.cx = c->cx; s.cy = c->cy; s.sigma = c->sigma_px; s.delta = c->huber_delta;
+  s.lambda0 = c->lambda0; s.ftol = c->ftol; s.k[0] = c->k[0]; s.k[1] = c->k[1];
+  s.cam_col.assign(C, -1);
+  for (int k = 0; k < C; ++k)
+    if (!c->fixed[k]) s.cam_col[k] = 6 * s.n_free++;
+  if (s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras"; return BA_E_ARG; }
+  int col = 6 * s.n_free;
+  if (c->intr_mask & 1) s.kcol0 = col++;
+  if (c->intr_mask & 2) s.kcol1 = col++;
+  s.m = col;
+  s.raw_cam.resize(30 * (size_t)C);
+  for (int k = 0; k < C; ++k) {
+    double* r = &s.raw_cam[30 * (size_t)k];
+    std::memcpy(r, c->R + 9 * k, 9 * sizeof(double));
+    std::memcpy(r + 9, c->T + 3 * k, 3 * sizeof(double));
+    std::memcpy(r + 12, c->prior_R + 9 * k, 9 * sizeof(double));
+    std::memcpy(r + 21, c->prior_T + 3 * k, 3 * sizeof(double));
+    std::memcpy(r + 24, c->prior_sigma + 6 * k, 6 * sizeof(double));
+  }
+  s.X.assign(c->X, c->X + 3 * (size_t)P);
+  // observations per point
+  std::vector<int> cnt(P + 1, 0);
+  for (int o = 0; o < O; ++o) {
+    const int cam = c->obs_cam[o], pt = c->obs_pt[o];
+    if (cam < 0 || cam >= C || pt < 0 || pt >= P) { err = "observation index out of range"; return BA_E_ARG; }
+    if (++cnt[pt + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
+  }
+  for (int j = 0; j < P; ++j) cnt[j + 1] += cnt[j];
+  std::vector<int> order(O);
+  {
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int o = 0; o < O; ++o) order[fill[c->obs_pt[o]]++] = o;
+  }
+  for (int j = 0; j < P; ++j) {
+    int* b = order.data() + cnt[j];
+    const int n = cnt[j + 1] - cnt[j];
+    std::sort(b, b + n, [&](int x, int y) { return c->obs_cam[x] < c->obs_cam[y]; });
+    for (int i = 1; i < n; ++i)
+      if (c->obs_cam[b[i]] == c->obs_cam[b[i - 1]]) { err = "a camera observes one point twice"; return BA_E_ARG; }
+  }
+  // greedy packing into 64-lane chunks
+  std::vector<int> start(P, 0);
+  int pos = 0;
+  for (int j = 0; j < P; ++j) {
+    const int n = cnt[j + 1] - cnt[j];
+    if (n == 0) continue;
+    if ((pos % kWave) + n > kWave) pos = (int)align_up(pos, kWave);
+    start[j] = pos;
+    pos += n;
+  }
+  s.L = (int)align_up(pos, kWave);
+  s.n_chunks = s.L / kWave;
+  s.lane_pt.assign(s.L, -1);
+  s.lane_cam.assign(s.L, 0);
+  s.lane_seg.resize(s.L);
+  s.lane_uv.assign(2 * (size_t)s.L, 0.0);
+  for (int i = 0; i < s.L; ++i) s.lane_seg[i] = ((i % kWave) << 8) | 1;
+  for (int j = 0; j < P; ++j) {
+    const int n = cnt[j + 1] - cnt[j];
+    for (int t = 0; t < n; ++t) {
+      const int o = order[cnt[j] + t], lane = start[j] + t;
+      s.lane_pt[lane] = j;
+      s.lane_cam[lane] = c->obs_cam[o];
+      s.lane_seg[lane] = ((start[j] % kWave) << 8) | n;
+      s.lane_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
+      s.lane_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
+    }
+  }
+  return BA_OK;
+}
+
+enum TicketState { TK_QUEUED, TK_RESIDENT, TK_DONE };
+
+struct Ticket {
+  ba_ticket id = 0;
+  TicketState state = TK_QUEUED;
+  bool serving = false;           // owned by the serving loop until done
+  std::unique_ptr<Staged> staged; // until admission
+  int C = 0, P = 0, max_iters = 0;
+  size_t bytes = 0;
+  int slot = -1;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  // results cached when the serving loop retires the cluster
+  std::vector<double> out, cost_log;
+  SlotCtl ctl{};
+};
+
+struct Slot {
+  bool used = false;
+  ba_ticket ticket = 0;
+  size_t off = 0, bytes = 0;
+  Layout lay{};
+  SlotDesc desc{};
+  bool mixed = false;
+};
+
+// Per-launcher device batch arrays and pinned mirrors.
+struct Launcher {
+  int* d_act = nullptr;
+  int* d_wgoff = nullptr;
+  int* h_act = nullptr;     // pinned: [max_slots] act, then [max_slots + 1] wg_off
+  SlotCtl* h_ctl = nullptr; // pinned readback of all slots' control blocks
+  hipEvent_t ev = nullptr;
+  hipEvent_t copy_ev = nullptr;  // after the last upload from h_act
+  bool copy_pending = false;
+};
+
+}  // namespace
+
+struct ba_ctx {
+  ba_options opt{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* arena_base = nullptr;
+  Arena arena;
+  SlotDesc* d_desc = nullptr;
+  SlotCtl* d_ctl = nullptr;
+  std::vector<Slot> slots;
+  std::map<ba_ticket, std::unique_ptr<Ticket>> tickets;
+  std::deque<ba_ticket> queue;    // FIFO of queued tickets (admission order)
+  ba_ticket next_id = 1;
+  std::mutex mu;
+  std::condition_variable cv;     // wakes the serving thread
+  std::condition_variable done_cv;
+  std::thread th;
+  bool stop = false;
+  bool dead = false;
+  std::string last_error;
+  Launcher api, srv;
+};
+
+namespace {
+
+int fail(ba_ctx* c, int code, const std::string& msg) {
+  c->last_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+  do {                                                                                       \
+    hipError_t e__ = (expr);                                                                 \
+    if (e__ != hipSuccess) {                                                                 \
+      (ctx)->dead = true;                                                                    \
+      return fail((ctx), BA_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e__));  \
+    }                                                                                        \
+  } while (0)
+
+int init_launcher(ba_ctx* c, Launcher& l) {
+  const int S = c->opt.max_slots;
+  HIPCHK(c, hipMalloc(&l.d_act, sizeof(int) * S));
+  HIPCHK(c, hipMalloc(&l.d_wgoff, sizeof(int) * (S + 1)));
+  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (2 * S + 1), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc(&l.h_ctl, sizeof(SlotCtl) * S, hipHostMallocDefault));
+  HIPCHK(c, hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreateWithFlags(&l.copy_ev, hipEventDisableTiming));
+  return BA_OK;
+}
+
+void free_launcher(Launcher& l) {
+  if (l.d_act) hipFree(l.d_act);
+  if (l.d_wgoff) hipFree(l.d_wgoff);
+  if (l.h_act) hipHostFree(l.h_act);
+  if (l.h_ctl) hipHostFree(l.h_ctl);
+  if (l.ev) hipEventDestroy(l.ev);
+  if (l.copy_ev) hipEventDestroy(l.copy_ev);
+  l = Launcher();
+}
+
+// Builds and uploads the batch arrays of the given slots on launcher l.
+int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) {
+  const int S = c->opt.max_slots;
+  int* act = l.h_act;
+  int* off = l.h_act + S;
+  // The pinned arrays are rewritten below: the previous upload from them must
+  // have been executed by the stream first.
+  if (l.copy_pending) {
+    HIPCHK(c, hipEventSynchronize(l.copy_ev));
+    l.copy_pending = false;
+  }
+  b = Batch{};
+  b.desc = c->d_desc;
+  b.ctl = c->d_ctl;
+  b.act = l.d_act;
+  b.wg_off = l.d_wgoff;
+  b.n_act = (int)slots.size();
+  int tot = 0;
+  for (int i = 0; i < b.n_act; ++i) {
+    const Slot& sl = c->slots[slots[i]];
+    act[i] = slots[i];
+    off[i] = tot;
+    tot += sl.lay.n_wg;
+    b.max_m = std::max(b.max_m, sl.desc.m);
+    b.max_C = std::max(b.max_C, sl.desc.C);
+    b.max_pstride = std::max(b.max_pstride, sl.lay.pstride);
+  }
+  off[b.n_act] = tot;
+  b.total_wg = tot;
+  if (b.n_act == 0) return BA_OK;
+  HIPCHK(c, hipMemcpyAsync(l.d_act, act, sizeof(int) * b.n_act, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * (b.n_act + 1), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipEventRecord(l.copy_ev, c->stream));
+  l.copy_pending = true;
+  return BA_OK;
+}
+
+// Copies the control blocks of all slots to the launcher's pinned mirror and waits.
+int read_ctl(ba_ctx* c, Launcher& l) {
+  HIPCHK(c, hipMemcpyAsync(l.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(l.ev, c->stream));
+  HIPCHK(c, hipEventSynchronize(l.ev));
+  return BA_OK;
+}
+
+// Moves the ticket's staged data into a free slot and arena block.  Returns
+// BA_E_AGAIN when no slot or memory is free.  Caller holds mu.
+int admit_one(ba_ctx* c, Ticket& t) {
+  int slot = -1;
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (!c->slots[i].used) { slot = i; break; }
+  if (slot < 0) return BA_E_AGAIN;
+  const Staged& s = *t.staged;
+  const bool mixed = c->opt.precision == BA_MIXED;
+  Layout lay = make_layout(s, mixed, c->opt.chunks_per_wg);
+  size_t off = 0;
+  if (!c->arena.alloc(lay.total, &off)) return BA_E_AGAIN;
+  Slot& sl = c->slots[slot];
+  sl.used = true;
+  sl.ticket = t.id;
+  sl.off = off;
+  sl.bytes = lay.total;
+  sl.lay = lay;
+  sl.mixed = mixed;
+  char* base = c->arena_base + off;
+  SlotDesc& d = sl.desc;
+  d = SlotDesc{};
+  d.C = s.C; d.P = s.P; d.L = s.L; d.n_chunks = s.n_chunks; d.n_wg = lay.n_wg; d.cpw = c->opt.chunks_per_wg;
+  d.m = s.m; d.n_free = s.n_free; d.kcol0 = s.kcol0; d.kcol1 = s.kcol1;
+  d.psize = lay.psize; d.pstride = lay.pstride;
+  d.max_iters = s.max_iters; d.stop_on_ftol = s.stop_on_ftol; d.mixed = mixed ? 1 : 0;
+  d.f = s.f; d.cx = s.cx; d.cy = s.cy; d.inv_sigma = 1.0 / s.sigma; d.huber_dt = s.delta / s.sigma;
+  d.ftol = s.ftol; d.lambda0 = s.lambda0;
+  d.lane_pt = (const int*)(base + lay.lane_pt);
+  d.lane_cam = (const int*)(base + lay.lane_cam);
+  d.lane_seg = (const int*)(base + lay.lane_seg);
+  d.lane_uv64 = (double*)(base + lay.uv64);
+  d.lane_uv32 = (float*)(base + lay.uv32);
+  d.cam[0] = (double*)(base + lay.cam0);
+  d.cam[1] = (double*)(base + lay.cam1);
+  d.prior = (double*)(base + lay.prior);
+  d.cam_col = (const int*)(base + lay.cam_col);
+  d.raw_cam = (const double*)(base + lay.raw_cam);
+  d.X[0] = (double*)(base + lay.X0);
+  d.X[1] = (double*)(base + lay.X1);
+  d.X32[0] = (float*)(base + lay.X320);
+  d.X32[1] = (float*)(base + lay.X321);
+  d.ptv = base + lay.ptv;
+  d.partial = base + lay.partial;
+  d.Sg = (double*)(base + lay.Sg);
+  d.Sd = (double*)(base + lay.Sd);
+  d.dc = (double*)(base + lay.dc);
+  d.cost_part = (double*)(base + lay.cost_part);
+  d.bad_part = (int*)(base + lay.bad_part);
+  d.cost_log = (double*)(base + lay.cost_log);
+  d.out = (double*)(base + lay.out);
+  hipStream_t st = c->stream;
+  HIPCHK(c, hipMemcpyAsync(base + lay.lane_pt, s.lane_pt.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(base + lay.lane_cam, s.lane_cam.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(base + lay.lane_seg, s.lane_seg.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(base + lay.uv64, s.lane_uv.data(), 16 * (size_t)s.L, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(base + lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(base + lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C, hipMemcpyHostToDevice, st));
+  if (s.P > 0) HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+  SlotCtl ctl{};
+  ctl.k[0][0] = s.k[0];
+  ctl.k[0][1] = s.k[1];
+  ctl.status = ST_RUNNING;
+  HIPCHK(c, hipMemcpyAsync(c->d_ctl + slot, &ctl, sizeof(SlotCtl), hipMemcpyHostToDevice, st));
+  // The staged host data must stay alive until the copies above have run.
+  HIPCHK(c, hipStreamSynchronize(st));
+  t.slot = slot;
+  t.state = TK_RESIDENT;
+  t.t_admit = now_s();
+  t.staged.reset();
+  return BA_OK;
+}
+
+// Runs prep and the initial FP64 cost for newly admitted slots.
+int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
+  if (slots.empty()) return BA_OK;
+  Batch b;
+  int rc = make_batch(c, l, slots, b);
+  if (rc) return rc;
+  int maxPL = 0;
+  for (int s : slots) maxPL = std::max({maxPL, c->slots[s].desc.P, c->slots[s].desc.L});
+  HIPCHK(c, launch_prep(b, maxPL, c->stream));
+  HIPCHK(c, launch_initial_cost(b, c->stream));
+  return BA_OK;
+}
+
+int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_iters) {
+  Batch b;
+  int rc = make_batch(c, l, slots, b);
+  if (rc) return rc;
+  const bool mixed = c->opt.precision == BA_MIXED;
+  for (int i = 0; i < n_iters; ++i) HIPCHK(c, launch_iteration(b, mixed, c->stream));
+  return BA_OK;
+}
+
+// Exports the listed slots' state into their ticket caches (synchronous).
+int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
+  if (slots.empty()) return BA_OK;
+  Batch b;
+  int rc = make_batch(c, l, slots, b);
+  if (rc) return rc;
+  int maxP = 0;
+  for (int s : slots) maxP = std::max(maxP, c->slots[s].desc.P);
+  HIPCHK(c, launch_export(b, maxP, c->stream));
+  for (int s : slots) {
+    Slot& sl = c->slots[s];
+    Ticket& t = *c->tickets[sl.ticket];
+    t.out.resize(12 * (size_t)sl.desc.C + 3 * (size_t)sl.desc.P + 2);
+    t.cost_log.resize((size_t)sl.desc.max_iters + 1);
+    HIPCHK(c, hipMemcpyAsync(t.out.data(), sl.desc.out, 8 * t.out.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(t.cost_log.data(), sl.desc.cost_log, 8 * t.cost_log.size(), hipMemcpyDeviceToHost, c->stream));
+  }
+  rc = read_ctl(c, l);
+  if (rc) return rc;
+  for (int s : slots) c->tickets[c->slots[s].ticket]->ctl = l.h_ctl[s];
+  return BA_OK;
+}
+
+void free_slot(ba_ctx* c, int s) {
+  Slot& sl = c->slots[s];
+  if (!sl.used) return;
+  c->arena.release(sl.off, sl.bytes);
+  sl = Slot();
+}
+
+// Admits queued tickets in FIFO order while slots and memory allow.  When
+// `serving_only`, only tickets handed to the serving loop are admitted.
+int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only) {
+  for (auto it = c->queue.begin(); it != c->queue.end();) {
+    Ticket& t = *c->tickets[*it];
+    if (serving_only && !t.serving) { ++it; continue; }
+    int rc = admit_one(c, t);
+    if (rc == BA_E_AGAIN) break;
+    if (rc) return rc;
+    admitted.push_back(t.slot);
+    it = c->queue.erase(it);
+  }
+  return BA_OK;
+}
+
+bool serving_queued(ba_ctx* c) {
+  for (ba_ticket id : c->queue)
+    if (c->tickets[id]->serving) return true;
+  return false;
+}
+
+bool is_finished(int status) { return status != ST_RUNNING && status != ST_QUEUED; }
+
+// One serving tick: retire finished clusters, admit queued ones, iterate.
+void serve_loop(ba_ctx* c) {
+  hipSetDevice(c->device);
+  std::vector<int> active;
+  std::unique_lock<std::mutex> lk(c->mu);
+  while (!c->stop) {
+    // retire
+    std::vector<int> fin;
+    for (int s : active)
+      if (is_finished(c->srv.h_ctl[s].status)) fin.push_back(s);
+    if (!fin.empty()) {
+      if (export_slots(c, c->srv, fin)) break;
+      const double t_done = now_s();
+      for (int s : fin) {
+        Ticket& t = *c->tickets[c->slots[s].ticket];
+        t.state = TK_DONE;
+        t.serving = false;
+        t.slot = -1;
+        t.t_done = t_done;
+        free_slot(c, s);
+      }
+      active.erase(std::remove_if(active.begin(), active.end(),
+                                  [&](int s) { return std::find(fin.begin(), fin.end(), s) != fin.end(); }),
+                   active.end());
+      c->done_cv.notify_all();
+    }
+    // admit
+    std::vector<int> adm;
+    if (admit_queue(c, adm, true)) break;
+    if (!adm.empty()) {
+      if (start_slots(c, c->srv, adm)) break;
+      active.insert(active.end(), adm.begin(), adm.end());
+    }
+    if (active.empty()) {
+      c->cv.wait(lk, [&] { return c->stop || serving_queued(c); });
+      continue;
+    }
+    if (run_iterations(c, c->srv, active, c->opt.iters_per_tick)) break;
+    if (hipMemcpyAsync(c->srv.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost, c->stream) ||
+        hipEventRecord(c->srv.ev, c->stream)) {
+      c->dead = true;
+      break;
+    }
+    lk.unlock();
+    const hipError_t e = hipEventSynchronize(c->srv.ev);
+    lk.lock();
+    if (e != hipSuccess) { c->dead = true; c->last_error = hipGetErrorString(e); break; }
+  }
+  if (c->dead) c->done_cv.notify_all();
+}
+
+Ticket* find_ticket(ba_ctx* c, ba_ticket id) {
+  auto it = c->tickets.find(id);
+  return it == c->tickets.end() ? nullptr : it->second.get();
+}
+
+// Ensures a ticket outside the serving loop is resident (admits it out of turn).
+int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
+  if (t.serving) return fail(c, BA_E_STATE, "cluster is owned by the serving loop");
+  if (t.state == TK_RESIDENT) return BA_OK;
+  if (t.state == TK_DONE) return fail(c, BA_E_STATE, "cluster already retired");
+  int rc = admit_one(c, t);
+  if (rc == BA_E_AGAIN) return fail(c, BA_E_AGAIN, "no free slot or arena memory");
+  if (rc) return rc;
+  c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), t.id), c->queue.end());
+  admitted.push_back(t.slot);
+  return BA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ba_strerror(int code) {
+  switch (code) {
+    case BA_OK: return "ok";
+    case BA_E_ARG: return "invalid argument";
+    case BA_E_NOMEM: return "out of memory";
+    case BA_E_AGAIN: return "try again";
+    case BA_E_STATE: return "invalid state";
+    case BA_E_DEVICE: return "device error";
+    case BA_E_TIMEOUT: return "timeout";
+    default: return "unknown error";
+  }
+}
+
+const char* ba_last_error(ba_ctx* c) { return c ? c->last_error.c_str() : "no context"; }
+
+int ba_create(const ba_options* opt, ba_ctx** out) {
+  if (!opt || !out) return BA_E_ARG;
+  *out = nullptr;
+  if (opt->precision != BA_FP64 && opt->precision != BA_MIXED) return BA_E_ARG;
+  auto c = std::make_unique<ba_ctx>();
+  c->opt = *opt;
+  if (c->opt.hbm_budget_bytes == 0) c->opt.hbm_budget_bytes = (size_t)1 << 30;
+  if (c->opt.max_slots <= 0) c->opt.max_slots = 256;
+  if (c->opt.max_queue <= 0) c->opt.max_queue = 4096;
+  if (c->opt.iters_per_tick <= 0) c->opt.iters_per_tick = 2;
+  if (c->opt.chunks_per_wg <= 0) c->opt.chunks_per_wg = 16;
+  if (c->opt.max_slots > 65536 || c->opt.chunks_per_wg > 4096) return BA_E_ARG;
+  c->device = opt->device;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return BA_E_DEVICE;
+  if (c->device < 0 || c->device >= ndev) return BA_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return BA_E_DEVICE;
+  if (opt->stream) c->stream = (hipStream_t)opt->stream;
+  else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return BA_E_DEVICE;
+    c->own_stream = true;
+  }
+  if (hipMalloc(&c->arena_base, c->opt.hbm_budget_bytes) != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    return BA_E_NOMEM;
+  }
+  c->arena.init(c->opt.hbm_budget_bytes);
+  if (hipMalloc(&c->d_desc, sizeof(SlotDesc) * c->opt.max_slots) != hipSuccess ||
+      hipMalloc(&c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots) != hipSuccess) {
+    return BA_E_NOMEM;
+  }
+  hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots);
+  c->slots.resize(c->opt.max_slots);
+  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return BA_E_DEVICE;
+  for (int i = 0; i < c->opt.max_slots; ++i) c->srv.h_ctl[i] = SlotCtl{};
+  if (hipDeviceSynchronize() != hipSuccess) return BA_E_DEVICE;
+  ba_ctx* raw = c.release();
+  if (opt->serve) raw->th = std::thread(serve_loop, raw);
+  *out = raw;
+  return BA_OK;
+}
+
+int ba_destroy(ba_ctx* c) {
+  if (!c) return BA_E_ARG;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    c->stop = true;
+  }
+  c->cv.notify_all();
+  if (c->th.joinable()) c->th.join();
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  free_launcher(c->api);
+  free_launcher(c->srv);
+  if (c->d_desc) hipFree(c->d_desc);
+  if (c->d_ctl) hipFree(c->d_ctl);
+  if (c->arena_base) hipFree(c->arena_base);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return BA_OK;
+}
+
+size_t ba_footprint(ba_ctx* c, const ba_cluster* cl) {
+  if (!c) return 0;
+  Staged s;
+  std::string err;
+  if (stage(cl, s, err)) return 0;
+  return make_layout(s, c->opt.precision == BA_MIXED, c->opt.chunks_per_wg).total;
+}
+
+int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
+  if (!c || !ticket) return BA_E_ARG;
+  auto st = std::make_unique<Staged>();
+  std::string err;
+  int rc = stage(cl, *st, err);
+  std::lock_guard<std::mutex> g(c->mu);
+  if (rc) return fail(c, rc, err);
+  if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
+  const size_t bytes = make_layout(*st, c->opt.precision == BA_MIXED, c->opt.chunks_per_wg).total;
+  if (bytes > c->arena.size()) return fail(c, BA_E_NOMEM, "cluster footprint exceeds the arena");
+  if ((int)c->queue.size() >= c->opt.max_queue) return fail(c, BA_E_AGAIN, "admission queue full");
+  auto t = std::make_unique<Ticket>();
+  t->id = c->next_id++;
+  t->C = st->C;
+  t->P = st->P;
+  t->max_iters = st->max_iters;
+  t->bytes = bytes;
+  t->t_submit = now_s();
+  t->staged = std::move(st);
+  const ba_ticket id = t->id;
+  c->tickets[id] = std::move(t);
+  c->queue.push_back(id);
+  *ticket = id;
+  return BA_OK;
+}
+
+int ba_step(ba_ctx* c, ba_ticket id, int32_t n_iters) {
+  if (!c) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
+  Ticket* t = find_ticket(c, id);
+  if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (n_iters < 0) return fail(c, BA_E_ARG, "negative iteration count");
+  hipSetDevice(c->device);
+  std::vector<int> adm;
+  int rc = ensure_resident(c, *t, adm);
+  if (rc) return rc;
+  if ((rc = start_slots(c, c->api, adm))) return rc;
+  const std::vector<int> one{t->slot};
+  if ((rc = read_ctl(c, c->api))) return rc;
+  for (int i = 0; i < n_iters; ++i) {
+    if (c->api.h_ctl[t->slot].status != ST_RUNNING) break;
+    if ((rc = run_iterations(c, c->api, one, 1))) return rc;
+    if ((rc = read_ctl(c, c->api))) return rc;
+  }
+  return BA_OK;
+}
+
+int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
+  if (!c || (n > 0 && !ids) || n < 0) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
+  hipSetDevice(c->device);
+  std::vector<int> adm, slots;
+  for (int i = 0; i < n; ++i) {
+    Ticket* t = find_ticket(c, ids[i]);
+    if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+    int rc = ensure_resident(c, *t, adm);
+    if (rc) return rc;
+    slots.push_back(t->slot);
+  }
+  int rc = start_slots(c, c->api, adm);
+  if (rc) return rc;
+  if ((rc = read_ctl(c, c->api))) return rc;
+  const int per = c->opt.iters_per_tick;
+  for (;;) {
+    std::vector<int> act;
+    for (int s : slots)
+      if (c->api.h_ctl[s].status == ST_RUNNING) act.push_back(s);
+    if (act.empty()) break;
+    if ((rc = run_iterations(c, c->api, act, per))) return rc;
+    if ((rc = read_ctl(c, c->api))) return rc;
+  }
+  return BA_OK;
+}
+
+int ba_solve(ba_ctx* c, ba_ticket id) {
+  if (!c) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  Ticket* t = find_ticket(c, id);
+  if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (!c->opt.serve) return fail(c, BA_E_STATE, "context has no serving loop");
+  if (t->serving || t->state != TK_QUEUED) return fail(c, BA_E_STATE, "cluster is not queued");
+  t->serving = true;
+  c->cv.notify_all();
+  return BA_OK;
+}
+
+int ba_wait(ba_ctx* c, ba_ticket id, double timeout_s) {
+  if (!c) return BA_E_ARG;
+  std::unique_lock<std::mutex> lk(c->mu);
+  Ticket* t = find_ticket(c, id);
+  if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (!t->serving && t->state != TK_DONE) return fail(c, BA_E_STATE, "cluster was not handed to ba_solve");
+  auto pred = [&] { return t->state == TK_DONE || c->dead; };
+  if (timeout_s < 0) c->done_cv.wait(lk, pred);
+  else if (!c->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return BA_E_TIMEOUT;
+  if (c->dead && t->state != TK_DONE) return fail(c, BA_E_DEVICE, "serving loop stopped on a device error");
+  return BA_OK;
+}
+
+int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
+  if (!c || !r) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  Ticket* t = find_ticket(c, id);
+  if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (t->serving) return fail(c, BA_E_STATE, "cluster is being solved by the serving loop");
+  if (t->state == TK_QUEUED) return fail(c, BA_E_STATE, "cluster is still queued");
+  if (t->state == TK_RESIDENT) {
+    if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
+    hipSetDevice(c->device);
+    const std::vector<int> one{t->slot};
+    int rc = export_slots(c, c->api, one);
+    if (rc) return rc;
+  }
+  const int C = t->C, P = t->P;
+  const double* o = t->out.data();
+  if (r->R) std::memcpy(r->R, o, 9 * sizeof(double) * C);
+  if (r->T) std::memcpy(r->T, o + 9 * C, 3 * sizeof(double) * C);
+  if (r->X && P > 0) std::memcpy(r->X, o + 12 * C, 3 * sizeof(double) * P);
+  if (r->k) std::memcpy(r->k, o + 12 * C + 3 * (size_t)P, 2 * sizeof(double));
+  const SlotCtl& ctl = t->ctl;
+  const int n_log = std::min(ctl.iter, t->max_iters) + 1;
+  if (r->cost_log) {
+    for (int i = 0; i <= t->max_iters; ++i) r->cost_log[i] = i < n_log ? t->cost_log[i] : NAN;
+  }
+  r->status = ctl.status;
+  r->iterations = ctl.iter;
+  r->accepted = ctl.accepted;
+  r->rejected = ctl.rejected;
+  r->lambda = ctl.lambda;
+  r->initial_cost = ctl.E0;
+  r->final_cost = ctl.E;
+  r->t_submit = t->t_submit;
+  r->t_admit = t->t_admit;
+  r->t_done = t->t_done;
+  return BA_OK;
+}
+
+int ba_release(ba_ctx* c, ba_ticket id) {
+  if (!c) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  Ticket* t = find_ticket(c, id);
+  if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (t->serving) return fail(c, BA_E_STATE, "cluster is being solved by the serving loop");
+  if (t->state == TK_RESIDENT) {
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    free_slot(c, t->slot);
+  }
+  c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), id), c->queue.end());
+  c->tickets.erase(id);
+  return BA_OK;
+}
+
+}  // extern "C"
