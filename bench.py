@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Local bundle-adjustment benchmark on one MI355X.
+
+Workload: the paper-scale local cluster -- 12 images (2 adjacent strips x 6),
+50 MP 8000x6000 px camera at 300 m, 80 % forward / 60 % side overlap, one tie
+point per 150x150 px cell (~20k points, ~85k observations), k1/k2 radial
+distortion estimated, Huber delta 1 px, GNSS/IMU pose priors; synthetic and
+seeded (synth/aerial.py).
+
+One step = every LM iteration of a batch of B resident clusters solved to the
+termination rule (ftol on the relative cost decrease, or max_iters) with the
+mixed path: FP32 residuals/Jacobians/Schur assembly, FP64 Cholesky, FP64 cost
+and gain ratio, LM control on the device, every cluster of the batch in the
+same launches.  Inputs are resident in HBM when a step's timer starts
+(admission is done before).  `value` = clusters solved per second.
+
+Reported beside it: the plain FP64 GPU LM (one cluster at a time, host-driven,
+status read back every iteration) on the same clusters and rule, p50/p99
+solve latency of both, p50/p99 of the continuous-batching serving loop, final
+RMS reprojection of both paths, the dominant kernel's roofline position
+measured with HIP events on the library's stream, and the FP64 oracle timed on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from synth import aerial as A  # noqa: E402
+
+PEAK_VALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+FLOP_PER_OBS = 613        # residual, Jacobians, point/camera blocks, Y = W Q, diagonal camera block
+FLOP_PER_PAIR = 216       # one off-diagonal 6x6 camera block: 36 entries x 3 FMA
+FLOP_PER_POINT = 40       # damped 3x3 inverse
+FLOP_PER_INTR_OBS = 60    # intrinsic rows of the reduced system, per observation
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def assembly_flops(sc):
+    cnt = np.bincount(sc["obs_pt"], minlength=sc["n_points"])
+    pairs = int((cnt * (cnt - 1) // 2).sum())
+    f = FLOP_PER_OBS * sc["n_obs"] + FLOP_PER_PAIR * pairs + FLOP_PER_POINT * sc["n_points"]
+    if sc["intr_mask"]:
+        f += FLOP_PER_INTR_OBS * sc["n_obs"]
+    return f, pairs
+
+
+def rms_px(sc, R, T, X, k):
+    """RMS reprojection error (px) over all observations, from the scene's
+    forward camera model."""
+    e = A.project_obs(R, T, X, k, sc["obs_cam"], sc["obs_pt"]) - sc["obs_uv"]
+    return float(np.sqrt((e ** 2).sum(1).mean()))
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else float("nan")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64, help="clusters per step")
+    ap.add_argument("--scenes", type=int, default=8, help="distinct seeded clusters (cycled)")
+    ap.add_argument("--max-iters", type=int, default=20)
+    ap.add_argument("--ftol", type=float, default=1e-6)
+    ap.add_argument("--plain", type=int, default=8, help="clusters solved by the plain FP64 path")
+    ap.add_argument("--serve", type=int, default=64, help="clusters through the serving loop (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(clusters are independent: see the sharding note in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2511_06152_amd import BA_FP64, BA_MIXED, Context
+
+    t_gen = time.perf_counter()
+    scenes = [A.make_scene(A.spec_cluster12(), 2 + i) for i in range(args.scenes)]
+    log(f"generated {len(scenes)} clusters in {time.perf_counter() - t_gen:.1f}s: "
+        + ", ".join(f"C={s['n_cams']} P={s['n_points']} O={s['n_obs']}" for s in scenes[:3]) + " ...")
+    kw = dict(max_iters=args.max_iters, stop_on_ftol=True, ftol=args.ftol)
+    flops = [assembly_flops(s)[0] for s in scenes]
+
+    # ---- mixed, batched: the timed steps --------------------------------------------------
+    B = args.batch
+    ctx = Context(precision=BA_MIXED, max_slots=max(B, 1), hbm_budget_bytes=int(B * 16e6) + (256 << 20))
+    step_ms, iters_total, fl_total, mixed_final = [], 0, 0.0, {}
+    ctx.ba_profile_enable(False)
+    for step in range(args.warmup + args.steps):
+        timed = step >= args.warmup
+        ids = [(step * B + i) % len(scenes) for i in range(B)]
+        tickets = [ctx.submit(scenes[j], **kw) for j in ids]
+        for t in tickets:
+            ctx.ba_step(t, 0)     # admission: upload, origin shift, initial FP64 cost
+        if timed:
+            ctx.ba_profile_enable(True)
+        t0 = time.perf_counter()
+        ctx.ba_solve_batch(tickets)
+        t1 = time.perf_counter()
+        if timed:
+            ctx.ba_profile_enable(False)
+            step_ms.append((t1 - t0) * 1e3)
+        for t, j in zip(tickets, ids):
+            r = ctx.ba_fetch(t)
+            if timed:
+                iters_total += r["iterations"]
+                fl_total += r["iterations"] * flops[j]
+            if j not in mixed_final:
+                mixed_final[j] = r
+            ctx.ba_release(t)
+        log(f"step {step}{'' if timed else ' (warmup)'}: {(t1 - t0) * 1e3:.2f} ms for {B} clusters")
+    prof = ctx.ba_profile_read()
+    ctx.close()
+    ms_per_step = float(np.mean(step_ms))
+    value = B / (ms_per_step / 1e3)
+
+    asm_ms, asm_n = prof["assemble"]
+    asm_avg_ms = asm_ms / max(asm_n, 1)
+    achieved_tflops = fl_total / max(asm_n, 1) / (asm_avg_ms / 1e3) / 1e12 if asm_n else float("nan")
+    kernels = {k: {"avg_us": (v[0] / max(v[1], 1)) * 1e3, "launches": v[1]} for k, v in prof.items()}
+
+    # ---- plain FP64 GPU LM: one cluster at a time, host-driven ---------------------------
+    plain_lat, plain_final = [], {}
+    if args.plain > 0:
+        pctx = Context(precision=BA_FP64, max_slots=4, hbm_budget_bytes=256 << 20)
+        for i in range(args.plain + 1):
+            j = i % len(scenes)
+            t = pctx.submit(scenes[j], **kw)
+            pctx.ba_step(t, 0)
+            t0 = time.perf_counter()
+            pctx.ba_step(t, args.max_iters)
+            t1 = time.perf_counter()
+            r = pctx.ba_fetch(t)
+            pctx.ba_release(t)
+            if i == 0:
+                continue  # warmup
+            plain_lat.append((t1 - t0) * 1e3)
+            plain_final.setdefault(j, r)
+        pctx.close()
+    plain_cps = 1e3 / float(np.mean(plain_lat)) if plain_lat else float("nan")
+
+    # ---- mixed-path solve latency of one cluster alone ---------------------------------
+    one_lat = []
+    octx = Context(precision=BA_MIXED, max_slots=4, hbm_budget_bytes=256 << 20)
+    for i in range(args.plain + 1):
+        j = i % len(scenes)
+        t = octx.submit(scenes[j], **kw)
+        octx.ba_step(t, 0)
+        t0 = time.perf_counter()
+        octx.ba_solve_batch([t])
+        t1 = time.perf_counter()
+        octx.ba_release(t)
+        if i:
+            one_lat.append((t1 - t0) * 1e3)
+    octx.close()
+
+    # ---- continuous-batching serving loop (closed loop, submit -> result) --------------
+    serve = {}
+    if args.serve > 0:
+        sctx = Context(precision=BA_MIXED, serve=True, max_slots=args.serve_slots,
+                       hbm_budget_bytes=int(args.serve_slots * 16e6) + (256 << 20))
+        inflight, lat, done = [], [], 0
+        nxt = 0
+        t_start = time.perf_counter()
+        while done < args.serve:
+            while len(inflight) < args.serve_slots and nxt < args.serve:
+                t = sctx.submit(scenes[nxt % len(scenes)], **kw)
+                sctx.ba_solve(t)
+                inflight.append(t)
+                nxt += 1
+            t = inflight.pop(0)
+            sctx.ba_wait(t)
+            r = sctx.ba_fetch(t)
+            lat.append((r["t_done"] - r["t_submit"]) * 1e3)
+            sctx.ba_release(t)
+            done += 1
+        wall = time.perf_counter() - t_start
+        sctx.close()
+        serve = {"clusters": done, "slots": args.serve_slots, "clusters_per_s": done / wall,
+                 "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)}
+
+    # ---- equal-RMS check -------------------------------------------------------------------
+    rms = {}
+    common = sorted(set(mixed_final) & set(plain_final))
+    if common:
+        d = []
+        for j in common:
+            rm = rms_px(scenes[j], *mixed_final[j]["state"])
+            rp = rms_px(scenes[j], *plain_final[j]["state"])
+            d.append(abs(rm - rp))
+            rms.setdefault("mixed_px", rm)
+            rms.setdefault("plain_fp64_px", rp)
+        rms["max_abs_diff_px"] = float(max(d))
+        rms["clusters_compared"] = len(common)
+
+    # ---- CPU baseline: the FP64 oracle on the host cores ---------------------------------
+    cpu = None
+    if args.cpu_clusters > 0:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        for i in range(args.cpu_clusters):
+            oracle.solve(scenes[i % len(scenes)], max_iters=args.max_iters, stop_on_ftol=True, ftol=args.ftol)
+        dt = time.perf_counter() - t0
+        cpu = {"value": args.cpu_clusters / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_clusters} clusters of the same workload, same termination rule, "
+                         f"single-threaded FP64 C++ ({dt:.1f} s)"}
+
+    O_mean = float(np.mean([s["n_obs"] for s in scenes]))
+    P_mean = float(np.mean([s["n_points"] for s in scenes]))
+    out = {
+        "metric": "local-BA clusters/sec + p50/p99 solve latency vs plain FP64 LM at equal RMS",
+        "value": value,
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded aerial scenes, synth/aerial.py)",
+        "config": {
+            "workload": "paper-scale local cluster: 12 cameras (2 strips x 6), 8000x6000 px, f=50 mm, 300 m, "
+                        "80/60 % overlap, one tie point per 150 px cell, k1/k2 estimated",
+            "clusters_per_step": B, "points_mean": P_mean, "obs_mean": O_mean,
+            "max_iters": args.max_iters, "ftol": args.ftol, "mean_iterations": iters_total / max(B * args.steps, 1),
+            "path": "mixed: FP32 assembly, FP64 Cholesky + refinement, FP64 cost/gain ratio, batched device-side LM",
+        },
+        "latency_ms": {"one_cluster_mixed_p50": pct(one_lat, 50), "one_cluster_mixed_p99": pct(one_lat, 99),
+                       "serving": serve},
+        "plain_fp64": {"clusters_per_s": plain_cps, "p50_ms": pct(plain_lat, 50), "p99_ms": pct(plain_lat, 99),
+                       "clusters": len(plain_lat)},
+        "speedup_vs_plain_fp64": value / plain_cps if plain_lat else None,
+        "rms": rms,
+        "kernels": kernels,
+        "roofline": {"bound": "alu", "kernel": "k_assemble<float>", "achieved": achieved_tflops,
+                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_VALU_TFLOPS,
+                     "traffic": None, "avg_launch_us": asm_avg_ms * 1e3,
+                     "algorithmic_flop_per_launch": fl_total / max(asm_n, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

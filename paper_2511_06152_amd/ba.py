@@ -22,7 +22,9 @@ BA_MAX_CAMS = 64
 BA_MAX_OBS_PER_POINT = 64
 
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
-            "ba_fetch", "ba_release", "ba_footprint", "ba_strerror", "ba_last_error"]
+            "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
+            "ba_last_error"]
+BA_PROF_KERNELS = ["assemble", "reduce", "solve", "backsub", "lm"]
 
 
 class ba_options(ct.Structure):
@@ -73,6 +75,8 @@ def load(path: str = LIB_PATH):
     L.ba_release.argtypes = [P, ct.c_int64]
     L.ba_footprint.argtypes = [P, ct.POINTER(ba_cluster)]
     L.ba_footprint.restype = ct.c_size_t
+    L.ba_profile_enable.argtypes = [P, ct.c_int32]
+    L.ba_profile_read.argtypes = [P, P, P]
     L.ba_strerror.argtypes = [ct.c_int]
     L.ba_strerror.restype = ct.c_char_p
     L.ba_last_error.argtypes = [P]
@@ -183,6 +187,15 @@ class Context:
     def ba_release(self, t: int):
         self.meta.pop(t, None)
         return self._chk(self.lib.ba_release(self.h, t), "ba_release")
+
+    def ba_profile_enable(self, enable: bool = True):
+        return self._chk(self.lib.ba_profile_enable(self.h, 1 if enable else 0), "ba_profile_enable")
+
+    def ba_profile_read(self) -> dict:
+        ms = np.zeros(len(BA_PROF_KERNELS))
+        n = np.zeros(len(BA_PROF_KERNELS), np.int64)
+        self._chk(self.lib.ba_profile_read(self.h, _p(ms), _p(n)), "ba_profile_read")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(BA_PROF_KERNELS)}
 
     def ba_fetch(self, t: int) -> dict:
         C, P, it = self.meta[t]

@@ -75,7 +75,9 @@ struct Batch {
 
 hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st);
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
-hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st);
+// ev (optional): 6 events recorded before the first kernel of the iteration
+// and after each of its five kernels.
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 
 size_t real_size(bool mixed);

@@ -1045,30 +1045,39 @@ hipError_t launch_initial_cost(const Batch& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st) {
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev) {
   if (b.n_act == 0) return hipSuccess;
   const dim3 red_grid((b.max_pstride + 255) / 256, b.n_act);
   hipError_t e;
   const size_t s_solve = solve_smem(b);
   if ((e = ensure_smem((const void*)k_solve, s_solve))) return e;
-  if (mixed) {
-    const size_t sa = assemble_smem<float>(b), sb = backsub_smem<float>(b);
-    if ((e = ensure_smem((const void*)k_assemble<float>, sa))) return e;
-    if ((e = ensure_smem((const void*)k_backsub<float>, sb))) return e;
-    if (b.total_wg > 0) hipLaunchKernelGGL(k_assemble<float>, dim3(b.total_wg), dim3(kWG), sa, st, b);
-    if (b.max_pstride > 0) hipLaunchKernelGGL(k_reduce<float>, red_grid, dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_solve, dim3(b.n_act), dim3(kSolveThreads), s_solve, st, b);
-    if (b.total_wg > 0) hipLaunchKernelGGL(k_backsub<float>, dim3(b.total_wg), dim3(kWG), sb, st, b);
-  } else {
-    const size_t sa = assemble_smem<double>(b), sb = backsub_smem<double>(b);
-    if ((e = ensure_smem((const void*)k_assemble<double>, sa))) return e;
-    if ((e = ensure_smem((const void*)k_backsub<double>, sb))) return e;
-    if (b.total_wg > 0) hipLaunchKernelGGL(k_assemble<double>, dim3(b.total_wg), dim3(kWG), sa, st, b);
-    if (b.max_pstride > 0) hipLaunchKernelGGL(k_reduce<double>, red_grid, dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_solve, dim3(b.n_act), dim3(kSolveThreads), s_solve, st, b);
-    if (b.total_wg > 0) hipLaunchKernelGGL(k_backsub<double>, dim3(b.total_wg), dim3(kWG), sb, st, b);
+  const size_t sa = mixed ? assemble_smem<float>(b) : assemble_smem<double>(b);
+  const size_t sb = mixed ? backsub_smem<float>(b) : backsub_smem<double>(b);
+  const void* fa = mixed ? (const void*)k_assemble<float> : (const void*)k_assemble<double>;
+  const void* fb = mixed ? (const void*)k_backsub<float> : (const void*)k_backsub<double>;
+  if ((e = ensure_smem(fa, sa))) return e;
+  if ((e = ensure_smem(fb, sb))) return e;
+  auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], st); };
+  mark(0);
+  if (b.total_wg > 0) {
+    if (mixed) hipLaunchKernelGGL(k_assemble<float>, dim3(b.total_wg), dim3(kWG), sa, st, b);
+    else hipLaunchKernelGGL(k_assemble<double>, dim3(b.total_wg), dim3(kWG), sa, st, b);
   }
+  mark(1);
+  if (b.max_pstride > 0) {
+    if (mixed) hipLaunchKernelGGL(k_reduce<float>, red_grid, dim3(256), 0, st, b);
+    else hipLaunchKernelGGL(k_reduce<double>, red_grid, dim3(256), 0, st, b);
+  }
+  mark(2);
+  hipLaunchKernelGGL(k_solve, dim3(b.n_act), dim3(kSolveThreads), s_solve, st, b);
+  mark(3);
+  if (b.total_wg > 0) {
+    if (mixed) hipLaunchKernelGGL(k_backsub<float>, dim3(b.total_wg), dim3(kWG), sb, st, b);
+    else hipLaunchKernelGGL(k_backsub<double>, dim3(b.total_wg), dim3(kWG), sb, st, b);
+  }
+  mark(4);
   hipLaunchKernelGGL(k_lm, dim3(b.n_act), dim3(64), 0, st, b);
+  mark(5);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -284,6 +285,12 @@ struct ba_ctx {
   bool dead = false;
   std::string last_error;
   Launcher api, srv;
+  // kernel timing (ba_profile_enable)
+  bool prof = false;
+  std::vector<std::array<hipEvent_t, 6>> prof_ev;  // one set per iteration since the last harvest
+  size_t prof_used = 0;
+  double prof_ms[BA_PROF_N] = {0, 0, 0, 0, 0};
+  int64_t prof_n[BA_PROF_N] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -361,10 +368,13 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
 }
 
 // Copies the control blocks of all slots to the launcher's pinned mirror and waits.
+int harvest_prof(ba_ctx* c);
+
 int read_ctl(ba_ctx* c, Launcher& l) {
   HIPCHK(c, hipMemcpyAsync(l.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipEventRecord(l.ev, c->stream));
   HIPCHK(c, hipEventSynchronize(l.ev));
+  if (c->prof_used) return harvest_prof(c);
   return BA_OK;
 }
 
@@ -455,12 +465,39 @@ int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   return BA_OK;
 }
 
+// Adds up the kernel times of the event sets recorded since the last call.
+// The stream must have passed the last recorded event.
+int harvest_prof(ba_ctx* c) {
+  for (size_t i = 0; i < c->prof_used; ++i) {
+    auto& ev = c->prof_ev[i];
+    for (int k = 0; k < BA_PROF_N; ++k) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      c->prof_ms[k] += ms;
+      c->prof_n[k] += 1;
+    }
+  }
+  c->prof_used = 0;
+  return BA_OK;
+}
+
 int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_iters) {
   Batch b;
   int rc = make_batch(c, l, slots, b);
   if (rc) return rc;
   const bool mixed = c->opt.precision == BA_MIXED;
-  for (int i = 0; i < n_iters; ++i) HIPCHK(c, launch_iteration(b, mixed, c->stream));
+  for (int i = 0; i < n_iters; ++i) {
+    hipEvent_t* ev = nullptr;
+    if (c->prof) {
+      if (c->prof_used == c->prof_ev.size()) {
+        std::array<hipEvent_t, 6> set;
+        for (auto& e : set) HIPCHK(c, hipEventCreate(&e));
+        c->prof_ev.push_back(set);
+      }
+      ev = c->prof_ev[c->prof_used++].data();
+    }
+    HIPCHK(c, launch_iteration(b, mixed, c->stream, ev));
+  }
   return BA_OK;
 }
 
@@ -564,6 +601,7 @@ void serve_loop(ba_ctx* c) {
     const hipError_t e = hipEventSynchronize(c->srv.ev);
     lk.lock();
     if (e != hipSuccess) { c->dead = true; c->last_error = hipGetErrorString(e); break; }
+    if (c->prof_used && harvest_prof(c)) break;
   }
   if (c->dead) c->done_cv.notify_all();
 }
@@ -659,6 +697,8 @@ int ba_destroy(ba_ctx* c) {
   hipStreamSynchronize(c->stream);
   free_launcher(c->api);
   free_launcher(c->srv);
+  for (auto& set : c->prof_ev)
+    for (auto& e : set) (void)hipEventDestroy(e);
   if (c->d_desc) hipFree(c->d_desc);
   if (c->d_ctl) hipFree(c->d_ctl);
   if (c->arena_base) hipFree(c->arena_base);
@@ -811,6 +851,29 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   r->t_submit = t->t_submit;
   r->t_admit = t->t_admit;
   r->t_done = t->t_done;
+  return BA_OK;
+}
+
+int ba_profile_enable(ba_ctx* c, int32_t enable) {
+  if (!c) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  c->prof = enable != 0;
+  return BA_OK;
+}
+
+int ba_profile_read(ba_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return BA_E_ARG;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int rc = harvest_prof(c);
+  if (rc) return rc;
+  for (int k = 0; k < BA_PROF_N; ++k) {
+    total_ms[k] = c->prof_ms[k];
+    launches[k] = c->prof_n[k];
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
   return BA_OK;
 }
 

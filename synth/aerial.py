@@ -147,6 +147,16 @@ def synth_project(R, T, X, k1, k2):
     return uv, z
 
 
+def project_obs(R, T, X, k, obs_cam, obs_pt):
+    """Data-generating camera applied per observation: pixel (O,2) of point
+    obs_pt[o] in camera obs_cam[o]."""
+    R, T, X = np.asarray(R).reshape(-1, 3, 3), np.asarray(T).reshape(-1, 3), np.asarray(X).reshape(-1, 3)
+    d = X[obs_pt] - T[obs_cam]
+    xc = np.einsum("nji,nj->ni", R[obs_cam], d)
+    a, b = _distort(xc[:, 0] / xc[:, 2], xc[:, 1] / xc[:, 2], k[0], k[1])
+    return np.stack([F_PX * a + CX, F_PX * b + CY], -1)
+
+
 def _undistort(ad, bd, k1, k2):
     a, b = ad.copy(), bd.copy()
     for _ in range(20):

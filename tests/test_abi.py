@@ -20,7 +20,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve", "ba_solve_batch",
-                 "ba_wait", "ba_fetch", "ba_release", "ba_footprint", "ba_strerror", "ba_last_error"]:
+                 "ba_wait", "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read",
+                 "ba_strerror", "ba_last_error"]:
         assert want in names
 
 

@@ -1,15 +1,26 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
-same seeded inputs."""
+same seeded inputs.
+
+Bars (floating point):
+  * plain FP64 path: cost after every LM iteration within 1e-8 relative of
+    the oracle's, same accept/reject sequence;
+  * mixed path (FP32 assembly): final state within RMS |p_gpu - p_oracle|
+    < 1e-3 px over all observations, camera centres < 1 mm, attitude
+    < 2e-6 rad.
+"""
 import numpy as np
 import pytest
+from scipy.spatial.transform import Rotation
 
 import oracle
 from synth import aerial as A
 
 pytestmark = pytest.mark.gpu
 
+FP64, MIXED = 0, 1
 
-def gpu_step(sc, iters, precision=0, **kw):
+
+def gpu_run(sc, iters, precision=FP64, **kw):
     from paper_2511_06152_amd import Context
     with Context(precision=precision) as ctx:
         t = ctx.submit(sc, max_iters=iters, **kw)
@@ -18,20 +29,256 @@ def gpu_step(sc, iters, precision=0, **kw):
 
 
 def rel(a, b):
-    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300)
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
 
 
-def test_tiny_fp64_cost_per_iteration():
-    """Plain FP64 GPU LM matches the oracle's cost at every iteration to 1e-8."""
-    sc = A.scene_tiny(1)
-    print("case tiny seed 1", sc["n_cams"], sc["n_points"], sc["n_obs"], flush=True)
-    ref = oracle.solve(sc, max_iters=10)
-    got = gpu_step(sc, 10)
+def check_cost_log(got, ref, tol=1e-8):
+    """Per-iteration cost within tol relative.  A cost that has collapsed to
+    rounding level (below 1e-12 of the initial cost, e.g. a quadratic
+    prior-only problem) is compared on that floor instead of its own value."""
     print("oracle", ref["cost_log"], flush=True)
     print("gpu   ", got["cost_log"], flush=True)
     assert got["iterations"] == ref["iterations"]
-    assert np.all(rel(got["cost_log"], ref["cost_log"]) <= 1e-8)
     assert got["accepted"] == ref["accepted"]
+    a, b = np.asarray(got["cost_log"]), np.asarray(ref["cost_log"])
+    err = np.abs(a - b) / np.maximum(np.abs(b), 1e-12 * abs(b[0]))
+    assert np.all(err <= tol), err.max()
+
+
+def final_errors(sc, got, ref):
+    uv_g = A.project_obs(got["R"], got["T"], got["X"], got["k"], sc["obs_cam"], sc["obs_pt"])
+    R, T, X, k = ref["state"]
+    uv_o = A.project_obs(R, T, X, k, sc["obs_cam"], sc["obs_pt"])
+    rms = float(np.sqrt(((uv_g - uv_o) ** 2).sum(1).mean())) if sc["n_obs"] else 0.0
+    dT = float(np.abs(got["T"] - T).max())
+    att = max(np.linalg.norm(Rotation.from_matrix(got["R"][c].T @ R[c]).as_rotvec()) for c in range(sc["n_cams"]))
+    return rms, dT, att
+
+
+def test_tiny_fp64_cost_per_iteration():
+    """6 cameras, 2,000 points, 10 iterations (the tiny workload)."""
+    sc = A.scene_tiny(1)
+    print("case tiny seed 1", sc["n_cams"], sc["n_points"], sc["n_obs"], flush=True)
+    ref = oracle.solve(sc, max_iters=10)
+    got = gpu_run(sc, 10)
+    check_cost_log(got, ref)
     R, T, X, k = ref["state"]
     assert np.abs(got["T"] - T).max() < 1e-6
     assert np.abs(got["X"] - X).max() < 1e-5
+
+
+def test_cluster12_fp64_cost_per_iteration():
+    """Paper-scale cluster: 12 cameras, ~20k points, ~85k observations, k1/k2."""
+    sc = A.scene_cluster12(2)
+    print("case cluster12 seed 2", sc["n_cams"], sc["n_points"], sc["n_obs"], flush=True)
+    ref = oracle.solve(sc, max_iters=8)
+    got = gpu_run(sc, 8)
+    check_cost_log(got, ref)
+    assert np.abs(got["k"] - ref["state"][3]).max() < 1e-9
+
+
+@pytest.mark.parametrize("name,spec,seed", [
+    ("fixed2_k1", A.spec_micro(n_strips=2, imgs_per_strip=3, n_points=500, n_fixed=2, intr_mask=1,
+                               k_true=(-0.05, 0.0)), 31),
+    ("k2_only_outliers", A.spec_micro(n_strips=3, imgs_per_strip=2, n_points=700, intr_mask=2,
+                                      k_true=(0.0, 0.02), outlier_frac=0.1), 32),
+    ("noise_free_priors_at_truth", A.spec_micro(n_strips=2, imgs_per_strip=2, n_points=300, noise_px=0.0,
+                                          outlier_frac=0.0, priors_at_truth=True), 33),
+    ("24_free_cams", A.SceneSpec(n_strips=3, imgs_per_strip=8, n_points=6000, obs_model=("tgeom", 0.5, 2, 6),
+                                 outlier_frac=0.05), 34),
+])
+def test_variants_fp64_cost_per_iteration(name, spec, seed):
+    sc = A.make_scene(spec, seed)
+    print("case", name, seed, sc["n_cams"], sc["n_points"], sc["n_obs"], flush=True)
+    ref = oracle.solve(sc, max_iters=6)
+    got = gpu_run(sc, 6)
+    check_cost_log(got, ref)
+
+
+def test_prior_only_cluster():
+    """No observations: the adjustment is the pose priors alone."""
+    sc = A.make_scene(A.spec_micro(n_points=5), 41)
+    sc.update(n_points=0, n_obs=0, X=np.zeros((0, 3)), obs_cam=np.zeros(0, np.int32),
+              obs_pt=np.zeros(0, np.int32), obs_uv=np.zeros((0, 2)))
+    sc["prior_T"] = sc["T"] + 0.3
+    print("case prior-only", flush=True)
+    ref = oracle.solve(sc, max_iters=3)
+    got = gpu_run(sc, 3)
+    check_cost_log(got, ref)
+
+
+def test_all_cameras_fixed_triangulation():
+    """Every camera fixed, no intrinsics: the reduced system is empty."""
+    sc = A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2, n_points=400, n_fixed=4), 42)
+    print("case all-fixed", flush=True)
+    ref = oracle.solve(sc, max_iters=5)
+    got = gpu_run(sc, 5)
+    check_cost_log(got, ref)
+
+
+def test_point_with_64_observations():
+    """A 64-camera grid (24 free, 40 fixed) seeing a common ground patch: the
+    longest segments fill a whole 64-lane wavefront."""
+    rng = np.random.default_rng(5)
+    C = 64
+    T = np.array([[10.0 * (c % 8), 10.0 * (c // 8), 300.0] for c in range(C)])
+    R = np.stack([A.R_NADIR @ A.rotvec_to_matrix(rng.normal(0, 0.01, 3)) for _ in range(C)])
+    P = 300
+    X = np.column_stack([rng.uniform(20, 50, P), rng.uniform(20, 50, P), rng.uniform(0, 20, P)])
+    obs_cam, obs_pt = [], []
+    for j in range(P):
+        n = 64 if j % 7 == 0 else int(rng.integers(2, 9))
+        cams = np.arange(C) if n == 64 else rng.choice(C, n, replace=False)
+        obs_cam += list(cams)
+        obs_pt += [j] * n
+    obs_cam, obs_pt = np.array(obs_cam, np.int32), np.array(obs_pt, np.int32)
+    uv = A.project_obs(R, T, X, (0.0, 0.0), obs_cam, obs_pt) + rng.normal(0, 0.5, (len(obs_cam), 2))
+    sig = np.column_stack([np.full((C, 3), 8.7e-4), np.full((C, 3), 0.5)])
+    fixed = np.zeros(C, np.uint8)
+    fixed[24:] = 1
+    sc = {"n_cams": C, "n_points": P, "n_obs": len(obs_cam),
+          "R": R @ A.rotvec_to_matrix(rng.normal(0, 1e-3, (C, 3))), "T": T + rng.normal(0, 0.3, (C, 3)),
+          "X": X + rng.normal(0, 0.5, X.shape), "k": np.zeros(2), "prior_R": R.copy(), "prior_T": T.copy(),
+          "prior_sigma": sig, "fixed": fixed, "obs_cam": obs_cam, "obs_pt": obs_pt, "obs_uv": uv,
+          "f": A.F_PX, "cx": A.CX, "cy": A.CY, "intr_mask": 0, "sigma_px": 0.5, "huber_delta": 1.0}
+    print("case 64-observation points", sc["n_obs"], flush=True)
+    ref = oracle.solve(sc, max_iters=5)
+    got = gpu_run(sc, 5)
+    check_cost_log(got, ref)
+
+
+@pytest.mark.parametrize("which", ["tiny", "cluster12"])
+def test_mixed_within_tolerance_after_fixed_iterations(which):
+    """Both paths run 40 iterations: by then the FP64 iterate moves < 0.1 mm
+    per 40 iterations on these scenes (at 10 it still moves ~1 cm), so the
+    comparison measures precision, not two points of a moving trajectory."""
+    sc = A.scene_tiny(1) if which == "tiny" else A.scene_cluster12(2)
+    iters = 40
+    ref = oracle.solve(sc, max_iters=iters)
+    got = gpu_run(sc, iters, precision=MIXED)
+    rms, dT, att = final_errors(sc, got, ref)
+    print(f"case mixed {which}: rms {rms:.3e} px, centres {dT:.3e} m, attitude {att:.3e} rad; "
+          f"E oracle {ref['cost_log'][-1]:.9g} gpu {got['cost_log'][-1]:.9g}", flush=True)
+    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
+
+
+def test_mixed_within_tolerance_converged():
+    sc = A.scene_tiny(3)
+    ref = oracle.solve(sc, max_iters=60, stop_on_ftol=True, ftol=1e-9)
+    got = gpu_run(sc, 60, precision=MIXED, stop_on_ftol=True, ftol=1e-9)
+    rms, dT, att = final_errors(sc, got, ref)
+    print(f"case mixed converged: iters oracle {ref['iterations']} gpu {got['iterations']}; rms {rms:.3e} px, "
+          f"centres {dT:.3e} m, attitude {att:.3e} rad", flush=True)
+    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_batched_equals_alone(precision):
+    """Clusters of uneven size solved together in one launch series give the
+    results they give alone."""
+    from paper_2511_06152_amd import Context
+    scenes = [A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + i, n_points=300 + 400 * i,
+                                        intr_mask=3 if i == 1 else 0, k_true=(-0.05, 0.02) if i == 1 else (0, 0)),
+                           50 + i) for i in range(4)]
+    kw = dict(max_iters=8, stop_on_ftol=True, ftol=1e-7)
+    alone = []
+    with Context(precision=precision) as ctx:
+        for sc in scenes:
+            t = ctx.submit(sc, **kw)
+            ctx.ba_solve_batch([t])
+            alone.append(ctx.ba_fetch(t))
+    with Context(precision=precision) as ctx:
+        ts = [ctx.submit(sc, **kw) for sc in scenes]
+        ctx.ba_solve_batch(ts)
+        mix = [ctx.ba_fetch(t) for t in ts]
+    for sc, a, b in zip(scenes, alone, mix):
+        assert a["iterations"] == b["iterations"]
+        assert np.all(rel(b["cost_log"], a["cost_log"]) <= 1e-9)
+        rms, dT, att = final_errors(sc, b, {"state": a["state"]})
+        assert rms < 1e-4 and dT < 1e-4 and att < 2e-7
+
+
+def test_serving_loop_equals_alone():
+    """Continuous batching: clusters handed to the serving loop while others
+    are iterating give the same result as alone, within tolerance."""
+    from paper_2511_06152_amd import Context
+    scenes = [A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + (i % 3), n_points=400 + 300 * i), 60 + i)
+              for i in range(8)]
+    kw = dict(max_iters=12, stop_on_ftol=True, ftol=1e-7)
+    with Context(precision=MIXED) as ctx:
+        alone = []
+        for sc in scenes:
+            t = ctx.submit(sc, **kw)
+            ctx.ba_solve_batch([t])
+            alone.append(ctx.ba_fetch(t))
+    with Context(precision=MIXED, serve=True, max_slots=3, iters_per_tick=1) as ctx:
+        ts = []
+        for sc in scenes:
+            t = ctx.submit(sc, **kw)
+            ctx.ba_solve(t)
+            ts.append(t)
+        res = []
+        for t in ts:
+            ctx.ba_wait(t, 60.0)
+            res.append(ctx.ba_fetch(t))
+    for sc, a, b in zip(scenes, alone, res):
+        assert b["iterations"] == a["iterations"]
+        rms, dT, att = final_errors(sc, b, {"state": a["state"]})
+        assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
+        assert b["t_done"] >= b["t_admit"] >= b["t_submit"] > 0
+
+
+def test_admission_by_arena_budget():
+    """Clusters larger than what is free wait in the queue; one larger than the
+    whole arena is refused."""
+    from paper_2511_06152_amd import BAError, Cluster, Context
+    sc = A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=3, n_points=3000), 70)
+    with Context(precision=FP64, hbm_budget_bytes=64 << 20) as ctx:
+        fp = ctx.ba_footprint(Cluster(sc, max_iters=4))
+        assert fp > 0
+    budget = int(fp * 2.5)
+    with Context(precision=FP64, hbm_budget_bytes=budget, serve=True, max_slots=8) as ctx:
+        ts = [ctx.submit(sc, max_iters=4) for _ in range(5)]
+        for t in ts:
+            ctx.ba_solve(t)
+        for t in ts:
+            ctx.ba_wait(t, 60.0)
+            r = ctx.ba_fetch(t)
+            assert r["iterations"] == 4
+    with Context(precision=FP64, hbm_budget_bytes=fp // 2) as ctx:
+        with pytest.raises(BAError) as e:
+            ctx.submit(sc, max_iters=4)
+        assert e.value.code == -2
+
+
+def test_invalid_inputs_are_rejected():
+    from paper_2511_06152_amd import BAError, Context
+    base = A.make_scene(A.spec_micro(n_points=20), 80)
+    bad = []
+    s = dict(base); s["obs_cam"] = base["obs_cam"].copy(); s["obs_cam"][0] = 99; bad.append(s)
+    s = dict(base); s["obs_pt"] = base["obs_pt"].copy(); s["obs_pt"][0] = -1; bad.append(s)
+    s = dict(base); s["obs_uv"] = base["obs_uv"].copy(); s["obs_uv"][3, 1] = np.nan; bad.append(s)
+    s = dict(base); s["X"] = base["X"].copy(); s["X"][2, 0] = np.inf; bad.append(s)
+    j = int(base["obs_pt"][0])
+    o2 = [o for o in range(base["n_obs"]) if base["obs_pt"][o] == j][1]
+    s = dict(base); s["obs_cam"] = base["obs_cam"].copy(); s["obs_cam"][o2] = base["obs_cam"][0]; bad.append(s)
+    with Context(precision=FP64) as ctx:
+        for s in bad:
+            with pytest.raises(BAError) as e:
+                ctx.submit(s, max_iters=3)
+            assert e.value.code == -1
+        with pytest.raises(BAError):
+            ctx.submit(base, max_iters=0)
+
+
+def test_bad_initial_depth_is_reported():
+    from paper_2511_06152_amd import Context
+    sc = A.make_scene(A.spec_micro(n_points=30), 81)
+    sc["X"] = sc["X"].copy()
+    sc["X"][0, 2] = 400.0   # above every camera: negative depth
+    with Context(precision=FP64) as ctx:
+        t = ctx.submit(sc, max_iters=3)
+        ctx.ba_step(t, 3)
+        r = ctx.ba_fetch(t)
+    assert r["status"] == 5 and r["iterations"] == 0
