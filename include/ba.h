@@ -91,8 +91,10 @@ typedef struct {
   int32_t precision;         /* enum ba_precision */
   int32_t serve;             /* 1: start the continuous-batching runtime thread */
   int32_t iters_per_tick;    /* LM iterations per serving tick; 0 -> 2 */
-  int32_t chunks_per_wg;     /* 64-observation chunks per workgroup in the assembly
+  int32_t chunks_per_wg;     /* 64-observation chunks per workgroup of the point-major
                                 kernels; 0 -> 16 */
+  int32_t chunks_per_task;   /* 64-lane chunks per wavefront task of the block kernel;
+                                0 -> 4 */
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */
@@ -196,8 +198,8 @@ size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
  * number of launches per kernel since the last read, in the order of
  * enum ba_prof_kernel, into caller arrays of BA_PROF_N entries, and resets
  * the counters.  Errors: BA_E_ARG, BA_E_DEVICE. */
-enum ba_prof_kernel { BA_PROF_ASSEMBLE = 0, BA_PROF_REDUCE = 1, BA_PROF_SOLVE = 2, BA_PROF_BACKSUB = 3,
-                      BA_PROF_LM = 4, BA_PROF_N = 5 };
+enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_BLOCKS = 1, BA_PROF_REDUCE = 2, BA_PROF_SOLVE = 3,
+                      BA_PROF_BACKSUB = 4, BA_PROF_LM = 5, BA_PROF_N = 6 };
 int ba_profile_enable(ba_ctx* ctx, int32_t enable);
 int ba_profile_read(ba_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -24,13 +24,14 @@ BA_MAX_OBS_PER_POINT = 64
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error"]
-BA_PROF_KERNELS = ["assemble", "reduce", "solve", "backsub", "lm"]
+BA_PROF_KERNELS = ["point", "blocks", "reduce", "solve", "backsub", "lm"]
 
 
 class ba_options(ct.Structure):
     _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("hbm_budget_bytes", ct.c_size_t),
                 ("max_slots", ct.c_int32), ("max_queue", ct.c_int32), ("precision", ct.c_int32),
-                ("serve", ct.c_int32), ("iters_per_tick", ct.c_int32), ("chunks_per_wg", ct.c_int32)]
+                ("serve", ct.c_int32), ("iters_per_tick", ct.c_int32), ("chunks_per_wg", ct.c_int32),
+                ("chunks_per_task", ct.c_int32)]
 
 
 class ba_cluster(ct.Structure):
@@ -129,10 +130,10 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256,
                  max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
-                 chunks_per_wg: int = 16):
+                 chunks_per_wg: int = 16, chunks_per_task: int = 4):
         self.lib = load()
         opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
-                         iters_per_tick, chunks_per_wg)
+                         iters_per_tick, chunks_per_wg, chunks_per_task)
         h = ct.c_void_p()
         rc = self.lib.ba_create(ct.byref(opt), ct.byref(h))
         if rc != BA_OK:

@@ -16,6 +16,12 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # Packed FP32 instructions stay off: ordinary float code only.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # No implicit FMA contraction: the observation model is evaluated by several
+    # kernels (point pass, block pass, back-substitution) and the Schur
+    # complement's reduced gradient -g_c + sum Y g_p cancels to the last bits,
+    # so every kernel must round the FP32 residuals and Jacobians identically.
+    # Fused multiply-adds are written explicitly where wanted.
+    "-ffp-contract=off",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

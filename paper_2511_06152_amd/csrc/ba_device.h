@@ -16,7 +16,13 @@ constexpr int kMaxCams = 64;              // camera table kept in LDS
 constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
 constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
 constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
-constexpr int kPtVals = 12;               // per point: Q (6 packed symmetric), g (3), D (3)
+constexpr int kPtVals = 18;               // per point: Q (6 packed symmetric), g (3), D (3), Z (6)
+constexpr int kTaskVals = 52;             // per block task partial: camera task 51 values, pair task 36
+constexpr int kPtPartVals = 10;           // per point-pass wavefront: intrinsic-intrinsic terms
+constexpr int kBlk = 6;                   // block size of the reduced-system factorisation
+// Work items of the block-assembly kernel (one wavefront each) and of its
+// reduction: int4 {kind << 24 | cam_a << 12 | cam_b, begin, end/count, 0}.
+enum TaskKind { TASK_CAM = 0, TASK_PAIR = 1, TARGET_INTR = 2 };
 
 enum SlotStatus { ST_QUEUED = 0, ST_RUNNING = 1, ST_MAXITER = 2, ST_CONVERGED = 3, ST_STALLED = 4, ST_BAD_INIT = 5 };
 
@@ -24,8 +30,9 @@ enum SlotStatus { ST_QUEUED = 0, ST_RUNNING = 1, ST_MAXITER = 2, ST_CONVERGED = 
 struct SlotDesc {
   int C, P, L, n_chunks, n_wg, cpw;       // cameras, points, lanes, 64-lane chunks, workgroups, chunks/WG
   int m, n_free, kcol0, kcol1;            // reduced system size, free cameras, intrinsic columns (-1: fixed)
-  int psize, pstride;                     // packed m(m+1)/2, partial stride (Real elements)
-  int max_iters, stop_on_ftol, mixed, pad0;
+  int psize, pstride;                     // packed m(m+1)/2, reduced-system vector stride (psize + 3m)
+  int max_iters, stop_on_ftol, mixed, nb;  // nb: 6x6 blocks per side of the reduced system
+  int Lc, Lq, n_tasks, n_task_wg, n_targets, n_pt_part;
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
   // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
   const int* lane_pt;                     // [L] point index, -1 for padding
@@ -33,6 +40,18 @@ struct SlotDesc {
   const int* lane_seg;                    // [L] (first lane of the point's segment in the chunk << 8) | length
   double* lane_uv64;                      // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
   float* lane_uv32;                       // [2L]
+  // camera lanes: observations of free cameras sorted by (camera, point), each
+  // camera's run padded to whole 64-lane chunks
+  const int* cl_pt;                       // [Lc] point index, -1 for padding
+  double* cl_uv64;                        // [2Lc]
+  float* cl_uv32;                         // [2Lc]
+  // pair lanes: observation pairs of one point with both cameras free, sorted
+  // by camera-pair block, each block's run padded to whole chunks
+  const int* ql_pt;                       // [Lq]
+  double* ql_uv64;                        // [4Lq] (u_a, v_a, u_b, v_b)
+  float* ql_uv32;                         // [4Lq]
+  const int4* tasks;                      // [n_tasks] camera tasks (by camera), then pair tasks (by block)
+  const int4* targets;                    // [n_targets] reduction targets with their task ranges
   // cameras
   double* cam[2];                         // [C][12] state buffers
   double* prior;                          // [C][18]
@@ -41,11 +60,12 @@ struct SlotDesc {
   // points
   double* X[2];                           // [P][3] state buffers (origin-shifted)
   float* X32[2];                          // [P][3] FP32 shadows of X
-  void* ptv;                              // [P][12] Real: Q, g, D from the last assembly
+  void* ptv;                              // [P][18] Real: Q, g, D, Z from the last assembly
   // reduced camera system
-  void* partial;                          // [n_wg][pstride] Real: per-workgroup S, g, bS, diag U
+  void* task_part;                        // [n_tasks][52] Real: per-task block sums
+  void* pt_part;                          // [n_pt_part][10] Real: per point-pass wavefront intrinsic sums
   double* Sg;                             // [pstride] reduced: packed S_acc (psize), g, bS, diag U (m each)
-  double* Sd;                             // [psize] damped S, kept for the refinement step
+  double* Sd;                             // [nb(nb+1)/2][36] damped S in 6x6 blocks, for the refinement step
   double* dc;                             // [m] camera / intrinsic update
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
   int* bad_part;                          // [n_wg] trial observations at non-positive depth
@@ -67,16 +87,18 @@ struct Batch {
   const SlotDesc* desc;
   SlotCtl* ctl;
   const int* act;
-  const int* wg_off;
+  const int* wg_off;                      // point-lane chunk workgroups
+  const int* tk_off;                      // block-task workgroups (4 tasks each)
+  const int* tg_off;                      // reduction targets
   int n_act;
-  int total_wg;                           // wg_off[n_act]
-  int max_m, max_C, max_pstride;
+  int total_wg, total_tk_wg, total_tg;
+  int max_m, max_C, max_pstride, max_nb;
 };
 
 hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st);
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
-// ev (optional): 6 events recorded before the first kernel of the iteration
-// and after each of its five kernels.
+// ev (optional): 12 events, the start and end of each of the six kernels of
+// the iteration, recorded by the kernel dispatches themselves.
 hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 

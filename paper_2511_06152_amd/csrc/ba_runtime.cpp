@@ -80,18 +80,23 @@ struct Staged {
   std::vector<int> cam_col;      // [C]
   std::vector<int> lane_pt, lane_cam, lane_seg;
   std::vector<double> lane_uv;   // [2L]
+  int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0;
+  std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
+  std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
+  std::vector<int4> tasks, targets;
 };
 
 struct Layout {                  // byte offsets inside a slot block
-  size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv,
-      partial, Sg, Sd, dc, cost_part, bad_part, cost_log, out, total;
+  size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
+      cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, task_part, pt_part, Sg, Sd, dc, cost_part,
+      bad_part, cost_log, out, total;
   int n_wg, psize, pstride;
 };
 
-Layout make_layout(const Staged& s, bool mixed, int cpw) {
+Layout make_layout(const Staged& s, bool mixed) {
   Layout l{};
   const size_t rs = real_size(mixed);
-  l.n_wg = (s.n_chunks + cpw - 1) / cpw;
+  l.n_wg = s.n_wg;
   l.psize = s.m * (s.m + 1) / 2;
   l.pstride = (int)align_up((size_t)l.psize + 3 * (size_t)s.m, 4);
   size_t o = 0;
@@ -101,6 +106,14 @@ Layout make_layout(const Staged& s, bool mixed, int cpw) {
   l.lane_seg = take(4 * (size_t)s.L);
   l.uv64 = take(16 * (size_t)s.L);
   l.uv32 = take(8 * (size_t)s.L);
+  l.cl_pt = take(4 * (size_t)s.Lc);
+  l.cl_uv64 = take(16 * (size_t)s.Lc);
+  l.cl_uv32 = take(8 * (size_t)s.Lc);
+  l.ql_pt = take(4 * (size_t)s.Lq);
+  l.ql_uv64 = take(32 * (size_t)s.Lq);
+  l.ql_uv32 = take(16 * (size_t)s.Lq);
+  l.tasks = take(sizeof(int4) * s.tasks.size());
+  l.targets = take(sizeof(int4) * s.targets.size());
   l.cam0 = take(8 * (size_t)kCamVals * s.C);
   l.cam1 = take(8 * (size_t)kCamVals * s.C);
   l.prior = take(8 * (size_t)kPriorVals * s.C);
@@ -111,9 +124,10 @@ Layout make_layout(const Staged& s, bool mixed, int cpw) {
   l.X320 = take(12 * (size_t)s.P);
   l.X321 = take(12 * (size_t)s.P);
   l.ptv = take(rs * kPtVals * (size_t)s.P);
-  l.partial = take(rs * (size_t)l.pstride * l.n_wg);
+  l.task_part = take(rs * kTaskVals * s.tasks.size());
+  l.pt_part = take(rs * kPtPartVals * (size_t)s.n_pt_part);
   l.Sg = take(8 * (size_t)l.pstride);
-  l.Sd = take(8 * (size_t)l.psize);
+  l.Sd = take(8 * 36 * (size_t)s.nb * (s.nb + 1) / 2);
   l.dc = take(8 * (size_t)s.m);
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
@@ -129,10 +143,17 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
-// Validates the cluster and builds the lane layout: observations sorted by
-// (point, camera), packed greedily into 64-lane chunks so that no point's
-// observations straddle a chunk.  Integer bookkeeping only.
-int stage(const ba_cluster* c, Staged& s, std::string& err) {
+int4 mk4(int kind, int a, int b, int y, int z) { return make_int4((kind << 24) | (a << 12) | b, y, z, 0); }
+
+// Validates the cluster and builds its work lists (integer bookkeeping only):
+//  * point lanes: observations sorted by (point, camera), packed greedily into
+//    64-lane chunks so that no point's observations straddle a chunk;
+//  * camera lanes: observations of each free camera in point order, each
+//    camera's run padded to whole chunks, cut into tasks of <= cpt chunks;
+//  * pair lanes: the observation pairs of each point whose two cameras are
+//    free, grouped by camera pair, padded and cut into tasks likewise;
+//  * reduction targets: each free camera, each camera pair, the intrinsics.
+int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
   if (!c) { err = "cluster is NULL"; return BA_E_ARG; }
   const int C = c->n_cams, P = c->n_points, O = c->n_obs;
   if (C < 1 || C > kMaxCams || P < 0 || O < 0) { err = "sizes out of range (1 <= n_cams <= 64)"; return BA_E_ARG; }
@@ -223,6 +244,83 @@ int stage(const ba_cluster* c, Staged& s, std::string& err) {
       s.lane_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
     }
   }
+  s.n_wg = (s.n_chunks + cpw - 1) / cpw;
+  const bool intr = s.kcol0 >= 0 || s.kcol1 >= 0;
+  s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
+  s.nb = s.n_free + (intr ? 1 : 0);
+  const int F = s.n_free;
+  std::vector<int> free_cam(F);
+  for (int k = 0; k < C; ++k)
+    if (s.cam_col[k] >= 0) free_cam[s.cam_col[k] / 6] = k;
+  // camera lanes and tasks
+  std::vector<std::vector<int>> cam_obs(F);
+  for (int j = 0; j < P; ++j)
+    for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
+      const int o = order[t], col = s.cam_col[c->obs_cam[o]];
+      if (col >= 0) cam_obs[col / 6].push_back(o);
+    }
+  std::vector<int2> cam_range(F);
+  for (int fi = 0; fi < F; ++fi) {
+    const int base = s.Lc / kWave;
+    const int n = (int)cam_obs[fi].size();
+    s.Lc += (int)align_up(n, kWave);
+    s.cl_pt.resize(s.Lc, -1);
+    s.cl_uv.resize(2 * (size_t)s.Lc, 0.0);
+    for (int t = 0; t < n; ++t) {
+      const int o = cam_obs[fi][t], lane = base * kWave + t;
+      s.cl_pt[lane] = c->obs_pt[o];
+      s.cl_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
+      s.cl_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
+    }
+    const int nch = (int)(align_up(n, kWave) / kWave);
+    cam_range[fi].x = (int)s.tasks.size();
+    for (int ch = 0; ch < nch; ch += cpt) s.tasks.push_back(mk4(TASK_CAM, free_cam[fi], 0, base + ch, std::min(cpt, nch - ch)));
+    cam_range[fi].y = (int)s.tasks.size();
+  }
+  // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order
+  const int nblk = F * (F - 1) / 2;
+  auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
+  std::vector<std::vector<int3>> pairs(nblk);   // (point, obs a, obs b)
+  for (int j = 0; j < P; ++j)
+    for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
+      const int oa = order[ta], ca = s.cam_col[c->obs_cam[oa]];
+      if (ca < 0) continue;
+      for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
+        const int ob = order[tb], cb = s.cam_col[c->obs_cam[ob]];
+        if (cb < 0) continue;
+        pairs[blk(ca / 6, cb / 6)].push_back(make_int3(j, oa, ob));
+      }
+    }
+  std::vector<int2> blk_range(nblk);
+  for (int fa = 0; fa < F; ++fa)
+    for (int fb = fa + 1; fb < F; ++fb) {
+      const auto& pl = pairs[blk(fa, fb)];
+      const int base = s.Lq / kWave;
+      const int n = (int)pl.size();
+      s.Lq += (int)align_up(n, kWave);
+      s.ql_pt.resize(s.Lq, -1);
+      s.ql_uv.resize(4 * (size_t)s.Lq, 0.0);
+      for (int t = 0; t < n; ++t) {
+        const size_t lane = (size_t)base * kWave + t;
+        s.ql_pt[lane] = pl[t].x;
+        s.ql_uv[4 * lane] = c->obs_uv[2 * (size_t)pl[t].y];
+        s.ql_uv[4 * lane + 1] = c->obs_uv[2 * (size_t)pl[t].y + 1];
+        s.ql_uv[4 * lane + 2] = c->obs_uv[2 * (size_t)pl[t].z];
+        s.ql_uv[4 * lane + 3] = c->obs_uv[2 * (size_t)pl[t].z + 1];
+      }
+      const int nch = (int)(align_up(n, kWave) / kWave);
+      blk_range[blk(fa, fb)].x = (int)s.tasks.size();
+      for (int ch = 0; ch < nch; ch += cpt)
+        s.tasks.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], base + ch, std::min(cpt, nch - ch)));
+      blk_range[blk(fa, fb)].y = (int)s.tasks.size();
+    }
+  for (int fi = 0; fi < F; ++fi) s.targets.push_back(mk4(TASK_CAM, free_cam[fi], 0, cam_range[fi].x, cam_range[fi].y));
+  for (int fa = 0; fa < F; ++fa)
+    for (int fb = fa + 1; fb < F; ++fb) {
+      const int2 r = blk_range[blk(fa, fb)];
+      s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
+    }
+  if (intr) s.targets.push_back(mk4(TARGET_INTR, 0, 0, 0, s.n_pt_part));
   return BA_OK;
 }
 
@@ -254,8 +352,8 @@ struct Slot {
 // Per-launcher device batch arrays and pinned mirrors.
 struct Launcher {
   int* d_act = nullptr;
-  int* d_wgoff = nullptr;
-  int* h_act = nullptr;     // pinned: [max_slots] act, then [max_slots + 1] wg_off
+  int* d_wgoff = nullptr;   // [3][max_slots + 1]: point-chunk, task and target workgroup prefixes
+  int* h_act = nullptr;     // pinned: [max_slots] act, then [3][max_slots + 1] prefixes
   SlotCtl* h_ctl = nullptr; // pinned readback of all slots' control blocks
   hipEvent_t ev = nullptr;
   hipEvent_t copy_ev = nullptr;  // after the last upload from h_act
@@ -287,10 +385,10 @@ struct ba_ctx {
   Launcher api, srv;
   // kernel timing (ba_profile_enable)
   bool prof = false;
-  std::vector<std::array<hipEvent_t, 6>> prof_ev;  // one set per iteration since the last harvest
+  std::vector<std::array<hipEvent_t, 2 * BA_PROF_N>> prof_ev;  // one set per iteration since the last harvest
   size_t prof_used = 0;
-  double prof_ms[BA_PROF_N] = {0, 0, 0, 0, 0};
-  int64_t prof_n[BA_PROF_N] = {0, 0, 0, 0, 0};
+  double prof_ms[BA_PROF_N] = {};
+  int64_t prof_n[BA_PROF_N] = {};
 };
 
 namespace {
@@ -312,8 +410,8 @@ int fail(ba_ctx* c, int code, const std::string& msg) {
 int init_launcher(ba_ctx* c, Launcher& l) {
   const int S = c->opt.max_slots;
   HIPCHK(c, hipMalloc(&l.d_act, sizeof(int) * S));
-  HIPCHK(c, hipMalloc(&l.d_wgoff, sizeof(int) * (S + 1)));
-  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (2 * S + 1), hipHostMallocDefault));
+  HIPCHK(c, hipMalloc(&l.d_wgoff, sizeof(int) * 3 * (S + 1)));
+  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (S + 3 * (S + 1)), hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc(&l.h_ctl, sizeof(SlotCtl) * S, hipHostMallocDefault));
   HIPCHK(c, hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
   HIPCHK(c, hipEventCreateWithFlags(&l.copy_ev, hipEventDisableTiming));
@@ -341,27 +439,40 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
     HIPCHK(c, hipEventSynchronize(l.copy_ev));
     l.copy_pending = false;
   }
+  int* tko = off + (S + 1);
+  int* tgo = tko + (S + 1);
   b = Batch{};
   b.desc = c->d_desc;
   b.ctl = c->d_ctl;
   b.act = l.d_act;
   b.wg_off = l.d_wgoff;
+  b.tk_off = l.d_wgoff + (S + 1);
+  b.tg_off = l.d_wgoff + 2 * (S + 1);
   b.n_act = (int)slots.size();
-  int tot = 0;
+  int tot = 0, tk = 0, tg = 0;
   for (int i = 0; i < b.n_act; ++i) {
     const Slot& sl = c->slots[slots[i]];
     act[i] = slots[i];
     off[i] = tot;
+    tko[i] = tk;
+    tgo[i] = tg;
     tot += sl.lay.n_wg;
+    tk += sl.desc.n_task_wg;
+    tg += sl.desc.n_targets;
     b.max_m = std::max(b.max_m, sl.desc.m);
     b.max_C = std::max(b.max_C, sl.desc.C);
     b.max_pstride = std::max(b.max_pstride, sl.lay.pstride);
+    b.max_nb = std::max(b.max_nb, sl.desc.nb);
   }
   off[b.n_act] = tot;
+  tko[b.n_act] = tk;
+  tgo[b.n_act] = tg;
   b.total_wg = tot;
+  b.total_tk_wg = tk;
+  b.total_tg = tg;
   if (b.n_act == 0) return BA_OK;
   HIPCHK(c, hipMemcpyAsync(l.d_act, act, sizeof(int) * b.n_act, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * (b.n_act + 1), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * 3 * (S + 1), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipEventRecord(l.copy_ev, c->stream));
   l.copy_pending = true;
   return BA_OK;
@@ -387,7 +498,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   if (slot < 0) return BA_E_AGAIN;
   const Staged& s = *t.staged;
   const bool mixed = c->opt.precision == BA_MIXED;
-  Layout lay = make_layout(s, mixed, c->opt.chunks_per_wg);
+  Layout lay = make_layout(s, mixed);
   size_t off = 0;
   if (!c->arena.alloc(lay.total, &off)) return BA_E_AGAIN;
   Slot& sl = c->slots[slot];
@@ -403,7 +514,10 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.C = s.C; d.P = s.P; d.L = s.L; d.n_chunks = s.n_chunks; d.n_wg = lay.n_wg; d.cpw = c->opt.chunks_per_wg;
   d.m = s.m; d.n_free = s.n_free; d.kcol0 = s.kcol0; d.kcol1 = s.kcol1;
   d.psize = lay.psize; d.pstride = lay.pstride;
-  d.max_iters = s.max_iters; d.stop_on_ftol = s.stop_on_ftol; d.mixed = mixed ? 1 : 0;
+  d.max_iters = s.max_iters; d.stop_on_ftol = s.stop_on_ftol; d.mixed = mixed ? 1 : 0; d.nb = s.nb;
+  d.Lc = s.Lc; d.Lq = s.Lq; d.n_tasks = (int)s.tasks.size();
+  d.n_task_wg = (d.n_tasks + kWavesPerWG - 1) / kWavesPerWG;
+  d.n_targets = (int)s.targets.size(); d.n_pt_part = s.n_pt_part;
   d.f = s.f; d.cx = s.cx; d.cy = s.cy; d.inv_sigma = 1.0 / s.sigma; d.huber_dt = s.delta / s.sigma;
   d.ftol = s.ftol; d.lambda0 = s.lambda0;
   d.lane_pt = (const int*)(base + lay.lane_pt);
@@ -411,6 +525,14 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.lane_seg = (const int*)(base + lay.lane_seg);
   d.lane_uv64 = (double*)(base + lay.uv64);
   d.lane_uv32 = (float*)(base + lay.uv32);
+  d.cl_pt = (const int*)(base + lay.cl_pt);
+  d.cl_uv64 = (double*)(base + lay.cl_uv64);
+  d.cl_uv32 = (float*)(base + lay.cl_uv32);
+  d.ql_pt = (const int*)(base + lay.ql_pt);
+  d.ql_uv64 = (double*)(base + lay.ql_uv64);
+  d.ql_uv32 = (float*)(base + lay.ql_uv32);
+  d.tasks = (const int4*)(base + lay.tasks);
+  d.targets = (const int4*)(base + lay.targets);
   d.cam[0] = (double*)(base + lay.cam0);
   d.cam[1] = (double*)(base + lay.cam1);
   d.prior = (double*)(base + lay.prior);
@@ -421,7 +543,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.X32[0] = (float*)(base + lay.X320);
   d.X32[1] = (float*)(base + lay.X321);
   d.ptv = base + lay.ptv;
-  d.partial = base + lay.partial;
+  d.task_part = base + lay.task_part;
+  d.pt_part = base + lay.pt_part;
   d.Sg = (double*)(base + lay.Sg);
   d.Sd = (double*)(base + lay.Sd);
   d.dc = (double*)(base + lay.dc);
@@ -434,6 +557,19 @@ int admit_one(ba_ctx* c, Ticket& t) {
   HIPCHK(c, hipMemcpyAsync(base + lay.lane_cam, s.lane_cam.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.lane_seg, s.lane_seg.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.uv64, s.lane_uv.data(), 16 * (size_t)s.L, hipMemcpyHostToDevice, st));
+  if (s.Lc) {
+    HIPCHK(c, hipMemcpyAsync(base + lay.cl_pt, s.cl_pt.data(), 4 * (size_t)s.Lc, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + lay.cl_uv64, s.cl_uv.data(), 16 * (size_t)s.Lc, hipMemcpyHostToDevice, st));
+  }
+  if (s.Lq) {
+    HIPCHK(c, hipMemcpyAsync(base + lay.ql_pt, s.ql_pt.data(), 4 * (size_t)s.Lq, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + lay.ql_uv64, s.ql_uv.data(), 32 * (size_t)s.Lq, hipMemcpyHostToDevice, st));
+  }
+  if (!s.tasks.empty())
+    HIPCHK(c, hipMemcpyAsync(base + lay.tasks, s.tasks.data(), sizeof(int4) * s.tasks.size(), hipMemcpyHostToDevice, st));
+  if (!s.targets.empty())
+    HIPCHK(c, hipMemcpyAsync(base + lay.targets, s.targets.data(), sizeof(int4) * s.targets.size(),
+                             hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C, hipMemcpyHostToDevice, st));
   if (s.P > 0) HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
@@ -459,7 +595,8 @@ int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   int rc = make_batch(c, l, slots, b);
   if (rc) return rc;
   int maxPL = 0;
-  for (int s : slots) maxPL = std::max({maxPL, c->slots[s].desc.P, c->slots[s].desc.L});
+  for (int s : slots)
+    maxPL = std::max({maxPL, c->slots[s].desc.P, c->slots[s].desc.L, c->slots[s].desc.Lc, 2 * c->slots[s].desc.Lq});
   HIPCHK(c, launch_prep(b, maxPL, c->stream));
   HIPCHK(c, launch_initial_cost(b, c->stream));
   return BA_OK;
@@ -472,7 +609,7 @@ int harvest_prof(ba_ctx* c) {
     auto& ev = c->prof_ev[i];
     for (int k = 0; k < BA_PROF_N; ++k) {
       float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      HIPCHK(c, hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
       c->prof_ms[k] += ms;
       c->prof_n[k] += 1;
     }
@@ -490,7 +627,7 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
     hipEvent_t* ev = nullptr;
     if (c->prof) {
       if (c->prof_used == c->prof_ev.size()) {
-        std::array<hipEvent_t, 6> set;
+        std::array<hipEvent_t, 2 * BA_PROF_N> set;
         for (auto& e : set) HIPCHK(c, hipEventCreate(&e));
         c->prof_ev.push_back(set);
       }
@@ -654,7 +791,8 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.max_queue <= 0) c->opt.max_queue = 4096;
   if (c->opt.iters_per_tick <= 0) c->opt.iters_per_tick = 2;
   if (c->opt.chunks_per_wg <= 0) c->opt.chunks_per_wg = 16;
-  if (c->opt.max_slots > 65536 || c->opt.chunks_per_wg > 4096) return BA_E_ARG;
+  if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
+  if (c->opt.max_slots > 65536 || c->opt.chunks_per_wg > 4096 || c->opt.chunks_per_task > 4096) return BA_E_ARG;
   c->device = opt->device;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return BA_E_DEVICE;
@@ -711,19 +849,19 @@ size_t ba_footprint(ba_ctx* c, const ba_cluster* cl) {
   if (!c) return 0;
   Staged s;
   std::string err;
-  if (stage(cl, s, err)) return 0;
-  return make_layout(s, c->opt.precision == BA_MIXED, c->opt.chunks_per_wg).total;
+  if (stage(cl, s, err, c->opt.chunks_per_wg, c->opt.chunks_per_task)) return 0;
+  return make_layout(s, c->opt.precision == BA_MIXED).total;
 }
 
 int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   if (!c || !ticket) return BA_E_ARG;
   auto st = std::make_unique<Staged>();
   std::string err;
-  int rc = stage(cl, *st, err);
+  int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task);
   std::lock_guard<std::mutex> g(c->mu);
   if (rc) return fail(c, rc, err);
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
-  const size_t bytes = make_layout(*st, c->opt.precision == BA_MIXED, c->opt.chunks_per_wg).total;
+  const size_t bytes = make_layout(*st, c->opt.precision == BA_MIXED).total;
   if (bytes > c->arena.size()) return fail(c, BA_E_NOMEM, "cluster footprint exceeds the arena");
   if ((int)c->queue.size() >= c->opt.max_queue) return fail(c, BA_E_AGAIN, "admission queue full");
   auto t = std::make_unique<Ticket>();
