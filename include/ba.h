@@ -198,8 +198,8 @@ size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
  * number of launches per kernel since the last read, in the order of
  * enum ba_prof_kernel, into caller arrays of BA_PROF_N entries, and resets
  * the counters.  Errors: BA_E_ARG, BA_E_DEVICE. */
-enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_BLOCKS = 1, BA_PROF_REDUCE = 2, BA_PROF_SOLVE = 3,
-                      BA_PROF_BACKSUB = 4, BA_PROF_LM = 5, BA_PROF_N = 6 };
+enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_CAMBLK = 1, BA_PROF_PAIRBLK = 2, BA_PROF_REDUCE = 3,
+                      BA_PROF_SOLVE = 4, BA_PROF_BACKSUB = 5, BA_PROF_LM = 6, BA_PROF_N = 7 };
 int ba_profile_enable(ba_ctx* ctx, int32_t enable);
 int ba_profile_read(ba_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -24,7 +24,7 @@ BA_MAX_OBS_PER_POINT = 64
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error"]
-BA_PROF_KERNELS = ["point", "blocks", "reduce", "solve", "backsub", "lm"]
+BA_PROF_KERNELS = ["point", "camblk", "pairblk", "reduce", "solve", "backsub", "lm"]
 
 
 class ba_options(ct.Structure):

@@ -16,7 +16,7 @@ constexpr int kMaxCams = 64;              // camera table kept in LDS
 constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
 constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
 constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
-constexpr int kPtVals = 18;               // per point: Q (6 packed symmetric), g (3), D (3), Z (6)
+constexpr int kPtVals = 16;               // per point: Q (6 packed symmetric), g (3), Z (6), pad (1)
 constexpr int kTaskVals = 52;             // per block task partial: camera task 51 values, pair task 36
 constexpr int kPtPartVals = 10;           // per point-pass wavefront: intrinsic-intrinsic terms
 constexpr int kBlk = 6;                   // block size of the reduced-system factorisation
@@ -32,12 +32,13 @@ struct SlotDesc {
   int m, n_free, kcol0, kcol1;            // reduced system size, free cameras, intrinsic columns (-1: fixed)
   int psize, pstride;                     // packed m(m+1)/2, reduced-system vector stride (psize + 3m)
   int max_iters, stop_on_ftol, mixed, nb;  // nb: 6x6 blocks per side of the reduced system
-  int Lc, Lq, n_tasks, n_task_wg, n_targets, n_pt_part;
+  int Lc, Lq, n_tasks, n_cam_tasks, n_cam_task_wg, n_pair_task_wg, n_targets, n_pt_part;
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
   // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
   const int* lane_pt;                     // [L] point index, -1 for padding
   const int* lane_cam;                    // [L] camera index
-  const int* lane_seg;                    // [L] (first lane of the point's segment in the chunk << 8) | length
+  const int* lane_seg;                    // [L] chunk's longest segment << 16 | first lane of the point's
+                                          //     segment in the chunk << 8 | its length
   double* lane_uv64;                      // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
   float* lane_uv32;                       // [2L]
   // camera lanes: observations of free cameras sorted by (camera, point), each
@@ -60,7 +61,9 @@ struct SlotDesc {
   // points
   double* X[2];                           // [P][3] state buffers (origin-shifted)
   float* X32[2];                          // [P][3] FP32 shadows of X
-  void* ptv;                              // [P][18] Real: Q, g, D, Z from the last assembly
+  void* ptv;                              // [P][16] Real: Q, g, Z (+1 pad) from the last point pass
+  void* ptd;                              // [P][4] Real: D_V (+1 pad)
+  const int* pt_orig;                     // [P] caller index of each internal point
   // reduced camera system
   void* task_part;                        // [n_tasks][52] Real: per-task block sums
   void* pt_part;                          // [n_pt_part][10] Real: per point-pass wavefront intrinsic sums
@@ -88,17 +91,18 @@ struct Batch {
   SlotCtl* ctl;
   const int* act;
   const int* wg_off;                      // point-lane chunk workgroups
-  const int* tk_off;                      // block-task workgroups (4 tasks each)
+  const int* tkc_off;                     // camera-task workgroups (4 tasks each)
+  const int* tkp_off;                     // pair-task workgroups (4 tasks each)
   const int* tg_off;                      // reduction targets
   int n_act;
-  int total_wg, total_tk_wg, total_tg;
+  int total_wg, total_tkc_wg, total_tkp_wg, total_tg;
   int max_m, max_C, max_pstride, max_nb;
 };
 
 hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st);
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
-// ev (optional): 12 events, the start and end of each of the six kernels of
-// the iteration, recorded by the kernel dispatches themselves.
+// ev (optional): 14 events, the start and end of each of the seven kernels
+// of the iteration, recorded by the kernel dispatches themselves.
 hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 

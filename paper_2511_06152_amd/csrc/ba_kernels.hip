@@ -1,14 +1,14 @@
 // HIP kernels (gfx950) of the cluster bundle-adjustment library.
 //
-// One Levenberg-Marquardt iteration over a batch of resident clusters is six
+// One Levenberg-Marquardt iteration over a batch of resident clusters is seven
 // launches, each covering every cluster of the batch:
 //
 //   k_point<Real>     per observation: residual of Eq. (5) with k1/k2 radial
 //                     terms, Huber IRLS weight (robust rho of Eq. 6/7), point
 //                     Jacobian; per point (wavefront-segmented sum): V_j, g_j
 //                     and the damped inverse
-//   k_blocks<Real>    one wavefront per task: a free camera's diagonal Schur
-//                     block (U_kk - sum W Q W^T, gradient, intrinsic border)
+//   k_camblk<Real>,   one wavefront per task: a free camera's diagonal Schur
+//   k_pairblk<Real>   block (U_kk - sum W Q W^T, gradient, intrinsic border)
 //                     over its observations, or one camera-pair block
 //                     (- sum W_a Q W_b^T) over the observation pairs of that
 //                     pair of cameras; register sums, fixed-order reductions
@@ -59,6 +59,39 @@ __device__ __forceinline__ void wave_sync() {
 
 template <typename T> __device__ __forceinline__ T clampd(T d) {
   return d < T(kDiagMin) ? T(kDiagMin) : (d > T(kDiagMax) ? T(kDiagMax) : d);
+}
+
+// Explicit fused multiply-add (the build does not contract a * b + c by itself)
+// and the depth reciprocal: the hardware reciprocal (1 ulp) in FP32, exact in FP64.
+__device__ __forceinline__ float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rcp(float z) { return __builtin_amdgcn_rcpf(z); }
+__device__ __forceinline__ double rcp(double z) { return 1.0 / z; }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+// Per-point record (kPtVals Real): vector loads/stores of its first n values.
+__device__ __forceinline__ void pt_load(const float* __restrict__ p, float* v, int n) {
+  for (int i = 0; i < n; i += 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p + i);
+    v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
+  }
+}
+__device__ __forceinline__ void pt_load(const double* __restrict__ p, double* v, int n) {
+  for (int i = 0; i < n; i += 2) {
+    const double2 t = *reinterpret_cast<const double2*>(p + i);
+    v[i] = t.x; v[i + 1] = t.y;
+  }
+}
+template <int N>
+__device__ __forceinline__ void pt_store(float* p, const float* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4) *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+}
+template <int N>
+__device__ __forceinline__ void pt_store(double* p, const double* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 2) *reinterpret_cast<double2*>(p + i) = make_double2(v[i], v[i + 1]);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -179,35 +212,36 @@ __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0,
                                           const R v, const R f, const R k1, const R k2, const R is, const R dt,
                                           bool valid, ObsJ<R>& o) {
   const R d0 = X0 - cam[9], d1 = X1 - cam[10], d2 = X2 - cam[11];
-  R x = cam[0] * d0 + cam[3] * d1 + cam[6] * d2;
-  R y = cam[1] * d0 + cam[4] * d1 + cam[7] * d2;
-  R z = cam[2] * d0 + cam[5] * d1 + cam[8] * d2;
+  R x = fm(cam[6], d2, fm(cam[3], d1, cam[0] * d0));
+  R y = fm(cam[7], d2, fm(cam[4], d1, cam[1] * d0));
+  R z = fm(cam[8], d2, fm(cam[5], d1, cam[2] * d0));
   if (!valid || !(z > R(0))) { x = R(0); y = R(0); z = R(1); valid = false; }
   o.xc[0] = x; o.xc[1] = y; o.xc[2] = z;
-  const R iz = R(1) / z;
+  const R iz = rcp(z);
   const R a = x * iz, b = y * iz;
-  const R r2 = a * a + b * b;
-  const R D = R(1) + k1 * r2 + k2 * r2 * r2;
+  const R r2 = fm(a, a, b * b);
+  const R D = fm(r2, fm(k2, r2, k1), R(1));     // 1 + k1 r^2 + k2 r^4
+  const R fD = f * D;
   const R fis = f * is;
-  o.e[0] = (f * D * a - u) * is;
-  o.e[1] = (f * D * b - v) * is;
-  const R s = o.e[0] * o.e[0] + o.e[1] * o.e[1];
-  o.w = valid ? (s <= dt * dt ? R(1) : dt / sqrt(s)) : R(0);
-  const R q = k1 + R(2) * k2 * r2;
-  const R A00 = fis * (D + R(2) * a * a * q), A01 = fis * (R(2) * a * b * q), A11 = fis * (D + R(2) * b * b * q);
-  const R Jx[2][3] = {{A00 * iz, A01 * iz, -(A00 * a + A01 * b) * iz},
-                      {A01 * iz, A11 * iz, -(A01 * a + A11 * b) * iz}};
+  o.e[0] = fm(fD, a, -u) * is;
+  o.e[1] = fm(fD, b, -v) * is;
+  const R s = fm(o.e[0], o.e[0], o.e[1] * o.e[1]);
+  o.w = valid ? (s <= dt * dt ? R(1) : dt * rsq(s)) : R(0);
+  const R q2 = R(2) * fm(R(2) * k2, r2, k1);     // 2 (k1 + 2 k2 r^2)
+  const R A00 = fis * fm(q2 * a, a, D), A01 = fis * (q2 * a * b), A11 = fis * fm(q2 * b, b, D);
+  const R Jx[2][3] = {{A00 * iz, A01 * iz, -fm(A00, a, A01 * b) * iz},
+                      {A01 * iz, A11 * iz, -fm(A01, a, A11 * b) * iz}};
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) o.Jp[i][j] = Jx[i][0] * cam[3 * j] + Jx[i][1] * cam[3 * j + 1] + Jx[i][2] * cam[3 * j + 2];
-    o.Jw[i][0] = Jx[i][1] * z - Jx[i][2] * y;
-    o.Jw[i][1] = Jx[i][2] * x - Jx[i][0] * z;
-    o.Jw[i][2] = Jx[i][0] * y - Jx[i][1] * x;
+    for (int j = 0; j < 3; ++j) o.Jp[i][j] = fm(Jx[i][2], cam[3 * j + 2], fm(Jx[i][1], cam[3 * j + 1], Jx[i][0] * cam[3 * j]));
+    o.Jw[i][0] = fm(Jx[i][1], z, -(Jx[i][2] * y));
+    o.Jw[i][1] = fm(Jx[i][2], x, -(Jx[i][0] * z));
+    o.Jw[i][2] = fm(Jx[i][0], y, -(Jx[i][1] * x));
   }
-  const R r4 = r2 * r2;
-  o.Jk[0][0] = fis * r2 * a; o.Jk[0][1] = fis * r4 * a;
-  o.Jk[1][0] = fis * r2 * b; o.Jk[1][1] = fis * r4 * b;
+  const R fr2 = fis * r2, fr4 = fr2 * r2;
+  o.Jk[0][0] = fr2 * a; o.Jk[0][1] = fr4 * a;
+  o.Jk[1][0] = fr2 * b; o.Jk[1][1] = fr4 * b;
 }
 
 // Camera-side whitened Jacobian column r (0..5) of row i: [Jw | -Jp].
@@ -238,25 +272,23 @@ __device__ __forceinline__ bool obs_rho(const double* __restrict__ cam, const do
 // Inverse of the 3x3 SPD matrix (a00 a01 a02 a11 a12 a22) via Cholesky.
 template <typename R>
 __device__ __forceinline__ bool spd3_inv(const R A[6], R Q[6]) {
-  const R l00s = A[0];
-  if (!(l00s > R(0))) return false;
-  const R l00 = sqrt(l00s);
-  const R l10 = A[1] / l00, l20 = A[2] / l00;
+  if (!(A[0] > R(0))) return false;
+  const R i00 = rsq(A[0]);
+  const R l10 = A[1] * i00, l20 = A[2] * i00;
   const R l11s = A[3] - l10 * l10;
   if (!(l11s > R(0))) return false;
-  const R l11 = sqrt(l11s);
-  const R l21 = (A[4] - l20 * l10) / l11;
+  const R i11 = rsq(l11s);
+  const R l21 = (A[4] - l20 * l10) * i11;
   const R l22s = A[5] - l20 * l20 - l21 * l21;
   if (!(l22s > R(0))) return false;
-  const R l22 = sqrt(l22s);
-  const R i00 = R(1) / l00, i11 = R(1) / l11, i22 = R(1) / l22;
+  const R i22 = rsq(l22s);
   const R i10 = -l10 * i00 * i11;
   const R i21 = -l21 * i11 * i22;
-  const R i20 = -(l20 * i00 + l21 * i10) * i22;
-  Q[0] = i00 * i00 + i10 * i10 + i20 * i20;
-  Q[1] = i10 * i11 + i20 * i21;
+  const R i20 = -fm(l20, i00, l21 * i10) * i22;
+  Q[0] = fm(i00, i00, fm(i10, i10, i20 * i20));
+  Q[1] = fm(i10, i11, i20 * i21);
   Q[2] = i20 * i22;
-  Q[3] = i11 * i11 + i21 * i21;
+  Q[3] = fm(i11, i11, i21 * i21);
   Q[4] = i21 * i22;
   Q[5] = i22 * i22;
   return true;
@@ -425,29 +457,23 @@ __global__ void k_init(Batch bt) {
 // of one wavefront.  Writes, per point, Q = (V + lambda D_V)^-1, g_p, D_V and
 // Z = sum of the intrinsic rows of W; per wavefront, the intrinsic-intrinsic
 // sums (U part of all observations, Schur part of all points).
-template <typename R>
-__global__ __launch_bounds__(kWG) void k_point(Batch bt) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.wg_off, bt.n_act, blockIdx.x);
-  const int s = bt.act[si];
-  const int wgl = blockIdx.x - bt.wg_off[si];
-  const SlotDesc& d = bt.desc[s];
-  SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
-  R* scam = reinterpret_cast<R*>(smem);
-  R* scr_all = scam + bt.max_C * kCamVals;
+// Observation lanes of chunk ch: seg = first lane of the point's segment << 8 |
+// its length, with the chunk's longest segment in bits 16..23.
+__device__ __forceinline__ int seg_first(int seg) { return (seg >> 8) & 255; }
+__device__ __forceinline__ int seg_len(int seg) { return seg & 255; }
+__device__ __forceinline__ int chunk_maxlen(int seg) { return __builtin_amdgcn_readfirstlane((seg >> 16) & 255); }
+
+template <typename R, bool INTR>
+__device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const R* scam, R* scr, int wgl, int wave,
+                                           int lane) {
+  constexpr int NV = INTR ? 15 : 9;
   const int cur = c.cur;
-  for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) scam[i] = (R)d.cam[cur][i];
-  __syncthreads();
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  R* scr = scr_all + wave * 15 * kWave;
   const R lam = (R)c.lambda;
   const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
-  const bool intr = (d.kcol0 >= 0) || (d.kcol1 >= 0);
   const bool mixed = sizeof(R) == 4;
   R* __restrict__ ptv = reinterpret_cast<R*>(d.ptv);
+  R* __restrict__ ptd = reinterpret_cast<R*>(d.ptd);
   R iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // S(k0k0) S(k0k1) S(k1k1) g0 g1 dU0 dU1 bS0 bS1
   bool fail = false;
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
@@ -457,8 +483,7 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
     const bool valid = pt >= 0;
     const int cam = valid ? d.lane_cam[idx] : 0;
     const int seg = d.lane_seg[idx];
-    const int sb = seg >> 8, sl = seg & 255;
-    const int maxl = wave_max(sl);
+    const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
     const bool head = valid && sb == lane;
     R X0 = 0, X1 = 0, X2 = 0, u = 0, v = 0;
     if (valid) {
@@ -478,72 +503,84 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int t = 0; t < 3; ++t) wJp[i][t] = w * o.Jp[i][t];
-    R vals[15];
-    vals[0] = o.Jp[0][0] * wJp[0][0] + o.Jp[1][0] * wJp[1][0];
-    vals[1] = o.Jp[0][0] * wJp[0][1] + o.Jp[1][0] * wJp[1][1];
-    vals[2] = o.Jp[0][0] * wJp[0][2] + o.Jp[1][0] * wJp[1][2];
-    vals[3] = o.Jp[0][1] * wJp[0][1] + o.Jp[1][1] * wJp[1][1];
-    vals[4] = o.Jp[0][1] * wJp[0][2] + o.Jp[1][1] * wJp[1][2];
-    vals[5] = o.Jp[0][2] * wJp[0][2] + o.Jp[1][2] * wJp[1][2];
+    R vals[NV];
+    vals[0] = fm(o.Jp[0][0], wJp[0][0], o.Jp[1][0] * wJp[1][0]);
+    vals[1] = fm(o.Jp[0][0], wJp[0][1], o.Jp[1][0] * wJp[1][1]);
+    vals[2] = fm(o.Jp[0][0], wJp[0][2], o.Jp[1][0] * wJp[1][2]);
+    vals[3] = fm(o.Jp[0][1], wJp[0][1], o.Jp[1][1] * wJp[1][1]);
+    vals[4] = fm(o.Jp[0][1], wJp[0][2], o.Jp[1][1] * wJp[1][2]);
+    vals[5] = fm(o.Jp[0][2], wJp[0][2], o.Jp[1][2] * wJp[1][2]);
 #pragma unroll
-    for (int t = 0; t < 3; ++t) vals[6 + t] = wJp[0][t] * o.e[0] + wJp[1][t] * o.e[1];
+    for (int t = 0; t < 3; ++t) vals[6 + t] = fm(wJp[0][t], o.e[0], wJp[1][t] * o.e[1]);
+    if constexpr (INTR) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) vals[9 + 3 * b + t] = o.Jk[0][b] * wJp[0][t] + o.Jk[1][b] * wJp[1][t];
-    const int nv = intr ? 15 : 9;
+        for (int t = 0; t < 3; ++t) vals[9 + 3 * b + t] = fm(o.Jk[0][b], wJp[0][t], o.Jk[1][b] * wJp[1][t]);
+    }
+    // segmented sums over the point's lanes (fixed order: first lane to last)
     wave_sync();
-    for (int i = 0; i < nv; ++i) scr[i * kWave + lane] = vals[i];
-    wave_sync();
-    R sum[15];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) sum[i] = R(0);
+    for (int i = 0; i < NV; ++i) scr[i * kWave + lane] = vals[i];
+    wave_sync();
+    R sum[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sum[i] = R(0);
     for (int t = 0; t < maxl; ++t) {
       if (t < sl) {
         const int src = sb + t;
-        for (int i = 0; i < nv; ++i) sum[i] += scr[i * kWave + src];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sum[i] += scr[i * kWave + src];
       }
     }
     const R Dp[3] = {clampd(sum[0]), clampd(sum[3]), clampd(sum[5])};
-    const R Vl[6] = {sum[0] + lam * Dp[0], sum[1], sum[2], sum[3] + lam * Dp[1], sum[4], sum[5] + lam * Dp[2]};
+    const R Vl[6] = {fm(lam, Dp[0], sum[0]), sum[1], sum[2], fm(lam, Dp[1], sum[3]), sum[4], fm(lam, Dp[2], sum[5])};
     R Q[6];
     if (!spd3_inv(Vl, Q)) {
       if (valid) fail = true;
+#pragma unroll
       for (int i = 0; i < 6; ++i) Q[i] = R(0);
     }
     if (head) {
-      R* pv = ptv + kPtVals * (size_t)pt;
-      for (int i = 0; i < 6; ++i) pv[i] = Q[i];
-      for (int i = 0; i < 3; ++i) pv[6 + i] = sum[6 + i];
-      for (int i = 0; i < 3; ++i) pv[9 + i] = Dp[i];
-      for (int i = 0; i < 6; ++i) pv[12 + i] = sum[9 + i];
+      R rec[kPtVals];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rec[i] = Q[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[6 + i] = sum[6 + i];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rec[9 + i] = INTR ? sum[(9 + i) % NV] : R(0);
+      rec[15] = R(0);
+      pt_store<kPtVals>(ptv + kPtVals * (size_t)pt, rec);
+      const R dr[4] = {Dp[0], Dp[1], Dp[2], R(0)};
+      pt_store<4>(ptd + 4 * (size_t)pt, dr);
     }
-    if (intr) {
-      const R u00 = w * (o.Jk[0][0] * o.Jk[0][0] + o.Jk[1][0] * o.Jk[1][0]);
-      const R u11 = w * (o.Jk[0][1] * o.Jk[0][1] + o.Jk[1][1] * o.Jk[1][1]);
+    if constexpr (INTR) {
+      const R u00 = w * fm(o.Jk[0][0], o.Jk[0][0], o.Jk[1][0] * o.Jk[1][0]);
+      const R u11 = w * fm(o.Jk[0][1], o.Jk[0][1], o.Jk[1][1] * o.Jk[1][1]);
       iv[0] += u00;
-      iv[1] += w * (o.Jk[0][0] * o.Jk[0][1] + o.Jk[1][0] * o.Jk[1][1]);
+      iv[1] += w * fm(o.Jk[0][0], o.Jk[0][1], o.Jk[1][0] * o.Jk[1][1]);
       iv[2] += u11;
-      iv[3] += w * (o.Jk[0][0] * o.e[0] + o.Jk[1][0] * o.e[1]);
-      iv[4] += w * (o.Jk[0][1] * o.e[0] + o.Jk[1][1] * o.e[1]);
+      iv[3] += w * fm(o.Jk[0][0], o.e[0], o.Jk[1][0] * o.e[1]);
+      iv[4] += w * fm(o.Jk[0][1], o.e[0], o.Jk[1][1] * o.e[1]);
       iv[5] += u00;
       iv[6] += u11;
       if (head) {
-        const R Z[2][3] = {{sum[9], sum[10], sum[11]}, {sum[12], sum[13], sum[14]}};
+        const R Z[2][3] = {{sum[9 % NV], sum[10 % NV], sum[11 % NV]}, {sum[12 % NV], sum[13 % NV], sum[14 % NV]}};
         R ZQ[2][3];
+#pragma unroll
         for (int b = 0; b < 2; ++b)
-          for (int t = 0; t < 3; ++t)
-            ZQ[b][t] = Z[b][0] * qel(Q, 0, t) + Z[b][1] * qel(Q, 1, t) + Z[b][2] * qel(Q, 2, t);
-        iv[0] -= ZQ[0][0] * Z[0][0] + ZQ[0][1] * Z[0][1] + ZQ[0][2] * Z[0][2];
-        iv[1] -= ZQ[0][0] * Z[1][0] + ZQ[0][1] * Z[1][1] + ZQ[0][2] * Z[1][2];
-        iv[2] -= ZQ[1][0] * Z[1][0] + ZQ[1][1] * Z[1][1] + ZQ[1][2] * Z[1][2];
-        iv[7] += ZQ[0][0] * sum[6] + ZQ[0][1] * sum[7] + ZQ[0][2] * sum[8];
-        iv[8] += ZQ[1][0] * sum[6] + ZQ[1][1] * sum[7] + ZQ[1][2] * sum[8];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) ZQ[b][t] = fm(Z[b][0], qel(Q, 0, t), fm(Z[b][1], qel(Q, 1, t), Z[b][2] * qel(Q, 2, t)));
+        iv[0] -= fm(ZQ[0][0], Z[0][0], fm(ZQ[0][1], Z[0][1], ZQ[0][2] * Z[0][2]));
+        iv[1] -= fm(ZQ[0][0], Z[1][0], fm(ZQ[0][1], Z[1][1], ZQ[0][2] * Z[1][2]));
+        iv[2] -= fm(ZQ[1][0], Z[1][0], fm(ZQ[1][1], Z[1][1], ZQ[1][2] * Z[1][2]));
+        iv[7] += fm(ZQ[0][0], sum[6], fm(ZQ[0][1], sum[7], ZQ[0][2] * sum[8]));
+        iv[8] += fm(ZQ[1][0], sum[6], fm(ZQ[1][1], sum[7], ZQ[1][2] * sum[8]));
       }
     }
   }
   if (fail) atomicOr(&c.point_fail, 1);
-  if (intr) {
+  if constexpr (INTR) {
     R* pp = reinterpret_cast<R*>(d.pt_part) + (size_t)(wgl * kWavesPerWG + wave) * kPtPartVals;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -553,9 +590,37 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   }
 }
 
-// ---- block pass: camera-diagonal and camera-pair blocks of the Schur complement ----
+// ---- point pass: damped point blocks --------------------------------------------
 //
-// One wavefront per task.  A camera task sums, over a run of observations of
+// One lane per observation, the observations of a point in consecutive lanes
+// of one wavefront.  Writes, per point, Q = (V + lambda D_V)^-1, g_p, Z = sum
+// of the intrinsic rows of W, and D_V; per wavefront, the intrinsic-intrinsic
+// sums (U part of all observations, Schur part of all points).
+template <typename R>
+__global__ __launch_bounds__(kWG) void k_point(Batch bt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
+  const int si = find_slot(bt.wg_off, bt.n_act, blockIdx.x);
+  const int s = bt.act[si];
+  const int wgl = blockIdx.x - bt.wg_off[si];
+  const SlotDesc& d = bt.desc[s];
+  SlotCtl& c = bt.ctl[s];
+  if (c.status != ST_RUNNING) return;
+  R* scam = reinterpret_cast<R*>(smem);
+  R* scr_all = scam + bt.max_C * kCamVals;
+  const int cur = c.cur;
+  for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) scam[i] = (R)d.cam[cur][i];
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  R* scr = scr_all + wave * 15 * kWave;
+  if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true>(d, c, scam, scr, wgl, wave, lane);
+  else point_pass<R, false>(d, c, scam, scr, wgl, wave, lane);
+}
+
+// ---- block passes: camera-diagonal and camera-pair blocks of the Schur complement ----
+//
+// One wavefront per task (k_camblk: camera tasks, k_pairblk: pair tasks; two
+// kernels so that each gets the register allocation it needs).  A camera task sums, over a run of observations of
 // one free camera, its diagonal block U_kk - sum Y W^T, g_k, sum Y g_p, diag
 // U_kk and its intrinsic border; a pair task sums -Y_a W_b^T over a run of
 // observation pairs (same point, cameras a < b).  Sums stay in registers and
@@ -577,7 +642,16 @@ __device__ __forceinline__ void cam_w(const ObsJ<R>& o, R Wc[6][3], R wJp[2][3])
 #pragma unroll
   for (int r = 0; r < 6; ++r)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) Wc[r][t] = jc(o, 0, r) * wJp[0][t] + jc(o, 1, r) * wJp[1][t];
+    for (int t = 0; t < 3; ++t) Wc[r][t] = fm(jc(o, 0, r), wJp[0][t], jc(o, 1, r) * wJp[1][t]);
+}
+
+// Y = W Q for the 6 camera rows of W (Q symmetric, packed).
+template <typename R>
+__device__ __forceinline__ void times_q(const R W[6][3], const R Q[6], R Y[6][3]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Y[r][q] = fm(W[r][2], qel(Q, 2, q), fm(W[r][1], qel(Q, 1, q), W[r][0] * qel(Q, 0, q)));
 }
 
 template <typename R, int N>
@@ -590,19 +664,19 @@ __device__ __forceinline__ void wave_store(R (&acc)[N], R* out, int lane) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(kWG) void k_blocks(Batch bt) {
+__global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.tk_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.tkc_off, bt.n_act, blockIdx.x);
   const int s = bt.act[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int t = (blockIdx.x - bt.tk_off[si]) * kWavesPerWG + wave;
-  if (t >= d.n_tasks) return;
+  const int t = 0 + (blockIdx.x - bt.tkc_off[si]) * kWavesPerWG + wave;
+  if (t >= d.n_cam_tasks) return;
   const int4 tk = d.tasks[t];
-  const int kind = tk.x >> 24, ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
+  const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
   const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
@@ -611,7 +685,8 @@ __global__ __launch_bounds__(kWG) void k_blocks(Batch bt) {
   R* part = reinterpret_cast<R*>(d.task_part) + (size_t)t * kTaskVals;
   R ca[kCamVals];
   load_cam(d.cam[cur] + kCamVals * ka, ca);
-  if (kind == TASK_CAM) {
+  (void)kb;
+
     const bool i0 = d.kcol0 >= 0, i1 = d.kcol1 >= 0;
     R acc[51];
 #pragma unroll
@@ -634,40 +709,63 @@ __global__ __launch_bounds__(kWG) void k_blocks(Batch bt) {
       obs_model<R>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
       R Wc[6][3], wJp[2][3];
       cam_w(o, Wc, wJp);
-      R Q[6] = {0, 0, 0, 0, 0, 0}, gp[3] = {0, 0, 0}, Z[2][3] = {{0, 0, 0}, {0, 0, 0}};
-      if (valid) {
-        const R* pv = ptv + kPtVals * (size_t)pt;
-        for (int i = 0; i < 6; ++i) Q[i] = pv[i];
-        for (int i = 0; i < 3; ++i) gp[i] = pv[6 + i];
-        if (i0 || i1)
-          for (int i = 0; i < 3; ++i) { Z[0][i] = pv[12 + i]; Z[1][i] = pv[15 + i]; }
-      }
-      R Y[6][3];
+      R rec[kPtVals];
 #pragma unroll
-      for (int r = 0; r < 6; ++r)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          Y[r][q] = Wc[r][0] * qel(Q, 0, q) + Wc[r][1] * qel(Q, 1, q) + Wc[r][2] * qel(Q, 2, q);
+      for (int i = 0; i < kPtVals; ++i) rec[i] = R(0);
+      if (valid) pt_load(ptv + kPtVals * (size_t)pt, rec, (i0 || i1) ? 16 : (sizeof(R) == 8 ? 10 : 12));
+      const R* Q = rec;
+      const R* gp = rec + 6;
+      const R Z[2][3] = {{rec[9], rec[10], rec[11]}, {rec[12], rec[13], rec[14]}};
       const R w = o.w;
       int e = 0;
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const R jr0 = jc(o, 0, r), jr1 = jc(o, 1, r);
+        const R wr0 = w * jc(o, 0, r), wr1 = w * jc(o, 1, r);   // row r of w J_c^T
+        R Yr[3];                                              // row r of Y = W Q
 #pragma unroll
-        for (int cc = r; cc < 6; ++cc, ++e)
-          acc[e] += w * (jr0 * jc(o, 0, cc) + jr1 * jc(o, 1, cc)) -
-                    (Y[r][0] * Wc[cc][0] + Y[r][1] * Wc[cc][1] + Y[r][2] * Wc[cc][2]);
-        acc[21 + r] += w * (jr0 * o.e[0] + jr1 * o.e[1]);
-        acc[27 + r] += Y[r][0] * gp[0] + Y[r][1] * gp[1] + Y[r][2] * gp[2];
-        acc[33 + r] += w * (jr0 * jr0 + jr1 * jr1);
-        if (i0) acc[39 + r] += w * (jr0 * o.Jk[0][0] + jr1 * o.Jk[1][0]) -
-                               (Y[r][0] * Z[0][0] + Y[r][1] * Z[0][1] + Y[r][2] * Z[0][2]);
-        if (i1) acc[45 + r] += w * (jr0 * o.Jk[0][1] + jr1 * o.Jk[1][1]) -
-                               (Y[r][0] * Z[1][0] + Y[r][1] * Z[1][1] + Y[r][2] * Z[1][2]);
+        for (int q = 0; q < 3; ++q) Yr[q] = fm(Wc[r][2], qel(Q, 2, q), fm(Wc[r][1], qel(Q, 1, q), Wc[r][0] * qel(Q, 0, q)));
+#pragma unroll
+        for (int cc = r; cc < 6; ++cc, ++e) {
+          const R u = fm(wr0, jc(o, 0, cc), wr1 * jc(o, 1, cc));
+          acc[e] += fm(-Yr[2], Wc[cc][2], fm(-Yr[1], Wc[cc][1], fm(-Yr[0], Wc[cc][0], u)));
+        }
+        acc[21 + r] += fm(wr0, o.e[0], wr1 * o.e[1]);
+        acc[27 + r] += fm(Yr[2], gp[2], fm(Yr[1], gp[1], Yr[0] * gp[0]));
+        acc[33 + r] += fm(wr0, jc(o, 0, r), wr1 * jc(o, 1, r));
+        if (i0)
+          acc[39 + r] += fm(-Yr[2], Z[0][2], fm(-Yr[1], Z[0][1], fm(-Yr[0], Z[0][0],
+                             fm(wr0, o.Jk[0][0], wr1 * o.Jk[1][0]))));
+        if (i1)
+          acc[45 + r] += fm(-Yr[2], Z[1][2], fm(-Yr[1], Z[1][1], fm(-Yr[0], Z[1][0],
+                             fm(wr0, o.Jk[0][1], wr1 * o.Jk[1][1]))));
       }
     }
     wave_store(acc, part, lane);
-  } else {
+}
+
+template <typename R>
+__global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
+  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
+  const int si = find_slot(bt.tkp_off, bt.n_act, blockIdx.x);
+  const int s = bt.act[si];
+  const SlotDesc& d = bt.desc[s];
+  const SlotCtl& c = bt.ctl[s];
+  if (c.status != ST_RUNNING) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int t = d.n_cam_tasks + (blockIdx.x - bt.tkp_off[si]) * kWavesPerWG + wave;
+  if (t >= d.n_tasks) return;
+  const int4 tk = d.tasks[t];
+  const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
+  const int cur = c.cur;
+  const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
+  const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
+  const bool mixed = sizeof(R) == 4;
+  const R* __restrict__ ptv = reinterpret_cast<const R*>(d.ptv);
+  R* part = reinterpret_cast<R*>(d.task_part) + (size_t)t * kTaskVals;
+  R ca[kCamVals];
+  load_cam(d.cam[cur] + kCamVals * ka, ca);
+
     R cb[kCamVals];
     load_cam(d.cam[cur] + kCamVals * kb, cb);
     R acc[36];
@@ -695,14 +793,9 @@ __global__ __launch_bounds__(kWG) void k_blocks(Batch bt) {
         obs_model<R>(ca, X0, X1, X2, ua, va, f, k1, k2, is, dt, valid, oa);
         R Wa[6][3], wJp[2][3];
         cam_w(oa, Wa, wJp);
-        R Q[6] = {0, 0, 0, 0, 0, 0};
-        if (valid)
-          for (int i = 0; i < 6; ++i) Q[i] = ptv[kPtVals * (size_t)pt + i];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int q = 0; q < 3; ++q)
-            Y[r][q] = Wa[r][0] * qel(Q, 0, q) + Wa[r][1] * qel(Q, 1, q) + Wa[r][2] * qel(Q, 2, q);
+        R Q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (valid) pt_load(ptv + kPtVals * (size_t)pt, Q, sizeof(R) == 8 ? 6 : 8);
+        times_q(Wa, Q, Y);
       }
       ObsJ<R> ob;
       obs_model<R>(cb, X0, X1, X2, ub, vb, f, k1, k2, is, dt, valid, ob);
@@ -712,10 +805,9 @@ __global__ __launch_bounds__(kWG) void k_blocks(Batch bt) {
       for (int r = 0; r < 6; ++r)
 #pragma unroll
         for (int cc = 0; cc < 6; ++cc)
-          acc[6 * r + cc] -= Y[r][0] * Wb[cc][0] + Y[r][1] * Wb[cc][1] + Y[r][2] * Wb[cc][2];
+          acc[6 * r + cc] = fm(-Y[r][2], Wb[cc][2], fm(-Y[r][1], Wb[cc][1], fm(-Y[r][0], Wb[cc][0], acc[6 * r + cc])));
     }
     wave_store(acc, part, lane);
-  }
 }
 
 // ---- reduction of the task partials into the packed reduced system ----------------
@@ -1168,8 +1260,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
     const bool valid = pt >= 0;
     const int cam = valid ? d.lane_cam[idx] : 0;
     const int seg = d.lane_seg[idx];
-    const int sb = seg >> 8, sl = seg & 255;
-    const int maxl = wave_max(sl);
+    const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
     const bool head = valid && sb == lane;
     double Xd[3] = {0, 0, 0};
     R X0 = 0, X1 = 0, X2 = 0, u = 0, v = 0;
@@ -1193,14 +1284,14 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
       if (fi >= 0) {
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
-          jd[0] += jc(o, 0, r) * sdc[fi + r];
-          jd[1] += jc(o, 1, r) * sdc[fi + r];
+          jd[0] = fm(jc(o, 0, r), sdc[fi + r], jd[0]);
+          jd[1] = fm(jc(o, 1, r), sdc[fi + r], jd[1]);
         }
       }
-      jd[0] += o.Jk[0][0] * dk0 + o.Jk[0][1] * dk1;
-      jd[1] += o.Jk[1][0] * dk0 + o.Jk[1][1] * dk1;
+      jd[0] = fm(o.Jk[0][0], dk0, fm(o.Jk[0][1], dk1, jd[0]));
+      jd[1] = fm(o.Jk[1][0], dk0, fm(o.Jk[1][1], dk1, jd[1]));
 #pragma unroll
-      for (int t = 0; t < 3; ++t) tv[t] = o.w * (o.Jp[0][t] * jd[0] + o.Jp[1][t] * jd[1]);
+      for (int t = 0; t < 3; ++t) tv[t] = o.w * fm(o.Jp[0][t], jd[0], o.Jp[1][t] * jd[1]);
     }
     wave_sync();
     for (int t = 0; t < 3; ++t) scr[t * kWave + lane] = tv[t];
@@ -1214,17 +1305,20 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
     }
     double Xn[3] = {Xd[0], Xd[1], Xd[2]};
     if (valid) {
-      const R* pv = ptv + kPtVals * (size_t)pt;
-      R Q[6];
-      for (int i = 0; i < 6; ++i) Q[i] = pv[i];
+      R pv[12];
+      pt_load(ptv + kPtVals * (size_t)pt, pv, sizeof(R) == 8 ? 10 : 12);
+      R dv[4];
+      pt_load(reinterpret_cast<const R*>(d.ptd) + 4 * (size_t)pt, dv, 4);
+      const R* Q = pv;
       const R rr[3] = {-pv[6] - ts[0], -pv[7] - ts[1], -pv[8] - ts[2]};
       R dp[3];
-      for (int t = 0; t < 3; ++t) dp[t] = qel(Q, t, 0) * rr[0] + qel(Q, t, 1) * rr[1] + qel(Q, t, 2) * rr[2];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) dp[t] = fm(qel(Q, t, 2), rr[2], fm(qel(Q, t, 1), rr[1], qel(Q, t, 0) * rr[0]));
       for (int t = 0; t < 3; ++t) Xn[t] = Xd[t] + (double)dp[t];
       if (head) {
         for (int t = 0; t < 3; ++t) {
           const double dd = (double)dp[t];
-          pred_sum += dd * (lambda * (double)pv[9 + t] * dd - (double)pv[6 + t]);
+          pred_sum += dd * (lambda * (double)dv[t] * dd - (double)pv[6 + t]);
           d.X[nxt][3 * pt + t] = Xn[t];
           d.X32[nxt][3 * pt + t] = (float)Xn[t];
         }
@@ -1308,8 +1402,10 @@ __global__ void k_export(Batch bt) {
   const SlotCtl& c = bt.ctl[s];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int cur = c.cur;
-  if (i < d.P)
-    for (int t = 0; t < 3; ++t) d.out[12 * d.C + 3 * i + t] = d.X[cur][3 * i + t] + c.origin[t];
+  if (i < d.P) {
+    const int o = d.pt_orig[i];
+    for (int t = 0; t < 3; ++t) d.out[12 * d.C + 3 * o + t] = d.X[cur][3 * i + t] + c.origin[t];
+  }
   if (i < d.C) {
     const double* cm = d.cam[cur] + kCamVals * i;
     for (int t = 0; t < 9; ++t) d.out[9 * i + t] = cm[t];
@@ -1393,8 +1489,7 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   if ((e = ensure_smem(fb, sb))) return e;
   // Every profiled kernel needs a dispatch to carry its events, also when a
   // batch has no work for it: a one-block launch that returns at once.
-  const dim3 g_pt(b.total_wg > 0 ? b.total_wg : 1), g_tk(b.total_tk_wg > 0 ? b.total_tk_wg : 1),
-      g_tg(b.total_tg > 0 ? b.total_tg : 1);
+  const dim3 g_pt(b.total_wg > 0 ? b.total_wg : 1), g_tg(b.total_tg > 0 ? b.total_tg : 1);
   Batch nob = b;
   nob.n_act = 0;
   if (b.total_wg > 0 || ev) {
@@ -1402,23 +1497,30 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
     if (mixed) launch(k_point<float>, g_pt, dim3(kWG), sp, st, ev, 0, bb);
     else launch(k_point<double>, g_pt, dim3(kWG), sp, st, ev, 0, bb);
   }
-  if (b.total_tk_wg > 0 || ev) {
-    const Batch& bb = b.total_tk_wg > 0 ? b : nob;
-    if (mixed) launch(k_blocks<float>, g_tk, dim3(kWG), 0, st, ev, 1, bb);
-    else launch(k_blocks<double>, g_tk, dim3(kWG), 0, st, ev, 1, bb);
+  if (b.total_tkc_wg > 0 || ev) {
+    const Batch& bb = b.total_tkc_wg > 0 ? b : nob;
+    const dim3 g(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1);
+    if (mixed) launch(k_camblk<float>, g, dim3(kWG), 0, st, ev, 1, bb);
+    else launch(k_camblk<double>, g, dim3(kWG), 0, st, ev, 1, bb);
+  }
+  if (b.total_tkp_wg > 0 || ev) {
+    const Batch& bb = b.total_tkp_wg > 0 ? b : nob;
+    const dim3 g(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1);
+    if (mixed) launch(k_pairblk<float>, g, dim3(kWG), 0, st, ev, 2, bb);
+    else launch(k_pairblk<double>, g, dim3(kWG), 0, st, ev, 2, bb);
   }
   if (b.total_tg > 0 || ev) {
     const Batch& bb = b.total_tg > 0 ? b : nob;
-    if (mixed) launch(k_reduce<float>, g_tg, dim3(kReduceThreads), 0, st, ev, 2, bb);
-    else launch(k_reduce<double>, g_tg, dim3(kReduceThreads), 0, st, ev, 2, bb);
+    if (mixed) launch(k_reduce<float>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
+    else launch(k_reduce<double>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
   }
-  launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 3, b);
+  launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 4, b);
   if (b.total_wg > 0 || ev) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, ev, 4, bb);
-    else launch(k_backsub<double>, g_pt, dim3(kWG), sb, st, ev, 4, bb);
+    if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, ev, 5, bb);
+    else launch(k_backsub<double>, g_pt, dim3(kWG), sb, st, ev, 5, bb);
   }
-  launch(k_lm, dim3(b.n_act), dim3(64), 0, st, ev, 5, b);
+  launch(k_lm, dim3(b.n_act), dim3(64), 0, st, ev, 6, b);
   return hipGetLastError();
 }
 

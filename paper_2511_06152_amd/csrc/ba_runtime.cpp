@@ -76,11 +76,12 @@ struct Staged {
   int max_iters = 0, stop_on_ftol = 0;
   double f = 0, cx = 0, cy = 0, sigma = 1, delta = 1, lambda0 = 1e-4, ftol = 0, k[2] = {0, 0};
   std::vector<double> raw_cam;   // [C][30]
-  std::vector<double> X;         // [3P]
+  std::vector<double> X;         // [3P] internal point order
+  std::vector<int> pt_orig;      // [P] caller index of each internal point
   std::vector<int> cam_col;      // [C]
   std::vector<int> lane_pt, lane_cam, lane_seg;
   std::vector<double> lane_uv;   // [2L]
-  int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0;
+  int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
   std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
   std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
   std::vector<int4> tasks, targets;
@@ -88,7 +89,8 @@ struct Staged {
 
 struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
-      cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, task_part, pt_part, Sg, Sd, dc, cost_part,
+      cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, pt_orig, task_part, pt_part, Sg, Sd, dc,
+      cost_part,
       bad_part, cost_log, out, total;
   int n_wg, psize, pstride;
 };
@@ -124,6 +126,8 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.X320 = take(12 * (size_t)s.P);
   l.X321 = take(12 * (size_t)s.P);
   l.ptv = take(rs * kPtVals * (size_t)s.P);
+  l.ptd = take(rs * 4 * (size_t)s.P);
+  l.pt_orig = take(4 * (size_t)s.P);
   l.task_part = take(rs * kTaskVals * s.tasks.size());
   l.pt_part = take(rs * kPtPartVals * (size_t)s.n_pt_part);
   l.Sg = take(8 * (size_t)l.pstride);
@@ -195,19 +199,50 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
     std::memcpy(r + 21, c->prior_T + 3 * k, 3 * sizeof(double));
     std::memcpy(r + 24, c->prior_sigma + 6 * k, 6 * sizeof(double));
   }
-  s.X.assign(c->X, c->X + 3 * (size_t)P);
-  // observations per point
-  std::vector<int> cnt(P + 1, 0);
   for (int o = 0; o < O; ++o) {
     const int cam = c->obs_cam[o], pt = c->obs_pt[o];
     if (cam < 0 || cam >= C || pt < 0 || pt >= P) { err = "observation index out of range"; return BA_E_ARG; }
-    if (++cnt[pt + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
   }
+  // Internal point order: Morton (z-order) of the initial ground position, so
+  // that a camera's observations touch nearby point records.
+  {
+    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+    for (int j = 0; j < P; ++j)
+      for (int t = 0; t < 2; ++t) {
+        lo[t] = std::min(lo[t], c->X[3 * (size_t)j + t]);
+        hi[t] = std::max(hi[t], c->X[3 * (size_t)j + t]);
+      }
+    std::vector<uint32_t> key(P);
+    for (int j = 0; j < P; ++j) {
+      uint32_t q[2];
+      for (int t = 0; t < 2; ++t) {
+        const double span = hi[t] - lo[t];
+        const double u = span > 0 ? (c->X[3 * (size_t)j + t] - lo[t]) / span : 0.0;
+        q[t] = (uint32_t)std::min(65535.0, std::max(0.0, u * 65535.0));
+      }
+      uint32_t k = 0;
+      for (int b = 0; b < 16; ++b) k |= ((q[0] >> b) & 1u) << (2 * b) | ((q[1] >> b) & 1u) << (2 * b + 1);
+      key[j] = k;
+    }
+    s.pt_orig.resize(P);
+    for (int j = 0; j < P; ++j) s.pt_orig[j] = j;
+    std::stable_sort(s.pt_orig.begin(), s.pt_orig.end(), [&](int a, int b) { return key[a] < key[b]; });
+  }
+  std::vector<int> inv(P), opt(O);
+  for (int n = 0; n < P; ++n) inv[s.pt_orig[n]] = n;
+  for (int o = 0; o < O; ++o) opt[o] = inv[c->obs_pt[o]];
+  s.X.resize(3 * (size_t)P);
+  for (int n = 0; n < P; ++n)
+    for (int t = 0; t < 3; ++t) s.X[3 * (size_t)n + t] = c->X[3 * (size_t)s.pt_orig[n] + t];
+  // observations per point
+  std::vector<int> cnt(P + 1, 0);
+  for (int o = 0; o < O; ++o)
+    if (++cnt[opt[o] + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
   for (int j = 0; j < P; ++j) cnt[j + 1] += cnt[j];
   std::vector<int> order(O);
   {
     std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-    for (int o = 0; o < O; ++o) order[fill[c->obs_pt[o]]++] = o;
+    for (int o = 0; o < O; ++o) order[fill[opt[o]]++] = o;
   }
   for (int j = 0; j < P; ++j) {
     int* b = order.data() + cnt[j];
@@ -233,6 +268,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
   s.lane_seg.resize(s.L);
   s.lane_uv.assign(2 * (size_t)s.L, 0.0);
   for (int i = 0; i < s.L; ++i) s.lane_seg[i] = ((i % kWave) << 8) | 1;
+  std::vector<int> chunk_max(s.n_chunks, 1);
   for (int j = 0; j < P; ++j) {
     const int n = cnt[j + 1] - cnt[j];
     for (int t = 0; t < n; ++t) {
@@ -240,10 +276,12 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
       s.lane_pt[lane] = j;
       s.lane_cam[lane] = c->obs_cam[o];
       s.lane_seg[lane] = ((start[j] % kWave) << 8) | n;
+      chunk_max[lane / kWave] = std::max(chunk_max[lane / kWave], n);
       s.lane_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
       s.lane_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
     }
   }
+  for (int i = 0; i < s.L; ++i) s.lane_seg[i] |= chunk_max[i / kWave] << 16;
   s.n_wg = (s.n_chunks + cpw - 1) / cpw;
   const bool intr = s.kcol0 >= 0 || s.kcol1 >= 0;
   s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
@@ -258,6 +296,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
     for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
       const int o = order[t], col = s.cam_col[c->obs_cam[o]];
       if (col >= 0) cam_obs[col / 6].push_back(o);
+      (void)j;
     }
   std::vector<int2> cam_range(F);
   for (int fi = 0; fi < F; ++fi) {
@@ -268,7 +307,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
     s.cl_uv.resize(2 * (size_t)s.Lc, 0.0);
     for (int t = 0; t < n; ++t) {
       const int o = cam_obs[fi][t], lane = base * kWave + t;
-      s.cl_pt[lane] = c->obs_pt[o];
+      s.cl_pt[lane] = opt[o];
       s.cl_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
       s.cl_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
     }
@@ -277,6 +316,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
     for (int ch = 0; ch < nch; ch += cpt) s.tasks.push_back(mk4(TASK_CAM, free_cam[fi], 0, base + ch, std::min(cpt, nch - ch)));
     cam_range[fi].y = (int)s.tasks.size();
   }
+  s.n_cam_tasks = (int)s.tasks.size();
   // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order
   const int nblk = F * (F - 1) / 2;
   auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
@@ -352,8 +392,8 @@ struct Slot {
 // Per-launcher device batch arrays and pinned mirrors.
 struct Launcher {
   int* d_act = nullptr;
-  int* d_wgoff = nullptr;   // [3][max_slots + 1]: point-chunk, task and target workgroup prefixes
-  int* h_act = nullptr;     // pinned: [max_slots] act, then [3][max_slots + 1] prefixes
+  int* d_wgoff = nullptr;   // [4][max_slots + 1]: point-chunk, camera-task, pair-task, target workgroup prefixes
+  int* h_act = nullptr;     // pinned: [max_slots] act, then [4][max_slots + 1] prefixes
   SlotCtl* h_ctl = nullptr; // pinned readback of all slots' control blocks
   hipEvent_t ev = nullptr;
   hipEvent_t copy_ev = nullptr;  // after the last upload from h_act
@@ -410,8 +450,8 @@ int fail(ba_ctx* c, int code, const std::string& msg) {
 int init_launcher(ba_ctx* c, Launcher& l) {
   const int S = c->opt.max_slots;
   HIPCHK(c, hipMalloc(&l.d_act, sizeof(int) * S));
-  HIPCHK(c, hipMalloc(&l.d_wgoff, sizeof(int) * 3 * (S + 1)));
-  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (S + 3 * (S + 1)), hipHostMallocDefault));
+  HIPCHK(c, hipMalloc(&l.d_wgoff, sizeof(int) * 4 * (S + 1)));
+  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (S + 4 * (S + 1)), hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc(&l.h_ctl, sizeof(SlotCtl) * S, hipHostMallocDefault));
   HIPCHK(c, hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
   HIPCHK(c, hipEventCreateWithFlags(&l.copy_ev, hipEventDisableTiming));
@@ -439,25 +479,29 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
     HIPCHK(c, hipEventSynchronize(l.copy_ev));
     l.copy_pending = false;
   }
-  int* tko = off + (S + 1);
-  int* tgo = tko + (S + 1);
+  int* tkc = off + (S + 1);
+  int* tkp = tkc + (S + 1);
+  int* tgo = tkp + (S + 1);
   b = Batch{};
   b.desc = c->d_desc;
   b.ctl = c->d_ctl;
   b.act = l.d_act;
   b.wg_off = l.d_wgoff;
-  b.tk_off = l.d_wgoff + (S + 1);
-  b.tg_off = l.d_wgoff + 2 * (S + 1);
+  b.tkc_off = l.d_wgoff + (S + 1);
+  b.tkp_off = l.d_wgoff + 2 * (S + 1);
+  b.tg_off = l.d_wgoff + 3 * (S + 1);
   b.n_act = (int)slots.size();
-  int tot = 0, tk = 0, tg = 0;
+  int tot = 0, tc = 0, tp = 0, tg = 0;
   for (int i = 0; i < b.n_act; ++i) {
     const Slot& sl = c->slots[slots[i]];
     act[i] = slots[i];
     off[i] = tot;
-    tko[i] = tk;
+    tkc[i] = tc;
+    tkp[i] = tp;
     tgo[i] = tg;
     tot += sl.lay.n_wg;
-    tk += sl.desc.n_task_wg;
+    tc += sl.desc.n_cam_task_wg;
+    tp += sl.desc.n_pair_task_wg;
     tg += sl.desc.n_targets;
     b.max_m = std::max(b.max_m, sl.desc.m);
     b.max_C = std::max(b.max_C, sl.desc.C);
@@ -465,14 +509,16 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
     b.max_nb = std::max(b.max_nb, sl.desc.nb);
   }
   off[b.n_act] = tot;
-  tko[b.n_act] = tk;
+  tkc[b.n_act] = tc;
+  tkp[b.n_act] = tp;
   tgo[b.n_act] = tg;
   b.total_wg = tot;
-  b.total_tk_wg = tk;
+  b.total_tkc_wg = tc;
+  b.total_tkp_wg = tp;
   b.total_tg = tg;
   if (b.n_act == 0) return BA_OK;
   HIPCHK(c, hipMemcpyAsync(l.d_act, act, sizeof(int) * b.n_act, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * 3 * (S + 1), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * 4 * (S + 1), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipEventRecord(l.copy_ev, c->stream));
   l.copy_pending = true;
   return BA_OK;
@@ -515,8 +561,9 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.m = s.m; d.n_free = s.n_free; d.kcol0 = s.kcol0; d.kcol1 = s.kcol1;
   d.psize = lay.psize; d.pstride = lay.pstride;
   d.max_iters = s.max_iters; d.stop_on_ftol = s.stop_on_ftol; d.mixed = mixed ? 1 : 0; d.nb = s.nb;
-  d.Lc = s.Lc; d.Lq = s.Lq; d.n_tasks = (int)s.tasks.size();
-  d.n_task_wg = (d.n_tasks + kWavesPerWG - 1) / kWavesPerWG;
+  d.Lc = s.Lc; d.Lq = s.Lq; d.n_tasks = (int)s.tasks.size(); d.n_cam_tasks = s.n_cam_tasks;
+  d.n_cam_task_wg = (d.n_cam_tasks + kWavesPerWG - 1) / kWavesPerWG;
+  d.n_pair_task_wg = (d.n_tasks - d.n_cam_tasks + kWavesPerWG - 1) / kWavesPerWG;
   d.n_targets = (int)s.targets.size(); d.n_pt_part = s.n_pt_part;
   d.f = s.f; d.cx = s.cx; d.cy = s.cy; d.inv_sigma = 1.0 / s.sigma; d.huber_dt = s.delta / s.sigma;
   d.ftol = s.ftol; d.lambda0 = s.lambda0;
@@ -543,6 +590,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.X32[0] = (float*)(base + lay.X320);
   d.X32[1] = (float*)(base + lay.X321);
   d.ptv = base + lay.ptv;
+  d.ptd = base + lay.ptd;
+  d.pt_orig = (const int*)(base + lay.pt_orig);
   d.task_part = base + lay.task_part;
   d.pt_part = base + lay.pt_part;
   d.Sg = (double*)(base + lay.Sg);
@@ -572,7 +621,10 @@ int admit_one(ba_ctx* c, Ticket& t) {
                              hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C, hipMemcpyHostToDevice, st));
-  if (s.P > 0) HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
+  if (s.P > 0) {
+    HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + lay.pt_orig, s.pt_orig.data(), 4 * (size_t)s.P, hipMemcpyHostToDevice, st));
+  }
   HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
   SlotCtl ctl{};
   ctl.k[0][0] = s.k[0];
