@@ -17,7 +17,9 @@
  * Levenberg-Marquardt: IRLS Gauss-Newton normal equations, Marquardt diagonal
  * scaling D = clamp(diag H, 1e-6, 1e32), Nielsen's damping update, the damped
  * system solved by eliminating the points (Schur complement), a Cholesky
- * factorisation of the reduced camera system in FP64 and point
+ * factorisation of the reduced camera system in FP64 (or, for large systems
+ * such as a whole-flight global adjustment, preconditioned conjugate
+ * gradients with a block-Jacobi 6x6 preconditioner) and point
  * back-substitution.  All of it runs in HIP kernels on the GPU.
  *
  * Conventions
@@ -72,6 +74,14 @@ enum ba_precision {
                     update, cost reductions and gain ratio in FP64 */
 };
 
+enum ba_solver {
+  BA_SOLVER_AUTO = 0,   /* dense Cholesky up to BA_MAX_FREE_CAMS free cameras, PCG above */
+  BA_SOLVER_DENSE = 1,  /* 6x6-block FP64 Cholesky of the reduced camera system */
+  BA_SOLVER_PCG = 2     /* conjugate gradients on the block-sparse reduced camera system,
+                           block-Jacobi 6x6 preconditioner; FP32 matrix-vector products in
+                           BA_MIXED, FP64 dot products and updates; no estimated intrinsics */
+};
+
 enum ba_solve_status {
   BA_ST_QUEUED = 0,     /* waiting for a slot / arena memory */
   BA_ST_RUNNING = 1,    /* admitted, iterations in progress */
@@ -95,6 +105,9 @@ typedef struct {
                                 kernels; 0 -> 16 */
   int32_t chunks_per_task;   /* 64-lane chunks per wavefront task of the block kernel;
                                 0 -> 4 */
+  int32_t solver;            /* enum ba_solver */
+  int32_t pcg_max_iters;     /* conjugate-gradient iterations per LM step; 0 -> 500 */
+  double pcg_tol;            /* stop when |r| <= pcg_tol |b|; 0 -> 1e-6 */
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */
@@ -137,8 +150,8 @@ typedef struct {
 } ba_result;
 
 /* Limits enforced by ba_submit_cluster (BA_E_ARG beyond them). */
-#define BA_MAX_FREE_CAMS 24     /* free cameras per cluster (reduced system <= 146) */
-#define BA_MAX_CAMS 64          /* cameras per cluster, fixed ones included */
+#define BA_MAX_FREE_CAMS 24     /* free cameras per cluster for the dense solver (m <= 146) */
+#define BA_MAX_CAMS 512         /* cameras per cluster, fixed ones included (also the PCG limit) */
 #define BA_MAX_OBS_PER_POINT 64 /* a point's observations share one 64-lane wavefront */
 
 /* Create a context on options->device.  Allocates the arena.
@@ -151,7 +164,8 @@ int ba_destroy(ba_ctx* ctx);
 /* Validate and copy one cluster (Eq. 7 problem data, Sec. 3.2), admit it to a
  * device slot if a slot and arena memory are free, else queue it.  Checks:
  * indices in range, finite inputs, 1..64 observations per observed point,
- * no camera twice on one point, <= BA_MAX_FREE_CAMS free cameras.
+ * no camera twice on one point, <= BA_MAX_CAMS cameras, <= BA_MAX_FREE_CAMS free
+ * cameras for the dense solver, no estimated intrinsics with the PCG solver.
  * Errors: BA_E_ARG, BA_E_NOMEM (larger than the whole arena), BA_E_AGAIN
  * (queue full), BA_E_DEVICE. */
 int ba_submit_cluster(ba_ctx* ctx, const ba_cluster* cluster, ba_ticket* ticket);
@@ -199,7 +213,8 @@ size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
  * enum ba_prof_kernel, into caller arrays of BA_PROF_N entries, and resets
  * the counters.  Errors: BA_E_ARG, BA_E_DEVICE. */
 enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_CAMBLK = 1, BA_PROF_PAIRBLK = 2, BA_PROF_REDUCE = 3,
-                      BA_PROF_SOLVE = 4, BA_PROF_BACKSUB = 5, BA_PROF_LM = 6, BA_PROF_N = 7 };
+                      BA_PROF_SOLVE = 4, BA_PROF_BACKSUB = 5, BA_PROF_LM = 6, BA_PROF_PCG = 7,
+                      BA_PROF_N = 8 };
 int ba_profile_enable(ba_ctx* ctx, int32_t enable);
 int ba_profile_read(ba_ctx* ctx, double* total_ms, int64_t* launches);
 

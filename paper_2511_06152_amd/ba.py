@@ -16,22 +16,24 @@ LIB_PATH = os.path.join(HERE, "libba.so")
 
 BA_OK, BA_E_ARG, BA_E_NOMEM, BA_E_AGAIN, BA_E_STATE, BA_E_DEVICE, BA_E_TIMEOUT = 0, -1, -2, -3, -4, -5, -7
 BA_FP64, BA_MIXED = 0, 1
+BA_SOLVER_AUTO, BA_SOLVER_DENSE, BA_SOLVER_PCG = 0, 1, 2
 BA_ST_QUEUED, BA_ST_RUNNING, BA_ST_MAXITER, BA_ST_CONVERGED, BA_ST_STALLED, BA_ST_BAD_INIT = range(6)
 BA_MAX_FREE_CAMS = 24
-BA_MAX_CAMS = 64
+BA_MAX_CAMS = 512
 BA_MAX_OBS_PER_POINT = 64
 
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error"]
-BA_PROF_KERNELS = ["point", "camblk", "pairblk", "reduce", "solve", "backsub", "lm"]
+BA_PROF_KERNELS = ["point", "camblk", "pairblk", "reduce", "solve", "backsub", "lm", "pcg"]
 
 
 class ba_options(ct.Structure):
     _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("hbm_budget_bytes", ct.c_size_t),
                 ("max_slots", ct.c_int32), ("max_queue", ct.c_int32), ("precision", ct.c_int32),
                 ("serve", ct.c_int32), ("iters_per_tick", ct.c_int32), ("chunks_per_wg", ct.c_int32),
-                ("chunks_per_task", ct.c_int32)]
+                ("chunks_per_task", ct.c_int32), ("solver", ct.c_int32), ("pcg_max_iters", ct.c_int32),
+                ("pcg_tol", ct.c_double)]
 
 
 class ba_cluster(ct.Structure):
@@ -130,10 +132,11 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256,
                  max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
-                 chunks_per_wg: int = 16, chunks_per_task: int = 4):
+                 chunks_per_wg: int = 16, chunks_per_task: int = 4, solver: int = BA_SOLVER_AUTO,
+                 pcg_max_iters: int = 500, pcg_tol: float = 1e-6):
         self.lib = load()
         opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
-                         iters_per_tick, chunks_per_wg, chunks_per_task)
+                         iters_per_tick, chunks_per_wg, chunks_per_task, solver, pcg_max_iters, pcg_tol)
         h = ct.c_void_p()
         rc = self.lib.ba_create(ct.byref(opt), ct.byref(h))
         if rc != BA_OK:

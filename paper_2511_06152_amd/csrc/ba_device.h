@@ -12,7 +12,7 @@ constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kWG = 256;                  // threads per workgroup of the chunk kernels
 constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kMaxFreeCams = 24;          // reduced system m <= 6*24 + 2 = 146
-constexpr int kMaxCams = 64;              // camera table kept in LDS
+constexpr int kMaxCams = 512;             // camera table kept in LDS by the point-lane kernels
 constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
 constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
 constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
@@ -33,6 +33,8 @@ struct SlotDesc {
   int psize, pstride;                     // packed m(m+1)/2, reduced-system vector stride (psize + 3m)
   int max_iters, stop_on_ftol, mixed, nb;  // nb: 6x6 blocks per side of the reduced system
   int Lc, Lq, n_tasks, n_cam_tasks, n_cam_task_wg, n_pair_task_wg, n_targets, n_pt_part;
+  int sparse, nnzb, pcg_max_iters, pad1;  // sparse: block-CSR reduced system solved by PCG
+  double pcg_tol;
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
   // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
   const int* lane_pt;                     // [L] point index, -1 for padding
@@ -69,6 +71,14 @@ struct SlotDesc {
   void* pt_part;                          // [n_pt_part][10] Real: per point-pass wavefront intrinsic sums
   double* Sg;                             // [pstride] reduced: packed S_acc (psize), g, bS, diag U (m each)
   double* Sd;                             // [nb(nb+1)/2][36] damped S in 6x6 blocks, for the refinement step
+  // sparse reduced system (PCG): block rows of the free cameras, diagonal block first
+  const int* brow;                        // [F + 1]
+  const int* bcol;                        // [nnzb] free-camera column of each block
+  const int2* tslot;                      // [n_targets] block slots of a target: (a,b) and (b,a)
+  double* Sblk;                           // [nnzb][36] FP64 blocks, row-major
+  float* Sblk32;                          // [nnzb][36] FP32 copy for the mixed-precision products
+  double* Minv;                           // [F][36] block-Jacobi preconditioner (inverse Cholesky factors)
+  double* pcgw;                           // [2m] PCG work: gradient with priors, clamped diagonal
   double* dc;                             // [m] camera / intrinsic update
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
   int* bad_part;                          // [n_wg] trial observations at non-positive depth
@@ -97,12 +107,14 @@ struct Batch {
   int n_act;
   int total_wg, total_tkc_wg, total_tkp_wg, total_tg;
   int max_m, max_C, max_pstride, max_nb;
+  int any_sparse, any_dense;
 };
 
 hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st);
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
-// ev (optional): 14 events, the start and end of each of the seven kernels
-// of the iteration, recorded by the kernel dispatches themselves.
+// ev (optional): 16 events, the start and end of each of the eight kernels
+// of the iteration (point, camera blocks, pair blocks, reduce, dense solve,
+// back-substitution, LM, PCG solve), recorded by the dispatches themselves.
 hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 

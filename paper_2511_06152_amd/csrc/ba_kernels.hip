@@ -872,6 +872,25 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
   const double t = fixed_sum(reinterpret_cast<const R*>(d.task_part), kTaskVals, nvals, tg.y, tg.z, sh, v);
   if (v >= nvals) return;
   const int fa = d.cam_col[ka];
+  if (d.sparse) {
+    // block-CSR reduced system: both orientations of a pair block, full diagonal blocks
+    const int2 sl = d.tslot[blockIdx.x - bt.tg_off[si]];
+    if (kind == TASK_PAIR) {
+      const int r = v / 6, cc = v % 6;
+      d.Sblk[36 * (size_t)sl.x + 6 * r + cc] = t;
+      d.Sblk[36 * (size_t)sl.y + 6 * cc + r] = t;
+      d.Sblk32[36 * (size_t)sl.x + 6 * r + cc] = (float)t;
+      d.Sblk32[36 * (size_t)sl.y + 6 * cc + r] = (float)t;
+      return;
+    }
+    if (v < 21) {
+      int r, cc;
+      tri6(v, &r, &cc);
+      d.Sblk[36 * (size_t)sl.x + 6 * r + cc] = t;
+      d.Sblk[36 * (size_t)sl.x + 6 * cc + r] = t;
+      return;
+    }
+  }
   if (kind == TASK_PAIR) {
     const int fb = d.cam_col[kb];
     Sg[pidx(fa + v / 6, fb + v % 6)] = t;
@@ -1016,7 +1035,7 @@ __global__ __launch_bounds__(kSolveLoadThreads) void k_solve(Batch bt) {
   const int s = bt.act[blockIdx.x];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
+  if (c.status != ST_RUNNING || d.sparse) return;
   const int tid = threadIdx.x;
   const int m = d.m, psize = d.psize, nb = d.nb;
   const int np = nb * kBlk, nblk = nb * (nb + 1) / 2;
@@ -1213,6 +1232,207 @@ __global__ __launch_bounds__(kSolveLoadThreads) void k_solve(Batch bt) {
     c.E_prior_trial = 0.5 * pc;
     c.k[nxt][0] = c.k[cur][0] + (d.kcol0 >= 0 ? xv[d.kcol0] : 0.0);
     c.k[nxt][1] = c.k[cur][1] + (d.kcol1 >= 0 ? xv[d.kcol1] : 0.0);
+  }
+}
+
+// ---- damped reduced-camera-system solve by preconditioned conjugate gradients ------
+//
+// For large reduced systems (a whole-flight adjustment: hundreds of cameras),
+// the Schur complement is kept as 6x6 blocks of the co-visible camera pairs
+// (block CSR, both orientations) and solved by conjugate gradients with the
+// inverse diagonal blocks as block-Jacobi preconditioner.  One workgroup of
+// 1024 threads per cluster; vectors in LDS.  In mixed mode the matrix-vector
+// products are FP32 (FP32 copy of the blocks); dot products, the preconditioner
+// and the updates are FP64.  Fixed-order reductions throughout.
+
+constexpr int kPcgThreads = 1024;
+
+__device__ double block_sum(double v, double* red, int tid) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((tid % kWave) == 0) red[tid / kWave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kPcgThreads / kWave; ++w) t += red[w];
+  return t;
+}
+
+// z = M^-1 r for block b: M^-1 = Li^T Li with Li the inverse Cholesky factor.
+__device__ __forceinline__ void precond(const double* __restrict__ Li, const double* r, double* z, int q) {
+  // thread q computes row q of the block: z = Li^T (Li r)
+  const int b = q / 6, rr = q % 6;
+  const double* L = Li + 36 * (size_t)b;
+  double y[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j <= i; ++j) t = fm(L[6 * i + j], r[6 * b + j], t);
+    y[i] = t;
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) t = i >= rr ? fm(L[6 * i + rr], y[i], t) : t;
+  z[q] = t;
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
+  extern __shared__ double sv[];
+  const int s = bt.act[blockIdx.x];
+  const SlotDesc& d = bt.desc[s];
+  SlotCtl& c = bt.ctl[s];
+  if (c.status != ST_RUNNING || !d.sparse) return;
+  const int tid = threadIdx.x;
+  const int F = d.n_free, m = d.m;
+  double* x = sv;            // [m]
+  double* r = x + m;         // [m]
+  double* z = r + m;         // [m]
+  double* pv = z + m;        // [m]
+  double* Ap = pv + m;       // [m]
+  double* red = Ap + m;      // [kPcgThreads / 64]
+  double* gv = d.pcgw;       // [m] gradient of the camera side (with priors)
+  double* Dv = gv + m;       // [m] clamped diagonal
+  __shared__ int ok;
+  const double lambda = c.lambda;
+  const int cur = c.cur;
+  if (tid == 0) ok = (c.point_fail == 0);
+  for (int q = tid; q < m; q += kPcgThreads) {
+    gv[q] = d.Sg[q];
+    r[q] = d.Sg[m + q];      // bS for now
+    Dv[q] = d.Sg[2 * m + q]; // diag U for now
+  }
+  __syncthreads();
+  // priors of the free cameras, then damping, preconditioner, FP32 diagonal blocks
+  for (int k = tid; k < d.C; k += kPcgThreads) {
+    const int col = d.cam_col[k];
+    if (col < 0) continue;
+    const int fi = col / 6;
+    double* Ab = d.Sblk + 36 * (size_t)d.brow[fi];
+    double e[6], J[9];
+    prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
+    const double* pr = d.prior + kPriorVals * k;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Ab[6 * a + q] += J[a] * J[q] + J[3 + a] * J[3 + q] + J[6 + a] * J[6 + q];
+      const double it = pr[15 + a];
+      Ab[6 * (3 + a) + 3 + a] += it * it;
+      Dv[col + a] += J[a] * J[a] + J[3 + a] * J[3 + a] + J[6 + a] * J[6 + a];
+      Dv[col + 3 + a] += it * it;
+      gv[col + a] += J[a] * e[0] + J[3 + a] * e[1] + J[6 + a] * e[2];
+      gv[col + 3 + a] += it * e[3 + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const double Di = clampd(Dv[col + a]);
+      Dv[col + a] = Di;
+      Ab[7 * a] += lambda * Di;
+    }
+    double blk[36];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) blk[i] = Ab[i];
+    if (!chol6_inv(blk, d.Minv + 36 * (size_t)fi)) ok = 0;
+    float* A32 = d.Sblk32 + 36 * (size_t)d.brow[fi];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) A32[i] = (float)Ab[i];
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) c.solve_ok = 0;
+    return;
+  }
+  for (int q = tid; q < m; q += kPcgThreads) {
+    r[q] = -gv[q] + r[q];   // b = -g + bS
+    x[q] = 0.0;
+  }
+  __syncthreads();
+  const double bnorm = sqrt(block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * r[q]; return t; }(), red, tid));
+  for (int q = tid; q < m; q += kPcgThreads) precond(d.Minv, r, z, q);
+  __syncthreads();
+  for (int q = tid; q < m; q += kPcgThreads) pv[q] = z[q];
+  double rz = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * z[q]; return t; }(), red, tid);
+  const bool mixed = d.mixed != 0;
+  bool good = true;
+  for (int it = 0; it < d.pcg_max_iters && bnorm > 0.0; ++it) {
+    // Ap = S p, thread q owns row q; the 6 rows of a block row read each block together
+    for (int q = tid; q < m; q += kPcgThreads) {
+      const int bi = q / 6, rr = q % 6;
+      double acc = 0.0;
+      if (mixed) {
+        float a32 = 0.f;
+        for (int k = d.brow[bi]; k < d.brow[bi + 1]; ++k) {
+          const float* B = d.Sblk32 + 36 * (size_t)k + 6 * rr;
+          const double* pp = pv + 6 * d.bcol[k];
+#pragma unroll
+          for (int cc = 0; cc < 6; ++cc) a32 = fm(B[cc], (float)pp[cc], a32);
+        }
+        acc = (double)a32;
+      } else {
+        for (int k = d.brow[bi]; k < d.brow[bi + 1]; ++k) {
+          const double* B = d.Sblk + 36 * (size_t)k + 6 * rr;
+          const double* pp = pv + 6 * d.bcol[k];
+#pragma unroll
+          for (int cc = 0; cc < 6; ++cc) acc = fm(B[cc], pp[cc], acc);
+        }
+      }
+      Ap[q] = acc;
+    }
+    __syncthreads();
+    const double pAp = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += pv[q] * Ap[q]; return t; }(), red, tid);
+    if (!(pAp > 0.0) || !isfinite(pAp)) { good = false; break; }
+    const double alpha = rz / pAp;
+    for (int q = tid; q < m; q += kPcgThreads) {
+      x[q] = fm(alpha, pv[q], x[q]);
+      r[q] = fm(-alpha, Ap[q], r[q]);
+    }
+    __syncthreads();
+    const double rr2 = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * r[q]; return t; }(), red, tid);
+    if (sqrt(rr2) <= d.pcg_tol * bnorm) break;
+    for (int q = tid; q < m; q += kPcgThreads) precond(d.Minv, r, z, q);
+    __syncthreads();
+    const double rz2 = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * z[q]; return t; }(), red, tid);
+    const double beta = rz2 / rz;
+    rz = rz2;
+    for (int q = tid; q < m; q += kPcgThreads) pv[q] = fm(beta, pv[q], z[q]);
+    __syncthreads();
+  }
+  if (!good) {
+    if (tid == 0) c.solve_ok = 0;
+    return;
+  }
+  const double predc = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += x[q] * (lambda * Dv[q] * x[q] - gv[q]); return t; }(), red, tid);
+  for (int q = tid; q < m; q += kPcgThreads) d.dc[q] = x[q];
+  const int nxt = 1 - cur;
+  double pc = 0.0;
+  for (int k = tid; k < d.C; k += kPcgThreads) {
+    const double* cm = d.cam[cur] + kCamVals * k;
+    double* cn = d.cam[nxt] + kCamVals * k;
+    const int col = d.cam_col[k];
+    if (col < 0) {
+      for (int i = 0; i < kCamVals; ++i) cn[i] = cm[i];
+      continue;
+    }
+    const double wv[3] = {x[col], x[col + 1], x[col + 2]};
+    double E[9];
+    so3_exp(wv, E);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cn[3 * i + j] = cm[3 * i] * E[j] + cm[3 * i + 1] * E[3 + j] + cm[3 * i + 2] * E[6 + j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + x[col + 3 + i];
+    double e[6], J[9];
+    prior_terms(cn, d.prior + kPriorVals * k, e, J);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) pc += e[i] * e[i];
+  }
+  pc = block_sum(pc, red, tid);
+  if (tid == 0) {
+    c.pred_c = predc;
+    c.E_prior_trial = 0.5 * pc;
+    c.k[nxt][0] = c.k[cur][0];
+    c.k[nxt][1] = c.k[cur][1];
   }
 }
 
@@ -1429,6 +1649,10 @@ size_t backsub_smem(const Batch& b) {
          sizeof(int) * (size_t)b.max_C;
 }
 
+size_t pcg_smem(const Batch& b) {
+  return sizeof(double) * (5 * (size_t)b.max_m + kPcgThreads / kWave);
+}
+
 size_t solve_smem(const Batch& b) {
   const size_t nb = (size_t)b.max_nb, blk = nb * (nb + 1) / 2 * 36;
   return sizeof(double) * (solve_lds_base(b.max_nb) + (solve_lds_copy(b.max_nb) ? blk : 0));
@@ -1464,8 +1688,12 @@ hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st) {
 
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st) {
   if (b.n_act == 0) return hipSuccess;
-  if (b.total_wg > 0)
-    hipLaunchKernelGGL(k_cost0, dim3(b.total_wg), dim3(kWG), sizeof(double) * b.max_C * kCamVals, st, b);
+  if (b.total_wg > 0) {
+    const size_t sc = sizeof(double) * b.max_C * kCamVals;
+    hipError_t e = ensure_smem((const void*)k_cost0, sc);
+    if (e) return e;
+    hipLaunchKernelGGL(k_cost0, dim3(b.total_wg), dim3(kWG), sc, st, b);
+  }
   hipLaunchKernelGGL(k_init, dim3(b.n_act), dim3(64), 0, st, b);
   return hipGetLastError();
 }
@@ -1487,6 +1715,10 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   const size_t sb = mixed ? backsub_smem<float>(b) : backsub_smem<double>(b);
   const void* fb = mixed ? (const void*)k_backsub<float> : (const void*)k_backsub<double>;
   if ((e = ensure_smem(fb, sb))) return e;
+  const void* fp = mixed ? (const void*)k_point<float> : (const void*)k_point<double>;
+  if ((e = ensure_smem(fp, sp))) return e;
+  const size_t s_pcg = pcg_smem(b);
+  if ((e = ensure_smem((const void*)k_pcg, s_pcg))) return e;
   // Every profiled kernel needs a dispatch to carry its events, also when a
   // batch has no work for it: a one-block launch that returns at once.
   const dim3 g_pt(b.total_wg > 0 ? b.total_wg : 1), g_tg(b.total_tg > 0 ? b.total_tg : 1);
@@ -1514,7 +1746,8 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
     if (mixed) launch(k_reduce<float>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
     else launch(k_reduce<double>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
   }
-  launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 4, b);
+  if (b.any_dense || ev) launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 4, b);
+  if (b.any_sparse || ev) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, ev, 7, b);
   if (b.total_wg > 0 || ev) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
     if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, ev, 5, bb);

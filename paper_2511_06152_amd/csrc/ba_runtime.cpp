@@ -85,12 +85,16 @@ struct Staged {
   std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
   std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
   std::vector<int4> tasks, targets;
+  // sparse (PCG) reduced system: block CSR over the free cameras, diagonal first
+  int sparse = 0;
+  std::vector<int> brow, bcol;   // [F + 1], [nnzb]
+  std::vector<int2> tslot;       // [n_targets] block slots (a,b), (b,a) of each target
 };
 
 struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, pt_orig, task_part, pt_part, Sg, Sd, dc,
-      cost_part,
+      brow, bcol, tslot, Sblk, Sblk32, Minv, pcgw, cost_part,
       bad_part, cost_log, out, total;
   int n_wg, psize, pstride;
 };
@@ -99,7 +103,8 @@ Layout make_layout(const Staged& s, bool mixed) {
   Layout l{};
   const size_t rs = real_size(mixed);
   l.n_wg = s.n_wg;
-  l.psize = s.m * (s.m + 1) / 2;
+  // the sparse form keeps no packed triangle: Sg holds g, bS, diag U only
+  l.psize = s.sparse ? 0 : s.m * (s.m + 1) / 2;
   l.pstride = (int)align_up((size_t)l.psize + 3 * (size_t)s.m, 4);
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
@@ -131,8 +136,16 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.task_part = take(rs * kTaskVals * s.tasks.size());
   l.pt_part = take(rs * kPtPartVals * (size_t)s.n_pt_part);
   l.Sg = take(8 * (size_t)l.pstride);
-  l.Sd = take(8 * 36 * (size_t)s.nb * (s.nb + 1) / 2);
+  l.Sd = take(s.sparse ? 0 : 8 * 36 * (size_t)s.nb * (s.nb + 1) / 2);
   l.dc = take(8 * (size_t)s.m);
+  const size_t nnzb = s.bcol.size();
+  l.brow = take(4 * s.brow.size());
+  l.bcol = take(4 * nnzb);
+  l.tslot = take(sizeof(int2) * s.tslot.size());
+  l.Sblk = take(8 * 36 * nnzb);
+  l.Sblk32 = take(4 * 36 * nnzb);
+  l.Minv = take(8 * 36 * (size_t)(s.sparse ? s.n_free : 0));
+  l.pcgw = take(8 * 2 * (size_t)(s.sparse ? s.m : 0));
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
   l.cost_log = take(8 * ((size_t)s.max_iters + 1));
@@ -157,10 +170,10 @@ int4 mk4(int kind, int a, int b, int y, int z) { return make_int4((kind << 24) |
 //  * pair lanes: the observation pairs of each point whose two cameras are
 //    free, grouped by camera pair, padded and cut into tasks likewise;
 //  * reduction targets: each free camera, each camera pair, the intrinsics.
-int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
+int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, int solver) {
   if (!c) { err = "cluster is NULL"; return BA_E_ARG; }
   const int C = c->n_cams, P = c->n_points, O = c->n_obs;
-  if (C < 1 || C > kMaxCams || P < 0 || O < 0) { err = "sizes out of range (1 <= n_cams <= 64)"; return BA_E_ARG; }
+  if (C < 1 || C > kMaxCams || P < 0 || O < 0) { err = "sizes out of range (1 <= n_cams <= 512)"; return BA_E_ARG; }
   if (!c->R || !c->T || !c->k || !c->prior_R || !c->prior_T || !c->prior_sigma || !c->fixed ||
       (P > 0 && !c->X) || (O > 0 && (!c->obs_cam || !c->obs_pt || !c->obs_uv))) {
     err = "missing input array"; return BA_E_ARG;
@@ -185,7 +198,11 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
   s.cam_col.assign(C, -1);
   for (int k = 0; k < C; ++k)
     if (!c->fixed[k]) s.cam_col[k] = 6 * s.n_free++;
-  if (s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras"; return BA_E_ARG; }
+  if (solver == BA_SOLVER_PCG) s.sparse = 1;
+  else if (solver == BA_SOLVER_AUTO) s.sparse = s.n_free > kMaxFreeCams;
+  else if (solver != BA_SOLVER_DENSE) { err = "unknown solver"; return BA_E_ARG; }
+  if (!s.sparse && s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras for the dense solver"; return BA_E_ARG; }
+  if (s.sparse && (c->intr_mask & 3)) { err = "the PCG solver does not estimate intrinsics"; return BA_E_ARG; }
   int col = 6 * s.n_free;
   if (c->intr_mask & 1) s.kcol0 = col++;
   if (c->intr_mask & 2) s.kcol1 = col++;
@@ -355,12 +372,47 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt) {
       blk_range[blk(fa, fb)].y = (int)s.tasks.size();
     }
   for (int fi = 0; fi < F; ++fi) s.targets.push_back(mk4(TASK_CAM, free_cam[fi], 0, cam_range[fi].x, cam_range[fi].y));
+  if (!s.sparse) {
+    for (int fa = 0; fa < F; ++fa)
+      for (int fb = fa + 1; fb < F; ++fb) {
+        const int2 r = blk_range[blk(fa, fb)];
+        s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
+      }
+    if (intr) s.targets.push_back(mk4(TARGET_INTR, 0, 0, 0, s.n_pt_part));
+    return BA_OK;
+  }
+  // Block CSR of the co-visible free-camera pairs.  Row fa lists its diagonal
+  // block, then the non-empty blocks (fa, fb) in increasing fb.  Each pair
+  // target writes its block and the transpose.
+  std::vector<std::vector<int>> nbr(F);
+  for (int fa = 0; fa < F; ++fa)
+    for (int fb = fa + 1; fb < F; ++fb)
+      if (!pairs[blk(fa, fb)].empty()) {
+        nbr[fa].push_back(fb);
+        nbr[fb].push_back(fa);
+      }
+  s.brow.assign(F + 1, 0);
+  std::vector<int> diag_slot(F);
+  std::map<std::pair<int, int>, int> slot_of;
+  for (int fa = 0; fa < F; ++fa) {
+    s.brow[fa] = (int)s.bcol.size();
+    diag_slot[fa] = (int)s.bcol.size();
+    s.bcol.push_back(fa);
+    std::sort(nbr[fa].begin(), nbr[fa].end());
+    for (int fb : nbr[fa]) {
+      slot_of[{fa, fb}] = (int)s.bcol.size();
+      s.bcol.push_back(fb);
+    }
+  }
+  s.brow[F] = (int)s.bcol.size();
+  for (int fi = 0; fi < F; ++fi) s.tslot.push_back(make_int2(diag_slot[fi], diag_slot[fi]));
   for (int fa = 0; fa < F; ++fa)
     for (int fb = fa + 1; fb < F; ++fb) {
+      if (pairs[blk(fa, fb)].empty()) continue;
       const int2 r = blk_range[blk(fa, fb)];
       s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
+      s.tslot.push_back(make_int2(slot_of[{fa, fb}], slot_of[{fb, fa}]));
     }
-  if (intr) s.targets.push_back(mk4(TARGET_INTR, 0, 0, 0, s.n_pt_part));
   return BA_OK;
 }
 
@@ -506,7 +558,9 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
     b.max_m = std::max(b.max_m, sl.desc.m);
     b.max_C = std::max(b.max_C, sl.desc.C);
     b.max_pstride = std::max(b.max_pstride, sl.lay.pstride);
-    b.max_nb = std::max(b.max_nb, sl.desc.nb);
+    // the dense solve's LDS layout is sized by the dense clusters only
+    if (sl.desc.sparse) b.any_sparse = 1;
+    else b.any_dense = 1, b.max_nb = std::max(b.max_nb, sl.desc.nb);
   }
   off[b.n_act] = tot;
   tkc[b.n_act] = tc;
@@ -567,6 +621,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.n_targets = (int)s.targets.size(); d.n_pt_part = s.n_pt_part;
   d.f = s.f; d.cx = s.cx; d.cy = s.cy; d.inv_sigma = 1.0 / s.sigma; d.huber_dt = s.delta / s.sigma;
   d.ftol = s.ftol; d.lambda0 = s.lambda0;
+  d.sparse = s.sparse; d.nnzb = (int)s.bcol.size();
+  d.pcg_max_iters = c->opt.pcg_max_iters; d.pcg_tol = c->opt.pcg_tol;
   d.lane_pt = (const int*)(base + lay.lane_pt);
   d.lane_cam = (const int*)(base + lay.lane_cam);
   d.lane_seg = (const int*)(base + lay.lane_seg);
@@ -597,6 +653,13 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.Sg = (double*)(base + lay.Sg);
   d.Sd = (double*)(base + lay.Sd);
   d.dc = (double*)(base + lay.dc);
+  d.brow = (const int*)(base + lay.brow);
+  d.bcol = (const int*)(base + lay.bcol);
+  d.tslot = (const int2*)(base + lay.tslot);
+  d.Sblk = (double*)(base + lay.Sblk);
+  d.Sblk32 = (float*)(base + lay.Sblk32);
+  d.Minv = (double*)(base + lay.Minv);
+  d.pcgw = (double*)(base + lay.pcgw);
   d.cost_part = (double*)(base + lay.cost_part);
   d.bad_part = (int*)(base + lay.bad_part);
   d.cost_log = (double*)(base + lay.cost_log);
@@ -620,6 +683,11 @@ int admit_one(ba_ctx* c, Ticket& t) {
     HIPCHK(c, hipMemcpyAsync(base + lay.targets, s.targets.data(), sizeof(int4) * s.targets.size(),
                              hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C, hipMemcpyHostToDevice, st));
+  if (s.sparse) {
+    HIPCHK(c, hipMemcpyAsync(base + lay.brow, s.brow.data(), 4 * s.brow.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + lay.bcol, s.bcol.data(), 4 * s.bcol.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + lay.tslot, s.tslot.data(), sizeof(int2) * s.tslot.size(), hipMemcpyHostToDevice, st));
+  }
   HIPCHK(c, hipMemcpyAsync(base + lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C, hipMemcpyHostToDevice, st));
   if (s.P > 0) {
     HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
@@ -844,6 +912,10 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.iters_per_tick <= 0) c->opt.iters_per_tick = 2;
   if (c->opt.chunks_per_wg <= 0) c->opt.chunks_per_wg = 16;
   if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
+  if (c->opt.pcg_max_iters <= 0) c->opt.pcg_max_iters = 500;
+  if (!(c->opt.pcg_tol > 0)) c->opt.pcg_tol = 1e-6;
+  if (c->opt.solver < BA_SOLVER_AUTO || c->opt.solver > BA_SOLVER_PCG || c->opt.pcg_max_iters > 100000 ||
+      !(c->opt.pcg_tol < 1)) return BA_E_ARG;
   if (c->opt.max_slots > 65536 || c->opt.chunks_per_wg > 4096 || c->opt.chunks_per_task > 4096) return BA_E_ARG;
   c->device = opt->device;
   int ndev = 0;
@@ -901,7 +973,7 @@ size_t ba_footprint(ba_ctx* c, const ba_cluster* cl) {
   if (!c) return 0;
   Staged s;
   std::string err;
-  if (stage(cl, s, err, c->opt.chunks_per_wg, c->opt.chunks_per_task)) return 0;
+  if (stage(cl, s, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver)) return 0;
   return make_layout(s, c->opt.precision == BA_MIXED).total;
 }
 
@@ -909,7 +981,7 @@ int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   if (!c || !ticket) return BA_E_ARG;
   auto st = std::make_unique<Staged>();
   std::string err;
-  int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task);
+  int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
   std::lock_guard<std::mutex> g(c->mu);
   if (rc) return fail(c, rc, err);
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");

@@ -77,6 +77,10 @@ class SceneSpec:
     jitter_deg: float = 1.0
     n_hills: int = 8
     first_strip: int = 0
+    # Whole-flight blocks: test visibility only against the cameras whose
+    # footprint can overlap the spawning image's, in chunks of candidate points
+    # (bounded memory for hundreds of cameras and ~1M points).
+    neighbour_vis: bool = False
 
 
 def rotvec_to_matrix(w: np.ndarray) -> np.ndarray:
@@ -210,6 +214,18 @@ def make_scene(spec: SceneSpec, seed: int) -> dict:
     k1t, k2t = spec.k_true
     ncx, ncy = IMG_W // CELL_PX, IMG_H // CELL_PX
 
+    if spec.neighbour_vis:
+        X_true, obs_cam, obs_pt, uv_true = _spawn_points_blocked(spec, rng, R_t, T_t, terrain)
+    else:
+        X_true, obs_cam, obs_pt, uv_true = _spawn_points(spec, rng, R_t, T_t, terrain)
+    return _finish_scene(spec, rng, R_t, T_t, strip, X_true, obs_cam, obs_pt, uv_true)
+
+
+def _spawn_points(spec, rng, R_t, T_t, terrain):
+    """Tie points and their true observations, testing every camera."""
+    C = R_t.shape[0]
+    k1t, k2t = spec.k_true
+    ncx, ncy = IMG_W // CELL_PX, IMG_H // CELL_PX
     X_list, obs_list = [], []
     have = 0
     guard = 0
@@ -248,6 +264,89 @@ def make_scene(spec: SceneSpec, seed: int) -> dict:
     obs_cam = np.concatenate([o[1] for o in obs_list]).astype(np.int32)
     obs_pt = np.concatenate([np.full(len(o[1]), o[0]) for o in obs_list]).astype(np.int32)
     uv_true = np.concatenate([o[2] for o in obs_list])
+    return X_true, obs_cam, obs_pt, uv_true
+
+
+def _spawn_points_blocked(spec, rng, R_t, T_t, terrain, chunk=32768):
+    """Tie points and their true observations for large blocks: each candidate
+    is tested against the cameras whose centre lies within one footprint of
+    the spawning camera's (with margin), so memory is chunk x neighbours."""
+    C = R_t.shape[0]
+    k1t, k2t = spec.k_true
+    ncx, ncy = IMG_W // CELL_PX, IMG_H // CELL_PX
+    dxy = np.abs(T_t[:, None, :2] - T_t[None, :, :2])
+    near = (dxy[..., 0] < 1.25 * FOOT_ACROSS) & (dxy[..., 1] < 1.25 * FOOT_ALONG)
+    np.fill_diagonal(near, False)
+    K = int(near.sum(1).max()) if C > 1 else 0
+    nbr = np.full((C, max(K, 1)), -1, np.int64)
+    for k in range(C):
+        idx = np.nonzero(near[k])[0]
+        nbr[k, : idx.size] = idx
+    Xs, cams_s, pts_s, uvs_s = [], [], [], []
+    have = 0
+    guard = 0
+    while have < spec.n_points:
+        guard += 1
+        if guard > 100000:
+            raise RuntimeError("scene generator could not place enough points")
+        B = int(min(chunk, max(1024, 1.6 * (spec.n_points - have))))
+        img = rng.integers(0, C, B)
+        cu = rng.integers(0, ncx, B)
+        cv = rng.integers(0, ncy, B)
+        u = (cu + rng.uniform(0, 1, B)) * CELL_PX
+        v = (cv + rng.uniform(0, 1, B)) * CELL_PX
+        a, b = _undistort((u - CX) / F_PX, (v - CY) / F_PX, k1t, k2t)
+        dirc = np.stack([a, b, np.ones(B)], -1)
+        dirw = np.einsum("nij,nj->ni", R_t[img], dirc)
+        X = terrain.intersect(T_t[img], dirw)
+        cand = nbr[img]                                   # (B, K), -1 padded
+        cs = np.where(cand < 0, 0, cand)
+        d = X[:, None, :] - T_t[cs]
+        xc = np.einsum("nkji,nkj->nki", R_t[cs], d)
+        z = xc[..., 2]
+        zs = np.where(np.abs(z) < 1e-9, 1e-9, z)
+        ad, bd = _distort(xc[..., 0] / zs, xc[..., 1] / zs, k1t, k2t)
+        uv = np.stack([F_PX * ad + CX, F_PX * bd + CY], -1)
+        vis = (cand >= 0) & (z > 1.0) & (uv[..., 0] >= 0) & (uv[..., 0] < IMG_W) & (uv[..., 1] >= 0) & \
+            (uv[..., 1] < IMG_H)
+        want = _n_observers(spec, rng, B) - 1
+        score = rng.uniform(0, 1, vis.shape)
+        score[~vis] = np.inf
+        order = np.argsort(score, axis=1)
+        n_extra = np.minimum(want, vis.sum(1))
+        keep = np.nonzero(n_extra >= 1)[0][: spec.n_points - have]
+        if keep.size == 0:
+            continue
+        ne = n_extra[keep]
+        col = np.arange(order.shape[1])[None, :]
+        sel = col < ne[:, None]                           # (n, K) chosen extra observers
+        rows = np.repeat(np.arange(keep.size), ne)
+        extra = cand[keep[:, None], order[keep]][sel]     # camera ids, row-major
+        extra_uv = uv[keep[:, None], order[keep]][sel]
+        # the spawning camera sees the point where its ray was cast
+        all_cam = np.concatenate([img[keep], extra])
+        all_row = np.concatenate([np.arange(keep.size), rows])
+        all_uv = np.concatenate([synth_pixel(R_t[img[keep]], T_t[img[keep]], X[keep], k1t, k2t), extra_uv])
+        srt = np.lexsort((all_cam, all_row))
+        Xs.append(X[keep])
+        cams_s.append(all_cam[srt])
+        pts_s.append(all_row[srt] + have)
+        uvs_s.append(all_uv[srt])
+        have += keep.size
+    return (np.concatenate(Xs), np.concatenate(cams_s).astype(np.int32), np.concatenate(pts_s).astype(np.int32),
+            np.concatenate(uvs_s))
+
+
+def synth_pixel(R, T, X, k1, k2):
+    """Data-generating camera per row: pixel (N,2) of X[n] in camera (R[n], T[n])."""
+    xc = np.einsum("nji,nj->ni", R, X - T)
+    a, b = _distort(xc[:, 0] / xc[:, 2], xc[:, 1] / xc[:, 2], k1, k2)
+    return np.stack([F_PX * a + CX, F_PX * b + CY], -1)
+
+
+def _finish_scene(spec, rng, R_t, T_t, strip, X_true, obs_cam, obs_pt, uv_true):
+    """Noise, outliers, observation shuffle, perturbed initial poses and priors."""
+    C = R_t.shape[0]
     O = obs_cam.shape[0]
 
     uv = uv_true + rng.normal(0.0, spec.noise_px, (O, 2))
@@ -356,3 +455,16 @@ def scene_cluster12(seed: int = 2) -> dict:
 def scene_batched(index: int) -> dict:
     seed = 4_000_000 + index
     return make_scene(spec_batched(seed), seed)
+
+
+def spec_global(n_strips: int = 10, imgs_per_strip: int = 40, n_points: int = 800_000) -> SceneSpec:
+    """Whole-flight block for the global adjustment: 400 cameras (10 strips x
+    40), 800k tie points, 1 + geometric extra observers with mean 4.8 total,
+    truncated by visibility (~4.39 per point, ~3.5M observations), 3% outliers,
+    pinhole."""
+    return SceneSpec(n_strips=n_strips, imgs_per_strip=imgs_per_strip, n_points=n_points,
+                     obs_model=("geom", 4.8), neighbour_vis=True)
+
+
+def scene_global(seed: int = 5, **kw) -> dict:
+    return make_scene(spec_global(**kw), seed)
