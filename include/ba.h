@@ -107,7 +107,8 @@ typedef struct {
                                 0 -> 4 */
   int32_t solver;            /* enum ba_solver */
   int32_t pcg_max_iters;     /* conjugate-gradient iterations per LM step; 0 -> 500 */
-  double pcg_tol;            /* stop when |r| <= pcg_tol |b|; 0 -> 1e-6 */
+  double pcg_tol;            /* stop when |r| <= pcg_tol |b| (the forcing term of an inexact
+                                LM step); 0 -> 0.1 */
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */
@@ -147,6 +148,7 @@ typedef struct {
   double lambda;                /* damping after the last iteration */
   double initial_cost, final_cost;
   double t_submit, t_admit, t_done;   /* seconds on the library's steady clock */
+  int64_t cg_iters;             /* conjugate-gradient iterations over all LM iterations (PCG solver; else 0) */
 } ba_result;
 
 /* Limits enforced by ba_submit_cluster (BA_E_ARG beyond them). */

@@ -52,7 +52,8 @@ class ba_result(ct.Structure):
                 ("cost_log", ct.c_void_p), ("status", ct.c_int32), ("iterations", ct.c_int32),
                 ("accepted", ct.c_int32), ("rejected", ct.c_int32), ("lambda_", ct.c_double),
                 ("initial_cost", ct.c_double), ("final_cost", ct.c_double),
-                ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double)]
+                ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double),
+                ("cg_iters", ct.c_int64)]
 
 
 _lib = None
@@ -133,7 +134,7 @@ class Context:
     def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256,
                  max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
                  chunks_per_wg: int = 16, chunks_per_task: int = 4, solver: int = BA_SOLVER_AUTO,
-                 pcg_max_iters: int = 500, pcg_tol: float = 1e-6):
+                 pcg_max_iters: int = 500, pcg_tol: float = 0.1):
         self.lib = load()
         opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
                          iters_per_tick, chunks_per_wg, chunks_per_task, solver, pcg_max_iters, pcg_tol)
@@ -211,7 +212,7 @@ class Context:
         n = r.iterations
         out.update(status=r.status, iterations=n, accepted=r.accepted, rejected=r.rejected, lambda_=r.lambda_,
                    initial_cost=r.initial_cost, final_cost=r.final_cost, t_submit=r.t_submit, t_admit=r.t_admit,
-                   t_done=r.t_done)
+                   t_done=r.t_done, cg_iters=r.cg_iters)
         out["cost_log"] = out["cost_log"][: n + 1]
         out["state"] = (out["R"], out["T"], out["X"], out["k"])
         return out

@@ -20,6 +20,8 @@ constexpr int kPtVals = 16;               // per point: Q (6 packed symmetric), 
 constexpr int kTaskVals = 52;             // per block task partial: camera task 51 values, pair task 36
 constexpr int kPtPartVals = 10;           // per point-pass wavefront: intrinsic-intrinsic terms
 constexpr int kBlk = 6;                   // block size of the reduced-system factorisation
+constexpr int kSbRow = 8;                 // sparse reduced-system block: 6 rows padded to 8 values
+constexpr int kSbVals = 6 * kSbRow;       //   (16-byte aligned rows for vector loads)
 // Work items of the block-assembly kernel (one wavefront each) and of its
 // reduction: int4 {kind << 24 | cam_a << 12 | cam_b, begin, end/count, 0}.
 enum TaskKind { TASK_CAM = 0, TASK_PAIR = 1, TARGET_INTR = 2 };
@@ -75,9 +77,8 @@ struct SlotDesc {
   const int* brow;                        // [F + 1]
   const int* bcol;                        // [nnzb] free-camera column of each block
   const int2* tslot;                      // [n_targets] block slots of a target: (a,b) and (b,a)
-  double* Sblk;                           // [nnzb][36] FP64 blocks, row-major
-  float* Sblk32;                          // [nnzb][36] FP32 copy for the mixed-precision products
-  double* Minv;                           // [F][36] block-Jacobi preconditioner (inverse Cholesky factors)
+  double* Sblk;                           // [nnzb][6][kSbRow] FP64 blocks, row-major, rows padded
+  float* Sblk32;                          // [nnzb][6][kSbRow] FP32 copy for the mixed-precision products
   double* pcgw;                           // [2m] PCG work: gradient with priors, clamped diagonal
   double* dc;                             // [m] camera / intrinsic update
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
@@ -92,6 +93,8 @@ struct SlotCtl {
   double k[2][2];                         // intrinsics per state buffer
   double lambda, nu, E, E_prior_trial, pred_c, E0;
   int cur, status, iter, accepted, rejected, solve_ok, point_fail, bad_init;
+  int cg_iters, pad;                      // conjugate-gradient iterations, summed over LM iterations
+  double cg_b0;                           // |b| of the first conjugate-gradient solve (forcing-term scale)
 };
 
 // Launch helpers (ba_kernels.hip).  `act` lists the slots of the batch,

@@ -323,6 +323,8 @@ __global__ void k_prep_slot(Batch bt) {
     c.solve_ok = 1;
     c.point_fail = 0;
     c.bad_init = 0;
+    c.cg_iters = 0;
+    c.cg_b0 = 0.0;
     c.k[1][0] = c.k[0][0];
     c.k[1][1] = c.k[0][1];
   }
@@ -877,17 +879,17 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
     const int2 sl = d.tslot[blockIdx.x - bt.tg_off[si]];
     if (kind == TASK_PAIR) {
       const int r = v / 6, cc = v % 6;
-      d.Sblk[36 * (size_t)sl.x + 6 * r + cc] = t;
-      d.Sblk[36 * (size_t)sl.y + 6 * cc + r] = t;
-      d.Sblk32[36 * (size_t)sl.x + 6 * r + cc] = (float)t;
-      d.Sblk32[36 * (size_t)sl.y + 6 * cc + r] = (float)t;
+      d.Sblk[kSbVals * (size_t)sl.x + kSbRow * r + cc] = t;
+      d.Sblk[kSbVals * (size_t)sl.y + kSbRow * cc + r] = t;
+      d.Sblk32[kSbVals * (size_t)sl.x + kSbRow * r + cc] = (float)t;
+      d.Sblk32[kSbVals * (size_t)sl.y + kSbRow * cc + r] = (float)t;
       return;
     }
     if (v < 21) {
       int r, cc;
       tri6(v, &r, &cc);
-      d.Sblk[36 * (size_t)sl.x + 6 * r + cc] = t;
-      d.Sblk[36 * (size_t)sl.x + 6 * cc + r] = t;
+      d.Sblk[kSbVals * (size_t)sl.x + kSbRow * r + cc] = t;
+      d.Sblk[kSbVals * (size_t)sl.x + kSbRow * cc + r] = t;
       return;
     }
   }
@@ -944,7 +946,7 @@ __device__ __forceinline__ void decode_tri(int e, int* ii, int* jj) {   // e -> 
 
 // In-place Cholesky of the 6x6 SPD block a (row-major, lower triangle used)
 // and the lower-triangular inverse of the factor into li; in registers.
-__device__ bool chol6_inv(double* __restrict__ a, double* __restrict__ li) {
+__device__ __forceinline__ bool chol6_inv(double* __restrict__ a, double* __restrict__ li) {
   double L[6][6];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
@@ -1241,168 +1243,286 @@ __global__ __launch_bounds__(kSolveLoadThreads) void k_solve(Batch bt) {
 // the Schur complement is kept as 6x6 blocks of the co-visible camera pairs
 // (block CSR, both orientations) and solved by conjugate gradients with the
 // inverse diagonal blocks as block-Jacobi preconditioner.  One workgroup of
-// 1024 threads per cluster; vectors in LDS.  In mixed mode the matrix-vector
-// products are FP32 (FP32 copy of the blocks); dot products, the preconditioner
-// and the updates are FP64.  Fixed-order reductions throughout.
+// 1024 threads per cluster.  Thread f owns block row f: its six entries of x
+// and r stay in registers and it applies its block of the preconditioner
+// (inverse Cholesky factor in LDS).  The direction p and the product S p live
+// in LDS; each thread computes whole rows of the product, several blocks at a
+// time.  In mixed mode the products are FP32 (FP32 copy of the blocks, FP32
+// accumulation); dot products, the preconditioner and the updates are FP64.
+// Every reduction has a fixed order.
 
 constexpr int kPcgThreads = 1024;
+constexpr int kPcgWaves = kPcgThreads / kWave;
 
-__device__ double block_sum(double v, double* red, int tid) {
-  v = wave_sum(v);
+// Sums over the workgroup in a fixed order (two values at once).
+__device__ __forceinline__ double2 block_sum2(double a, double b, double* red, int tid) {
+  a = wave_sum(a);
+  b = wave_sum(b);
   __syncthreads();
-  if ((tid % kWave) == 0) red[tid / kWave] = v;
+  if ((tid % kWave) == 0) {
+    red[tid / kWave] = a;
+    red[kPcgWaves + tid / kWave] = b;
+  }
   __syncthreads();
-  double t = 0.0;
+  double2 t = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int w = 0; w < kPcgThreads / kWave; ++w) t += red[w];
+  for (int w = 0; w < kPcgWaves; ++w) {
+    t.x += red[w];
+    t.y += red[kPcgWaves + w];
+  }
   return t;
 }
 
-// z = M^-1 r for block b: M^-1 = Li^T Li with Li the inverse Cholesky factor.
-__device__ __forceinline__ void precond(const double* __restrict__ Li, const double* r, double* z, int q) {
-  // thread q computes row q of the block: z = Li^T (Li r)
-  const int b = q / 6, rr = q % 6;
-  const double* L = Li + 36 * (size_t)b;
+// Rows of S p owned by one thread (q = tid, tid + 1024, ...); returns this
+// thread's part of p.Ap.  Row q = 6 bi + r reads row r of every block of
+// block row bi (16-byte vector loads of the padded row), NB blocks at a time
+// so that their loads are in flight together; out-of-range slots of a batch
+// re-read the row's first block and are multiplied by zero.  p is read from
+// LDS in the product's precision: FP32 copy [F][8] (mixed) or FP64 [m].
+__device__ __forceinline__ void row_load(const float* __restrict__ row, float v[6], const float* pp, float w[6]) {
+  const float4 a = *reinterpret_cast<const float4*>(row);
+  const float2 b = *reinterpret_cast<const float2*>(row + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
+  const float4 c = *reinterpret_cast<const float4*>(pp);
+  const float2 e = *reinterpret_cast<const float2*>(pp + 4);
+  w[0] = c.x; w[1] = c.y; w[2] = c.z; w[3] = c.w; w[4] = e.x; w[5] = e.y;
+}
+__device__ __forceinline__ void row_load(const double* __restrict__ row, double v[6], const double* pp, double w[6]) {
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const double2 a = *reinterpret_cast<const double2*>(row + 2 * h);
+    v[2 * h] = a.x;
+    v[2 * h + 1] = a.y;
+    const double2 c = *reinterpret_cast<const double2*>(pp + 2 * h);
+    w[2 * h] = c.x;
+    w[2 * h + 1] = c.y;
+  }
+}
+
+template <typename B, int NB, int PS>
+__device__ __forceinline__ double pcg_spmv(const B* __restrict__ blk, const int* __restrict__ brow,
+                                           const int* __restrict__ bcol, const B* pB, const double* p, double* Ap,
+                                           int m, int tid) {
+  double pap = 0.0;
+  for (int q = tid; q < m; q += kPcgThreads) {
+    const int bi = q / 6, r = q % 6;
+    const int k0 = brow[bi], k1 = brow[bi + 1];
+    B acc = B(0);
+    for (int kb = k0; kb < k1; kb += NB) {
+      int cj[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) cj[u] = bcol[kb + u < k1 ? kb + u : k0];
+      B v[NB][6], w[NB][6];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int k = kb + u < k1 ? kb + u : k0;
+        row_load(blk + kSbVals * (size_t)k + kSbRow * r, v[u], pB + PS * cj[u], w[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const B z = kb + u < k1 ? B(1) : B(0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc = fm(v[u][c] * z, w[u][c], acc);
+      }
+    }
+    const double a = (double)acc;
+    Ap[q] = a;
+    pap = fm(a, p[q], pap);
+  }
+  return pap;
+}
+
+// z = Li^T Li r for one 6x6 block (Li: packed lower triangle, row-major).
+__device__ __forceinline__ void pcg_precond(const double* Li, const double r[6], double z[6]) {
   double y[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j <= i; ++j) t = fm(L[6 * i + j], r[6 * b + j], t);
+    for (int c = 0; c <= i; ++c) t = fm(Li[i * (i + 1) / 2 + c], r[c], t);
     y[i] = t;
   }
-  double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) t = i >= rr ? fm(L[6 * i + rr], y[i], t) : t;
-  z[q] = t;
+  for (int c = 0; c < 6; ++c) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 5; i >= c; --i) t = fm(Li[i * (i + 1) / 2 + c], y[i], t);
+    z[c] = t;
+  }
 }
 
 __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
-  extern __shared__ double sv[];
+  extern __shared__ __attribute__((aligned(16))) double sv[];   // 16-byte vector reads of p
+  __shared__ int own_cam[kMaxCams];
+  __shared__ int ok;
   const int s = bt.act[blockIdx.x];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING || !d.sparse) return;
   const int tid = threadIdx.x;
   const int F = d.n_free, m = d.m;
-  double* x = sv;            // [m]
-  double* r = x + m;         // [m]
-  double* z = r + m;         // [m]
-  double* pv = z + m;        // [m]
-  double* Ap = pv + m;       // [m]
-  double* red = Ap + m;      // [kPcgThreads / 64]
-  double* gv = d.pcgw;       // [m] gradient of the camera side (with priors)
-  double* Dv = gv + m;       // [m] clamped diagonal
-  __shared__ int ok;
+  double* pv = sv;               // [m] search direction
+  double* Ap = pv + m;           // [m] S p; the solution at the end
+  double* Lf = Ap + m;           // [F][21] inverse Cholesky factors of the damped diagonal blocks
+  double* red = Lf + 21 * F;     // [2 * kPcgWaves]
+  // [F][8] FP32 copy of p (mixed), 16-byte aligned
+  float* p32 = reinterpret_cast<float*>(sv + ((2 * m + 21 * F + 2 * kPcgWaves + 1) & ~1));
+  double* gv = d.pcgw;           // [m] gradient of the camera side (with priors)
+  double* Dv = gv + m;           // [m] clamped diagonal
   const double lambda = c.lambda;
   const int cur = c.cur;
   if (tid == 0) ok = (c.point_fail == 0);
-  for (int q = tid; q < m; q += kPcgThreads) {
-    gv[q] = d.Sg[q];
-    r[q] = d.Sg[m + q];      // bS for now
-    Dv[q] = d.Sg[2 * m + q]; // diag U for now
-  }
-  __syncthreads();
-  // priors of the free cameras, then damping, preconditioner, FP32 diagonal blocks
   for (int k = tid; k < d.C; k += kPcgThreads) {
     const int col = d.cam_col[k];
-    if (col < 0) continue;
-    const int fi = col / 6;
-    double* Ab = d.Sblk + 36 * (size_t)d.brow[fi];
+    if (col >= 0) own_cam[col / 6] = k;
+  }
+  __syncthreads();
+  // Owner set-up: priors, damping, preconditioner, right-hand side.
+  const bool own = tid < F;
+  double xr[6], rr[6];
+  double part_rr = 0.0, part_rz = 0.0;
+  if (own) {
+    const int f = tid, k = own_cam[f], col = 6 * f;
+    double g[6], Dg[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      g[a] = d.Sg[col + a];
+      rr[a] = d.Sg[m + col + a];      // bS for now
+      Dg[a] = d.Sg[2 * m + col + a];  // diag U for now
+    }
+    double* Ab = d.Sblk + kSbVals * (size_t)d.brow[f];
+    double blkv[36];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) blkv[i] = Ab[kSbRow * (i / 6) + i % 6];
     double e[6], J[9];
     prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
     const double* pr = d.prior + kPriorVals * k;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Ab[6 * a + q] += J[a] * J[q] + J[3 + a] * J[3 + q] + J[6 + a] * J[6 + q];
+      for (int q = 0; q < 3; ++q) {
+        const double h = J[a] * J[q] + J[3 + a] * J[3 + q] + J[6 + a] * J[6 + q];
+        blkv[6 * a + q] += h;
+        if (q == a) Dg[a] += h;
+      }
+      g[a] += J[a] * e[0] + J[3 + a] * e[1] + J[6 + a] * e[2];
       const double it = pr[15 + a];
-      Ab[6 * (3 + a) + 3 + a] += it * it;
-      Dv[col + a] += J[a] * J[a] + J[3 + a] * J[3 + a] + J[6 + a] * J[6 + a];
-      Dv[col + 3 + a] += it * it;
-      gv[col + a] += J[a] * e[0] + J[3 + a] * e[1] + J[6 + a] * e[2];
-      gv[col + 3 + a] += it * e[3 + a];
+      blkv[6 * (3 + a) + 3 + a] += it * it;
+      Dg[3 + a] += it * it;
+      g[3 + a] += it * e[3 + a];
     }
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      const double Di = clampd(Dv[col + a]);
-      Dv[col + a] = Di;
-      Ab[7 * a] += lambda * Di;
+      Dg[a] = clampd(Dg[a]);
+      blkv[7 * a] += lambda * Dg[a];
+      gv[col + a] = g[a];
+      Dv[col + a] = Dg[a];
+      rr[a] = -g[a] + rr[a];
+      xr[a] = 0.0;
     }
-    double blk[36];
+    float* A32 = d.Sblk32 + kSbVals * (size_t)d.brow[f];
 #pragma unroll
-    for (int i = 0; i < 36; ++i) blk[i] = Ab[i];
-    if (!chol6_inv(blk, d.Minv + 36 * (size_t)fi)) ok = 0;
-    float* A32 = d.Sblk32 + 36 * (size_t)d.brow[fi];
+    for (int i = 0; i < 36; ++i) {
+      Ab[kSbRow * (i / 6) + i % 6] = blkv[i];
+      A32[kSbRow * (i / 6) + i % 6] = (float)blkv[i];
+    }
+    double li[36];
+    if (!chol6_inv(blkv, li)) ok = 0;
+    double* L = Lf + 21 * f;
 #pragma unroll
-    for (int i = 0; i < 36; ++i) A32[i] = (float)Ab[i];
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int cc = 0; cc <= i; ++cc) L[i * (i + 1) / 2 + cc] = li[6 * i + cc];
+    double z[6];
+    pcg_precond(L, rr, z);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      pv[col + a] = z[a];
+      p32[kSbRow * f + a] = (float)z[a];
+      part_rr = fm(rr[a], rr[a], part_rr);
+      part_rz = fm(rr[a], z[a], part_rz);
+    }
   }
-  __syncthreads();
+  const double2 s0 = block_sum2(part_rr, part_rz, red, tid);
   if (!ok) {
     if (tid == 0) c.solve_ok = 0;
     return;
   }
-  for (int q = tid; q < m; q += kPcgThreads) {
-    r[q] = -gv[q] + r[q];   // b = -g + bS
-    x[q] = 0.0;
-  }
-  __syncthreads();
-  const double bnorm = sqrt(block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * r[q]; return t; }(), red, tid));
-  for (int q = tid; q < m; q += kPcgThreads) precond(d.Minv, r, z, q);
-  __syncthreads();
-  for (int q = tid; q < m; q += kPcgThreads) pv[q] = z[q];
-  double rz = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * z[q]; return t; }(), red, tid);
+  const double bnorm = sqrt(s0.x);
+  double rz = s0.y;
   const bool mixed = d.mixed != 0;
+  // loop invariants in registers (the barriers would otherwise reload them)
+  const int* const brow = d.brow;
+  const int* const bcol = d.bcol;
+  const float* const S32 = d.Sblk32;
+  const double* const S64 = d.Sblk;
+  const int max_it = d.pcg_max_iters;
+  // Forcing term of the inexact step: |r| <= eta |b| with
+  // eta = min(pcg_tol, |b| / |b_0|), |b_0| the first solve's right-hand side,
+  // so the steps become exact as the reduced gradient vanishes.
+  const double b0 = c.cg_b0 > 0.0 ? c.cg_b0 : bnorm;
+  const double tol = b0 > 0.0 ? fmin(d.pcg_tol, bnorm / b0) : d.pcg_tol;
   bool good = true;
-  for (int it = 0; it < d.pcg_max_iters && bnorm > 0.0; ++it) {
-    // Ap = S p, thread q owns row q; the 6 rows of a block row read each block together
-    for (int q = tid; q < m; q += kPcgThreads) {
-      const int bi = q / 6, rr = q % 6;
-      double acc = 0.0;
-      if (mixed) {
-        float a32 = 0.f;
-        for (int k = d.brow[bi]; k < d.brow[bi + 1]; ++k) {
-          const float* B = d.Sblk32 + 36 * (size_t)k + 6 * rr;
-          const double* pp = pv + 6 * d.bcol[k];
-#pragma unroll
-          for (int cc = 0; cc < 6; ++cc) a32 = fm(B[cc], (float)pp[cc], a32);
-        }
-        acc = (double)a32;
-      } else {
-        for (int k = d.brow[bi]; k < d.brow[bi + 1]; ++k) {
-          const double* B = d.Sblk + 36 * (size_t)k + 6 * rr;
-          const double* pp = pv + 6 * d.bcol[k];
-#pragma unroll
-          for (int cc = 0; cc < 6; ++cc) acc = fm(B[cc], pp[cc], acc);
-        }
-      }
-      Ap[q] = acc;
+  int it = 0;
+  for (; it < max_it && bnorm > 0.0;) {
+    const double pap_part = mixed ? pcg_spmv<float, 8, kSbRow>(S32, brow, bcol, p32, pv, Ap, m, tid)
+                                  : pcg_spmv<double, 4, 6>(S64, brow, bcol, pv, pv, Ap, m, tid);
+    const double pAp = block_sum2(pap_part, 0.0, red, tid).x;
+    ++it;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+      good = false;
+      break;
     }
-    __syncthreads();
-    const double pAp = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += pv[q] * Ap[q]; return t; }(), red, tid);
-    if (!(pAp > 0.0) || !isfinite(pAp)) { good = false; break; }
     const double alpha = rz / pAp;
-    for (int q = tid; q < m; q += kPcgThreads) {
-      x[q] = fm(alpha, pv[q], x[q]);
-      r[q] = fm(-alpha, Ap[q], r[q]);
+    double z[6];
+    part_rr = part_rz = 0.0;
+    if (own) {
+      const int col = 6 * tid;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        xr[a] = fm(alpha, pv[col + a], xr[a]);
+        rr[a] = fm(-alpha, Ap[col + a], rr[a]);
+      }
+      pcg_precond(Lf + 21 * tid, rr, z);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        part_rr = fm(rr[a], rr[a], part_rr);
+        part_rz = fm(rr[a], z[a], part_rz);
+      }
     }
-    __syncthreads();
-    const double rr2 = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * r[q]; return t; }(), red, tid);
-    if (sqrt(rr2) <= d.pcg_tol * bnorm) break;
-    for (int q = tid; q < m; q += kPcgThreads) precond(d.Minv, r, z, q);
-    __syncthreads();
-    const double rz2 = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += r[q] * z[q]; return t; }(), red, tid);
-    const double beta = rz2 / rz;
-    rz = rz2;
-    for (int q = tid; q < m; q += kPcgThreads) pv[q] = fm(beta, pv[q], z[q]);
+    const double2 s1 = block_sum2(part_rr, part_rz, red, tid);
+    if (sqrt(s1.x) <= tol * bnorm) break;
+    const double beta = s1.y / rz;
+    rz = s1.y;
+    if (own) {
+      const int col = 6 * tid;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double pn = fm(beta, pv[col + a], z[a]);
+        pv[col + a] = pn;
+        p32[kSbRow * tid + a] = (float)pn;
+      }
+    }
     __syncthreads();
   }
   if (!good) {
     if (tid == 0) c.solve_ok = 0;
     return;
   }
-  const double predc = block_sum([&] { double t = 0.0; for (int q = tid; q < m; q += kPcgThreads) t += x[q] * (lambda * Dv[q] * x[q] - gv[q]); return t; }(), red, tid);
-  for (int q = tid; q < m; q += kPcgThreads) d.dc[q] = x[q];
+  // Solution to LDS (over S p), predicted camera-side reduction.
+  double part_pred = 0.0;
+  __syncthreads();
+  if (own) {
+    const int col = 6 * tid;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      Ap[col + a] = xr[a];
+      d.dc[col + a] = xr[a];
+      part_pred += xr[a] * (lambda * Dv[col + a] * xr[a] - gv[col + a]);
+    }
+  }
+  const double predc = block_sum2(part_pred, 0.0, red, tid).x;
+  const double* x = Ap;
   const int nxt = 1 - cur;
   double pc = 0.0;
   for (int k = tid; k < d.C; k += kPcgThreads) {
@@ -1427,12 +1547,14 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) pc += e[i] * e[i];
   }
-  pc = block_sum(pc, red, tid);
+  pc = block_sum2(pc, 0.0, red, tid).x;
   if (tid == 0) {
     c.pred_c = predc;
     c.E_prior_trial = 0.5 * pc;
     c.k[nxt][0] = c.k[cur][0];
     c.k[nxt][1] = c.k[cur][1];
+    c.cg_iters += it;
+    if (!(c.cg_b0 > 0.0)) c.cg_b0 = bnorm;
   }
 }
 
@@ -1650,7 +1772,8 @@ size_t backsub_smem(const Batch& b) {
 }
 
 size_t pcg_smem(const Batch& b) {
-  return sizeof(double) * (5 * (size_t)b.max_m + kPcgThreads / kWave);
+  const size_t m = (size_t)b.max_m;
+  return sizeof(double) * (2 * m + 21 * ((m + 5) / 6) + 2 * kPcgWaves + 1) + sizeof(float) * kSbRow * ((m + 5) / 6);
 }
 
 size_t solve_smem(const Batch& b) {

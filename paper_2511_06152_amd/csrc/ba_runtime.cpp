@@ -94,7 +94,7 @@ struct Staged {
 struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, pt_orig, task_part, pt_part, Sg, Sd, dc,
-      brow, bcol, tslot, Sblk, Sblk32, Minv, pcgw, cost_part,
+      brow, bcol, tslot, Sblk, Sblk32, pcgw, cost_part,
       bad_part, cost_log, out, total;
   int n_wg, psize, pstride;
 };
@@ -142,9 +142,8 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.brow = take(4 * s.brow.size());
   l.bcol = take(4 * nnzb);
   l.tslot = take(sizeof(int2) * s.tslot.size());
-  l.Sblk = take(8 * 36 * nnzb);
-  l.Sblk32 = take(4 * 36 * nnzb);
-  l.Minv = take(8 * 36 * (size_t)(s.sparse ? s.n_free : 0));
+  l.Sblk = take(8 * (size_t)kSbVals * nnzb);
+  l.Sblk32 = take(4 * (size_t)kSbVals * nnzb);
   l.pcgw = take(8 * 2 * (size_t)(s.sparse ? s.m : 0));
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
@@ -658,7 +657,6 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.tslot = (const int2*)(base + lay.tslot);
   d.Sblk = (double*)(base + lay.Sblk);
   d.Sblk32 = (float*)(base + lay.Sblk32);
-  d.Minv = (double*)(base + lay.Minv);
   d.pcgw = (double*)(base + lay.pcgw);
   d.cost_part = (double*)(base + lay.cost_part);
   d.bad_part = (int*)(base + lay.bad_part);
@@ -913,7 +911,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.chunks_per_wg <= 0) c->opt.chunks_per_wg = 16;
   if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
   if (c->opt.pcg_max_iters <= 0) c->opt.pcg_max_iters = 500;
-  if (!(c->opt.pcg_tol > 0)) c->opt.pcg_tol = 1e-6;
+  if (!(c->opt.pcg_tol > 0)) c->opt.pcg_tol = 0.1;
   if (c->opt.solver < BA_SOLVER_AUTO || c->opt.solver > BA_SOLVER_PCG || c->opt.pcg_max_iters > 100000 ||
       !(c->opt.pcg_tol < 1)) return BA_E_ARG;
   if (c->opt.max_slots > 65536 || c->opt.chunks_per_wg > 4096 || c->opt.chunks_per_task > 4096) return BA_E_ARG;
@@ -1113,6 +1111,7 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   r->t_submit = t->t_submit;
   r->t_admit = t->t_admit;
   r->t_done = t->t_done;
+  r->cg_iters = ctl.cg_iters;
   return BA_OK;
 }
 

@@ -6,9 +6,12 @@ Bars:
   * FP64 path with a tight PCG tolerance (1e-12 relative residual): cost after
     every LM iteration within 1e-8 relative of the oracle's, same accepted
     steps;
-  * mixed path (FP32 products, PCG tolerance 1e-6): after the LM has converged,
-    RMS |p_gpu - p_oracle| < 1e-3 px, camera centres < 1 mm, attitude
-    < 2e-6 rad;
+  * mixed path (FP32 products) with a tight PCG tolerance (1e-6), so that it
+    follows the exact LM's trajectory: after 60 iterations RMS
+    |p_gpu - p_oracle| < 1e-3 px, camera centres < 1 mm, attitude < 2e-6 rad;
+  * default inexact steps (forcing term min(0.1, |b|/|b_0|)): these take a
+    different path down the same cost, so they are held to the oracle's cost
+    and RMS reprojection error at equal iteration count, not to its state;
   * a cluster solved by PCG gives bit-identical results alone and batched with
     dense-solver clusters.
 """
@@ -69,16 +72,38 @@ def test_pcg_fp64_with_fixed_cameras_and_prior_only_camera():
     check_cost_log(got, ref)
 
 
-def test_pcg_mixed_converged_40_cams():
+def test_pcg_mixed_tight_tolerance_40_cams():
     sc = medium(8)
     print("case pcg mixed medium seed 8", sc["n_cams"], sc["n_points"], sc["n_obs"], flush=True)
     ref = oracle.solve(sc, max_iters=60)
-    got = run(sc, 60, precision=MIXED)
+    got = run(sc, 60, precision=MIXED, pcg_tol=1e-6)
     rms, dT, att = final_errors(sc, got, ref)
     print("rms px", rms, "centre m", dT, "attitude rad", att, flush=True)
     assert rms < 1e-3
     assert dT < 1e-3
     assert att < 2e-6
+
+
+def rms_reprojection(sc, R, T, X, k):
+    e = A.project_obs(R, T, X, k, sc["obs_cam"], sc["obs_pt"]) - sc["obs_uv"]
+    return float(np.sqrt((e ** 2).sum(1).mean()))
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_pcg_default_forcing_reaches_oracle_cost_40_cams(precision):
+    """Inexact steps (default forcing term): after 40 iterations the cost is at
+    most the exact LM's (relative slack 1e-7) and the RMS reprojection error
+    over all observations equals the oracle's within 1e-3 px."""
+    sc = medium(8)
+    print("case pcg default forcing seed 8 precision", precision, flush=True)
+    ref = oracle.solve(sc, max_iters=40)
+    got = run(sc, 40, precision=precision)
+    e_gpu = oracle.cost(sc, got["state"])
+    e_ref = ref["cost_log"][-1]
+    r_gpu, r_ref = rms_reprojection(sc, *got["state"]), rms_reprojection(sc, *ref["state"])
+    print("cost gpu", e_gpu, "oracle", e_ref, "rms px", r_gpu, r_ref, "cg iters", got["cg_iters"], flush=True)
+    assert e_gpu <= e_ref * (1 + 1e-7)
+    assert abs(r_gpu - r_ref) < 1e-3
 
 
 def test_auto_solver_uses_pcg_above_24_free_cameras():
