@@ -49,6 +49,41 @@ FLOP_CAM_INTR_OBS = 48
 FLOP_PAIR = 216
 
 
+# HBM traffic of the dominant kernel (k_camblk<float>, 64 paper-scale clusters),
+# from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch) over `bench.py --steps 1 --warmup 0 --batch 64 --plain 0 --serve 0
+# --uneven 0 --global-iters 0 --cpu-clusters 0`, each scaled by what the same
+# counter reads for a plain copy of known size (`bench.py --copy-calibration
+# 256`: FETCH_SIZE reads 131084.8 KiB for 262144 KiB read, WRITE_SIZE 262144.0
+# KiB for 262144 KiB written).  Valid only for the kernel source it was taken
+# on (sha256 of csrc/ba_kernels.hip and csrc/ba_device.h); otherwise reported
+# as null.
+TRAFFIC = {
+    "kernel": "camblk",
+    "fetch_kib": 93408.6, "write_kib": 1991.8,
+    "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
+    "clusters": 64,
+    "sources_sha256": {
+        "ba_kernels.hip": "82508e4d000b535891ad573e107f4bdda14af5aa4591967446dd928851407942",
+        "ba_device.h": "8822d966b96cdcaffb22362a4a32d252d742771623e0f1330abd7519e06c680d",
+    },
+}
+
+
+def traffic_bytes(kernel: str, batch: int):
+    """Measured HBM bytes per launch of `kernel`, or None when the counters
+    were taken on other kernel sources or another batch size."""
+    import hashlib
+    if kernel != TRAFFIC["kernel"] or batch != TRAFFIC["clusters"]:
+        return None
+    csrc = os.path.join(ROOT, "paper_2511_06152_amd", "csrc")
+    for name, sha in TRAFFIC["sources_sha256"].items():
+        with open(os.path.join(csrc, name), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != sha:
+                return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -74,6 +109,105 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else float("nan")
 
 
+def copy_calibration(mib: int):
+    """A plain elementwise copy of known size on cuda:0: each launch reads and
+    writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "launches": 5}), flush=True)
+
+
+def run_uneven(args, Context, precision, kw):
+    """The batched-uneven workload: N resident clusters of 6-24 cameras with
+    log-uniform 5k-60k points and 2-6 observations per point, solved as one
+    batch per step (inputs resident before the timer)."""
+    t_gen = time.perf_counter()
+    scs = [A.scene_batched(i) for i in range(args.uneven_scenes)]
+    log(f"uneven: generated {len(scs)} clusters in {time.perf_counter() - t_gen:.1f}s")
+    from paper_2511_06152_amd.ba import Cluster
+    N = args.uneven
+    probe = Context(precision=precision, max_slots=4, hbm_budget_bytes=64 << 20)
+    foot = [probe.ba_footprint(Cluster(sc, **kw)) for sc in scs]
+    probe.close()
+    budget = int(sum(foot[i % len(scs)] for i in range(N)) * 1.02) + (64 << 20)
+    ctx = Context(precision=precision, max_slots=N, hbm_budget_bytes=budget, chunks_per_task=args.chunks_per_task)
+    times, iters, its_max = [], 0, 0
+    for step in range(1 + max(args.steps // 2, 1)):
+        tickets = [ctx.submit(scs[i % len(scs)], **kw) for i in range(N)]
+        for t in tickets:
+            ctx.ba_step(t, 0)
+        t0 = time.perf_counter()
+        ctx.ba_solve_batch(tickets)
+        dt = time.perf_counter() - t0
+        its = [ctx.ba_fetch(t)["iterations"] for t in tickets]
+        for t in tickets:
+            ctx.ba_release(t)
+        if step:
+            times.append(dt)
+            iters += sum(its)
+            its_max = max(its_max, max(its))
+        log(f"uneven step {step}{'' if step else ' (warmup)'}: {dt * 1e3:.1f} ms for {N} clusters")
+    ctx.close()
+    cams = [scs[i % len(scs)]["n_cams"] for i in range(N)]
+    pts = [scs[i % len(scs)]["n_points"] for i in range(N)]
+    obs = [scs[i % len(scs)]["n_obs"] for i in range(N)]
+    return {"clusters": N, "distinct": len(scs), "clusters_per_s": N / float(np.mean(times)),
+            "ms_per_batch": 1e3 * float(np.mean(times)), "mean_iterations": iters / (N * len(times)),
+            "max_iterations": its_max, "cams_range": [min(cams), max(cams)],
+            "points_range": [min(pts), max(pts)], "obs_total": int(sum(obs)), "hbm_budget_bytes": budget}
+
+
+def run_global(args, Context, precision):
+    """Whole-flight global adjustment: 400 cameras (10 strips x 40), 800k points,
+    ~3.5M observations; the reduced camera system (m = 2400) by block-Jacobi
+    PCG with FP32 products.  Times LM iterations with the cluster resident;
+    the oracle re-evaluates the cost of the returned state."""
+    import oracle
+    from paper_2511_06152_amd.ba import Cluster
+    t_gen = time.perf_counter()
+    sc = A.scene_global(5)
+    log(f"global: generated C={sc['n_cams']} P={sc['n_points']} O={sc['n_obs']} "
+        f"in {time.perf_counter() - t_gen:.1f}s")
+    n = args.global_iters
+    cl = Cluster(sc, max_iters=n + 1)
+    probe = Context(precision=precision, max_slots=2, hbm_budget_bytes=64 << 20)
+    foot = probe.ba_footprint(cl)
+    probe.close()
+    ctx = Context(precision=precision, max_slots=2, hbm_budget_bytes=int(foot * 1.05) + (64 << 20),
+                  chunks_per_task=args.chunks_per_task)
+    t = ctx.ba_submit_cluster(cl)
+    ctx.ba_step(t, 1)             # admission, initial cost and the first iteration (warmup)
+    ctx.ba_profile_enable(True)
+    t0 = time.perf_counter()
+    ctx.ba_step(t, n)
+    dt = time.perf_counter() - t0
+    prof = ctx.ba_profile_read()
+    r = ctx.ba_fetch(t)
+    ctx.close()
+    e_or = oracle.cost(sc, r["state"])
+    e_gpu = float(r["cost_log"][-1])
+    out = {"cams": sc["n_cams"], "points": sc["n_points"], "obs": sc["n_obs"], "m": 6 * sc["n_cams"],
+           "lm_iterations_timed": n, "ms_per_lm_iteration": 1e3 * dt / n,
+           "cg_iterations_total": r["cg_iters"], "pcg_avg_ms": prof["pcg"][0] / max(prof["pcg"][1], 1),
+           "kernel_avg_us": {k: 1e3 * v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+           "cost_initial": float(r["cost_log"][0]), "cost_final": e_gpu,
+           "oracle_cost_of_final_state_rel_diff": abs(e_or - e_gpu) / e_or, "hbm_footprint_bytes": foot}
+    if args.global_oracle_iters > 0:
+        t0 = time.perf_counter()
+        ref = oracle.solve(sc, max_iters=args.global_oracle_iters)
+        out["oracle_s_per_lm_iteration"] = (time.perf_counter() - t0) / args.global_oracle_iters
+        del ref
+    log(f"global: {out['ms_per_lm_iteration']:.2f} ms per LM iteration, {r['cg_iters']} CG iterations")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,11 +222,25 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
     ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
+    ap.add_argument("--uneven", type=int, default=256,
+                    help="clusters of the uneven batched workload (6-24 cameras, 5k-60k points; 0: skip)")
+    ap.add_argument("--uneven-scenes", type=int, default=64, help="distinct seeded uneven clusters (cycled)")
+    ap.add_argument("--global-iters", type=int, default=10,
+                    help="LM iterations of the whole-flight global adjustment (400 cameras, 800k points; 0: skip)")
+    ap.add_argument("--global-oracle-iters", type=int, default=1,
+                    help="oracle LM iterations timed on the whole-flight scene (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(clusters are independent: see the sharding note in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
 
     from paper_2511_06152_amd import BA_FP64, BA_MIXED, Context
 
@@ -219,6 +367,12 @@ def main():
         rms["max_abs_diff_px"] = float(max(d))
         rms["clusters_compared"] = len(common)
 
+    # ---- uneven batched clusters: 6-24 cameras, 5k-60k points, one batch --------------------
+    uneven = run_uneven(args, Context, BA_MIXED, kw) if args.uneven > 0 else None
+
+    # ---- whole-flight global adjustment (PCG on the reduced camera system) ------------------
+    glob = run_global(args, Context, BA_MIXED) if args.global_iters > 0 else None
+
     # ---- CPU baseline: the FP64 oracle on the host cores ---------------------------------
     cpu = None
     if args.cpu_clusters > 0:
@@ -263,9 +417,12 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": achieved_tflops,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_VALU_TFLOPS,
-                     "traffic": None, "avg_launch_us": asm_avg_ms * 1e3,
+                     "traffic": traffic_bytes(dom, B), "traffic_unit": "bytes per launch",
+                     "avg_launch_us": asm_avg_ms * 1e3,
                      "algorithmic_flop_per_launch": fl_total[dom] / max(asm_n, 1)},
         "cpu_baseline": cpu,
+        "batched_uneven": uneven,
+        "global_ba": glob,
     }
     print(json.dumps(out), flush=True)
 

@@ -48,6 +48,16 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ wg_off, int n_a
   return lo;
 }
 
+// Logical workgroup index of this workgroup.  Workgroups are dispatched to the
+// eight XCDs round-robin (physical block b runs on XCD b % 8); the mapping
+// gives each XCD one contiguous eighth of the logical range, so the clusters
+// of a batch (contiguous in logical order) stay within one XCD's L2.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, G = gridDim.x;
+  const int q = G >> 3, r = G & 7, x = b & 7, slot = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
 // Packed storage of a symmetric matrix: element (r, c), r <= c.
 __device__ __forceinline__ int pidx(int r, int c) { return c * (c + 1) / 2 + r; }
 
@@ -386,11 +396,12 @@ __global__ void k_prep_points(Batch bt) {
 // ---- FP64 cost of the current state (admission) -----------------------------------
 
 __global__ __launch_bounds__(kWG) void k_cost0(Batch bt) {
+  const int bx = xcd_block();
   extern __shared__ double sh_cam[];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.wg_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.wg_off, bt.n_act, bx);
   const int s = bt.act[si];
-  const int wgl = blockIdx.x - bt.wg_off[si];
+  const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   const int cur = c.cur;
@@ -433,18 +444,24 @@ __global__ void k_init(Batch bt) {
   const int s = bt.act[blockIdx.x];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
-  if (threadIdx.x != 0) return;
-  double rho = 0.0;
+  // one wavefront: strided lane sums in order, then a fixed xor tree
+  double rho = 0.0, pr = 0.0;
   int bad = 0;
-  for (int w = 0; w < d.n_wg; ++w) { rho += d.cost_part[2 * w]; bad += d.bad_part[w]; }
-  double pr = 0.0;
-  for (int k = 0; k < d.C; ++k) {
+  for (int w = threadIdx.x; w < d.n_wg; w += kWave) {
+    rho += d.cost_part[2 * w];
+    bad += d.bad_part[w];
+  }
+  for (int k = threadIdx.x; k < d.C; k += kWave) {
     if (d.cam_col[k] < 0) continue;
     double e[6], J[9];
     prior_terms(d.cam[c.cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
     #pragma unroll
     for (int i = 0; i < 6; ++i) pr += e[i] * e[i];
   }
+  rho = wave_sum(rho);
+  pr = wave_sum(pr);
+  bad = wave_sum(bad);
+  if (threadIdx.x != 0) return;
   const double E = 0.5 * rho + 0.5 * pr;
   c.E = E;
   c.E0 = E;
@@ -600,11 +617,12 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 // sums (U part of all observations, Schur part of all points).
 template <typename R>
 __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
+  const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.wg_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.wg_off, bt.n_act, bx);
   const int s = bt.act[si];
-  const int wgl = blockIdx.x - bt.wg_off[si];
+  const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING) return;
@@ -667,15 +685,16 @@ __device__ __forceinline__ void wave_store(R (&acc)[N], R* out, int lane) {
 
 template <typename R>
 __global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
+  const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.tkc_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.tkc_off, bt.n_act, bx);
   const int s = bt.act[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int t = 0 + (blockIdx.x - bt.tkc_off[si]) * kWavesPerWG + wave;
+  const int t = 0 + (bx - bt.tkc_off[si]) * kWavesPerWG + wave;
   if (t >= d.n_cam_tasks) return;
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
@@ -747,15 +766,16 @@ __global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
 
 template <typename R>
 __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
+  const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.tkp_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.tkp_off, bt.n_act, bx);
   const int s = bt.act[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int t = d.n_cam_tasks + (blockIdx.x - bt.tkp_off[si]) * kWavesPerWG + wave;
+  const int t = d.n_cam_tasks + (bx - bt.tkp_off[si]) * kWavesPerWG + wave;
   if (t >= d.n_tasks) return;
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
@@ -846,13 +866,14 @@ __device__ double fixed_sum(const R* __restrict__ vals, int stride, int nvals, i
 
 template <typename R>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
+  const int bx = xcd_block();
   __shared__ double sh[kReduceThreads];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.tg_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.tg_off, bt.n_act, bx);
   const int s = bt.act[si];
   const SlotDesc& d = bt.desc[s];
   if (bt.ctl[s].status != ST_RUNNING) return;
-  const int4 tg = d.targets[blockIdx.x - bt.tg_off[si]];
+  const int4 tg = d.targets[bx - bt.tg_off[si]];
   const int kind = tg.x >> 24, ka = (tg.x >> 12) & 0xfff, kb = tg.x & 0xfff;
   const int v = threadIdx.x;
   const int m = d.m, psize = d.psize, kc0 = d.kcol0, kc1 = d.kcol1;
@@ -876,7 +897,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
   const int fa = d.cam_col[ka];
   if (d.sparse) {
     // block-CSR reduced system: both orientations of a pair block, full diagonal blocks
-    const int2 sl = d.tslot[blockIdx.x - bt.tg_off[si]];
+    const int2 sl = d.tslot[bx - bt.tg_off[si]];
     if (kind == TASK_PAIR) {
       const int r = v / 6, cc = v % 6;
       d.Sblk[kSbVals * (size_t)sl.x + kSbRow * r + cc] = t;
@@ -1458,10 +1479,11 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
   const double* const S64 = d.Sblk;
   const int max_it = d.pcg_max_iters;
   // Forcing term of the inexact step: |r| <= eta |b| with
-  // eta = min(pcg_tol, |b| / |b_0|), |b_0| the first solve's right-hand side,
-  // so the steps become exact as the reduced gradient vanishes.
+  // eta = min(pcg_tol, sqrt(|b| / |b_0|)), |b_0| the first solve's right-hand
+  // side: the inexact-Newton choice that keeps superlinear local convergence
+  // while the early steps stay cheap.
   const double b0 = c.cg_b0 > 0.0 ? c.cg_b0 : bnorm;
-  const double tol = b0 > 0.0 ? fmin(d.pcg_tol, bnorm / b0) : d.pcg_tol;
+  const double tol = b0 > 0.0 ? fmin(d.pcg_tol, sqrt(bnorm / b0)) : d.pcg_tol;
   bool good = true;
   int it = 0;
   for (; it < max_it && bnorm > 0.0;) {
@@ -1562,11 +1584,12 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
 
 template <typename R>
 __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
+  const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.wg_off, bt.n_act, blockIdx.x);
+  const int si = find_slot(bt.wg_off, bt.n_act, bx);
   const int s = bt.act[si];
-  const int wgl = blockIdx.x - bt.wg_off[si];
+  const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING || !c.solve_ok || c.point_fail) return;
@@ -1694,13 +1717,23 @@ __global__ void k_lm(Batch bt) {
   const int s = bt.act[blockIdx.x];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
-  if (threadIdx.x != 0 || c.status != ST_RUNNING) return;
+  if (c.status != ST_RUNNING) return;
+  // Workgroup parts of the trial cost: lane l sums parts l, l + 64, ... in
+  // order, then a fixed xor tree (one wavefront; the same order in any batch).
+  double rs = 0.0, ps = 0.0;
+  int bad = 0;
+  for (int w = threadIdx.x; w < d.n_wg; w += kWave) {
+    rs += d.cost_part[2 * w];
+    ps += d.cost_part[2 * w + 1];
+    bad += d.bad_part[w];
+  }
+  rs = wave_sum(rs);
+  ps = wave_sum(ps);
+  bad = wave_sum(bad);
+  if (threadIdx.x != 0) return;
   bool ok = c.solve_ok && !c.point_fail;
   double E2 = INFINITY, pred = 0.0, rho = -INFINITY;
   if (ok) {
-    double rs = 0.0, ps = 0.0;
-    int bad = 0;
-    for (int w = 0; w < d.n_wg; ++w) { rs += d.cost_part[2 * w]; ps += d.cost_part[2 * w + 1]; bad += d.bad_part[w]; }
     if (bad > 0) ok = false;
     E2 = 0.5 * rs + c.E_prior_trial;
     pred = 0.5 * (c.pred_c + ps);
@@ -1869,8 +1902,12 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
     if (mixed) launch(k_reduce<float>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
     else launch(k_reduce<double>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
   }
-  if (b.any_dense || ev) launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 4, b);
-  if (b.any_sparse || ev) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, ev, 7, b);
+  // A solver with no cluster in the batch is not launched; with timing on, its
+  // events mark an empty interval.
+  if (b.any_dense) launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 4, b);
+  else if (ev && ((e = hipEventRecord(ev[8], st)) || (e = hipEventRecord(ev[9], st)))) return e;
+  if (b.any_sparse) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, ev, 7, b);
+  else if (ev && ((e = hipEventRecord(ev[14], st)) || (e = hipEventRecord(ev[15], st)))) return e;
   if (b.total_wg > 0 || ev) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
     if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, ev, 5, bb);

@@ -1,9 +1,18 @@
-"""Summarise a rocprofv3 results database (--kernel-trace): per kernel name and
-launch shape, the number of dispatches and their mean duration.
+"""Summaries of rocprofv3 output.
+
+Kernel trace (results database of --kernel-trace): per kernel name and launch
+shape, the number of dispatches and their mean duration.
 
     python -m paper_2511_06152_amd.profsum <results.db> [top]
+
+Counters (counter_collection.csv of --pmc ... --output-format csv): per kernel
+name, the number of dispatches and the mean value of each counter per
+dispatch; optional substring filter on the kernel name.
+
+    python -m paper_2511_06152_amd.profsum --pmc <counter_collection.csv> [filter]
 """
 import collections
+import csv
 import sqlite3
 import sys
 
@@ -21,5 +30,26 @@ def summarise(path: str, top: int = 20) -> str:
     return "\n".join(lines)
 
 
+def summarise_pmc(path: str, filt: str = "") -> str:
+    vals = collections.defaultdict(list)
+    grids = collections.defaultdict(set)
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"]
+            if filt and filt not in name:
+                continue
+            vals[(name, r["Counter_Name"])].append(float(r["Counter_Value"]))
+            grids[name].add(int(r["Grid_Size"]))
+    lines = [f"{'kernel':60s} {'counter':>12s} {'dispatches':>10s} {'mean/dispatch':>14s} {'grid sizes':>12s}"]
+    for (name, cn), v in sorted(vals.items()):
+        g = sorted(grids[name])
+        gs = str(g[0]) if len(g) == 1 else f"{g[0]}..{g[-1]}"
+        lines.append(f"{name[:60]:60s} {cn:>12s} {len(v):10d} {sum(v) / len(v):14.1f} {gs:>12s}")
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
-    print(summarise(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 20))
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc":
+        print(summarise_pmc(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ""))
+    else:
+        print(summarise(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 20))

@@ -251,18 +251,28 @@ def _spawn_points(spec, rng, R_t, T_t, terrain):
         score[~vis] = np.inf
         order = np.argsort(score, axis=1)
         n_extra = np.minimum(want, vis.sum(1))
-        keep = n_extra >= 1
-        for i in np.nonzero(keep)[0]:
-            if have >= spec.n_points:
-                break
-            cams = np.concatenate([[img[i]], order[i, : n_extra[i]]])
-            X_list.append(X[i])
-            obs_list.append((have, np.sort(cams), uv[i, np.sort(cams)]))
-            have += 1
+        keep = np.nonzero(n_extra >= 1)[0][: spec.n_points - have]
+        if keep.size == 0:
+            continue
+        # observers of each kept point: its spawning image and its n_extra
+        # chosen images, in camera order
+        ne = n_extra[keep]
+        w = int(ne.max()) + 1
+        cams = np.full((keep.size, w), C, np.int64)
+        cams[:, 0] = img[keep]
+        cols = np.arange(1, w)[None, :]
+        cams[:, 1:] = np.where(cols <= ne[:, None], order[keep, : w - 1], C)
+        cams.sort(axis=1)
+        sel = np.arange(w)[None, :] <= ne[:, None]
+        rows = np.repeat(np.arange(keep.size), ne + 1)
+        cam_flat = cams[sel]
+        X_list.append(X[keep])
+        obs_list.append((rows + have, cam_flat, uv[keep[rows], cam_flat]))
+        have += keep.size
 
-    X_true = np.array(X_list)
+    X_true = np.concatenate(X_list)
     obs_cam = np.concatenate([o[1] for o in obs_list]).astype(np.int32)
-    obs_pt = np.concatenate([np.full(len(o[1]), o[0]) for o in obs_list]).astype(np.int32)
+    obs_pt = np.concatenate([o[0] for o in obs_list]).astype(np.int32)
     uv_true = np.concatenate([o[2] for o in obs_list])
     return X_true, obs_cam, obs_pt, uv_true
 

@@ -9,7 +9,7 @@ Bars:
   * mixed path (FP32 products) with a tight PCG tolerance (1e-6), so that it
     follows the exact LM's trajectory: after 60 iterations RMS
     |p_gpu - p_oracle| < 1e-3 px, camera centres < 1 mm, attitude < 2e-6 rad;
-  * default inexact steps (forcing term min(0.1, |b|/|b_0|)): these take a
+  * default inexact steps (forcing term min(0.1, sqrt(|b|/|b_0|))): these take a
     different path down the same cost, so they are held to the oracle's cost
     and RMS reprojection error at equal iteration count, not to its state;
   * a cluster solved by PCG gives bit-identical results alone and batched with
