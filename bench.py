@@ -164,6 +164,57 @@ def run_uneven(args, Context, precision, kw):
             "points_range": [min(pts), max(pts)], "obs_total": int(sum(obs)), "hbm_budget_bytes": budget}
 
 
+def run_stream(args, Context, precision, kw):
+    """The serving stream: 4 strips x 40 images flown in order, each arriving
+    image triggering a sliding cluster of 8-20 images over one global
+    tie-point pool.  Clusters go to the continuous-batching loop with resident
+    state keyed by image and point IDs (each starts from the state the clusters
+    before it left, in submission order), closed loop with a fixed number in
+    flight.  Latency = submit -> result available."""
+    from collections import deque
+    from paper_2511_06152_amd.ba import Cluster
+    t_gen = time.perf_counter()
+    st = A.make_stream(3)
+    cl = st["clusters"]
+    log(f"stream: {len(cl)} clusters from {st['flight']['n_cams']} images, "
+        f"{st['flight']['n_points']} pool points in {time.perf_counter() - t_gen:.1f}s")
+    probe = Context(precision=precision, max_slots=2, hbm_budget_bytes=64 << 20)
+    foot = max(probe.ba_footprint(Cluster(sc, **kw)) for sc in cl)
+    probe.close()
+    W = max(args.stream_window, 1)
+    lat, walls = [], []
+    for rep in range(args.stream_reps):
+        ctx = Context(precision=precision, serve=True, max_slots=W + 2, hbm_budget_bytes=(W + 2) * foot + (64 << 20))
+        pending = deque()
+        t0 = time.perf_counter()
+
+        def retire():
+            t = pending.popleft()
+            ctx.ba_wait(t)
+            r = ctx.ba_fetch(t)
+            lat.append((r["t_done"] - r["t_submit"]) * 1e3)
+            ctx.ba_release(t)
+
+        for sc in cl:
+            while len(pending) >= W:
+                retire()
+            t = ctx.submit(sc, use_resident=True, **kw)
+            ctx.ba_solve(t)
+            pending.append(t)
+        while pending:
+            retire()
+        walls.append(time.perf_counter() - t0)
+        ctx.close()
+        log(f"stream rep {rep}: {len(cl)} clusters in {walls[-1] * 1e3:.0f} ms")
+    return {"clusters_per_rep": len(cl), "reps": args.stream_reps, "window": W,
+            "cams_range": [min(c["n_cams"] for c in cl), max(c["n_cams"] for c in cl)],
+            "points_range": [min(c["n_points"] for c in cl), max(c["n_points"] for c in cl)],
+            "obs_range": [min(c["n_obs"] for c in cl), max(c["n_obs"] for c in cl)],
+            "clusters_per_s": len(cl) * len(walls) / sum(walls), "latencies": len(lat),
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "budget_ms": 2080.0,
+            "p99_fraction_of_budget": pct(lat, 99) / 2080.0}
+
+
 def run_global(args, Context, precision):
     """Whole-flight global adjustment: 400 cameras (10 strips x 40), 800k points,
     ~3.5M observations; the reduced camera system (m = 2400) by block-Jacobi
@@ -229,6 +280,10 @@ def main():
                     help="LM iterations of the whole-flight global adjustment (400 cameras, 800k points; 0: skip)")
     ap.add_argument("--global-oracle-iters", type=int, default=1,
                     help="oracle LM iterations timed on the whole-flight scene (0: skip)")
+    ap.add_argument("--stream-reps", type=int, default=5,
+                    help="repetitions of the serving stream (4 strips x 40 images, one cluster per arriving "
+                         "image, resident state; 0: skip)")
+    ap.add_argument("--stream-window", type=int, default=2, help="stream clusters in flight (closed loop)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -370,6 +425,9 @@ def main():
     # ---- uneven batched clusters: 6-24 cameras, 5k-60k points, one batch --------------------
     uneven = run_uneven(args, Context, BA_MIXED, kw) if args.uneven > 0 else None
 
+    # ---- serving stream: one cluster per arriving image, resident state -------------------
+    stream = run_stream(args, Context, BA_MIXED, kw) if args.stream_reps > 0 else None
+
     # ---- whole-flight global adjustment (PCG on the reduced camera system) ------------------
     glob = run_global(args, Context, BA_MIXED) if args.global_iters > 0 else None
 
@@ -422,6 +480,7 @@ def main():
                      "algorithmic_flop_per_launch": fl_total[dom] / max(asm_n, 1)},
         "cpu_baseline": cpu,
         "batched_uneven": uneven,
+        "serving_stream": stream,
         "global_ba": glob,
     }
     print(json.dumps(out), flush=True)

@@ -109,6 +109,11 @@ typedef struct {
   int32_t pcg_max_iters;     /* conjugate-gradient iterations per LM step; 0 -> 500 */
   double pcg_tol;            /* stop when |r| <= pcg_tol |b| (the forcing term of an inexact
                                 LM step); 0 -> 0.1 */
+  int32_t resident_cams;     /* capacity of the device-resident camera state keyed by global
+                                ID (see ba_cluster.use_resident); 0 -> 8192 */
+  int32_t resident_points;   /* capacity of the resident point state; 0 -> 4194304.  The
+                                store (96 B per camera, 24 B per point) is allocated at the
+                                first cluster that uses it, outside the arena */
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */
@@ -132,8 +137,26 @@ typedef struct {
   double huber_delta;           /* Huber threshold on |e|, pixels (> 0) */
   int32_t max_iters;            /* LM iterations (1..4096) */
   int32_t stop_on_ftol;         /* 1: stop when an accepted step has (E - E') < ftol E */
-  double lambda0;               /* initial damping (clamped to [1e-16, 1e32]) */
+  double lambda0;               /* initial damping (clamped to [1e-16, 1e32]); NaN: the damping
+                                   the last cluster written back to the resident state ended
+                                   with, or 1e-4 when there is none */
   double ftol;
+  /* Resident state across overlapping clusters (Sec. 3.2: consecutive clusters
+   * share images and tie points; the next cluster starts from the previous
+   * one's solution).  cam_ids / point_ids give each camera and point a global
+   * ID (unique within the cluster).  With use_resident = 1:
+   *  - every ID written back by an earlier cluster takes its initial value
+   *    (R, T or X) from the device-resident state, and the caller's value for it
+   *    is ignored; priors always come from the caller;
+   *  - the cluster is admitted only after every earlier-submitted cluster that
+   *    shares an ID with it has finished and written back (or was released), so
+   *    overlapping clusters run in submission order;
+   *  - when it finishes (any status but BA_ST_BAD_INIT) its final poses and
+   *    points are written back under their IDs, on the device.
+   * With use_resident = 0 the IDs are ignored and nothing is read or written. */
+  const int64_t* cam_ids;       /* [C] or NULL (required with use_resident) */
+  const int64_t* point_ids;     /* [P] or NULL (required with use_resident) */
+  int32_t use_resident;
 } ba_cluster;
 
 /* Results (ba_fetch).  Every pointer may be NULL (not written). */
@@ -167,16 +190,19 @@ int ba_destroy(ba_ctx* ctx);
  * device slot if a slot and arena memory are free, else queue it.  Checks:
  * indices in range, finite inputs, 1..64 observations per observed point,
  * no camera twice on one point, <= BA_MAX_CAMS cameras, <= BA_MAX_FREE_CAMS free
- * cameras for the dense solver, no estimated intrinsics with the PCG solver.
- * Errors: BA_E_ARG, BA_E_NOMEM (larger than the whole arena), BA_E_AGAIN
- * (queue full), BA_E_DEVICE. */
+ * cameras for the dense solver, no estimated intrinsics with the PCG solver,
+ * unique global IDs when use_resident is set.
+ * Errors: BA_E_ARG, BA_E_NOMEM (larger than the whole arena, or the resident
+ * store is full), BA_E_AGAIN (queue full), BA_E_DEVICE. */
 int ba_submit_cluster(ba_ctx* ctx, const ba_cluster* cluster, ba_ticket* ticket);
 
 /* Run up to n_iters LM iterations of one cluster now, on the calling thread,
  * reading the LM status back after every iteration (the plain, host-driven
- * loop).  Admits the cluster first if it is still queued.
+ * loop).  Admits the cluster first if it is still queued.  A resident cluster
+ * that finishes writes its state back before this returns.
  * Errors: BA_E_ARG (unknown ticket), BA_E_AGAIN (no slot or memory free),
- * BA_E_STATE (the cluster is owned by the serving loop), BA_E_DEVICE. */
+ * BA_E_STATE (the cluster is owned by the serving loop, or it uses resident
+ * state that an unfinished earlier cluster has still to write), BA_E_DEVICE. */
 int ba_step(ba_ctx* ctx, ba_ticket ticket, int32_t n_iters);
 
 /* Solve the given clusters together to termination on the calling thread:

@@ -33,7 +33,7 @@ class ba_options(ct.Structure):
                 ("max_slots", ct.c_int32), ("max_queue", ct.c_int32), ("precision", ct.c_int32),
                 ("serve", ct.c_int32), ("iters_per_tick", ct.c_int32), ("chunks_per_wg", ct.c_int32),
                 ("chunks_per_task", ct.c_int32), ("solver", ct.c_int32), ("pcg_max_iters", ct.c_int32),
-                ("pcg_tol", ct.c_double)]
+                ("pcg_tol", ct.c_double), ("resident_cams", ct.c_int32), ("resident_points", ct.c_int32)]
 
 
 class ba_cluster(ct.Structure):
@@ -44,7 +44,8 @@ class ba_cluster(ct.Structure):
                 ("f", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double),
                 ("sigma_px", ct.c_double), ("huber_delta", ct.c_double),
                 ("max_iters", ct.c_int32), ("stop_on_ftol", ct.c_int32),
-                ("lambda0", ct.c_double), ("ftol", ct.c_double)]
+                ("lambda0", ct.c_double), ("ftol", ct.c_double),
+                ("cam_ids", ct.c_void_p), ("point_ids", ct.c_void_p), ("use_resident", ct.c_int32)]
 
 
 class ba_result(ct.Structure):
@@ -106,7 +107,7 @@ class Cluster:
     """Marshals a scene dict into a ba_cluster, keeping the arrays alive."""
 
     def __init__(self, sc: dict, max_iters: int = 10, lambda0: float = 1e-4, ftol: float = 1e-10,
-                 stop_on_ftol: bool = False):
+                 stop_on_ftol: bool = False, use_resident: bool = False):
         C, P, O = int(sc["n_cams"]), int(sc["n_points"]), int(sc["n_obs"])
         f64 = lambda x: np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1))
         self.arrays = {
@@ -118,6 +119,9 @@ class Cluster:
             "obs_pt": np.ascontiguousarray(np.asarray(sc["obs_pt"], np.int32).reshape(-1)),
             "obs_uv": f64(sc["obs_uv"]) if O else np.zeros(2),
         }
+        for key in ("cam_ids", "point_ids"):
+            if sc.get(key) is not None:
+                self.arrays[key] = np.ascontiguousarray(np.asarray(sc[key], np.int64).reshape(-1))
         a = self.arrays
         self.C, self.P, self.O, self.max_iters = C, P, O, max_iters
         self.c = ba_cluster(C, P, O, int(sc["intr_mask"]),
@@ -125,7 +129,8 @@ class Cluster:
                             _p(a["prior_sigma"]), _p(a["fixed"]), _p(a["obs_cam"]), _p(a["obs_pt"]), _p(a["obs_uv"]),
                             float(sc["f"]), float(sc["cx"]), float(sc["cy"]), float(sc["sigma_px"]),
                             float(sc["huber_delta"]), int(max_iters), 1 if stop_on_ftol else 0,
-                            float(lambda0), float(ftol))
+                            float(lambda0), float(ftol), _p(a.get("cam_ids")), _p(a.get("point_ids")),
+                            1 if use_resident else 0)
 
 
 class Context:
@@ -134,10 +139,12 @@ class Context:
     def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256,
                  max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
                  chunks_per_wg: int = 16, chunks_per_task: int = 4, solver: int = BA_SOLVER_AUTO,
-                 pcg_max_iters: int = 500, pcg_tol: float = 0.1):
+                 pcg_max_iters: int = 500, pcg_tol: float = 0.1, resident_cams: int = 0,
+                 resident_points: int = 0):
         self.lib = load()
         opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
-                         iters_per_tick, chunks_per_wg, chunks_per_task, solver, pcg_max_iters, pcg_tol)
+                         iters_per_tick, chunks_per_wg, chunks_per_task, solver, pcg_max_iters, pcg_tol,
+                         resident_cams, resident_points)
         h = ct.c_void_p()
         rc = self.lib.ba_create(ct.byref(opt), ct.byref(h))
         if rc != BA_OK:

@@ -61,7 +61,7 @@ struct SlotDesc {
   double* cam[2];                         // [C][12] state buffers
   double* prior;                          // [C][18]
   const int* cam_col;                     // [C] first reduced-system column, -1 if fixed
-  const double* raw_cam;                  // [C][30] R (9), T (3), R_prior (9), T_prior (3), sigma (6)
+  double* raw_cam;                        // [C][30] R (9), T (3), R_prior (9), T_prior (3), sigma (6)
   // points
   double* X[2];                           // [P][3] state buffers (origin-shifted)
   float* X32[2];                          // [P][3] FP32 shadows of X
@@ -80,6 +80,14 @@ struct SlotDesc {
   double* Sblk;                           // [nnzb][6][kSbRow] FP64 blocks, row-major, rows padded
   float* Sblk32;                          // [nnzb][6][kSbRow] FP32 copy for the mixed-precision products
   double* pcgw;                           // [2m] PCG work: gradient with priors, clamped diagonal
+  // resident state keyed by global IDs (shared by the context's clusters)
+  int n_rin_cam, n_rin_pt, n_rout_cam, n_rout_pt;
+  double* res_cam;                        // [cap][12] world frame: R row-major (9), T (3)
+  double* res_pt;                         // [cap][3] world frame
+  const int2* rin_cam;                    // [n_rin_cam] (camera, row) read at admission
+  const int2* rin_pt;                     // [n_rin_pt] (internal point, row) read at admission
+  const int2* rout_cam;                   // [n_rout_cam] (camera, row) written back
+  const int2* rout_pt;                    // [n_rout_pt] (caller's point index, row) written back
   double* dc;                             // [m] camera / intrinsic update
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
   int* bad_part;                          // [n_wg] trial observations at non-positive depth
@@ -113,13 +121,17 @@ struct Batch {
   int any_sparse, any_dense;
 };
 
-hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st);
+// max_rin: largest resident gather list of the batch (0: none).
+hipError_t launch_prep(const Batch& b, int max_P_L, int max_rin, hipStream_t st);
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
 // ev (optional): 16 events, the start and end of each of the eight kernels
 // of the iteration (point, camera blocks, pair blocks, reduce, dense solve,
 // back-substitution, LM, PCG solve), recorded by the dispatches themselves.
 hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
+// Writes the exported state of the batch's clusters back to the resident
+// store (after launch_export); max_rout: largest write-back list.
+hipError_t launch_writeback(const Batch& b, int max_rout, hipStream_t st);
 
 size_t real_size(bool mixed);
 

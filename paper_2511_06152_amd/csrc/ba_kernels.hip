@@ -356,6 +356,41 @@ __global__ void k_prep_slot(Batch bt) {
   }
 }
 
+// Initial values of cameras and points known to the resident store, before
+// the origin shift (world frame, over the caller's values).
+__global__ void k_res_gather(Batch bt) {
+  const int s = bt.act[blockIdx.y];
+  const SlotDesc& d = bt.desc[s];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n_rin_cam) {
+    const int2 e = d.rin_cam[i];
+    double* r = d.raw_cam + 30 * (size_t)e.x;
+    const double* src = d.res_cam + 12 * (size_t)e.y;
+    for (int t = 0; t < 12; ++t) r[t] = src[t];
+  }
+  if (i < d.n_rin_pt) {
+    const int2 e = d.rin_pt[i];
+    for (int t = 0; t < 3; ++t) d.X[0][3 * (size_t)e.x + t] = d.res_pt[3 * (size_t)e.y + t];
+  }
+}
+
+// Final state (export staging, world frame) into the resident store.
+__global__ void k_res_scatter(Batch bt) {
+  const int s = bt.act[blockIdx.y];
+  const SlotDesc& d = bt.desc[s];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n_rout_cam) {
+    const int2 e = d.rout_cam[i];
+    double* dst = d.res_cam + 12 * (size_t)e.y;
+    for (int t = 0; t < 9; ++t) dst[t] = d.out[9 * (size_t)e.x + t];
+    for (int t = 0; t < 3; ++t) dst[9 + t] = d.out[9 * (size_t)d.C + 3 * (size_t)e.x + t];
+  }
+  if (i < d.n_rout_pt) {
+    const int2 e = d.rout_pt[i];
+    for (int t = 0; t < 3; ++t) d.res_pt[3 * (size_t)e.y + t] = d.out[12 * (size_t)d.C + 3 * (size_t)e.x + t];
+  }
+}
+
 __global__ void k_prep_points(Batch bt) {
   const int s = bt.act[blockIdx.y];
   const SlotDesc& d = bt.desc[s];
@@ -1835,8 +1870,9 @@ hipError_t ensure_smem(const void* fn, size_t bytes) {
 
 size_t real_size(bool mixed) { return mixed ? sizeof(float) : sizeof(double); }
 
-hipError_t launch_prep(const Batch& b, int max_P_L, hipStream_t st) {
+hipError_t launch_prep(const Batch& b, int max_P_L, int max_rin, hipStream_t st) {
   if (b.n_act == 0) return hipSuccess;
+  if (max_rin > 0) hipLaunchKernelGGL(k_res_gather, dim3((max_rin + 255) / 256, b.n_act), dim3(256), 0, st, b);
   hipLaunchKernelGGL(k_prep_slot, dim3(b.n_act), dim3(64), 0, st, b);
   if (max_P_L > 0) hipLaunchKernelGGL(k_prep_points, dim3((max_P_L + 255) / 256, b.n_act), dim3(256), 0, st, b);
   return hipGetLastError();
@@ -1914,6 +1950,12 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
     else launch(k_backsub<double>, g_pt, dim3(kWG), sb, st, ev, 5, bb);
   }
   launch(k_lm, dim3(b.n_act), dim3(64), 0, st, ev, 6, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_writeback(const Batch& b, int max_rout, hipStream_t st) {
+  if (b.n_act == 0 || max_rout <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_res_scatter, dim3((max_rout + 255) / 256, b.n_act), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

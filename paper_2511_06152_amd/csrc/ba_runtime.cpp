@@ -17,6 +17,8 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/ba.h"
@@ -89,12 +91,15 @@ struct Staged {
   int sparse = 0;
   std::vector<int> brow, bcol;   // [F + 1], [nnzb]
   std::vector<int2> tslot;       // [n_targets] block slots (a,b), (b,a) of each target
+  // resident state: global IDs (caller order) when the cluster uses it
+  bool resident = false;
+  std::vector<int64_t> cam_ids, point_ids;
 };
 
 struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, pt_orig, task_part, pt_part, Sg, Sd, dc,
-      brow, bcol, tslot, Sblk, Sblk32, pcgw, cost_part,
+      brow, bcol, tslot, Sblk, Sblk32, pcgw, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, out, total;
   int n_wg, psize, pstride;
 };
@@ -145,6 +150,11 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.Sblk = take(8 * (size_t)kSbVals * nnzb);
   l.Sblk32 = take(4 * (size_t)kSbVals * nnzb);
   l.pcgw = take(8 * 2 * (size_t)(s.sparse ? s.m : 0));
+  const size_t rc = s.resident ? (size_t)s.C : 0, rp = s.resident ? (size_t)s.P : 0;
+  l.rin_cam = take(sizeof(int2) * rc);
+  l.rin_pt = take(sizeof(int2) * rp);
+  l.rout_cam = take(sizeof(int2) * rc);
+  l.rout_pt = take(sizeof(int2) * rp);
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
   l.cost_log = take(8 * ((size_t)s.max_iters + 1));
@@ -189,8 +199,21 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   }
   for (size_t i = 0; i < 6 * (size_t)C; ++i)
     if (std::isnan(c->prior_sigma[i])) { err = "NaN prior sigma"; return BA_E_ARG; }
+  if (c->use_resident != 0 && c->use_resident != 1) { err = "use_resident must be 0 or 1"; return BA_E_ARG; }
+  if (c->use_resident) {
+    if (!c->cam_ids || (P > 0 && !c->point_ids)) { err = "use_resident needs cam_ids and point_ids"; return BA_E_ARG; }
+    std::unordered_set<int64_t> seen(c->cam_ids, c->cam_ids + C);
+    if ((int)seen.size() != C) { err = "duplicate camera ID in the cluster"; return BA_E_ARG; }
+    seen = std::unordered_set<int64_t>(c->point_ids, c->point_ids + P);
+    if ((int)seen.size() != P) { err = "duplicate point ID in the cluster"; return BA_E_ARG; }
+  }
   s = Staged();
   s.C = C; s.P = P; s.O = O;
+  if (c->use_resident) {
+    s.resident = true;
+    s.cam_ids.assign(c->cam_ids, c->cam_ids + C);
+    s.point_ids.assign(c->point_ids, c->point_ids + P);
+  }
   s.max_iters = c->max_iters; s.stop_on_ftol = c->stop_on_ftol;
   s.f = c->f; s.cx = c->cx; s.cy = c->cy; s.sigma = c->sigma_px; s.delta = c->huber_delta;
   s.lambda0 = c->lambda0; s.ftol = c->ftol; s.k[0] = c->k[0]; s.k[1] = c->k[1];
@@ -429,6 +452,12 @@ struct Ticket {
   // results cached when the serving loop retires the cluster
   std::vector<double> out, cost_log;
   SlotCtl ctl{};
+  // resident state: rows of the store per camera and per point (caller order),
+  // clusters that must write back first, and whether this one has finished
+  // with the store (written back, or nothing to write)
+  bool resident = false, res_done = false;
+  std::vector<int> cam_rows, pt_rows;
+  std::vector<ba_ticket> deps;
 };
 
 struct Slot {
@@ -480,6 +509,13 @@ struct ba_ctx {
   size_t prof_used = 0;
   double prof_ms[BA_PROF_N] = {};
   int64_t prof_n[BA_PROF_N] = {};
+  // resident state keyed by global IDs (allocated at first use)
+  struct ResRow { ba_ticket pending = 0; bool valid = false; };
+  double* res_cam = nullptr;      // [cap][12]
+  double* res_pt = nullptr;       // [cap][3]
+  std::unordered_map<int64_t, int> res_cam_row, res_pt_row;
+  std::vector<ResRow> res_cam_meta, res_pt_meta;
+  double res_lambda = NAN;        // damping the last written-back cluster ended with
 };
 
 namespace {
@@ -588,6 +624,64 @@ int read_ctl(ba_ctx* c, Launcher& l) {
   return BA_OK;
 }
 
+bool is_finished(int status) { return status != ST_RUNNING && status != ST_QUEUED; }
+
+// ---- resident state ---------------------------------------------------------------
+
+bool deps_done(ba_ctx* c, const Ticket& t) {
+  for (ba_ticket dep : t.deps) {
+    auto it = c->tickets.find(dep);
+    if (it != c->tickets.end() && !it->second->res_done) return false;
+  }
+  return true;
+}
+
+// Assigns store rows to the cluster's IDs (new IDs get new rows) and records
+// which earlier clusters must write back before it may read them.  Caller
+// holds mu.
+int res_register(ba_ctx* c, Ticket& t, const Staged& s) {
+  const int capC = c->opt.resident_cams, capP = c->opt.resident_points;
+  if (!c->res_cam) {
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, BA_E_DEVICE, "hipSetDevice failed");
+    if (hipMalloc(&c->res_cam, sizeof(double) * 12 * (size_t)capC) != hipSuccess ||
+        hipMalloc(&c->res_pt, sizeof(double) * 3 * (size_t)capP) != hipSuccess) {
+      return fail(c, BA_E_NOMEM, "cannot allocate the resident store");
+    }
+  }
+  size_t new_c = 0, new_p = 0;
+  for (int64_t id : s.cam_ids) new_c += c->res_cam_row.count(id) ? 0 : 1;
+  for (int64_t id : s.point_ids) new_p += c->res_pt_row.count(id) ? 0 : 1;
+  if (c->res_cam_meta.size() + new_c > (size_t)capC || c->res_pt_meta.size() + new_p > (size_t)capP)
+    return fail(c, BA_E_NOMEM, "resident store full");
+  std::unordered_set<ba_ticket> deps;
+  auto reg = [&](int64_t id, std::unordered_map<int64_t, int>& rows, std::vector<ba_ctx::ResRow>& meta) {
+    auto it = rows.find(id);
+    int row;
+    if (it == rows.end()) {
+      row = (int)meta.size();
+      rows.emplace(id, row);
+      meta.emplace_back();
+    } else {
+      row = it->second;
+    }
+    const ba_ticket p = meta[row].pending;
+    if (p) {
+      auto pt = c->tickets.find(p);
+      if (pt != c->tickets.end() && !pt->second->res_done) deps.insert(p);
+    }
+    meta[row].pending = t.id;
+    return row;
+  };
+  t.cam_rows.resize(s.C);
+  t.pt_rows.resize(s.P);
+  for (int k = 0; k < s.C; ++k) t.cam_rows[k] = reg(s.cam_ids[k], c->res_cam_row, c->res_cam_meta);
+  for (int j = 0; j < s.P; ++j) t.pt_rows[j] = reg(s.point_ids[j], c->res_pt_row, c->res_pt_meta);
+  t.deps.assign(deps.begin(), deps.end());
+  std::sort(t.deps.begin(), t.deps.end());
+  t.resident = true;
+  return BA_OK;
+}
+
 // Moves the ticket's staged data into a free slot and arena block.  Returns
 // BA_E_AGAIN when no slot or memory is free.  Caller holds mu.
 int admit_one(ba_ctx* c, Ticket& t) {
@@ -619,7 +713,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.n_pair_task_wg = (d.n_tasks - d.n_cam_tasks + kWavesPerWG - 1) / kWavesPerWG;
   d.n_targets = (int)s.targets.size(); d.n_pt_part = s.n_pt_part;
   d.f = s.f; d.cx = s.cx; d.cy = s.cy; d.inv_sigma = 1.0 / s.sigma; d.huber_dt = s.delta / s.sigma;
-  d.ftol = s.ftol; d.lambda0 = s.lambda0;
+  d.ftol = s.ftol;
+  d.lambda0 = std::isnan(s.lambda0) ? (std::isnan(c->res_lambda) ? 1e-4 : c->res_lambda) : s.lambda0;
   d.sparse = s.sparse; d.nnzb = (int)s.bcol.size();
   d.pcg_max_iters = c->opt.pcg_max_iters; d.pcg_tol = c->opt.pcg_tol;
   d.lane_pt = (const int*)(base + lay.lane_pt);
@@ -639,7 +734,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.cam[1] = (double*)(base + lay.cam1);
   d.prior = (double*)(base + lay.prior);
   d.cam_col = (const int*)(base + lay.cam_col);
-  d.raw_cam = (const double*)(base + lay.raw_cam);
+  d.raw_cam = (double*)(base + lay.raw_cam);
   d.X[0] = (double*)(base + lay.X0);
   d.X[1] = (double*)(base + lay.X1);
   d.X32[0] = (float*)(base + lay.X320);
@@ -658,6 +753,27 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.Sblk = (double*)(base + lay.Sblk);
   d.Sblk32 = (float*)(base + lay.Sblk32);
   d.pcgw = (double*)(base + lay.pcgw);
+  std::vector<int2> rin_c, rin_p, rout_c, rout_p;
+  if (t.resident) {
+    for (int k = 0; k < s.C; ++k) {
+      const int row = t.cam_rows[k];
+      rout_c.push_back(make_int2(k, row));
+      if (c->res_cam_meta[row].valid) rin_c.push_back(make_int2(k, row));
+    }
+    for (int n = 0; n < s.P; ++n) {
+      const int j = s.pt_orig[n], row = t.pt_rows[j];
+      rout_p.push_back(make_int2(j, row));
+      if (c->res_pt_meta[row].valid) rin_p.push_back(make_int2(n, row));
+    }
+  }
+  d.n_rin_cam = (int)rin_c.size(); d.n_rin_pt = (int)rin_p.size();
+  d.n_rout_cam = (int)rout_c.size(); d.n_rout_pt = (int)rout_p.size();
+  d.res_cam = c->res_cam;
+  d.res_pt = c->res_pt;
+  d.rin_cam = (const int2*)(base + lay.rin_cam);
+  d.rin_pt = (const int2*)(base + lay.rin_pt);
+  d.rout_cam = (const int2*)(base + lay.rout_cam);
+  d.rout_pt = (const int2*)(base + lay.rout_pt);
   d.cost_part = (double*)(base + lay.cost_part);
   d.bad_part = (int*)(base + lay.bad_part);
   d.cost_log = (double*)(base + lay.cost_log);
@@ -691,6 +807,13 @@ int admit_one(ba_ctx* c, Ticket& t) {
     HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(base + lay.pt_orig, s.pt_orig.data(), 4 * (size_t)s.P, hipMemcpyHostToDevice, st));
   }
+  auto up2 = [&](size_t off, const std::vector<int2>& v) {
+    return v.empty() ? hipSuccess : hipMemcpyAsync(base + off, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, st);
+  };
+  HIPCHK(c, up2(lay.rin_cam, rin_c));
+  HIPCHK(c, up2(lay.rin_pt, rin_p));
+  HIPCHK(c, up2(lay.rout_cam, rout_c));
+  HIPCHK(c, up2(lay.rout_pt, rout_p));
   HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
   SlotCtl ctl{};
   ctl.k[0][0] = s.k[0];
@@ -712,10 +835,13 @@ int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   Batch b;
   int rc = make_batch(c, l, slots, b);
   if (rc) return rc;
-  int maxPL = 0;
-  for (int s : slots)
-    maxPL = std::max({maxPL, c->slots[s].desc.P, c->slots[s].desc.L, c->slots[s].desc.Lc, 2 * c->slots[s].desc.Lq});
-  HIPCHK(c, launch_prep(b, maxPL, c->stream));
+  int maxPL = 0, maxRin = 0;
+  for (int s : slots) {
+    const SlotDesc& d = c->slots[s].desc;
+    maxPL = std::max({maxPL, d.P, d.L, d.Lc, 2 * d.Lq});
+    maxRin = std::max({maxRin, d.n_rin_cam, d.n_rin_pt});
+  }
+  HIPCHK(c, launch_prep(b, maxPL, maxRin, c->stream));
   HIPCHK(c, launch_initial_cost(b, c->stream));
   return BA_OK;
 }
@@ -773,9 +899,39 @@ int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
     HIPCHK(c, hipMemcpyAsync(t.out.data(), sl.desc.out, 8 * t.out.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(t.cost_log.data(), sl.desc.cost_log, 8 * t.cost_log.size(), hipMemcpyDeviceToHost, c->stream));
   }
+  // Finished resident clusters write their state back (once).
+  std::vector<int> wb, done;
+  for (int s : slots) {
+    Ticket& t = *c->tickets[c->slots[s].ticket];
+    const int st = l.h_ctl[s].status;
+    if (!t.resident || t.res_done || !is_finished(st)) continue;
+    done.push_back(s);
+    if (st != ST_BAD_INIT) wb.push_back(s);
+  }
+  if (!wb.empty()) {
+    Batch bw;
+    if ((rc = make_batch(c, l, wb, bw))) return rc;
+    int maxR = 0;
+    for (int s : wb) maxR = std::max({maxR, c->slots[s].desc.n_rout_cam, c->slots[s].desc.n_rout_pt});
+    HIPCHK(c, launch_writeback(bw, maxR, c->stream));
+  }
   rc = read_ctl(c, l);
   if (rc) return rc;
   for (int s : slots) c->tickets[c->slots[s].ticket]->ctl = l.h_ctl[s];
+  for (int s : done) {
+    Ticket& t = *c->tickets[c->slots[s].ticket];
+    if (l.h_ctl[s].status != ST_BAD_INIT) {
+      for (int row : t.cam_rows) c->res_cam_meta[row].valid = true;
+      for (int row : t.pt_rows) c->res_pt_meta[row].valid = true;
+      c->res_lambda = l.h_ctl[s].lambda;
+    }
+    for (int row : t.cam_rows)
+      if (c->res_cam_meta[row].pending == t.id) c->res_cam_meta[row].pending = 0;
+    for (int row : t.pt_rows)
+      if (c->res_pt_meta[row].pending == t.id) c->res_pt_meta[row].pending = 0;
+    t.res_done = true;
+  }
+  if (!done.empty()) c->cv.notify_all();
   return BA_OK;
 }
 
@@ -787,11 +943,13 @@ void free_slot(ba_ctx* c, int s) {
 }
 
 // Admits queued tickets in FIFO order while slots and memory allow.  When
-// `serving_only`, only tickets handed to the serving loop are admitted.
+// `serving_only`, only tickets handed to the serving loop are admitted.  A
+// ticket that waits for earlier clusters to write back resident state is
+// passed over (later tickets that do not depend on it go ahead).
 int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only) {
   for (auto it = c->queue.begin(); it != c->queue.end();) {
     Ticket& t = *c->tickets[*it];
-    if (serving_only && !t.serving) { ++it; continue; }
+    if ((serving_only && !t.serving) || !deps_done(c, t)) { ++it; continue; }
     int rc = admit_one(c, t);
     if (rc == BA_E_AGAIN) break;
     if (rc) return rc;
@@ -801,13 +959,15 @@ int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only) {
   return BA_OK;
 }
 
+// A serving ticket is queued that could be admitted now (its resident
+// dependencies have written back).
 bool serving_queued(ba_ctx* c) {
-  for (ba_ticket id : c->queue)
-    if (c->tickets[id]->serving) return true;
+  for (ba_ticket id : c->queue) {
+    const Ticket& t = *c->tickets[id];
+    if (t.serving && deps_done(c, t)) return true;
+  }
   return false;
 }
-
-bool is_finished(int status) { return status != ST_RUNNING && status != ST_QUEUED; }
 
 // One serving tick: retire finished clusters, admit queued ones, iterate.
 void serve_loop(ba_ctx* c) {
@@ -871,6 +1031,8 @@ int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
   if (t.serving) return fail(c, BA_E_STATE, "cluster is owned by the serving loop");
   if (t.state == TK_RESIDENT) return BA_OK;
   if (t.state == TK_DONE) return fail(c, BA_E_STATE, "cluster already retired");
+  if (!deps_done(c, t))
+    return fail(c, BA_E_STATE, "cluster reads resident state that an unfinished earlier cluster has still to write");
   int rc = admit_one(c, t);
   if (rc == BA_E_AGAIN) return fail(c, BA_E_AGAIN, "no free slot or arena memory");
   if (rc) return rc;
@@ -912,6 +1074,8 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
   if (c->opt.pcg_max_iters <= 0) c->opt.pcg_max_iters = 500;
   if (!(c->opt.pcg_tol > 0)) c->opt.pcg_tol = 0.1;
+  if (c->opt.resident_cams <= 0) c->opt.resident_cams = 8192;
+  if (c->opt.resident_points <= 0) c->opt.resident_points = 1 << 22;
   if (c->opt.solver < BA_SOLVER_AUTO || c->opt.solver > BA_SOLVER_PCG || c->opt.pcg_max_iters > 100000 ||
       !(c->opt.pcg_tol < 1)) return BA_E_ARG;
   if (c->opt.max_slots > 65536 || c->opt.chunks_per_wg > 4096 || c->opt.chunks_per_task > 4096) return BA_E_ARG;
@@ -962,6 +1126,8 @@ int ba_destroy(ba_ctx* c) {
   if (c->d_desc) hipFree(c->d_desc);
   if (c->d_ctl) hipFree(c->d_ctl);
   if (c->arena_base) hipFree(c->arena_base);
+  if (c->res_cam) hipFree(c->res_cam);
+  if (c->res_pt) hipFree(c->res_pt);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return BA_OK;
@@ -987,7 +1153,9 @@ int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   if (bytes > c->arena.size()) return fail(c, BA_E_NOMEM, "cluster footprint exceeds the arena");
   if ((int)c->queue.size() >= c->opt.max_queue) return fail(c, BA_E_AGAIN, "admission queue full");
   auto t = std::make_unique<Ticket>();
-  t->id = c->next_id++;
+  t->id = c->next_id;
+  if (st->resident && (rc = res_register(c, *t, *st))) return rc;
+  c->next_id++;
   t->C = st->C;
   t->P = st->P;
   t->max_iters = st->max_iters;
@@ -1020,6 +1188,7 @@ int ba_step(ba_ctx* c, ba_ticket id, int32_t n_iters) {
     if ((rc = run_iterations(c, c->api, one, 1))) return rc;
     if ((rc = read_ctl(c, c->api))) return rc;
   }
+  if (t->resident && !t->res_done && is_finished(c->api.h_ctl[t->slot].status)) return export_slots(c, c->api, one);
   return BA_OK;
 }
 
@@ -1048,7 +1217,10 @@ int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
     if ((rc = run_iterations(c, c->api, act, per))) return rc;
     if ((rc = read_ctl(c, c->api))) return rc;
   }
-  return BA_OK;
+  std::vector<int> wb;
+  for (int s : slots)
+    if (c->tickets[c->slots[s].ticket]->resident && !c->tickets[c->slots[s].ticket]->res_done) wb.push_back(s);
+  return wb.empty() ? BA_OK : export_slots(c, c->api, wb);
 }
 
 int ba_solve(ba_ctx* c, ba_ticket id) {

@@ -478,3 +478,65 @@ def spec_global(n_strips: int = 10, imgs_per_strip: int = 40, n_points: int = 80
 
 def scene_global(seed: int = 5, **kw) -> dict:
     return make_scene(spec_global(**kw), seed)
+
+
+def make_stream(seed: int = 3, n_strips: int = 4, imgs_per_strip: int = 40, pts_per_image: int = 2000,
+                max_cams: int = 20, min_cams: int = 8, back: int = 7, free_back: int = 3,
+                obs_mean: float = 4.8) -> dict:
+    """A flight of n_strips x imgs_per_strip images in flight order with one
+    global tie-point pool (~pts_per_image spawned per image), cut into the
+    sliding clusters that each arriving image triggers (Sec. 3.2): image i,
+    its up to `back` in-strip predecessors and the previous strip's images
+    whose footprint overlaps it (nearest first), capped at max_cams; a cluster
+    is emitted once it has min_cams images.  Points are the pool points with
+    at least two observations inside the cluster.  Images older than
+    `free_back` in-strip steps and previous-strip images are fixed (they were
+    adjusted by earlier clusters); the rest are free.
+
+    Returns {"flight": scene of the whole block, "clusters": [scene, ...]} where
+    each cluster scene carries cam_ids / point_ids (indices into the flight)
+    and "image": the triggering image."""
+    spec = SceneSpec(n_strips=n_strips, imgs_per_strip=imgs_per_strip,
+                     n_points=pts_per_image * n_strips * imgs_per_strip,
+                     obs_model=("geom", obs_mean), neighbour_vis=True)
+    fl = make_scene(spec, seed)
+    C = fl["n_cams"]
+    strip = fl["truth"]["strip"]
+    Txy = fl["truth"]["T"][:, :2]
+    # observations grouped by camera
+    order = np.argsort(fl["obs_cam"], kind="stable")
+    starts = np.searchsorted(fl["obs_cam"][order], np.arange(C + 1))
+    clusters = []
+    for i in range(C):
+        s, pos = int(strip[i]), i % imgs_per_strip
+        own = [i - b for b in range(1, back + 1) if pos - b >= 0]
+        prev = np.nonzero(strip == s - 1)[0]
+        d = np.abs(Txy[prev] - Txy[i])
+        prev = prev[(d[:, 0] < FOOT_ACROSS) & (d[:, 1] < FOOT_ALONG)]
+        prev = prev[np.argsort(np.hypot(*(Txy[prev] - Txy[i]).T))]
+        cams = ([i] + own + [int(k) for k in prev])[:max_cams]
+        if len(cams) < min_cams:
+            continue
+        cams = np.array(sorted(cams), np.int64)
+        obs = np.concatenate([order[starts[k]:starts[k + 1]] for k in cams])
+        cnt = np.bincount(fl["obs_pt"][obs], minlength=fl["n_points"])
+        pts = np.nonzero(cnt >= 2)[0]
+        obs = obs[cnt[fl["obs_pt"][obs]] >= 2]
+        obs = np.sort(obs)
+        cam_loc = np.full(C, -1, np.int64)
+        cam_loc[cams] = np.arange(cams.size)
+        pt_loc = np.full(fl["n_points"], -1, np.int64)
+        pt_loc[pts] = np.arange(pts.size)
+        fixed = np.array([0 if (k == i or (strip[k] == s and i - k <= free_back)) else 1 for k in cams], np.uint8)
+        c = lambda x, dt=np.float64: np.ascontiguousarray(x, dtype=dt)
+        clusters.append({
+            "image": i, "n_cams": int(cams.size), "n_points": int(pts.size), "n_obs": int(obs.size),
+            "R": c(fl["R"][cams]), "T": c(fl["T"][cams]), "X": c(fl["X"][pts]), "k": c(fl["k"]),
+            "prior_R": c(fl["prior_R"][cams]), "prior_T": c(fl["prior_T"][cams]),
+            "prior_sigma": c(fl["prior_sigma"][cams]), "fixed": fixed,
+            "obs_cam": c(cam_loc[fl["obs_cam"][obs]], np.int32), "obs_pt": c(pt_loc[fl["obs_pt"][obs]], np.int32),
+            "obs_uv": c(fl["obs_uv"][obs]), "f": fl["f"], "cx": fl["cx"], "cy": fl["cy"], "intr_mask": 0,
+            "sigma_px": fl["sigma_px"], "huber_delta": fl["huber_delta"],
+            "cam_ids": c(cams, np.int64), "point_ids": c(pts, np.int64),
+        })
+    return {"flight": fl, "clusters": clusters}
