@@ -84,6 +84,13 @@ def traffic_bytes(kernel: str, batch: int):
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
 
 
+# kernels timed inside the timed region (bits of ba_profile_enable): the two
+# Schur block kernels, the candidates for the dominant kernel; timing all
+# eight costs ~7 % of the step, so the full breakdown is taken on one more,
+# untimed step
+BLOCK_KERNELS = (1 << 1) | (1 << 2)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -289,6 +296,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
     ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
+    ap.add_argument("--iters-per-tick", type=int, default=4,
+                    help="LM iterations launched between control read-backs (batched context)")
     ap.add_argument("--uneven", type=int, default=256,
                     help="clusters of the uneven batched workload (6-24 cameras, 5k-60k points; 0: skip)")
     ap.add_argument("--uneven-scenes", type=int, default=64, help="distinct seeded uneven clusters (cycled)")
@@ -325,7 +334,7 @@ def main():
     # ---- mixed, batched: the timed steps --------------------------------------------------
     B = args.batch
     ctx = Context(precision=BA_MIXED, max_slots=max(B, 1), hbm_budget_bytes=int(B * 16e6) + (256 << 20),
-                  chunks_per_task=args.chunks_per_task)
+                  chunks_per_task=args.chunks_per_task, iters_per_tick=args.iters_per_tick)
     step_ms, iters_total, mixed_final = [], 0, {}
     fl_total = {"camblk": 0.0, "pairblk": 0.0}
     ctx.ba_profile_enable(False)
@@ -336,7 +345,7 @@ def main():
         for t in tickets:
             ctx.ba_step(t, 0)     # admission: upload, origin shift, initial FP64 cost
         if timed:
-            ctx.ba_profile_enable(True)
+            ctx.ba_profile_enable(BLOCK_KERNELS)   # the two roofline candidates only
         t0 = time.perf_counter()
         ctx.ba_solve_batch(tickets)
         t1 = time.perf_counter()
@@ -354,6 +363,16 @@ def main():
             ctx.ba_release(t)
         log(f"step {step}{'' if timed else ' (warmup)'}: {(t1 - t0) * 1e3:.2f} ms for {B} clusters")
     prof = ctx.ba_profile_read()
+    # one more step, untimed, with every kernel timed: the per-kernel breakdown
+    tickets = [ctx.submit(scenes[i % len(scenes)], **kw) for i in range(B)]
+    for t in tickets:
+        ctx.ba_step(t, 0)
+    ctx.ba_profile_enable(True)
+    ctx.ba_solve_batch(tickets)
+    ctx.ba_profile_enable(False)
+    prof_all = ctx.ba_profile_read()
+    for t in tickets:
+        ctx.ba_release(t)
     ctx.close()
     ms_per_step = float(np.mean(step_ms))
     value = B / (ms_per_step / 1e3)
@@ -362,7 +381,7 @@ def main():
     asm_ms, asm_n = prof[dom]
     asm_avg_ms = asm_ms / max(asm_n, 1)
     achieved_tflops = fl_total[dom] / max(asm_n, 1) / (asm_avg_ms / 1e3) / 1e12 if asm_n else float("nan")
-    kernels = {k: {"avg_us": (v[0] / max(v[1], 1)) * 1e3, "launches": v[1]} for k, v in prof.items()}
+    kernels = {k: {"avg_us": (v[0] / max(v[1], 1)) * 1e3, "launches": v[1]} for k, v in prof_all.items()}
 
     # ---- plain FP64 GPU LM: one cluster at a time, host-driven ---------------------------
     plain_lat, plain_final = [], {}

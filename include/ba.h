@@ -234,16 +234,19 @@ int ba_release(ba_ctx* ctx, ba_ticket ticket);
  * footprint), or 0 if the cluster is invalid. */
 size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
 
-/* Per-kernel timing with HIP events recorded around every launch of an LM
- * iteration on the context's stream (off by default; costs one event record
- * per kernel while on).  ba_profile_read adds up the elapsed time and the
- * number of launches per kernel since the last read, in the order of
+/* Per-kernel timing with HIP events that the dispatches of an LM iteration
+ * record themselves on the context's stream (off by default).  `kernels` is
+ * a bitmask of (1 << enum ba_prof_kernel) selecting the kernels to time
+ * (BA_PROF_ALL: every one; 0: off); each timed kernel costs two event records
+ * per launch.  ba_profile_read adds up the elapsed time and the number of
+ * timed launches per kernel since the last read, in the order of
  * enum ba_prof_kernel, into caller arrays of BA_PROF_N entries, and resets
  * the counters.  Errors: BA_E_ARG, BA_E_DEVICE. */
 enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_CAMBLK = 1, BA_PROF_PAIRBLK = 2, BA_PROF_REDUCE = 3,
                       BA_PROF_SOLVE = 4, BA_PROF_BACKSUB = 5, BA_PROF_LM = 6, BA_PROF_PCG = 7,
                       BA_PROF_N = 8 };
-int ba_profile_enable(ba_ctx* ctx, int32_t enable);
+#define BA_PROF_ALL ((1 << BA_PROF_N) - 1)
+int ba_profile_enable(ba_ctx* ctx, int32_t kernels);
 int ba_profile_read(ba_ctx* ctx, double* total_ms, int64_t* launches);
 
 const char* ba_strerror(int code);

@@ -26,6 +26,7 @@ EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error"]
 BA_PROF_KERNELS = ["point", "camblk", "pairblk", "reduce", "solve", "backsub", "lm", "pcg"]
+BA_PROF_ALL = (1 << len(BA_PROF_KERNELS)) - 1
 
 
 class ba_options(ct.Structure):
@@ -200,8 +201,10 @@ class Context:
         self.meta.pop(t, None)
         return self._chk(self.lib.ba_release(self.h, t), "ba_release")
 
-    def ba_profile_enable(self, enable: bool = True):
-        return self._chk(self.lib.ba_profile_enable(self.h, 1 if enable else 0), "ba_profile_enable")
+    def ba_profile_enable(self, kernels=True):
+        """kernels: True (every kernel), False (off), or a bitmask of 1 << index in BA_PROF_KERNELS."""
+        mask = BA_PROF_ALL if kernels is True else (0 if kernels is False else int(kernels))
+        return self._chk(self.lib.ba_profile_enable(self.h, mask), "ba_profile_enable")
 
     def ba_profile_read(self) -> dict:
         ms = np.zeros(len(BA_PROF_KERNELS))

@@ -126,8 +126,9 @@ hipError_t launch_prep(const Batch& b, int max_P_L, int max_rin, hipStream_t st)
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
 // ev (optional): 16 events, the start and end of each of the eight kernels
 // of the iteration (point, camera blocks, pair blocks, reduce, dense solve,
-// back-substitution, LM, PCG solve), recorded by the dispatches themselves.
-hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr);
+// back-substitution, LM, PCG solve), recorded by the dispatches themselves
+// for the kernels whose bit is set in `timed`.
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr, int timed = 0);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 // Writes the exported state of the batch's clusters back to the resident
 // store (after launch_export); max_rout: largest write-back list.

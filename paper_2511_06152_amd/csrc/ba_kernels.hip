@@ -1898,7 +1898,7 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, hipEve
   else hipLaunchKernelGGL(kernel, grid, block, smem, st, b);
 }
 
-hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev_all, int timed) {
   if (b.n_act == 0) return hipSuccess;
   hipError_t e;
   const size_t s_solve = solve_smem(b);
@@ -1911,45 +1911,47 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   if ((e = ensure_smem(fp, sp))) return e;
   const size_t s_pcg = pcg_smem(b);
   if ((e = ensure_smem((const void*)k_pcg, s_pcg))) return e;
-  // Every profiled kernel needs a dispatch to carry its events, also when a
+  // Events of kernel slot k, or none when it is not timed.
+  auto evk = [&](int k) { return (ev_all && ((timed >> k) & 1)) ? ev_all : nullptr; };
+  // Every timed kernel needs a dispatch to carry its events, also when a
   // batch has no work for it: a one-block launch that returns at once.
   const dim3 g_pt(b.total_wg > 0 ? b.total_wg : 1), g_tg(b.total_tg > 0 ? b.total_tg : 1);
   Batch nob = b;
   nob.n_act = 0;
-  if (b.total_wg > 0 || ev) {
+  if (b.total_wg > 0 || evk(0)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_point<float>, g_pt, dim3(kWG), sp, st, ev, 0, bb);
-    else launch(k_point<double>, g_pt, dim3(kWG), sp, st, ev, 0, bb);
+    if (mixed) launch(k_point<float>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
+    else launch(k_point<double>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
   }
-  if (b.total_tkc_wg > 0 || ev) {
+  if (b.total_tkc_wg > 0 || evk(1)) {
     const Batch& bb = b.total_tkc_wg > 0 ? b : nob;
     const dim3 g(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1);
-    if (mixed) launch(k_camblk<float>, g, dim3(kWG), 0, st, ev, 1, bb);
-    else launch(k_camblk<double>, g, dim3(kWG), 0, st, ev, 1, bb);
+    if (mixed) launch(k_camblk<float>, g, dim3(kWG), 0, st, evk(1), 1, bb);
+    else launch(k_camblk<double>, g, dim3(kWG), 0, st, evk(1), 1, bb);
   }
-  if (b.total_tkp_wg > 0 || ev) {
+  if (b.total_tkp_wg > 0 || evk(2)) {
     const Batch& bb = b.total_tkp_wg > 0 ? b : nob;
     const dim3 g(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1);
-    if (mixed) launch(k_pairblk<float>, g, dim3(kWG), 0, st, ev, 2, bb);
-    else launch(k_pairblk<double>, g, dim3(kWG), 0, st, ev, 2, bb);
+    if (mixed) launch(k_pairblk<float>, g, dim3(kWG), 0, st, evk(2), 2, bb);
+    else launch(k_pairblk<double>, g, dim3(kWG), 0, st, evk(2), 2, bb);
   }
-  if (b.total_tg > 0 || ev) {
+  if (b.total_tg > 0 || evk(3)) {
     const Batch& bb = b.total_tg > 0 ? b : nob;
-    if (mixed) launch(k_reduce<float>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
-    else launch(k_reduce<double>, g_tg, dim3(kReduceThreads), 0, st, ev, 3, bb);
+    if (mixed) launch(k_reduce<float>, g_tg, dim3(kReduceThreads), 0, st, evk(3), 3, bb);
+    else launch(k_reduce<double>, g_tg, dim3(kReduceThreads), 0, st, evk(3), 3, bb);
   }
   // A solver with no cluster in the batch is not launched; with timing on, its
   // events mark an empty interval.
-  if (b.any_dense) launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, ev, 4, b);
-  else if (ev && ((e = hipEventRecord(ev[8], st)) || (e = hipEventRecord(ev[9], st)))) return e;
-  if (b.any_sparse) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, ev, 7, b);
-  else if (ev && ((e = hipEventRecord(ev[14], st)) || (e = hipEventRecord(ev[15], st)))) return e;
-  if (b.total_wg > 0 || ev) {
+  if (b.any_dense) launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, evk(4), 4, b);
+  else if (evk(4) && ((e = hipEventRecord(ev_all[8], st)) || (e = hipEventRecord(ev_all[9], st)))) return e;
+  if (b.any_sparse) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, evk(7), 7, b);
+  else if (evk(7) && ((e = hipEventRecord(ev_all[14], st)) || (e = hipEventRecord(ev_all[15], st)))) return e;
+  if (b.total_wg > 0 || evk(5)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, ev, 5, bb);
-    else launch(k_backsub<double>, g_pt, dim3(kWG), sb, st, ev, 5, bb);
+    if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
+    else launch(k_backsub<double>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
   }
-  launch(k_lm, dim3(b.n_act), dim3(64), 0, st, ev, 6, b);
+  launch(k_lm, dim3(b.n_act), dim3(64), 0, st, evk(6), 6, b);
   return hipGetLastError();
 }
 

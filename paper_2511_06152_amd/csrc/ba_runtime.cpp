@@ -504,7 +504,8 @@ struct ba_ctx {
   std::string last_error;
   Launcher api, srv;
   // kernel timing (ba_profile_enable)
-  bool prof = false;
+  int prof = 0;                   // bitmask of timed kernels
+  std::vector<int> prof_set_mask; // mask each used event set was recorded with
   std::vector<std::array<hipEvent_t, 2 * BA_PROF_N>> prof_ev;  // one set per iteration since the last harvest
   size_t prof_used = 0;
   double prof_ms[BA_PROF_N] = {};
@@ -852,6 +853,7 @@ int harvest_prof(ba_ctx* c) {
   for (size_t i = 0; i < c->prof_used; ++i) {
     auto& ev = c->prof_ev[i];
     for (int k = 0; k < BA_PROF_N; ++k) {
+      if (!((c->prof_set_mask[i] >> k) & 1)) continue;
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
       c->prof_ms[k] += ms;
@@ -874,10 +876,12 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
         std::array<hipEvent_t, 2 * BA_PROF_N> set;
         for (auto& e : set) HIPCHK(c, hipEventCreate(&e));
         c->prof_ev.push_back(set);
+        c->prof_set_mask.push_back(0);
       }
+      c->prof_set_mask[c->prof_used] = c->prof;
       ev = c->prof_ev[c->prof_used++].data();
     }
-    HIPCHK(c, launch_iteration(b, mixed, c->stream, ev));
+    HIPCHK(c, launch_iteration(b, mixed, c->stream, ev, c->prof));
   }
   return BA_OK;
 }
@@ -1287,10 +1291,10 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   return BA_OK;
 }
 
-int ba_profile_enable(ba_ctx* c, int32_t enable) {
-  if (!c) return BA_E_ARG;
+int ba_profile_enable(ba_ctx* c, int32_t kernels) {
+  if (!c || (kernels & ~BA_PROF_ALL)) return BA_E_ARG;
   std::lock_guard<std::mutex> g(c->mu);
-  c->prof = enable != 0;
+  c->prof = kernels;
   return BA_OK;
 }
 
