@@ -675,12 +675,15 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
 // ---- block passes: camera-diagonal and camera-pair blocks of the Schur complement ----
 //
 // One wavefront per task (k_camblk: camera tasks, k_pairblk: pair tasks; two
-// kernels so that each gets the register allocation it needs).  A camera task sums, over a run of observations of
-// one free camera, its diagonal block U_kk - sum Y W^T, g_k, sum Y g_p, diag
-// U_kk and its intrinsic border; a pair task sums -Y_a W_b^T over a run of
-// observation pairs (same point, cameras a < b).  Sums stay in registers and
-// are reduced across the wavefront in a fixed order: no atomics, so a
-// cluster's result does not depend on what else is in the batch.
+// kernels so that each gets the register allocation it needs).  A camera
+// task sums, over a run of observations of one free camera, its diagonal
+// block U_kk - sum Y W^T, g_k, sum Y g_p, diag U_kk and its intrinsic border;
+// a pair task sums -Y_a W_b^T over a run of observation pairs (same point,
+// cameras a < b).  W = w J_c^T J_p and Y = W Q (Q = V^-1 of the point) are
+// never formed: each term is a 2x2 or 2-vector quantity of the observation
+// pushed through the 2x6 camera Jacobian (see the kernels).  Sums stay in
+// registers and are reduced across the wavefront in a fixed order: no
+// atomics, so a cluster's result does not depend on what else is in the batch.
 
 template <typename R>
 __device__ __forceinline__ void load_cam(const double* __restrict__ src, R* dst) {
@@ -688,25 +691,14 @@ __device__ __forceinline__ void load_cam(const double* __restrict__ src, R* dst)
   for (int i = 0; i < kCamVals; ++i) dst[i] = (R)src[i];
 }
 
+// T = J_p Q (2 x 3) for the packed symmetric 3x3 Q.
 template <typename R>
-__device__ __forceinline__ void cam_w(const ObsJ<R>& o, R Wc[6][3], R wJp[2][3]) {
+__device__ __forceinline__ void jp_q(const ObsJ<R>& o, const R* Q, R T[2][3]) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) wJp[i][t] = o.w * o.Jp[i][t];
-#pragma unroll
-  for (int r = 0; r < 6; ++r)
-#pragma unroll
-    for (int t = 0; t < 3; ++t) Wc[r][t] = fm(jc(o, 0, r), wJp[0][t], jc(o, 1, r) * wJp[1][t]);
-}
-
-// Y = W Q for the 6 camera rows of W (Q symmetric, packed).
-template <typename R>
-__device__ __forceinline__ void times_q(const R W[6][3], const R Q[6], R Y[6][3]) {
-#pragma unroll
-  for (int r = 0; r < 6; ++r)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) Y[r][q] = fm(W[r][2], qel(Q, 2, q), fm(W[r][1], qel(Q, 1, q), W[r][0] * qel(Q, 0, q)));
+    for (int t = 0; t < 3; ++t)
+      T[a][t] = fm(o.Jp[a][2], qel(Q, 2, t), fm(o.Jp[a][1], qel(Q, 1, t), o.Jp[a][0] * qel(Q, 0, t)));
 }
 
 template <typename R, int N>
@@ -763,37 +755,53 @@ __global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
       }
       ObsJ<R> o;
       obs_model<R>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
-      R Wc[6][3], wJp[2][3];
-      cam_w(o, Wc, wJp);
       R rec[kPtVals];
 #pragma unroll
       for (int i = 0; i < kPtVals; ++i) rec[i] = R(0);
       if (valid) pt_load(ptv + kPtVals * (size_t)pt, rec, (i0 || i1) ? 16 : (sizeof(R) == 8 ? 10 : 12));
       const R* Q = rec;
       const R* gp = rec + 6;
-      const R Z[2][3] = {{rec[9], rec[10], rec[11]}, {rec[12], rec[13], rec[14]}};
       const R w = o.w;
+      // With W = w J_c^T J_p and Y = W Q, every term of the observation goes
+      // through 2-vectors: U - Y W^T = J_c^T M J_c with the 2x2
+      // M = w I - w^2 J_p Q J_p^T; Y g_p = J_c^T (w T g_p); the intrinsic
+      // border w J_c^T J_k - Y Z^T = J_c^T w (J_k - T Z^T), where T = J_p Q.
+      R T[2][3];
+      jp_q(o, Q, T);
+      const R w2 = w * w;
+      const R P00 = fm(T[0][2], o.Jp[0][2], fm(T[0][1], o.Jp[0][1], T[0][0] * o.Jp[0][0]));
+      const R P01 = fm(T[0][2], o.Jp[1][2], fm(T[0][1], o.Jp[1][1], T[0][0] * o.Jp[1][0]));
+      const R P11 = fm(T[1][2], o.Jp[1][2], fm(T[1][1], o.Jp[1][1], T[1][0] * o.Jp[1][0]));
+      const R M00 = fm(-w2, P00, w), M01 = -w2 * P01, M11 = fm(-w2, P11, w);
+      const R ve0 = w * o.e[0], ve1 = w * o.e[1];
+      const R vg0 = w * fm(T[0][2], gp[2], fm(T[0][1], gp[1], T[0][0] * gp[0]));
+      const R vg1 = w * fm(T[1][2], gp[2], fm(T[1][1], gp[1], T[1][0] * gp[0]));
+      R vk[2][2] = {{0, 0}, {0, 0}};   // [intrinsic][row]
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (q == 0 ? !i0 : !i1) continue;
+        const R* z = rec + 9 + 3 * q;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) vk[q][a] = w * (o.Jk[a][q] - fm(T[a][2], z[2], fm(T[a][1], z[1], T[a][0] * z[0])));
+      }
+      R a0[6], a1[6], G0[6], G1[6];   // J_c rows and M J_c
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        a0[r] = jc(o, 0, r);
+        a1[r] = jc(o, 1, r);
+        G0[r] = fm(M00, a0[r], M01 * a1[r]);
+        G1[r] = fm(M01, a0[r], M11 * a1[r]);
+      }
       int e = 0;
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const R wr0 = w * jc(o, 0, r), wr1 = w * jc(o, 1, r);   // row r of w J_c^T
-        R Yr[3];                                              // row r of Y = W Q
 #pragma unroll
-        for (int q = 0; q < 3; ++q) Yr[q] = fm(Wc[r][2], qel(Q, 2, q), fm(Wc[r][1], qel(Q, 1, q), Wc[r][0] * qel(Q, 0, q)));
-#pragma unroll
-        for (int cc = r; cc < 6; ++cc, ++e) {
-          const R u = fm(wr0, jc(o, 0, cc), wr1 * jc(o, 1, cc));
-          acc[e] += fm(-Yr[2], Wc[cc][2], fm(-Yr[1], Wc[cc][1], fm(-Yr[0], Wc[cc][0], u)));
-        }
-        acc[21 + r] += fm(wr0, o.e[0], wr1 * o.e[1]);
-        acc[27 + r] += fm(Yr[2], gp[2], fm(Yr[1], gp[1], Yr[0] * gp[0]));
-        acc[33 + r] += fm(wr0, jc(o, 0, r), wr1 * jc(o, 1, r));
-        if (i0)
-          acc[39 + r] += fm(-Yr[2], Z[0][2], fm(-Yr[1], Z[0][1], fm(-Yr[0], Z[0][0],
-                             fm(wr0, o.Jk[0][0], wr1 * o.Jk[1][0]))));
-        if (i1)
-          acc[45 + r] += fm(-Yr[2], Z[1][2], fm(-Yr[1], Z[1][1], fm(-Yr[0], Z[1][0],
-                             fm(wr0, o.Jk[0][1], wr1 * o.Jk[1][1]))));
+        for (int cc = r; cc < 6; ++cc, ++e) acc[e] = fm(a0[r], G0[cc], fm(a1[r], G1[cc], acc[e]));
+        acc[21 + r] = fm(a0[r], ve0, fm(a1[r], ve1, acc[21 + r]));
+        acc[27 + r] = fm(a0[r], vg0, fm(a1[r], vg1, acc[27 + r]));
+        acc[33 + r] = fm(w * a0[r], a0[r], fm(w * a1[r], a1[r], acc[33 + r]));
+        if (i0) acc[39 + r] = fm(a0[r], vk[0][0], fm(a1[r], vk[0][1], acc[39 + r]));
+        if (i1) acc[45 + r] = fm(a0[r], vk[1][0], fm(a1[r], vk[1][1], acc[45 + r]));
       }
     }
     wave_store(acc, part, lane);
@@ -844,25 +852,41 @@ __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
           ub = (R)d.ql_uv64[4 * idx + 2]; vb = (R)d.ql_uv64[4 * idx + 3];
         }
       }
-      R Y[6][3];
+      // -Y_a W_b^T = J_ca^T M J_cb with the 2x2 M = -w_a w_b J_pa Q J_pb^T.
+      R a0[6], a1[6], T[2][3], wa;
       {
         ObsJ<R> oa;
         obs_model<R>(ca, X0, X1, X2, ua, va, f, k1, k2, is, dt, valid, oa);
-        R Wa[6][3], wJp[2][3];
-        cam_w(oa, Wa, wJp);
         R Q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (valid) pt_load(ptv + kPtVals * (size_t)pt, Q, sizeof(R) == 8 ? 6 : 8);
-        times_q(Wa, Q, Y);
+        jp_q(oa, Q, T);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          a0[r] = jc(oa, 0, r);
+          a1[r] = jc(oa, 1, r);
+        }
+        wa = oa.w;
       }
       ObsJ<R> ob;
       obs_model<R>(cb, X0, X1, X2, ub, vb, f, k1, k2, is, dt, valid, ob);
-      R Wb[6][3], wJp[2][3];
-      cam_w(ob, Wb, wJp);
+      const R ww = -wa * ob.w;
+      R M[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          M[i][j] = ww * fm(T[i][2], ob.Jp[j][2], fm(T[i][1], ob.Jp[j][1], T[i][0] * ob.Jp[j][0]));
+      R G0[6], G1[6];
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc) {
+        const R b0 = jc(ob, 0, cc), b1 = jc(ob, 1, cc);
+        G0[cc] = fm(M[0][0], b0, M[0][1] * b1);
+        G1[cc] = fm(M[1][0], b0, M[1][1] * b1);
+      }
 #pragma unroll
       for (int r = 0; r < 6; ++r)
 #pragma unroll
-        for (int cc = 0; cc < 6; ++cc)
-          acc[6 * r + cc] = fm(-Y[r][2], Wb[cc][2], fm(-Y[r][1], Wb[cc][1], fm(-Y[r][0], Wb[cc][0], acc[6 * r + cc])));
+        for (int cc = 0; cc < 6; ++cc) acc[6 * r + cc] = fm(a0[r], G0[cc], fm(a1[r], G1[cc], acc[6 * r + cc]));
     }
     wave_store(acc, part, lane);
 }
