@@ -38,15 +38,17 @@ sys.path.insert(0, ROOT)
 from synth import aerial as A  # noqa: E402
 
 PEAK_VALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-# Algorithmic work of the two Schur block kernels.  k_camblk, per observation
-# of a free camera: Y = W V^-1 (108 flop), its diagonal-block and reduced-
-# gradient terms (126), the camera block U and gradient of the observation
-# (84 + 24), and the intrinsic border when k1/k2 are estimated (48).
-# k_pairblk, per observation pair of one point with both cameras free: one 6x6
-# off-diagonal block -Y_a W_b^T (216).
-FLOP_CAM_OBS = 342
-FLOP_CAM_INTR_OBS = 48
-FLOP_PAIR = 216
+# Algorithmic work of the two Schur block kernels (flops; an FMA counts 2), in
+# the 2x2 / 2-vector formulation they use.  k_camblk, per observation of a free
+# camera: T = J_p Q (36), M = w I - w^2 T J_p^T (25), w e and w T g_p (16),
+# M J_c (36), the 21 entries of J_c^T M J_c (84), J_c^T of the three 2-vectors
+# for g, Y g_p and diag U (84): 281; the intrinsic border when k1/k2 are
+# estimated, 40 per intrinsic.  k_pairblk, per observation pair of one point
+# with both cameras free: T_a = J_pa Q (36), M = -w_a w_b T_a J_pb^T (30),
+# M J_cb (36), J_ca^T (M J_cb) (144): 246.
+FLOP_CAM_OBS = 281
+FLOP_CAM_INTR_OBS = 80
+FLOP_PAIR = 246
 
 
 # HBM traffic of the dominant kernel (k_camblk<float>, 64 paper-scale clusters),

@@ -1673,7 +1673,6 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const double tk1 = c.k[nxt][0], tk2 = c.k[nxt][1];
   const int kc0 = d.kcol0, kc1 = d.kcol1;
   const R dk0 = kc0 >= 0 ? sdc[kc0] : R(0), dk1 = kc1 >= 0 ? sdc[kc1] : R(0);
-  const bool mixed = sizeof(R) == 4;
   const R* __restrict__ ptv = reinterpret_cast<const R*>(d.ptv);
   double rho_sum = 0.0, pred_sum = 0.0;
   int bad = 0;
@@ -1686,18 +1685,14 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
     const int seg = d.lane_seg[idx];
     const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
     const bool head = valid && sb == lane;
-    double Xd[3] = {0, 0, 0};
-    R X0 = 0, X1 = 0, X2 = 0, u = 0, v = 0;
+    // The FP64 point and pixel serve both models: their FP32 shadows are these
+    // values rounded, so they are not read again.
+    double Xd[3] = {0, 0, 0}, ud = 0.0, vd = 0.0;
     if (valid) {
       Xd[0] = d.X[cur][3 * pt]; Xd[1] = d.X[cur][3 * pt + 1]; Xd[2] = d.X[cur][3 * pt + 2];
-      if (mixed) {
-        X0 = (R)d.X32[cur][3 * pt]; X1 = (R)d.X32[cur][3 * pt + 1]; X2 = (R)d.X32[cur][3 * pt + 2];
-        u = (R)d.lane_uv32[2 * idx]; v = (R)d.lane_uv32[2 * idx + 1];
-      } else {
-        X0 = (R)Xd[0]; X1 = (R)Xd[1]; X2 = (R)Xd[2];
-        u = (R)d.lane_uv64[2 * idx]; v = (R)d.lane_uv64[2 * idx + 1];
-      }
+      ud = d.lane_uv64[2 * idx]; vd = d.lane_uv64[2 * idx + 1];
     }
+    const R X0 = (R)Xd[0], X1 = (R)Xd[1], X2 = (R)Xd[2], u = (R)ud, v = (R)vd;
     ObsJ<R> o;
     obs_model<R>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
     const int fi = valid ? scol[cam] : -1;
@@ -1748,8 +1743,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
         }
       }
       double rho;
-      if (obs_rho(tcam + kCamVals * cam, Xn, d.lane_uv64[2 * idx], d.lane_uv64[2 * idx + 1], d.f, tk1, tk2,
-                  d.inv_sigma, d.huber_dt, &rho)) rho_sum += rho;
+      if (obs_rho(tcam + kCamVals * cam, Xn, ud, vd, d.f, tk1, tk2, d.inv_sigma, d.huber_dt, &rho)) rho_sum += rho;
       else ++bad;
     }
   }
