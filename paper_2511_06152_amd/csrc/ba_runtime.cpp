@@ -503,6 +503,12 @@ struct ba_ctx {
   bool dead = false;
   std::string last_error;
   Launcher api, srv;
+  // Batched solves split a batch in two halves on two streams, so that one
+  // half's latency-bound kernels (reduce, solve, LM) overlap the other half's
+  // assembly kernels.
+  Launcher api2;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // kernel timing (ba_profile_enable)
   int prof = 0;                   // bitmask of timed kernels
   std::vector<int> prof_set_mask; // mask each used event set was recorded with
@@ -886,6 +892,51 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
   return BA_OK;
 }
 
+// n LM iterations of two disjoint groups of slots, A on the context's stream
+// and B on the second stream; the context's stream then waits for B.
+int run_iterations_split(ba_ctx* c, const std::vector<int>& A, const std::vector<int>& B, int n_iters) {
+  Batch ba, bb;
+  int rc;
+  if ((rc = make_batch(c, c->api, A, ba))) return rc;
+  if ((rc = make_batch(c, c->api2, B, bb))) return rc;   // uploads on the context's stream
+  HIPCHK(c, hipEventRecord(c->fork_ev, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->stream2, c->fork_ev, 0));
+  const bool mixed = c->opt.precision == BA_MIXED;
+  for (int i = 0; i < n_iters; ++i) {
+    for (int h = 0; h < 2; ++h) {
+      hipEvent_t* ev = nullptr;
+      if (c->prof) {
+        if (c->prof_used == c->prof_ev.size()) {
+          std::array<hipEvent_t, 2 * BA_PROF_N> set;
+          for (auto& e : set) HIPCHK(c, hipEventCreate(&e));
+          c->prof_ev.push_back(set);
+          c->prof_set_mask.push_back(0);
+        }
+        c->prof_set_mask[c->prof_used] = c->prof;
+        ev = c->prof_ev[c->prof_used++].data();
+      }
+      HIPCHK(c, launch_iteration(h ? bb : ba, mixed, h ? c->stream2 : c->stream, ev, c->prof));
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->join_ev, c->stream2));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
+  return BA_OK;
+}
+
+// Splits running slots into two halves of about equal assembly work (point
+// workgroups), in slot order.
+void split_halves(ba_ctx* c, const std::vector<int>& act, std::vector<int>& A, std::vector<int>& B) {
+  size_t total = 0;
+  for (int s : act) total += (size_t)c->slots[s].desc.n_wg;
+  size_t acc = 0;
+  A.clear();
+  B.clear();
+  for (int s : act) {
+    (acc * 2 < total ? A : B).push_back(s);
+    acc += (size_t)c->slots[s].desc.n_wg;
+  }
+}
+
 // Exports the listed slots' state into their ticket caches (synchronous).
 int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   if (slots.empty()) return BA_OK;
@@ -1104,7 +1155,12 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   }
   hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots);
   c->slots.resize(c->opt.max_slots);
-  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return BA_E_DEVICE;
+  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv) || init_launcher(c.get(), c->api2))
+    return BA_E_DEVICE;
+  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess)
+    return BA_E_DEVICE;
   for (int i = 0; i < c->opt.max_slots; ++i) c->srv.h_ctl[i] = SlotCtl{};
   if (hipDeviceSynchronize() != hipSuccess) return BA_E_DEVICE;
   ba_ctx* raw = c.release();
@@ -1123,7 +1179,12 @@ int ba_destroy(ba_ctx* c) {
   if (c->th.joinable()) c->th.join();
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  if (c->stream2) (void)hipStreamSynchronize(c->stream2);
   free_launcher(c->api);
+  free_launcher(c->api2);
+  if (c->stream2) (void)hipStreamDestroy(c->stream2);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
   free_launcher(c->srv);
   for (auto& set : c->prof_ev)
     for (auto& e : set) (void)hipEventDestroy(e);
@@ -1213,12 +1274,18 @@ int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
   if (rc) return rc;
   if ((rc = read_ctl(c, c->api))) return rc;
   const int per = c->opt.iters_per_tick;
+  std::vector<int> A, B;
   for (;;) {
     std::vector<int> act;
     for (int s : slots)
       if (c->api.h_ctl[s].status == ST_RUNNING) act.push_back(s);
     if (act.empty()) break;
-    if ((rc = run_iterations(c, c->api, act, per))) return rc;
+    if (act.size() >= 8) {
+      split_halves(c, act, A, B);
+      if ((rc = run_iterations_split(c, A, B, per))) return rc;
+    } else if ((rc = run_iterations(c, c->api, act, per))) {
+      return rc;
+    }
     if ((rc = read_ctl(c, c->api))) return rc;
   }
   std::vector<int> wb;

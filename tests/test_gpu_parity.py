@@ -176,11 +176,14 @@ def test_mixed_within_tolerance_converged():
 @pytest.mark.parametrize("precision", [FP64, MIXED])
 def test_batched_equals_alone(precision):
     """Clusters of uneven size solved together in one launch series give
-    bit-identical results to each solved alone (every sum has a fixed order)."""
+    bit-identical results to each solved alone (every sum has a fixed order).
+    Ten clusters: the batch runs as two halves on two streams while eight or
+    more are running, then as one."""
     from paper_2511_06152_amd import Context
-    scenes = [A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + i, n_points=300 + 400 * i,
-                                        intr_mask=3 if i == 1 else 0, k_true=(-0.05, 0.02) if i == 1 else (0, 0)),
-                           50 + i) for i in range(4)]
+    scenes = [A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + i % 4, n_points=300 + 400 * (i % 4),
+                                        intr_mask=3 if i % 4 == 1 else 0,
+                                        k_true=(-0.05, 0.02) if i % 4 == 1 else (0, 0)),
+                           50 + i) for i in range(10)]
     kw = dict(max_iters=8, stop_on_ftol=True, ftol=1e-7)
     alone = []
     with Context(precision=precision) as ctx:
