@@ -114,6 +114,10 @@ typedef struct {
   int32_t resident_points;   /* capacity of the resident point state; 0 -> 4194304.  The
                                 store (96 B per camera, 24 B per point) is allocated at the
                                 first cluster that uses it, outside the arena */
+  int32_t single_stream;     /* 0: batched solves and the serving loop run 8 or more running
+                                clusters as two halves on two streams, so that one half's
+                                latency-bound kernels overlap the other's assembly;
+                                1: one stream */
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */

@@ -506,7 +506,7 @@ struct ba_ctx {
   // Batched solves split a batch in two halves on two streams, so that one
   // half's latency-bound kernels (reduce, solve, LM) overlap the other half's
   // assembly kernels.
-  Launcher api2;
+  Launcher api2, srv2;
   hipStream_t stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // kernel timing (ba_profile_enable)
@@ -894,11 +894,12 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
 
 // n LM iterations of two disjoint groups of slots, A on the context's stream
 // and B on the second stream; the context's stream then waits for B.
-int run_iterations_split(ba_ctx* c, const std::vector<int>& A, const std::vector<int>& B, int n_iters) {
+int run_iterations_split(ba_ctx* c, Launcher& la, Launcher& lb, const std::vector<int>& A, const std::vector<int>& B,
+                         int n_iters) {
   Batch ba, bb;
   int rc;
-  if ((rc = make_batch(c, c->api, A, ba))) return rc;
-  if ((rc = make_batch(c, c->api2, B, bb))) return rc;   // uploads on the context's stream
+  if ((rc = make_batch(c, la, A, ba))) return rc;
+  if ((rc = make_batch(c, lb, B, bb))) return rc;   // uploads on the context's stream
   HIPCHK(c, hipEventRecord(c->fork_ev, c->stream));
   HIPCHK(c, hipStreamWaitEvent(c->stream2, c->fork_ev, 0));
   const bool mixed = c->opt.precision == BA_MIXED;
@@ -1061,7 +1062,13 @@ void serve_loop(ba_ctx* c) {
       c->cv.wait(lk, [&] { return c->stop || serving_queued(c); });
       continue;
     }
-    if (run_iterations(c, c->srv, active, c->opt.iters_per_tick)) break;
+    if (active.size() >= 8 && !c->opt.single_stream) {
+      std::vector<int> A, B;
+      split_halves(c, active, A, B);
+      if (run_iterations_split(c, c->srv, c->srv2, A, B, c->opt.iters_per_tick)) break;
+    } else if (run_iterations(c, c->srv, active, c->opt.iters_per_tick)) {
+      break;
+    }
     if (hipMemcpyAsync(c->srv.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost, c->stream) ||
         hipEventRecord(c->srv.ev, c->stream)) {
       c->dead = true;
@@ -1129,6 +1136,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
   if (c->opt.pcg_max_iters <= 0) c->opt.pcg_max_iters = 500;
   if (!(c->opt.pcg_tol > 0)) c->opt.pcg_tol = 0.1;
+  if (c->opt.single_stream != 0 && c->opt.single_stream != 1) return BA_E_ARG;
   if (c->opt.resident_cams <= 0) c->opt.resident_cams = 8192;
   if (c->opt.resident_points <= 0) c->opt.resident_points = 1 << 22;
   if (c->opt.solver < BA_SOLVER_AUTO || c->opt.solver > BA_SOLVER_PCG || c->opt.pcg_max_iters > 100000 ||
@@ -1155,7 +1163,8 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   }
   hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots);
   c->slots.resize(c->opt.max_slots);
-  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv) || init_launcher(c.get(), c->api2))
+  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv) || init_launcher(c.get(), c->api2) ||
+      init_launcher(c.get(), c->srv2))
     return BA_E_DEVICE;
   if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
@@ -1182,6 +1191,7 @@ int ba_destroy(ba_ctx* c) {
   if (c->stream2) (void)hipStreamSynchronize(c->stream2);
   free_launcher(c->api);
   free_launcher(c->api2);
+  free_launcher(c->srv2);
   if (c->stream2) (void)hipStreamDestroy(c->stream2);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->join_ev) (void)hipEventDestroy(c->join_ev);
@@ -1280,9 +1290,9 @@ int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
     for (int s : slots)
       if (c->api.h_ctl[s].status == ST_RUNNING) act.push_back(s);
     if (act.empty()) break;
-    if (act.size() >= 8) {
+    if (act.size() >= 8 && !c->opt.single_stream) {
       split_halves(c, act, A, B);
-      if ((rc = run_iterations_split(c, A, B, per))) return rc;
+      if ((rc = run_iterations_split(c, c->api, c->api2, A, B, per))) return rc;
     } else if ((rc = run_iterations(c, c->api, act, per))) {
       return rc;
     }

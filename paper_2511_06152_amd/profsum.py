@@ -6,8 +6,8 @@ shape, the number of dispatches and their mean duration.
     python -m paper_2511_06152_amd.profsum <results.db> [top]
 
 Counters (counter_collection.csv of --pmc ... --output-format csv): per kernel
-name, the number of dispatches and the mean value of each counter per
-dispatch; optional substring filter on the kernel name.
+name and grid size, the number of dispatches and the mean value of each
+counter per dispatch; optional substring filter on the kernel name.
 
     python -m paper_2511_06152_amd.profsum --pmc <counter_collection.csv> [filter]
 """
@@ -32,19 +32,15 @@ def summarise(path: str, top: int = 20) -> str:
 
 def summarise_pmc(path: str, filt: str = "") -> str:
     vals = collections.defaultdict(list)
-    grids = collections.defaultdict(set)
     with open(path, newline="") as fh:
         for r in csv.DictReader(fh):
             name = r["Kernel_Name"]
             if filt and filt not in name:
                 continue
-            vals[(name, r["Counter_Name"])].append(float(r["Counter_Value"]))
-            grids[name].add(int(r["Grid_Size"]))
-    lines = [f"{'kernel':60s} {'counter':>12s} {'dispatches':>10s} {'mean/dispatch':>14s} {'grid sizes':>12s}"]
-    for (name, cn), v in sorted(vals.items()):
-        g = sorted(grids[name])
-        gs = str(g[0]) if len(g) == 1 else f"{g[0]}..{g[-1]}"
-        lines.append(f"{name[:60]:60s} {cn:>12s} {len(v):10d} {sum(v) / len(v):14.1f} {gs:>12s}")
+            vals[(name, int(r["Grid_Size"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    lines = [f"{'kernel':60s} {'counter':>12s} {'dispatches':>10s} {'mean/dispatch':>14s} {'grid size':>12s}"]
+    for (name, grid, cn), v in sorted(vals.items()):
+        lines.append(f"{name[:60]:60s} {cn:>12s} {len(v):10d} {sum(v) / len(v):14.1f} {grid:>12d}")
     return "\n".join(lines)
 
 
