@@ -54,10 +54,10 @@ FLOP_PAIR = 246
 # HBM traffic per launch of the two block kernels on 64 paper-scale clusters,
 # from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch) over `bench.py --steps 1 --warmup 0 --batch 64 --plain 0 --serve 0
-# --uneven 0 --stream-reps 0 --global-iters 0 --cpu-clusters 0` (mode
-# "in_step": the batch runs as two halves on two streams, so a launch covers
-# half the batch) and the same with `--single-stream` (mode "isolated": one
-# launch covers the batch), each scaled by what the same counter reads for a
+# --uneven 0 --stream-reps 0 --global-iters 0 --cpu-clusters 0` (the batch
+# runs as S parts on S streams, so a launch covers 1/S of the batch; key
+# (S, kernel)) and the same with `--batch-streams 1` (one launch covers the
+# batch: the kernel alone on the GPU), each scaled by what the same counter reads for a
 # plain copy of known size (`bench.py --copy-calibration 256`: FETCH_SIZE
 # reads 131084.8 KiB for 262144 KiB read, WRITE_SIZE 262144.0 KiB for 262144
 # KiB written).  Valid only for the kernel sources they were taken on (sha256
@@ -65,11 +65,11 @@ FLOP_PAIR = 246
 TRAFFIC = {
     "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
-    "kib": {  # (mode, kernel): (FETCH_SIZE, WRITE_SIZE)
-        ("in_step", "camblk"): (55459.1, 992.5),
-        ("in_step", "pairblk"): (72169.5, 1369.0),
-        ("isolated", "camblk"): (103839.2, 1998.7),
-        ("isolated", "pairblk"): (138407.9, 2761.3),
+    "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
+        (2, "camblk"): (55459.1, 992.5),
+        (2, "pairblk"): (72169.5, 1369.0),
+        (1, "camblk"): (103839.2, 1998.7),
+        (1, "pairblk"): (138407.9, 2761.3),
     },
     "sources_sha256": {
         "ba_kernels.hip": "9f0ee4ffcb6fd36bc094c7b046c684c95db87399c6eff4a12bd6c57880a3b3d1",
@@ -78,11 +78,11 @@ TRAFFIC = {
 }
 
 
-def traffic_bytes(kernel: str, batch: int, mode: str):
+def traffic_bytes(kernel: str, batch: int, streams: int):
     """Measured HBM bytes per launch of `kernel`, or None when the counters
     were taken on other kernel sources, another batch size or not at all."""
     import hashlib
-    key = (mode, kernel)
+    key = (streams, kernel)
     if key not in TRAFFIC["kib"] or batch != TRAFFIC["clusters"]:
         return None
     csrc = os.path.join(ROOT, "paper_2511_06152_amd", "csrc")
@@ -130,7 +130,7 @@ def measure_isolated(args, Context, ctx_kw, scenes, kw, flops):
     """One step of the same batch on a single stream with the two block
     kernels timed: their roofline when nothing else shares the GPU."""
     B = args.batch
-    ctx = Context(single_stream=True, **ctx_kw)
+    ctx = Context(batch_streams=1, **ctx_kw)
     ids = [i % len(scenes) for i in range(B)]
     tickets = [ctx.submit(scenes[j], **kw) for j in ids]
     for t in tickets:
@@ -151,7 +151,7 @@ def measure_isolated(args, Context, ctx_kw, scenes, kw, flops):
     avg = ms / max(n, 1)
     ach = fl[dom] / max(n, 1) / (avg / 1e3) / 1e12 if n else float("nan")
     return {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": ach, "peak": PEAK_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TFLOPS, "traffic": traffic_bytes(dom, B, "isolated"),
+            "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TFLOPS, "traffic": traffic_bytes(dom, B, 1),
             "traffic_unit": "bytes per launch", "avg_launch_us": avg * 1e3, "algorithmic_flop_per_launch": fl[dom] / max(n, 1),
             "note": "same batch, one stream: the kernel without the other half's kernels beside it"}
 
@@ -336,8 +336,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
     ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
-    ap.add_argument("--single-stream", action="store_true",
-                    help="run batches on one stream (no two-half overlap)")
+    ap.add_argument("--batch-streams", type=int, default=2,
+                    help="streams a batch is split across (1: one stream, no overlap)")
     ap.add_argument("--iters-per-tick", type=int, default=4,
                     help="LM iterations launched between control read-backs (batched context)")
     ap.add_argument("--uneven", type=int, default=256,
@@ -377,7 +377,7 @@ def main():
     B = args.batch
     ctx_kw = dict(precision=BA_MIXED, max_slots=max(B, 1), hbm_budget_bytes=int(B * 16e6) + (256 << 20),
                   chunks_per_task=args.chunks_per_task, iters_per_tick=args.iters_per_tick)
-    ctx = Context(single_stream=args.single_stream, **ctx_kw)
+    ctx = Context(batch_streams=args.batch_streams, **ctx_kw)
     step_ms, iters_total, mixed_final = [], 0, {}
     fl_total = {"camblk": 0.0, "pairblk": 0.0}
     ctx.ba_profile_enable(False)
@@ -419,14 +419,13 @@ def main():
     ctx.close()
     ms_per_step = float(np.mean(step_ms))
     # the block kernels alone on the GPU: one more step on a single stream
-    iso = measure_isolated(args, Context, ctx_kw, scenes, kw, flops) if not args.single_stream else None
+    iso = measure_isolated(args, Context, ctx_kw, scenes, kw, flops) if args.batch_streams > 1 else None
     value = B / (ms_per_step / 1e3)
 
     dom = max(("camblk", "pairblk"), key=lambda k: prof[k][0])
     asm_ms, asm_n = prof[dom]
     asm_avg_ms = asm_ms / max(asm_n, 1)
     achieved_tflops = fl_total[dom] / max(asm_n, 1) / (asm_avg_ms / 1e3) / 1e12 if asm_n else float("nan")
-    mode = "isolated" if args.single_stream else "in_step"
     kernels = {k: {"avg_us": (v[0] / max(v[1], 1)) * 1e3, "launches": v[1]} for k, v in prof_all.items()}
 
     # ---- plain FP64 GPU LM: one cluster at a time, host-driven ---------------------------
@@ -562,9 +561,10 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": achieved_tflops,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_VALU_TFLOPS,
-                     "traffic": traffic_bytes(dom, B, mode), "traffic_unit": "bytes per launch",
+                     "traffic": traffic_bytes(dom, B, args.batch_streams), "traffic_unit": "bytes per launch",
                      "avg_launch_us": asm_avg_ms * 1e3,
-                     "algorithmic_flop_per_launch": fl_total[dom] / max(asm_n, 1)},
+                     "algorithmic_flop_per_launch": fl_total[dom] / max(asm_n, 1),
+                     "batch_streams": args.batch_streams},
         "roofline_isolated": iso,
         "cpu_baseline": cpu,
         "batched_uneven": uneven,

@@ -114,10 +114,11 @@ typedef struct {
   int32_t resident_points;   /* capacity of the resident point state; 0 -> 4194304.  The
                                 store (96 B per camera, 24 B per point) is allocated at the
                                 first cluster that uses it, outside the arena */
-  int32_t single_stream;     /* 0: batched solves and the serving loop run 8 or more running
-                                clusters as two halves on two streams, so that one half's
-                                latency-bound kernels overlap the other's assembly;
-                                1: one stream */
+  int32_t batch_streams;     /* batched solves and the serving loop run S parts of the running
+                                clusters (of about equal assembly work) on S streams when at
+                                least 4 S clusters run, so that one part's latency-bound
+                                kernels overlap the others' assembly; 1: one stream;
+                                0 -> 2; at most 4, else BA_E_ARG */
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */

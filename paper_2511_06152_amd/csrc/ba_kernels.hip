@@ -701,13 +701,78 @@ __device__ __forceinline__ void jp_q(const ObsJ<R>& o, const R* Q, R T[2][3]) {
       T[a][t] = fm(o.Jp[a][2], qel(Q, 2, t), fm(o.Jp[a][1], qel(Q, 1, t), o.Jp[a][0] * qel(Q, 0, t)));
 }
 
-template <typename R, int N>
-__device__ __forceinline__ void wave_store(R (&acc)[N], R* out, int lane) {
+// Wavefront sums of N per-lane values written to out[0..N): N full-wave
+// reductions for FP64; for FP32 a reduce-scatter in six halving stages, each
+// pairing a lane with one that differs in one lane-index bit (bits 5 and 4 by
+// the CDNA4 cross-half swaps, bits 3..0 by DPP moves inside a row).  At each
+// stage the lower lane keeps the sum of the first half of its values, the
+// upper lane of the second half, so ~N exchanges replace 6 N, and lane l ends
+// up holding the whole-wave sum of one value, stored with one instruction.
+// The summation tree is fixed, so the result depends on the inputs only.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int N, int STAGE>
+__device__ __forceinline__ void rs_stage(float* v, int lane) {
+  constexpr int H = (N + 1) / 2;
+  if constexpr (STAGE < 2) {
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const unsigned a = __float_as_uint(v[i]), b = i + H < N ? __float_as_uint(v[i + H]) : 0u;
+      // swap a's upper 32 (16) lanes with b's lower 32 (16): each lane then
+      // holds its own value of one half and its partner's of the same half
+      const auto r = STAGE == 0 ? __builtin_amdgcn_permlane32_swap(a, b, false, false)
+                                : __builtin_amdgcn_permlane16_swap(a, b, false, false);
+      v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+  } else {
+    const bool hi = (lane >> (5 - STAGE)) & 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float a = v[i], b = i + H < N ? v[i + H] : 0.0f;
+      const float keep = hi ? b : a, send = hi ? a : b;
+      float got;
+      if constexpr (STAGE == 2) got = dpp_mov<0x128>(send);        // row_ror:8: partner lane ^ 8
+      else if constexpr (STAGE == 3) got = dpp_mov<0x141>(send);   // row_half_mirror: lane ^ 7
+      else if constexpr (STAGE == 4) got = dpp_mov<0x4E>(send);    // quad_perm 2,3,0,1: lane ^ 2
+      else got = dpp_mov<0xB1>(send);                              // quad_perm 1,0,3,2: lane ^ 1
+      v[i] = keep + got;
+    }
+  }
+  if constexpr (STAGE < 5) rs_stage<H, STAGE + 1>(v, lane);
+}
+
+// Index of the value lane `lane` holds after rs_stage<N, 0>, or -1 (padding).
+template <int N>
+__device__ __forceinline__ int rs_index(int lane) {
+  int n[7] = {N};
+#pragma unroll
+  for (int s = 0; s < 6; ++s) n[s + 1] = (n[s] + 1) / 2;
+  int l = 0;
+  bool ok = true;
+#pragma unroll
+  for (int s = 5; s >= 0; --s) {
+    l += ((lane >> (5 - s)) & 1) * n[s + 1];
+    ok = ok && l < n[s];
+  }
+  return ok ? l : -1;
+}
+
+template <int N>
+__device__ __forceinline__ void wave_store(double (&acc)[N], double* out, int lane) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const R t = wave_sum(acc[i]);
+    const double t = wave_sum(acc[i]);
     if (lane == 0) out[i] = t;
   }
+}
+template <int N>
+__device__ __forceinline__ void wave_store(float (&acc)[N], float* out, int lane) {
+  rs_stage<N, 0>(acc, lane);
+  const int j = rs_index<N>(lane);
+  if (j >= 0) out[j] = acc[0];
 }
 
 template <typename R>

@@ -503,12 +503,13 @@ struct ba_ctx {
   bool dead = false;
   std::string last_error;
   Launcher api, srv;
-  // Batched solves split a batch in two halves on two streams, so that one
-  // half's latency-bound kernels (reduce, solve, LM) overlap the other half's
-  // assembly kernels.
-  Launcher api2, srv2;
-  hipStream_t stream2 = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // Batched solves split a batch into parts on separate streams, so that one
+  // part's latency-bound kernels (reduce, solve, LM) overlap the others'
+  // assembly kernels.  Part 0 uses the launchers above and `stream`.
+  static constexpr int kMaxParts = 4;
+  Launcher api_p[kMaxParts], srv_p[kMaxParts];   // [0] unused
+  hipStream_t stream_p[kMaxParts] = {};           // [0] unused
+  hipEvent_t fork_ev = nullptr, join_ev[kMaxParts] = {};
   // kernel timing (ba_profile_enable)
   int prof = 0;                   // bitmask of timed kernels
   std::vector<int> prof_set_mask; // mask each used event set was recorded with
@@ -553,12 +554,12 @@ int init_launcher(ba_ctx* c, Launcher& l) {
 }
 
 void free_launcher(Launcher& l) {
-  if (l.d_act) hipFree(l.d_act);
-  if (l.d_wgoff) hipFree(l.d_wgoff);
-  if (l.h_act) hipHostFree(l.h_act);
-  if (l.h_ctl) hipHostFree(l.h_ctl);
-  if (l.ev) hipEventDestroy(l.ev);
-  if (l.copy_ev) hipEventDestroy(l.copy_ev);
+  if (l.d_act) (void)hipFree(l.d_act);
+  if (l.d_wgoff) (void)hipFree(l.d_wgoff);
+  if (l.h_act) (void)hipHostFree(l.h_act);
+  if (l.h_ctl) (void)hipHostFree(l.h_ctl);
+  if (l.ev) (void)hipEventDestroy(l.ev);
+  if (l.copy_ev) (void)hipEventDestroy(l.copy_ev);
   l = Launcher();
 }
 
@@ -892,19 +893,22 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
   return BA_OK;
 }
 
-// n LM iterations of two disjoint groups of slots, A on the context's stream
-// and B on the second stream; the context's stream then waits for B.
-int run_iterations_split(ba_ctx* c, Launcher& la, Launcher& lb, const std::vector<int>& A, const std::vector<int>& B,
-                         int n_iters) {
-  Batch ba, bb;
+// n LM iterations of disjoint groups of slots, part p on stream p (part 0 on
+// the context's stream, with launcher l0); the context's stream then waits
+// for every part.
+int run_iterations_parts(ba_ctx* c, bool serving, const std::vector<std::vector<int>>& parts, int n_iters) {
+  const int P = (int)parts.size();
+  Batch b[ba_ctx::kMaxParts];
   int rc;
-  if ((rc = make_batch(c, la, A, ba))) return rc;
-  if ((rc = make_batch(c, lb, B, bb))) return rc;   // uploads on the context's stream
+  for (int p = 0; p < P; ++p) {
+    Launcher& l = p == 0 ? (serving ? c->srv : c->api) : (serving ? c->srv_p[p] : c->api_p[p]);
+    if ((rc = make_batch(c, l, parts[p], b[p]))) return rc;   // uploads on the context's stream
+  }
   HIPCHK(c, hipEventRecord(c->fork_ev, c->stream));
-  HIPCHK(c, hipStreamWaitEvent(c->stream2, c->fork_ev, 0));
+  for (int p = 1; p < P; ++p) HIPCHK(c, hipStreamWaitEvent(c->stream_p[p], c->fork_ev, 0));
   const bool mixed = c->opt.precision == BA_MIXED;
   for (int i = 0; i < n_iters; ++i) {
-    for (int h = 0; h < 2; ++h) {
+    for (int p = 0; p < P; ++p) {
       hipEvent_t* ev = nullptr;
       if (c->prof) {
         if (c->prof_used == c->prof_ev.size()) {
@@ -916,26 +920,41 @@ int run_iterations_split(ba_ctx* c, Launcher& la, Launcher& lb, const std::vecto
         c->prof_set_mask[c->prof_used] = c->prof;
         ev = c->prof_ev[c->prof_used++].data();
       }
-      HIPCHK(c, launch_iteration(h ? bb : ba, mixed, h ? c->stream2 : c->stream, ev, c->prof));
+      HIPCHK(c, launch_iteration(b[p], mixed, p ? c->stream_p[p] : c->stream, ev, c->prof));
     }
   }
-  HIPCHK(c, hipEventRecord(c->join_ev, c->stream2));
-  HIPCHK(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
+  for (int p = 1; p < P; ++p) {
+    HIPCHK(c, hipEventRecord(c->join_ev[p], c->stream_p[p]));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->join_ev[p], 0));
+  }
   return BA_OK;
 }
 
-// Splits running slots into two halves of about equal assembly work (point
+// Splits running slots into `P` parts of about equal assembly work (point
 // workgroups), in slot order.
-void split_halves(ba_ctx* c, const std::vector<int>& act, std::vector<int>& A, std::vector<int>& B) {
+void split_parts(ba_ctx* c, const std::vector<int>& act, int P, std::vector<std::vector<int>>& parts) {
   size_t total = 0;
   for (int s : act) total += (size_t)c->slots[s].desc.n_wg;
+  parts.assign(P, {});
   size_t acc = 0;
-  A.clear();
-  B.clear();
   for (int s : act) {
-    (acc * 2 < total ? A : B).push_back(s);
+    const int p = (int)std::min<size_t>(P - 1, acc * P / std::max<size_t>(total, 1));
+    parts[p].push_back(s);
     acc += (size_t)c->slots[s].desc.n_wg;
   }
+  parts.erase(std::remove_if(parts.begin(), parts.end(), [](const std::vector<int>& v) { return v.empty(); }),
+              parts.end());
+}
+
+// Iterations of the running slots, split across streams when there are enough.
+int run_tick(ba_ctx* c, bool serving, const std::vector<int>& act, int n_iters) {
+  const int P = c->opt.batch_streams;
+  if (P > 1 && (int)act.size() >= 4 * P) {
+    std::vector<std::vector<int>> parts;
+    split_parts(c, act, P, parts);
+    return run_iterations_parts(c, serving, parts, n_iters);
+  }
+  return run_iterations(c, serving ? c->srv : c->api, act, n_iters);
 }
 
 // Exports the listed slots' state into their ticket caches (synchronous).
@@ -1027,7 +1046,7 @@ bool serving_queued(ba_ctx* c) {
 
 // One serving tick: retire finished clusters, admit queued ones, iterate.
 void serve_loop(ba_ctx* c) {
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   std::vector<int> active;
   std::unique_lock<std::mutex> lk(c->mu);
   while (!c->stop) {
@@ -1062,13 +1081,7 @@ void serve_loop(ba_ctx* c) {
       c->cv.wait(lk, [&] { return c->stop || serving_queued(c); });
       continue;
     }
-    if (active.size() >= 8 && !c->opt.single_stream) {
-      std::vector<int> A, B;
-      split_halves(c, active, A, B);
-      if (run_iterations_split(c, c->srv, c->srv2, A, B, c->opt.iters_per_tick)) break;
-    } else if (run_iterations(c, c->srv, active, c->opt.iters_per_tick)) {
-      break;
-    }
+    if (run_tick(c, true, active, c->opt.iters_per_tick)) break;
     if (hipMemcpyAsync(c->srv.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost, c->stream) ||
         hipEventRecord(c->srv.ev, c->stream)) {
       c->dead = true;
@@ -1136,7 +1149,8 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
   if (c->opt.pcg_max_iters <= 0) c->opt.pcg_max_iters = 500;
   if (!(c->opt.pcg_tol > 0)) c->opt.pcg_tol = 0.1;
-  if (c->opt.single_stream != 0 && c->opt.single_stream != 1) return BA_E_ARG;
+  if (c->opt.batch_streams == 0) c->opt.batch_streams = 2;
+  if (c->opt.batch_streams < 1 || c->opt.batch_streams > ba_ctx::kMaxParts) return BA_E_ARG;
   if (c->opt.resident_cams <= 0) c->opt.resident_cams = 8192;
   if (c->opt.resident_points <= 0) c->opt.resident_points = 1 << 22;
   if (c->opt.solver < BA_SOLVER_AUTO || c->opt.solver > BA_SOLVER_PCG || c->opt.pcg_max_iters > 100000 ||
@@ -1153,7 +1167,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
     c->own_stream = true;
   }
   if (hipMalloc(&c->arena_base, c->opt.hbm_budget_bytes) != hipSuccess) {
-    if (c->own_stream) hipStreamDestroy(c->stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     return BA_E_NOMEM;
   }
   c->arena.init(c->opt.hbm_budget_bytes);
@@ -1161,15 +1175,16 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
       hipMalloc(&c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots) != hipSuccess) {
     return BA_E_NOMEM;
   }
-  hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots);
+  (void)hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots);
   c->slots.resize(c->opt.max_slots);
-  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv) || init_launcher(c.get(), c->api2) ||
-      init_launcher(c.get(), c->srv2))
-    return BA_E_DEVICE;
-  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess)
-    return BA_E_DEVICE;
+  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return BA_E_DEVICE;
+  if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) return BA_E_DEVICE;
+  for (int p = 1; p < c->opt.batch_streams; ++p) {
+    if (init_launcher(c.get(), c->api_p[p]) || init_launcher(c.get(), c->srv_p[p]) ||
+        hipStreamCreateWithFlags(&c->stream_p[p], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev[p], hipEventDisableTiming) != hipSuccess)
+      return BA_E_DEVICE;
+  }
   for (int i = 0; i < c->opt.max_slots; ++i) c->srv.h_ctl[i] = SlotCtl{};
   if (hipDeviceSynchronize() != hipSuccess) return BA_E_DEVICE;
   ba_ctx* raw = c.release();
@@ -1186,24 +1201,27 @@ int ba_destroy(ba_ctx* c) {
   }
   c->cv.notify_all();
   if (c->th.joinable()) c->th.join();
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
-  if (c->stream2) (void)hipStreamSynchronize(c->stream2);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (int p = 1; p < ba_ctx::kMaxParts; ++p)
+    if (c->stream_p[p]) (void)hipStreamSynchronize(c->stream_p[p]);
   free_launcher(c->api);
-  free_launcher(c->api2);
-  free_launcher(c->srv2);
-  if (c->stream2) (void)hipStreamDestroy(c->stream2);
+  for (int p = 1; p < ba_ctx::kMaxParts; ++p) {
+    free_launcher(c->api_p[p]);
+    free_launcher(c->srv_p[p]);
+    if (c->stream_p[p]) (void)hipStreamDestroy(c->stream_p[p]);
+    if (c->join_ev[p]) (void)hipEventDestroy(c->join_ev[p]);
+  }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
-  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
   free_launcher(c->srv);
   for (auto& set : c->prof_ev)
     for (auto& e : set) (void)hipEventDestroy(e);
-  if (c->d_desc) hipFree(c->d_desc);
-  if (c->d_ctl) hipFree(c->d_ctl);
-  if (c->arena_base) hipFree(c->arena_base);
-  if (c->res_cam) hipFree(c->res_cam);
-  if (c->res_pt) hipFree(c->res_pt);
-  if (c->own_stream) hipStreamDestroy(c->stream);
+  if (c->d_desc) (void)hipFree(c->d_desc);
+  if (c->d_ctl) (void)hipFree(c->d_ctl);
+  if (c->arena_base) (void)hipFree(c->arena_base);
+  if (c->res_cam) (void)hipFree(c->res_cam);
+  if (c->res_pt) (void)hipFree(c->res_pt);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return BA_OK;
 }
@@ -1251,7 +1269,7 @@ int ba_step(ba_ctx* c, ba_ticket id, int32_t n_iters) {
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
   if (n_iters < 0) return fail(c, BA_E_ARG, "negative iteration count");
-  hipSetDevice(c->device);
+  HIPCHK(c, hipSetDevice(c->device));
   std::vector<int> adm;
   int rc = ensure_resident(c, *t, adm);
   if (rc) return rc;
@@ -1271,7 +1289,7 @@ int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
   if (!c || (n > 0 && !ids) || n < 0) return BA_E_ARG;
   std::lock_guard<std::mutex> g(c->mu);
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
-  hipSetDevice(c->device);
+  HIPCHK(c, hipSetDevice(c->device));
   std::vector<int> adm, slots;
   for (int i = 0; i < n; ++i) {
     Ticket* t = find_ticket(c, ids[i]);
@@ -1284,18 +1302,12 @@ int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
   if (rc) return rc;
   if ((rc = read_ctl(c, c->api))) return rc;
   const int per = c->opt.iters_per_tick;
-  std::vector<int> A, B;
   for (;;) {
     std::vector<int> act;
     for (int s : slots)
       if (c->api.h_ctl[s].status == ST_RUNNING) act.push_back(s);
     if (act.empty()) break;
-    if (act.size() >= 8 && !c->opt.single_stream) {
-      split_halves(c, act, A, B);
-      if ((rc = run_iterations_split(c, c->api, c->api2, A, B, per))) return rc;
-    } else if ((rc = run_iterations(c, c->api, act, per))) {
-      return rc;
-    }
+    if ((rc = run_tick(c, false, act, per))) return rc;
     if ((rc = read_ctl(c, c->api))) return rc;
   }
   std::vector<int> wb;
@@ -1338,7 +1350,7 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   if (t->state == TK_QUEUED) return fail(c, BA_E_STATE, "cluster is still queued");
   if (t->state == TK_RESIDENT) {
     if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
-    hipSetDevice(c->device);
+    HIPCHK(c, hipSetDevice(c->device));
     const std::vector<int> one{t->slot};
     int rc = export_slots(c, c->api, one);
     if (rc) return rc;
@@ -1398,8 +1410,8 @@ int ba_release(ba_ctx* c, ba_ticket id) {
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
   if (t->serving) return fail(c, BA_E_STATE, "cluster is being solved by the serving loop");
   if (t->state == TK_RESIDENT) {
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     free_slot(c, t->slot);
   }
   c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), id), c->queue.end());

@@ -173,17 +173,18 @@ def test_mixed_within_tolerance_converged():
     assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
 
 
-@pytest.mark.parametrize("precision", [FP64, MIXED])
-def test_batched_equals_alone(precision):
+@pytest.mark.parametrize("precision,streams,n", [(FP64, 2, 10), (MIXED, 2, 10), (FP64, 4, 18), (MIXED, 4, 18)])
+def test_batched_equals_alone(precision, streams, n):
     """Clusters of uneven size solved together in one launch series give
     bit-identical results to each solved alone (every sum has a fixed order).
-    Ten clusters: the batch runs as two halves on two streams while eight or
-    more are running, then as one."""
+    The batch runs as `streams` parts on as many streams while at least four
+    per stream are running, then as one."""
     from paper_2511_06152_amd import Context
+    print("case batched", precision, streams, n, flush=True)
     scenes = [A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + i % 4, n_points=300 + 400 * (i % 4),
                                         intr_mask=3 if i % 4 == 1 else 0,
                                         k_true=(-0.05, 0.02) if i % 4 == 1 else (0, 0)),
-                           50 + i) for i in range(10)]
+                           50 + i) for i in range(n)]
     kw = dict(max_iters=8, stop_on_ftol=True, ftol=1e-7)
     alone = []
     with Context(precision=precision) as ctx:
@@ -191,7 +192,7 @@ def test_batched_equals_alone(precision):
             t = ctx.submit(sc, **kw)
             ctx.ba_solve_batch([t])
             alone.append(ctx.ba_fetch(t))
-    with Context(precision=precision) as ctx:
+    with Context(precision=precision, batch_streams=streams) as ctx:
         ts = [ctx.submit(sc, **kw) for sc in scenes]
         ctx.ba_solve_batch(ts)
         mix = [ctx.ba_fetch(t) for t in ts]
