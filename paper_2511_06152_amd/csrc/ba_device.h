@@ -19,7 +19,8 @@ constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 
 constexpr int kPtVals = 16;               // per point: Q (6 packed symmetric), g (3), Z (6), pad (1)
 constexpr int kTaskVals = 52;             // per block task partial: camera task 51 values, pair task 36
 constexpr int kPtPartVals = 10;           // per point-pass wavefront: intrinsic-intrinsic terms
-constexpr int kBlk = 6;                   // block size of the reduced-system factorisation
+constexpr int kSolveTb = 16;              // block size of the dense reduced-system factorisation
+constexpr int kSolveTbVals = kSolveTb * (kSolveTb + 1);   // doubles per block (rows padded to 17)
 constexpr int kSbRow = 8;                 // sparse reduced-system block: 6 rows padded to 8 values
 constexpr int kSbVals = 6 * kSbRow;       //   (16-byte aligned rows for vector loads)
 // Work items of the block-assembly kernel (one wavefront each) and of its
@@ -33,7 +34,7 @@ struct SlotDesc {
   int C, P, L, n_chunks, n_wg, cpw;       // cameras, points, lanes, 64-lane chunks, workgroups, chunks/WG
   int m, n_free, kcol0, kcol1;            // reduced system size, free cameras, intrinsic columns (-1: fixed)
   int psize, pstride;                     // packed m(m+1)/2, reduced-system vector stride (psize + 3m)
-  int max_iters, stop_on_ftol, mixed, nb;  // nb: 6x6 blocks per side of the reduced system
+  int max_iters, stop_on_ftol, mixed, nb;  // nb: 16x16 blocks per side of the dense reduced system
   int Lc, Lq, n_tasks, n_cam_tasks, n_cam_task_wg, n_pair_task_wg, n_targets, n_pt_part;
   int sparse, nnzb, pcg_max_iters, pad1;  // sparse: block-CSR reduced system solved by PCG
   double pcg_tol;
@@ -72,7 +73,7 @@ struct SlotDesc {
   void* task_part;                        // [n_tasks][52] Real: per-task block sums
   void* pt_part;                          // [n_pt_part][10] Real: per point-pass wavefront intrinsic sums
   double* Sg;                             // [pstride] reduced: packed S_acc (psize), g, bS, diag U (m each)
-  double* Sd;                             // [nb(nb+1)/2][36] damped S in 6x6 blocks, for the refinement step
+  double* Sd;                             // [nb(nb+1)/2][272] damped S in 16x16 blocks, for the refinement step
   // sparse reduced system (PCG): block rows of the free cameras, diagonal block first
   const int* brow;                        // [F + 1]
   const int* bcol;                        // [nnzb] free-camera column of each block

@@ -1054,32 +1054,38 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
   else if (kc1 >= 0) Sg[pidx(fa + (v - 45), kc1)] = t;
 }
 
-// ---- damped reduced-camera-system solve (one wavefront per cluster) -------------
+// ---- damped reduced-camera-system solve (one workgroup per cluster) ------------
 //
-// The system is handled in 6x6 blocks (one per free camera, the intrinsics
-// padded with identity rows into one more block): right-looking block
-// Cholesky in LDS, block triangular solves, and in mixed mode one FP64
-// refinement step against the damped system kept in global memory.  A single
-// wavefront runs it, so its phases are ordered by program order alone (no
-// workgroup barriers on the critical path of a latency-bound factorisation).
+// The damped system is held in LDS as the lower triangle of 16x16 FP64 blocks
+// (the padding rows and columns are identity; each block row is padded to 17
+// doubles so that 16 lanes reading one column hit 16 distinct bank pairs).
+// Right-looking block Cholesky: one wavefront factors the diagonal block and
+// forms the inverse of its factor; the panel (A_IK L_KK^-T) and the trailing
+// update (A_IJ -= L_IK L_JK^T) are 16x16x16 FP64 products on the matrix cores
+// (v_mfma_f64_16x16x4), spread over the four wavefronts.  The block
+// triangular solves use the inverted diagonal blocks; in mixed mode one FP64
+// refinement step runs against a copy of the damped system (LDS when it fits,
+// global memory otherwise).
 
-constexpr int kSolveThreads = 64;        // the factorisation and solves: one wavefront
-constexpr int kSolveLoadThreads = 256;   // the load phase: four wavefronts
+constexpr int kSolveWG = 256;                   // four wavefronts
+constexpr int kTbS = kSolveTb + 1;              // LDS row stride of a block (doubles)
+constexpr int kTbV = kSolveTb * kTbS;           // doubles per block
+constexpr int kSolveWk = 2 * kSolveTb * kSolveTb + kSolveTb;   // factor scratch + solve vector
 constexpr size_t kSolveLdsCap = 150 * 1024;
 
 // LDS doubles of the solve kernel for a batch whose largest system has nbm
 // blocks per side, without and with the refinement copy.  Every cluster of the
 // batch uses at most this layout, so the copy decision is made per launch.
 __host__ __device__ inline size_t solve_lds_base(int nbm) {
-  const size_t nb = (size_t)nbm, blk = nb * (nb + 1) / 2 * 36;
-  return blk + nb * 36 + 5 * 6 * nb + kSolveThreads;
+  const size_t nb = (size_t)nbm;
+  return nb * (nb + 1) / 2 * kTbV + nb * kTbV + 5 * kSolveTb * nb + kSolveWk;
 }
 __host__ __device__ inline bool solve_lds_copy(int nbm) {
   const size_t nb = (size_t)nbm;
-  return sizeof(double) * (solve_lds_base(nbm) + nb * (nb + 1) / 2 * 36) <= kSolveLdsCap;
+  return sizeof(double) * (solve_lds_base(nbm) + nb * (nb + 1) / 2 * kTbV) <= kSolveLdsCap;
 }
 
-__device__ __forceinline__ int bidx(int i, int j) { return (i * (i + 1) / 2 + j) * 36; }   // i >= j
+__device__ __forceinline__ int tblk(int I, int J) { return (I * (I + 1) / 2 + J) * kTbV; }   // I >= J
 
 __device__ __forceinline__ void decode_tri(int e, int* ii, int* jj) {   // e -> (ii >= jj)
   int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
@@ -1139,87 +1145,155 @@ __device__ __forceinline__ bool chol6_inv(double* __restrict__ a, double* __rest
   return true;
 }
 
-// Solves L L^T x = x in place (padded length 6 nb); Li holds the inverses of
-// the diagonal blocks of L; tmp has >= 6 entries.  One wavefront.
-__device__ void blk_solve(const double* __restrict__ A, const double* __restrict__ Li, double* x, double* tmp,
-                          int nb, int tid) {
-  for (int k = 0; k < nb; ++k) {
-    if (tid < 6) {
-      double y = 0.0;
-      for (int t = 0; t <= tid; ++t) y += Li[36 * k + 6 * tid + t] * x[6 * k + t];
-      tmp[tid] = y;
-    }
-    wave_sync();
-    for (int e = tid; e < (nb - k - 1) * 6; e += kSolveThreads) {
-      const int i = k + 1 + e / 6, r = e % 6;
-      const double* Aik = A + bidx(i, k) + 6 * r;
-      x[6 * i + r] -= Aik[0] * tmp[0] + Aik[1] * tmp[1] + Aik[2] * tmp[2] + Aik[3] * tmp[3] + Aik[4] * tmp[4] +
-                      Aik[5] * tmp[5];
-    }
-    if (tid < 6) x[6 * k + tid] = tmp[tid];
-    wave_sync();
-  }
-  for (int k = nb - 1; k >= 0; --k) {
-    if (tid < 6) {
-      double y = 0.0;
-      for (int t = tid; t < 6; ++t) y += Li[36 * k + 6 * t + tid] * x[6 * k + t];
-      tmp[tid] = y;
-    }
-    wave_sync();
-    for (int e = tid; e < k * 6; e += kSolveThreads) {
-      const int j = e / 6, cc = e % 6;
-      const double* Akj = A + bidx(k, j) + cc;
-      x[6 * j + cc] -= Akj[0] * tmp[0] + Akj[6] * tmp[1] + Akj[12] * tmp[2] + Akj[18] * tmp[3] + Akj[24] * tmp[4] +
-                       Akj[30] * tmp[5];
-    }
-    if (tid < 6) x[6 * k + tid] = tmp[tid];
-    wave_sync();
-  }
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// Lane l's value of v from lane `src` (wave-uniform result).
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(kSolveLoadThreads) void k_solve(Batch bt) {
+// 1/sqrt(x) for x > 0: the hardware estimate and two Newton steps
+// y <- y + y (1 - x y^2) / 2 (each roughly doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = __builtin_fma(-x, y * y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Cholesky factor of the 16x16 SPD block a (full symmetric storage, stride
+// kTbS) and the inverse of the factor into li (lower, zeros above); one
+// wavefront.  Lane c + 16 g holds rows g, g+4, g+8, g+12 of column c of the
+// block and of the inverse (forward substitution of L X = I, column by column
+// alongside the factorisation).  Column j: the lanes holding row j form
+// L[c][j] and X[j][c] and post them to LDS; every lane then updates its four
+// rows.  The next pivot is formed from two lane reads before that update, so
+// the LDS round trip stays off the pivot chain; the column steps have no
+// branches (every group posts to its own slot, updates are masked), so the
+// unrolled steps can overlap.  wk: 2 x 256 doubles scratch.  Returns false
+// (wave-uniform) when a pivot is not positive and finite.
+__device__ bool chol16_inv(const double* __restrict__ a, double* __restrict__ li, double* __restrict__ wk, int lane) {
+  constexpr int T = kSolveTb;
+  const int c = lane & (T - 1), g = lane >> 4;
+  double* colL = wk;           // [j % 4][group][c] = L[c][j]
+  double* rowX = wk + T * T;   // [j % 4][group][c] = X[j][c]
+  double v[4], x[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = a[(4 * k + g) * kTbS + c];
+    x[k] = (4 * k + g == c) ? 1.0 : 0.0;
+  }
+  bool good = true;
+  double piv = readlane_d(v[0], 0);
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int jg = j & 3, jk = j >> 2, slot = (j & 3) * 4 * T;
+    good = good && piv > 0.0 && piv < 1e300;
+    const double rs = rsqrt_nr(piv);
+    const double l = c >= j ? v[jk] * rs : 0.0;   // L[c][j], meaningful in group jg
+    const double xj = x[jk] * rs;                  // X[j][c], meaningful in group jg
+    double pn = 1.0;
+    if (j + 1 < T) {
+      const double lt = readlane_d(l, (j + 1) + 16 * jg);                            // L[j+1][j]
+      const double dv = readlane_d(v[(j + 1) >> 2], (j + 1) + 16 * ((j + 1) & 3));   // A[j+1][j+1]
+      pn = __builtin_fma(-lt, lt, dv);
+    }
+    colL[slot + g * T + c] = l;
+    rowX[slot + g * T + c] = xj;
+    x[jk] = g == jg ? xj : x[jk];
+    wave_sync();
+    const double lc = colL[slot + jg * T + c], xc = rowX[slot + jg * T + c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double lij = 4 * k + g > j ? colL[slot + jg * T + 4 * k + g] : 0.0;   // L[i][j], rows below j
+      v[k] = __builtin_fma(-lij, lc, v[k]);
+      x[k] = __builtin_fma(-lij, xc, x[k]);
+    }
+    piv = pn;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) li[(4 * k + g) * kTbS + c] = x[k];
+  wave_sync();
+  return good;
+}
+
+// 16x16 block product on the matrix cores: out = cin + sgn * P Q^T, with P, Q,
+// cin and out blocks of stride kTbS (out may alias cin or P); one wavefront.
+// Operand layouts of v_mfma_f64_16x16x4: A lane l -> (row l%16, k l/16),
+// B lane l -> (k l/16, column l%16), C/D lane l, register r -> (row l/16 + 4r,
+// column l%16).
+__device__ __forceinline__ void mfma_blk(const double* P, const double* Q,
+                                         const double* cin, double* out, double sgn, int lane) {
+  const int lo = lane & 15, hi = lane >> 4;
+  double pa[4], qb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    pa[s] = sgn * P[lo * kTbS + 4 * s + hi];
+    qb[s] = Q[lo * kTbS + 4 * s + hi];
+  }
+  double4_t acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = cin ? cin[(hi + 4 * r) * kTbS + lo] : 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[s], qb[s], acc, 0, 0, 0);
+  wave_sync();   // every lane's operands are read before any result lands (out may alias them)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[(hi + 4 * r) * kTbS + lo] = acc[r];
+}
+
+__global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   extern __shared__ double sd[];
   const int s = bt.act[blockIdx.x];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING || d.sparse) return;
   const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int m = d.m, psize = d.psize, nb = d.nb;
-  const int np = nb * kBlk, nblk = nb * (nb + 1) / 2;
-  double* A = sd;                 // [nblk][36] lower block triangle, row-major blocks
-  double* Li = A + nblk * 36;     // [nb][36] inverse diagonal factors
-  double* gv = Li + nb * 36;      // [np] gradient of the camera side (with priors)
-  double* Dv = gv + np;           // [np] clamped diagonal of H
-  double* xv = Dv + np;           // [np] solution
-  double* bv = xv + np;           // [np] right-hand side
-  double* rv = bv + np;           // [np] refinement residual
-  double* tmp = rv + np;          // [kSolveThreads]
-  double* Sl = tmp + kSolveThreads;   // [nblk][36] damped copy, when it fits
+  const int np = nb * kSolveTb, ntri = nb * (nb + 1) / 2;
+  double* A = sd;                    // [ntri] lower block triangle
+  double* Li = A + ntri * kTbV;      // [nb] inverses of the diagonal factor blocks
+  double* gv = Li + nb * kTbV;       // [np] gradient of the camera side (with priors)
+  double* Dv = gv + np;              // [np] clamped diagonal of H
+  double* xv = Dv + np;              // [np] solution
+  double* bv = xv + np;              // [np] right-hand side
+  double* rv = bv + np;              // [np] refinement residual
+  double* wk = rv + np;              // [kSolveWk] factor scratch, solve vector
+  double* Sl = wk + kSolveWk;        // [ntri] damped copy, when it fits
   __shared__ int ok;
   const double lambda = c.lambda;
   const int cur = c.cur;
-  // Load phase, all waves: packed reduced system -> 6x6 blocks.
-  for (int e0 = tid; e0 < nblk * 36; e0 += 4 * kSolveLoadThreads) {
-    double val[4];
-    int at[4];
+  // Load: packed reduced system -> blocks (diagonal blocks full, symmetric).
+  constexpr int kLd = 16;   // loads in flight per thread
+  for (int e0 = tid; e0 < ntri * kSolveTb * kSolveTb; e0 += kLd * kSolveWG) {
+    double val[kLd];
+    int at[kLd];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * kSolveLoadThreads;
-      at[u] = e;
+    for (int u = 0; u < kLd; ++u) {
+      const int e = e0 + u * kSolveWG;
+      at[u] = -1;
       val[u] = 0.0;
-      if (e < nblk * 36) {
+      if (e < ntri * kSolveTb * kSolveTb) {
         int bi, bj;
-        decode_tri(e / 36, &bi, &bj);
-        const int p = 6 * bi + (e % 36) / 6, q = 6 * bj + (e % 6);
+        decode_tri(e / (kSolveTb * kSolveTb), &bi, &bj);
+        const int r = (e / kSolveTb) % kSolveTb, q0 = e % kSolveTb;
+        const int p = kSolveTb * bi + r, q = kSolveTb * bj + q0;
         val[u] = (p == q) ? 1.0 : 0.0;
         if (p < m && q < m) val[u] = d.Sg[p <= q ? pidx(p, q) : pidx(q, p)];
+        at[u] = tblk(bi, bj) + r * kTbS + q0;
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (at[u] < nblk * 36) A[at[u]] = val[u];
+    for (int u = 0; u < kLd; ++u)
+      if (at[u] >= 0) A[at[u]] = val[u];
   }
-  for (int p = tid; p < np; p += kSolveLoadThreads) {
+  for (int p = tid; p < np; p += kSolveWG) {
     const bool real = p < m;
     gv[p] = real ? d.Sg[psize + p] : 0.0;
     xv[p] = real ? d.Sg[psize + m + p] : 0.0;     // bS for now
@@ -1227,37 +1301,40 @@ __global__ __launch_bounds__(kSolveLoadThreads) void k_solve(Batch bt) {
   }
   if (tid == 0) ok = (c.point_fail == 0);
   __syncthreads();
-  // From here on a single wavefront: phases are ordered by program order.
-  if (tid >= kSolveThreads) return;
-  // pose priors of the free cameras; each lane owns whole camera blocks
-  for (int k = tid; k < d.C; k += kSolveThreads) {
+  // Pose priors of the free cameras, one thread per camera (disjoint entries).
+  // Element (p, q) is stored when p's block row is at or below q's; the
+  // diagonal blocks hold both triangles.
+  for (int k = tid; k < d.C; k += kSolveWG) {
     const int col = d.cam_col[k];
     if (col < 0) continue;
     double e[6], J[9];
     prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
     const double* pr = d.prior + kPriorVals * k;
-    double* Ab = A + bidx(col / 6, col / 6);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const double h = J[r] * J[q] + J[3 + r] * J[3 + q] + J[6 + r] * J[6 + q];
-        Ab[6 * r + q] += h;
+        const int p0 = col + r, q1 = col + q;
+        if (p0 / kSolveTb >= q1 / kSolveTb)
+          A[tblk(p0 / kSolveTb, q1 / kSolveTb) + (p0 % kSolveTb) * kTbS + q1 % kSolveTb] += h;
         if (q == r) Dv[col + r] += h;
       }
       gv[col + r] += J[r] * e[0] + J[3 + r] * e[1] + J[6 + r] * e[2];
       const double it = pr[15 + r];
-      Ab[6 * (3 + r) + 3 + r] += it * it;
+      const int p3 = col + 3 + r;
+      A[tblk(p3 / kSolveTb, p3 / kSolveTb) + (p3 % kSolveTb) * (kTbS + 1)] += it * it;
       Dv[col + 3 + r] += it * it;
       gv[col + 3 + r] += it * e[3 + r];
     }
   }
-  wave_sync();
-  for (int p = tid; p < np; p += kSolveThreads) {
+  __syncthreads();
+  // Marquardt damping and the right-hand side.
+  for (int p = tid; p < np; p += kSolveWG) {
     if (p < m) {
       const double Di = clampd(Dv[p]);
       Dv[p] = Di;
-      A[bidx(p / 6, p / 6) + 7 * (p % 6)] += lambda * Di;
+      A[tblk(p / kSolveTb, p / kSolveTb) + (p % kSolveTb) * (kTbS + 1)] += lambda * Di;
       bv[p] = -gv[p] + xv[p];
     } else {
       Dv[p] = 0.0;
@@ -1265,93 +1342,129 @@ __global__ __launch_bounds__(kSolveLoadThreads) void k_solve(Batch bt) {
     }
     xv[p] = bv[p];
   }
-  wave_sync();
+  __syncthreads();
   const bool lds_copy = solve_lds_copy(bt.max_nb);
   if (d.mixed) {
-    if (lds_copy) for (int e = tid; e < nblk * 36; e += kSolveThreads) Sl[e] = A[e];
-    else for (int e = tid; e < nblk * 36; e += kSolveThreads) d.Sd[e] = A[e];
+    if (lds_copy) for (int e = tid; e < ntri * kTbV; e += kSolveWG) Sl[e] = A[e];
+    else for (int e = tid; e < ntri * kTbV; e += kSolveWG) d.Sd[e] = A[e];
+    __syncthreads();
   }
-  for (int k = 0; k < nb; ++k) {
-    if (tid == 0 && !chol6_inv(A + bidx(k, k), Li + 36 * k)) ok = 0;
-    wave_sync();
-    if (!ok) break;
-    const double* li = Li + 36 * k;
-    // panel: A_ik <- A_ik L_kk^-T, one lane per row of a block
-    for (int e = tid; e < (nb - k - 1) * 6; e += kSolveThreads) {
-      double* row = A + bidx(k + 1 + e / 6, k) + 6 * (e % 6);
-      double in[6];
-#pragma unroll
-      for (int t = 0; t < 6; ++t) in[t] = row[t];
-#pragma unroll
-      for (int cc = 0; cc < 6; ++cc) {
-        double v = 0.0;
-#pragma unroll
-        for (int t = 0; t <= cc; ++t) v += in[t] * li[6 * cc + t];
-        row[cc] = v;
-      }
+  // Right-looking block Cholesky.
+  for (int K = 0; K < nb; ++K) {
+    if (wave == 0) {
+      const bool good = chol16_inv(A + tblk(K, K), Li + K * kTbV, wk, lane);
+      if (!good && lane == 0) ok = 0;
     }
-    wave_sync();
-    // trailing update, one lane per block pair: A_ij -= A_ik A_jk^T, k < j <= i
-    const int rows = nb - k - 1;
-    for (int pr = tid; pr < rows * (rows + 1) / 2; pr += kSolveThreads) {
+    __syncthreads();
+    if (!ok) break;
+    // panel: L_IK = A_IK L_KK^-T
+    for (int I = K + 1 + wave; I < nb; I += kSolveWG / kWave)
+      mfma_blk(A + tblk(I, K), Li + K * kTbV, nullptr, A + tblk(I, K), 1.0, lane);
+    __syncthreads();
+    // trailing update: A_IJ -= L_IK L_JK^T for K < J <= I
+    const int R = nb - K - 1;
+    for (int pr = wave; pr < R * (R + 1) / 2; pr += kSolveWG / kWave) {
       int ii, jj;
       decode_tri(pr, &ii, &jj);
-      const int i = k + 1 + ii, j = k + 1 + jj;
-      const double* a = A + bidx(i, k);
-      const double* bb = A + bidx(j, k);
-      double* o = A + bidx(i, j);
-      double ar[36];
-#pragma unroll
-      for (int t = 0; t < 36; ++t) ar[t] = a[t];
-#pragma unroll
-      for (int cc = 0; cc < 6; ++cc) {
-        double bc[6];
-#pragma unroll
-        for (int t = 0; t < 6; ++t) bc[t] = bb[6 * cc + t];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          if (i == j && cc > r) continue;
-          o[6 * r + cc] -= ar[6 * r] * bc[0] + ar[6 * r + 1] * bc[1] + ar[6 * r + 2] * bc[2] +
-                           ar[6 * r + 3] * bc[3] + ar[6 * r + 4] * bc[4] + ar[6 * r + 5] * bc[5];
-        }
-      }
+      const int I = K + 1 + ii, J = K + 1 + jj;
+      mfma_blk(A + tblk(I, K), A + tblk(J, K), A + tblk(I, J), A + tblk(I, J), -1.0, lane);
     }
-    wave_sync();
+    __syncthreads();
   }
   if (!ok) {
     if (tid == 0) c.solve_ok = 0;
     return;
   }
-  blk_solve(A, Li, xv, tmp, nb, tid);
+  double* yk = wk + 2 * kSolveTb * kSolveTb;   // [16]
+  // L L^T x = x in place, block by block with the inverted diagonal blocks;
+  // one wavefront (at most 144 rows below a block: three per lane).
+  auto solve = [&](double* x) {
+    for (int K = 0; K < nb; ++K) {            // forward: L y = x
+      if (lane < kSolveTb) {
+        const double* li = Li + K * kTbV + lane * kTbS;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSolveTb; q += 2) {
+          s0 = __builtin_fma(li[q], x[kSolveTb * K + q], s0);
+          s1 = __builtin_fma(li[q + 1], x[kSolveTb * K + q + 1], s1);
+        }
+        yk[lane] = s0 + s1;
+      }
+      wave_sync();
+      for (int p = kSolveTb * (K + 1) + lane; p < np; p += kWave) {
+        const double* row = A + tblk(p / kSolveTb, K) + (p % kSolveTb) * kTbS;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSolveTb; q += 2) {
+          s0 = __builtin_fma(row[q], yk[q], s0);
+          s1 = __builtin_fma(row[q + 1], yk[q + 1], s1);
+        }
+        x[p] -= s0 + s1;
+      }
+      if (lane < kSolveTb) x[kSolveTb * K + lane] = yk[lane];
+      wave_sync();
+    }
+    for (int K = nb - 1; K >= 0; --K) {       // backward: L^T x = y
+      if (lane < kSolveTb) {
+        const double* li = Li + K * kTbV + lane;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSolveTb; q += 2) {
+          s0 = __builtin_fma(li[q * kTbS], x[kSolveTb * K + q], s0);
+          s1 = __builtin_fma(li[(q + 1) * kTbS], x[kSolveTb * K + q + 1], s1);
+        }
+        yk[lane] = s0 + s1;
+      }
+      wave_sync();
+      for (int p = lane; p < kSolveTb * K; p += kWave) {
+        const double* colp = A + tblk(K, p / kSolveTb) + p % kSolveTb;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kSolveTb; r += 2) {
+          s0 = __builtin_fma(colp[r * kTbS], yk[r], s0);
+          s1 = __builtin_fma(colp[(r + 1) * kTbS], yk[r + 1], s1);
+        }
+        x[p] -= s0 + s1;
+      }
+      if (lane < kSolveTb) x[kSolveTb * K + lane] = yk[lane];
+      wave_sync();
+    }
+  };
+  if (wave == 0) solve(xv);
   if (d.mixed) {
     // one FP64 refinement step: r = b - S_damped x, then L L^T dx = r, x += dx
+    __syncthreads();
     const double* Sd = lds_copy ? Sl : d.Sd;
-    for (int p = tid; p < np; p += kSolveThreads) {
-      const int pb = p / 6, pr_ = p % 6;
-      double t = bv[p];
-      for (int qb = 0; qb < nb; ++qb) {
-        const double* B = Sd + (pb >= qb ? bidx(pb, qb) + 6 * pr_ : bidx(qb, pb) + pr_);
-        const int stride = pb >= qb ? 1 : 6;
-        double bq[6];
+    for (int p = tid; p < np; p += kSolveWG) {
+      const int P = p / kSolveTb, pr_ = p % kSolveTb;
+      double t0 = bv[p], t1 = 0.0;
+      for (int Q = 0; Q < nb; ++Q) {
+        const double* B = Sd + (P >= Q ? tblk(P, Q) + pr_ * kTbS : tblk(Q, P) + pr_);
+        const int stride = P >= Q ? 1 : kTbS;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) bq[q] = B[stride * q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) t -= bq[q] * xv[6 * qb + q];
+        for (int q = 0; q < kSolveTb; q += 2) {
+          t0 = __builtin_fma(-B[stride * q], xv[kSolveTb * Q + q], t0);
+          t1 = __builtin_fma(-B[stride * (q + 1)], xv[kSolveTb * Q + q + 1], t1);
+        }
       }
-      rv[p] = t;
+      rv[p] = t0 + t1;
     }
-    wave_sync();
-    blk_solve(A, Li, rv, tmp, nb, tid);
-    for (int p = tid; p < np; p += kSolveThreads) xv[p] += rv[p];
-    wave_sync();
+    __syncthreads();
+    if (wave == 0) {
+      solve(rv);
+      for (int p = lane; p < np; p += kWave) xv[p] += rv[p];
+      wave_sync();
+    }
   }
+  if (tid >= kWave) return;
+  // From here on one wavefront: predicted decrease, trial cameras, prior cost.
   double pacc = 0.0;
-  for (int p = tid; p < m; p += kSolveThreads) pacc += xv[p] * (lambda * Dv[p] * xv[p] - gv[p]);
+  for (int p = tid; p < m; p += kWave) pacc += xv[p] * (lambda * Dv[p] * xv[p] - gv[p]);
   const double predc = wave_sum(pacc);
-  for (int p = tid; p < m; p += kSolveThreads) d.dc[p] = xv[p];
+  for (int p = tid; p < m; p += kWave) d.dc[p] = xv[p];
   const int nxt = 1 - cur;
   double pc = 0.0;
-  for (int k = tid; k < d.C; k += kSolveThreads) {
+  for (int k = tid; k < d.C; k += kWave) {
     const double* cm = d.cam[cur] + kCamVals * k;
     double* cn = d.cam[nxt] + kCamVals * k;
     const int col = d.cam_col[k];
@@ -1928,7 +2041,7 @@ size_t pcg_smem(const Batch& b) {
 }
 
 size_t solve_smem(const Batch& b) {
-  const size_t nb = (size_t)b.max_nb, blk = nb * (nb + 1) / 2 * 36;
+  const size_t nb = (size_t)b.max_nb, blk = nb * (nb + 1) / 2 * kTbV;
   return sizeof(double) * (solve_lds_base(b.max_nb) + (solve_lds_copy(b.max_nb) ? blk : 0));
 }
 
@@ -2025,7 +2138,7 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   }
   // A solver with no cluster in the batch is not launched; with timing on, its
   // events mark an empty interval.
-  if (b.any_dense) launch(k_solve, dim3(b.n_act), dim3(kSolveLoadThreads), s_solve, st, evk(4), 4, b);
+  if (b.any_dense) launch(k_solve, dim3(b.n_act), dim3(kSolveWG), s_solve, st, evk(4), 4, b);
   else if (evk(4) && ((e = hipEventRecord(ev_all[8], st)) || (e = hipEventRecord(ev_all[9], st)))) return e;
   if (b.any_sparse) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, evk(7), 7, b);
   else if (evk(7) && ((e = hipEventRecord(ev_all[14], st)) || (e = hipEventRecord(ev_all[15], st)))) return e;

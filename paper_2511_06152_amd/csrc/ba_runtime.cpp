@@ -141,7 +141,7 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.task_part = take(rs * kTaskVals * s.tasks.size());
   l.pt_part = take(rs * kPtPartVals * (size_t)s.n_pt_part);
   l.Sg = take(8 * (size_t)l.pstride);
-  l.Sd = take(s.sparse ? 0 : 8 * 36 * (size_t)s.nb * (s.nb + 1) / 2);
+  l.Sd = take(s.sparse ? 0 : 8 * kSolveTbVals * (size_t)s.nb * (s.nb + 1) / 2);
   l.dc = take(8 * (size_t)s.m);
   const size_t nnzb = s.bcol.size();
   l.brow = take(4 * s.brow.size());
@@ -324,7 +324,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   s.n_wg = (s.n_chunks + cpw - 1) / cpw;
   const bool intr = s.kcol0 >= 0 || s.kcol1 >= 0;
   s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
-  s.nb = s.n_free + (intr ? 1 : 0);
+  s.nb = (s.m + kSolveTb - 1) / kSolveTb;
   const int F = s.n_free;
   std::vector<int> free_cam(F);
   for (int k = 0; k < C; ++k)
