@@ -121,6 +121,52 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Global-memory view of a device pointer.  Loads and stores through it are
+// global rather than generic (flat) operations: they count on the vector
+// memory counter only, so the waits for LDS and scalar loads in the chunk
+// loops do not also wait for them.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> gmem(T* p) { return (gptr<T>)p; }
+
+// First N values of a per-point record, as vector loads.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+template <int N>
+__device__ __forceinline__ void rec_load(gptr<const float> p, float* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4) {
+    const vf4 t = *reinterpret_cast<gptr<const vf4>>(p + i);
+    v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
+  }
+}
+template <int N>
+__device__ __forceinline__ void rec_load(gptr<const double> p, double* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 2) {
+    const vd2 t = *reinterpret_cast<gptr<const vd2>>(p + i);
+    v[i] = t.x; v[i + 1] = t.y;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void rec_store(gptr<float> p, const float* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4) *reinterpret_cast<gptr<vf4>>(p + i) = vf4{v[i], v[i + 1], v[i + 2], v[i + 3]};
+}
+template <int N>
+__device__ __forceinline__ void rec_store(gptr<double> p, const double* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 2) *reinterpret_cast<gptr<vd2>>(p + i) = vd2{v[i], v[i + 1]};
+}
+
+// FP32 or FP64 views of the point state and the observed pixels.
+template <typename R> __device__ __forceinline__ gptr<const R> pts_of(const SlotDesc& d, int cur);
+template <> __device__ __forceinline__ gptr<const float> pts_of<float>(const SlotDesc& d, int cur) { return gmem((const float*)d.X32[cur]); }
+template <> __device__ __forceinline__ gptr<const double> pts_of<double>(const SlotDesc& d, int cur) { return gmem((const double*)d.X[cur]); }
+template <typename R> __device__ __forceinline__ gptr<const R> uv_of(const double* p64, const float* p32);
+template <> __device__ __forceinline__ gptr<const float> uv_of<float>(const double*, const float* p32) { return gmem(p32); }
+template <> __device__ __forceinline__ gptr<const double> uv_of<double>(const double* p64, const float*) { return gmem(p64); }
+
 // ---- SO(3) (FP64) -----------------------------------------------------------
 
 __device__ __forceinline__ void so3_exp(const double w[3], double R[9]) {
@@ -525,30 +571,33 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
   const R lam = (R)c.lambda;
   const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
-  const bool mixed = sizeof(R) == 4;
-  R* __restrict__ ptv = reinterpret_cast<R*>(d.ptv);
-  R* __restrict__ ptd = reinterpret_cast<R*>(d.ptd);
+  const gptr<R> ptv = gmem(reinterpret_cast<R*>(d.ptv)), ptd = gmem(reinterpret_cast<R*>(d.ptd));
+  const gptr<const int> lpt = gmem(d.lane_pt), lcam = gmem(d.lane_cam), lseg = gmem(d.lane_seg);
+  const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.lane_uv64, d.lane_uv32);
   R iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // S(k0k0) S(k0k1) S(k1k1) g0 g1 dU0 dU1 bS0 bS1
   bool fail = false;
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
+  // The lane words of the next chunk are requested a chunk ahead; loads are
+  // unconditional (padding lanes read point 0, then zero what they read).
+  int pt_n = 0, cam_n = 0, seg_n = 0;
+  if (c0 + wave < c1) {
+    const int i0 = (c0 + wave) * kWave + lane;
+    pt_n = lpt[i0]; cam_n = lcam[i0]; seg_n = lseg[i0];
+  }
   for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
     const int idx = ch * kWave + lane;
-    const int pt = d.lane_pt[idx];
+    const int pt = pt_n, cam_l = cam_n, seg = seg_n;
+    if (ch + kWavesPerWG < c1) {
+      const int in = idx + kWavesPerWG * kWave;
+      pt_n = lpt[in]; cam_n = lcam[in]; seg_n = lseg[in];
+    }
     const bool valid = pt >= 0;
-    const int cam = valid ? d.lane_cam[idx] : 0;
-    const int seg = d.lane_seg[idx];
+    const int cam = valid ? cam_l : 0, ps = valid ? pt : 0;
     const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
     const bool head = valid && sb == lane;
-    R X0 = 0, X1 = 0, X2 = 0, u = 0, v = 0;
-    if (valid) {
-      if (mixed) {
-        X0 = (R)d.X32[cur][3 * pt]; X1 = (R)d.X32[cur][3 * pt + 1]; X2 = (R)d.X32[cur][3 * pt + 2];
-        u = (R)d.lane_uv32[2 * idx]; v = (R)d.lane_uv32[2 * idx + 1];
-      } else {
-        X0 = (R)d.X[cur][3 * pt]; X1 = (R)d.X[cur][3 * pt + 1]; X2 = (R)d.X[cur][3 * pt + 2];
-        u = (R)d.lane_uv64[2 * idx]; v = (R)d.lane_uv64[2 * idx + 1];
-      }
-    }
+    const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2], ur = uvs[2 * idx], vr = uvs[2 * idx + 1];
+    const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
+    const R u = valid ? ur : R(0), v = valid ? vr : R(0);
     ObsJ<R> o;
     obs_model<R>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
     const R w = o.w;
@@ -604,9 +653,9 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 #pragma unroll
       for (int i = 0; i < 6; ++i) rec[9 + i] = INTR ? sum[(9 + i) % NV] : R(0);
       rec[15] = R(0);
-      pt_store<kPtVals>(ptv + kPtVals * (size_t)pt, rec);
+      rec_store<kPtVals>(ptv + kPtVals * (size_t)pt, rec);
       const R dr[4] = {Dp[0], Dp[1], Dp[2], R(0)};
-      pt_store<4>(ptd + 4 * (size_t)pt, dr);
+      rec_store<4>(ptd + 4 * (size_t)pt, dr);
     }
     if constexpr (INTR) {
       const R u00 = w * fm(o.Jk[0][0], o.Jk[0][0], o.Jk[1][0] * o.Jk[1][0]);
@@ -651,12 +700,12 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 // of the intrinsic rows of W, and D_V; per wavefront, the intrinsic-intrinsic
 // sums (U part of all observations, Schur part of all points).
 template <typename R>
-__global__ __launch_bounds__(kWG) void k_point(Batch bt) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 7 : 4))) void k_point(Batch bt) {
   const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.wg_off, bt.n_act, bx);
-  const int s = bt.act[si];
+  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.wg_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
@@ -776,11 +825,11 @@ __device__ __forceinline__ void wave_store(float (&acc)[N], float* out, int lane
 }
 
 template <typename R>
-__global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_camblk(Batch bt) {
   const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.tkc_off, bt.n_act, bx);
-  const int s = bt.act[si];
+  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.tkc_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING) return;
@@ -801,29 +850,31 @@ __global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
   (void)kb;
 
     const bool i0 = d.kcol0 >= 0, i1 = d.kcol1 >= 0;
+    const gptr<const int> cl_pt = gmem(d.cl_pt);
+    const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.cl_uv64, d.cl_uv32), recs = gmem(ptv);
     R acc[51];
 #pragma unroll
     for (int i = 0; i < 51; ++i) acc[i] = R(0);
-    for (int ch = tk.y; ch < tk.y + tk.z; ++ch) {
+    // Loads are unconditional (padding lanes read point 0, then zero what
+    // they read), and the next chunk's point index is requested a chunk
+    // ahead.
+    const int ch_end = tk.y + tk.z;
+    int pt_next = cl_pt[tk.y * kWave + lane];
+    for (int ch = tk.y; ch < ch_end; ++ch) {
       const int idx = ch * kWave + lane;
-      const int pt = d.cl_pt[idx];
+      const int pt = pt_next;
+      if (ch + 1 < ch_end) pt_next = cl_pt[idx + kWave];
       const bool valid = pt >= 0;
-      R X0 = 0, X1 = 0, X2 = 0, u = 0, v = 0;
-      if (valid) {
-        if (mixed) {
-          X0 = (R)d.X32[cur][3 * pt]; X1 = (R)d.X32[cur][3 * pt + 1]; X2 = (R)d.X32[cur][3 * pt + 2];
-          u = (R)d.cl_uv32[2 * idx]; v = (R)d.cl_uv32[2 * idx + 1];
-        } else {
-          X0 = (R)d.X[cur][3 * pt]; X1 = (R)d.X[cur][3 * pt + 1]; X2 = (R)d.X[cur][3 * pt + 2];
-          u = (R)d.cl_uv64[2 * idx]; v = (R)d.cl_uv64[2 * idx + 1];
-        }
-      }
+      const int ps = valid ? pt : 0;
+      const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2], ur = uvs[2 * idx], vr = uvs[2 * idx + 1];
+      R rec[kPtVals];
+      rec_load<kPtVals>(recs + kPtVals * (size_t)ps, rec);
+      const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
+      const R u = valid ? ur : R(0), v = valid ? vr : R(0);
+#pragma unroll
+      for (int i = 0; i < kPtVals; ++i) rec[i] = valid && (i < 12 || i0 || i1) ? rec[i] : R(0);
       ObsJ<R> o;
       obs_model<R>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
-      R rec[kPtVals];
-#pragma unroll
-      for (int i = 0; i < kPtVals; ++i) rec[i] = R(0);
-      if (valid) pt_load(ptv + kPtVals * (size_t)pt, rec, (i0 || i1) ? 16 : (sizeof(R) == 8 ? 10 : 12));
       const R* Q = rec;
       const R* gp = rec + 6;
       const R w = o.w;
@@ -876,8 +927,8 @@ template <typename R>
 __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
   const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.tkp_off, bt.n_act, bx);
-  const int s = bt.act[si];
+  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.tkp_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING) return;
@@ -898,32 +949,35 @@ __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
 
     R cb[kCamVals];
     load_cam(d.cam[cur] + kCamVals * kb, cb);
+    const gptr<const int> ql_pt = gmem(d.ql_pt);
+    const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.ql_uv64, d.ql_uv32), recs = gmem(ptv);
     R acc[36];
 #pragma unroll
     for (int i = 0; i < 36; ++i) acc[i] = R(0);
-    for (int ch = tk.y; ch < tk.y + tk.z; ++ch) {
+    // Loads are unconditional (padding lanes read point 0, then zero what
+    // they read), and the next chunk's point index is requested a chunk
+    // ahead.
+    const int ch_end = tk.y + tk.z;
+    int pt_next = ql_pt[tk.y * kWave + lane];
+    for (int ch = tk.y; ch < ch_end; ++ch) {
       const int idx = ch * kWave + lane;
-      const int pt = d.ql_pt[idx];
+      const int pt = pt_next;
+      if (ch + 1 < ch_end) pt_next = ql_pt[idx + kWave];
       const bool valid = pt >= 0;
-      R X0 = 0, X1 = 0, X2 = 0, ua = 0, va = 0, ub = 0, vb = 0;
-      if (valid) {
-        if (mixed) {
-          X0 = (R)d.X32[cur][3 * pt]; X1 = (R)d.X32[cur][3 * pt + 1]; X2 = (R)d.X32[cur][3 * pt + 2];
-          ua = (R)d.ql_uv32[4 * idx]; va = (R)d.ql_uv32[4 * idx + 1];
-          ub = (R)d.ql_uv32[4 * idx + 2]; vb = (R)d.ql_uv32[4 * idx + 3];
-        } else {
-          X0 = (R)d.X[cur][3 * pt]; X1 = (R)d.X[cur][3 * pt + 1]; X2 = (R)d.X[cur][3 * pt + 2];
-          ua = (R)d.ql_uv64[4 * idx]; va = (R)d.ql_uv64[4 * idx + 1];
-          ub = (R)d.ql_uv64[4 * idx + 2]; vb = (R)d.ql_uv64[4 * idx + 3];
-        }
-      }
+      const int ps = valid ? pt : 0;
+      const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2];
+      const R uar = uvs[4 * idx], var = uvs[4 * idx + 1], ubr = uvs[4 * idx + 2], vbr = uvs[4 * idx + 3];
+      R Q[8];
+      rec_load<sizeof(R) == 8 ? 6 : 8>(recs + kPtVals * (size_t)ps, Q);
+      const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
+      const R ua = valid ? uar : R(0), va = valid ? var : R(0), ub = valid ? ubr : R(0), vb = valid ? vbr : R(0);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Q[i] = valid && i < (sizeof(R) == 8 ? 6 : 8) ? Q[i] : R(0);
       // -Y_a W_b^T = J_ca^T M J_cb with the 2x2 M = -w_a w_b J_pa Q J_pb^T.
       R a0[6], a1[6], T[2][3], wa;
       {
         ObsJ<R> oa;
         obs_model<R>(ca, X0, X1, X2, ua, va, f, k1, k2, is, dt, valid, oa);
-        R Q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (valid) pt_load(ptv + kPtVals * (size_t)pt, Q, sizeof(R) == 8 ? 6 : 8);
         jp_q(oa, Q, T);
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
@@ -1270,45 +1324,62 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   const double lambda = c.lambda;
   const int cur = c.cur;
   // Load: packed reduced system -> blocks (diagonal blocks full, symmetric).
-  constexpr int kLd = 16;   // loads in flight per thread
-  for (int e0 = tid; e0 < ntri * kSolveTb * kSolveTb; e0 += kLd * kSolveWG) {
-    double val[kLd];
-    int at[kLd];
+  // Thread tid owns element (tid / 16, tid % 16) of every block; kLd blocks
+  // are requested at once.  The pose-prior terms of camera tid are computed
+  // while the first batch is in flight: its camera and prior are requested
+  // first, so that the prior math waits for them alone.
+  constexpr int kLd = 16;
+  // global (not generic) loads: they count on the vector-memory counter only,
+  // so waits for scalar loads do not wait for them
+  typedef const __attribute__((address_space(1))) double* gdp;
+  const gdp __restrict__ Sg = (gdp)d.Sg;
+  const int er = tid / kSolveTb, ec = tid % kSolveTb;
+  double val[kLd];
+  auto fetch = [&](int b0) {
+    int bi = 0, bj = b0;
+    while (bj > bi) bj -= ++bi;   // block b0 -> (bi, bj), bj <= bi (uniform)
 #pragma unroll
     for (int u = 0; u < kLd; ++u) {
-      const int e = e0 + u * kSolveWG;
-      at[u] = -1;
-      val[u] = 0.0;
-      if (e < ntri * kSolveTb * kSolveTb) {
-        int bi, bj;
-        decode_tri(e / (kSolveTb * kSolveTb), &bi, &bj);
-        const int r = (e / kSolveTb) % kSolveTb, q0 = e % kSolveTb;
-        const int p = kSolveTb * bi + r, q = kSolveTb * bj + q0;
-        val[u] = (p == q) ? 1.0 : 0.0;
-        if (p < m && q < m) val[u] = d.Sg[p <= q ? pidx(p, q) : pidx(q, p)];
-        at[u] = tblk(bi, bj) + r * kTbS + q0;
-      }
+      const int p = kSolveTb * bi + er, q = kSolveTb * bj + ec;
+      val[u] = (p == q) ? 1.0 : 0.0;
+      if (b0 + u < ntri && p < m && q < m) val[u] = Sg[p <= q ? pidx(p, q) : pidx(q, p)];
+      if (++bj > bi) { ++bi; bj = 0; }
     }
+  };
+  auto put = [&](int b0) {
 #pragma unroll
     for (int u = 0; u < kLd; ++u)
-      if (at[u] >= 0) A[at[u]] = val[u];
+      if (b0 + u < ntri) A[(b0 + u) * kTbV + er * kTbS + ec] = val[u];
+  };
+  const int pk = min(tid, d.C - 1);
+  double pcam[kCamVals], ppr[kPriorVals];
+  const gdp gcam = (gdp)d.cam[cur] + kCamVals * pk, gpr = (gdp)d.prior + kPriorVals * pk;
+#pragma unroll
+  for (int i = 0; i < kCamVals; ++i) pcam[i] = gcam[i];
+#pragma unroll
+  for (int i = 0; i < kPriorVals; ++i) ppr[i] = gpr[i];
+  const int pcol = tid < d.C ? d.cam_col[tid] : -1;
+  __asm__ volatile("" ::: "memory");
+  fetch(0);
+  double pe[6], pJ[9];
+  if (pcol >= 0) prior_terms(pcam, ppr, pe, pJ);
+  put(0);
+  for (int b0 = kLd; b0 < ntri; b0 += kLd) {
+    fetch(b0);
+    put(b0);
   }
   for (int p = tid; p < np; p += kSolveWG) {
     const bool real = p < m;
-    gv[p] = real ? d.Sg[psize + p] : 0.0;
-    xv[p] = real ? d.Sg[psize + m + p] : 0.0;     // bS for now
-    Dv[p] = real ? d.Sg[psize + 2 * m + p] : 0.0; // diag U for now
+    gv[p] = real ? Sg[psize + p] : 0.0;
+    xv[p] = real ? Sg[psize + m + p] : 0.0;     // bS for now
+    Dv[p] = real ? Sg[psize + 2 * m + p] : 0.0; // diag U for now
   }
   if (tid == 0) ok = (c.point_fail == 0);
   __syncthreads();
   // Pose priors of the free cameras, one thread per camera (disjoint entries).
   // Element (p, q) is stored when p's block row is at or below q's; the
   // diagonal blocks hold both triangles.
-  for (int k = tid; k < d.C; k += kSolveWG) {
-    const int col = d.cam_col[k];
-    if (col < 0) continue;
-    double e[6], J[9];
-    prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
+  auto add_prior = [&](int k, int col, const double* e, const double* J) {
     const double* pr = d.prior + kPriorVals * k;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -1327,6 +1398,14 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
       Dv[col + 3 + r] += it * it;
       gv[col + 3 + r] += it * e[3 + r];
     }
+  };
+  if (pcol >= 0) add_prior(tid, pcol, pe, pJ);
+  for (int k = tid + kSolveWG; k < d.C; k += kSolveWG) {   // clusters of more than 256 cameras
+    const int col = d.cam_col[k];
+    if (col < 0) continue;
+    double e[6], J[9];
+    prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
+    add_prior(k, col, e, J);
   }
   __syncthreads();
   // Marquardt damping and the right-hand side.
@@ -1824,8 +1903,8 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = find_slot(bt.wg_off, bt.n_act, bx);
-  const int s = bt.act[si];
+  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.wg_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
@@ -1851,25 +1930,40 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const double tk1 = c.k[nxt][0], tk2 = c.k[nxt][1];
   const int kc0 = d.kcol0, kc1 = d.kcol1;
   const R dk0 = kc0 >= 0 ? sdc[kc0] : R(0), dk1 = kc1 >= 0 ? sdc[kc1] : R(0);
-  const R* __restrict__ ptv = reinterpret_cast<const R*>(d.ptv);
+  const gptr<const R> ptv = gmem(reinterpret_cast<const R*>(d.ptv)), ptd = gmem(reinterpret_cast<const R*>(d.ptd));
+  const gptr<const int> lpt = gmem(d.lane_pt), lcam = gmem(d.lane_cam), lseg = gmem(d.lane_seg);
+  const gptr<const double> Xc = gmem((const double*)d.X[cur]), uv64 = gmem((const double*)d.lane_uv64);
+  const gptr<double> Xn64 = gmem(d.X[nxt]);
+  const gptr<float> Xn32 = gmem(d.X32[nxt]);
   double rho_sum = 0.0, pred_sum = 0.0;
   int bad = 0;
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
+  // The lane words of the next chunk are requested a chunk ahead; loads are
+  // unconditional (padding lanes read point 0 and do not use it).
+  int pt_n = 0, cam_n = 0, seg_n = 0;
+  if (c0 + wave < c1) {
+    const int i0 = (c0 + wave) * kWave + lane;
+    pt_n = lpt[i0]; cam_n = lcam[i0]; seg_n = lseg[i0];
+  }
   for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
     const int idx = ch * kWave + lane;
-    const int pt = d.lane_pt[idx];
+    const int pt = pt_n, cam_l = cam_n, seg = seg_n;
+    if (ch + kWavesPerWG < c1) {
+      const int in = idx + kWavesPerWG * kWave;
+      pt_n = lpt[in]; cam_n = lcam[in]; seg_n = lseg[in];
+    }
     const bool valid = pt >= 0;
-    const int cam = valid ? d.lane_cam[idx] : 0;
-    const int seg = d.lane_seg[idx];
+    const int cam = valid ? cam_l : 0, ps = valid ? pt : 0;
     const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
     const bool head = valid && sb == lane;
     // The FP64 point and pixel serve both models: their FP32 shadows are these
     // values rounded, so they are not read again.
-    double Xd[3] = {0, 0, 0}, ud = 0.0, vd = 0.0;
-    if (valid) {
-      Xd[0] = d.X[cur][3 * pt]; Xd[1] = d.X[cur][3 * pt + 1]; Xd[2] = d.X[cur][3 * pt + 2];
-      ud = d.lane_uv64[2 * idx]; vd = d.lane_uv64[2 * idx + 1];
-    }
+    const double Xr[3] = {Xc[3 * ps], Xc[3 * ps + 1], Xc[3 * ps + 2]}, ur = uv64[2 * idx], vr = uv64[2 * idx + 1];
+    R pv[12], dv[4];
+    rec_load<sizeof(R) == 8 ? 10 : 12>(ptv + kPtVals * (size_t)ps, pv);
+    rec_load<4>(ptd + 4 * (size_t)ps, dv);
+    const double Xd[3] = {valid ? Xr[0] : 0.0, valid ? Xr[1] : 0.0, valid ? Xr[2] : 0.0};
+    const double ud = valid ? ur : 0.0, vd = valid ? vr : 0.0;
     const R X0 = (R)Xd[0], X1 = (R)Xd[1], X2 = (R)Xd[2], u = (R)ud, v = (R)vd;
     ObsJ<R> o;
     obs_model<R>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
@@ -1902,10 +1996,6 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
     }
     double Xn[3] = {Xd[0], Xd[1], Xd[2]};
     if (valid) {
-      R pv[12];
-      pt_load(ptv + kPtVals * (size_t)pt, pv, sizeof(R) == 8 ? 10 : 12);
-      R dv[4];
-      pt_load(reinterpret_cast<const R*>(d.ptd) + 4 * (size_t)pt, dv, 4);
       const R* Q = pv;
       const R rr[3] = {-pv[6] - ts[0], -pv[7] - ts[1], -pv[8] - ts[2]};
       R dp[3];
@@ -1916,8 +2006,8 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
         for (int t = 0; t < 3; ++t) {
           const double dd = (double)dp[t];
           pred_sum += dd * (lambda * (double)dv[t] * dd - (double)pv[6 + t]);
-          d.X[nxt][3 * pt + t] = Xn[t];
-          d.X32[nxt][3 * pt + t] = (float)Xn[t];
+          Xn64[3 * pt + t] = Xn[t];
+          Xn32[3 * pt + t] = (float)Xn[t];
         }
       }
       double rho;

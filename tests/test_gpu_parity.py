@@ -148,13 +148,19 @@ def test_point_with_64_observations():
     check_cost_log(got, ref)
 
 
-@pytest.mark.parametrize("which", ["tiny", "cluster12"])
+@pytest.mark.parametrize("which", ["tiny", "cluster12", "24_free_cams"])
 def test_mixed_within_tolerance_after_fixed_iterations(which):
-    """Both paths run 40 iterations: by then the FP64 iterate moves < 0.1 mm
-    per 40 iterations on these scenes (at 10 it still moves ~1 cm), so the
-    comparison measures precision, not two points of a moving trajectory."""
-    sc = A.scene_tiny(1) if which == "tiny" else A.scene_cluster12(2)
-    iters = 40
+    """Both paths run 40 iterations (60 for 24 free cameras, whose damped
+    system is too large for the LDS copy, so the refinement step reads it from
+    global memory): by then the FP64 iterate moves < 0.1 mm per 40 iterations
+    on these scenes (at 10 it still moves ~1 cm), so the comparison measures
+    precision, not two points of a moving trajectory."""
+    if which == "24_free_cams":
+        sc = A.make_scene(A.SceneSpec(n_strips=3, imgs_per_strip=8, n_points=6000, obs_model=("tgeom", 0.5, 2, 6),
+                                      outlier_frac=0.05), 35)
+    else:
+        sc = A.scene_tiny(1) if which == "tiny" else A.scene_cluster12(2)
+    iters = 60 if which == "24_free_cams" else 40
     ref = oracle.solve(sc, max_iters=iters)
     got = gpu_run(sc, iters, precision=MIXED)
     rms, dT, att = final_errors(sc, got, ref)
