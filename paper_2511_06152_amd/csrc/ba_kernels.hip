@@ -159,6 +159,38 @@ __device__ __forceinline__ void rec_store(gptr<double> p, const double* v) {
   for (int i = 0; i < N; i += 2) *reinterpret_cast<gptr<vd2>>(p + i) = vd2{v[i], v[i + 1]};
 }
 
+// Vector LDS rows (16-byte aligned).
+template <int N>
+__device__ __forceinline__ void lds_store(float* p, const float* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4) *reinterpret_cast<vf4*>(__builtin_assume_aligned(p + i, 16)) = vf4{v[i], v[i + 1], v[i + 2], v[i + 3]};
+}
+template <int N>
+__device__ __forceinline__ void lds_store(double* p, const double* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 2) *reinterpret_cast<vd2*>(__builtin_assume_aligned(p + i, 16)) = vd2{v[i], v[i + 1]};
+}
+template <int N>
+__device__ __forceinline__ void lds_load(const float* p, float* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4) {
+    const vf4 t = *reinterpret_cast<const vf4*>(__builtin_assume_aligned(p + i, 16));
+    v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
+  }
+}
+template <int N>
+__device__ __forceinline__ void lds_load(const double* p, double* v) {
+#pragma unroll
+  for (int i = 0; i < N; i += 2) {
+    const vd2 t = *reinterpret_cast<const vd2*>(__builtin_assume_aligned(p + i, 16));
+    v[i] = t.x; v[i + 1] = t.y;
+  }
+}
+// Row stride (elements) of the point pass's segmented-sum scratch: a row of
+// up to 16 values per lane, 16-byte aligned, padded so that rows of nearby
+// lanes start on different banks.
+template <typename R> constexpr int seg_stride() { return sizeof(R) == 4 ? 20 : 18; }
+
 // FP32 or FP64 views of the point state and the observed pixels.
 template <typename R> __device__ __forceinline__ gptr<const R> pts_of(const SlotDesc& d, int cur);
 template <> __device__ __forceinline__ gptr<const float> pts_of<float>(const SlotDesc& d, int cur) { return gmem((const float*)d.X32[cur]); }
@@ -166,6 +198,16 @@ template <> __device__ __forceinline__ gptr<const double> pts_of<double>(const S
 template <typename R> __device__ __forceinline__ gptr<const R> uv_of(const double* p64, const float* p32);
 template <> __device__ __forceinline__ gptr<const float> uv_of<float>(const double*, const float* p32) { return gmem(p32); }
 template <> __device__ __forceinline__ gptr<const double> uv_of<double>(const double* p64, const float*) { return gmem(p64); }
+
+// A wave-uniform value marked as such, so that it is kept in scalar registers.
+__device__ __forceinline__ float uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // ---- SO(3) (FP64) -----------------------------------------------------------
 
@@ -317,7 +359,8 @@ __device__ __forceinline__ bool obs_rho(const double* __restrict__ cam, const do
   const double y = cam[1] * d0 + cam[4] * d1 + cam[7] * d2;
   const double z = cam[2] * d0 + cam[5] * d1 + cam[8] * d2;
   if (!(z > 0.0)) { *rho = 0.0; return false; }
-  const double a = x / z, b = y / z;
+  const double iz = 1.0 / z;
+  const double a = x * iz, b = y * iz;
   const double r2 = a * a + b * b;
   const double D = 1.0 + k1 * r2 + k2 * r2 * r2;
   const double e0 = (f * D * a - u) * is, e1 = (f * D * b - v) * is;
@@ -621,19 +664,33 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 #pragma unroll
         for (int t = 0; t < 3; ++t) vals[9 + 3 * b + t] = fm(o.Jk[0][b], wJp[0][t], o.Jk[1][b] * wJp[1][t]);
     }
-    // segmented sums over the point's lanes (fixed order: first lane to last)
+    // segmented sums over the point's lanes (fixed order: first lane to
+    // last); each lane posts its values as one LDS row, read back with
+    // 16-byte loads
+    constexpr int SS = seg_stride<R>(), NVP = (NV + 3) / 4 * 4;
     wave_sync();
+    {
+      R row[NVP];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) scr[i * kWave + lane] = vals[i];
+      for (int i = 0; i < NVP; ++i) row[i] = i < NV ? vals[i] : R(0);
+      lds_store<NVP>(scr + lane * SS, row);
+    }
     wave_sync();
     R sum[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) sum[i] = R(0);
     for (int t = 0; t < maxl; ++t) {
       if (t < sl) {
-        const int src = sb + t;
+        const R* src = scr + (sb + t) * SS;
+        constexpr int VW = 16 / sizeof(R);   // values per 16-byte load
 #pragma unroll
-        for (int i = 0; i < NV; ++i) sum[i] += scr[i * kWave + src];
+        for (int q = 0; q < NVP; q += VW) {
+          R part[VW];
+          lds_load<VW>(src + q, part);
+#pragma unroll
+          for (int i = 0; i < VW; ++i)
+            if (q + i < NV) sum[q + i] += part[i];
+        }
       }
     }
     const R Dp[3] = {clampd(sum[0]), clampd(sum[3]), clampd(sum[5])};
@@ -716,7 +773,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
   for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) scam[i] = (R)d.cam[cur][i];
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  R* scr = scr_all + wave * 15 * kWave;
+  R* scr = scr_all + wave * seg_stride<R>() * kWave;
   if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true>(d, c, scam, scr, wgl, wave, lane);
   else point_pass<R, false>(d, c, scam, scr, wgl, wave, lane);
 }
@@ -737,7 +794,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 template <typename R>
 __device__ __forceinline__ void load_cam(const double* __restrict__ src, R* dst) {
 #pragma unroll
-  for (int i = 0; i < kCamVals; ++i) dst[i] = (R)src[i];
+  for (int i = 0; i < kCamVals; ++i) dst[i] = uniform((R)src[i]);
 }
 
 // T = J_p Q (2 x 3) for the packed symmetric 3x3 Q.
@@ -2115,7 +2172,7 @@ __global__ void k_export(Batch bt) {
 
 template <typename R>
 size_t point_smem(const Batch& b) {
-  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * 15 * kWave);
+  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * seg_stride<R>() * kWave);
 }
 
 template <typename R>

@@ -1,0 +1,45 @@
+"""Host-side checks of bench.py: the one-GPU contract, the algorithmic flop
+counts it divides by (against a brute-force count over the observations),
+and the guard that withholds measured traffic from other configurations."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from synth import aerial as A  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_block_flops_against_brute_force():
+    sc = A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=3, n_points=400, n_fixed=1, intr_mask=3,
+                                   k_true=(-0.05, 0.02)), 5)
+    fl = bench.block_flops(sc)
+    free = sc["fixed"] == 0
+    n_cam_obs, n_pairs = 0, 0
+    for j in range(sc["n_points"]):
+        cams = [int(c) for c in sc["obs_cam"][sc["obs_pt"] == j] if free[c]]
+        n_cam_obs += len(cams)
+        n_pairs += sum(1 for a in range(len(cams)) for b in range(a + 1, len(cams)))
+    assert fl["camblk"] == (bench.FLOP_CAM_OBS + bench.FLOP_CAM_INTR_OBS) * n_cam_obs
+    assert fl["pairblk"] == bench.FLOP_PAIR * n_pairs
+    sc["intr_mask"] = 0
+    assert bench.block_flops(sc)["camblk"] == bench.FLOP_CAM_OBS * n_cam_obs
+
+
+def test_traffic_only_for_the_measured_configuration():
+    k = next(iter(bench.TRAFFIC["kib"]))
+    streams, kernel = k
+    assert bench.traffic_bytes(kernel, bench.TRAFFIC["clusters"] + 1, streams) is None
+    assert bench.traffic_bytes(kernel, bench.TRAFFIC["clusters"], 7) is None
+    assert bench.traffic_bytes("no_such_kernel", bench.TRAFFIC["clusters"], streams) is None
