@@ -66,10 +66,8 @@ TRAFFIC = {
     "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "camblk"): (55459.1, 992.5),
-        (2, "pairblk"): (72169.5, 1369.0),
-        (1, "camblk"): (103839.2, 1998.7),
-        (1, "pairblk"): (138407.9, 2761.3),
+        (2, "blocks"): (0.0, 0.0),
+        (1, "blocks"): (0.0, 0.0),
     },
     "sources_sha256": {
         "ba_kernels.hip": "9f0ee4ffcb6fd36bc094c7b046c684c95db87399c6eff4a12bd6c57880a3b3d1",
@@ -94,11 +92,11 @@ def traffic_bytes(kernel: str, batch: int, streams: int):
     return 1024.0 * (f * TRAFFIC["fetch_scale"] + w * TRAFFIC["write_scale"])
 
 
-# kernels timed inside the timed region (bits of ba_profile_enable): the two
-# Schur block kernels, the candidates for the dominant kernel; timing all
-# eight costs ~7 % of the step, so the full breakdown is taken on one more,
+# kernels timed inside the timed region (bits of ba_profile_enable): the
+# Schur-block launch (camera and pair tasks), the dominant kernel; timing all
+# of them costs ~7 % of the step, so the full breakdown is taken on one more,
 # untimed step
-BLOCK_KERNELS = (1 << 1) | (1 << 2)
+BLOCK_KERNELS = 1 << 1
 
 
 def log(msg):
@@ -106,13 +104,15 @@ def log(msg):
 
 
 def block_flops(sc):
-    """Algorithmic flops of one k_camblk and one k_pairblk pass over the cluster."""
+    """Algorithmic flops of one pass of the camera tasks and of the pair tasks
+    over the cluster, and their sum (the Schur-block launch k_blocks)."""
     free = sc["fixed"][sc["obs_cam"]] == 0
     cnt = np.bincount(sc["obs_pt"][free], minlength=sc["n_points"])
     pairs = int((cnt * (cnt - 1) // 2).sum())
     n_free_obs = int(free.sum())
     cam = (FLOP_CAM_OBS + (FLOP_CAM_INTR_OBS if sc["intr_mask"] else 0)) * n_free_obs
-    return {"camblk": cam, "pairblk": FLOP_PAIR * pairs}
+    pair = FLOP_PAIR * pairs
+    return {"camblk": cam, "pairblk": pair, "blocks": cam + pair}
 
 
 def rms_px(sc, R, T, X, k):
@@ -139,20 +139,18 @@ def measure_isolated(args, Context, ctx_kw, scenes, kw, flops):
     ctx.ba_solve_batch(tickets)
     ctx.ba_profile_enable(False)
     prof = ctx.ba_profile_read()
-    fl = {"camblk": 0.0, "pairblk": 0.0}
+    fl = 0.0
     for t, j in zip(tickets, ids):
-        it = ctx.ba_fetch(t)["iterations"]
-        for k in fl:
-            fl[k] += it * flops[j][k]
+        fl += ctx.ba_fetch(t)["iterations"] * flops[j]["blocks"]
         ctx.ba_release(t)
     ctx.close()
-    dom = max(fl, key=lambda k: prof[k][0])
+    dom = "blocks"
     ms, n = prof[dom]
     avg = ms / max(n, 1)
-    ach = fl[dom] / max(n, 1) / (avg / 1e3) / 1e12 if n else float("nan")
+    ach = fl / max(n, 1) / (avg / 1e3) / 1e12 if n else float("nan")
     return {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": ach, "peak": PEAK_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TFLOPS, "traffic": traffic_bytes(dom, B, 1),
-            "traffic_unit": "bytes per launch", "avg_launch_us": avg * 1e3, "algorithmic_flop_per_launch": fl[dom] / max(n, 1),
+            "traffic_unit": "bytes per launch", "avg_launch_us": avg * 1e3, "algorithmic_flop_per_launch": fl / max(n, 1),
             "note": "same batch, one stream: the kernel without the other half's kernels beside it"}
 
 
@@ -379,7 +377,7 @@ def main():
                   chunks_per_task=args.chunks_per_task, iters_per_tick=args.iters_per_tick)
     ctx = Context(batch_streams=args.batch_streams, **ctx_kw)
     step_ms, iters_total, mixed_final = [], 0, {}
-    fl_total = {"camblk": 0.0, "pairblk": 0.0}
+    fl_total = {"blocks": 0.0}
     ctx.ba_profile_enable(False)
     for step in range(args.warmup + args.steps):
         timed = step >= args.warmup
@@ -422,11 +420,13 @@ def main():
     iso = measure_isolated(args, Context, ctx_kw, scenes, kw, flops) if args.batch_streams > 1 else None
     value = B / (ms_per_step / 1e3)
 
-    dom = max(("camblk", "pairblk"), key=lambda k: prof[k][0])
+    dom = "blocks"
     asm_ms, asm_n = prof[dom]
     asm_avg_ms = asm_ms / max(asm_n, 1)
     achieved_tflops = fl_total[dom] / max(asm_n, 1) / (asm_avg_ms / 1e3) / 1e12 if asm_n else float("nan")
-    kernels = {k: {"avg_us": (v[0] / max(v[1], 1)) * 1e3, "launches": v[1]} for k, v in prof_all.items()}
+    # (the mixed path has no separate pair-task launch: that slot is empty)
+    kernels = {k: {"avg_us": (v[0] / max(v[1], 1)) * 1e3, "launches": v[1]} for k, v in prof_all.items()
+               if k != "pairblk"}
 
     # ---- plain FP64 GPU LM: one cluster at a time, host-driven ---------------------------
     plain_lat, plain_final = [], {}

@@ -246,8 +246,11 @@ size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
  * per launch.  ba_profile_read adds up the elapsed time and the number of
  * timed launches per kernel since the last read, in the order of
  * enum ba_prof_kernel, into caller arrays of BA_PROF_N entries, and resets
- * the counters.  Errors: BA_E_ARG, BA_E_DEVICE. */
-enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_CAMBLK = 1, BA_PROF_PAIRBLK = 2, BA_PROF_REDUCE = 3,
+ * the counters.  The Schur-block tasks are one launch in BA_MIXED (timed as
+ * BA_PROF_BLOCKS; BA_PROF_PAIRBLK then marks an empty interval) and two in
+ * BA_FP64 (camera tasks as BA_PROF_BLOCKS, pair tasks as BA_PROF_PAIRBLK).
+ * Errors: BA_E_ARG, BA_E_DEVICE. */
+enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_BLOCKS = 1, BA_PROF_PAIRBLK = 2, BA_PROF_REDUCE = 3,
                       BA_PROF_SOLVE = 4, BA_PROF_BACKSUB = 5, BA_PROF_LM = 6, BA_PROF_PCG = 7,
                       BA_PROF_N = 8 };
 #define BA_PROF_ALL ((1 << BA_PROF_N) - 1)

@@ -25,7 +25,10 @@ BA_MAX_OBS_PER_POINT = 64
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error"]
-BA_PROF_KERNELS = ["point", "camblk", "pairblk", "reduce", "solve", "backsub", "lm", "pcg"]
+# Kernel slots of ba_profile_enable / ba_profile_read.  "blocks" is the Schur
+# block launch: camera and pair tasks together in BA_MIXED, camera tasks
+# alone in BA_FP64 (whose pair tasks are "pairblk").
+BA_PROF_KERNELS = ["point", "blocks", "pairblk", "reduce", "solve", "backsub", "lm", "pcg"]
 BA_PROF_ALL = (1 << len(BA_PROF_KERNELS)) - 1
 
 

@@ -159,38 +159,6 @@ __device__ __forceinline__ void rec_store(gptr<double> p, const double* v) {
   for (int i = 0; i < N; i += 2) *reinterpret_cast<gptr<vd2>>(p + i) = vd2{v[i], v[i + 1]};
 }
 
-// Vector LDS rows (16-byte aligned).
-template <int N>
-__device__ __forceinline__ void lds_store(float* p, const float* v) {
-#pragma unroll
-  for (int i = 0; i < N; i += 4) *reinterpret_cast<vf4*>(__builtin_assume_aligned(p + i, 16)) = vf4{v[i], v[i + 1], v[i + 2], v[i + 3]};
-}
-template <int N>
-__device__ __forceinline__ void lds_store(double* p, const double* v) {
-#pragma unroll
-  for (int i = 0; i < N; i += 2) *reinterpret_cast<vd2*>(__builtin_assume_aligned(p + i, 16)) = vd2{v[i], v[i + 1]};
-}
-template <int N>
-__device__ __forceinline__ void lds_load(const float* p, float* v) {
-#pragma unroll
-  for (int i = 0; i < N; i += 4) {
-    const vf4 t = *reinterpret_cast<const vf4*>(__builtin_assume_aligned(p + i, 16));
-    v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
-  }
-}
-template <int N>
-__device__ __forceinline__ void lds_load(const double* p, double* v) {
-#pragma unroll
-  for (int i = 0; i < N; i += 2) {
-    const vd2 t = *reinterpret_cast<const vd2*>(__builtin_assume_aligned(p + i, 16));
-    v[i] = t.x; v[i + 1] = t.y;
-  }
-}
-// Row stride (elements) of the point pass's segmented-sum scratch: a row of
-// up to 16 values per lane, 16-byte aligned, padded so that rows of nearby
-// lanes start on different banks.
-template <typename R> constexpr int seg_stride() { return sizeof(R) == 4 ? 20 : 18; }
-
 // FP32 or FP64 views of the point state and the observed pixels.
 template <typename R> __device__ __forceinline__ gptr<const R> pts_of(const SlotDesc& d, int cur);
 template <> __device__ __forceinline__ gptr<const float> pts_of<float>(const SlotDesc& d, int cur) { return gmem((const float*)d.X32[cur]); }
@@ -664,33 +632,19 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 #pragma unroll
         for (int t = 0; t < 3; ++t) vals[9 + 3 * b + t] = fm(o.Jk[0][b], wJp[0][t], o.Jk[1][b] * wJp[1][t]);
     }
-    // segmented sums over the point's lanes (fixed order: first lane to
-    // last); each lane posts its values as one LDS row, read back with
-    // 16-byte loads
-    constexpr int SS = seg_stride<R>(), NVP = (NV + 3) / 4 * 4;
+    // segmented sums over the point's lanes (fixed order: first lane to last)
     wave_sync();
-    {
-      R row[NVP];
 #pragma unroll
-      for (int i = 0; i < NVP; ++i) row[i] = i < NV ? vals[i] : R(0);
-      lds_store<NVP>(scr + lane * SS, row);
-    }
+    for (int i = 0; i < NV; ++i) scr[i * kWave + lane] = vals[i];
     wave_sync();
     R sum[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) sum[i] = R(0);
     for (int t = 0; t < maxl; ++t) {
       if (t < sl) {
-        const R* src = scr + (sb + t) * SS;
-        constexpr int VW = 16 / sizeof(R);   // values per 16-byte load
+        const int src = sb + t;
 #pragma unroll
-        for (int q = 0; q < NVP; q += VW) {
-          R part[VW];
-          lds_load<VW>(src + q, part);
-#pragma unroll
-          for (int i = 0; i < VW; ++i)
-            if (q + i < NV) sum[q + i] += part[i];
-        }
+        for (int i = 0; i < NV; ++i) sum[i] += scr[i * kWave + src];
       }
     }
     const R Dp[3] = {clampd(sum[0]), clampd(sum[3]), clampd(sum[5])};
@@ -757,7 +711,7 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 // of the intrinsic rows of W, and D_V; per wavefront, the intrinsic-intrinsic
 // sums (U part of all observations, Schur part of all points).
 template <typename R>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 7 : 4))) void k_point(Batch bt) {
+__global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
@@ -773,7 +727,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
   for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) scam[i] = (R)d.cam[cur][i];
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  R* scr = scr_all + wave * seg_stride<R>() * kWave;
+  R* scr = scr_all + wave * 15 * kWave;
   if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true>(d, c, scam, scr, wgl, wave, lane);
   else point_pass<R, false>(d, c, scam, scr, wgl, wave, lane);
 }
@@ -881,19 +835,9 @@ __device__ __forceinline__ void wave_store(float (&acc)[N], float* out, int lane
   if (j >= 0) out[j] = acc[0];
 }
 
+// Camera task t of a cluster (one wavefront).
 template <typename R>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_camblk(Batch bt) {
-  const int bx = xcd_block();
-  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.tkc_off, bt.n_act, bx));
-  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
-  const SlotDesc& d = bt.desc[s];
-  const SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lane = threadIdx.x % kWave;
-  const int t = 0 + (bx - bt.tkc_off[si]) * kWavesPerWG + wave;
-  if (t >= d.n_cam_tasks) return;
+__device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
@@ -980,19 +924,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     wave_store(acc, part, lane);
 }
 
+// Pair task t of a cluster (one wavefront).
 template <typename R>
-__global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
-  const int bx = xcd_block();
-  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
-  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.tkp_off, bt.n_act, bx));
-  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
-  const SlotDesc& d = bt.desc[s];
-  const SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lane = threadIdx.x % kWave;
-  const int t = d.n_cam_tasks + (bx - bt.tkp_off[si]) * kWavesPerWG + wave;
-  if (t >= d.n_tasks) return;
+__device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
@@ -1065,6 +999,73 @@ __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
         for (int cc = 0; cc < 6; ++cc) acc[6 * r + cc] = fm(a0[r], G0[cc], fm(a1[r], G1[cc], acc[6 * r + cc]));
     }
     wave_store(acc, part, lane);
+}
+
+// Slot of logical workgroup b when cluster i owns workgroups
+// [off_a[i] + off_b[i], off_a[i + 1] + off_b[i + 1]).
+__device__ __forceinline__ int find_slot2(const int* __restrict__ off_a, const int* __restrict__ off_b, int n_act,
+                                          int b) {
+  int lo = 0, hi = n_act - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off_a[mid] + off_b[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Camera and pair tasks of every cluster in one launch (the FP32 path): a
+// cluster's workgroups are contiguous, its camera tasks first, so its two
+// kinds of task run side by side on one XCD and read its points through one
+// L2, and the launch has one tail instead of two.
+template <typename R>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_blocks(Batch bt) {
+  const int bx = xcd_block();
+  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
+  const int si = __builtin_amdgcn_readfirstlane(find_slot2(bt.tkc_off, bt.tkp_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
+  const SlotDesc& d = bt.desc[s];
+  const SlotCtl& c = bt.ctl[s];
+  if (c.status != ST_RUNNING) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int loc = bx - (bt.tkc_off[si] + bt.tkp_off[si]);
+  const int ncw = bt.tkc_off[si + 1] - bt.tkc_off[si];
+  if (loc < ncw) {
+    const int t = loc * kWavesPerWG + wave;
+    if (t < d.n_cam_tasks) camblk_task<R>(d, c, t, lane);
+  } else {
+    const int t = d.n_cam_tasks + (loc - ncw) * kWavesPerWG + wave;
+    if (t < d.n_tasks) pairblk_task<R>(d, c, t, lane);
+  }
+}
+
+// The two kinds of task as separate launches (the FP64 path, whose pair tasks
+// need fewer registers than its camera tasks).
+template <typename R>
+__global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
+  const int bx = xcd_block();
+  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
+  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.tkc_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
+  const SlotDesc& d = bt.desc[s];
+  const SlotCtl& c = bt.ctl[s];
+  if (c.status != ST_RUNNING) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int t = (bx - bt.tkc_off[si]) * kWavesPerWG + wave;
+  if (t < d.n_cam_tasks) camblk_task<R>(d, c, t, threadIdx.x % kWave);
+}
+template <typename R>
+__global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
+  const int bx = xcd_block();
+  if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
+  const int si = __builtin_amdgcn_readfirstlane(find_slot(bt.tkp_off, bt.n_act, bx));
+  const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
+  const SlotDesc& d = bt.desc[s];
+  const SlotCtl& c = bt.ctl[s];
+  if (c.status != ST_RUNNING) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int t = d.n_cam_tasks + (bx - bt.tkp_off[si]) * kWavesPerWG + wave;
+  if (t < d.n_tasks) pairblk_task<R>(d, c, t, threadIdx.x % kWave);
 }
 
 // ---- reduction of the task partials into the packed reduced system ----------------
@@ -2172,7 +2173,7 @@ __global__ void k_export(Batch bt) {
 
 template <typename R>
 size_t point_smem(const Batch& b) {
-  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * seg_stride<R>() * kWave);
+  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * 15 * kWave);
 }
 
 template <typename R>
@@ -2266,17 +2267,20 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
     if (mixed) launch(k_point<float>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
     else launch(k_point<double>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
   }
-  if (b.total_tkc_wg > 0 || evk(1)) {
-    const Batch& bb = b.total_tkc_wg > 0 ? b : nob;
-    const dim3 g(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1);
-    if (mixed) launch(k_camblk<float>, g, dim3(kWG), 0, st, evk(1), 1, bb);
-    else launch(k_camblk<double>, g, dim3(kWG), 0, st, evk(1), 1, bb);
-  }
-  if (b.total_tkp_wg > 0 || evk(2)) {
-    const Batch& bb = b.total_tkp_wg > 0 ? b : nob;
-    const dim3 g(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1);
-    if (mixed) launch(k_pairblk<float>, g, dim3(kWG), 0, st, evk(2), 2, bb);
-    else launch(k_pairblk<double>, g, dim3(kWG), 0, st, evk(2), 2, bb);
+  if (mixed) {
+    // camera and pair tasks in one launch (slot 1); slot 2 marks an empty interval
+    const int nwg = b.total_tkc_wg + b.total_tkp_wg;
+    if (nwg > 0 || evk(1)) launch(k_blocks<float>, dim3(nwg > 0 ? nwg : 1), dim3(kWG), 0, st, evk(1), 1, nwg > 0 ? b : nob);
+    if (evk(2) && ((e = hipEventRecord(ev_all[4], st)) || (e = hipEventRecord(ev_all[5], st)))) return e;
+  } else {
+    if (b.total_tkc_wg > 0 || evk(1)) {
+      const Batch& bb = b.total_tkc_wg > 0 ? b : nob;
+      launch(k_camblk<double>, dim3(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1), dim3(kWG), 0, st, evk(1), 1, bb);
+    }
+    if (b.total_tkp_wg > 0 || evk(2)) {
+      const Batch& bb = b.total_tkp_wg > 0 ? b : nob;
+      launch(k_pairblk<double>, dim3(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1), dim3(kWG), 0, st, evk(2), 2, bb);
+    }
   }
   if (b.total_tg > 0 || evk(3)) {
     const Batch& bb = b.total_tg > 0 ? b : nob;
