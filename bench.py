@@ -337,7 +337,7 @@ def main():
     ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
     ap.add_argument("--batch-streams", type=int, default=2,
                     help="streams a batch is split across (1: one stream, no overlap)")
-    ap.add_argument("--iters-per-tick", type=int, default=4,
+    ap.add_argument("--iters-per-tick", type=int, default=10,
                     help="LM iterations launched between control read-backs (batched context)")
     ap.add_argument("--uneven", type=int, default=256,
                     help="clusters of the uneven batched workload (6-24 cameras, 5k-60k points; 0: skip)")

@@ -91,6 +91,8 @@ enum ba_solve_status {
   BA_ST_BAD_INIT = 5    /* the initial state has a point at non-positive depth */
 };
 
+/* Context options.  A count or tolerance of 0 selects its default; a negative
+ * one makes ba_create return BA_E_ARG. */
 typedef struct {
   int32_t device;            /* HIP device ordinal */
   void* stream;              /* hipStream_t to run on (e.g. torch.cuda.current_stream().cuda_stream);

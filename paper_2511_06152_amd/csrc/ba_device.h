@@ -41,9 +41,9 @@ struct SlotDesc {
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
   // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
   const int* lane_pt;                     // [L] point index, -1 for padding
-  const int* lane_cam;                    // [L] camera index
-  const int* lane_seg;                    // [L] chunk's longest segment << 16 | first lane of the point's
-                                          //     segment in the chunk << 8 | its length
+  const int* lane_meta;                   // [L] camera index (bits 0-8) | first lane of the point's
+                                          //     segment in the chunk << 9 | its length << 15 |
+                                          //     the chunk's longest segment << 22
   double* lane_uv64;                      // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
   float* lane_uv32;                       // [2L]
   // camera lanes: observations of free cameras sorted by (camera, point), each

@@ -58,6 +58,14 @@ __device__ __forceinline__ int xcd_block() {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
 }
 
+// Observation lanes of chunk ch: one lane word holds the camera (bits 0-8),
+// the first lane of the point's segment (9-14), its length (15-21) and the
+// chunk's longest segment (22-28).
+__device__ __forceinline__ int meta_cam(int m) { return m & 511; }
+__device__ __forceinline__ int seg_first(int m) { return (m >> 9) & 63; }
+__device__ __forceinline__ int seg_len(int m) { return (m >> 15) & 127; }
+__device__ __forceinline__ int chunk_maxlen(int m) { return __builtin_amdgcn_readfirstlane((m >> 22) & 127); }
+
 // Packed storage of a symmetric matrix: element (r, c), r <= c.
 __device__ __forceinline__ int pidx(int r, int c) { return c * (c + 1) / 2 + r; }
 
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(kWG) void k_cost0(Batch bt) {
     const int idx = ch * kWave + lane;
     const int pt = d.lane_pt[idx];
     if (pt >= 0) {
-      const int cam = d.lane_cam[idx];
+      const int cam = meta_cam(d.lane_meta[idx]);
       const double X[3] = {d.X[cur][3 * pt], d.X[cur][3 * pt + 1], d.X[cur][3 * pt + 2]};
       double rho;
       if (obs_rho(sh_cam + kCamVals * cam, X, d.lane_uv64[2 * idx], d.lane_uv64[2 * idx + 1], d.f, k1, k2,
@@ -568,11 +576,6 @@ __global__ void k_init(Batch bt) {
 // of one wavefront.  Writes, per point, Q = (V + lambda D_V)^-1, g_p, D_V and
 // Z = sum of the intrinsic rows of W; per wavefront, the intrinsic-intrinsic
 // sums (U part of all observations, Schur part of all points).
-// Observation lanes of chunk ch: seg = first lane of the point's segment << 8 |
-// its length, with the chunk's longest segment in bits 16..23.
-__device__ __forceinline__ int seg_first(int seg) { return (seg >> 8) & 255; }
-__device__ __forceinline__ int seg_len(int seg) { return seg & 255; }
-__device__ __forceinline__ int chunk_maxlen(int seg) { return __builtin_amdgcn_readfirstlane((seg >> 16) & 255); }
 
 template <typename R, bool INTR>
 __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const R* scam, R* scr, int wgl, int wave,
@@ -583,24 +586,24 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
   const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
   const gptr<R> ptv = gmem(reinterpret_cast<R*>(d.ptv)), ptd = gmem(reinterpret_cast<R*>(d.ptd));
-  const gptr<const int> lpt = gmem(d.lane_pt), lcam = gmem(d.lane_cam), lseg = gmem(d.lane_seg);
+  const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
   const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.lane_uv64, d.lane_uv32);
   R iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // S(k0k0) S(k0k1) S(k1k1) g0 g1 dU0 dU1 bS0 bS1
   bool fail = false;
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
   // The lane words of the next chunk are requested a chunk ahead; loads are
   // unconditional (padding lanes read point 0, then zero what they read).
-  int pt_n = 0, cam_n = 0, seg_n = 0;
+  int pt_n = 0, meta_n = 0;
   if (c0 + wave < c1) {
     const int i0 = (c0 + wave) * kWave + lane;
-    pt_n = lpt[i0]; cam_n = lcam[i0]; seg_n = lseg[i0];
+    pt_n = lpt[i0]; meta_n = lmeta[i0];
   }
   for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
     const int idx = ch * kWave + lane;
-    const int pt = pt_n, cam_l = cam_n, seg = seg_n;
+    const int pt = pt_n, seg = meta_n, cam_l = meta_cam(seg);
     if (ch + kWavesPerWG < c1) {
       const int in = idx + kWavesPerWG * kWave;
-      pt_n = lpt[in]; cam_n = lcam[in]; seg_n = lseg[in];
+      pt_n = lpt[in]; meta_n = lmeta[in];
     }
     const bool valid = pt >= 0;
     const int cam = valid ? cam_l : 0, ps = valid ? pt : 0;
@@ -1184,6 +1187,8 @@ constexpr int kTbS = kSolveTb + 1;              // LDS row stride of a block (do
 constexpr int kTbV = kSolveTb * kTbS;           // doubles per block
 constexpr int kSolveWk = 2 * kSolveTb * kSolveTb + kSolveTb;   // factor scratch + solve vector
 constexpr size_t kSolveLdsCap = 150 * 1024;
+static_assert(kSolveTb * ((6 * kMaxFreeCams + 2 + kSolveTb - 1) / kSolveTb) <= kSolveWG,
+              "one thread per unknown of the padded system in the solve's load");
 
 // LDS doubles of the solve kernel for a batch whose largest system has nbm
 // blocks per side, without and with the refinement copy.  Every cluster of the
@@ -1419,6 +1424,10 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   const int pcol = tid < d.C ? d.cam_col[tid] : -1;
   __asm__ volatile("" ::: "memory");
   fetch(0);
+  // gradient, bS and diag U of unknown tid (np <= 160 < kSolveWG), in the same batch
+  const bool vreal = tid < m;
+  const double g0 = vreal ? Sg[psize + tid] : 0.0, b0v = vreal ? Sg[psize + m + tid] : 0.0,
+               d0 = vreal ? Sg[psize + 2 * m + tid] : 0.0;
   double pe[6], pJ[9];
   if (pcol >= 0) prior_terms(pcam, ppr, pe, pJ);
   put(0);
@@ -1426,11 +1435,10 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     fetch(b0);
     put(b0);
   }
-  for (int p = tid; p < np; p += kSolveWG) {
-    const bool real = p < m;
-    gv[p] = real ? Sg[psize + p] : 0.0;
-    xv[p] = real ? Sg[psize + m + p] : 0.0;     // bS for now
-    Dv[p] = real ? Sg[psize + 2 * m + p] : 0.0; // diag U for now
+  if (tid < np) {
+    gv[tid] = g0;
+    xv[tid] = b0v;   // bS for now
+    Dv[tid] = d0;    // diag U for now
   }
   if (tid == 0) ok = (c.point_fail == 0);
   __syncthreads();
@@ -1989,7 +1997,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const int kc0 = d.kcol0, kc1 = d.kcol1;
   const R dk0 = kc0 >= 0 ? sdc[kc0] : R(0), dk1 = kc1 >= 0 ? sdc[kc1] : R(0);
   const gptr<const R> ptv = gmem(reinterpret_cast<const R*>(d.ptv)), ptd = gmem(reinterpret_cast<const R*>(d.ptd));
-  const gptr<const int> lpt = gmem(d.lane_pt), lcam = gmem(d.lane_cam), lseg = gmem(d.lane_seg);
+  const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
   const gptr<const double> Xc = gmem((const double*)d.X[cur]), uv64 = gmem((const double*)d.lane_uv64);
   const gptr<double> Xn64 = gmem(d.X[nxt]);
   const gptr<float> Xn32 = gmem(d.X32[nxt]);
@@ -1998,17 +2006,17 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
   // The lane words of the next chunk are requested a chunk ahead; loads are
   // unconditional (padding lanes read point 0 and do not use it).
-  int pt_n = 0, cam_n = 0, seg_n = 0;
+  int pt_n = 0, meta_n = 0;
   if (c0 + wave < c1) {
     const int i0 = (c0 + wave) * kWave + lane;
-    pt_n = lpt[i0]; cam_n = lcam[i0]; seg_n = lseg[i0];
+    pt_n = lpt[i0]; meta_n = lmeta[i0];
   }
   for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
     const int idx = ch * kWave + lane;
-    const int pt = pt_n, cam_l = cam_n, seg = seg_n;
+    const int pt = pt_n, seg = meta_n, cam_l = meta_cam(seg);
     if (ch + kWavesPerWG < c1) {
       const int in = idx + kWavesPerWG * kWave;
-      pt_n = lpt[in]; cam_n = lcam[in]; seg_n = lseg[in];
+      pt_n = lpt[in]; meta_n = lmeta[in];
     }
     const bool valid = pt >= 0;
     const int cam = valid ? cam_l : 0, ps = valid ? pt : 0;

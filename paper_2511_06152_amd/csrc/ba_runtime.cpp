@@ -81,7 +81,7 @@ struct Staged {
   std::vector<double> X;         // [3P] internal point order
   std::vector<int> pt_orig;      // [P] caller index of each internal point
   std::vector<int> cam_col;      // [C]
-  std::vector<int> lane_pt, lane_cam, lane_seg;
+  std::vector<int> lane_pt, lane_meta;
   std::vector<double> lane_uv;   // [2L]
   int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
   std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
@@ -97,7 +97,7 @@ struct Staged {
 };
 
 struct Layout {                  // byte offsets inside a slot block
-  size_t lane_pt, lane_cam, lane_seg, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
+  size_t lane_pt, lane_meta, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, out, total;
@@ -114,8 +114,7 @@ Layout make_layout(const Staged& s, bool mixed) {
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
   l.lane_pt = take(4 * (size_t)s.L);
-  l.lane_cam = take(4 * (size_t)s.L);
-  l.lane_seg = take(4 * (size_t)s.L);
+  l.lane_meta = take(4 * (size_t)s.L);
   l.uv64 = take(16 * (size_t)s.L);
   l.uv32 = take(8 * (size_t)s.L);
   l.cl_pt = take(4 * (size_t)s.Lc);
@@ -303,24 +302,24 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   s.L = (int)align_up(pos, kWave);
   s.n_chunks = s.L / kWave;
   s.lane_pt.assign(s.L, -1);
-  s.lane_cam.assign(s.L, 0);
-  s.lane_seg.resize(s.L);
+  // lane word: camera (9 bits) | segment start in the chunk << 9 (6 bits) |
+  // segment length << 15 (7 bits) | the chunk's longest segment << 22 (7 bits)
+  s.lane_meta.resize(s.L);
   s.lane_uv.assign(2 * (size_t)s.L, 0.0);
-  for (int i = 0; i < s.L; ++i) s.lane_seg[i] = ((i % kWave) << 8) | 1;
+  for (int i = 0; i < s.L; ++i) s.lane_meta[i] = ((i % kWave) << 9) | (1 << 15);
   std::vector<int> chunk_max(s.n_chunks, 1);
   for (int j = 0; j < P; ++j) {
     const int n = cnt[j + 1] - cnt[j];
     for (int t = 0; t < n; ++t) {
       const int o = order[cnt[j] + t], lane = start[j] + t;
       s.lane_pt[lane] = j;
-      s.lane_cam[lane] = c->obs_cam[o];
-      s.lane_seg[lane] = ((start[j] % kWave) << 8) | n;
+      s.lane_meta[lane] = c->obs_cam[o] | ((start[j] % kWave) << 9) | (n << 15);
       chunk_max[lane / kWave] = std::max(chunk_max[lane / kWave], n);
       s.lane_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
       s.lane_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
     }
   }
-  for (int i = 0; i < s.L; ++i) s.lane_seg[i] |= chunk_max[i / kWave] << 16;
+  for (int i = 0; i < s.L; ++i) s.lane_meta[i] |= chunk_max[i / kWave] << 22;
   s.n_wg = (s.n_chunks + cpw - 1) / cpw;
   const bool intr = s.kcol0 >= 0 || s.kcol1 >= 0;
   s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
@@ -726,8 +725,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.sparse = s.sparse; d.nnzb = (int)s.bcol.size();
   d.pcg_max_iters = c->opt.pcg_max_iters; d.pcg_tol = c->opt.pcg_tol;
   d.lane_pt = (const int*)(base + lay.lane_pt);
-  d.lane_cam = (const int*)(base + lay.lane_cam);
-  d.lane_seg = (const int*)(base + lay.lane_seg);
+  d.lane_meta = (const int*)(base + lay.lane_meta);
   d.lane_uv64 = (double*)(base + lay.uv64);
   d.lane_uv32 = (float*)(base + lay.uv32);
   d.cl_pt = (const int*)(base + lay.cl_pt);
@@ -788,8 +786,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.out = (double*)(base + lay.out);
   hipStream_t st = c->stream;
   HIPCHK(c, hipMemcpyAsync(base + lay.lane_pt, s.lane_pt.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
-  HIPCHK(c, hipMemcpyAsync(base + lay.lane_cam, s.lane_cam.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
-  HIPCHK(c, hipMemcpyAsync(base + lay.lane_seg, s.lane_seg.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(base + lay.lane_meta, s.lane_meta.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(base + lay.uv64, s.lane_uv.data(), 16 * (size_t)s.L, hipMemcpyHostToDevice, st));
   if (s.Lc) {
     HIPCHK(c, hipMemcpyAsync(base + lay.cl_pt, s.cl_pt.data(), 4 * (size_t)s.Lc, hipMemcpyHostToDevice, st));
@@ -1139,6 +1136,11 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (!opt || !out) return BA_E_ARG;
   *out = nullptr;
   if (opt->precision != BA_FP64 && opt->precision != BA_MIXED) return BA_E_ARG;
+  // 0 selects a field's default; a negative count is an error
+  if (opt->max_slots < 0 || opt->max_queue < 0 || opt->iters_per_tick < 0 || opt->chunks_per_wg < 0 ||
+      opt->chunks_per_task < 0 || opt->pcg_max_iters < 0 || opt->pcg_tol < 0 || opt->resident_cams < 0 ||
+      opt->resident_points < 0)
+    return BA_E_ARG;
   auto c = std::make_unique<ba_ctx>();
   c->opt = *opt;
   if (c->opt.hbm_budget_bytes == 0) c->opt.hbm_budget_bytes = (size_t)1 << 30;

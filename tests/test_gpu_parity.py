@@ -283,6 +283,16 @@ def test_invalid_inputs_are_rejected():
             ctx.submit(base, max_iters=0)
 
 
+@pytest.mark.parametrize("kw", [dict(batch_streams=5), dict(batch_streams=-1), dict(iters_per_tick=-3),
+                                dict(max_slots=-1), dict(chunks_per_task=-2), dict(precision=7), dict(solver=9),
+                                dict(pcg_tol=2.0)])
+def test_invalid_options_are_rejected(kw):
+    from paper_2511_06152_amd import BAError, Context
+    with pytest.raises(BAError) as e:
+        Context(**kw)
+    assert e.value.code == -1
+
+
 def test_bad_initial_depth_is_reported():
     from paper_2511_06152_amd import Context
     sc = A.make_scene(A.spec_micro(n_points=30), 81)
