@@ -838,9 +838,11 @@ __device__ __forceinline__ void wave_store(float (&acc)[N], float* out, int lane
   if (j >= 0) out[j] = acc[0];
 }
 
-// Camera task t of a cluster (one wavefront).
-template <typename R>
-__device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
+// Camera task t of a cluster (one wavefront).  INTR: at least one of k1, k2
+// is estimated; both borders are then summed (the reduction writes only the
+// estimated ones).
+template <typename R, bool INTR>
+__device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
@@ -853,15 +855,15 @@ __device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c,
   load_cam(d.cam[cur] + kCamVals * ka, ca);
   (void)kb;
 
-    const bool i0 = d.kcol0 >= 0, i1 = d.kcol1 >= 0;
     const gptr<const int> cl_pt = gmem(d.cl_pt);
     const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.cl_uv64, d.cl_uv32), recs = gmem(ptv);
     R acc[51];
 #pragma unroll
     for (int i = 0; i < 51; ++i) acc[i] = R(0);
-    // Loads are unconditional (padding lanes read point 0, then zero what
-    // they read), and the next chunk's point index is requested a chunk
-    // ahead.
+    // Loads are unconditional: padding lanes read point 0 (finite state and
+    // record; their pixel is 0) and the observation model gives them weight
+    // 0, which zeroes every term they add.  The next chunk's point index is
+    // requested a chunk ahead.
     const int ch_end = tk.y + tk.z;
     int pt_next = cl_pt[tk.y * kWave + lane];
     for (int ch = tk.y; ch < ch_end; ++ch) {
@@ -870,13 +872,9 @@ __device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c,
       if (ch + 1 < ch_end) pt_next = cl_pt[idx + kWave];
       const bool valid = pt >= 0;
       const int ps = valid ? pt : 0;
-      const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2], ur = uvs[2 * idx], vr = uvs[2 * idx + 1];
+      const R X0 = Xs[3 * ps], X1 = Xs[3 * ps + 1], X2 = Xs[3 * ps + 2], u = uvs[2 * idx], v = uvs[2 * idx + 1];
       R rec[kPtVals];
       rec_load<kPtVals>(recs + kPtVals * (size_t)ps, rec);
-      const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
-      const R u = valid ? ur : R(0), v = valid ? vr : R(0);
-#pragma unroll
-      for (int i = 0; i < kPtVals; ++i) rec[i] = valid && (i < 12 || i0 || i1) ? rec[i] : R(0);
       ObsJ<R> o;
       obs_model<R>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
       const R* Q = rec;
@@ -899,7 +897,7 @@ __device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c,
       R vk[2][2] = {{0, 0}, {0, 0}};   // [intrinsic][row]
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        if (q == 0 ? !i0 : !i1) continue;
+        if (!INTR) continue;
         const R* z = rec + 9 + 3 * q;
 #pragma unroll
         for (int a = 0; a < 2; ++a) vk[q][a] = w * (o.Jk[a][q] - fm(T[a][2], z[2], fm(T[a][1], z[1], T[a][0] * z[0])));
@@ -920,11 +918,19 @@ __device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c,
         acc[21 + r] = fm(a0[r], ve0, fm(a1[r], ve1, acc[21 + r]));
         acc[27 + r] = fm(a0[r], vg0, fm(a1[r], vg1, acc[27 + r]));
         acc[33 + r] = fm(w * a0[r], a0[r], fm(w * a1[r], a1[r], acc[33 + r]));
-        if (i0) acc[39 + r] = fm(a0[r], vk[0][0], fm(a1[r], vk[0][1], acc[39 + r]));
-        if (i1) acc[45 + r] = fm(a0[r], vk[1][0], fm(a1[r], vk[1][1], acc[45 + r]));
+        if (INTR) {
+          acc[39 + r] = fm(a0[r], vk[0][0], fm(a1[r], vk[0][1], acc[39 + r]));
+          acc[45 + r] = fm(a0[r], vk[1][0], fm(a1[r], vk[1][1], acc[45 + r]));
+        }
       }
     }
     wave_store(acc, part, lane);
+}
+
+template <typename R>
+__device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
+  if (d.kcol0 >= 0 || d.kcol1 >= 0) camblk_task_k<R, true>(d, c, t, lane);
+  else camblk_task_k<R, false>(d, c, t, lane);
 }
 
 // Pair task t of a cluster (one wavefront).
@@ -948,9 +954,10 @@ __device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c
     R acc[36];
 #pragma unroll
     for (int i = 0; i < 36; ++i) acc[i] = R(0);
-    // Loads are unconditional (padding lanes read point 0, then zero what
-    // they read), and the next chunk's point index is requested a chunk
-    // ahead.
+    // Loads are unconditional: padding lanes read point 0 (finite state and
+    // record; their pixels are 0) and the observation model gives them weight
+    // 0, which zeroes every term they add.  The next chunk's point index is
+    // requested a chunk ahead.
     const int ch_end = tk.y + tk.z;
     int pt_next = ql_pt[tk.y * kWave + lane];
     for (int ch = tk.y; ch < ch_end; ++ch) {
@@ -959,14 +966,10 @@ __device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c
       if (ch + 1 < ch_end) pt_next = ql_pt[idx + kWave];
       const bool valid = pt >= 0;
       const int ps = valid ? pt : 0;
-      const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2];
-      const R uar = uvs[4 * idx], var = uvs[4 * idx + 1], ubr = uvs[4 * idx + 2], vbr = uvs[4 * idx + 3];
+      const R X0 = Xs[3 * ps], X1 = Xs[3 * ps + 1], X2 = Xs[3 * ps + 2];
+      const R ua = uvs[4 * idx], va = uvs[4 * idx + 1], ub = uvs[4 * idx + 2], vb = uvs[4 * idx + 3];
       R Q[8];
       rec_load<sizeof(R) == 8 ? 6 : 8>(recs + kPtVals * (size_t)ps, Q);
-      const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
-      const R ua = valid ? uar : R(0), va = valid ? var : R(0), ub = valid ? ubr : R(0), vb = valid ? vbr : R(0);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Q[i] = valid && i < (sizeof(R) == 8 ? 6 : 8) ? Q[i] : R(0);
       // -Y_a W_b^T = J_ca^T M J_cb with the 2x2 M = -w_a w_b J_pa Q J_pb^T.
       R a0[6], a1[6], T[2][3], wa;
       {
