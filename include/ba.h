@@ -76,7 +76,7 @@ enum ba_precision {
 
 enum ba_solver {
   BA_SOLVER_AUTO = 0,   /* dense Cholesky up to BA_MAX_FREE_CAMS free cameras, PCG above */
-  BA_SOLVER_DENSE = 1,  /* 6x6-block FP64 Cholesky of the reduced camera system */
+  BA_SOLVER_DENSE = 1,  /* FP64 Cholesky of the reduced camera system in 16x16 blocks */
   BA_SOLVER_PCG = 2     /* conjugate gradients on the block-sparse reduced camera system,
                            block-Jacobi 6x6 preconditioner; FP32 matrix-vector products in
                            BA_MIXED, FP64 dot products and updates; no estimated intrinsics */

@@ -1,23 +1,28 @@
 // HIP kernels (gfx950) of the cluster bundle-adjustment library.
 //
-// One Levenberg-Marquardt iteration over a batch of resident clusters is seven
-// launches, each covering every cluster of the batch:
+// One Levenberg-Marquardt iteration over a batch of resident clusters is six
+// launches in the mixed path (seven in the plain FP64 path), each covering
+// every cluster of the batch:
 //
 //   k_point<Real>     per observation: residual of Eq. (5) with k1/k2 radial
 //                     terms, Huber IRLS weight (robust rho of Eq. 6/7), point
 //                     Jacobian; per point (wavefront-segmented sum): V_j, g_j
 //                     and the damped inverse
-//   k_camblk<Real>,   one wavefront per task: a free camera's diagonal Schur
-//   k_pairblk<Real>   block (U_kk - sum W Q W^T, gradient, intrinsic border)
-//                     over its observations, or one camera-pair block
+//   k_blocks<float>   one wavefront per task: a free camera's diagonal Schur
+//   (k_camblk<double>, block (U_kk - sum W Q W^T, gradient, intrinsic border)
+//    k_pairblk<double>) over its observations, or one camera-pair block
 //                     (- sum W_a Q W_b^T) over the observation pairs of that
 //                     pair of cameras; register sums, fixed-order reductions
 //   k_reduce<Real>    per target block: fixed-order sum of its task partials
 //                     into the packed reduced camera system, in FP64
 //   k_solve           one workgroup per cluster: pose priors, Marquardt
-//                     damping, FP64 6x6-block Cholesky of the reduced camera
-//                     system, triangular solves (+ one FP64 refinement step in
-//                     mixed mode), trial camera poses and prior cost
+//                     damping, FP64 Cholesky of the reduced camera system in
+//                     16x16 blocks (matrix-core panel and trailing updates),
+//                     triangular solves (+ one FP64 refinement step in mixed
+//                     mode), trial camera poses and prior cost
+//   k_pcg             (large systems instead of k_solve) block-Jacobi
+//                     preconditioned conjugate gradients on the block-sparse
+//                     reduced system
 //   k_backsub<Real>   per point back-substitution, trial points, and the FP64
 //                     trial cost of every observation
 //   k_lm              gain ratio, accept/reject, Nielsen damping update,
