@@ -67,12 +67,12 @@ TRAFFIC = {
     "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "blocks"): (92368.2, 4797.7),
-        (1, "blocks"): (176926.4, 9605.2),
+        (2, "blocks"): (91093.1, 2386.1),
+        (1, "blocks"): (174431.9, 4783.6),
     },
     "sources_sha256": {
-        "ba_kernels.hip": "8aa417da2c2bc6360feb5bbd5931576dd0264d3381b70fe51c050a54a9c5acb2",
-        "ba_device.h": "4066bd56a0cec3317ceabc2575ba26c5a89c721fbff1d9b60177cffe51f6ea3d",
+        "ba_kernels.hip": "6c800aa1d90884f692d4e3fbc138eb2cf4b745c74d2a27b6fdf3158c55d4dcc0",
+        "ba_device.h": "0af29ef79b2bf33278eaf53eb0e033d7faefd1431761b8d6e337b071c1419b33",
     },
 }
 
