@@ -67,12 +67,12 @@ TRAFFIC = {
     "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "blocks"): (91093.1, 2386.1),
-        (1, "blocks"): (174431.9, 4783.6),
+        (2, "blocks"): (91038.4, 2385.7),
+        (1, "blocks"): (173850.7, 4782.2),
     },
     "sources_sha256": {
-        "ba_kernels.hip": "6c800aa1d90884f692d4e3fbc138eb2cf4b745c74d2a27b6fdf3158c55d4dcc0",
-        "ba_device.h": "0af29ef79b2bf33278eaf53eb0e033d7faefd1431761b8d6e337b071c1419b33",
+        "ba_kernels.hip": "6ce0af57522b915fcf3cc503c4b96337078a24ead20c1be3c004871b0882e4c7",
+        "ba_device.h": "7816f47f3954da6c8b99a3f87488d3050511d7fadfe938f2925dd6c9a2c19734",
     },
 }
 
@@ -250,8 +250,10 @@ def run_stream(args, Context, precision, kw):
     image triggering a sliding cluster of 8-20 images over one global
     tie-point pool.  Clusters go to the continuous-batching loop with resident
     state keyed by image and point IDs (each starts from the state the clusters
-    before it left, in submission order), closed loop with a fixed number in
-    flight.  Latency = submit -> result available."""
+    before it left, in submission order; free images already solved by an
+    earlier cluster are written back by the match-count weighted pose fusion
+    of Eq. (8)), closed loop with a fixed number in flight.  Latency =
+    submit -> result available."""
     from collections import deque
     from paper_2511_06152_amd.ba import Cluster
     t_gen = time.perf_counter()
@@ -279,7 +281,7 @@ def run_stream(args, Context, precision, kw):
         for sc in cl:
             while len(pending) >= W:
                 retire()
-            t = ctx.submit(sc, use_resident=True, **kw)
+            t = ctx.submit(sc, use_resident=True, fuse_resident=True, **kw)
             ctx.ba_solve(t)
             pending.append(t)
         while pending:

@@ -160,10 +160,24 @@ typedef struct {
    *    overlapping clusters run in submission order;
    *  - when it finishes (any status but BA_ST_BAD_INIT) its final poses and
    *    points are written back under their IDs, on the device.
-   * With use_resident = 0 the IDs are ignored and nothing is read or written. */
+   * With use_resident = 0 the IDs are ignored and nothing is read or written.
+   *
+   * fuse_resident = 1 (with use_resident) writes the poses back by the pose
+   * fusion of Sec. 3.2, Eq. (8): a free camera whose ID already holds a pose
+   * written back by an earlier cluster gets the weighted mean of that pose and
+   * this cluster's, the weights being match counts: this cluster's
+   * observations of the camera, and the accumulated weight stored with the
+   * earlier pose.  Positions are averaged linearly; rotations along the
+   * geodesic, R = R_old Exp(w_new / (w_old + w_new) Log(R_old^T R_new)).
+   * The stored weight becomes w_old + w_new.  Fixed cameras (the retained
+   * first half of the overlap) and cameras seen for the first time are
+   * written back as solved, with weight w_new; points are always written back
+   * as solved.  ba_fetch returns the cluster's own solution, not the fused
+   * poses (see ba_resident_poses). */
   const int64_t* cam_ids;       /* [C] or NULL (required with use_resident) */
   const int64_t* point_ids;     /* [P] or NULL (required with use_resident) */
   int32_t use_resident;
+  int32_t fuse_resident;
 } ba_cluster;
 
 /* Results (ba_fetch).  Every pointer may be NULL (not written). */
@@ -236,6 +250,15 @@ int ba_fetch(ba_ctx* ctx, ba_ticket ticket, ba_result* result);
 /* Forget a ticket and free its slot and arena block.  Errors: BA_E_ARG,
  * BA_E_STATE (being solved by the serving loop). */
 int ba_release(ba_ctx* ctx, ba_ticket ticket);
+
+/* The device-resident poses of n camera IDs (world frame, as last written
+ * back; with fuse_resident, the fused poses of Eq. (8)), copied to host
+ * arrays R [9n] (row-major, camera->world), T [3n] and w [n] (the stored
+ * match-count weight); w may be NULL.  Waits for the library's streams.
+ * Errors: BA_E_ARG (NULL arrays, n < 0, or an ID never written back),
+ * BA_E_STATE (an ID has a pending writer: a submitted cluster holding it has
+ * not finished), BA_E_DEVICE. */
+int ba_resident_poses(ba_ctx* ctx, int32_t n, const int64_t* cam_ids, double* R, double* T, double* w);
 
 /* Bytes of arena the cluster would take once admitted (its admission
  * footprint), or 0 if the cluster is invalid. */

@@ -7,6 +7,9 @@ HIP library.
 
 A scene is the dict produced by ``synth.aerial.make_scene``; a state is the
 tuple (R[C,3,3], T[C,3], X[P,3], k[2]).
+
+The pose fusion between successive clusters (:func:`fuse_pose`, Sec. 3.2,
+Eq. (8)) is plain numpy in this module.
 """
 from __future__ import annotations
 
@@ -212,3 +215,59 @@ def solve(sc, state=None, max_iters: int = 10, lambda0: float = 1e-4, ftol: floa
             "rho_log": rho_log[:n], "accepted_log": acc_log[:n], "iterations": n,
             "accepted": st.accepted, "rejected": st.rejected, "status": st.status,
             "lambda": st.lambda_, "nu": st.nu}
+
+
+# --- Pose fusion between successive clusters (Sec. 3.2, Eq. (8)) -----------
+# Eq. (8) averages the overlapping image's pose from the previous and the new
+# cluster with match-count weights.  Positions are averaged as written; a
+# weighted mean of two rotations is taken on SO(3), i.e. the point at fraction
+# w_new / (w_old + w_new) along the geodesic from the old to the new rotation
+# (a linear mean of rotation matrices is not a rotation).
+
+def so3_log(R) -> np.ndarray:
+    """Rotation vector (unit axis times angle in [0, pi]) of a rotation matrix."""
+    R = np.asarray(R, np.float64)
+    c = np.clip(0.5 * (np.trace(R) - 1.0), -1.0, 1.0)      # cos(theta)
+    v = 0.5 * np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])  # sin(theta) * axis
+    s = np.linalg.norm(v)
+    theta = np.arctan2(s, c)
+    if theta < 1e-8:
+        return v * (1.0 + theta * theta / 6.0)
+    if np.pi - theta < 1e-6:
+        # The symmetric part of R is cos(theta) I + (1 - cos(theta)) a a^T:
+        # the axis from the column of (R + R^T) / 2 - cos(theta) I with the
+        # largest diagonal entry, its sign from the skew part.
+        B = 0.5 * (R + R.T) - c * np.eye(3)
+        j = int(np.argmax(np.diag(B)))
+        a = B[:, j] / np.linalg.norm(B[:, j])
+        if a @ v < 0:
+            a = -a
+        return theta * a
+    return theta * v / s
+
+
+def so3_exp(w) -> np.ndarray:
+    """Rotation matrix of a rotation vector (Rodrigues' formula)."""
+    w = np.asarray(w, np.float64)
+    theta = np.linalg.norm(w)
+    K = np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+    if theta < 1e-12:
+        return np.eye(3) + K
+    K /= theta
+    return np.eye(3) + np.sin(theta) * K + (1.0 - np.cos(theta)) * (K @ K)
+
+
+def fuse_pose(R_old, T_old, w_old, R_new, T_new, w_new):
+    """Eq. (8) for one camera: the match-count weighted mean of the pose left
+    by the earlier cluster (weight w_old) and the new cluster's (w_new).
+    Returns (R, T, w_old + w_new); with w_old <= 0 there is nothing to average
+    and the new pose is returned with weight w_new."""
+    R_old, R_new = np.asarray(R_old, np.float64), np.asarray(R_new, np.float64)
+    T_old, T_new = np.asarray(T_old, np.float64), np.asarray(T_new, np.float64)
+    if w_old <= 0:
+        return R_new.copy(), T_new.copy(), float(w_new)
+    wsum = float(w_old) + float(w_new)
+    a = float(w_new) / wsum
+    R = R_old @ so3_exp(a * so3_log(R_old.T @ R_new))
+    T = (w_old * T_old + w_new * T_new) / wsum
+    return R, T, wsum

@@ -24,7 +24,7 @@ BA_MAX_OBS_PER_POINT = 64
 
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
-            "ba_last_error"]
+            "ba_last_error", "ba_resident_poses"]
 # Kernel slots of ba_profile_enable / ba_profile_read.  "blocks" is the Schur
 # block launch: camera and pair tasks together in BA_MIXED, camera tasks
 # alone in BA_FP64 (whose pair tasks are "pairblk").
@@ -50,7 +50,8 @@ class ba_cluster(ct.Structure):
                 ("sigma_px", ct.c_double), ("huber_delta", ct.c_double),
                 ("max_iters", ct.c_int32), ("stop_on_ftol", ct.c_int32),
                 ("lambda0", ct.c_double), ("ftol", ct.c_double),
-                ("cam_ids", ct.c_void_p), ("point_ids", ct.c_void_p), ("use_resident", ct.c_int32)]
+                ("cam_ids", ct.c_void_p), ("point_ids", ct.c_void_p), ("use_resident", ct.c_int32),
+                ("fuse_resident", ct.c_int32)]
 
 
 class ba_result(ct.Structure):
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     L.ba_footprint.restype = ct.c_size_t
     L.ba_profile_enable.argtypes = [P, ct.c_int32]
     L.ba_profile_read.argtypes = [P, P, P]
+    L.ba_resident_poses.argtypes = [P, ct.c_int32, P, P, P, P]
     L.ba_strerror.argtypes = [ct.c_int]
     L.ba_strerror.restype = ct.c_char_p
     L.ba_last_error.argtypes = [P]
@@ -112,7 +114,7 @@ class Cluster:
     """Marshals a scene dict into a ba_cluster, keeping the arrays alive."""
 
     def __init__(self, sc: dict, max_iters: int = 10, lambda0: float = 1e-4, ftol: float = 1e-10,
-                 stop_on_ftol: bool = False, use_resident: bool = False):
+                 stop_on_ftol: bool = False, use_resident: bool = False, fuse_resident: bool = False):
         C, P, O = int(sc["n_cams"]), int(sc["n_points"]), int(sc["n_obs"])
         f64 = lambda x: np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1))
         self.arrays = {
@@ -135,7 +137,7 @@ class Cluster:
                             float(sc["f"]), float(sc["cx"]), float(sc["cy"]), float(sc["sigma_px"]),
                             float(sc["huber_delta"]), int(max_iters), 1 if stop_on_ftol else 0,
                             float(lambda0), float(ftol), _p(a.get("cam_ids")), _p(a.get("point_ids")),
-                            1 if use_resident else 0)
+                            1 if use_resident else 0, 1 if fuse_resident else 0)
 
 
 class Context:
@@ -215,6 +217,14 @@ class Context:
         n = np.zeros(len(BA_PROF_KERNELS), np.int64)
         self._chk(self.lib.ba_profile_read(self.h, _p(ms), _p(n)), "ba_profile_read")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(BA_PROF_KERNELS)}
+
+    def ba_resident_poses(self, cam_ids):
+        """(R [n,3,3], T [n,3], w [n]) held on the device for the given camera IDs."""
+        ids = np.ascontiguousarray(np.asarray(cam_ids, np.int64).reshape(-1))
+        n = ids.size
+        R, T, w = np.zeros((n, 3, 3)), np.zeros((n, 3)), np.zeros(n)
+        self._chk(self.lib.ba_resident_poses(self.h, n, _p(ids), _p(R), _p(T), _p(w)), "ba_resident_poses")
+        return R, T, w
 
     def ba_fetch(self, t: int) -> dict:
         C, P, it = self.meta[t]

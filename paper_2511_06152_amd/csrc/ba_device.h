@@ -84,10 +84,12 @@ struct SlotDesc {
   // resident state keyed by global IDs (shared by the context's clusters)
   int n_rin_cam, n_rin_pt, n_rout_cam, n_rout_pt;
   double* res_cam;                        // [cap][12] world frame: R row-major (9), T (3)
+  double* res_cam_w;                      // [cap] match-count weight of each resident pose
   double* res_pt;                         // [cap][3] world frame
   const int2* rin_cam;                    // [n_rin_cam] (camera, row) read at admission
   const int2* rin_pt;                     // [n_rin_pt] (internal point, row) read at admission
-  const int2* rout_cam;                   // [n_rout_cam] (camera, row) written back
+  const int4* rout_cam;                   // [n_rout_cam] (camera, row, observations of the camera,
+                                          //   1: fuse with the resident pose by Eq. 8) written back
   const int2* rout_pt;                    // [n_rout_pt] (caller's point index, row) written back
   double* dc;                             // [m] camera / intrinsic update
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction

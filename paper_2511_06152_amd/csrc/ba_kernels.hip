@@ -444,16 +444,40 @@ __global__ void k_res_gather(Batch bt) {
   }
 }
 
-// Final state (export staging, world frame) into the resident store.
+// Final state (export staging, world frame) into the resident store.  A camera
+// flagged for fusion whose row holds an earlier cluster's pose (weight > 0)
+// gets the match-count weighted mean of Eq. (8): T linearly, R along the
+// geodesic from the stored rotation; the row's weight accumulates.
 __global__ void k_res_scatter(Batch bt) {
   const int s = bt.act[blockIdx.y];
   const SlotDesc& d = bt.desc[s];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < d.n_rout_cam) {
-    const int2 e = d.rout_cam[i];
+    const int4 e = d.rout_cam[i];
     double* dst = d.res_cam + 12 * (size_t)e.y;
-    for (int t = 0; t < 9; ++t) dst[t] = d.out[9 * (size_t)e.x + t];
-    for (int t = 0; t < 3; ++t) dst[9 + t] = d.out[9 * (size_t)d.C + 3 * (size_t)e.x + t];
+    double Rn[9], Tn[3];
+    for (int t = 0; t < 9; ++t) Rn[t] = d.out[9 * (size_t)e.x + t];
+    for (int t = 0; t < 3; ++t) Tn[t] = d.out[9 * (size_t)d.C + 3 * (size_t)e.x + t];
+    const double wn = (double)e.z, wo = d.res_cam_w[e.y];
+    if (e.w && wo > 0.0) {
+      const double a = wn / (wo + wn);
+      double Ro[9], M[9];
+      for (int t = 0; t < 9; ++t) Ro[t] = dst[t];
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) M[3 * r + q] = Ro[r] * Rn[q] + Ro[3 + r] * Rn[3 + q] + Ro[6 + r] * Rn[6 + q];
+      double phi[3], E[9];
+      so3_log(M, phi);
+      for (int t = 0; t < 3; ++t) phi[t] *= a;
+      so3_exp(phi, E);
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) dst[3 * r + q] = Ro[3 * r] * E[q] + Ro[3 * r + 1] * E[3 + q] + Ro[3 * r + 2] * E[6 + q];
+      for (int t = 0; t < 3; ++t) dst[9 + t] = (wo * dst[9 + t] + wn * Tn[t]) / (wo + wn);
+      d.res_cam_w[e.y] = wo + wn;
+    } else {
+      for (int t = 0; t < 9; ++t) dst[t] = Rn[t];
+      for (int t = 0; t < 3; ++t) dst[9 + t] = Tn[t];
+      d.res_cam_w[e.y] = wn;
+    }
   }
   if (i < d.n_rout_pt) {
     const int2 e = d.rout_pt[i];

@@ -91,9 +91,11 @@ struct Staged {
   int sparse = 0;
   std::vector<int> brow, bcol;   // [F + 1], [nnzb]
   std::vector<int2> tslot;       // [n_targets] block slots (a,b), (b,a) of each target
-  // resident state: global IDs (caller order) when the cluster uses it
-  bool resident = false;
+  // resident state: global IDs (caller order) when the cluster uses it;
+  // observations per camera (the match-count weights of Eq. 8 fusion)
+  bool resident = false, fuse = false;
   std::vector<int64_t> cam_ids, point_ids;
+  std::vector<int> cam_nobs;
 };
 
 struct Layout {                  // byte offsets inside a slot block
@@ -152,7 +154,7 @@ Layout make_layout(const Staged& s, bool mixed) {
   const size_t rc = s.resident ? (size_t)s.C : 0, rp = s.resident ? (size_t)s.P : 0;
   l.rin_cam = take(sizeof(int2) * rc);
   l.rin_pt = take(sizeof(int2) * rp);
-  l.rout_cam = take(sizeof(int2) * rc);
+  l.rout_cam = take(sizeof(int4) * rc);
   l.rout_pt = take(sizeof(int2) * rp);
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
@@ -199,6 +201,8 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   for (size_t i = 0; i < 6 * (size_t)C; ++i)
     if (std::isnan(c->prior_sigma[i])) { err = "NaN prior sigma"; return BA_E_ARG; }
   if (c->use_resident != 0 && c->use_resident != 1) { err = "use_resident must be 0 or 1"; return BA_E_ARG; }
+  if (c->fuse_resident != 0 && c->fuse_resident != 1) { err = "fuse_resident must be 0 or 1"; return BA_E_ARG; }
+  if (c->fuse_resident && !c->use_resident) { err = "fuse_resident needs use_resident"; return BA_E_ARG; }
   if (c->use_resident) {
     if (!c->cam_ids || (P > 0 && !c->point_ids)) { err = "use_resident needs cam_ids and point_ids"; return BA_E_ARG; }
     std::unordered_set<int64_t> seen(c->cam_ids, c->cam_ids + C);
@@ -210,8 +214,11 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   s.C = C; s.P = P; s.O = O;
   if (c->use_resident) {
     s.resident = true;
+    s.fuse = c->fuse_resident != 0;
     s.cam_ids.assign(c->cam_ids, c->cam_ids + C);
     s.point_ids.assign(c->point_ids, c->point_ids + P);
+    s.cam_nobs.assign(C, 0);
+    for (int o = 0; o < O; ++o) ++s.cam_nobs[c->obs_cam[o]];
   }
   s.max_iters = c->max_iters; s.stop_on_ftol = c->stop_on_ftol;
   s.f = c->f; s.cx = c->cx; s.cy = c->cy; s.sigma = c->sigma_px; s.delta = c->huber_delta;
@@ -519,6 +526,7 @@ struct ba_ctx {
   // resident state keyed by global IDs (allocated at first use)
   struct ResRow { ba_ticket pending = 0; bool valid = false; };
   double* res_cam = nullptr;      // [cap][12]
+  double* res_cam_w = nullptr;    // [cap] match-count weight of each pose (Eq. 8)
   double* res_pt = nullptr;       // [cap][3]
   std::unordered_map<int64_t, int> res_cam_row, res_pt_row;
   std::vector<ResRow> res_cam_meta, res_pt_meta;
@@ -651,9 +659,12 @@ int res_register(ba_ctx* c, Ticket& t, const Staged& s) {
   if (!c->res_cam) {
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, BA_E_DEVICE, "hipSetDevice failed");
     if (hipMalloc(&c->res_cam, sizeof(double) * 12 * (size_t)capC) != hipSuccess ||
+        hipMalloc(&c->res_cam_w, sizeof(double) * (size_t)capC) != hipSuccess ||
         hipMalloc(&c->res_pt, sizeof(double) * 3 * (size_t)capP) != hipSuccess) {
       return fail(c, BA_E_NOMEM, "cannot allocate the resident store");
     }
+    if (hipMemset(c->res_cam_w, 0, sizeof(double) * (size_t)capC) != hipSuccess)
+      return fail(c, BA_E_DEVICE, "cannot clear the resident weights");
   }
   size_t new_c = 0, new_p = 0;
   for (int64_t id : s.cam_ids) new_c += c->res_cam_row.count(id) ? 0 : 1;
@@ -759,11 +770,12 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.Sblk = (double*)(base + lay.Sblk);
   d.Sblk32 = (float*)(base + lay.Sblk32);
   d.pcgw = (double*)(base + lay.pcgw);
-  std::vector<int2> rin_c, rin_p, rout_c, rout_p;
+  std::vector<int2> rin_c, rin_p, rout_p;
+  std::vector<int4> rout_c;
   if (t.resident) {
     for (int k = 0; k < s.C; ++k) {
       const int row = t.cam_rows[k];
-      rout_c.push_back(make_int2(k, row));
+      rout_c.push_back(make_int4(k, row, s.cam_nobs[k], s.fuse && s.cam_col[k] >= 0 ? 1 : 0));
       if (c->res_cam_meta[row].valid) rin_c.push_back(make_int2(k, row));
     }
     for (int n = 0; n < s.P; ++n) {
@@ -775,10 +787,11 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.n_rin_cam = (int)rin_c.size(); d.n_rin_pt = (int)rin_p.size();
   d.n_rout_cam = (int)rout_c.size(); d.n_rout_pt = (int)rout_p.size();
   d.res_cam = c->res_cam;
+  d.res_cam_w = c->res_cam_w;
   d.res_pt = c->res_pt;
   d.rin_cam = (const int2*)(base + lay.rin_cam);
   d.rin_pt = (const int2*)(base + lay.rin_pt);
-  d.rout_cam = (const int2*)(base + lay.rout_cam);
+  d.rout_cam = (const int4*)(base + lay.rout_cam);
   d.rout_pt = (const int2*)(base + lay.rout_pt);
   d.cost_part = (double*)(base + lay.cost_part);
   d.bad_part = (int*)(base + lay.bad_part);
@@ -817,7 +830,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   };
   HIPCHK(c, up2(lay.rin_cam, rin_c));
   HIPCHK(c, up2(lay.rin_pt, rin_p));
-  HIPCHK(c, up2(lay.rout_cam, rout_c));
+  if (!rout_c.empty())
+    HIPCHK(c, hipMemcpyAsync(base + lay.rout_cam, rout_c.data(), sizeof(int4) * rout_c.size(), hipMemcpyHostToDevice, st));
   HIPCHK(c, up2(lay.rout_pt, rout_p));
   HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
   SlotCtl ctl{};
@@ -1222,6 +1236,7 @@ int ba_destroy(ba_ctx* c) {
   if (c->d_ctl) (void)hipFree(c->d_ctl);
   if (c->arena_base) (void)hipFree(c->arena_base);
   if (c->res_cam) (void)hipFree(c->res_cam);
+  if (c->res_cam_w) (void)hipFree(c->res_cam_w);
   if (c->res_pt) (void)hipFree(c->res_pt);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -1401,6 +1416,40 @@ int ba_profile_read(ba_ctx* c, double* total_ms, int64_t* launches) {
     launches[k] = c->prof_n[k];
     c->prof_ms[k] = 0.0;
     c->prof_n[k] = 0;
+  }
+  return BA_OK;
+}
+
+int ba_resident_poses(ba_ctx* c, int32_t n, const int64_t* ids, double* R, double* T, double* w) {
+  if (!c) return BA_E_ARG;
+  if (n < 0 || (n > 0 && (!ids || !R || !T))) return fail(c, BA_E_ARG, "bad resident pose query");
+  std::lock_guard<std::mutex> g(c->mu);
+  std::vector<int> rows(n);
+  for (int i = 0; i < n; ++i) {
+    auto it = c->res_cam_row.find(ids[i]);
+    if (it == c->res_cam_row.end()) return fail(c, BA_E_ARG, "camera ID never submitted");
+    const ba_ctx::ResRow& m = c->res_cam_meta[it->second];
+    if (m.pending) {
+      auto pt = c->tickets.find(m.pending);
+      if (pt != c->tickets.end() && !pt->second->res_done)
+        return fail(c, BA_E_STATE, "camera ID has an unfinished writer");
+    }
+    if (!m.valid) return fail(c, BA_E_ARG, "camera ID never written back");
+    rows[i] = it->second;
+  }
+  if (n == 0) return BA_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double v[12], wr = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const size_t r = (size_t)rows[i];
+    HIPCHK(c, hipMemcpy(v, c->res_cam + 12 * r, sizeof(v), hipMemcpyDeviceToHost));
+    std::copy(v, v + 9, R + 9 * (size_t)i);
+    std::copy(v + 9, v + 12, T + 3 * (size_t)i);
+    if (w) {
+      HIPCHK(c, hipMemcpy(&wr, c->res_cam_w + r, sizeof(double), hipMemcpyDeviceToHost));
+      w[i] = wr;
+    }
   }
   return BA_OK;
 }

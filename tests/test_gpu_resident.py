@@ -14,6 +14,7 @@ import math
 
 import numpy as np
 import pytest
+from scipy.spatial.transform import Rotation
 
 import oracle
 from synth import aerial as A
@@ -51,15 +52,54 @@ def oracle_chain(clusters, iters, lambdas=None):
     return refs
 
 
-def api_chain(clusters, iters, precision=FP64, lambda0=1e-4):
+def nobs_per_cam(sc):
+    return np.bincount(sc["obs_cam"], minlength=sc["n_cams"]).astype(np.float64)
+
+
+def oracle_chain_fused(clusters, iters):
+    """The chain with Eq. (8) fusion on write-back: a free camera whose ID holds
+    an earlier pose stores the match-count weighted mean of that pose and the
+    new solution (weights: observations of the camera, accumulated); fixed
+    and first-seen cameras store the solution with this cluster's count."""
+    cam, pt, refs = {}, {}, []
+    for sc in clusters:
+        R, T, X = sc["R"].copy(), sc["T"].copy(), sc["X"].copy()
+        for k, cid in enumerate(sc["cam_ids"]):
+            if cid in cam:
+                R[k], T[k] = cam[cid][0], cam[cid][1]
+        for j, pid in enumerate(sc["point_ids"]):
+            if pid in pt:
+                X[j] = pt[pid]
+        ref = oracle.solve(dict(sc, R=R, T=T, X=X), max_iters=iters)
+        Rf, Tf, Xf, _ = ref["state"]
+        n = nobs_per_cam(sc)
+        for k, cid in enumerate(sc["cam_ids"]):
+            if not sc["fixed"][k] and cid in cam:
+                cam[cid] = oracle.fuse_pose(cam[cid][0], cam[cid][1], cam[cid][2], Rf[k], Tf[k], n[k])
+            else:
+                cam[cid] = (Rf[k].copy(), Tf[k].copy(), float(n[k]))
+        for j, pid in enumerate(sc["point_ids"]):
+            pt[pid] = Xf[j].copy()
+        refs.append(ref)
+    return refs, cam
+
+
+def api_chain(clusters, iters, precision=FP64, lambda0=1e-4, fuse=False, ctx_out=None):
     from paper_2511_06152_amd import Context
     out = []
-    with Context(precision=precision) as ctx:
+    ctx = Context(precision=precision)
+    try:
         for sc in clusters:
-            t = ctx.submit(sc, max_iters=iters, use_resident=True, lambda0=lambda0)
+            t = ctx.submit(sc, max_iters=iters, use_resident=True, fuse_resident=fuse, lambda0=lambda0)
             ctx.ba_step(t, iters)
             out.append(ctx.ba_fetch(t))
             ctx.ba_release(t)
+        if ctx_out is not None:
+            ids = np.unique(np.concatenate([sc["cam_ids"] for sc in clusters]))
+            ctx_out["ids"] = ids
+            ctx_out["poses"] = ctx.ba_resident_poses(ids)
+    finally:
+        ctx.close()
     return out
 
 
@@ -100,27 +140,122 @@ def test_resident_lambda_nan_takes_previous_damping():
     assert math.isfinite(got[-1]["lambda_"])
 
 
-@pytest.mark.parametrize("precision", [FP64, MIXED])
-def test_resident_serving_equals_api(precision):
+@pytest.mark.parametrize("precision,fuse", [(FP64, False), (MIXED, False), (MIXED, True)])
+def test_resident_serving_equals_api(precision, fuse):
     """All clusters of the stream handed to the serving loop at once: shared
-    IDs order them; results bit-identical to solving them one at a time."""
+    IDs order them; results (and, with fusion, the resident poses) bit-identical
+    to solving them one at a time."""
     from paper_2511_06152_amd import Context
     st = small_stream()
     cl = st["clusters"][:6]
-    ref = api_chain(cl, 8, precision=precision)
+    res = {}
+    ref = api_chain(cl, 8, precision=precision, fuse=fuse, ctx_out=res)
     with Context(precision=precision, serve=True, max_slots=8) as ctx:
         ts = []
         for sc in cl:
-            t = ctx.submit(sc, max_iters=8, use_resident=True)
+            t = ctx.submit(sc, max_iters=8, use_resident=True, fuse_resident=fuse)
             ctx.ba_solve(t)
             ts.append(t)
         got = []
         for t in ts:
             ctx.ba_wait(t)
             got.append(ctx.ba_fetch(t))
+        poses = ctx.ba_resident_poses(res["ids"])
     for a, g in zip(ref, got):
         for key in ("R", "T", "X", "cost_log"):
             assert np.array_equal(a[key], g[key]), key
+    for a, g in zip(res["poses"], poses):
+        assert np.array_equal(a, g)
+
+
+def test_fused_chain_fp64_matches_oracle():
+    """Eq. (8) fusion on write-back: every cluster of the chain starts from the
+    fused poses, so its cost per iteration matches the oracle's fused chain
+    (1e-8 relative); the resident poses after the chain match the oracle's
+    store (attitude 2e-8 rad, centres 10 um) and the weights exactly."""
+    st = small_stream()
+    cl = st["clusters"][:6]
+    print("case fused chain", [(c["image"], c["n_cams"], c["n_points"]) for c in cl], flush=True)
+    refs, store = oracle_chain_fused(cl, 6)
+    res = {}
+    got = api_chain(cl, 6, fuse=True, ctx_out=res)
+    for g, r in zip(got, refs):
+        check_cost_log(g, r)
+    R, T, w = res["poses"]
+    att, dT = 0.0, 0.0
+    for n, cid in enumerate(res["ids"]):
+        Ro, To, wo = store[cid]
+        att = max(att, float(np.linalg.norm(Rotation.from_matrix(R[n].T @ Ro).as_rotvec())))
+        dT = max(dT, float(np.abs(T[n] - To).max()))
+        assert w[n] == wo, (cid, w[n], wo)
+    print("fused store: attitude", att, "rad, centre", dT, "m", flush=True)
+    assert att < 2e-8 and dT < 1e-5
+
+
+def test_fusion_arithmetic_matches_oracle():
+    """The write-back fusion alone, on identical inputs: the resident poses
+    before a cluster, its own solution (ba_fetch) and its observation counts
+    give, through the oracle's Eq. (8), the resident poses after it
+    (rotation 1e-13, centre 1e-9 m: rounding only)."""
+    from paper_2511_06152_amd import Context
+    st = small_stream()
+    cl = st["clusters"][:4]
+    fused = 0
+    with Context(precision=FP64) as ctx:
+        for sc in cl:
+            ids = sc["cam_ids"]
+            known = [k for k, cid in enumerate(ids) if int(cid) in ctx_known(ctx, cid)]
+            before = ctx.ba_resident_poses(ids[known]) if known else None
+            t = ctx.submit(sc, max_iters=5, use_resident=True, fuse_resident=True)
+            ctx.ba_step(t, 5)
+            out = ctx.ba_fetch(t)
+            ctx.ba_release(t)
+            R, T, w = ctx.ba_resident_poses(ids)
+            n = nobs_per_cam(sc)
+            for k in range(sc["n_cams"]):
+                if k in known and not sc["fixed"][k]:
+                    i = known.index(k)
+                    eR, eT, ew = oracle.fuse_pose(before[0][i], before[1][i], before[2][i], out["R"][k], out["T"][k], n[k])
+                    fused += 1
+                else:
+                    eR, eT, ew = out["R"][k], out["T"][k], n[k]
+                assert np.abs(R[k] - eR).max() < 1e-13, (sc["image"], k)
+                assert np.abs(T[k] - eT).max() < 1e-9, (sc["image"], k)
+                assert w[k] == ew
+    print("cameras fused", fused, flush=True)
+    assert fused > 0
+
+
+def ctx_known(ctx, cid):
+    """{cid} when the context holds a written-back pose for it, else {}."""
+    from paper_2511_06152_amd import BAError
+    try:
+        ctx.ba_resident_poses([cid])
+        return {int(cid)}
+    except BAError as e:
+        assert e.code == -1
+        return set()
+
+
+def test_resident_pose_query_errors():
+    from paper_2511_06152_amd import BAError, Context
+    st = small_stream()
+    a, b = st["clusters"][:2]
+    with Context(precision=FP64) as ctx:
+        with pytest.raises(BAError) as e:
+            ctx.submit(a, max_iters=2, fuse_resident=True)          # fusion needs the resident state
+        assert e.value.code == -1
+        ta = ctx.submit(a, max_iters=2, use_resident=True, fuse_resident=True)
+        with pytest.raises(BAError) as e:
+            ctx.ba_resident_poses(a["cam_ids"][:1])                 # writer not finished
+        assert e.value.code == -4
+        ctx.ba_step(ta, 2)
+        R, T, w = ctx.ba_resident_poses(a["cam_ids"])
+        assert np.all(w == nobs_per_cam(a))
+        with pytest.raises(BAError) as e:
+            ctx.ba_resident_poses([10 ** 12])                       # never submitted
+        assert e.value.code == -1
+        assert ctx.ba_resident_poses([])[0].shape == (0, 3, 3)
 
 
 def test_resident_dependency_order_enforced():
