@@ -55,7 +55,7 @@ FLOP_PAIR = 246
 # HBM traffic per launch of the two block kernels on 64 paper-scale clusters,
 # from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch) over `bench.py --steps 1 --warmup 0 --batch 64 --plain 0 --serve 0
-# --uneven 0 --stream-reps 0 --global-iters 0 --cpu-clusters 0` (the batch
+# --uneven 0 --stream-reps 0 --chain-reps 0 --global-iters 0 --cpu-clusters 0` (the batch
 # runs as S parts on S streams, so a launch covers 1/S of the batch; key
 # (S, kernel)) and the same with `--batch-streams 1` (one launch covers the
 # batch: the kernel alone on the GPU), each scaled by what the same counter reads for a
@@ -298,6 +298,52 @@ def run_stream(args, Context, precision, kw):
             "p99_fraction_of_budget": pct(lat, 99) / 2080.0}
 
 
+def run_chain(args, Context, precision, kw):
+    """The paper's evaluation shape (Sec. 4): a 60-image, two-strip flight cut
+    into clusters of 12 that reuse the last three images of the cluster
+    before (the first of them fixed, the other two free and fused by Eq. 8 on
+    write-back), each with up to 8 overlapping images of the previous strip
+    (fixed).  All clusters go to the serving loop at once; their shared IDs
+    order them, so the flight runs as a chain.  Reports the flight's wall
+    time (first submit to last result), per-cluster latency, and the mean and
+    standard deviation of the reprojection error norms at each cluster's
+    solution.  Returns the report and the clusters (for the oracle timing)."""
+    t_gen = time.perf_counter()
+    cl = A.make_chain(9)["clusters"]
+    log(f"chain: {len(cl)} clusters of {[c['n_cams'] for c in cl]} images in {time.perf_counter() - t_gen:.1f}s")
+    walls, lat, errs = [], [], []
+    for rep in range(args.chain_reps):
+        ctx = Context(precision=precision, serve=True, max_slots=4, hbm_budget_bytes=1 << 30)
+        t0 = time.perf_counter()
+        ts = []
+        for sc in cl:
+            t = ctx.submit(sc, use_resident=True, fuse_resident=True, **kw)
+            ctx.ba_solve(t)
+            ts.append(t)
+        res = []
+        for t in ts:
+            ctx.ba_wait(t)
+            res.append(ctx.ba_fetch(t))
+        walls.append(time.perf_counter() - t0)
+        lat += [(r["t_done"] - r["t_submit"]) * 1e3 for r in res]
+        if rep == 0:
+            for sc, r in zip(cl, res):
+                e = A.project_obs(r["R"], r["T"], r["X"], r["k"], sc["obs_cam"], sc["obs_pt"]) - sc["obs_uv"]
+                errs.append(np.sqrt((e ** 2).sum(1)))
+        ctx.close()
+        log(f"chain rep {rep}: {len(cl)} clusters in {walls[-1] * 1e3:.1f} ms")
+    e = np.concatenate(errs)
+    n_img = len({int(k) for sc in cl for k in sc["cam_ids"]})
+    return {"images": n_img, "clusters": len(cl), "reps": args.chain_reps,
+            "cams_range": [min(c["n_cams"] for c in cl), max(c["n_cams"] for c in cl)],
+            "points_range": [min(c["n_points"] for c in cl), max(c["n_points"] for c in cl)],
+            "ms_per_flight": 1e3 * float(np.mean(walls)), "ms_per_image": 1e3 * float(np.mean(walls)) / n_img,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "reproj_err_mean_px": float(e.mean()), "reproj_err_std_px": float(e.std()),
+            "paper_context": "MATLAB on an i7 laptop CPU, 60 images: 66.45 s total with feature extraction and "
+                             "matching, 1.11 s per image pair (Table 1)"}, cl
+
+
 def run_global(args, Context, precision):
     """Whole-flight global adjustment: 400 cameras (10 strips x 40), 800k points,
     ~3.5M observations; the reduced camera system (m = 2400) by block-Jacobi
@@ -364,6 +410,9 @@ def main():
                     help="repetitions of the serving stream (4 strips x 40 images, one cluster per arriving "
                          "image, resident state; 0: skip)")
     ap.add_argument("--stream-window", type=int, default=2, help="stream clusters in flight (closed loop)")
+    ap.add_argument("--chain-reps", type=int, default=5,
+                    help="repetitions of the chained 60-image flight (clusters of 12 reusing 3 images, Eq. 8 "
+                         "fusion; 0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -539,6 +588,9 @@ def main():
     # ---- serving stream: one cluster per arriving image, resident state -------------------
     stream = run_stream(args, Context, BA_MIXED, kw) if args.stream_reps > 0 else None
 
+    # ---- the paper's chained flight: clusters of 12 reusing 3 images, Eq. (8) fusion --------
+    chain, chain_cl = run_chain(args, Context, BA_MIXED, kw) if args.chain_reps > 0 else (None, None)
+
     # ---- whole-flight global adjustment (PCG on the reduced camera system) ------------------
     glob, glob_scene = run_global(args, Context, BA_MIXED) if args.global_iters > 0 else (None, None)
 
@@ -554,6 +606,33 @@ def main():
         cpu = {"value": args.cpu_clusters / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_clusters} clusters of the same workload, same termination rule, "
                          f"single-threaded FP64 C++ ({dt:.1f} s)"}
+        if chain_cl is not None:
+            # the same chain on the host: each cluster from the fused poses and
+            # points the clusters before it left
+            t0 = time.perf_counter()
+            store_c, store_p = {}, {}
+            for sc in chain_cl:
+                R, T, X = sc["R"].copy(), sc["T"].copy(), sc["X"].copy()
+                for k, cid in enumerate(sc["cam_ids"]):
+                    if cid in store_c:
+                        R[k], T[k] = store_c[cid][0], store_c[cid][1]
+                for j, pid in enumerate(sc["point_ids"]):
+                    if pid in store_p:
+                        X[j] = store_p[pid]
+                ref = oracle.solve(dict(sc, R=R, T=T, X=X), max_iters=args.max_iters, stop_on_ftol=True,
+                                   ftol=args.ftol)
+                Rf, Tf, Xf, _ = ref["state"]
+                n = np.bincount(sc["obs_cam"], minlength=sc["n_cams"]).astype(np.float64)
+                for k, cid in enumerate(sc["cam_ids"]):
+                    if not sc["fixed"][k] and cid in store_c:
+                        store_c[cid] = oracle.fuse_pose(*store_c[cid], Rf[k], Tf[k], n[k])
+                    else:
+                        store_c[cid] = (Rf[k], Tf[k], float(n[k]))
+                for j, pid in enumerate(sc["point_ids"]):
+                    store_p[pid] = Xf[j]
+            cpu["chain_s_per_flight"] = time.perf_counter() - t0
+            cpu["chain_sample"] = (f"the chained {len(chain_cl)}-cluster flight once, same termination rule, "
+                                   "single-threaded")
         if glob_scene is not None and args.global_oracle_iters > 0:
             t0 = time.perf_counter()
             oracle.solve(glob_scene, max_iters=args.global_oracle_iters)
@@ -600,6 +679,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_uneven": uneven,
         "serving_stream": stream,
+        "paper_chain": chain,
         "global_ba": glob,
     }
     print(json.dumps(out), flush=True)

@@ -218,7 +218,8 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
     s.cam_ids.assign(c->cam_ids, c->cam_ids + C);
     s.point_ids.assign(c->point_ids, c->point_ids + P);
     s.cam_nobs.assign(C, 0);
-    for (int o = 0; o < O; ++o) ++s.cam_nobs[c->obs_cam[o]];
+    for (int o = 0; o < O; ++o)   // indices are range-checked below; count only valid ones here
+      if (c->obs_cam[o] >= 0 && c->obs_cam[o] < C) ++s.cam_nobs[c->obs_cam[o]];
   }
   s.max_iters = c->max_iters; s.stop_on_ftol = c->stop_on_ftol;
   s.f = c->f; s.cx = c->cx; s.cy = c->cy; s.sigma = c->sigma_px; s.delta = c->huber_delta;

@@ -480,6 +480,54 @@ def scene_global(seed: int = 5, **kw) -> dict:
     return make_scene(spec_global(**kw), seed)
 
 
+def _flight(seed, n_strips, imgs_per_strip, pts_per_image, obs_mean):
+    """A flight with one global tie-point pool, and its observations grouped
+    by camera (order, starts)."""
+    spec = SceneSpec(n_strips=n_strips, imgs_per_strip=imgs_per_strip,
+                     n_points=pts_per_image * n_strips * imgs_per_strip,
+                     obs_model=("geom", obs_mean), neighbour_vis=True)
+    fl = make_scene(spec, seed)
+    order = np.argsort(fl["obs_cam"], kind="stable")
+    starts = np.searchsorted(fl["obs_cam"][order], np.arange(fl["n_cams"] + 1))
+    return fl, order, starts
+
+
+def _overlapping_prev_strip(fl, i):
+    """Images of the previous strip whose footprint overlaps image i's, nearest first."""
+    strip = fl["truth"]["strip"]
+    Txy = fl["truth"]["T"][:, :2]
+    prev = np.nonzero(strip == strip[i] - 1)[0]
+    d = np.abs(Txy[prev] - Txy[i])
+    prev = prev[(d[:, 0] < FOOT_ACROSS) & (d[:, 1] < FOOT_ALONG)]
+    return prev[np.argsort(np.hypot(*(Txy[prev] - Txy[i]).T))]
+
+
+def _cut_cluster(fl, order, starts, cams, fixed, image):
+    """The cluster scene of the given flight images: pool points with at least
+    two observations among them, IDs = flight indices."""
+    C = fl["n_cams"]
+    obs = np.concatenate([order[starts[k]:starts[k + 1]] for k in cams])
+    cnt = np.bincount(fl["obs_pt"][obs], minlength=fl["n_points"])
+    pts = np.nonzero(cnt >= 2)[0]
+    obs = obs[cnt[fl["obs_pt"][obs]] >= 2]
+    obs = np.sort(obs)
+    cam_loc = np.full(C, -1, np.int64)
+    cam_loc[cams] = np.arange(cams.size)
+    pt_loc = np.full(fl["n_points"], -1, np.int64)
+    pt_loc[pts] = np.arange(pts.size)
+    c = lambda x, dt=np.float64: np.ascontiguousarray(x, dtype=dt)
+    return {
+        "image": image, "n_cams": int(cams.size), "n_points": int(pts.size), "n_obs": int(obs.size),
+        "R": c(fl["R"][cams]), "T": c(fl["T"][cams]), "X": c(fl["X"][pts]), "k": c(fl["k"]),
+        "prior_R": c(fl["prior_R"][cams]), "prior_T": c(fl["prior_T"][cams]),
+        "prior_sigma": c(fl["prior_sigma"][cams]), "fixed": np.asarray(fixed, np.uint8),
+        "obs_cam": c(cam_loc[fl["obs_cam"][obs]], np.int32), "obs_pt": c(pt_loc[fl["obs_pt"][obs]], np.int32),
+        "obs_uv": c(fl["obs_uv"][obs]), "f": fl["f"], "cx": fl["cx"], "cy": fl["cy"], "intr_mask": 0,
+        "sigma_px": fl["sigma_px"], "huber_delta": fl["huber_delta"],
+        "cam_ids": c(cams, np.int64), "point_ids": c(pts, np.int64),
+    }
+
+
 def make_stream(seed: int = 3, n_strips: int = 4, imgs_per_strip: int = 40, pts_per_image: int = 2000,
                 max_cams: int = 20, min_cams: int = 8, back: int = 7, free_back: int = 3,
                 obs_mean: float = 4.8) -> dict:
@@ -496,47 +544,64 @@ def make_stream(seed: int = 3, n_strips: int = 4, imgs_per_strip: int = 40, pts_
     Returns {"flight": scene of the whole block, "clusters": [scene, ...]} where
     each cluster scene carries cam_ids / point_ids (indices into the flight)
     and "image": the triggering image."""
-    spec = SceneSpec(n_strips=n_strips, imgs_per_strip=imgs_per_strip,
-                     n_points=pts_per_image * n_strips * imgs_per_strip,
-                     obs_model=("geom", obs_mean), neighbour_vis=True)
-    fl = make_scene(spec, seed)
-    C = fl["n_cams"]
+    fl, order, starts = _flight(seed, n_strips, imgs_per_strip, pts_per_image, obs_mean)
     strip = fl["truth"]["strip"]
-    Txy = fl["truth"]["T"][:, :2]
-    # observations grouped by camera
-    order = np.argsort(fl["obs_cam"], kind="stable")
-    starts = np.searchsorted(fl["obs_cam"][order], np.arange(C + 1))
     clusters = []
-    for i in range(C):
+    for i in range(fl["n_cams"]):
         s, pos = int(strip[i]), i % imgs_per_strip
         own = [i - b for b in range(1, back + 1) if pos - b >= 0]
-        prev = np.nonzero(strip == s - 1)[0]
-        d = np.abs(Txy[prev] - Txy[i])
-        prev = prev[(d[:, 0] < FOOT_ACROSS) & (d[:, 1] < FOOT_ALONG)]
-        prev = prev[np.argsort(np.hypot(*(Txy[prev] - Txy[i]).T))]
+        prev = _overlapping_prev_strip(fl, i)
         cams = ([i] + own + [int(k) for k in prev])[:max_cams]
         if len(cams) < min_cams:
             continue
         cams = np.array(sorted(cams), np.int64)
-        obs = np.concatenate([order[starts[k]:starts[k + 1]] for k in cams])
-        cnt = np.bincount(fl["obs_pt"][obs], minlength=fl["n_points"])
-        pts = np.nonzero(cnt >= 2)[0]
-        obs = obs[cnt[fl["obs_pt"][obs]] >= 2]
-        obs = np.sort(obs)
-        cam_loc = np.full(C, -1, np.int64)
-        cam_loc[cams] = np.arange(cams.size)
-        pt_loc = np.full(fl["n_points"], -1, np.int64)
-        pt_loc[pts] = np.arange(pts.size)
         fixed = np.array([0 if (k == i or (strip[k] == s and i - k <= free_back)) else 1 for k in cams], np.uint8)
-        c = lambda x, dt=np.float64: np.ascontiguousarray(x, dtype=dt)
-        clusters.append({
-            "image": i, "n_cams": int(cams.size), "n_points": int(pts.size), "n_obs": int(obs.size),
-            "R": c(fl["R"][cams]), "T": c(fl["T"][cams]), "X": c(fl["X"][pts]), "k": c(fl["k"]),
-            "prior_R": c(fl["prior_R"][cams]), "prior_T": c(fl["prior_T"][cams]),
-            "prior_sigma": c(fl["prior_sigma"][cams]), "fixed": fixed,
-            "obs_cam": c(cam_loc[fl["obs_cam"][obs]], np.int32), "obs_pt": c(pt_loc[fl["obs_pt"][obs]], np.int32),
-            "obs_uv": c(fl["obs_uv"][obs]), "f": fl["f"], "cx": fl["cx"], "cy": fl["cy"], "intr_mask": 0,
-            "sigma_px": fl["sigma_px"], "huber_delta": fl["huber_delta"],
-            "cam_ids": c(cams, np.int64), "point_ids": c(pts, np.int64),
-        })
+        clusters.append(_cut_cluster(fl, order, starts, cams, fixed, i))
+    return {"flight": fl, "clusters": clusters}
+
+
+def chain_membership(n_images: int, cluster_size: int = 12, n_ref: int = 3):
+    """The paper's chaining of clusters (Sec. 3.2, Sec. 4): images in flight
+    order are cut into clusters of cluster_size; each cluster after the first
+    starts with the last n_ref images of its predecessor as references, the
+    first half of them (n_ref // 2) fixed and the rest free (their poses are
+    then fused by Eq. 8), followed by new images.  A shorter last cluster
+    takes the images left over.  Returns [(own, refs, fixed_refs)]: the
+    cluster's images in flight order, its references, and the fixed ones."""
+    if not 0 <= n_ref < cluster_size:
+        raise ValueError("need 0 <= n_ref < cluster_size")
+    out, prev, start = [], [], 0
+    while start < n_images:
+        refs = prev[len(prev) - n_ref:] if (prev and n_ref) else []
+        new = list(range(start, min(n_images, start + cluster_size - len(refs))))
+        own = refs + new
+        out.append((own, refs, refs[: len(refs) // 2]))
+        prev, start = own, new[-1] + 1
+    return out
+
+
+def make_chain(seed: int = 9, n_strips: int = 2, imgs_per_strip: int = 30, pts_per_image: int = 2000,
+               cluster_size: int = 12, n_ref: int = 3, max_neighbours: int = 8, obs_mean: float = 4.8) -> dict:
+    """The paper's evaluation flight shape (Sec. 4: 60 images in two strips,
+    clusters of 12 reusing the last 3 images) cut by `chain_membership`.  Each
+    cluster also holds up to max_neighbours images of the previous strip
+    whose footprints overlap its own images (nearest first per image, fixed:
+    adjusted by earlier clusters).  Cluster scenes as in make_stream, with
+    "image" the cluster's last image, "refs" its reference IDs and
+    "refs_fixed" the fixed ones."""
+    fl, order, starts = _flight(seed, n_strips, imgs_per_strip, pts_per_image, obs_mean)
+    clusters = []
+    for own, refs, fixed_refs in chain_membership(fl["n_cams"], cluster_size, n_ref):
+        nb = []
+        for i in own:
+            for k in _overlapping_prev_strip(fl, i):
+                if int(k) not in own and int(k) not in nb:
+                    nb.append(int(k))
+        nb = nb[:max_neighbours]
+        cams = np.array(sorted(own + nb), np.int64)
+        fixed = np.array([1 if (k in fixed_refs or k in nb) else 0 for k in cams], np.uint8)
+        sc = _cut_cluster(fl, order, starts, cams, fixed, own[-1])
+        sc["refs"] = np.array(refs, np.int64)
+        sc["refs_fixed"] = np.array(fixed_refs, np.int64)
+        clusters.append(sc)
     return {"flight": fl, "clusters": clusters}

@@ -18,7 +18,7 @@ from scipy.spatial.transform import Rotation
 
 import oracle
 from synth import aerial as A
-from test_gpu_parity import check_cost_log
+from test_gpu_parity import check_cost_log, final_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -168,6 +168,20 @@ def test_resident_serving_equals_api(precision, fuse):
         assert np.array_equal(a, g)
 
 
+def store_errors(res, store):
+    """Largest attitude (rad) and centre (m) difference between the resident
+    poses read back and the oracle's store; the weights must be equal."""
+    R, T, w = res["poses"]
+    att, dT = 0.0, 0.0
+    for n, cid in enumerate(res["ids"]):
+        Ro, To, wo = store[cid]
+        att = max(att, float(np.linalg.norm(Rotation.from_matrix(R[n].T @ Ro).as_rotvec())))
+        dT = max(dT, float(np.abs(T[n] - To).max()))
+        assert w[n] == wo, (cid, w[n], wo)
+    print("resident poses vs oracle store: attitude", att, "rad, centre", dT, "m", flush=True)
+    return att, dT
+
+
 def test_fused_chain_fp64_matches_oracle():
     """Eq. (8) fusion on write-back: every cluster of the chain starts from the
     fused poses, so its cost per iteration matches the oracle's fused chain
@@ -181,15 +195,44 @@ def test_fused_chain_fp64_matches_oracle():
     got = api_chain(cl, 6, fuse=True, ctx_out=res)
     for g, r in zip(got, refs):
         check_cost_log(g, r)
-    R, T, w = res["poses"]
-    att, dT = 0.0, 0.0
-    for n, cid in enumerate(res["ids"]):
-        Ro, To, wo = store[cid]
-        att = max(att, float(np.linalg.norm(Rotation.from_matrix(R[n].T @ Ro).as_rotvec())))
-        dT = max(dT, float(np.abs(T[n] - To).max()))
-        assert w[n] == wo, (cid, w[n], wo)
-    print("fused store: attitude", att, "rad, centre", dT, "m", flush=True)
+    att, dT = store_errors(res, store)
     assert att < 2e-8 and dT < 1e-5
+
+
+def small_chain():
+    """The paper's chaining (60 images in two strips, clusters of 12, the last
+    three reused, one of them fixed) over a lighter tie-point pool."""
+    return A.make_chain(9, pts_per_image=300)
+
+
+def test_paper_chain_fp64_matches_oracle():
+    cl = small_chain()["clusters"]
+    print("case paper chain", [(c["image"], c["n_cams"], c["n_points"]) for c in cl], flush=True)
+    refs, store = oracle_chain_fused(cl, 6)
+    res = {}
+    got = api_chain(cl, 6, fuse=True, ctx_out=res)
+    for g, r in zip(got, refs):
+        check_cost_log(g, r)
+    att, dT = store_errors(res, store)
+    assert att < 2e-8 and dT < 1e-5
+
+
+def test_paper_chain_mixed_within_bars():
+    """The mixed path over the whole chain, 30 iterations per cluster: every
+    cluster's solution within the mixed-precision bars of the oracle's fused
+    chain (RMS reprojection difference 1e-3 px, centres 1 mm, attitude
+    2e-6 rad), and so are the fused resident poses after the chain."""
+    cl = small_chain()["clusters"]
+    print("case paper chain mixed", len(cl), flush=True)
+    refs, store = oracle_chain_fused(cl, 30)
+    res = {}
+    got = api_chain(cl, 30, precision=MIXED, fuse=True, ctx_out=res)
+    for sc, g, r in zip(cl, got, refs):
+        rms, dT, att = final_errors(sc, g, r)
+        print("cluster", sc["image"], "rms", rms, "px, centre", dT, "m, attitude", att, "rad", flush=True)
+        assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
+    att, dT = store_errors(res, store)
+    assert att < 2e-6 and dT < 1e-3
 
 
 def test_fusion_arithmetic_matches_oracle():
