@@ -14,7 +14,8 @@ Readings (the paper names the operations, not their numerics):
 * Ray / DSM intersection: the first lam > 0 where the ray's height meets the
   surface, g(lam) = z(lam) - H(x(lam), y(lam)) = 0.  The ray is sampled from
   where it passes the raster's highest node to where it passes the lowest,
-  in n equal steps, n = ceil(horizontal travel / half a cell) (at least 1);
+  in n equal steps, n = ceil(horizontal travel / half a cell), at least 1
+  and at most 65536;
   the first sample with g <= 0 and the one before it bracket the root,
   which up to 64 halvings then narrow (the root is the bracket's final
   upper end).  A ray that does not descend misses.
@@ -24,7 +25,8 @@ Readings (the paper names the operations, not their numerics):
   quadrilaterals in the horizontal plane (both convex).
 * Eq. 3 with an a-priori elevation model: lam of the patch centre's ray in
   image 0 is its DSM intersection; the ground point is projected into image
-  k with K and (R_k, T_k).  A patch whose centre leaves the image
+  k with K and (R_k, T_k) (a ground point not in front of camera k counts
+  as a miss).  A patch whose centre leaves the image
   [0, W) x [0, H) re-enters at the opposite edge (Sec. 3.1): the coordinate
   is wrapped modulo the image size, and the patch is flagged.
 """
@@ -74,7 +76,7 @@ def ray_dsm(dsm: dict, T, d):
     if g(lam_a) <= 0.0:
         return lam_a, 0
     dxy = math.hypot(d[0], d[1])
-    n = 1 if dxy == 0.0 else max(1, int(math.ceil((lam_b - lam_a) * dxy / (0.5 * dsm["cell"]))))
+    n = 1 if dxy == 0.0 else min(65536, max(1, int(math.ceil((lam_b - lam_a) * dxy / (0.5 * dsm["cell"])))))
     lo = lam_a
     hi = lam_b
     for i in range(1, n + 1):
@@ -190,6 +192,9 @@ def transfer_eq3(dsm: dict, R0, T0, Rk, Tk, f, cx, cy, width, height, uv0):
             continue
         X = np.asarray(T0, np.float64) + lam * d
         xc = Rk.T @ (X - np.asarray(Tk, np.float64))
+        if not xc[2] > 0.0:
+            flags[p] = MISS
+            continue
         u = f * xc[0] / xc[2] + cx
         v = f * xc[1] / xc[2] + cy
         if not (0.0 <= u < width and 0.0 <= v < height):

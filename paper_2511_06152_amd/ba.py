@@ -24,7 +24,8 @@ BA_MAX_OBS_PER_POINT = 64
 
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
-            "ba_last_error", "ba_resident_poses"]
+            "ba_last_error", "ba_resident_poses", "ba_geo_create", "ba_geo_destroy", "ba_footprints",
+            "ba_footprint_overlaps", "ba_patch_transfer", "ba_geo_last_ms", "ba_geo_last_error"]
 # Kernel slots of ba_profile_enable / ba_profile_read.  "blocks" is the Schur
 # block launch: camera and pair tasks together in BA_MIXED, camera tasks
 # alone in BA_FP64 (whose pair tasks are "pairblk").
@@ -52,6 +53,16 @@ class ba_cluster(ct.Structure):
                 ("lambda0", ct.c_double), ("ftol", ct.c_double),
                 ("cam_ids", ct.c_void_p), ("point_ids", ct.c_void_p), ("use_resident", ct.c_int32),
                 ("fuse_resident", ct.c_int32)]
+
+
+class ba_dsm(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("x0", ct.c_double), ("y0", ct.c_double),
+                ("cell", ct.c_double), ("h", ct.c_void_p)]
+
+
+class ba_pinhole(ct.Structure):
+    _fields_ = [("f", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double), ("width", ct.c_int32),
+                ("height", ct.c_int32)]
 
 
 class ba_result(ct.Structure):
@@ -89,12 +100,21 @@ def load(path: str = LIB_PATH):
     L.ba_profile_enable.argtypes = [P, ct.c_int32]
     L.ba_profile_read.argtypes = [P, P, P]
     L.ba_resident_poses.argtypes = [P, ct.c_int32, P, P, P, P]
+    L.ba_geo_create.argtypes = [ct.c_int32, ct.POINTER(ba_dsm), ct.POINTER(P)]
+    L.ba_geo_destroy.argtypes = [P]
+    L.ba_footprints.argtypes = [P, ct.c_int32, P, P, ct.POINTER(ba_pinhole), P, P]
+    L.ba_footprint_overlaps.argtypes = [P, ct.c_int32, P, P]
+    L.ba_patch_transfer.argtypes = [P, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(ba_pinhole),
+                                    P, P, P]
+    L.ba_geo_last_ms.argtypes = [P, P, P]
+    L.ba_geo_last_error.argtypes = [P]
+    L.ba_geo_last_error.restype = ct.c_char_p
     L.ba_strerror.argtypes = [ct.c_int]
     L.ba_strerror.restype = ct.c_char_p
     L.ba_last_error.argtypes = [P]
     L.ba_last_error.restype = ct.c_char_p
     for name in EXPORTED:
-        if name not in ("ba_footprint", "ba_strerror", "ba_last_error"):
+        if name not in ("ba_footprint", "ba_strerror", "ba_last_error", "ba_geo_last_error"):
             getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -240,3 +260,86 @@ class Context:
         out["cost_log"] = out["cost_log"][: n + 1]
         out["state"] = (out["R"], out["T"], out["X"], out["k"])
         return out
+
+
+GEO_OK, GEO_MISS, GEO_REINIT = 0, 1, 2
+
+
+class Geo:
+    """Owns a ba_geo (include/ba_geo.h): footprints, footprint overlaps and
+    the Eq. (3) patch transfer over a DSM.  dsm: dict with nx, ny, x0, y0,
+    cell, h ([ny][nx] float32)."""
+
+    def __init__(self, dsm: dict, device: int = 0):
+        self.lib = load()
+        self._h = np.ascontiguousarray(np.asarray(dsm["h"], np.float32))
+        d = ba_dsm(int(dsm["nx"]), int(dsm["ny"]), float(dsm["x0"]), float(dsm["y0"]), float(dsm["cell"]),
+                   _p(self._h))
+        h = ct.c_void_p()
+        rc = self.lib.ba_geo_create(device, ct.byref(d), ct.byref(h))
+        if rc != BA_OK:
+            raise BAError(rc, "ba_geo_create failed: " + self.lib.ba_strerror(rc).decode())
+        self.h = h
+
+    def _chk(self, rc, what):
+        if rc != BA_OK:
+            raise BAError(rc, f"{what}: {self.lib.ba_strerror(rc).decode()}: {self.lib.ba_geo_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ba_geo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @staticmethod
+    def _cam(cam: dict):
+        return ba_pinhole(float(cam["f"]), float(cam["cx"]), float(cam["cy"]), int(cam["width"]), int(cam["height"]))
+
+    def ba_footprints(self, R, T, cam: dict):
+        """(ground [n,5,3], status [n]) for poses R [n,3,3], T [n,3]."""
+        R = np.ascontiguousarray(np.asarray(R, np.float64))
+        T = np.ascontiguousarray(np.asarray(T, np.float64))
+        n = T.shape[0]
+        ground, status = np.zeros((n, 5, 3)), np.zeros(n, np.int32)
+        c = self._cam(cam)
+        self._chk(self.lib.ba_footprints(self.h, n, _p(R), _p(T), ct.byref(c), _p(ground), _p(status)),
+                  "ba_footprints")
+        return ground, status
+
+    def ba_footprint_overlaps(self, ground):
+        """Packed upper triangle of the pairwise overlap areas."""
+        ground = np.ascontiguousarray(np.asarray(ground, np.float64))
+        n = ground.shape[0]
+        area = np.zeros(max(n * (n - 1) // 2, 1))
+        self._chk(self.lib.ba_footprint_overlaps(self.h, n, _p(ground), _p(area)), "ba_footprint_overlaps")
+        return area[: n * (n - 1) // 2]
+
+    def ba_patch_transfer(self, R, T, uv0, pairs, cam: dict, want_lam: bool = False):
+        """(uv [n_pairs, n_patch, 2], flags [n_pairs, n_patch], lam [n_img, n_patch] or None)."""
+        R = np.ascontiguousarray(np.asarray(R, np.float64))
+        T = np.ascontiguousarray(np.asarray(T, np.float64))
+        uv0 = np.ascontiguousarray(np.asarray(uv0, np.float64))
+        pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+        n_img, n_patch, n_pairs = T.shape[0], uv0.shape[0], pairs.shape[0]
+        uv = np.zeros((n_pairs, n_patch, 2))
+        flags = np.zeros((n_pairs, n_patch), np.int32)
+        lam = np.zeros((n_img, n_patch)) if want_lam else None
+        c = self._cam(cam)
+        self._chk(self.lib.ba_patch_transfer(self.h, n_img, _p(R), _p(T), n_patch, _p(uv0), n_pairs, _p(pairs),
+                                             ct.byref(c), _p(uv), _p(flags), _p(lam)), "ba_patch_transfer")
+        return uv, flags, lam
+
+    def ba_geo_last_ms(self, last_kernel: bool = False) -> float:
+        """Device ms of the last call's kernels (or of its last kernel alone)."""
+        tot, last = ct.c_double(), ct.c_double()
+        self._chk(self.lib.ba_geo_last_ms(self.h, ct.byref(tot), ct.byref(last)), "ba_geo_last_ms")
+        return last.value if last_kernel else tot.value

@@ -1,0 +1,485 @@
+// Footprints, footprint overlaps and the GNSS/IMU patch transfer of Eq. (3)
+// over a digital surface model (Sec. 3.1), for gfx950; the C ABI of
+// include/ba_geo.h.
+//
+// Kernels
+//   k_footprint_rays, k_patch_rays
+//               one thread per pixel ray: the ray's first crossing with the
+//               bilinear DSM (marched in half-cell steps of horizontal
+//               travel, then bisected).  Footprints: five rays per image
+//               (corners and centre).  Patch transfer: one ray per patch of
+//               each source image; the crossing is kept as (x, y, z, lam).
+//   k_overlap   one workgroup per footprint i, its threads over j > i: area of
+//               the intersection of the two corner quadrilaterals
+//               (Sutherland-Hodgman clip of one convex polygon by the other).
+//   k_project   one thread per (pair, patch): Eq. (3)'s projection of the
+//               source patch's ground point into the destination image and
+//               the wrap-around re-initialisation; coalesced 16-byte uv
+//               stores, the dominant traffic of the transfer.
+// The DSM heights (float32) stay in device memory for the context's life; a
+// flight's raster is tens of kilobytes and sits in L2 across the launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ba_geo.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxSteps = 65536;     // march steps per ray, at most
+constexpr int kHalvings = 64;
+
+struct Dsm {
+  const float* h;                    // [ny][nx]
+  int nx, ny;
+  double x0, y0, cell, hmin, hmax;
+};
+
+struct Cam {
+  double f, cx, cy;
+  int w, hgt;
+};
+
+// Bilinear height at (x, y), the position clamped to the raster.
+__device__ double dsm_h(const Dsm& m, double x, double y) {
+  double gx = (x - m.x0) / m.cell, gy = (y - m.y0) / m.cell;
+  gx = fmin(fmax(gx, 0.0), (double)(m.nx - 1));
+  gy = fmin(fmax(gy, 0.0), (double)(m.ny - 1));
+  const int i = min((int)floor(gx), m.nx - 2), j = min((int)floor(gy), m.ny - 2);
+  const double fx = gx - i, fy = gy - j;
+  const float* r0 = m.h + (size_t)j * m.nx + i;
+  const float* r1 = r0 + m.nx;
+  const double a = r0[0], b = r0[1], c = r1[0], d = r1[1];
+  return (1.0 - fx) * (1.0 - fy) * a + fx * (1.0 - fy) * b + (1.0 - fx) * fy * c + fx * fy * d;
+}
+
+// Height of the ray above the surface at depth lam.
+__device__ double ray_gap(const Dsm& m, const double T[3], const double d[3], double lam) {
+  return T[2] + lam * d[2] - dsm_h(m, T[0] + lam * d[0], T[1] + lam * d[1]);
+}
+
+// First crossing of T + lam d with the DSM; false when the ray misses.
+__device__ bool ray_dsm(const Dsm& m, const double T[3], const double d[3], double* lam_out) {
+  if (!(d[2] < 0.0)) return false;
+  const double lam_a = fmax(0.0, (T[2] - m.hmax) / -d[2]);
+  const double lam_b = (T[2] - m.hmin) / -d[2];
+  if (!(lam_b > 0.0)) return false;
+  if (ray_gap(m, T, d, lam_a) <= 0.0) {
+    *lam_out = lam_a;
+    return true;
+  }
+  const double dxy = hypot(d[0], d[1]);
+  int n = 1;
+  if (dxy != 0.0) {
+    const double steps = ceil((lam_b - lam_a) * dxy / (0.5 * m.cell));
+    n = steps >= (double)kMaxSteps ? kMaxSteps : max(1, (int)steps);
+  }
+  double lo = lam_a, hi = lam_b;
+  for (int s = 1; s <= n; ++s) {
+    const double lam = s == n ? lam_b : lam_a + (lam_b - lam_a) * s / n;
+    if (ray_gap(m, T, d, lam) <= 0.0) {
+      hi = lam;
+      break;
+    }
+    lo = lam;
+  }
+  for (int it = 0; it < kHalvings; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (ray_gap(m, T, d, mid) > 0.0) lo = mid;
+    else hi = mid;
+  }
+  *lam_out = hi;
+  return true;
+}
+
+// World direction R K^-1 (u, v, 1) of a pixel.
+__device__ void pixel_dir(const double* R, const Cam& k, double u, double v, double d[3]) {
+  const double a = (u - k.cx) / k.f, b = (v - k.cy) / k.f;
+  for (int r = 0; r < 3; ++r) d[r] = R[3 * r] * a + R[3 * r + 1] * b + R[3 * r + 2];
+}
+
+// Footprint rays: ray r = 5 image + corner; ground [n][5][3], status per ray.
+__global__ __launch_bounds__(kBlock) void k_footprint_rays(Dsm m, Cam k, int n, const double* __restrict__ R,
+                                                           const double* __restrict__ T, double* __restrict__ ground,
+                                                           int* __restrict__ ray_ok) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 5 * n) return;
+  const int img = r / 5, c = r % 5;
+  const double u = (c == 1 || c == 2) ? (double)k.w : (c == 4 ? 0.5 * k.w : 0.0);
+  const double v = (c == 2 || c == 3) ? (double)k.hgt : (c == 4 ? 0.5 * k.hgt : 0.0);
+  double d[3], Tc[3];
+  pixel_dir(R + 9 * (size_t)img, k, u, v, d);
+  for (int t = 0; t < 3; ++t) Tc[t] = T[3 * (size_t)img + t];
+  double lam;
+  const bool ok = ray_dsm(m, Tc, d, &lam);
+  for (int t = 0; t < 3; ++t) ground[3 * (size_t)r + t] = ok ? Tc[t] + lam * d[t] : NAN;
+  ray_ok[r] = ok ? 1 : 0;
+}
+
+// Patch rays: ray r = n_patch slot + patch of source image src[slot]; out
+// (x, y, z, lam) per ray.
+__global__ __launch_bounds__(kBlock) void k_patch_rays(Dsm m, Cam k, int n_src, int n_patch, const int* __restrict__ src,
+                                                       const double* __restrict__ R, const double* __restrict__ T,
+                                                       const double* __restrict__ uv0, double4* __restrict__ gp) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (size_t)n_src * n_patch) return;
+  const int slot = (int)(r / n_patch), q = (int)(r % n_patch);
+  const int img = src[slot];
+  double d[3], Tc[3];
+  pixel_dir(R + 9 * (size_t)img, k, uv0[2 * (size_t)q], uv0[2 * (size_t)q + 1], d);
+  for (int t = 0; t < 3; ++t) Tc[t] = T[3 * (size_t)img + t];
+  double lam;
+  if (ray_dsm(m, Tc, d, &lam)) gp[r] = make_double4(Tc[0] + lam * d[0], Tc[1] + lam * d[1], Tc[2] + lam * d[2], lam);
+  else gp[r] = make_double4(NAN, NAN, NAN, NAN);
+}
+
+// Signed area (counter-clockwise positive), shoelace.
+__device__ double signed_area(const double* x, const double* y, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int j = i + 1 == n ? 0 : i + 1;
+    s += x[i] * y[j] - x[j] * y[i];
+  }
+  return 0.5 * s;
+}
+
+// Loads the corner quadrilateral of footprint i in counter-clockwise order;
+// false when it is missing or not convex.
+__device__ bool load_quad(const double* __restrict__ ground, int i, double x[4], double y[4]) {
+  for (int c = 0; c < 4; ++c) {
+    x[c] = ground[15 * (size_t)i + 3 * c];
+    y[c] = ground[15 * (size_t)i + 3 * c + 1];
+  }
+  for (int c = 0; c < 4; ++c)
+    if (!(isfinite(x[c]) && isfinite(y[c]))) return false;
+  if (signed_area(x, y, 4) < 0.0) {
+    double t = x[1]; x[1] = x[3]; x[3] = t;
+    t = y[1]; y[1] = y[3]; y[3] = t;
+  }
+  for (int c = 0; c < 4; ++c) {
+    const int b = (c + 1) & 3, e = (c + 2) & 3;
+    if ((x[b] - x[c]) * (y[e] - y[b]) - (y[b] - y[c]) * (x[e] - x[b]) < 0.0) return false;
+  }
+  return true;
+}
+
+constexpr int kClipMax = 9;   // 4 vertices + at most one more per clipping edge
+
+// Area of the part of quadrilateral (ax, ay) inside convex CCW quadrilateral (bx, by).
+__device__ double clip_area(const double ax[4], const double ay[4], const double bx[4], const double by[4]) {
+  double px[kClipMax], py[kClipMax], qx[kClipMax], qy[kClipMax];
+  int n = 4;
+  for (int c = 0; c < 4; ++c) { px[c] = ax[c]; py[c] = ay[c]; }
+  for (int e = 0; e < 4 && n > 0; ++e) {
+    const double x0 = bx[e], y0 = by[e], ex = bx[(e + 1) & 3] - x0, ey = by[(e + 1) & 3] - y0;
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+      const int j = i + 1 == n ? 0 : i + 1;
+      const double sp = ex * (py[i] - y0) - ey * (px[i] - x0);
+      const double sq = ex * (py[j] - y0) - ey * (px[j] - x0);
+      if (sp >= 0.0 && m < kClipMax) { qx[m] = px[i]; qy[m] = py[i]; ++m; }
+      if ((sp >= 0.0) != (sq >= 0.0) && m < kClipMax) {
+        const double t = sp / (sp - sq);
+        qx[m] = px[i] + (px[j] - px[i]) * t;
+        qy[m] = py[i] + (py[j] - py[i]) * t;
+        ++m;
+      }
+    }
+    n = m;
+    for (int i = 0; i < n; ++i) { px[i] = qx[i]; py[i] = qy[i]; }
+  }
+  return n >= 3 ? fabs(signed_area(px, py, n)) : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_overlap(int n, const double* __restrict__ ground, double* __restrict__ area) {
+  const int i = blockIdx.x;
+  double ax[4], ay[4];
+  const bool ok_i = load_quad(ground, i, ax, ay);
+  const size_t row = (size_t)i * n - (size_t)i * (i + 1) / 2;
+  for (int j = i + 1 + threadIdx.x; j < n; j += blockDim.x) {
+    double bx[4], by[4];
+    const bool ok_j = load_quad(ground, j, bx, by);
+    area[row + (j - i - 1)] = (ok_i && ok_j) ? clip_area(ax, ay, bx, by) : NAN;
+  }
+}
+
+// Eq. (3): the ground point of source patch q projected into image dst, then
+// wrapped into the image (re-initialisation at the opposite edge).
+__global__ __launch_bounds__(kBlock) void k_project(Cam k, int n_patch, size_t total, const int* __restrict__ pairs,
+                                                    const int* __restrict__ slot_of, const double* __restrict__ R,
+                                                    const double* __restrict__ T, const double4* __restrict__ gp,
+                                                    double2* __restrict__ uv, int* __restrict__ flags) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(t / n_patch), q = (int)(t % n_patch);
+    const int src = pairs[2 * p], dst = pairs[2 * p + 1];
+    const double4 g = gp[(size_t)slot_of[src] * n_patch + q];
+    const double* Rd = R + 9 * (size_t)dst;
+    const double dx = g.x - T[3 * (size_t)dst], dy = g.y - T[3 * (size_t)dst + 1], dz = g.z - T[3 * (size_t)dst + 2];
+    const double xc = Rd[0] * dx + Rd[3] * dy + Rd[6] * dz;
+    const double yc = Rd[1] * dx + Rd[4] * dy + Rd[7] * dz;
+    const double zc = Rd[2] * dx + Rd[5] * dy + Rd[8] * dz;
+    int fl = BA_GEO_OK;
+    double u = NAN, v = NAN;
+    if (!isfinite(g.w) || !(zc > 0.0)) {
+      fl = BA_GEO_MISS;
+    } else {
+      u = k.f * xc / zc + k.cx;
+      v = k.f * yc / zc + k.cy;
+      if (!(u >= 0.0 && u < k.w && v >= 0.0 && v < k.hgt)) {
+        u -= k.w * floor(u / k.w);
+        v -= k.hgt * floor(v / k.hgt);
+        fl = BA_GEO_REINIT;
+      }
+    }
+    uv[t] = make_double2(u, v);
+    flags[t] = fl;
+  }
+}
+
+}  // namespace
+
+struct ba_geo {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // start, before the last kernel, end
+  Dsm dsm{};
+  float* d_h = nullptr;
+  std::vector<void*> bufs;           // work buffers, grown on demand
+  std::vector<size_t> caps;
+  double total_ms = 0.0, last_ms = 0.0;
+  std::string err;
+};
+
+namespace {
+
+int gfail(ba_geo* g, int code, const std::string& msg) {
+  g->err = msg;
+  return code;
+}
+
+#define GEOCHK(g, expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return gfail(g, BA_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device buffer `slot` of at least `bytes` bytes (kept and grown across calls).
+int buf(ba_geo* g, int slot, size_t bytes, void** out) {
+  if ((int)g->bufs.size() <= slot) {
+    g->bufs.resize(slot + 1, nullptr);
+    g->caps.resize(slot + 1, 0);
+  }
+  if (g->caps[slot] < bytes) {
+    if (g->bufs[slot]) (void)hipFree(g->bufs[slot]);
+    g->bufs[slot] = nullptr;
+    g->caps[slot] = 0;
+    if (hipMalloc(&g->bufs[slot], std::max<size_t>(bytes, 256)) != hipSuccess)
+      return gfail(g, BA_E_NOMEM, "cannot allocate a work buffer");
+    g->caps[slot] = std::max<size_t>(bytes, 256);
+  }
+  *out = g->bufs[slot];
+  return BA_OK;
+}
+
+bool cam_ok(const ba_pinhole* c) {
+  return c && std::isfinite(c->f) && c->f > 0 && std::isfinite(c->cx) && std::isfinite(c->cy) && c->width > 0 &&
+         c->height > 0;
+}
+
+Cam to_cam(const ba_pinhole* c) { return Cam{c->f, c->cx, c->cy, c->width, c->height}; }
+
+// Ends a call's launches: `split` says whether ev[1] marks the start of its
+// last kernel (else the last kernel is timed from the start).
+int finish(ba_geo* g, bool split) {
+  GEOCHK(g, hipEventRecord(g->ev[2], g->stream));
+  GEOCHK(g, hipStreamSynchronize(g->stream));
+  float tot = 0.0f, last = 0.0f;
+  GEOCHK(g, hipEventElapsedTime(&tot, g->ev[0], g->ev[2]));
+  if (split) GEOCHK(g, hipEventElapsedTime(&last, g->ev[1], g->ev[2]));
+  g->total_ms = tot;
+  g->last_ms = split ? last : tot;
+  return BA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ba_geo_create(int32_t device, const ba_dsm* dsm, ba_geo** out) {
+  if (!dsm || !out || !dsm->h || dsm->nx < 2 || dsm->ny < 2 || !(dsm->cell > 0) || !std::isfinite(dsm->cell) ||
+      !std::isfinite(dsm->x0) || !std::isfinite(dsm->y0))
+    return BA_E_ARG;
+  const size_t nn = (size_t)dsm->nx * dsm->ny;
+  double hmin = INFINITY, hmax = -INFINITY;
+  for (size_t i = 0; i < nn; ++i) {
+    if (!std::isfinite(dsm->h[i])) return BA_E_ARG;
+    hmin = std::min(hmin, (double)dsm->h[i]);
+    hmax = std::max(hmax, (double)dsm->h[i]);
+  }
+  ba_geo* g = new ba_geo();
+  g->device = device;
+  auto bail = [&](int code) {
+    ba_geo_destroy(g);
+    return code;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(BA_E_DEVICE);
+  if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) return bail(BA_E_DEVICE);
+  for (hipEvent_t& e : g->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail(BA_E_DEVICE);
+  if (hipMalloc(&g->d_h, nn * sizeof(float)) != hipSuccess) return bail(BA_E_NOMEM);
+  if (hipMemcpy(g->d_h, dsm->h, nn * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return bail(BA_E_DEVICE);
+  g->dsm = Dsm{g->d_h, dsm->nx, dsm->ny, dsm->x0, dsm->y0, dsm->cell, hmin, hmax};
+  *out = g;
+  return BA_OK;
+}
+
+int ba_geo_destroy(ba_geo* g) {
+  if (!g) return BA_E_ARG;
+  (void)hipSetDevice(g->device);
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (void* p : g->bufs)
+    if (p) (void)hipFree(p);
+  if (g->d_h) (void)hipFree(g->d_h);
+  for (hipEvent_t e : g->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+  return BA_OK;
+}
+
+int ba_footprints(ba_geo* g, int32_t n, const double* R, const double* T, const ba_pinhole* cam, double* ground,
+                  int32_t* status) {
+  if (!g) return BA_E_ARG;
+  if (n < 0 || !cam_ok(cam)) return gfail(g, BA_E_ARG, "bad image count or camera");
+  if (n == 0) return BA_OK;
+  if (!R || !T || !ground || !status) return gfail(g, BA_E_ARG, "missing array");
+  if (n > (1 << 26)) return gfail(g, BA_E_ARG, "too many images");
+  GEOCHK(g, hipSetDevice(g->device));
+  void *dR, *dT, *dG, *dOk;
+  int rc;
+  if ((rc = buf(g, 0, 72 * (size_t)n, &dR)) || (rc = buf(g, 1, 24 * (size_t)n, &dT)) ||
+      (rc = buf(g, 2, 120 * (size_t)n, &dG)) || (rc = buf(g, 3, 20 * (size_t)n, &dOk)))
+    return rc;
+  GEOCHK(g, hipMemcpyAsync(dR, R, 72 * (size_t)n, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dT, T, 24 * (size_t)n, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
+  const int rays = 5 * n;
+  hipLaunchKernelGGL(k_footprint_rays, dim3((rays + kBlock - 1) / kBlock), dim3(kBlock), 0, g->stream, g->dsm,
+                     to_cam(cam), n, (const double*)dR, (const double*)dT, (double*)dG, (int*)dOk);
+  GEOCHK(g, hipGetLastError());
+  if ((rc = finish(g, false))) return rc;
+  std::vector<int> ok(rays);
+  GEOCHK(g, hipMemcpy(ground, dG, 120 * (size_t)n, hipMemcpyDeviceToHost));
+  GEOCHK(g, hipMemcpy(ok.data(), dOk, 4 * (size_t)rays, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    status[i] = BA_GEO_OK;
+    for (int c = 0; c < 5; ++c)
+      if (!ok[5 * i + c]) status[i] = BA_GEO_MISS;
+  }
+  return BA_OK;
+}
+
+int ba_footprint_overlaps(ba_geo* g, int32_t n, const double* ground, double* area) {
+  if (!g) return BA_E_ARG;
+  if (n < 0 || n > 65536) return gfail(g, BA_E_ARG, "footprint count out of range (0..65536)");
+  if (n < 2) return BA_OK;
+  if (!ground || !area) return gfail(g, BA_E_ARG, "missing array");
+  GEOCHK(g, hipSetDevice(g->device));
+  const size_t np = (size_t)n * (n - 1) / 2;
+  void *dG, *dA;
+  int rc;
+  if ((rc = buf(g, 2, 120 * (size_t)n, &dG)) || (rc = buf(g, 4, 8 * np, &dA))) return rc;
+  GEOCHK(g, hipMemcpyAsync(dG, ground, 120 * (size_t)n, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
+  hipLaunchKernelGGL(k_overlap, dim3(n - 1), dim3(kBlock), 0, g->stream, n, (const double*)dG, (double*)dA);
+  GEOCHK(g, hipGetLastError());
+  if ((rc = finish(g, false))) return rc;
+  GEOCHK(g, hipMemcpy(area, dA, 8 * np, hipMemcpyDeviceToHost));
+  return BA_OK;
+}
+
+int ba_patch_transfer(ba_geo* g, int32_t n_img, const double* R, const double* T, int32_t n_patch,
+                      const double* uv0, int32_t n_pairs, const int32_t* pairs, const ba_pinhole* cam, double* uv,
+                      int32_t* flags, double* lam) {
+  if (!g) return BA_E_ARG;
+  if (n_img < 0 || n_patch < 0 || n_pairs < 0 || !cam_ok(cam)) return gfail(g, BA_E_ARG, "bad counts or camera");
+  if (n_img == 0 || n_patch == 0) {
+    if (n_pairs > 0 && n_img == 0) return gfail(g, BA_E_ARG, "pairs without images");
+    return BA_OK;
+  }
+  if (!R || !T || !uv0 || (n_pairs > 0 && (!pairs || !uv || !flags))) return gfail(g, BA_E_ARG, "missing array");
+  for (int i = 0; i < 2 * n_patch; ++i)
+    if (!std::isfinite(uv0[i])) return gfail(g, BA_E_ARG, "non-finite patch centre");
+  std::vector<int> slot_of(n_img, -1), src;
+  for (int p = 0; p < n_pairs; ++p) {
+    const int a = pairs[2 * p], b = pairs[2 * p + 1];
+    if (a < 0 || a >= n_img || b < 0 || b >= n_img) return gfail(g, BA_E_ARG, "pair index out of range");
+    if (slot_of[a] < 0) {
+      slot_of[a] = (int)src.size();
+      src.push_back(a);
+    }
+  }
+  const int n_src = (int)src.size();
+  if (lam)
+    for (size_t i = 0; i < (size_t)n_img * n_patch; ++i) lam[i] = NAN;
+  if (n_src == 0) return BA_OK;
+  const size_t rays = (size_t)n_src * n_patch, total = (size_t)n_pairs * n_patch;
+  GEOCHK(g, hipSetDevice(g->device));
+  void *dR, *dT, *dUv0, *dSrc, *dSlot, *dPairs, *dGp, *dUv, *dFl;
+  int rc;
+  if ((rc = buf(g, 0, 72 * (size_t)n_img, &dR)) || (rc = buf(g, 1, 24 * (size_t)n_img, &dT)) ||
+      (rc = buf(g, 5, 16 * (size_t)n_patch, &dUv0)) || (rc = buf(g, 6, 4 * (size_t)n_src, &dSrc)) ||
+      (rc = buf(g, 7, 4 * (size_t)n_img, &dSlot)) || (rc = buf(g, 8, 8 * (size_t)n_pairs, &dPairs)) ||
+      (rc = buf(g, 9, 32 * rays, &dGp)) || (rc = buf(g, 10, 16 * total, &dUv)) || (rc = buf(g, 11, 4 * total, &dFl)))
+    return rc;
+  GEOCHK(g, hipMemcpyAsync(dR, R, 72 * (size_t)n_img, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dT, T, 24 * (size_t)n_img, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dUv0, uv0, 16 * (size_t)n_patch, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dSrc, src.data(), 4 * (size_t)n_src, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dSlot, slot_of.data(), 4 * (size_t)n_img, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dPairs, pairs, 8 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
+  const Cam k = to_cam(cam);
+  hipLaunchKernelGGL(k_patch_rays, dim3((unsigned)((rays + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream, g->dsm, k,
+                     n_src, n_patch, (const int*)dSrc, (const double*)dR, (const double*)dT, (const double*)dUv0,
+                     (double4*)dGp);
+  GEOCHK(g, hipGetLastError());
+  GEOCHK(g, hipEventRecord(g->ev[1], g->stream));
+  if (total > 0) {
+    const size_t blocks = std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(kBlock), 0, g->stream, k, n_patch, total,
+                       (const int*)dPairs, (const int*)dSlot, (const double*)dR, (const double*)dT,
+                       (const double4*)dGp, (double2*)dUv, (int*)dFl);
+    GEOCHK(g, hipGetLastError());
+  }
+  if ((rc = finish(g, true))) return rc;
+  if (total > 0) {
+    GEOCHK(g, hipMemcpy(uv, dUv, 16 * total, hipMemcpyDeviceToHost));
+    GEOCHK(g, hipMemcpy(flags, dFl, 4 * total, hipMemcpyDeviceToHost));
+  }
+  if (lam) {
+    std::vector<double> gp(4 * rays);
+    GEOCHK(g, hipMemcpy(gp.data(), dGp, 32 * rays, hipMemcpyDeviceToHost));
+    for (int s = 0; s < n_src; ++s)
+      for (int q = 0; q < n_patch; ++q) lam[(size_t)src[s] * n_patch + q] = gp[4 * ((size_t)s * n_patch + q) + 3];
+  }
+  return BA_OK;
+}
+
+int ba_geo_last_ms(ba_geo* g, double* total_ms, double* last_ms) {
+  if (!g) return BA_E_ARG;
+  if (total_ms) *total_ms = g->total_ms;
+  if (last_ms) *last_ms = g->last_ms;
+  return BA_OK;
+}
+
+const char* ba_geo_last_error(ba_geo* g) { return g ? g->err.c_str() : "no context"; }
+
+}  // extern "C"

@@ -1,18 +1,19 @@
-"""The C-ABI library loads and exports every function include/ba.h declares
+"""The C-ABI library loads and exports every function include/*.h declares
 (CPU only: no compute call is made without a GPU)."""
 import ctypes as ct
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ba.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_2511_06152_amd", "libba.so")
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "\n".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(ba_[a-z_]+)\s*\(", src, flags=re.M)))
 
@@ -21,7 +22,9 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve", "ba_solve_batch",
                  "ba_wait", "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read",
-                 "ba_strerror", "ba_last_error"]:
+                 "ba_strerror", "ba_last_error", "ba_resident_poses", "ba_geo_create", "ba_geo_destroy",
+                 "ba_footprints", "ba_footprint_overlaps", "ba_patch_transfer", "ba_geo_last_ms",
+                 "ba_geo_last_error"]:
         assert want in names
 
 

@@ -1,0 +1,182 @@
+"""GPU parity of the footprint, overlap and Eq. (3) patch-transfer kernels
+(Sec. 3.1) with the geometry oracle, through the C ABI of include/ba_geo.h.
+
+Bars (FP64 on both sides, the same algorithm with different rounding
+order): ground points within 1e-6 m, overlap areas within 1e-6 relative of
+the footprint area (and exactly 0 where the footprints are disjoint),
+transferred patch centres within 1e-6 px with identical flags away from the
+image edges, depths within 1e-6 m.  Inputs: the seeded 4 x 40-image flight
+over its 12 m DSM (synth.geo), the 150 px patch grid (2120 patches)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geo as G
+from synth import geo as SG
+
+pytestmark = pytest.mark.gpu
+
+
+def flight(**kw):
+    return SG.make_geo_flight(21, **kw)
+
+
+def cam_of(g):
+    return {k: g[k] for k in ("f", "cx", "cy", "width", "height")}
+
+
+def oracle_footprints(g):
+    fp, st = [], []
+    for k in range(g["n_images"]):
+        a, s = G.footprint(g["dsm"], g["R"][k], g["T"][k], g["f"], g["cx"], g["cy"], g["width"], g["height"])
+        fp.append(a)
+        st.append(s)
+    return np.array(fp), np.array(st)
+
+
+def geo_ctx(g):
+    from paper_2511_06152_amd import Geo
+    return Geo(g["dsm"])
+
+
+def test_footprints_match_oracle():
+    g = flight()
+    print("case footprints", g["n_images"], "images, dsm", g["dsm"]["nx"], "x", g["dsm"]["ny"], flush=True)
+    ref, st_ref = oracle_footprints(g)
+    with geo_ctx(g) as geo:
+        got, st = geo.ba_footprints(g["R"], g["T"], cam_of(g))
+        print("kernel ms", geo.ba_geo_last_ms(), flush=True)
+    assert np.array_equal(st, st_ref) and np.all(st == 0)
+    err = np.abs(got - ref).max()
+    print("max ground point difference", err, "m", flush=True)
+    assert err < 1e-6
+
+
+def test_footprint_misses_and_empty():
+    g = flight(n_strips=1, imgs_per_strip=3)
+    R = g["R"].copy()
+    R[1] = np.eye(3)                      # camera axis up: every ray of image 1 misses
+    with geo_ctx(g) as geo:
+        got, st = geo.ba_footprints(R, g["T"], cam_of(g))
+        assert list(st) == [0, 1, 0]
+        assert np.all(np.isnan(got[1])) and np.all(np.isfinite(got[[0, 2]]))
+        e, s = geo.ba_footprints(np.zeros((0, 3, 3)), np.zeros((0, 3)), cam_of(g))
+        assert e.shape == (0, 5, 3)
+        a = geo.ba_footprint_overlaps(got)
+        assert math.isnan(a[0]) and math.isnan(a[2]) and np.isfinite(a[1])   # pairs (0,1), (1,2) touch image 1
+        assert geo.ba_footprint_overlaps(got[:1]).shape == (0,)
+
+
+def test_overlaps_match_oracle():
+    g = flight()
+    ref_fp, _ = oracle_footprints(g)
+    ref = G.overlaps(ref_fp)
+    with geo_ctx(g) as geo:
+        fp, _ = geo.ba_footprints(g["R"], g["T"], cam_of(g))
+        got = geo.ba_footprint_overlaps(fp)
+        same_in = geo.ba_footprint_overlaps(ref_fp)        # the kernel alone, on the oracle's footprints
+        print("kernel ms", geo.ba_geo_last_ms(), "pairs", got.size, flush=True)
+    area = abs(G.polygon_area(ref_fp[0][:4, :2]))
+    print("max overlap difference", np.abs(got - ref).max(), "m2, same input", np.abs(same_in - ref).max(), flush=True)
+    assert np.array_equal(got == 0.0, ref == 0.0)
+    assert np.abs(got - ref).max() < 1e-6 * area
+    assert np.abs(same_in - ref).max() < 1e-9 * area
+    assert (ref > 0).sum() > g["n_images"]                  # in-strip and cross-strip neighbours exist
+
+
+def transfer_pairs(g, ref_fp, sources):
+    """Ordered (src, dst) pairs of overlapping footprints, src in sources."""
+    n = g["n_images"]
+    pairs = []
+    for i in sources:
+        for j in range(n):
+            if j != i and G.overlap_area(ref_fp[i][:4], ref_fp[j][:4]) > 0.0:
+                pairs.append((i, j))
+    return np.array(pairs, np.int32)
+
+
+def check_transfer(g, uv0, pairs, got_uv, got_fl, got_lam, tol_px=1e-6):
+    W, H = g["width"], g["height"]
+    worst = 0.0
+    lam_done = {}
+    for p, (s, d) in enumerate(pairs):
+        ref_uv, ref_lam, ref_fl = G.transfer_eq3(g["dsm"], g["R"][s], g["T"][s], g["R"][d], g["T"][d], g["f"],
+                                                 g["cx"], g["cy"], W, H, uv0)
+        if s not in lam_done:
+            ok = np.isfinite(ref_lam)
+            assert np.array_equal(ok, np.isfinite(got_lam[s]))
+            assert np.abs(got_lam[s][ok] - ref_lam[ok]).max() < 1e-6
+            lam_done[s] = True
+        near_edge = (np.minimum(np.minimum(ref_uv[:, 0], W - ref_uv[:, 0]),
+                                np.minimum(ref_uv[:, 1], H - ref_uv[:, 1])) < tol_px)
+        sure = ~near_edge
+        assert np.array_equal(got_fl[p][sure], ref_fl[sure]), (s, d)
+        fine = sure & (ref_fl != G.MISS)
+        err = np.abs(got_uv[p][fine] - ref_uv[fine]).max() if fine.any() else 0.0
+        worst = max(worst, err)
+    print("max transferred-centre difference", worst, "px", flush=True)
+    assert worst < tol_px
+
+
+def test_patch_transfer_matches_oracle():
+    g = flight()
+    ref_fp, _ = oracle_footprints(g)
+    uv0 = SG.patch_grid()[::5]                       # 424 patches spread over the image
+    pairs = transfer_pairs(g, ref_fp, [0, 17, 45, 90, 121])
+    print("case transfer", len(pairs), "pairs x", len(uv0), "patches", flush=True)
+    with geo_ctx(g) as geo:
+        uv, fl, lam = geo.ba_patch_transfer(g["R"], g["T"], uv0, pairs, cam_of(g), want_lam=True)
+    assert (fl == 2).any() and (fl == 0).any()
+    check_transfer(g, uv0, pairs, uv, fl, lam)
+
+
+def test_patch_transfer_identity_and_errors():
+    from paper_2511_06152_amd import BAError
+    g = flight(n_strips=1, imgs_per_strip=4)
+    uv0 = SG.patch_grid()
+    with geo_ctx(g) as geo:
+        uv, fl, _ = geo.ba_patch_transfer(g["R"], g["T"], uv0, [(2, 2)], cam_of(g))
+        assert np.all(fl == 0) and np.abs(uv[0] - uv0).max() < 1e-8          # Eq. (3) with k = 0
+        uv, fl, lam = geo.ba_patch_transfer(g["R"], g["T"], uv0, np.zeros((0, 2)), cam_of(g), want_lam=True)
+        assert uv.shape == (0, len(uv0), 2) and np.all(np.isnan(lam))
+        with pytest.raises(BAError) as e:
+            geo.ba_patch_transfer(g["R"], g["T"], uv0, [(0, 4)], cam_of(g))
+        assert e.value.code == -1
+        with pytest.raises(BAError) as e:
+            geo.ba_patch_transfer(g["R"], g["T"], uv0, [(0, 1)], dict(cam_of(g), f=0.0))
+        assert e.value.code == -1
+
+
+def test_full_flight_transfer_sampled():
+    """The configuration the benchmark times: every ordered pair of
+    overlapping footprints of the 160-image flight, all 2120 patches; 300
+    sampled (pair, patch) outputs against the oracle, one by one, and every
+    identity pair (i, i) returning its patch centres."""
+    g = flight()
+    uv0 = SG.patch_grid()
+    with geo_ctx(g) as geo:
+        fp, _ = geo.ba_footprints(g["R"], g["T"], cam_of(g))
+        area = geo.ba_footprint_overlaps(fp)
+        n = g["n_images"]
+        iu, ju = np.triu_indices(n, 1)
+        pos = area > 0
+        pairs = np.concatenate([np.stack([iu[pos], ju[pos]], 1), np.stack([ju[pos], iu[pos]], 1),
+                                np.stack([np.arange(n), np.arange(n)], 1)]).astype(np.int32)
+        uv, fl, lam = geo.ba_patch_transfer(g["R"], g["T"], uv0, pairs, cam_of(g), want_lam=True)
+        print("full flight:", len(pairs), "pairs x", len(uv0), "patches, kernel ms", geo.ba_geo_last_ms(), flush=True)
+    ident = pairs[:, 0] == pairs[:, 1]
+    assert np.all(fl[ident] == 0) and np.abs(uv[ident] - uv0[None]).max() < 1e-8
+    rng = np.random.default_rng(7)
+    W, H = g["width"], g["height"]
+    worst = 0.0
+    for p, q in zip(rng.integers(0, len(pairs), 300), rng.integers(0, len(uv0), 300)):
+        s, d = pairs[p]
+        ref_uv, ref_lam, ref_fl = G.transfer_eq3(g["dsm"], g["R"][s], g["T"][s], g["R"][d], g["T"][d], g["f"],
+                                                 g["cx"], g["cy"], W, H, uv0[q:q + 1])
+        assert abs(lam[s, q] - ref_lam[0]) < 1e-6
+        if min(ref_uv[0, 0], W - ref_uv[0, 0], ref_uv[0, 1], H - ref_uv[0, 1]) > 1e-6:
+            assert fl[p, q] == ref_fl[0]
+        worst = max(worst, float(np.abs(uv[p, q] - ref_uv[0]).max()))
+    print("sampled max difference", worst, "px", flush=True)
+    assert worst < 1e-6
