@@ -55,7 +55,7 @@ FLOP_PAIR = 246
 # HBM traffic per launch of the two block kernels on 64 paper-scale clusters,
 # from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch) over `bench.py --steps 1 --warmup 0 --batch 64 --plain 0 --serve 0
-# --uneven 0 --stream-reps 0 --chain-reps 0 --global-iters 0 --cpu-clusters 0` (the batch
+# --uneven 0 --stream-reps 0 --chain-reps 0 --geo-reps 0 --global-iters 0 --cpu-clusters 0` (the batch
 # runs as S parts on S streams, so a launch covers 1/S of the batch; key
 # (S, kernel)) and the same with `--batch-streams 1` (one launch covers the
 # batch: the kernel alone on the GPU), each scaled by what the same counter reads for a
@@ -344,6 +344,56 @@ def run_chain(args, Context, precision, kw):
                              "matching, 1.11 s per image pair (Table 1)"}, cl
 
 
+def run_geo(args):
+    """Sec. 3.1 on the serving stream's flight (4 strips x 40 images over a
+    12 m DSM): the 160 footprints (corner and centre rays intersected with the
+    DSM), the overlap areas of all 12,720 footprint pairs, and the Eq. (3)
+    transfer of all 2120 patch centres (150 px grid) of every image into every
+    image whose footprint overlaps it (and into itself).  Device time of each
+    call's kernels from HIP events, best of `geo_reps`; the projection
+    kernel's roofline position (HBM: 16-byte uv and 4-byte flag per output,
+    32-byte ground point per source patch read once).  Returns the report
+    and the inputs (for the oracle timing)."""
+    from synth import geo as SG
+    from paper_2511_06152_amd import Geo
+    g = SG.make_geo_flight(21)
+    cam = {k: g[k] for k in ("f", "cx", "cy", "width", "height")}
+    uv0 = SG.patch_grid()
+    n = g["n_images"]
+    t_fp, t_ov, t_tr, t_pr = [], [], [], []
+    with Geo(g["dsm"]) as geo:
+        for rep in range(args.geo_reps + 1):
+            fp, st = geo.ba_footprints(g["R"], g["T"], cam)
+            t_fp.append(geo.ba_geo_last_ms())
+            area = geo.ba_footprint_overlaps(fp)
+            t_ov.append(geo.ba_geo_last_ms())
+            if rep == 0:
+                iu, ju = np.triu_indices(n, 1)
+                pos = area > 0
+                pairs = np.concatenate([np.stack([iu[pos], ju[pos]], 1), np.stack([ju[pos], iu[pos]], 1),
+                                        np.stack([np.arange(n), np.arange(n)], 1)]).astype(np.int32)
+            uv, fl, _ = geo.ba_patch_transfer(g["R"], g["T"], uv0, pairs, cam)
+            t_tr.append(geo.ba_geo_last_ms())
+            t_pr.append(geo.ba_geo_last_ms(last_kernel=True))
+    best = lambda v: float(min(v[1:])) if len(v) > 1 else float(v[0])   # the first call loads the code object
+    P, Q = len(pairs), len(uv0)
+    outputs = P * Q
+    byts = outputs * (16 + 4) + n * Q * 32 + P * 8 + n * 96
+    pr_ms = best(t_pr)
+    ach = byts / (pr_ms * 1e-3) / 1e9
+    rep = {"images": n, "dsm_nodes": [g["dsm"]["nx"], g["dsm"]["ny"]], "dsm_cell_m": g["dsm"]["cell"],
+           "footprints_ms": best(t_fp), "rays_footprint": 5 * n,
+           "overlap_pairs": n * (n - 1) // 2, "overlapping_pairs": int((area > 0).sum()), "overlaps_ms": best(t_ov),
+           "transfer_pairs": P, "patches": Q, "transfers": outputs, "reinitialised": int((fl == 2).sum()),
+           "transfer_ms": best(t_tr), "transfers_per_s": outputs / (best(t_tr) * 1e-3),
+           "project_roofline": {"bound": "hbm", "kernel": "k_project", "achieved": ach, "peak": 8000.0,
+                                "unit": "GB/s", "frac": ach / 8000.0, "algorithmic_bytes": byts,
+                                "avg_launch_us": pr_ms * 1e3}}
+    log(f"geo: footprints {rep['footprints_ms'] * 1e3:.1f} us, overlaps {rep['overlaps_ms'] * 1e3:.1f} us, "
+        f"transfer {rep['transfer_ms'] * 1e3:.1f} us ({outputs} outputs; projection {pr_ms * 1e3:.1f} us)")
+    return rep, (g, cam, uv0, pairs)
+
+
 def run_global(args, Context, precision):
     """Whole-flight global adjustment: 400 cameras (10 strips x 40), 800k points,
     ~3.5M observations; the reduced camera system (m = 2400) by block-Jacobi
@@ -413,6 +463,8 @@ def main():
     ap.add_argument("--chain-reps", type=int, default=5,
                     help="repetitions of the chained 60-image flight (clusters of 12 reusing 3 images, Eq. 8 "
                          "fusion; 0: skip)")
+    ap.add_argument("--geo-reps", type=int, default=5,
+                    help="timed repetitions of the footprint / overlap / Eq. (3) transfer leg (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -591,6 +643,9 @@ def main():
     # ---- the paper's chained flight: clusters of 12 reusing 3 images, Eq. (8) fusion --------
     chain, chain_cl = run_chain(args, Context, BA_MIXED, kw) if args.chain_reps > 0 else (None, None)
 
+    # ---- footprints, overlaps and Eq. (3) patch transfer over the DSM (Sec. 3.1) -------------
+    geo, geo_in = run_geo(args) if args.geo_reps > 0 else (None, None)
+
     # ---- whole-flight global adjustment (PCG on the reduced camera system) ------------------
     glob, glob_scene = run_global(args, Context, BA_MIXED) if args.global_iters > 0 else (None, None)
 
@@ -633,6 +688,18 @@ def main():
             cpu["chain_s_per_flight"] = time.perf_counter() - t0
             cpu["chain_sample"] = (f"the chained {len(chain_cl)}-cluster flight once, same termination rule, "
                                    "single-threaded")
+        if geo_in is not None:
+            from oracle import geo as OG
+            g, cam, uv0, pairs = geo_in
+            t0 = time.perf_counter()
+            n_out = 0
+            for s_, d_ in pairs[:: max(1, len(pairs) // 8)][:8]:
+                OG.transfer_eq3(g["dsm"], g["R"][s_], g["T"][s_], g["R"][d_], g["T"][d_], cam["f"], cam["cx"],
+                                cam["cy"], cam["width"], cam["height"], uv0)
+                n_out += len(uv0)
+            dt = time.perf_counter() - t0
+            cpu["geo_transfers_per_s"] = n_out / dt
+            cpu["geo_sample"] = f"{n_out} Eq. (3) transfers (8 pairs x {len(uv0)} patches), single-threaded numpy"
         if glob_scene is not None and args.global_oracle_iters > 0:
             t0 = time.perf_counter()
             oracle.solve(glob_scene, max_iters=args.global_oracle_iters)
@@ -680,6 +747,7 @@ def main():
         "batched_uneven": uneven,
         "serving_stream": stream,
         "paper_chain": chain,
+        "geo": geo,
         "global_ba": glob,
     }
     print(json.dumps(out), flush=True)

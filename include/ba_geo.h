@@ -8,9 +8,9 @@
  * footprints that finds overlapping images, within and across flight strips,
  * for a cluster's membership, and the GNSS/IMU-based patch transfer of
  * Eq. (3), which carries each patch centre of an image into the images that
- * overlap it, with the patch's depth taken from the DSM (the "a-priori known
- * elevation model" case of Eq. 3) and re-initialisation at the opposite
- * edge for patches that leave the image.
+ * overlap it, with the patch's depth taken from the DSM (Eq. 3 with a known
+ * elevation model instead of flat ground) and re-initialisation at the
+ * opposite edge for patches that leave the image.
  *
  * Conventions (as in ba.h)
  *   R camera->world rotation, row-major 3x3; T projection centre; camera z
@@ -29,8 +29,10 @@
  *   raster's highest and lowest nodes, in n equal steps with n =
  *   ceil(horizontal travel / half a cell), at least 1 and at most 65536;
  *   the first sample at or below the surface and the sample before it
- *   bracket the crossing, which up to 64 halvings narrow; the result is the
- *   bracket's final upper end.  A ray that does not descend misses.
+ *   bracket the crossing, which a safeguarded Illinois (modified regula
+ *   falsi) iteration narrows to 1e-12 of the depth (at most 64 steps); the
+ *   result is the bracket's final upper end.  A ray that does not descend
+ *   misses.
  *
  * Memory and threads
  *   Every array is a HOST pointer owned by the caller, read (inputs) or

@@ -6,14 +6,15 @@
 //   k_footprint_rays, k_patch_rays
 //               one thread per pixel ray: the ray's first crossing with the
 //               bilinear DSM (marched in half-cell steps of horizontal
-//               travel, then bisected).  Footprints: five rays per image
+//               travel, then refined by a safeguarded Illinois iteration).  Footprints: five rays per image
 //               (corners and centre).  Patch transfer: one ray per patch of
 //               each source image; the crossing is kept as (x, y, z, lam).
 //   k_overlap   one workgroup per footprint i, its threads over j > i: area of
 //               the intersection of the two corner quadrilaterals
 //               (Sutherland-Hodgman clip of one convex polygon by the other).
-//   k_project   one thread per (pair, patch): Eq. (3)'s projection of the
-//               source patch's ground point into the destination image and
+//   k_project   one thread per (source image, patch), looping over the
+//               source's destination images: Eq. (3)'s projection of the
+//               patch's ground point (read once) into each destination and
 //               the wrap-around re-initialisation; coalesced 16-byte uv
 //               stores, the dominant traffic of the transfer.
 // The DSM heights (float32) stay in device memory for the context's life; a
@@ -33,12 +34,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxSteps = 65536;     // march steps per ray, at most
-constexpr int kHalvings = 64;
+constexpr int kRefine = 64;         // root-refinement iterations per ray, at most
 
 struct Dsm {
   const float* h;                    // [ny][nx]
   int nx, ny;
-  double x0, y0, cell, hmin, hmax;
+  double x0, y0, cell, inv_cell, hmin, hmax;
 };
 
 struct Cam {
@@ -46,31 +47,36 @@ struct Cam {
   int w, hgt;
 };
 
-// Bilinear height at (x, y), the position clamped to the raster.
-__device__ double dsm_h(const Dsm& m, double x, double y) {
-  double gx = (x - m.x0) / m.cell, gy = (y - m.y0) / m.cell;
+// Bilinear height at (x, y), the position clamped to the raster; the heights
+// are read from `h` (the global raster, or its copy in LDS).
+__device__ __forceinline__ double dsm_h(const Dsm& m, const float* h, double x, double y) {
+  double gx = (x - m.x0) * m.inv_cell, gy = (y - m.y0) * m.inv_cell;
   gx = fmin(fmax(gx, 0.0), (double)(m.nx - 1));
   gy = fmin(fmax(gy, 0.0), (double)(m.ny - 1));
   const int i = min((int)floor(gx), m.nx - 2), j = min((int)floor(gy), m.ny - 2);
   const double fx = gx - i, fy = gy - j;
-  const float* r0 = m.h + (size_t)j * m.nx + i;
+  const float* r0 = h + (size_t)j * m.nx + i;
   const float* r1 = r0 + m.nx;
   const double a = r0[0], b = r0[1], c = r1[0], d = r1[1];
   return (1.0 - fx) * (1.0 - fy) * a + fx * (1.0 - fy) * b + (1.0 - fx) * fy * c + fx * fy * d;
 }
 
 // Height of the ray above the surface at depth lam.
-__device__ double ray_gap(const Dsm& m, const double T[3], const double d[3], double lam) {
-  return T[2] + lam * d[2] - dsm_h(m, T[0] + lam * d[0], T[1] + lam * d[1]);
+__device__ __forceinline__ double ray_gap(const Dsm& m, const float* h, const double T[3], const double d[3],
+                                          double lam) {
+  return T[2] + lam * d[2] - dsm_h(m, h, T[0] + lam * d[0], T[1] + lam * d[1]);
 }
 
-// First crossing of T + lam d with the DSM; false when the ray misses.
-__device__ bool ray_dsm(const Dsm& m, const double T[3], const double d[3], double* lam_out) {
+// First crossing of T + lam d with the DSM (heights read from h); false when
+// the ray misses.
+__device__ __forceinline__ bool ray_dsm(const Dsm& m, const float* h, const double T[3], const double d[3],
+                                        double* lam_out) {
   if (!(d[2] < 0.0)) return false;
   const double lam_a = fmax(0.0, (T[2] - m.hmax) / -d[2]);
   const double lam_b = (T[2] - m.hmin) / -d[2];
   if (!(lam_b > 0.0)) return false;
-  if (ray_gap(m, T, d, lam_a) <= 0.0) {
+  const double g_a = ray_gap(m, h, T, d, lam_a);
+  if (g_a <= 0.0) {
     *lam_out = lam_a;
     return true;
   }
@@ -80,20 +86,43 @@ __device__ bool ray_dsm(const Dsm& m, const double T[3], const double d[3], doub
     const double steps = ceil((lam_b - lam_a) * dxy / (0.5 * m.cell));
     n = steps >= (double)kMaxSteps ? kMaxSteps : max(1, (int)steps);
   }
-  double lo = lam_a, hi = lam_b;
+  double lo = lam_a, hi = lam_b, glo = g_a, ghi = 1.0;
   for (int s = 1; s <= n; ++s) {
     const double lam = s == n ? lam_b : lam_a + (lam_b - lam_a) * s / n;
-    if (ray_gap(m, T, d, lam) <= 0.0) {
+    const double gs = ray_gap(m, h, T, d, lam);
+    if (gs <= 0.0) {
       hi = lam;
+      ghi = gs;
       break;
     }
     lo = lam;
+    glo = gs;
   }
-  for (int it = 0; it < kHalvings; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (ray_gap(m, T, d, mid) > 0.0) lo = mid;
-    else hi = mid;
+  if (ghi > 0.0) {           // rounding kept the lowest sample above the surface: no crossing to refine
+    *lam_out = lam_b;
+    return true;
+  }
+  // Illinois (modified regula falsi) inside the bracket, the midpoint when
+  // the secant point leaves it; until the bracket is within 1e-12 of the
+  // depth or a sample lands on the surface.
+  int side = 0;
+  for (int it = 0; it < kRefine && hi - lo > 1e-12 * hi; ++it) {
+    double mid = hi - ghi * (hi - lo) / (ghi - glo);
+    if (!(mid > lo && mid < hi)) mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    const double gm = ray_gap(m, h, T, d, mid);
+    if (gm > 0.0) {
+      lo = mid;
+      glo = gm;
+      if (side < 0) ghi *= 0.5;
+      side = -1;
+    } else {
+      hi = mid;
+      ghi = gm;
+      if (side > 0) glo *= 0.5;
+      side = 1;
+      if (gm == 0.0) break;
+    }
   }
   *lam_out = hi;
   return true;
@@ -109,6 +138,7 @@ __device__ void pixel_dir(const double* R, const Cam& k, double u, double v, dou
 __global__ __launch_bounds__(kBlock) void k_footprint_rays(Dsm m, Cam k, int n, const double* __restrict__ R,
                                                            const double* __restrict__ T, double* __restrict__ ground,
                                                            int* __restrict__ ray_ok) {
+  const float* h = m.h;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= 5 * n) return;
   const int img = r / 5, c = r % 5;
@@ -118,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_footprint_rays(Dsm m, Cam k, int n, 
   pixel_dir(R + 9 * (size_t)img, k, u, v, d);
   for (int t = 0; t < 3; ++t) Tc[t] = T[3 * (size_t)img + t];
   double lam;
-  const bool ok = ray_dsm(m, Tc, d, &lam);
+  const bool ok = ray_dsm(m, h, Tc, d, &lam);
   for (int t = 0; t < 3; ++t) ground[3 * (size_t)r + t] = ok ? Tc[t] + lam * d[t] : NAN;
   ray_ok[r] = ok ? 1 : 0;
 }
@@ -128,6 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_footprint_rays(Dsm m, Cam k, int n, 
 __global__ __launch_bounds__(kBlock) void k_patch_rays(Dsm m, Cam k, int n_src, int n_patch, const int* __restrict__ src,
                                                        const double* __restrict__ R, const double* __restrict__ T,
                                                        const double* __restrict__ uv0, double4* __restrict__ gp) {
+  const float* h = m.h;
   const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (size_t)n_src * n_patch) return;
   const int slot = (int)(r / n_patch), q = (int)(r % n_patch);
@@ -136,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_patch_rays(Dsm m, Cam k, int n_src, 
   pixel_dir(R + 9 * (size_t)img, k, uv0[2 * (size_t)q], uv0[2 * (size_t)q + 1], d);
   for (int t = 0; t < 3; ++t) Tc[t] = T[3 * (size_t)img + t];
   double lam;
-  if (ray_dsm(m, Tc, d, &lam)) gp[r] = make_double4(Tc[0] + lam * d[0], Tc[1] + lam * d[1], Tc[2] + lam * d[2], lam);
+  if (ray_dsm(m, h, Tc, d, &lam)) gp[r] = make_double4(Tc[0] + lam * d[0], Tc[1] + lam * d[1], Tc[2] + lam * d[2], lam);
   else gp[r] = make_double4(NAN, NAN, NAN, NAN);
 }
 
@@ -210,16 +241,26 @@ __global__ __launch_bounds__(kBlock) void k_overlap(int n, const double* __restr
   }
 }
 
-// Eq. (3): the ground point of source patch q projected into image dst, then
-// wrapped into the image (re-initialisation at the opposite edge).
-__global__ __launch_bounds__(kBlock) void k_project(Cam k, int n_patch, size_t total, const int* __restrict__ pairs,
-                                                    const int* __restrict__ slot_of, const double* __restrict__ R,
-                                                    const double* __restrict__ T, const double4* __restrict__ gp,
-                                                    double2* __restrict__ uv, int* __restrict__ flags) {
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    const int p = (int)(t / n_patch), q = (int)(t % n_patch);
-    const int src = pairs[2 * p], dst = pairs[2 * p + 1];
-    const double4 g = gp[(size_t)slot_of[src] * n_patch + q];
+// Eq. (3): the ground point of source patch q projected into each image the
+// source is paired with, then wrapped into the image (re-initialisation at
+// the opposite edge).  One thread per (source, patch): the ground point is
+// read once and each destination's camera is uniform across the workgroup
+// (blockIdx.y = source slot).  Pair e of source slot s (e in
+// [src_off[s], src_off[s+1])) writes row pidx[e] of uv and flags.
+__global__ __launch_bounds__(kBlock) void k_project(Cam k, int n_patch, int slot0, const int* __restrict__ src_off,
+                                                    const int* __restrict__ pidx, const int* __restrict__ pdst,
+                                                    const double* __restrict__ R, const double* __restrict__ T,
+                                                    const double4* __restrict__ gp, double2* __restrict__ uv,
+                                                    int* __restrict__ flags) {
+  const int slot = slot0 + blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_patch) return;
+  const double4 g = gp[(size_t)slot * n_patch + q];
+  const bool hit = isfinite(g.w);
+  const int e1 = src_off[slot + 1];
+  for (int e = src_off[slot]; e < e1; ++e) {
+    const int dst = pdst[e];
+    const size_t row = (size_t)pidx[e] * n_patch + q;
     const double* Rd = R + 9 * (size_t)dst;
     const double dx = g.x - T[3 * (size_t)dst], dy = g.y - T[3 * (size_t)dst + 1], dz = g.z - T[3 * (size_t)dst + 2];
     const double xc = Rd[0] * dx + Rd[3] * dy + Rd[6] * dz;
@@ -227,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_project(Cam k, int n_patch, size_t t
     const double zc = Rd[2] * dx + Rd[5] * dy + Rd[8] * dz;
     int fl = BA_GEO_OK;
     double u = NAN, v = NAN;
-    if (!isfinite(g.w) || !(zc > 0.0)) {
+    if (!hit || !(zc > 0.0)) {
       fl = BA_GEO_MISS;
     } else {
       u = k.f * xc / zc + k.cx;
@@ -238,8 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_project(Cam k, int n_patch, size_t t
         fl = BA_GEO_REINIT;
       }
     }
-    uv[t] = make_double2(u, v);
-    flags[t] = fl;
+    uv[row] = make_double2(u, v);
+    flags[row] = fl;
   }
 }
 
@@ -335,7 +376,7 @@ int ba_geo_create(int32_t device, const ba_dsm* dsm, ba_geo** out) {
     if (hipEventCreate(&e) != hipSuccess) return bail(BA_E_DEVICE);
   if (hipMalloc(&g->d_h, nn * sizeof(float)) != hipSuccess) return bail(BA_E_NOMEM);
   if (hipMemcpy(g->d_h, dsm->h, nn * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return bail(BA_E_DEVICE);
-  g->dsm = Dsm{g->d_h, dsm->nx, dsm->ny, dsm->x0, dsm->y0, dsm->cell, hmin, hmax};
+  g->dsm = Dsm{g->d_h, dsm->nx, dsm->ny, dsm->x0, dsm->y0, dsm->cell, 1.0 / dsm->cell, hmin, hmax};
   *out = g;
   return BA_OK;
 }
@@ -430,21 +471,35 @@ int ba_patch_transfer(ba_geo* g, int32_t n_img, const double* R, const double* T
   if (lam)
     for (size_t i = 0; i < (size_t)n_img * n_patch; ++i) lam[i] = NAN;
   if (n_src == 0) return BA_OK;
+  // pairs grouped by source slot (counting sort, stable in pair order)
+  std::vector<int> src_off(n_src + 1, 0), pidx(n_pairs), pdst(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) ++src_off[slot_of[pairs[2 * p]] + 1];
+  for (int s = 0; s < n_src; ++s) src_off[s + 1] += src_off[s];
+  {
+    std::vector<int> fill(src_off.begin(), src_off.end() - 1);
+    for (int p = 0; p < n_pairs; ++p) {
+      const int e = fill[slot_of[pairs[2 * p]]]++;
+      pidx[e] = p;
+      pdst[e] = pairs[2 * p + 1];
+    }
+  }
   const size_t rays = (size_t)n_src * n_patch, total = (size_t)n_pairs * n_patch;
   GEOCHK(g, hipSetDevice(g->device));
-  void *dR, *dT, *dUv0, *dSrc, *dSlot, *dPairs, *dGp, *dUv, *dFl;
+  void *dR, *dT, *dUv0, *dSrc, *dOff, *dPidx, *dPdst, *dGp, *dUv, *dFl;
   int rc;
   if ((rc = buf(g, 0, 72 * (size_t)n_img, &dR)) || (rc = buf(g, 1, 24 * (size_t)n_img, &dT)) ||
       (rc = buf(g, 5, 16 * (size_t)n_patch, &dUv0)) || (rc = buf(g, 6, 4 * (size_t)n_src, &dSrc)) ||
-      (rc = buf(g, 7, 4 * (size_t)n_img, &dSlot)) || (rc = buf(g, 8, 8 * (size_t)n_pairs, &dPairs)) ||
-      (rc = buf(g, 9, 32 * rays, &dGp)) || (rc = buf(g, 10, 16 * total, &dUv)) || (rc = buf(g, 11, 4 * total, &dFl)))
+      (rc = buf(g, 7, 4 * (size_t)(n_src + 1), &dOff)) || (rc = buf(g, 8, 4 * (size_t)n_pairs, &dPidx)) ||
+      (rc = buf(g, 12, 4 * (size_t)n_pairs, &dPdst)) || (rc = buf(g, 9, 32 * rays, &dGp)) ||
+      (rc = buf(g, 10, 16 * total, &dUv)) || (rc = buf(g, 11, 4 * total, &dFl)))
     return rc;
   GEOCHK(g, hipMemcpyAsync(dR, R, 72 * (size_t)n_img, hipMemcpyHostToDevice, g->stream));
   GEOCHK(g, hipMemcpyAsync(dT, T, 24 * (size_t)n_img, hipMemcpyHostToDevice, g->stream));
   GEOCHK(g, hipMemcpyAsync(dUv0, uv0, 16 * (size_t)n_patch, hipMemcpyHostToDevice, g->stream));
   GEOCHK(g, hipMemcpyAsync(dSrc, src.data(), 4 * (size_t)n_src, hipMemcpyHostToDevice, g->stream));
-  GEOCHK(g, hipMemcpyAsync(dSlot, slot_of.data(), 4 * (size_t)n_img, hipMemcpyHostToDevice, g->stream));
-  GEOCHK(g, hipMemcpyAsync(dPairs, pairs, 8 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dOff, src_off.data(), 4 * (size_t)(n_src + 1), hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dPidx, pidx.data(), 4 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dPdst, pdst.data(), 4 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
   GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
   const Cam k = to_cam(cam);
   hipLaunchKernelGGL(k_patch_rays, dim3((unsigned)((rays + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream, g->dsm, k,
@@ -453,11 +508,14 @@ int ba_patch_transfer(ba_geo* g, int32_t n_img, const double* R, const double* T
   GEOCHK(g, hipGetLastError());
   GEOCHK(g, hipEventRecord(g->ev[1], g->stream));
   if (total > 0) {
-    const size_t blocks = std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(kBlock), 0, g->stream, k, n_patch, total,
-                       (const int*)dPairs, (const int*)dSlot, (const double*)dR, (const double*)dT,
-                       (const double4*)dGp, (double2*)dUv, (int*)dFl);
-    GEOCHK(g, hipGetLastError());
+    const unsigned bx = (unsigned)((n_patch + kBlock - 1) / kBlock);
+    for (int s0 = 0; s0 < n_src; s0 += 65535) {
+      const unsigned by = (unsigned)std::min(65535, n_src - s0);
+      hipLaunchKernelGGL(k_project, dim3(bx, by), dim3(kBlock), 0, g->stream, k, n_patch, s0, (const int*)dOff,
+                         (const int*)dPidx, (const int*)dPdst, (const double*)dR, (const double*)dT,
+                         (const double4*)dGp, (double2*)dUv, (int*)dFl);
+      GEOCHK(g, hipGetLastError());
+    }
   }
   if ((rc = finish(g, true))) return rc;
   if (total > 0) {

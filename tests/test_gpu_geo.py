@@ -180,3 +180,17 @@ def test_full_flight_transfer_sampled():
         worst = max(worst, float(np.abs(uv[p, q] - ref_uv[0]).max()))
     print("sampled max difference", worst, "px", flush=True)
     assert worst < 1e-6
+
+
+def test_fine_dsm():
+    """A 3 m raster (89,600 nodes; more march steps per ray): the same parity."""
+    g = flight(n_strips=2, imgs_per_strip=10, cell=3.0)
+    assert g["dsm"]["nx"] * g["dsm"]["ny"] > 16384
+    ref, _ = oracle_footprints(g)
+    uv0 = SG.patch_grid()[::11]
+    pairs = np.array([(0, 1), (0, 3), (12, 4), (7, 7)], np.int32)
+    with geo_ctx(g) as geo:
+        got, st = geo.ba_footprints(g["R"], g["T"], cam_of(g))
+        uv, fl, lam = geo.ba_patch_transfer(g["R"], g["T"], uv0, pairs, cam_of(g), want_lam=True)
+    assert np.all(st == 0) and np.abs(got - ref).max() < 1e-6
+    check_transfer(g, uv0, pairs, uv, fl, lam)
