@@ -164,6 +164,78 @@ Layout make_layout(const Staged& s, bool mixed) {
   return l;
 }
 
+// splitmix64 finaliser: spreads IDs over a power-of-two table.
+inline uint64_t mix_id(int64_t id) {
+  uint64_t z = (uint64_t)id + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Global ID -> row, open addressing with linear probing (the resident store's
+// index; looked up for every camera and point of every resident cluster).
+class IdMap {
+ public:
+  const int* find(int64_t id) const {
+    if (n_ == 0) return nullptr;
+    for (size_t h = mix_id(id) & mask_;; h = (h + 1) & mask_) {
+      if (!used_[h]) return nullptr;
+      if (key_[h] == id) return &val_[h];
+    }
+  }
+  void insert(int64_t id, int v) {     // id must not be present
+    if (2 * (n_ + 1) > key_.size()) grow();
+    size_t h = mix_id(id) & mask_;
+    while (used_[h]) h = (h + 1) & mask_;
+    used_[h] = 1;
+    key_[h] = id;
+    val_[h] = v;
+    ++n_;
+  }
+  size_t size() const { return n_; }
+
+ private:
+  void grow() {
+    const size_t cap = key_.empty() ? 1024 : 2 * key_.size();
+    std::vector<int64_t> k(cap);
+    std::vector<int> v(cap);
+    std::vector<uint8_t> u(cap, 0);
+    const size_t m = cap - 1;
+    for (size_t i = 0; i < key_.size(); ++i)
+      if (used_[i]) {
+        size_t h = mix_id(key_[i]) & m;
+        while (u[h]) h = (h + 1) & m;
+        u[h] = 1;
+        k[h] = key_[i];
+        v[h] = val_[i];
+      }
+    key_.swap(k);
+    val_.swap(v);
+    used_.swap(u);
+    mask_ = m;
+  }
+  std::vector<int64_t> key_;
+  std::vector<int> val_;
+  std::vector<uint8_t> used_;
+  size_t mask_ = 0, n_ = 0;
+};
+
+// True when the n IDs are pairwise distinct.
+bool ids_unique(const int64_t* id, int n) {
+  size_t cap = 16;
+  while (cap < 2 * (size_t)n) cap <<= 1;
+  std::vector<int64_t> key(cap);
+  std::vector<uint8_t> used(cap, 0);
+  for (int i = 0; i < n; ++i) {
+    size_t h = mix_id(id[i]) & (cap - 1);
+    for (; used[h]; h = (h + 1) & (cap - 1))
+      if (key[h] == id[i]) return false;
+    used[h] = 1;
+    key[h] = id[i];
+  }
+  return true;
+}
+
 bool finite_all(const double* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -205,10 +277,8 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   if (c->fuse_resident && !c->use_resident) { err = "fuse_resident needs use_resident"; return BA_E_ARG; }
   if (c->use_resident) {
     if (!c->cam_ids || (P > 0 && !c->point_ids)) { err = "use_resident needs cam_ids and point_ids"; return BA_E_ARG; }
-    std::unordered_set<int64_t> seen(c->cam_ids, c->cam_ids + C);
-    if ((int)seen.size() != C) { err = "duplicate camera ID in the cluster"; return BA_E_ARG; }
-    seen = std::unordered_set<int64_t>(c->point_ids, c->point_ids + P);
-    if ((int)seen.size() != P) { err = "duplicate point ID in the cluster"; return BA_E_ARG; }
+    if (!ids_unique(c->cam_ids, C)) { err = "duplicate camera ID in the cluster"; return BA_E_ARG; }
+    if (!ids_unique(c->point_ids, P)) { err = "duplicate point ID in the cluster"; return BA_E_ARG; }
   }
   s = Staged();
   s.C = C; s.P = P; s.O = O;
@@ -250,7 +320,8 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
     if (cam < 0 || cam >= C || pt < 0 || pt >= P) { err = "observation index out of range"; return BA_E_ARG; }
   }
   // Internal point order: Morton (z-order) of the initial ground position, so
-  // that a camera's observations touch nearby point records.
+  // that a camera's observations touch nearby point records.  Ties keep the
+  // caller's order (LSD radix sort of key << 32 | index on the key bits).
   {
     double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
     for (int j = 0; j < P; ++j)
@@ -258,7 +329,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
         lo[t] = std::min(lo[t], c->X[3 * (size_t)j + t]);
         hi[t] = std::max(hi[t], c->X[3 * (size_t)j + t]);
       }
-    std::vector<uint32_t> key(P);
+    std::vector<uint64_t> kj(P), tmp(P);
     for (int j = 0; j < P; ++j) {
       uint32_t q[2];
       for (int t = 0; t < 2; ++t) {
@@ -268,11 +339,17 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
       }
       uint32_t k = 0;
       for (int b = 0; b < 16; ++b) k |= ((q[0] >> b) & 1u) << (2 * b) | ((q[1] >> b) & 1u) << (2 * b + 1);
-      key[j] = k;
+      kj[j] = (uint64_t)k << 32 | (uint32_t)j;
+    }
+    for (int shift = 32; shift < 64; shift += 11) {
+      size_t cnt_d[2049] = {0};
+      for (int j = 0; j < P; ++j) ++cnt_d[((kj[j] >> shift) & 2047u) + 1];
+      for (int d = 0; d < 2048; ++d) cnt_d[d + 1] += cnt_d[d];
+      for (int j = 0; j < P; ++j) tmp[cnt_d[(kj[j] >> shift) & 2047u]++] = kj[j];
+      kj.swap(tmp);
     }
     s.pt_orig.resize(P);
-    for (int j = 0; j < P; ++j) s.pt_orig[j] = j;
-    std::stable_sort(s.pt_orig.begin(), s.pt_orig.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (int n = 0; n < P; ++n) s.pt_orig[n] = (int)(uint32_t)kj[n];
   }
   std::vector<int> inv(P), opt(O);
   for (int n = 0; n < P; ++n) inv[s.pt_orig[n]] = n;
@@ -285,18 +362,28 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   for (int o = 0; o < O; ++o)
     if (++cnt[opt[o] + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
   for (int j = 0; j < P; ++j) cnt[j + 1] += cnt[j];
+  // observations in (point, camera) order: a counting sort by camera, then a
+  // stable one by point; then their camera, pixel and point in that order
   std::vector<int> order(O);
   {
+    std::vector<int> by_cam(O), cc(C + 1, 0);
+    for (int o = 0; o < O; ++o) ++cc[c->obs_cam[o] + 1];
+    for (int k = 0; k < C; ++k) cc[k + 1] += cc[k];
+    for (int o = 0; o < O; ++o) by_cam[cc[c->obs_cam[o]]++] = o;
     std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-    for (int o = 0; o < O; ++o) order[fill[opt[o]]++] = o;
+    for (int t = 0; t < O; ++t) order[fill[opt[by_cam[t]]]++] = by_cam[t];
   }
-  for (int j = 0; j < P; ++j) {
-    int* b = order.data() + cnt[j];
-    const int n = cnt[j + 1] - cnt[j];
-    std::sort(b, b + n, [&](int x, int y) { return c->obs_cam[x] < c->obs_cam[y]; });
-    for (int i = 1; i < n; ++i)
-      if (c->obs_cam[b[i]] == c->obs_cam[b[i - 1]]) { err = "a camera observes one point twice"; return BA_E_ARG; }
-  }
+  std::vector<int> scam(O), spt(O);
+  std::vector<double> suv(2 * (size_t)O);
+  for (int j = 0; j < P; ++j)
+    for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
+      const int o = order[t];
+      scam[t] = c->obs_cam[o];
+      spt[t] = j;
+      suv[2 * (size_t)t] = c->obs_uv[2 * (size_t)o];
+      suv[2 * (size_t)t + 1] = c->obs_uv[2 * (size_t)o + 1];
+      if (t > cnt[j] && scam[t] == scam[t - 1]) { err = "a camera observes one point twice"; return BA_E_ARG; }
+    }
   // greedy packing into 64-lane chunks
   std::vector<int> start(P, 0);
   int pos = 0;
@@ -319,12 +406,12 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   for (int j = 0; j < P; ++j) {
     const int n = cnt[j + 1] - cnt[j];
     for (int t = 0; t < n; ++t) {
-      const int o = order[cnt[j] + t], lane = start[j] + t;
+      const int so = cnt[j] + t, lane = start[j] + t;
       s.lane_pt[lane] = j;
-      s.lane_meta[lane] = c->obs_cam[o] | ((start[j] % kWave) << 9) | (n << 15);
+      s.lane_meta[lane] = scam[so] | ((start[j] % kWave) << 9) | (n << 15);
       chunk_max[lane / kWave] = std::max(chunk_max[lane / kWave], n);
-      s.lane_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
-      s.lane_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
+      s.lane_uv[2 * (size_t)lane] = suv[2 * (size_t)so];
+      s.lane_uv[2 * (size_t)lane + 1] = suv[2 * (size_t)so + 1];
     }
   }
   for (int i = 0; i < s.L; ++i) s.lane_meta[i] |= chunk_max[i / kWave] << 22;
@@ -336,69 +423,92 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   std::vector<int> free_cam(F);
   for (int k = 0; k < C; ++k)
     if (s.cam_col[k] >= 0) free_cam[s.cam_col[k] / 6] = k;
-  // camera lanes and tasks
-  std::vector<std::vector<int>> cam_obs(F);
-  for (int j = 0; j < P; ++j)
-    for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
-      const int o = order[t], col = s.cam_col[c->obs_cam[o]];
-      if (col >= 0) cam_obs[col / 6].push_back(o);
-      (void)j;
+  // camera lanes and tasks: each free camera's observations in point order
+  std::vector<int> coff(F + 1, 0);
+  for (int t = 0; t < O; ++t) {
+    const int col = s.cam_col[scam[t]];
+    if (col >= 0) ++coff[col / 6 + 1];
+  }
+  for (int fi = 0; fi < F; ++fi) coff[fi + 1] += coff[fi];
+  std::vector<int> cobs(coff[F]);
+  {
+    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    for (int t = 0; t < O; ++t) {
+      const int col = s.cam_col[scam[t]];
+      if (col >= 0) cobs[fill[col / 6]++] = t;
     }
+  }
+  for (int fi = 0; fi < F; ++fi) s.Lc += (int)align_up(coff[fi + 1] - coff[fi], kWave);
+  s.cl_pt.assign(s.Lc, -1);
+  s.cl_uv.assign(2 * (size_t)s.Lc, 0.0);
   std::vector<int2> cam_range(F);
-  for (int fi = 0; fi < F; ++fi) {
-    const int base = s.Lc / kWave;
-    const int n = (int)cam_obs[fi].size();
-    s.Lc += (int)align_up(n, kWave);
-    s.cl_pt.resize(s.Lc, -1);
-    s.cl_uv.resize(2 * (size_t)s.Lc, 0.0);
+  for (int fi = 0, base = 0; fi < F; ++fi) {
+    const int n = coff[fi + 1] - coff[fi];
     for (int t = 0; t < n; ++t) {
-      const int o = cam_obs[fi][t], lane = base * kWave + t;
-      s.cl_pt[lane] = opt[o];
-      s.cl_uv[2 * (size_t)lane] = c->obs_uv[2 * (size_t)o];
-      s.cl_uv[2 * (size_t)lane + 1] = c->obs_uv[2 * (size_t)o + 1];
+      const int so = cobs[coff[fi] + t];
+      const size_t lane = (size_t)base * kWave + t;
+      s.cl_pt[lane] = spt[so];
+      s.cl_uv[2 * lane] = suv[2 * (size_t)so];
+      s.cl_uv[2 * lane + 1] = suv[2 * (size_t)so + 1];
     }
     const int nch = (int)(align_up(n, kWave) / kWave);
     cam_range[fi].x = (int)s.tasks.size();
     for (int ch = 0; ch < nch; ch += cpt) s.tasks.push_back(mk4(TASK_CAM, free_cam[fi], 0, base + ch, std::min(cpt, nch - ch)));
     cam_range[fi].y = (int)s.tasks.size();
+    base += nch;
   }
   s.n_cam_tasks = (int)s.tasks.size();
-  // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order
+  // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order;
+  // within a block the pairs (point, obs a, obs b) in point order
   const int nblk = F * (F - 1) / 2;
   auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
-  std::vector<std::vector<int3>> pairs(nblk);   // (point, obs a, obs b)
+  std::vector<int> poff(nblk + 1, 0);
   for (int j = 0; j < P; ++j)
     for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
-      const int oa = order[ta], ca = s.cam_col[c->obs_cam[oa]];
+      const int ca = s.cam_col[scam[ta]];
       if (ca < 0) continue;
       for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
-        const int ob = order[tb], cb = s.cam_col[c->obs_cam[ob]];
-        if (cb < 0) continue;
-        pairs[blk(ca / 6, cb / 6)].push_back(make_int3(j, oa, ob));
+        const int cb = s.cam_col[scam[tb]];
+        if (cb >= 0) ++poff[blk(ca / 6, cb / 6) + 1];
       }
     }
+  for (int b = 0; b < nblk; ++b) poff[b + 1] += poff[b];
+  std::vector<int3> pairs(poff[nblk]);
+  {
+    std::vector<int> fill(poff.begin(), poff.end() - 1);
+    for (int j = 0; j < P; ++j)
+      for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
+        const int ca = s.cam_col[scam[ta]];
+        if (ca < 0) continue;
+        for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
+          const int cb = s.cam_col[scam[tb]];
+          if (cb >= 0) pairs[fill[blk(ca / 6, cb / 6)]++] = make_int3(j, ta, tb);
+        }
+      }
+  }
+  auto blk_empty = [&](int b) { return poff[b + 1] == poff[b]; };
+  for (int b = 0; b < nblk; ++b) s.Lq += (int)align_up(poff[b + 1] - poff[b], kWave);
+  s.ql_pt.assign(s.Lq, -1);
+  s.ql_uv.assign(4 * (size_t)s.Lq, 0.0);
   std::vector<int2> blk_range(nblk);
-  for (int fa = 0; fa < F; ++fa)
+  for (int fa = 0, base = 0; fa < F; ++fa)
     for (int fb = fa + 1; fb < F; ++fb) {
-      const auto& pl = pairs[blk(fa, fb)];
-      const int base = s.Lq / kWave;
-      const int n = (int)pl.size();
-      s.Lq += (int)align_up(n, kWave);
-      s.ql_pt.resize(s.Lq, -1);
-      s.ql_uv.resize(4 * (size_t)s.Lq, 0.0);
+      const int b = blk(fa, fb), n = poff[b + 1] - poff[b];
       for (int t = 0; t < n; ++t) {
+        const int3 pr = pairs[poff[b] + t];
         const size_t lane = (size_t)base * kWave + t;
-        s.ql_pt[lane] = pl[t].x;
-        s.ql_uv[4 * lane] = c->obs_uv[2 * (size_t)pl[t].y];
-        s.ql_uv[4 * lane + 1] = c->obs_uv[2 * (size_t)pl[t].y + 1];
-        s.ql_uv[4 * lane + 2] = c->obs_uv[2 * (size_t)pl[t].z];
-        s.ql_uv[4 * lane + 3] = c->obs_uv[2 * (size_t)pl[t].z + 1];
+        s.ql_pt[lane] = pr.x;
+        s.ql_uv[4 * lane] = suv[2 * (size_t)pr.y];
+        s.ql_uv[4 * lane + 1] = suv[2 * (size_t)pr.y + 1];
+        s.ql_uv[4 * lane + 2] = suv[2 * (size_t)pr.z];
+        s.ql_uv[4 * lane + 3] = suv[2 * (size_t)pr.z + 1];
       }
       const int nch = (int)(align_up(n, kWave) / kWave);
-      blk_range[blk(fa, fb)].x = (int)s.tasks.size();
+      blk_range[b].x = (int)s.tasks.size();
       for (int ch = 0; ch < nch; ch += cpt)
         s.tasks.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], base + ch, std::min(cpt, nch - ch)));
-      blk_range[blk(fa, fb)].y = (int)s.tasks.size();
+      blk_range[b].y = (int)s.tasks.size();
+      base += nch;
     }
   for (int fi = 0; fi < F; ++fi) s.targets.push_back(mk4(TASK_CAM, free_cam[fi], 0, cam_range[fi].x, cam_range[fi].y));
   if (!s.sparse) {
@@ -416,7 +526,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   std::vector<std::vector<int>> nbr(F);
   for (int fa = 0; fa < F; ++fa)
     for (int fb = fa + 1; fb < F; ++fb)
-      if (!pairs[blk(fa, fb)].empty()) {
+      if (!blk_empty(blk(fa, fb))) {
         nbr[fa].push_back(fb);
         nbr[fb].push_back(fa);
       }
@@ -437,7 +547,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   for (int fi = 0; fi < F; ++fi) s.tslot.push_back(make_int2(diag_slot[fi], diag_slot[fi]));
   for (int fa = 0; fa < F; ++fa)
     for (int fb = fa + 1; fb < F; ++fb) {
-      if (pairs[blk(fa, fb)].empty()) continue;
+      if (blk_empty(blk(fa, fb))) continue;
       const int2 r = blk_range[blk(fa, fb)];
       s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
       s.tslot.push_back(make_int2(slot_of[{fa, fb}], slot_of[{fb, fa}]));
@@ -529,7 +639,7 @@ struct ba_ctx {
   double* res_cam = nullptr;      // [cap][12]
   double* res_cam_w = nullptr;    // [cap] match-count weight of each pose (Eq. 8)
   double* res_pt = nullptr;       // [cap][3]
-  std::unordered_map<int64_t, int> res_cam_row, res_pt_row;
+  IdMap res_cam_row, res_pt_row;
   std::vector<ResRow> res_cam_meta, res_pt_meta;
   double res_lambda = NAN;        // damping the last written-back cluster ended with
 };
@@ -668,23 +778,25 @@ int res_register(ba_ctx* c, Ticket& t, const Staged& s) {
       return fail(c, BA_E_DEVICE, "cannot clear the resident weights");
   }
   size_t new_c = 0, new_p = 0;
-  for (int64_t id : s.cam_ids) new_c += c->res_cam_row.count(id) ? 0 : 1;
-  for (int64_t id : s.point_ids) new_p += c->res_pt_row.count(id) ? 0 : 1;
+  for (int64_t id : s.cam_ids) new_c += c->res_cam_row.find(id) ? 0 : 1;
+  for (int64_t id : s.point_ids) new_p += c->res_pt_row.find(id) ? 0 : 1;
   if (c->res_cam_meta.size() + new_c > (size_t)capC || c->res_pt_meta.size() + new_p > (size_t)capP)
     return fail(c, BA_E_NOMEM, "resident store full");
   std::unordered_set<ba_ticket> deps;
-  auto reg = [&](int64_t id, std::unordered_map<int64_t, int>& rows, std::vector<ba_ctx::ResRow>& meta) {
-    auto it = rows.find(id);
+  ba_ticket seen = 0;              // the last earlier writer looked at (runs of IDs share one)
+  auto reg = [&](int64_t id, IdMap& rows, std::vector<ba_ctx::ResRow>& meta) {
+    const int* r = rows.find(id);
     int row;
-    if (it == rows.end()) {
+    if (!r) {
       row = (int)meta.size();
-      rows.emplace(id, row);
+      rows.insert(id, row);
       meta.emplace_back();
     } else {
-      row = it->second;
+      row = *r;
     }
     const ba_ticket p = meta[row].pending;
-    if (p) {
+    if (p && p != seen) {
+      seen = p;
       auto pt = c->tickets.find(p);
       if (pt != c->tickets.end() && !pt->second->res_done) deps.insert(p);
     }
@@ -1427,16 +1539,16 @@ int ba_resident_poses(ba_ctx* c, int32_t n, const int64_t* ids, double* R, doubl
   std::lock_guard<std::mutex> g(c->mu);
   std::vector<int> rows(n);
   for (int i = 0; i < n; ++i) {
-    auto it = c->res_cam_row.find(ids[i]);
-    if (it == c->res_cam_row.end()) return fail(c, BA_E_ARG, "camera ID never submitted");
-    const ba_ctx::ResRow& m = c->res_cam_meta[it->second];
+    const int* r = c->res_cam_row.find(ids[i]);
+    if (!r) return fail(c, BA_E_ARG, "camera ID never submitted");
+    const ba_ctx::ResRow& m = c->res_cam_meta[*r];
     if (m.pending) {
       auto pt = c->tickets.find(m.pending);
       if (pt != c->tickets.end() && !pt->second->res_done)
         return fail(c, BA_E_STATE, "camera ID has an unfinished writer");
     }
     if (!m.valid) return fail(c, BA_E_ARG, "camera ID never written back");
-    rows[i] = it->second;
+    rows[i] = *r;
   }
   if (n == 0) return BA_OK;
   HIPCHK(c, hipSetDevice(c->device));

@@ -194,3 +194,25 @@ def test_fine_dsm():
         uv, fl, lam = geo.ba_patch_transfer(g["R"], g["T"], uv0, pairs, cam_of(g), want_lam=True)
     assert np.all(st == 0) and np.abs(got - ref).max() < 1e-6
     check_transfer(g, uv0, pairs, uv, fl, lam)
+
+
+def test_flat_nominal_depth_mode():
+    """Eq. (3) with a flat nominal depth (GNSS/IMU only, no elevation model):
+    a constant 2 x 2 raster at the nominal ground height; the oracle on the
+    same raster, and the closed form of a pure translation."""
+    g = flight(n_strips=2, imgs_per_strip=5)
+    h0 = 25.0
+    flat = SG.plane_dsm(2, 2, -1e5, -1e5, 2e5, 0.0, 0.0, h0)
+    uv0 = SG.patch_grid()[::7]
+    pairs = np.array([(0, 1), (0, 2), (3, 8), (9, 4)], np.int32)
+    from paper_2511_06152_amd import Geo
+    with Geo(flat) as geo:
+        uv, fl, lam = geo.ba_patch_transfer(g["R"], g["T"], uv0, pairs, cam_of(g), want_lam=True)
+        R = np.stack([np.diag([1.0, -1.0, -1.0])] * 2)            # nadir, same attitude
+        T = np.array([[0.0, 0.0, 325.0], [3.0, -7.5, 325.0]])
+        uv2, fl2, _ = geo.ba_patch_transfer(R, T, uv0, [(0, 1)], cam_of(g))
+    g_flat = dict(g, dsm=flat)
+    check_transfer(g_flat, uv0, pairs, uv, fl, lam)
+    shift = -(g["f"] / 300.0) * (R[0].T @ (T[1] - T[0]))[:2]
+    inner = fl2[0] == 0
+    assert inner.any() and np.abs(uv2[0][inner] - (uv0[inner] + shift)).max() < 1e-8
