@@ -219,11 +219,10 @@ def run_uneven(args, Context, precision, kw):
     sctx = Context(precision=precision, serve=True, max_slots=N, hbm_budget_bytes=int(0.25 * total),
                    chunks_per_task=args.chunks_per_task)
     t0 = time.perf_counter()
-    tickets = []
-    for i in range(N):
-        t = sctx.submit(scs[i % len(scs)], **kw)
+    # they arrive together: one batched submit lays them out on host threads
+    tickets = sctx.submit_many([scs[i % len(scs)] for i in range(N)], **kw)
+    for t in tickets:
         sctx.ba_solve(t)
-        tickets.append(t)
     lat = []
     for t in tickets:
         sctx.ba_wait(t)
@@ -303,8 +302,8 @@ def run_chain(args, Context, precision, kw):
     into clusters of 12 that reuse the last three images of the cluster
     before (the first of them fixed, the other two free and fused by Eq. 8 on
     write-back), each with up to 8 overlapping images of the previous strip
-    (fixed).  All clusters go to the serving loop at once; their shared IDs
-    order them, so the flight runs as a chain.  Reports the flight's wall
+    (fixed).  All clusters go to the serving loop at once (one batched
+    submit); their shared IDs order them, so the flight runs as a chain.  Reports the flight's wall
     time (first submit to last result), per-cluster latency, and the mean and
     standard deviation of the reprojection error norms at each cluster's
     solution.  Returns the report and the clusters (for the oracle timing)."""
@@ -315,11 +314,9 @@ def run_chain(args, Context, precision, kw):
     for rep in range(args.chain_reps):
         ctx = Context(precision=precision, serve=True, max_slots=4, hbm_budget_bytes=1 << 30)
         t0 = time.perf_counter()
-        ts = []
-        for sc in cl:
-            t = ctx.submit(sc, use_resident=True, fuse_resident=True, **kw)
+        ts = ctx.submit_many(cl, use_resident=True, fuse_resident=True, **kw)
+        for t in ts:
             ctx.ba_solve(t)
-            ts.append(t)
         res = []
         for t in ts:
             ctx.ba_wait(t)

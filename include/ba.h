@@ -217,6 +217,16 @@ int ba_destroy(ba_ctx* ctx);
  * store is full), BA_E_AGAIN (queue full), BA_E_DEVICE. */
 int ba_submit_cluster(ba_ctx* ctx, const ba_cluster* cluster, ba_ticket* ticket);
 
+/* Submit n clusters that arrive together (clusters [n]): they are validated
+ * and laid out on up to 8 host threads at once, then queued in array order,
+ * exactly as n calls of ba_submit_cluster in that order would (resident IDs
+ * order them the same way).  Writes tickets [n].  A cluster that fails
+ * validation fails the call before any is queued (BA_E_ARG, the message
+ * names its index; every ticket 0).  A later error (BA_E_NOMEM: resident
+ * store full, BA_E_AGAIN: queue full, BA_E_DEVICE) leaves the clusters
+ * before it queued with their tickets, and the rest with ticket 0. */
+int ba_submit_clusters(ba_ctx* ctx, int32_t n, const ba_cluster* clusters, ba_ticket* tickets);
+
 /* Run up to n_iters LM iterations of one cluster now, on the calling thread,
  * reading the LM status back after every iteration (the plain, host-driven
  * loop).  Admits the cluster first if it is still queued.  A resident cluster

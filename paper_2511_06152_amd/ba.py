@@ -22,7 +22,7 @@ BA_MAX_FREE_CAMS = 24
 BA_MAX_CAMS = 512
 BA_MAX_OBS_PER_POINT = 64
 
-EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
+EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_submit_clusters", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error", "ba_resident_poses", "ba_geo_create", "ba_geo_destroy", "ba_footprints",
             "ba_footprint_overlaps", "ba_patch_transfer", "ba_geo_last_ms", "ba_geo_last_error"]
@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
     L.ba_create.argtypes = [ct.POINTER(ba_options), ct.POINTER(P)]
     L.ba_destroy.argtypes = [P]
     L.ba_submit_cluster.argtypes = [P, ct.POINTER(ba_cluster), ct.POINTER(ct.c_int64)]
+    L.ba_submit_clusters.argtypes = [P, ct.c_int32, ct.POINTER(ba_cluster), ct.POINTER(ct.c_int64)]
     L.ba_step.argtypes = [P, ct.c_int64, ct.c_int32]
     L.ba_solve_batch.argtypes = [P, ct.POINTER(ct.c_int64), ct.c_int32]
     L.ba_solve.argtypes = [P, ct.c_int64]
@@ -206,6 +207,22 @@ class Context:
 
     def submit(self, sc: dict, **kw) -> int:
         return self.ba_submit_cluster(Cluster(sc, **kw))
+
+    def ba_submit_clusters(self, cls) -> list:
+        """Submit clusters that arrive together (laid out on host threads, queued in order)."""
+        n = len(cls)
+        arr = (ba_cluster * max(n, 1))(*[c.c for c in cls])
+        t = (ct.c_int64 * max(n, 1))()
+        try:
+            self._chk(self.lib.ba_submit_clusters(self.h, n, arr, t), "ba_submit_clusters")
+        finally:
+            for i, c in enumerate(cls):
+                if t[i]:
+                    self.meta[t[i]] = (c.C, c.P, c.max_iters)
+        return [t[i] for i in range(n)]
+
+    def submit_many(self, scenes, **kw) -> list:
+        return self.ba_submit_clusters([Cluster(sc, **kw) for sc in scenes])
 
     def ba_footprint(self, cl: Cluster) -> int:
         return int(self.lib.ba_footprint(self.h, ct.byref(cl.c)))

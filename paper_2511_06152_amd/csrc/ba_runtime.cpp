@@ -17,6 +17,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <atomic>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -1242,6 +1243,10 @@ int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
 
 }  // namespace
 
+namespace {
+int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket);
+}  // namespace
+
 extern "C" {
 
 const char* ba_strerror(int code) {
@@ -1371,6 +1376,49 @@ int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
   std::lock_guard<std::mutex> g(c->mu);
   if (rc) return fail(c, rc, err);
+  return enqueue_staged(c, std::move(st), ticket);
+}
+
+int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* tickets) {
+  if (!c || n < 0 || (n > 0 && (!cl || !tickets))) return BA_E_ARG;
+  for (int i = 0; i < n; ++i) tickets[i] = 0;
+  std::vector<std::unique_ptr<Staged>> st(n);
+  std::vector<int> rc(n, BA_OK);
+  std::vector<std::string> err(n);
+  {
+    // lay the clusters out on up to 8 host threads; they share nothing
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      for (int i; (i = next.fetch_add(1)) < n;) {
+        st[i] = std::make_unique<Staged>();
+        rc[i] = stage(&cl[i], *st[i], err[i], c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
+      }
+    };
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::min({n, hw, 8});
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
+  }
+  std::lock_guard<std::mutex> g(c->mu);
+  for (int i = 0; i < n; ++i)
+    if (rc[i]) return fail(c, rc[i], "cluster " + std::to_string(i) + ": " + err[i]);
+  for (int i = 0; i < n; ++i) {
+    const int r = enqueue_staged(c, std::move(st[i]), &tickets[i]);
+    if (r) return r;
+  }
+  return BA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Queues a laid-out cluster (registering its resident IDs) and returns its
+// ticket.  Caller holds mu.
+int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket) {
+  int rc;
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
   const size_t bytes = make_layout(*st, c->opt.precision == BA_MIXED).total;
   if (bytes > c->arena.size()) return fail(c, BA_E_NOMEM, "cluster footprint exceeds the arena");
@@ -1391,6 +1439,10 @@ int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   *ticket = id;
   return BA_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int ba_step(ba_ctx* c, ba_ticket id, int32_t n_iters) {
   if (!c) return BA_E_ARG;

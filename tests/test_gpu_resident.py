@@ -327,3 +327,50 @@ def test_resident_rejects_duplicate_ids():
         with pytest.raises(BAError) as e:
             ctx.submit(sc, max_iters=2, use_resident=True)
         assert e.value.code == -1
+
+
+def test_batched_submit_equals_single():
+    """ba_submit_clusters (layout on host threads, queued in array order):
+    the chained stream through the serving loop gives the same results,
+    bit for bit, as submitting the clusters one by one."""
+    from paper_2511_06152_amd import Context
+    from paper_2511_06152_amd.ba import Cluster
+    cl = small_stream()["clusters"][:6]
+    res = {}
+    ref = api_chain(cl, 8, precision=MIXED, fuse=True, ctx_out=res)
+    with Context(precision=MIXED, serve=True, max_slots=8) as ctx:
+        ts = ctx.ba_submit_clusters([Cluster(sc, max_iters=8, use_resident=True, fuse_resident=True) for sc in cl])
+        assert len(set(ts)) == len(cl) and ts == sorted(ts)
+        for t in ts:
+            ctx.ba_solve(t)
+        got = []
+        for t in ts:
+            ctx.ba_wait(t)
+            got.append(ctx.ba_fetch(t))
+        poses = ctx.ba_resident_poses(res["ids"])
+    for a, g in zip(ref, got):
+        for key in ("R", "T", "X", "cost_log"):
+            assert np.array_equal(a[key], g[key]), key
+    for a, g in zip(res["poses"], poses):
+        assert np.array_equal(a, g)
+
+
+def test_batched_submit_rejects_before_queueing():
+    """One invalid cluster fails the whole call before any is queued: the
+    valid ones submitted afterwards run with no pending writers in the way."""
+    from paper_2511_06152_amd import BAError, Context
+    from paper_2511_06152_amd.ba import Cluster
+    cl = small_stream()["clusters"][:3]
+    bad = dict(cl[1])
+    ids = bad["point_ids"].copy()
+    ids[1] = ids[0]
+    bad["point_ids"] = ids
+    with Context(precision=FP64) as ctx:
+        with pytest.raises(BAError) as e:
+            ctx.ba_submit_clusters([Cluster(sc, max_iters=3, use_resident=True) for sc in (cl[0], bad, cl[2])])
+        assert e.value.code == -1 and "cluster 1" in str(e.value)
+        ts = ctx.ba_submit_clusters([Cluster(sc, max_iters=3, use_resident=True) for sc in cl])
+        for t in ts:
+            ctx.ba_step(t, 3)
+            assert ctx.ba_fetch(t)["iterations"] == 3
+        assert ctx.ba_submit_clusters([]) == []
