@@ -195,10 +195,11 @@ def run_uneven(args, Context, precision, kw):
     foot = [probe.ba_footprint(Cluster(sc, **kw)) for sc in scs]
     probe.close()
     budget = int(sum(foot[i % len(scs)] for i in range(N)) * 1.02) + (64 << 20)
-    ctx = Context(precision=precision, max_slots=N, hbm_budget_bytes=budget, chunks_per_task=args.chunks_per_task)
+    ctx = Context(precision=precision, max_slots=N, hbm_budget_bytes=budget, chunks_per_task=args.chunks_per_task,
+                  batch_streams=args.batch_streams, iters_per_tick=args.iters_per_tick)
     times, iters, its_max = [], 0, 0
     for step in range(1 + max(args.steps // 2, 1)):
-        tickets = [ctx.submit(scs[i % len(scs)], **kw) for i in range(N)]
+        tickets = ctx.submit_many([scs[i % len(scs)] for i in range(N)], **kw)
         for t in tickets:
             ctx.ba_step(t, 0)
         t0 = time.perf_counter()
@@ -213,6 +214,15 @@ def run_uneven(args, Context, precision, kw):
             its_max = max(its_max, max(its))
         log(f"uneven step {step}{'' if step else ' (warmup)'}: {dt * 1e3:.1f} ms for {N} clusters")
     ctx.close()
+    cams = [scs[i % len(scs)]["n_cams"] for i in range(N)]
+    pts = [scs[i % len(scs)]["n_points"] for i in range(N)]
+    obs = [scs[i % len(scs)]["n_obs"] for i in range(N)]
+    rep = {"clusters": N, "distinct": len(scs), "clusters_per_s": N / float(np.mean(times)),
+           "ms_per_batch": 1e3 * float(np.mean(times)), "mean_iterations": iters / (N * len(times)),
+           "max_iterations": its_max, "cams_range": [min(cams), max(cams)],
+           "points_range": [min(pts), max(pts)], "obs_total": int(sum(obs)), "hbm_budget_bytes": budget}
+    if not args.uneven_serve:
+        return rep
     # the same clusters through the serving loop under a quarter of their total
     # footprint: admission by HBM budget, continuous batching
     total = sum(foot[i % len(scs)] for i in range(N))
@@ -232,16 +242,9 @@ def run_uneven(args, Context, precision, kw):
     wall = time.perf_counter() - t0
     sctx.close()
     log(f"uneven, quarter budget through the serving loop: {wall * 1e3:.1f} ms for {N} clusters")
-    budgeted = {"hbm_budget_bytes": int(0.25 * total), "total_footprint_bytes": int(total),
-                "clusters_per_s": N / wall, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)}
-    cams = [scs[i % len(scs)]["n_cams"] for i in range(N)]
-    pts = [scs[i % len(scs)]["n_points"] for i in range(N)]
-    obs = [scs[i % len(scs)]["n_obs"] for i in range(N)]
-    return {"clusters": N, "distinct": len(scs), "clusters_per_s": N / float(np.mean(times)),
-            "ms_per_batch": 1e3 * float(np.mean(times)), "mean_iterations": iters / (N * len(times)),
-            "max_iterations": its_max, "cams_range": [min(cams), max(cams)],
-            "points_range": [min(pts), max(pts)], "obs_total": int(sum(obs)), "hbm_budget_bytes": budget,
-            "serving_quarter_budget": budgeted}
+    rep["serving_quarter_budget"] = {"hbm_budget_bytes": int(0.25 * total), "total_footprint_bytes": int(total),
+                                     "clusters_per_s": N / wall, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)}
+    return rep
 
 
 def run_stream(args, Context, precision, kw):
@@ -449,6 +452,8 @@ def main():
     ap.add_argument("--uneven", type=int, default=256,
                     help="clusters of the uneven batched workload (6-24 cameras, 5k-60k points; 0: skip)")
     ap.add_argument("--uneven-scenes", type=int, default=64, help="distinct seeded uneven clusters (cycled)")
+    ap.add_argument("--uneven-serve", type=int, default=1,
+                    help="also pass the uneven clusters through the serving loop under a quarter budget (0: skip)")
     ap.add_argument("--global-iters", type=int, default=10,
                     help="LM iterations of the whole-flight global adjustment (400 cameras, 800k points; 0: skip)")
     ap.add_argument("--global-oracle-iters", type=int, default=1,
