@@ -121,6 +121,19 @@ typedef struct {
                                 least 4 S clusters run, so that one part's latency-bound
                                 kernels overlap the others' assembly; 1: one stream;
                                 0 -> 2; at most 4, else BA_E_ARG */
+  /* Device-memory provider, e.g. PyTorch's caching allocator.  With both
+   * set, every device allocation of the context (the arena, the slot
+   * tables, the launch lists, the resident store) is dev_alloc(bytes,
+   * alloc_user), and each is returned by dev_free(ptr, alloc_user) before
+   * ba_destroy returns (or before a failing ba_create returns).  A block
+   * must be device memory of the context's device, aligned to 256 bytes,
+   * valid until freed; NULL means out of memory (BA_E_NOMEM).  The hooks
+   * are called from the thread of ba_create, ba_submit_cluster(s) or
+   * ba_destroy, never from the serving thread.  Both NULL: hipMalloc /
+   * hipFree.  Only one of them set: BA_E_ARG. */
+  void* (*dev_alloc)(size_t bytes, void* user);
+  void (*dev_free)(void* ptr, void* user);
+  void* alloc_user;
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */

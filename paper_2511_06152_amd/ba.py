@@ -33,13 +33,43 @@ BA_PROF_KERNELS = ["point", "blocks", "pairblk", "reduce", "solve", "backsub", "
 BA_PROF_ALL = (1 << len(BA_PROF_KERNELS)) - 1
 
 
+DEV_ALLOC = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
+DEV_FREE = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
+
+
 class ba_options(ct.Structure):
     _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("hbm_budget_bytes", ct.c_size_t),
                 ("max_slots", ct.c_int32), ("max_queue", ct.c_int32), ("precision", ct.c_int32),
                 ("serve", ct.c_int32), ("iters_per_tick", ct.c_int32), ("chunks_per_wg", ct.c_int32),
                 ("chunks_per_task", ct.c_int32), ("solver", ct.c_int32), ("pcg_max_iters", ct.c_int32),
                 ("pcg_tol", ct.c_double), ("resident_cams", ct.c_int32), ("resident_points", ct.c_int32),
-                ("batch_streams", ct.c_int32)]
+                ("batch_streams", ct.c_int32), ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE),
+                ("alloc_user", ct.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory for a context from PyTorch's caching allocator (the
+    ba_options.dev_alloc / dev_free hooks): each block is a uint8 tensor kept
+    alive until the library frees it."""
+
+    def __init__(self, device: int):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self.c_alloc = DEV_ALLOC(self._alloc)
+        self.c_free = DEV_FREE(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self._torch.empty(max(int(nbytes), 1), dtype=self._torch.uint8, device=f"cuda:{self.device}")
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
 
 
 class ba_cluster(ct.Structure):
@@ -168,11 +198,18 @@ class Context:
                  max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
                  chunks_per_wg: int = 16, chunks_per_task: int = 4, solver: int = BA_SOLVER_AUTO,
                  pcg_max_iters: int = 500, pcg_tol: float = 0.1, resident_cams: int = 0,
-                 resident_points: int = 0, batch_streams: int = 0):
+                 resident_points: int = 0, batch_streams: int = 0, allocator=None):
+        """allocator: None (hipMalloc) or "torch" (PyTorch's caching allocator)."""
         self.lib = load()
         opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
                          iters_per_tick, chunks_per_wg, chunks_per_task, solver, pcg_max_iters, pcg_tol,
                          resident_cams, resident_points, batch_streams)
+        self.allocator = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator(device)
+            opt.dev_alloc, opt.dev_free = self.allocator.c_alloc, self.allocator.c_free
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
         h = ct.c_void_p()
         rc = self.lib.ba_create(ct.byref(opt), ct.byref(h))
         if rc != BA_OK:

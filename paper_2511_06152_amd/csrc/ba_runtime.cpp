@@ -661,10 +661,31 @@ int fail(ba_ctx* c, int code, const std::string& msg) {
     }                                                                                        \
   } while (0)
 
+// Device memory of the context: the caller's provider when it gave one, else
+// hipMalloc / hipFree.
+hipError_t dmalloc(ba_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (!c->opt.dev_alloc) return hipMalloc(p, bytes);
+  void* q = c->opt.dev_alloc(bytes, c->opt.alloc_user);
+  if (!q) return hipErrorOutOfMemory;
+  if ((uintptr_t)q % 256) {
+    c->opt.dev_free(q, c->opt.alloc_user);
+    return hipErrorInvalidValue;
+  }
+  *p = q;
+  return hipSuccess;
+}
+
+void dfree(ba_ctx* c, void* p) {
+  if (!p) return;
+  if (c->opt.dev_free) c->opt.dev_free(p, c->opt.alloc_user);
+  else (void)hipFree(p);
+}
+
 int init_launcher(ba_ctx* c, Launcher& l) {
   const int S = c->opt.max_slots;
-  HIPCHK(c, hipMalloc(&l.d_act, sizeof(int) * S));
-  HIPCHK(c, hipMalloc(&l.d_wgoff, sizeof(int) * 4 * (S + 1)));
+  HIPCHK(c, dmalloc(c, (void**)&l.d_act, sizeof(int) * S));
+  HIPCHK(c, dmalloc(c, (void**)&l.d_wgoff, sizeof(int) * 4 * (S + 1)));
   HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (S + 4 * (S + 1)), hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc(&l.h_ctl, sizeof(SlotCtl) * S, hipHostMallocDefault));
   HIPCHK(c, hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
@@ -672,9 +693,9 @@ int init_launcher(ba_ctx* c, Launcher& l) {
   return BA_OK;
 }
 
-void free_launcher(Launcher& l) {
-  if (l.d_act) (void)hipFree(l.d_act);
-  if (l.d_wgoff) (void)hipFree(l.d_wgoff);
+void free_launcher(ba_ctx* c, Launcher& l) {
+  dfree(c, l.d_act);
+  dfree(c, l.d_wgoff);
   if (l.h_act) (void)hipHostFree(l.h_act);
   if (l.h_ctl) (void)hipHostFree(l.h_ctl);
   if (l.ev) (void)hipEventDestroy(l.ev);
@@ -770,9 +791,9 @@ int res_register(ba_ctx* c, Ticket& t, const Staged& s) {
   const int capC = c->opt.resident_cams, capP = c->opt.resident_points;
   if (!c->res_cam) {
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, BA_E_DEVICE, "hipSetDevice failed");
-    if (hipMalloc(&c->res_cam, sizeof(double) * 12 * (size_t)capC) != hipSuccess ||
-        hipMalloc(&c->res_cam_w, sizeof(double) * (size_t)capC) != hipSuccess ||
-        hipMalloc(&c->res_pt, sizeof(double) * 3 * (size_t)capP) != hipSuccess) {
+    if (dmalloc(c, (void**)&c->res_cam, sizeof(double) * 12 * (size_t)capC) != hipSuccess ||
+        dmalloc(c, (void**)&c->res_cam_w, sizeof(double) * (size_t)capC) != hipSuccess ||
+        dmalloc(c, (void**)&c->res_pt, sizeof(double) * 3 * (size_t)capP) != hipSuccess) {
       return fail(c, BA_E_NOMEM, "cannot allocate the resident store");
     }
     if (hipMemset(c->res_cam_w, 0, sizeof(double) * (size_t)capC) != hipSuccess)
@@ -1268,6 +1289,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (!opt || !out) return BA_E_ARG;
   *out = nullptr;
   if (opt->precision != BA_FP64 && opt->precision != BA_MIXED) return BA_E_ARG;
+  if ((opt->dev_alloc == nullptr) != (opt->dev_free == nullptr)) return BA_E_ARG;
   // 0 selects a field's default; a negative count is an error
   if (opt->max_slots < 0 || opt->max_queue < 0 || opt->iters_per_tick < 0 || opt->chunks_per_wg < 0 ||
       opt->chunks_per_task < 0 || opt->pcg_max_iters < 0 || opt->pcg_tol < 0 || opt->resident_cams < 0 ||
@@ -1300,27 +1322,29 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return BA_E_DEVICE;
     c->own_stream = true;
   }
-  if (hipMalloc(&c->arena_base, c->opt.hbm_budget_bytes) != hipSuccess) {
-    if (c->own_stream) (void)hipStreamDestroy(c->stream);
-    return BA_E_NOMEM;
-  }
+  // from here on a failure releases what was set up (ba_destroy copes with a
+  // partly built context)
+  auto bail = [&](int code) {
+    ba_destroy(c.release());
+    return code;
+  };
+  if (dmalloc(c.get(), (void**)&c->arena_base, c->opt.hbm_budget_bytes) != hipSuccess) return bail(BA_E_NOMEM);
   c->arena.init(c->opt.hbm_budget_bytes);
-  if (hipMalloc(&c->d_desc, sizeof(SlotDesc) * c->opt.max_slots) != hipSuccess ||
-      hipMalloc(&c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots) != hipSuccess) {
-    return BA_E_NOMEM;
-  }
-  (void)hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots);
+  if (dmalloc(c.get(), (void**)&c->d_desc, sizeof(SlotDesc) * c->opt.max_slots) != hipSuccess ||
+      dmalloc(c.get(), (void**)&c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots) != hipSuccess)
+    return bail(BA_E_NOMEM);
+  if (hipMemset(c->d_ctl, 0, sizeof(SlotCtl) * c->opt.max_slots) != hipSuccess) return bail(BA_E_DEVICE);
   c->slots.resize(c->opt.max_slots);
-  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return BA_E_DEVICE;
-  if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) return BA_E_DEVICE;
+  if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return bail(BA_E_DEVICE);
+  if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) return bail(BA_E_DEVICE);
   for (int p = 1; p < c->opt.batch_streams; ++p) {
     if (init_launcher(c.get(), c->api_p[p]) || init_launcher(c.get(), c->srv_p[p]) ||
         hipStreamCreateWithFlags(&c->stream_p[p], hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->join_ev[p], hipEventDisableTiming) != hipSuccess)
-      return BA_E_DEVICE;
+      return bail(BA_E_DEVICE);
   }
   for (int i = 0; i < c->opt.max_slots; ++i) c->srv.h_ctl[i] = SlotCtl{};
-  if (hipDeviceSynchronize() != hipSuccess) return BA_E_DEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return bail(BA_E_DEVICE);
   ba_ctx* raw = c.release();
   if (opt->serve) raw->th = std::thread(serve_loop, raw);
   *out = raw;
@@ -1339,23 +1363,23 @@ int ba_destroy(ba_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (int p = 1; p < ba_ctx::kMaxParts; ++p)
     if (c->stream_p[p]) (void)hipStreamSynchronize(c->stream_p[p]);
-  free_launcher(c->api);
+  free_launcher(c, c->api);
   for (int p = 1; p < ba_ctx::kMaxParts; ++p) {
-    free_launcher(c->api_p[p]);
-    free_launcher(c->srv_p[p]);
+    free_launcher(c, c->api_p[p]);
+    free_launcher(c, c->srv_p[p]);
     if (c->stream_p[p]) (void)hipStreamDestroy(c->stream_p[p]);
     if (c->join_ev[p]) (void)hipEventDestroy(c->join_ev[p]);
   }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
-  free_launcher(c->srv);
+  free_launcher(c, c->srv);
   for (auto& set : c->prof_ev)
     for (auto& e : set) (void)hipEventDestroy(e);
-  if (c->d_desc) (void)hipFree(c->d_desc);
-  if (c->d_ctl) (void)hipFree(c->d_ctl);
-  if (c->arena_base) (void)hipFree(c->arena_base);
-  if (c->res_cam) (void)hipFree(c->res_cam);
-  if (c->res_cam_w) (void)hipFree(c->res_cam_w);
-  if (c->res_pt) (void)hipFree(c->res_pt);
+  dfree(c, c->d_desc);
+  dfree(c, c->d_ctl);
+  dfree(c, c->arena_base);
+  dfree(c, c->res_cam);
+  dfree(c, c->res_cam_w);
+  dfree(c, c->res_pt);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return BA_OK;

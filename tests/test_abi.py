@@ -46,3 +46,26 @@ def test_strerror_without_gpu():
 def test_binding_names_match_header():
     from paper_2511_06152_amd import ba
     assert sorted(ba.EXPORTED) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libba.so not built")
+def test_options_rejected_before_any_device_call():
+    """Option checks come first, so they answer without a GPU: a negative
+    count, an unknown precision, or only one of the two allocator hooks."""
+    from paper_2511_06152_amd import ba
+    lib = ba.load()
+
+    def create(**kw):
+        o = ba.ba_options(0, None, 1 << 20, 4, 16, ba.BA_FP64, 0, 2, 16, 4, 0, 500, 0.1, 0, 0, 0)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        h = ct.c_void_p()
+        return lib.ba_create(ct.byref(o), ct.byref(h))
+
+    assert create(max_slots=-1) == ba.BA_E_ARG
+    assert create(precision=7) == ba.BA_E_ARG
+    assert create(pcg_tol=-1.0) == ba.BA_E_ARG
+    keep = ba.DEV_ALLOC(lambda n, u: None)
+    assert create(dev_alloc=keep) == ba.BA_E_ARG
+    keep2 = ba.DEV_FREE(lambda p, u: None)
+    assert create(dev_free=keep2) == ba.BA_E_ARG
