@@ -262,7 +262,8 @@ int ba_solve_batch(ba_ctx* ctx, const ba_ticket* tickets, int32_t n);
 int ba_solve(ba_ctx* ctx, ba_ticket ticket);
 
 /* Wait until a cluster handed to ba_solve has terminated.  timeout_s < 0
- * waits forever.  Errors: BA_E_ARG, BA_E_STATE, BA_E_TIMEOUT. */
+ * waits forever.  Errors: BA_E_ARG, BA_E_STATE (not handed to ba_solve, or
+ * released while waiting), BA_E_TIMEOUT. */
 int ba_wait(ba_ctx* ctx, ba_ticket ticket, double timeout_s);
 
 /* Copy the cluster's current (or final) state and statistics into result
@@ -270,8 +271,12 @@ int ba_wait(ba_ctx* ctx, ba_ticket ticket, double timeout_s);
  * BA_E_STATE (still queued or being solved by the serving loop), BA_E_DEVICE. */
 int ba_fetch(ba_ctx* ctx, ba_ticket ticket, ba_result* result);
 
-/* Forget a ticket and free its slot and arena block.  Errors: BA_E_ARG,
- * BA_E_STATE (being solved by the serving loop). */
+/* Forget a ticket and free its slot and arena block.  A cluster handed to
+ * ba_solve and not yet finished is cancelled instead: the call returns at
+ * once and the serving loop drops the cluster at its next tick boundary
+ * (its resident state is not written back, and no later cluster waits for
+ * it); ba_wait on it then returns BA_E_STATE.  Errors: BA_E_ARG (unknown
+ * ticket), BA_E_DEVICE. */
 int ba_release(ba_ctx* ctx, ba_ticket ticket);
 
 /* The device-resident poses of n camera IDs (world frame, as last written

@@ -615,6 +615,7 @@ struct ba_ctx {
   ba_ticket next_id = 1;
   std::mutex mu;
   std::condition_variable cv;     // wakes the serving thread
+  std::vector<ba_ticket> cancel;  // released while the serving loop owns them
   std::condition_variable done_cv;
   std::thread th;
   bool stop = false;
@@ -1191,11 +1192,31 @@ bool serving_queued(ba_ctx* c) {
 }
 
 // One serving tick: retire finished clusters, admit queued ones, iterate.
+Ticket* find_ticket(ba_ctx* c, ba_ticket id);
+
 void serve_loop(ba_ctx* c) {
   (void)hipSetDevice(c->device);
   std::vector<int> active;
   std::unique_lock<std::mutex> lk(c->mu);
   while (!c->stop) {
+    // cancel: clusters released while the loop owned them.  The previous
+    // tick has completed on the device, so their slots can be freed; they
+    // write nothing back, and a ticket that no longer exists holds back no
+    // later cluster.
+    if (!c->cancel.empty()) {
+      for (ba_ticket id : c->cancel) {
+        Ticket* t = find_ticket(c, id);
+        if (!t) continue;
+        if (t->state == TK_RESIDENT) {
+          active.erase(std::remove(active.begin(), active.end(), t->slot), active.end());
+          free_slot(c, t->slot);
+        }
+        c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), id), c->queue.end());
+        c->tickets.erase(id);
+      }
+      c->cancel.clear();
+      c->done_cv.notify_all();
+    }
     // retire
     std::vector<int> fin;
     for (int s : active)
@@ -1224,7 +1245,7 @@ void serve_loop(ba_ctx* c) {
       active.insert(active.end(), adm.begin(), adm.end());
     }
     if (active.empty()) {
-      c->cv.wait(lk, [&] { return c->stop || serving_queued(c); });
+      c->cv.wait(lk, [&] { return c->stop || serving_queued(c) || !c->cancel.empty(); });
       continue;
     }
     if (run_tick(c, true, active, c->opt.iters_per_tick)) break;
@@ -1540,9 +1561,15 @@ int ba_wait(ba_ctx* c, ba_ticket id, double timeout_s) {
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
   if (!t->serving && t->state != TK_DONE) return fail(c, BA_E_STATE, "cluster was not handed to ba_solve");
-  auto pred = [&] { return t->state == TK_DONE || c->dead; };
+  // the ticket may be released (and removed) while this thread waits
+  auto pred = [&] {
+    Ticket* x = find_ticket(c, id);
+    return !x || x->state == TK_DONE || c->dead;
+  };
   if (timeout_s < 0) c->done_cv.wait(lk, pred);
   else if (!c->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return BA_E_TIMEOUT;
+  t = find_ticket(c, id);
+  if (!t) return fail(c, BA_E_STATE, "cluster was released while waiting");
   if (c->dead && t->state != TK_DONE) return fail(c, BA_E_DEVICE, "serving loop stopped on a device error");
   return BA_OK;
 }
@@ -1648,7 +1675,11 @@ int ba_release(ba_ctx* c, ba_ticket id) {
   std::lock_guard<std::mutex> g(c->mu);
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
-  if (t->serving) return fail(c, BA_E_STATE, "cluster is being solved by the serving loop");
+  if (t->serving) {   // cancelled: the serving loop drops it at its next tick boundary
+    if (std::find(c->cancel.begin(), c->cancel.end(), id) == c->cancel.end()) c->cancel.push_back(id);
+    c->cv.notify_all();
+    return BA_OK;
+  }
   if (t->state == TK_RESIDENT) {
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -240,6 +240,53 @@ def test_serving_loop_equals_alone():
         assert b["t_done"] >= b["t_admit"] >= b["t_submit"] > 0
 
 
+def test_release_cancels_serving_clusters():
+    """ba_release on clusters handed to the serving loop cancels them (one
+    still queued, one likely iterating); the others finish bit-identical to
+    each solved alone, and waiting on a cancelled one reports BA_E_STATE."""
+    from paper_2511_06152_amd import BAError, Context
+    scenes = [A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + (i % 3), n_points=400 + 300 * i), 80 + i)
+              for i in range(6)]
+    kw = dict(max_iters=30, stop_on_ftol=False)
+    with Context(precision=MIXED) as ctx:
+        alone = []
+        for sc in scenes:
+            t = ctx.submit(sc, **kw)
+            ctx.ba_solve_batch([t])
+            alone.append(ctx.ba_fetch(t))
+    with Context(precision=MIXED, serve=True, max_slots=2, iters_per_tick=1) as ctx:
+        ts = []
+        for sc in scenes:
+            t = ctx.submit(sc, **kw)
+            ctx.ba_solve(t)
+            ts.append(t)
+        gone = {ts[1], ts[4]}
+        for t in gone:
+            ctx.ba_release(t)
+        for i, t in enumerate(ts):
+            if t in gone:
+                with pytest.raises(BAError) as e:
+                    ctx.ba_wait(t, 60.0)
+                assert e.value.code in (-1, -4)      # removed already, or removed while waiting
+                continue
+            ctx.ba_wait(t, 60.0)
+            r = ctx.ba_fetch(t)
+            assert np.array_equal(r["cost_log"], alone[i]["cost_log"])
+            for key in ("R", "T", "X", "k"):
+                assert np.array_equal(r[key], alone[i][key]), key
+
+
+def test_full_queue_is_back_pressure():
+    from paper_2511_06152_amd import BAError, Context
+    sc = A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2, n_points=200), 90)
+    with Context(precision=FP64, max_queue=2) as ctx:
+        ctx.submit(sc, max_iters=2)
+        ctx.submit(sc, max_iters=2)
+        with pytest.raises(BAError) as e:
+            ctx.submit(sc, max_iters=2)
+        assert e.value.code == -3
+
+
 def test_admission_by_arena_budget():
     """Clusters larger than what is free wait in the queue; one larger than the
     whole arena is refused."""
