@@ -68,7 +68,7 @@ def lib():
         L.or_residuals.restype = ct.c_int
         L.or_residuals.argtypes = [P] * 11
         L.or_jacobians.restype = None
-        L.or_jacobians.argtypes = [P] * 9
+        L.or_jacobians.argtypes = [P] * 10
         L.or_prior.restype = None
         L.or_prior.argtypes = [P] * 5
         L.or_cost.restype = ct.c_double
@@ -120,22 +120,40 @@ def _scene(sc) -> Scene:
     return sc if isinstance(sc, Scene) else Scene(sc)
 
 
+SELF_CAL = 0b11100    # intr_mask bits of f, cx, cy
+
+
 def initial_state(sc: dict):
+    """(R, T, X, k); k = (k1, k2), or (k1, k2, f, cx, cy) when the scene
+    estimates any of f, cx, cy (intr_mask bits 2, 3, 4)."""
+    k = np.array(sc["k"], np.float64).reshape(2)
+    if int(sc["intr_mask"]) & SELF_CAL:
+        k = np.array([k[0], k[1], sc["f"], sc["cx"], sc["cy"]], np.float64)
     return (np.array(sc["R"], np.float64).reshape(-1, 3, 3).copy(),
             np.array(sc["T"], np.float64).reshape(-1, 3).copy(),
             np.array(sc["X"], np.float64).reshape(-1, 3).copy(),
-            np.array(sc["k"], np.float64).reshape(2).copy())
+            k.copy())
 
 
-def _state(state):
+def _state(state, sc):
+    """Contiguous arrays; the intrinsic state widened to (k1, k2, f, cx, cy)
+    with the scene's f, cx, cy when only (k1, k2) is given."""
     R, T, X, k = state
+    k = np.asarray(k, np.float64).reshape(-1)
+    if k.size == 2:
+        k = np.array([k[0], k[1], sc["f"], sc["cx"], sc["cy"]], np.float64)
     return (np.ascontiguousarray(R, np.float64), np.ascontiguousarray(T, np.float64),
             np.ascontiguousarray(X, np.float64), np.ascontiguousarray(k, np.float64))
 
 
+def _k_out(k5, like):
+    """The intrinsic state in the length the caller used (2 or 5)."""
+    return k5.copy() if np.asarray(like).size == 5 else k5[:2].copy()
+
+
 def residuals(sc, state) -> dict:
     S = _scene(sc)
-    R, T, X, k = _state(state)
+    R, T, X, k = _state(state, S.sc)
     O = S.sc["n_obs"]
     out = {n: np.zeros(O * (2 if n in ("uv", "e") else 1)) for n in ("uv", "z", "e", "s", "rho", "w")}
     bad = lib().or_residuals(S.ptr, _p(R), _p(T), _p(X), _p(k), *(_p(out[n]) for n in ("uv", "z", "e", "s", "rho", "w")))
@@ -147,16 +165,17 @@ def residuals(sc, state) -> dict:
 
 def jacobians(sc, state) -> dict:
     S = _scene(sc)
-    R, T, X, k = _state(state)
+    R, T, X, k = _state(state, S.sc)
     O = S.sc["n_obs"]
-    Jw, JT, JX, Jk = (np.zeros((O, 2, 3)), np.zeros((O, 2, 3)), np.zeros((O, 2, 3)), np.zeros((O, 2, 2)))
-    lib().or_jacobians(S.ptr, _p(R), _p(T), _p(X), _p(k), _p(Jw), _p(JT), _p(JX), _p(Jk))
-    return {"Jw": Jw, "JT": JT, "JX": JX, "Jk": Jk}
+    Jw, JT, JX, Jk, Ji = (np.zeros((O, 2, 3)), np.zeros((O, 2, 3)), np.zeros((O, 2, 3)), np.zeros((O, 2, 2)),
+                          np.zeros((O, 2, 3)))
+    lib().or_jacobians(S.ptr, _p(R), _p(T), _p(X), _p(k), _p(Jw), _p(JT), _p(JX), _p(Jk), _p(Ji))
+    return {"Jw": Jw, "JT": JT, "JX": JX, "Jk": Jk, "Ji": Ji}
 
 
 def prior(sc, state):
     S = _scene(sc)
-    R, T, X, k = _state(state)
+    R, T, X, k = _state(state, S.sc)
     C = S.sc["n_cams"]
     e, Jw = np.zeros((C, 6)), np.zeros((C, 3, 3))
     lib().or_prior(S.ptr, _p(R), _p(T), _p(e), _p(Jw))
@@ -165,7 +184,7 @@ def prior(sc, state):
 
 def cost(sc, state) -> float:
     S = _scene(sc)
-    R, T, X, k = _state(state)
+    R, T, X, k = _state(state, S.sc)
     return float(lib().or_cost(S.ptr, _p(R), _p(T), _p(X), _p(k)))
 
 
@@ -179,7 +198,7 @@ def dims(sc):
 def step(sc, state, lam: float):
     """Damped step delta[N] at the state; returns (status, delta, pred)."""
     S = _scene(sc)
-    R, T, X, k = _state(state)
+    R, T, X, k = _state(state, S.sc)
     N, _ = dims(S)
     delta = np.zeros(N)
     pred = ct.c_double()
@@ -189,10 +208,10 @@ def step(sc, state, lam: float):
 
 def apply(sc, state, delta):
     S = _scene(sc)
-    R, T, X, k = _state(state)
+    R, T, X, k = _state(state, S.sc)
     out = (np.zeros_like(R), np.zeros_like(T), np.zeros_like(X), np.zeros_like(k))
     lib().or_apply(S.ptr, _p(R), _p(T), _p(X), _p(k), _p(np.ascontiguousarray(delta, np.float64)), *(_p(a) for a in out))
-    return out
+    return out[0], out[1], out[2], _k_out(out[3], state[3])
 
 
 def solve(sc, state=None, max_iters: int = 10, lambda0: float = 1e-4, ftol: float = 1e-10,
@@ -201,7 +220,7 @@ def solve(sc, state=None, max_iters: int = 10, lambda0: float = 1e-4, ftol: floa
     S = _scene(sc)
     if state is None:
         state = initial_state(S.sc)
-    R, T, X, k = (a.copy() for a in _state(state))
+    R, T, X, k = (a.copy() for a in _state(state, S.sc))
     opt = _Options(max_iters, 1 if stop_on_ftol else 0, lambda0, ftol)
     cost_log = np.full(max_iters + 1, np.nan)
     lam_log = np.full(max_iters, np.nan)
@@ -211,7 +230,8 @@ def solve(sc, state=None, max_iters: int = 10, lambda0: float = 1e-4, ftol: floa
     lib().or_solve(S.ptr, _p(R), _p(T), _p(X), _p(k), ct.byref(opt), _p(cost_log), _p(lam_log),
                    _p(rho_log), _p(acc_log), ct.byref(st))
     n = st.iterations
-    return {"state": (R, T, X, k), "cost_log": cost_log[: n + 1], "lambda_log": lam_log[:n],
+    k_ret = k.copy() if (np.asarray(state[3]).size == 5 or int(S.sc["intr_mask"]) & SELF_CAL) else k[:2].copy()
+    return {"state": (R, T, X, k_ret), "intr": k[2:].copy(), "cost_log": cost_log[: n + 1], "lambda_log": lam_log[:n],
             "rho_log": rho_log[:n], "accepted_log": acc_log[:n], "iterations": n,
             "accepted": st.accepted, "rejected": st.rejected, "status": st.status,
             "lambda": st.lambda_, "nu": st.nu}

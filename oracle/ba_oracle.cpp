@@ -27,8 +27,11 @@
 //     overlap, Sec. 3.2) carry no unknowns.
 //
 // Unknown ordering: for each free camera in camera order (omega[3], T[3]),
-// then the estimated intrinsics (k1 if bit 0 of intr_mask, k2 if bit 1), then
-// the points (X, Y, Z) in point order.  Rotation update: R <- R Exp(domega).
+// then the estimated intrinsics of the cluster in the order k1 (bit 0 of
+// intr_mask), k2 (bit 1), f (bit 2), cx (bit 3), cy (bit 4) -- f, cx, cy being
+// the focal length and principal point of K, the k1, k2 the radial terms --
+// then the points (X, Y, Z) in point order.  The intrinsic state is the
+// vector k[5] = (k1, k2, f, cx, cy).  Rotation update: R <- R Exp(domega).
 //
 // Everything is plain loops in double precision; no blocking, fusion or
 // reordering beyond the textbook definitions.
@@ -165,9 +168,10 @@ void project(const double R[9], const double T[3], const double X[3], double f, 
 double huber_rho(double s, double dt) { return s <= dt * dt ? s : 2.0 * dt * std::sqrt(s) - dt * dt; }
 double huber_w(double s, double dt) { return s <= dt * dt ? 1.0 : dt / std::sqrt(s); }
 
-// Jacobians of the predicted pixel (u, v) of one observation, row-major 2xN.
+// Jacobians of the predicted pixel (u, v) of one observation, row-major 2xN:
+// Jk for (k1, k2), Ji for (f, cx, cy).
 struct ObsJac {
-  double Jw[6], JT[6], Jp[6], Jk[4];
+  double Jw[6], JT[6], Jp[6], Jk[4], Ji[6];
 };
 
 void obs_jacobian(const double R[9], const Proj& p, double f, double k1, double k2, ObsJac& J) {
@@ -201,6 +205,14 @@ void obs_jacobian(const double R[9], const Proj& p, double f, double k1, double 
   const double r4 = p.r2 * p.r2;
   J.Jk[0] = f * p.r2 * a; J.Jk[1] = f * r4 * a;
   J.Jk[2] = f * p.r2 * b; J.Jk[3] = f * r4 * b;
+  // u = f D a + cx, v = f D b + cy
+  J.Ji[0] = p.D * a; J.Ji[1] = 1.0; J.Ji[2] = 0.0;
+  J.Ji[3] = p.D * b; J.Ji[4] = 0.0; J.Ji[5] = 1.0;
+}
+
+// project() with the intrinsic state k = (k1, k2, f, cx, cy)
+void project_k(const double R[9], const double T[3], const double X[3], const double* k, Proj& p) {
+  project(R, T, X, k[2], k[3], k[4], k[0], k[1], p);
 }
 
 double inv_sigma(double s) { return (s > 0.0 && std::isfinite(s)) ? 1.0 / s : 0.0; }
@@ -235,7 +247,7 @@ void prior_residual(const OrScene& sc, int k, const double R[9], const double T[
 struct Layout {
   std::vector<int> cam_col;   // first column of a free camera, -1 if fixed
   int n_free = 0, n_intr = 0, m = 0;
-  int k_col[2] = {-1, -1};
+  int k_col[5] = {-1, -1, -1, -1, -1};
   long N = 0;
 };
 
@@ -245,7 +257,7 @@ Layout make_layout(const OrScene& sc) {
   for (int k = 0; k < sc.n_cams; ++k)
     if (!sc.fixed[k]) L.cam_col[k] = 6 * L.n_free++;
   int c = 6 * L.n_free;
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < 5; ++b)
     if (sc.intr_mask & (1 << b)) L.k_col[b] = c++;
   L.n_intr = c - 6 * L.n_free;
   L.m = c;
@@ -262,7 +274,7 @@ double cost(const OrScene& sc, const double* R, const double* T, const double* X
   for (int o = 0; o < sc.n_obs; ++o) {
     const int c = sc.obs_cam[o], j = sc.obs_pt[o];
     Proj p;
-    project(R + 9 * c, T + 3 * c, X + 3 * j, sc.f, sc.cx, sc.cy, k[0], k[1], p);
+    project_k(R + 9 * c, T + 3 * c, X + 3 * j, k, p);
     if (!(p.xc[2] > 0.0)) return kInf;
     double ex = (p.uv[0] - sc.obs_uv[2 * o]) / sc.sigma_px;
     double ey = (p.uv[1] - sc.obs_uv[2 * o + 1]) / sc.sigma_px;
@@ -342,42 +354,43 @@ int schur_step(const OrScene& sc, const Layout& L, const double* R, const double
 
   std::vector<double> U((long)m * m, 0.0), gc(m, 0.0);
   std::vector<double> V(9L * P, 0.0), gp(3L * P, 0.0);
-  std::vector<double> Wo(24L * O, 0.0);     // per observation: 8 camera-side rows x 3
-  std::vector<int> idx(8L * O, -1);         // global column of each camera-side row
+  constexpr int NR = 11;                    // camera-side rows: omega, T, k1, k2, f, cx, cy
+  std::vector<double> Wo(3L * NR * O, 0.0); // per observation: NR camera-side rows x 3
+  std::vector<int> idx((long)NR * O, -1);   // global column of each camera-side row
 
   for (int o = 0; o < O; ++o) {
     const int c = sc.obs_cam[o], j = sc.obs_pt[o];
     Proj p;
-    project(R + 9 * c, T + 3 * c, X + 3 * j, sc.f, sc.cx, sc.cy, k[0], k[1], p);
+    project_k(R + 9 * c, T + 3 * c, X + 3 * j, k, p);
     if (!(p.xc[2] > 0.0)) return 1;
     ObsJac J;
-    obs_jacobian(R + 9 * c, p, sc.f, k[0], k[1], J);
+    obs_jacobian(R + 9 * c, p, k[2], k[0], k[1], J);
     double e[2] = {(p.uv[0] - sc.obs_uv[2 * o]) * is, (p.uv[1] - sc.obs_uv[2 * o + 1]) * is};
     const double w = huber_w(e[0] * e[0] + e[1] * e[1], dt);
-    // Camera-side Jacobian A (2 x 8): omega, T, k1, k2 (columns absent -> idx -1).
-    double A[2][8];
+    // Camera-side Jacobian A (2 x NR) (columns absent -> idx -1).
+    double A[2][NR];
     for (int i = 0; i < 2; ++i) {
       for (int t = 0; t < 3; ++t) { A[i][t] = J.Jw[3 * i + t] * is; A[i][3 + t] = J.JT[3 * i + t] * is; }
       A[i][6] = J.Jk[2 * i + 0] * is;
       A[i][7] = J.Jk[2 * i + 1] * is;
+      for (int t = 0; t < 3; ++t) A[i][8 + t] = J.Ji[3 * i + t] * is;
     }
-    int* id = &idx[8L * o];
+    int* id = &idx[(long)NR * o];
     if (L.cam_col[c] >= 0)
       for (int t = 0; t < 6; ++t) id[t] = L.cam_col[c] + t;
-    id[6] = L.k_col[0];
-    id[7] = L.k_col[1];
+    for (int b = 0; b < 5; ++b) id[6 + b] = L.k_col[b];
     double Jp[2][3];
     for (int i = 0; i < 2; ++i)
       for (int t = 0; t < 3; ++t) Jp[i][t] = J.Jp[3 * i + t] * is;
 
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < NR; ++r) {
       if (id[r] < 0) continue;
-      for (int s = 0; s < 8; ++s) {
+      for (int s = 0; s < NR; ++s) {
         if (id[s] < 0) continue;
         U[(long)id[r] * m + id[s]] += w * (A[0][r] * A[0][s] + A[1][r] * A[1][s]);
       }
       gc[id[r]] += w * (A[0][r] * e[0] + A[1][r] * e[1]);
-      for (int t = 0; t < 3; ++t) Wo[24L * o + 3 * r + t] = w * (A[0][r] * Jp[0][t] + A[1][r] * Jp[1][t]);
+      for (int t = 0; t < 3; ++t) Wo[3L * NR * o + 3 * r + t] = w * (A[0][r] * Jp[0][t] + A[1][r] * Jp[1][t]);
     }
     for (int r = 0; r < 3; ++r) {
       for (int s = 0; s < 3; ++s) V[9L * j + 3 * r + s] += w * (Jp[0][r] * Jp[0][s] + Jp[1][r] * Jp[1][s]);
@@ -434,27 +447,27 @@ int schur_step(const OrScene& sc, const Layout& L, const double* R, const double
     const double* Qj = &Q[9L * j];
     for (int ia = ptr[j]; ia < ptr[j + 1]; ++ia) {
       const int oa = list[ia];
-      const double* Wa = &Wo[24L * oa];
-      const int* ida = &idx[8L * oa];
+      const double* Wa = &Wo[3L * NR * oa];
+      const int* ida = &idx[(long)NR * oa];
       // Y = W_a Q
-      double Y[8][3];
-      for (int r = 0; r < 8; ++r)
+      double Y[NR][3];
+      for (int r = 0; r < NR; ++r)
         for (int t = 0; t < 3; ++t) {
           double s = 0;
           for (int u = 0; u < 3; ++u) s += Wa[3 * r + u] * Qj[3 * u + t];
           Y[r][t] = s;
         }
-      for (int r = 0; r < 8; ++r) {
+      for (int r = 0; r < NR; ++r) {
         if (ida[r] < 0) continue;
         b[ida[r]] += Y[r][0] * gp[3L * j] + Y[r][1] * gp[3L * j + 1] + Y[r][2] * gp[3L * j + 2];
       }
       for (int ib = ptr[j]; ib < ptr[j + 1]; ++ib) {
         const int ob = list[ib];
-        const double* Wb = &Wo[24L * ob];
-        const int* idb = &idx[8L * ob];
-        for (int r = 0; r < 8; ++r) {
+        const double* Wb = &Wo[3L * NR * ob];
+        const int* idb = &idx[(long)NR * ob];
+        for (int r = 0; r < NR; ++r) {
           if (ida[r] < 0) continue;
-          for (int s = 0; s < 8; ++s) {
+          for (int s = 0; s < NR; ++s) {
             if (idb[s] < 0) continue;
             S[(long)ida[r] * m + idb[s]] -= Y[r][0] * Wb[3 * s] + Y[r][1] * Wb[3 * s + 1] + Y[r][2] * Wb[3 * s + 2];
           }
@@ -479,9 +492,9 @@ int schur_step(const OrScene& sc, const Layout& L, const double* R, const double
     double rhs[3] = {-gp[3L * j], -gp[3L * j + 1], -gp[3L * j + 2]};
     for (int ia = ptr[j]; ia < ptr[j + 1]; ++ia) {
       const int oa = list[ia];
-      const double* Wa = &Wo[24L * oa];
-      const int* ida = &idx[8L * oa];
-      for (int r = 0; r < 8; ++r) {
+      const double* Wa = &Wo[3L * NR * oa];
+      const int* ida = &idx[(long)NR * oa];
+      for (int r = 0; r < NR; ++r) {
         if (ida[r] < 0) continue;
         for (int t = 0; t < 3; ++t) rhs[t] -= Wa[3 * r + t] * dc[ida[r]];
       }
@@ -512,7 +525,7 @@ void apply_update(const OrScene& sc, const Layout& L, const double* R, const dou
     matmul3(R + 9 * c, E, R2 + 9 * c);
     for (int i = 0; i < 3; ++i) T2[3 * c + i] = T[3 * c + i] + d[3 + i];
   }
-  for (int b = 0; b < 2; ++b) k2[b] = k[b] + (L.k_col[b] >= 0 ? delta[L.k_col[b]] : 0.0);
+  for (int b = 0; b < 5; ++b) k2[b] = k[b] + (L.k_col[b] >= 0 ? delta[L.k_col[b]] : 0.0);
   for (long i = 0; i < 3L * sc.n_points; ++i) X2[i] = X[i] + delta[L.m + i];
 }
 
@@ -530,7 +543,7 @@ int or_residuals(const OrScene* sc, const double* R, const double* T, const doub
   for (int o = 0; o < sc->n_obs; ++o) {
     const int c = sc->obs_cam[o], j = sc->obs_pt[o];
     Proj p;
-    project(R + 9 * c, T + 3 * c, X + 3 * j, sc->f, sc->cx, sc->cy, k[0], k[1], p);
+    project_k(R + 9 * c, T + 3 * c, X + 3 * j, k, p);
     if (!(p.xc[2] > 0.0)) ++bad;
     double ex = (p.uv[0] - sc->obs_uv[2 * o]) / sc->sigma_px;
     double ey = (p.uv[1] - sc->obs_uv[2 * o + 1]) / sc->sigma_px;
@@ -546,19 +559,21 @@ int or_residuals(const OrScene* sc, const double* R, const double* T, const doub
 }
 
 // Unwhitened Jacobians of the predicted pixel per observation, row-major 2x3 /
-// 2x3 / 2x3 / 2x2: Jw (right rotation perturbation), JT, JX, Jk (k1, k2).
+// 2x3 / 2x3 / 2x2 / 2x3: Jw (right rotation perturbation), JT, JX, Jk (k1, k2),
+// Ji (f, cx, cy).
 void or_jacobians(const OrScene* sc, const double* R, const double* T, const double* X,
-                  const double* k, double* Jw, double* JT, double* JX, double* Jk) {
+                  const double* k, double* Jw, double* JT, double* JX, double* Jk, double* Ji) {
   for (int o = 0; o < sc->n_obs; ++o) {
     const int c = sc->obs_cam[o], j = sc->obs_pt[o];
     Proj p;
-    project(R + 9 * c, T + 3 * c, X + 3 * j, sc->f, sc->cx, sc->cy, k[0], k[1], p);
+    project_k(R + 9 * c, T + 3 * c, X + 3 * j, k, p);
     ObsJac J;
-    obs_jacobian(R + 9 * c, p, sc->f, k[0], k[1], J);
+    obs_jacobian(R + 9 * c, p, k[2], k[0], k[1], J);
     std::memcpy(Jw + 6 * o, J.Jw, sizeof J.Jw);
     std::memcpy(JT + 6 * o, J.JT, sizeof J.JT);
     std::memcpy(JX + 6 * o, J.Jp, sizeof J.Jp);
     std::memcpy(Jk + 4 * o, J.Jk, sizeof J.Jk);
+    std::memcpy(Ji + 6 * o, J.Ji, sizeof J.Ji);
   }
 }
 
@@ -600,7 +615,7 @@ int or_solve(const OrScene* sc, double* R, double* T, double* X, double* k, cons
              OrStats* st) {
   Layout L = make_layout(*sc);
   const int C = sc->n_cams, P = sc->n_points;
-  std::vector<double> delta(L.N), R2(9L * C), T2(3L * C), X2(3L * P), k2(2);
+  std::vector<double> delta(L.N), R2(9L * C), T2(3L * C), X2(3L * P), k2(5);
   double lambda = opt->lambda0;
   if (!(lambda >= kLambdaMin)) lambda = kLambdaMin;
   if (lambda > kLambdaMax) lambda = kLambdaMax;
@@ -628,8 +643,7 @@ int or_solve(const OrScene* sc, double* R, double* T, double* X, double* k, cons
       std::memcpy(R, R2.data(), R2.size() * sizeof(double));
       std::memcpy(T, T2.data(), T2.size() * sizeof(double));
       std::memcpy(X, X2.data(), X2.size() * sizeof(double));
-      k[0] = k2[0];
-      k[1] = k2[1];
+      for (int b = 0; b < 5; ++b) k[b] = k2[b];
       E = E2;
       const double t = 2.0 * rho - 1.0;
       double fac = 1.0 - t * t * t;

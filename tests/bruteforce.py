@@ -2,8 +2,10 @@
 independent rotation implementation (scipy), dense normal equations, and a
 flat parameter vector for generic minimisers.
 
-State convention: (R[C,3,3], T[C,3], X[P,3], k[2]); unknown ordering: free
-cameras (omega[3], T[3]), estimated intrinsics (k1, k2 per mask), points.
+State convention: (R[C,3,3], T[C,3], X[P,3], k) with k = (k1, k2), or
+(k1, k2, f, cx, cy) when the scene estimates f, cx or cy; unknown ordering:
+free cameras (omega[3], T[3]), estimated intrinsics (k1, k2, f, cx, cy per
+mask bits 0-4), points.
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ def layout(sc):
     cam_col = {c: 6 * i for i, c in enumerate(free)}
     kcols = []
     col = 6 * len(free)
-    for b in range(2):
+    for b in range(5):
         if sc["intr_mask"] & (1 << b):
             kcols.append((b, col))
             col += 1
@@ -68,7 +70,7 @@ def dense_system(sc, state):
             J[sl, c0:c0 + 3] = jac["Jw"][o] / sig
             J[sl, c0 + 3:c0 + 6] = jac["JT"][o] / sig
         for b, col in kcols:
-            J[sl, col] = jac["Jk"][o][:, b] / sig
+            J[sl, col] = (jac["Jk"][o][:, b] if b < 2 else jac["Ji"][o][:, b - 2]) / sig
         J[sl, m + 3 * j:m + 3 * j + 3] = jac["JX"][o] / sig
     for i, c in enumerate(free):
         base = 2 * O + 6 * i

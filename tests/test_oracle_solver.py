@@ -23,6 +23,11 @@ SCENES = [
     dict(seed=103, n_strips=2, imgs_per_strip=3, n_points=200, n_fixed=2, intr_mask=1, k_true=(-0.05, 0.0)),
     dict(seed=104, n_strips=3, imgs_per_strip=2, n_points=120, intr_mask=2, k_true=(0.0, 0.02),
          outlier_frac=0.1),
+    # self-calibration: f, cx, cy in the intrinsic border (bits 2, 3, 4)
+    dict(seed=105, n_strips=2, imgs_per_strip=2, n_points=80, k_true=(-0.05, 0.02), intr_mask=0b11111),
+    dict(seed=106, n_strips=2, imgs_per_strip=3, n_points=150, n_fixed=1, intr_mask=0b11100),
+    dict(seed=107, n_strips=3, imgs_per_strip=2, n_points=120, intr_mask=0b01101, k_true=(-0.05, 0.0),
+         outlier_frac=0.1),
 ]
 
 
@@ -230,3 +235,58 @@ def test_lm_accepts_only_decreasing_steps_and_follows_nielsen():
             assert r["rho_log"][i] > 1e-3
         else:
             assert lam[i + 1] > lam[i]
+
+
+def test_self_calibration_noise_free_recovers_f_cx_cy():
+    """Self-calibration (Sec. 5 names it as a variant): noise-free
+    observations, priors at the truth, f, cx, cy started 0.3 %, +4 px and
+    -3 px off the truth with k1, k2 also estimated: E -> ~0 and the truth,
+    intrinsics included, is recovered."""
+    sc = micro(121, n_strips=2, imgs_per_strip=3, n_points=200, noise_px=0.0, outlier_frac=0.0,
+               priors_at_truth=True, k_true=(-0.05, 0.02), intr_mask=0b11111)
+    f0, cx0, cy0 = sc["f"], sc["cx"], sc["cy"]
+    sc = dict(sc, f=f0 * 1.003, cx=cx0 + 4.0, cy=cy0 - 3.0)
+    r = oracle.solve(sc, max_iters=60)
+    E0, E = r["cost_log"][0], r["cost_log"][-1]
+    assert E < 1e-18 * E0 or E < 1e-16
+    R, T, X, k = r["state"]
+    tr = sc["truth"]
+    assert k.size == 5
+    assert np.abs(k[:2] - tr["k"]).max() < 1e-9
+    assert abs(k[2] - f0) < 1e-6 * f0 and abs(k[3] - cx0) < 1e-6 and abs(k[4] - cy0) < 1e-6
+    assert np.abs(r["intr"] - k[2:]).max() == 0.0
+    assert np.abs(T - tr["T"]).max() < 1e-6
+
+
+def test_self_calibration_jacobian_columns_closed_form():
+    """d(u, v)/d(f, cx, cy) = [[D a, 1, 0], [D b, 0, 1]] with D the radial
+    factor, from the predicted pixel: (u - cx) / f = D a."""
+    sc = micro(122, n_strips=2, imgs_per_strip=2, n_points=30, k_true=(-0.05, 0.02), intr_mask=0b11111)
+    st = oracle.initial_state(sc)
+    jac = oracle.jacobians(sc, st)
+    uv = oracle.residuals(sc, st)["uv"]
+    Da = (uv[:, 0] - sc["cx"]) / sc["f"]
+    Db = (uv[:, 1] - sc["cy"]) / sc["f"]
+    Ji = jac["Ji"]
+    assert np.abs(Ji[:, 0, 0] - Da).max() < 1e-12 and np.abs(Ji[:, 1, 0] - Db).max() < 1e-12
+    assert np.all(Ji[:, 0, 1] == 1) and np.all(Ji[:, 1, 2] == 1) and np.all(Ji[:, 0, 2] == 0) and np.all(Ji[:, 1, 1] == 0)
+
+
+def test_self_calibration_optimum_matches_scipy_lm():
+    """f, cx, cy estimated, no Huber: MINPACK's LM from the start reaches the
+    oracle's minimum and cannot lower it."""
+    sc = micro(123, n_strips=2, imgs_per_strip=2, n_points=40, outlier_frac=0.0, huber_delta_px=1e9,
+               intr_mask=0b11100)
+    sc = dict(sc, f=sc["f"] * 1.002, cx=sc["cx"] + 2.0)
+    r = oracle.solve(sc, max_iters=300, stop_on_ftol=True, ftol=1e-15)
+    E_or = r["cost_log"][-1]
+    _, _, m, N = layout(sc)
+    for start in (oracle.initial_state(sc), r["state"]):
+        def resid(x, start=start):
+            rr, J, w = dense_system(sc, boxplus(sc, start, x))
+            return rr
+
+        sol = scipy.optimize.least_squares(resid, np.zeros(N), method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15)
+        E_sp = 0.5 * (sol.fun ** 2).sum()
+        assert E_sp >= E_or * (1 - 1e-12)
+        assert E_sp == pytest.approx(E_or, rel=1e-6)
