@@ -139,7 +139,11 @@ typedef struct {
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */
 typedef struct {
   int32_t n_cams, n_points, n_obs;
-  int32_t intr_mask;            /* bit 0: estimate k1, bit 1: estimate k2 */
+  int32_t intr_mask;            /* intrinsics estimated with the poses (the intrinsic border of
+                                   the reduced system): bit 0 k1, bit 1 k2, bit 2 f, bit 3 cx,
+                                   bit 4 cy; at most two of them (BA_E_ARG beyond); f, cx, cy
+                                   (self-calibration, a variant Sec. 5 names) start at the
+                                   values below */
   const double* R;              /* [9C] initial rotations, camera->world, row-major */
   const double* T;              /* [3C] initial projection centres */
   const double* X;              /* [3P] initial tie points */
@@ -206,6 +210,7 @@ typedef struct {
   double initial_cost, final_cost;
   double t_submit, t_admit, t_done;   /* seconds on the library's steady clock */
   int64_t cg_iters;             /* conjugate-gradient iterations over all LM iterations (PCG solver; else 0) */
+  double* intr;                 /* [3] f, cx, cy (estimated, or as submitted) */
 } ba_result;
 
 /* Limits enforced by ba_submit_cluster (BA_E_ARG beyond them). */

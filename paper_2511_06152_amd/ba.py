@@ -101,7 +101,7 @@ class ba_result(ct.Structure):
                 ("accepted", ct.c_int32), ("rejected", ct.c_int32), ("lambda_", ct.c_double),
                 ("initial_cost", ct.c_double), ("final_cost", ct.c_double),
                 ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double),
-                ("cg_iters", ct.c_int64)]
+                ("cg_iters", ct.c_int64), ("intr", ct.c_void_p)]
 
 
 _lib = None
@@ -303,8 +303,9 @@ class Context:
     def ba_fetch(self, t: int) -> dict:
         C, P, it = self.meta[t]
         out = {"R": np.zeros((C, 3, 3)), "T": np.zeros((C, 3)), "X": np.zeros((max(P, 1), 3)), "k": np.zeros(2),
-               "cost_log": np.zeros(it + 1)}
+               "cost_log": np.zeros(it + 1), "intr": np.zeros(3)}
         r = ba_result(_p(out["R"]), _p(out["T"]), _p(out["X"]), _p(out["k"]), _p(out["cost_log"]))
+        r.intr = _p(out["intr"])
         self._chk(self.lib.ba_fetch(self.h, t, ct.byref(r)), "ba_fetch")
         out["X"] = out["X"][:P]
         n = r.iterations

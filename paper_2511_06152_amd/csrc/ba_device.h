@@ -37,6 +37,9 @@ struct SlotDesc {
   int max_iters, stop_on_ftol, mixed, nb;  // nb: 16x16 blocks per side of the dense reduced system
   int Lc, Lq, n_tasks, n_cam_tasks, n_cam_task_wg, n_pair_task_wg, n_targets, n_pt_part;
   int sparse, nnzb, pcg_max_iters, pad1;  // sparse: block-CSR reduced system solved by PCG
+  // intrinsic of each of the two intrinsic columns (kcol0, kcol1): 0 k1, 1 k2,
+  // 2 f, 3 cx, 4 cy; sc = 1 when f, cx or cy is among them (self-calibration)
+  int ktype0, ktype1, sc, pad2;
   double pcg_tol;
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
   // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
@@ -95,13 +98,14 @@ struct SlotDesc {
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
   int* bad_part;                          // [n_wg] trial observations at non-positive depth
   double* cost_log;                       // [max_iters + 1]
-  double* out;                            // [12C + 3P + 2] export staging
+  double* out;                            // [12C + 3P + 5] export staging
 };
 
 // Levenberg-Marquardt control of one cluster, updated on the device.
 struct SlotCtl {
   double origin[3];
-  double k[2][2];                         // intrinsics per state buffer
+  double k[2][5];                         // intrinsics per state buffer: k1, k2, f, and the principal
+                                          //   point's offset (x, y) from the caller's (cx, cy)
   double lambda, nu, E, E_prior_trial, pred_c, E0;
   int cur, status, iter, accepted, rejected, solve_ok, point_fail, bad_init;
   int cg_iters, pad;                      // conjugate-gradient iterations, summed over LM iterations
@@ -121,7 +125,7 @@ struct Batch {
   int n_act;
   int total_wg, total_tkc_wg, total_tkp_wg, total_tg;
   int max_m, max_C, max_pstride, max_nb;
-  int any_sparse, any_dense;
+  int any_sparse, any_dense, any_sc, pad;   // any_sc: a self-calibrating cluster in the batch
 };
 
 // max_rin: largest resident gather list of the batch (0: none).

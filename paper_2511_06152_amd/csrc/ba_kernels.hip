@@ -286,10 +286,14 @@ struct ObsJ {
 
 // Residual, Huber weight and Jacobians of one observation.  cam = R (9,
 // row-major, camera->world), T (3).  Invalid lanes get w = 0 and finite values.
-template <typename R>
+// SC (self-calibration): the prediction adds the principal point's offset
+// (cxo, cyo), and the two intrinsic Jacobian columns are those of the
+// intrinsics t0, t1 (0 k1, 1 k2, 2 f, 3 cx, 4 cy) instead of k1, k2.
+template <typename R, bool SC = false>
 __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0, const R X1, const R X2, const R u,
                                           const R v, const R f, const R k1, const R k2, const R is, const R dt,
-                                          bool valid, ObsJ<R>& o) {
+                                          bool valid, ObsJ<R>& o, const R cxo = R(0), const R cyo = R(0),
+                                          const int t0 = 0, const int t1 = 1) {
   const R d0 = X0 - cam[9], d1 = X1 - cam[10], d2 = X2 - cam[11];
   R x = fm(cam[6], d2, fm(cam[3], d1, cam[0] * d0));
   R y = fm(cam[7], d2, fm(cam[4], d1, cam[1] * d0));
@@ -302,8 +306,13 @@ __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0,
   const R D = fm(r2, fm(k2, r2, k1), R(1));     // 1 + k1 r^2 + k2 r^4
   const R fD = f * D;
   const R fis = f * is;
-  o.e[0] = fm(fD, a, -u) * is;
-  o.e[1] = fm(fD, b, -v) * is;
+  if constexpr (SC) {
+    o.e[0] = fm(fD, a, cxo - u) * is;
+    o.e[1] = fm(fD, b, cyo - v) * is;
+  } else {
+    o.e[0] = fm(fD, a, -u) * is;
+    o.e[1] = fm(fD, b, -v) * is;
+  }
   const R s = fm(o.e[0], o.e[0], o.e[1] * o.e[1]);
   o.w = valid ? (s <= dt * dt ? R(1) : dt * rsq(s)) : R(0);
   const R q2 = R(2) * fm(R(2) * k2, r2, k1);     // 2 (k1 + 2 k2 r^2)
@@ -319,8 +328,17 @@ __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0,
     o.Jw[i][2] = fm(Jx[i][0], y, -(Jx[i][1] * x));
   }
   const R fr2 = fis * r2, fr4 = fr2 * r2;
-  o.Jk[0][0] = fr2 * a; o.Jk[0][1] = fr4 * a;
-  o.Jk[1][0] = fr2 * b; o.Jk[1][1] = fr4 * b;
+  if constexpr (SC) {
+    // whitened d(u, v)/d(k1, k2, f, cx, cy): f r^2 (a, b), f r^4 (a, b), D (a, b), (1, 0), (0, 1)
+    const R Da = is * D * a, Db = is * D * b;
+    const R cu[5] = {fr2 * a, fr4 * a, Da, is, R(0)};
+    const R cv[5] = {fr2 * b, fr4 * b, Db, R(0), is};
+    o.Jk[0][0] = cu[t0]; o.Jk[1][0] = cv[t0];
+    o.Jk[0][1] = cu[t1]; o.Jk[1][1] = cv[t1];
+  } else {
+    o.Jk[0][0] = fr2 * a; o.Jk[0][1] = fr4 * a;
+    o.Jk[1][0] = fr2 * b; o.Jk[1][1] = fr4 * b;
+  }
 }
 
 // Camera-side whitened Jacobian column r (0..5) of row i: [Jw | -Jp].
@@ -333,8 +351,10 @@ __device__ __forceinline__ double huber_rho(double s, double dt) {
 }
 
 // FP64 residual rho(s) of one observation; returns false at non-positive depth.
-__device__ __forceinline__ bool obs_rho(const double* __restrict__ cam, const double X[3], double u, double v, double f,
-                                        double k1, double k2, double is, double dt, double* rho) {
+// ki: the intrinsic state (k1, k2, f, principal-point offset x, y).
+__device__ __forceinline__ bool obs_rho(const double* __restrict__ cam, const double X[3], double u, double v,
+                                        const double* ki, double is, double dt, double* rho) {
+  const double k1 = ki[0], k2 = ki[1], f = ki[2];
   const double d0 = X[0] - cam[9], d1 = X[1] - cam[10], d2 = X[2] - cam[11];
   const double x = cam[0] * d0 + cam[3] * d1 + cam[6] * d2;
   const double y = cam[1] * d0 + cam[4] * d1 + cam[7] * d2;
@@ -344,7 +364,7 @@ __device__ __forceinline__ bool obs_rho(const double* __restrict__ cam, const do
   const double a = x * iz, b = y * iz;
   const double r2 = a * a + b * b;
   const double D = 1.0 + k1 * r2 + k2 * r2 * r2;
-  const double e0 = (f * D * a - u) * is, e1 = (f * D * b - v) * is;
+  const double e0 = (f * D * a + ki[3] - u) * is, e1 = (f * D * b + ki[4] - v) * is;
   *rho = huber_rho(e0 * e0 + e1 * e1, dt);
   return true;
 }
@@ -405,8 +425,7 @@ __global__ void k_prep_slot(Batch bt) {
     c.bad_init = 0;
     c.cg_iters = 0;
     c.cg_b0 = 0.0;
-    c.k[1][0] = c.k[0][0];
-    c.k[1][1] = c.k[0][1];
+    for (int t = 0; t < 5; ++t) c.k[1][t] = c.k[0][t];
   }
   __syncthreads();
   for (int k = threadIdx.x; k < d.C; k += blockDim.x) {
@@ -537,7 +556,7 @@ __global__ __launch_bounds__(kWG) void k_cost0(Batch bt) {
   for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) sh_cam[i] = d.cam[cur][i];
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const double k1 = c.k[cur][0], k2 = c.k[cur][1];
+  const double* ki = c.k[cur];
   double acc = 0.0;
   int bad = 0;
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
@@ -548,8 +567,8 @@ __global__ __launch_bounds__(kWG) void k_cost0(Batch bt) {
       const int cam = meta_cam(d.lane_meta[idx]);
       const double X[3] = {d.X[cur][3 * pt], d.X[cur][3 * pt + 1], d.X[cur][3 * pt + 2]};
       double rho;
-      if (obs_rho(sh_cam + kCamVals * cam, X, d.lane_uv64[2 * idx], d.lane_uv64[2 * idx + 1], d.f, k1, k2,
-                  d.inv_sigma, d.huber_dt, &rho)) acc += rho;
+      if (obs_rho(sh_cam + kCamVals * cam, X, d.lane_uv64[2 * idx], d.lane_uv64[2 * idx + 1], ki, d.inv_sigma,
+                  d.huber_dt, &rho)) acc += rho;
       else ++bad;
     }
   }
@@ -606,14 +625,18 @@ __global__ void k_init(Batch bt) {
 // Z = sum of the intrinsic rows of W; per wavefront, the intrinsic-intrinsic
 // sums (U part of all observations, Schur part of all points).
 
-template <typename R, bool INTR>
+template <typename R, bool INTR, bool SC>
 __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const R* scam, R* scr, int wgl, int wave,
                                            int lane) {
   constexpr int NV = INTR ? 15 : 9;
   const int cur = c.cur;
   const R lam = (R)c.lambda;
-  const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
+  // f is the state's (it equals d.f unless self-calibrating); the principal
+  // point's offset and the intrinsic types matter only when self-calibrating
+  const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
+  const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
+  const int t0 = SC ? d.ktype0 : 0, t1 = SC ? d.ktype1 : 1;
   const gptr<R> ptv = gmem(reinterpret_cast<R*>(d.ptv)), ptd = gmem(reinterpret_cast<R*>(d.ptd));
   const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
   const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.lane_uv64, d.lane_uv32);
@@ -642,7 +665,7 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
     const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
     const R u = valid ? ur : R(0), v = valid ? vr : R(0);
     ObsJ<R> o;
-    obs_model<R>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
+    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo, t0, t1);
     const R w = o.w;
     R wJp[2][3];
 #pragma unroll
@@ -742,7 +765,10 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 // of one wavefront.  Writes, per point, Q = (V + lambda D_V)^-1, g_p, Z = sum
 // of the intrinsic rows of W, and D_V; per wavefront, the intrinsic-intrinsic
 // sums (U part of all observations, Schur part of all points).
-template <typename R>
+// SC: the launch for self-calibrating clusters (f, cx or cy estimated); each
+// instantiation skips the other kind, so that the common one keeps its
+// register allocation.
+template <typename R, bool SC>
 __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -752,7 +778,7 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
+  if (c.status != ST_RUNNING || (d.sc != 0) != SC) return;
   R* scam = reinterpret_cast<R*>(smem);
   R* scr_all = scam + bt.max_C * kCamVals;
   const int cur = c.cur;
@@ -760,8 +786,9 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   R* scr = scr_all + wave * 15 * kWave;
-  if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true>(d, c, scam, scr, wgl, wave, lane);
-  else point_pass<R, false>(d, c, scam, scr, wgl, wave, lane);
+  if constexpr (SC) point_pass<R, true, true>(d, c, scam, scr, wgl, wave, lane);
+  else if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true, false>(d, c, scam, scr, wgl, wave, lane);
+  else point_pass<R, false, false>(d, c, scam, scr, wgl, wave, lane);
 }
 
 // ---- block passes: camera-diagonal and camera-pair blocks of the Schur complement ----
@@ -870,13 +897,17 @@ __device__ __forceinline__ void wave_store(float (&acc)[N], float* out, int lane
 // Camera task t of a cluster (one wavefront).  INTR: at least one of k1, k2
 // is estimated; both borders are then summed (the reduction writes only the
 // estimated ones).
-template <typename R, bool INTR>
+template <typename R, bool INTR, bool SC>
 __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
-  const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
+  // f is the state's (it equals d.f unless self-calibrating); the principal
+  // point's offset and the intrinsic types matter only when self-calibrating
+  const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
+  const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
+  const int t0 = SC ? d.ktype0 : 0, t1 = SC ? d.ktype1 : 1;
   const bool mixed = sizeof(R) == 4;
   const R* __restrict__ ptv = reinterpret_cast<const R*>(d.ptv);
   R* part = reinterpret_cast<R*>(d.task_part) + (size_t)t * kTaskVals;
@@ -905,7 +936,7 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
       R rec[kPtVals];
       rec_load<kPtVals>(recs + kPtVals * (size_t)ps, rec);
       ObsJ<R> o;
-      obs_model<R>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
+      obs_model<R, SC>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo, t0, t1);
       const R* Q = rec;
       const R* gp = rec + 6;
       const R w = o.w;
@@ -956,20 +987,22 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
     wave_store(acc, part, lane);
 }
 
-template <typename R>
+template <typename R, bool SC>
 __device__ __forceinline__ void camblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
-  if (d.kcol0 >= 0 || d.kcol1 >= 0) camblk_task_k<R, true>(d, c, t, lane);
-  else camblk_task_k<R, false>(d, c, t, lane);
+  if constexpr (SC) camblk_task_k<R, true, true>(d, c, t, lane);
+  else if (d.kcol0 >= 0 || d.kcol1 >= 0) camblk_task_k<R, true, false>(d, c, t, lane);
+  else camblk_task_k<R, false, false>(d, c, t, lane);
 }
 
 // Pair task t of a cluster (one wavefront).
-template <typename R>
-__device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
+template <typename R, bool SC>
+__device__ __forceinline__ void pairblk_task_k(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
-  const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
+  const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
+  const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
   const bool mixed = sizeof(R) == 4;
   const R* __restrict__ ptv = reinterpret_cast<const R*>(d.ptv);
   R* part = reinterpret_cast<R*>(d.task_part) + (size_t)t * kTaskVals;
@@ -1003,7 +1036,7 @@ __device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c
       R a0[6], a1[6], T[2][3], wa;
       {
         ObsJ<R> oa;
-        obs_model<R>(ca, X0, X1, X2, ua, va, f, k1, k2, is, dt, valid, oa);
+        obs_model<R, SC>(ca, X0, X1, X2, ua, va, f, k1, k2, is, dt, valid, oa, cxo, cyo);
         jp_q(oa, Q, T);
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
@@ -1013,7 +1046,7 @@ __device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c
         wa = oa.w;
       }
       ObsJ<R> ob;
-      obs_model<R>(cb, X0, X1, X2, ub, vb, f, k1, k2, is, dt, valid, ob);
+      obs_model<R, SC>(cb, X0, X1, X2, ub, vb, f, k1, k2, is, dt, valid, ob, cxo, cyo);
       const R ww = -wa * ob.w;
       R M[2][2];
 #pragma unroll
@@ -1036,6 +1069,11 @@ __device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c
     wave_store(acc, part, lane);
 }
 
+template <typename R, bool SC>
+__device__ __forceinline__ void pairblk_task(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
+  pairblk_task_k<R, SC>(d, c, t, lane);
+}
+
 // Slot of logical workgroup b when cluster i owns workgroups
 // [off_a[i] + off_b[i], off_a[i + 1] + off_b[i + 1]).
 __device__ __forceinline__ int find_slot2(const int* __restrict__ off_a, const int* __restrict__ off_b, int n_act,
@@ -1052,7 +1090,7 @@ __device__ __forceinline__ int find_slot2(const int* __restrict__ off_a, const i
 // cluster's workgroups are contiguous, its camera tasks first, so its two
 // kinds of task run side by side on one XCD and read its points through one
 // L2, and the launch has one tail instead of two.
-template <typename R>
+template <typename R, bool SC>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_blocks(Batch bt) {
   const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
@@ -1060,23 +1098,23 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
+  if (c.status != ST_RUNNING || (d.sc != 0) != SC) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int loc = bx - (bt.tkc_off[si] + bt.tkp_off[si]);
   const int ncw = bt.tkc_off[si + 1] - bt.tkc_off[si];
   if (loc < ncw) {
     const int t = loc * kWavesPerWG + wave;
-    if (t < d.n_cam_tasks) camblk_task<R>(d, c, t, lane);
+    if (t < d.n_cam_tasks) camblk_task<R, SC>(d, c, t, lane);
   } else {
     const int t = d.n_cam_tasks + (loc - ncw) * kWavesPerWG + wave;
-    if (t < d.n_tasks) pairblk_task<R>(d, c, t, lane);
+    if (t < d.n_tasks) pairblk_task<R, SC>(d, c, t, lane);
   }
 }
 
 // The two kinds of task as separate launches (the FP64 path, whose pair tasks
 // need fewer registers than its camera tasks).
-template <typename R>
+template <typename R, bool SC>
 __global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
   const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
@@ -1084,12 +1122,12 @@ __global__ __launch_bounds__(kWG) void k_camblk(Batch bt) {
   const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
+  if (c.status != ST_RUNNING || (d.sc != 0) != SC) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int t = (bx - bt.tkc_off[si]) * kWavesPerWG + wave;
-  if (t < d.n_cam_tasks) camblk_task<R>(d, c, t, threadIdx.x % kWave);
+  if (t < d.n_cam_tasks) camblk_task<R, SC>(d, c, t, threadIdx.x % kWave);
 }
-template <typename R>
+template <typename R, bool SC>
 __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
   const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
@@ -1097,10 +1135,10 @@ __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
   const int s = __builtin_amdgcn_readfirstlane(bt.act[si]);
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING) return;
+  if (c.status != ST_RUNNING || (d.sc != 0) != SC) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int t = d.n_cam_tasks + (bx - bt.tkp_off[si]) * kWavesPerWG + wave;
-  if (t < d.n_tasks) pairblk_task<R>(d, c, t, threadIdx.x % kWave);
+  if (t < d.n_tasks) pairblk_task<R, SC>(d, c, t, threadIdx.x % kWave);
 }
 
 // ---- reduction of the task partials into the packed reduced system ----------------
@@ -1667,8 +1705,9 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   if (tid == 0) {
     c.pred_c = predc;
     c.E_prior_trial = 0.5 * pc;
-    c.k[nxt][0] = c.k[cur][0] + (d.kcol0 >= 0 ? xv[d.kcol0] : 0.0);
-    c.k[nxt][1] = c.k[cur][1] + (d.kcol1 >= 0 ? xv[d.kcol1] : 0.0);
+    for (int t = 0; t < 5; ++t)
+      c.k[nxt][t] = c.k[cur][t] + (d.kcol0 >= 0 && t == d.ktype0 ? xv[d.kcol0]
+                                   : (d.kcol1 >= 0 && t == d.ktype1 ? xv[d.kcol1] : 0.0));
   }
 }
 
@@ -1987,8 +2026,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
   if (tid == 0) {
     c.pred_c = predc;
     c.E_prior_trial = 0.5 * pc;
-    c.k[nxt][0] = c.k[cur][0];
-    c.k[nxt][1] = c.k[cur][1];
+    for (int t = 0; t < 5; ++t) c.k[nxt][t] = c.k[cur][t];
     c.cg_iters += it;
     if (!(c.cg_b0 > 0.0)) c.cg_b0 = bnorm;
   }
@@ -1996,7 +2034,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
 
 // ---- back-substitution, trial points and FP64 trial cost -------------------------
 
-template <typename R>
+template <typename R, bool SC>
 __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const int bx = xcd_block();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -2006,7 +2044,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const int wgl = bx - bt.wg_off[si];
   const SlotDesc& d = bt.desc[s];
   const SlotCtl& c = bt.ctl[s];
-  if (c.status != ST_RUNNING || !c.solve_ok || c.point_fail) return;
+  if (c.status != ST_RUNNING || !c.solve_ok || c.point_fail || (d.sc != 0) != SC) return;
   double* tcam = reinterpret_cast<double*>(smem);               // trial cameras FP64
   R* scam = reinterpret_cast<R*>(tcam + bt.max_C * kCamVals);  // current cameras
   R* sdc = scam + bt.max_C * kCamVals;                         // camera update
@@ -2023,9 +2061,10 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   R* scr = scr_all + wave * 3 * kWave;
   const double lambda = c.lambda;
-  const R f = (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
+  const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
-  const double tk1 = c.k[nxt][0], tk2 = c.k[nxt][1];
+  const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
+  const double* tki = c.k[nxt];   // trial intrinsics
   const int kc0 = d.kcol0, kc1 = d.kcol1;
   const R dk0 = kc0 >= 0 ? sdc[kc0] : R(0), dk1 = kc1 >= 0 ? sdc[kc1] : R(0);
   const gptr<const R> ptv = gmem(reinterpret_cast<const R*>(d.ptv)), ptd = gmem(reinterpret_cast<const R*>(d.ptd));
@@ -2064,7 +2103,8 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
     const double ud = valid ? ur : 0.0, vd = valid ? vr : 0.0;
     const R X0 = (R)Xd[0], X1 = (R)Xd[1], X2 = (R)Xd[2], u = (R)ud, v = (R)vd;
     ObsJ<R> o;
-    obs_model<R>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o);
+    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo,
+                     SC ? d.ktype0 : 0, SC ? d.ktype1 : 1);
     const int fi = valid ? scol[cam] : -1;
     // t = W_c^T dc + W_i^T dk, with W = w J_side^T J_p
     R tv[3] = {0, 0, 0};
@@ -2109,7 +2149,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
         }
       }
       double rho;
-      if (obs_rho(tcam + kCamVals * cam, Xn, ud, vd, d.f, tk1, tk2, d.inv_sigma, d.huber_dt, &rho)) rho_sum += rho;
+      if (obs_rho(tcam + kCamVals * cam, Xn, ud, vd, tki, d.inv_sigma, d.huber_dt, &rho)) rho_sum += rho;
       else ++bad;
     }
   }
@@ -2208,6 +2248,9 @@ __global__ void k_export(Batch bt) {
   if (i == 0) {
     d.out[12 * d.C + 3 * d.P] = c.k[cur][0];
     d.out[12 * d.C + 3 * d.P + 1] = c.k[cur][1];
+    d.out[12 * d.C + 3 * d.P + 2] = c.k[cur][2];
+    d.out[12 * d.C + 3 * d.P + 3] = d.cx + c.k[cur][3];
+    d.out[12 * d.C + 3 * d.P + 4] = d.cy + c.k[cur][4];
   }
 }
 
@@ -2289,37 +2332,50 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   if ((e = ensure_smem((const void*)k_solve, s_solve))) return e;
   const size_t sp = mixed ? point_smem<float>(b) : point_smem<double>(b);
   const size_t sb = mixed ? backsub_smem<float>(b) : backsub_smem<double>(b);
-  const void* fb = mixed ? (const void*)k_backsub<float> : (const void*)k_backsub<double>;
-  if ((e = ensure_smem(fb, sb))) return e;
-  const void* fp = mixed ? (const void*)k_point<float> : (const void*)k_point<double>;
-  if ((e = ensure_smem(fp, sp))) return e;
+  {
+    const void* fn[4] = {mixed ? (const void*)k_backsub<float, false> : (const void*)k_backsub<double, false>,
+                         mixed ? (const void*)k_backsub<float, true> : (const void*)k_backsub<double, true>,
+                         mixed ? (const void*)k_point<float, false> : (const void*)k_point<double, false>,
+                         mixed ? (const void*)k_point<float, true> : (const void*)k_point<double, true>};
+    for (int i = 0; i < 4; ++i)
+      if ((i & 1) == 0 || b.any_sc)
+        if ((e = ensure_smem(fn[i], i < 2 ? sb : sp))) return e;
+  }
   const size_t s_pcg = pcg_smem(b);
   if ((e = ensure_smem((const void*)k_pcg, s_pcg))) return e;
   // Events of kernel slot k, or none when it is not timed.
   auto evk = [&](int k) { return (ev_all && ((timed >> k) & 1)) ? ev_all : nullptr; };
   // Every timed kernel needs a dispatch to carry its events, also when a
   // batch has no work for it: a one-block launch that returns at once.
+  // Self-calibrating clusters run in a second launch of the same kernel
+  // (each launch skips the other kind); it carries no events.
   const dim3 g_pt(b.total_wg > 0 ? b.total_wg : 1), g_tg(b.total_tg > 0 ? b.total_tg : 1);
   Batch nob = b;
   nob.n_act = 0;
+  const bool sc = b.any_sc != 0;
   if (b.total_wg > 0 || evk(0)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_point<float>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
-    else launch(k_point<double>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
+    if (mixed) launch(k_point<float, false>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
+    else launch(k_point<double, false>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
+    if (sc && mixed) launch(k_point<float, true>, g_pt, dim3(kWG), sp, st, nullptr, 0, bb);
+    if (sc && !mixed) launch(k_point<double, true>, g_pt, dim3(kWG), sp, st, nullptr, 0, bb);
   }
   if (mixed) {
     // camera and pair tasks in one launch (slot 1); slot 2 marks an empty interval
     const int nwg = b.total_tkc_wg + b.total_tkp_wg;
-    if (nwg > 0 || evk(1)) launch(k_blocks<float>, dim3(nwg > 0 ? nwg : 1), dim3(kWG), 0, st, evk(1), 1, nwg > 0 ? b : nob);
+    if (nwg > 0 || evk(1)) launch(k_blocks<float, false>, dim3(nwg > 0 ? nwg : 1), dim3(kWG), 0, st, evk(1), 1, nwg > 0 ? b : nob);
+    if (sc && nwg > 0) launch(k_blocks<float, true>, dim3(nwg), dim3(kWG), 0, st, nullptr, 1, b);
     if (evk(2) && ((e = hipEventRecord(ev_all[4], st)) || (e = hipEventRecord(ev_all[5], st)))) return e;
   } else {
     if (b.total_tkc_wg > 0 || evk(1)) {
       const Batch& bb = b.total_tkc_wg > 0 ? b : nob;
-      launch(k_camblk<double>, dim3(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1), dim3(kWG), 0, st, evk(1), 1, bb);
+      launch(k_camblk<double, false>, dim3(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1), dim3(kWG), 0, st, evk(1), 1, bb);
+      if (sc && b.total_tkc_wg > 0) launch(k_camblk<double, true>, dim3(b.total_tkc_wg), dim3(kWG), 0, st, nullptr, 1, b);
     }
     if (b.total_tkp_wg > 0 || evk(2)) {
       const Batch& bb = b.total_tkp_wg > 0 ? b : nob;
-      launch(k_pairblk<double>, dim3(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1), dim3(kWG), 0, st, evk(2), 2, bb);
+      launch(k_pairblk<double, false>, dim3(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1), dim3(kWG), 0, st, evk(2), 2, bb);
+      if (sc && b.total_tkp_wg > 0) launch(k_pairblk<double, true>, dim3(b.total_tkp_wg), dim3(kWG), 0, st, nullptr, 2, b);
     }
   }
   if (b.total_tg > 0 || evk(3)) {
@@ -2335,8 +2391,10 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   else if (evk(7) && ((e = hipEventRecord(ev_all[14], st)) || (e = hipEventRecord(ev_all[15], st)))) return e;
   if (b.total_wg > 0 || evk(5)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_backsub<float>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
-    else launch(k_backsub<double>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
+    if (mixed) launch(k_backsub<float, false>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
+    else launch(k_backsub<double, false>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
+    if (sc && mixed) launch(k_backsub<float, true>, g_pt, dim3(kWG), sb, st, nullptr, 5, bb);
+    if (sc && !mixed) launch(k_backsub<double, true>, g_pt, dim3(kWG), sb, st, nullptr, 5, bb);
   }
   launch(k_lm, dim3(b.n_act), dim3(64), 0, st, evk(6), 6, b);
   return hipGetLastError();

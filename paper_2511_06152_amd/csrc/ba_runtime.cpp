@@ -76,6 +76,7 @@ class Arena {
 
 struct Staged {
   int C = 0, P = 0, O = 0, L = 0, n_chunks = 0, m = 0, n_free = 0, kcol0 = -1, kcol1 = -1;
+  int ktype0 = 0, ktype1 = 1, sc = 0;   // intrinsic of each intrinsic column; f, cx or cy estimated
   int max_iters = 0, stop_on_ftol = 0;
   double f = 0, cx = 0, cy = 0, sigma = 1, delta = 1, lambda0 = 1e-4, ftol = 0, k[2] = {0, 0};
   std::vector<double> raw_cam;   // [C][30]
@@ -160,7 +161,7 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
   l.cost_log = take(8 * ((size_t)s.max_iters + 1));
-  l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 2));
+  l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 5));
   l.total = o;
   return l;
 }
@@ -302,10 +303,23 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   else if (solver == BA_SOLVER_AUTO) s.sparse = s.n_free > kMaxFreeCams;
   else if (solver != BA_SOLVER_DENSE) { err = "unknown solver"; return BA_E_ARG; }
   if (!s.sparse && s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras for the dense solver"; return BA_E_ARG; }
-  if (s.sparse && (c->intr_mask & 3)) { err = "the PCG solver does not estimate intrinsics"; return BA_E_ARG; }
+  if (c->intr_mask & ~31) { err = "intr_mask has bits beyond k1, k2, f, cx, cy"; return BA_E_ARG; }
+  if (__builtin_popcount((unsigned)c->intr_mask) > 2) { err = "at most two estimated intrinsics"; return BA_E_ARG; }
+  if (s.sparse && c->intr_mask) { err = "the PCG solver does not estimate intrinsics"; return BA_E_ARG; }
   int col = 6 * s.n_free;
-  if (c->intr_mask & 1) s.kcol0 = col++;
-  if (c->intr_mask & 2) s.kcol1 = col++;
+  if ((c->intr_mask & ~3) == 0) {     // k1 and/or k2: column 0 is k1's, column 1 is k2's
+    if (c->intr_mask & 1) s.kcol0 = col++;
+    if (c->intr_mask & 2) s.kcol1 = col++;
+  } else {                            // f, cx or cy among them: the columns in bit order
+    s.sc = 1;
+    int slot = 0;
+    for (int b = 0; b < 5; ++b)
+      if (c->intr_mask & (1 << b)) {
+        if (slot == 0) { s.kcol0 = col++; s.ktype0 = b; }
+        else { s.kcol1 = col++; s.ktype1 = b; }
+        ++slot;
+      }
+  }
   s.m = col;
   s.raw_cam.resize(30 * (size_t)C);
   for (int k = 0; k < C; ++k) {
@@ -743,6 +757,7 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
     b.max_C = std::max(b.max_C, sl.desc.C);
     b.max_pstride = std::max(b.max_pstride, sl.lay.pstride);
     // the dense solve's LDS layout is sized by the dense clusters only
+    if (sl.desc.sc) b.any_sc = 1;
     if (sl.desc.sparse) b.any_sparse = 1;
     else b.any_dense = 1, b.max_nb = std::max(b.max_nb, sl.desc.nb);
   }
@@ -860,6 +875,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d = SlotDesc{};
   d.C = s.C; d.P = s.P; d.L = s.L; d.n_chunks = s.n_chunks; d.n_wg = lay.n_wg; d.cpw = c->opt.chunks_per_wg;
   d.m = s.m; d.n_free = s.n_free; d.kcol0 = s.kcol0; d.kcol1 = s.kcol1;
+  d.ktype0 = s.ktype0; d.ktype1 = s.ktype1; d.sc = s.sc;
   d.psize = lay.psize; d.pstride = lay.pstride;
   d.max_iters = s.max_iters; d.stop_on_ftol = s.stop_on_ftol; d.mixed = mixed ? 1 : 0; d.nb = s.nb;
   d.Lc = s.Lc; d.Lq = s.Lq; d.n_tasks = (int)s.tasks.size(); d.n_cam_tasks = s.n_cam_tasks;
@@ -973,6 +989,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   SlotCtl ctl{};
   ctl.k[0][0] = s.k[0];
   ctl.k[0][1] = s.k[1];
+  ctl.k[0][2] = s.f;      // principal-point offsets start at 0
   ctl.status = ST_RUNNING;
   HIPCHK(c, hipMemcpyAsync(c->d_ctl + slot, &ctl, sizeof(SlotCtl), hipMemcpyHostToDevice, st));
   // The staged host data must stay alive until the copies above have run.
@@ -1116,7 +1133,7 @@ int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   for (int s : slots) {
     Slot& sl = c->slots[s];
     Ticket& t = *c->tickets[sl.ticket];
-    t.out.resize(12 * (size_t)sl.desc.C + 3 * (size_t)sl.desc.P + 2);
+    t.out.resize(12 * (size_t)sl.desc.C + 3 * (size_t)sl.desc.P + 5);
     t.cost_log.resize((size_t)sl.desc.max_iters + 1);
     HIPCHK(c, hipMemcpyAsync(t.out.data(), sl.desc.out, 8 * t.out.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(t.cost_log.data(), sl.desc.cost_log, 8 * t.cost_log.size(), hipMemcpyDeviceToHost, c->stream));
@@ -1594,6 +1611,7 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   if (r->T) std::memcpy(r->T, o + 9 * C, 3 * sizeof(double) * C);
   if (r->X && P > 0) std::memcpy(r->X, o + 12 * C, 3 * sizeof(double) * P);
   if (r->k) std::memcpy(r->k, o + 12 * C + 3 * (size_t)P, 2 * sizeof(double));
+  if (r->intr) std::memcpy(r->intr, o + 12 * C + 3 * (size_t)P + 2, 3 * sizeof(double));
   const SlotCtl& ctl = t->ctl;
   const int n_log = std::min(ctl.iter, t->max_iters) + 1;
   if (r->cost_log) {

@@ -169,6 +169,75 @@ def test_mixed_within_tolerance_after_fixed_iterations(which):
     assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
 
 
+def self_cal_scene(name):
+    """Self-calibration cases (f, cx, cy in the intrinsic border): micro
+    scenes whose submitted f, cx, cy are off the generating ones, and the
+    paper-scale cluster with f estimated beside k1."""
+    if name == "cluster12_f_k1":
+        sc = dict(A.scene_cluster12(2))
+        sc["intr_mask"] = 0b00101
+        sc["f"] = sc["f"] * 1.001
+        return sc
+    cfg = {"f_k1": (141, 0b00101, dict(k_true=(-0.05, 0.0)), dict(f=1.002)),
+           "cx_cy": (142, 0b11000, {}, dict(cx=3.0, cy=-2.0)),
+           "f_only": (143, 0b00100, {}, dict(f=0.998))}[name]
+    seed, mask, spec_kw, off = cfg
+    sc = dict(A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=3, n_points=800, **spec_kw), seed))
+    sc["intr_mask"] = mask
+    if "f" in off:
+        sc["f"] = sc["f"] * off["f"]
+    sc["cx"] = sc["cx"] + off.get("cx", 0.0)
+    sc["cy"] = sc["cy"] + off.get("cy", 0.0)
+    return sc
+
+
+@pytest.mark.parametrize("name", ["f_k1", "cx_cy", "f_only", "cluster12_f_k1"])
+def test_self_calibration_fp64_cost_per_iteration(name):
+    """FP64 path with f, cx or cy estimated: cost after every iteration within
+    1e-8 of the oracle, and the estimated intrinsics equal to its own."""
+    sc = self_cal_scene(name)
+    print("case self-calibration", name, sc["intr_mask"], sc["n_cams"], sc["n_points"], flush=True)
+    ref = oracle.solve(sc, max_iters=10)
+    got = gpu_run(sc, 10)
+    check_cost_log(got, ref)
+    k5 = ref["state"][3]
+    print("f, cx, cy oracle", k5[2:], "gpu", got["intr"], flush=True)
+    assert abs(got["intr"][0] - k5[2]) < 1e-9 * k5[2]
+    assert np.abs(got["intr"][1:] - k5[3:]).max() < 1e-6
+    assert np.abs(got["k"] - k5[:2]).max() < 1e-9
+
+
+def test_self_calibration_mixed_within_tolerance():
+    """Mixed path, f and k1 estimated, 40 iterations: the predicted pixels of
+    the two final states (each with its own intrinsics) within 1e-3 px RMS,
+    centres within 1 mm, f within 1e-6 relative."""
+    sc = self_cal_scene("f_k1")
+    ref = oracle.solve(sc, max_iters=40)
+    got = gpu_run(sc, 40, precision=MIXED)
+    kg = np.concatenate([got["k"], got["intr"]])
+    uv_g = oracle.residuals(sc, (got["R"], got["T"], got["X"], kg))["uv"]
+    uv_o = oracle.residuals(sc, ref["state"])["uv"]
+    rms = float(np.sqrt(((uv_g - uv_o) ** 2).sum(1).mean()))
+    dT = float(np.abs(got["T"] - ref["state"][1]).max())
+    df = abs(got["intr"][0] - ref["state"][3][2]) / ref["state"][3][2]
+    print(f"self-calibration mixed: rms {rms:.3e} px, centres {dT:.3e} m, f {df:.3e}", flush=True)
+    assert rms < 1e-3 and dT < 1e-3 and df < 1e-6
+
+
+def test_self_calibration_limits_rejected():
+    from paper_2511_06152_amd import BAError, Context
+    sc = dict(A.scene_tiny(1))
+    with Context(precision=FP64) as ctx:
+        for mask in (0b00111, 0b11100, 32):
+            with pytest.raises(BAError) as e:
+                ctx.submit(dict(sc, intr_mask=mask), max_iters=2)
+            assert e.value.code == -1
+    with Context(precision=FP64, solver=2) as ctx:
+        with pytest.raises(BAError) as e:
+            ctx.submit(dict(sc, intr_mask=0b00100), max_iters=2)
+        assert e.value.code == -1
+
+
 def test_mixed_within_tolerance_converged():
     sc = A.scene_tiny(3)
     ref = oracle.solve(sc, max_iters=60, stop_on_ftol=True, ftol=1e-9)
