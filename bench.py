@@ -60,19 +60,19 @@ FLOP_PAIR = 246
 # (S, kernel)) and the same with `--batch-streams 1` (one launch covers the
 # batch: the kernel alone on the GPU), each scaled by what the same counter reads for a
 # plain copy of known size (`bench.py --copy-calibration 256`: FETCH_SIZE
-# reads 131084.8 KiB for 262144 KiB read, WRITE_SIZE 262144.0 KiB for 262144
+# reads 131084.9 KiB for 262144 KiB read, WRITE_SIZE 262144.0 KiB for 262144
 # KiB written).  Valid only for the kernel sources they were taken on (sha256
 # of csrc/ba_kernels.hip and csrc/ba_device.h); otherwise reported as null.
 TRAFFIC = {
-    "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
+    "fetch_scale": 262144.0 / 131084.9, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "blocks"): (91038.4, 2385.7),
-        (1, "blocks"): (173850.7, 4782.2),
+        (2, "blocks"): (91133.0, 2385.0),
+        (1, "blocks"): (174498.1, 4782.1),
     },
     "sources_sha256": {
-        "ba_kernels.hip": "6ce0af57522b915fcf3cc503c4b96337078a24ead20c1be3c004871b0882e4c7",
-        "ba_device.h": "7816f47f3954da6c8b99a3f87488d3050511d7fadfe938f2925dd6c9a2c19734",
+        "ba_kernels.hip": "910b81f89b5637c58852a3e30961f139c5c17ef5f74df0d34c290d7f723537f4",
+        "ba_device.h": "65de8338718987ac0c51c57b2fb4fa7bffd4a571b4f6c07c65442c3654688941",
     },
 }
 
