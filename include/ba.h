@@ -141,7 +141,8 @@ typedef struct {
   int32_t n_cams, n_points, n_obs;
   int32_t intr_mask;            /* intrinsics estimated with the poses (the intrinsic border of
                                    the reduced system): bit 0 k1, bit 1 k2, bit 2 f, bit 3 cx,
-                                   bit 4 cy; at most two of them (BA_E_ARG beyond); f, cx, cy
+                                   bit 4 cy; any subset, each an extra column of the reduced
+                                   system after the cameras' (other bits: BA_E_ARG); f, cx, cy
                                    (self-calibration, a variant Sec. 5 names) start at the
                                    values below */
   const double* R;              /* [9C] initial rotations, camera->world, row-major */
@@ -214,7 +215,7 @@ typedef struct {
 } ba_result;
 
 /* Limits enforced by ba_submit_cluster (BA_E_ARG beyond them). */
-#define BA_MAX_FREE_CAMS 24     /* free cameras per cluster for the dense solver (m <= 146) */
+#define BA_MAX_FREE_CAMS 24     /* free cameras per cluster for the dense solver (m <= 149) */
 #define BA_MAX_CAMS 512         /* cameras per cluster, fixed ones included (also the PCG limit) */
 #define BA_MAX_OBS_PER_POINT 64 /* a point's observations share one 64-lane wavefront */
 

@@ -11,14 +11,18 @@ namespace bagpu {
 constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kWG = 256;                  // threads per workgroup of the chunk kernels
 constexpr int kWavesPerWG = kWG / kWave;
-constexpr int kMaxFreeCams = 24;          // reduced system m <= 6*24 + 2 = 146
+constexpr int kMaxFreeCams = 24;          // reduced system m <= 6*24 + 5 = 149
 constexpr int kMaxCams = 512;             // camera table kept in LDS by the point-lane kernels
 constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
 constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
 constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
 constexpr int kPtVals = 16;               // per point: Q (6 packed symmetric), g (3), Z (6), pad (1)
-constexpr int kTaskVals = 52;             // per block task partial: camera task 51 values, pair task 36
-constexpr int kPtPartVals = 10;           // per point-pass wavefront: intrinsic-intrinsic terms
+constexpr int kTaskVals = 72;             // per block task partial: camera task 51 values (69 when
+                                          // self-calibrating), pair task 36
+constexpr int kPtPartVals = 32;           // per point-pass wavefront: intrinsic-intrinsic terms (9, or 30
+                                          // when self-calibrating)
+constexpr int kPtzVals = 12;              // per point when self-calibrating: Z rows of f, cx, cy (9), pad (3)
+constexpr int kIntr = 5;                  // intrinsic state: k1, k2, f, principal-point offset x, y
 constexpr int kSolveTb = 16;              // block size of the dense reduced-system factorisation
 constexpr int kSolveTbVals = kSolveTb * (kSolveTb + 1);   // doubles per block (rows padded to 17)
 constexpr int kSbRow = 8;                 // sparse reduced-system block: 6 rows padded to 8 values
@@ -37,9 +41,10 @@ struct SlotDesc {
   int max_iters, stop_on_ftol, mixed, nb;  // nb: 16x16 blocks per side of the dense reduced system
   int Lc, Lq, n_tasks, n_cam_tasks, n_cam_task_wg, n_pair_task_wg, n_targets, n_pt_part;
   int sparse, nnzb, pcg_max_iters, pad1;  // sparse: block-CSR reduced system solved by PCG
-  // intrinsic of each of the two intrinsic columns (kcol0, kcol1): 0 k1, 1 k2,
-  // 2 f, 3 cx, 4 cy; sc = 1 when f, cx or cy is among them (self-calibration)
-  int ktype0, ktype1, sc, pad2;
+  // reduced-system column of each intrinsic (0 k1, 1 k2, 2 f, 3 cx, 4 cy; -1:
+  // fixed; kcol0, kcol1 repeat those of k1, k2); sc = 1 when f, cx or cy is
+  // estimated (self-calibration)
+  int kcolt[kIntr], sc, pad2[2];
   double pcg_tol;
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
   // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
@@ -71,10 +76,11 @@ struct SlotDesc {
   float* X32[2];                          // [P][3] FP32 shadows of X
   void* ptv;                              // [P][16] Real: Q, g, Z (+1 pad) from the last point pass
   void* ptd;                              // [P][4] Real: D_V (+1 pad)
+  void* ptz;                              // [P][12] Real, self-calibration only: Z rows of f, cx, cy
   const int* pt_orig;                     // [P] caller index of each internal point
   // reduced camera system
-  void* task_part;                        // [n_tasks][52] Real: per-task block sums
-  void* pt_part;                          // [n_pt_part][10] Real: per point-pass wavefront intrinsic sums
+  void* task_part;                        // [n_tasks][72] Real: per-task block sums
+  void* pt_part;                          // [n_pt_part][32] Real: per point-pass wavefront intrinsic sums
   double* Sg;                             // [pstride] reduced: packed S_acc (psize), g, bS, diag U (m each)
   double* Sd;                             // [nb(nb+1)/2][272] damped S in 16x16 blocks, for the refinement step
   // sparse reduced system (PCG): block rows of the free cameras, diagonal block first

@@ -274,26 +274,30 @@ __device__ __forceinline__ void prior_terms(const double* __restrict__ cam, cons
 
 // ---- per-observation model ------------------------------------------------------
 
-template <typename R>
+template <typename R, int NK = 2>
 struct ObsJ {
   R xc[3];
   R e[2];       // whitened residual
   R w;          // IRLS weight rho'(s)
   R Jp[2][3];   // whitened d(u,v)/dX
   R Jw[2][3];   // whitened d(u,v)/d omega
-  R Jk[2][2];   // whitened d(u,v)/d(k1, k2)
+  R Jk[2][NK];  // whitened d(u,v)/d(k1, k2[, f, cx, cy])
 };
+
+// Intrinsic Jacobian columns an observation carries: k1, k2, and with
+// self-calibration also f, cx, cy (column t is always intrinsic t).
+template <bool SC>
+constexpr int kNk = SC ? kIntr : 2;
 
 // Residual, Huber weight and Jacobians of one observation.  cam = R (9,
 // row-major, camera->world), T (3).  Invalid lanes get w = 0 and finite values.
 // SC (self-calibration): the prediction adds the principal point's offset
-// (cxo, cyo), and the two intrinsic Jacobian columns are those of the
-// intrinsics t0, t1 (0 k1, 1 k2, 2 f, 3 cx, 4 cy) instead of k1, k2.
+// (cxo, cyo), and the Jacobian has the columns of all five intrinsics (k1,
+// k2, f, cx, cy) instead of k1, k2 only.
 template <typename R, bool SC = false>
 __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0, const R X1, const R X2, const R u,
                                           const R v, const R f, const R k1, const R k2, const R is, const R dt,
-                                          bool valid, ObsJ<R>& o, const R cxo = R(0), const R cyo = R(0),
-                                          const int t0 = 0, const int t1 = 1) {
+                                          bool valid, ObsJ<R, kNk<SC>>& o, const R cxo = R(0), const R cyo = R(0)) {
   const R d0 = X0 - cam[9], d1 = X1 - cam[10], d2 = X2 - cam[11];
   R x = fm(cam[6], d2, fm(cam[3], d1, cam[0] * d0));
   R y = fm(cam[7], d2, fm(cam[4], d1, cam[1] * d0));
@@ -331,10 +335,8 @@ __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0,
   if constexpr (SC) {
     // whitened d(u, v)/d(k1, k2, f, cx, cy): f r^2 (a, b), f r^4 (a, b), D (a, b), (1, 0), (0, 1)
     const R Da = is * D * a, Db = is * D * b;
-    const R cu[5] = {fr2 * a, fr4 * a, Da, is, R(0)};
-    const R cv[5] = {fr2 * b, fr4 * b, Db, R(0), is};
-    o.Jk[0][0] = cu[t0]; o.Jk[1][0] = cv[t0];
-    o.Jk[0][1] = cu[t1]; o.Jk[1][1] = cv[t1];
+    o.Jk[0][0] = fr2 * a; o.Jk[0][1] = fr4 * a; o.Jk[0][2] = Da; o.Jk[0][3] = is;   o.Jk[0][4] = R(0);
+    o.Jk[1][0] = fr2 * b; o.Jk[1][1] = fr4 * b; o.Jk[1][2] = Db; o.Jk[1][3] = R(0); o.Jk[1][4] = is;
   } else {
     o.Jk[0][0] = fr2 * a; o.Jk[0][1] = fr4 * a;
     o.Jk[1][0] = fr2 * b; o.Jk[1][1] = fr4 * b;
@@ -342,8 +344,8 @@ __device__ __forceinline__ void obs_model(const R* __restrict__ cam, const R X0,
 }
 
 // Camera-side whitened Jacobian column r (0..5) of row i: [Jw | -Jp].
-template <typename R>
-__device__ __forceinline__ R jc(const ObsJ<R>& o, int i, int r) { return r < 3 ? o.Jw[i][r] : -o.Jp[i][r - 3]; }
+template <typename R, int NK>
+__device__ __forceinline__ R jc(const ObsJ<R, NK>& o, int i, int r) { return r < 3 ? o.Jw[i][r] : -o.Jp[i][r - 3]; }
 
 // Huber rho of the squared whitened norm s, dt = delta / sigma.
 __device__ __forceinline__ double huber_rho(double s, double dt) {
@@ -628,7 +630,8 @@ __global__ void k_init(Batch bt) {
 template <typename R, bool INTR, bool SC>
 __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const R* scam, R* scr, int wgl, int wave,
                                            int lane) {
-  constexpr int NV = INTR ? 15 : 9;
+  constexpr int NK = kNk<SC>, NS = NK * (NK + 1) / 2, NI = NS + 3 * NK;
+  constexpr int NV = INTR ? 9 + 3 * NK : 9;
   const int cur = c.cur;
   const R lam = (R)c.lambda;
   // f is the state's (it equals d.f unless self-calibrating); the principal
@@ -636,11 +639,13 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
   const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
   const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
-  const int t0 = SC ? d.ktype0 : 0, t1 = SC ? d.ktype1 : 1;
   const gptr<R> ptv = gmem(reinterpret_cast<R*>(d.ptv)), ptd = gmem(reinterpret_cast<R*>(d.ptd));
   const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
   const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.lane_uv64, d.lane_uv32);
-  R iv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // S(k0k0) S(k0k1) S(k1k1) g0 g1 dU0 dU1 bS0 bS1
+  // intrinsic sums: S (packed upper triangle, NS), g (NK), diag U (NK), Schur part of b (NK)
+  R iv[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) iv[i] = R(0);
   bool fail = false;
   const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
   // The lane words of the next chunk are requested a chunk ahead; loads are
@@ -664,8 +669,8 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
     const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2], ur = uvs[2 * idx], vr = uvs[2 * idx + 1];
     const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
     const R u = valid ? ur : R(0), v = valid ? vr : R(0);
-    ObsJ<R> o;
-    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo, t0, t1);
+    ObsJ<R, NK> o;
+    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
     const R w = o.w;
     R wJp[2][3];
 #pragma unroll
@@ -683,7 +688,7 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
     for (int t = 0; t < 3; ++t) vals[6 + t] = fm(wJp[0][t], o.e[0], wJp[1][t] * o.e[1]);
     if constexpr (INTR) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < NK; ++b)
 #pragma unroll
         for (int t = 0; t < 3; ++t) vals[9 + 3 * b + t] = fm(o.Jk[0][b], wJp[0][t], o.Jk[1][b] * wJp[1][t]);
     }
@@ -720,31 +725,43 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
       for (int i = 0; i < 6; ++i) rec[9 + i] = INTR ? sum[(9 + i) % NV] : R(0);
       rec[15] = R(0);
       rec_store<kPtVals>(ptv + kPtVals * (size_t)pt, rec);
+      if constexpr (SC) {
+        R rz[kPtzVals];
+#pragma unroll
+        for (int i = 0; i < kPtzVals; ++i) rz[i] = i < 9 ? sum[(15 + i) % NV] : R(0);
+        rec_store<kPtzVals>(gmem(reinterpret_cast<R*>(d.ptz)) + kPtzVals * (size_t)pt, rz);
+      }
       const R dr[4] = {Dp[0], Dp[1], Dp[2], R(0)};
       rec_store<4>(ptd + 4 * (size_t)pt, dr);
     }
     if constexpr (INTR) {
-      const R u00 = w * fm(o.Jk[0][0], o.Jk[0][0], o.Jk[1][0] * o.Jk[1][0]);
-      const R u11 = w * fm(o.Jk[0][1], o.Jk[0][1], o.Jk[1][1] * o.Jk[1][1]);
-      iv[0] += u00;
-      iv[1] += w * fm(o.Jk[0][0], o.Jk[0][1], o.Jk[1][0] * o.Jk[1][1]);
-      iv[2] += u11;
-      iv[3] += w * fm(o.Jk[0][0], o.e[0], o.Jk[1][0] * o.e[1]);
-      iv[4] += w * fm(o.Jk[0][1], o.e[0], o.Jk[1][1] * o.e[1]);
-      iv[5] += u00;
-      iv[6] += u11;
-      if (head) {
-        const R Z[2][3] = {{sum[9 % NV], sum[10 % NV], sum[11 % NV]}, {sum[12 % NV], sum[13 % NV], sum[14 % NV]}};
-        R ZQ[2][3];
+      int e = 0;
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < NK; ++a) {
+        const R uaa = w * fm(o.Jk[0][a], o.Jk[0][a], o.Jk[1][a] * o.Jk[1][a]);
+        iv[e++] += uaa;
+#pragma unroll
+        for (int b = a + 1; b < NK; ++b) iv[e++] += w * fm(o.Jk[0][a], o.Jk[0][b], o.Jk[1][a] * o.Jk[1][b]);
+        iv[NS + a] += w * fm(o.Jk[0][a], o.e[0], o.Jk[1][a] * o.e[1]);
+        iv[NS + NK + a] += uaa;
+      }
+      if (head) {
+        R Z[NK][3], ZQ[NK][3];
+#pragma unroll
+        for (int b = 0; b < NK; ++b)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) Z[b][t] = sum[(9 + 3 * b + t) % NV];
+#pragma unroll
+        for (int b = 0; b < NK; ++b)
 #pragma unroll
           for (int t = 0; t < 3; ++t) ZQ[b][t] = fm(Z[b][0], qel(Q, 0, t), fm(Z[b][1], qel(Q, 1, t), Z[b][2] * qel(Q, 2, t)));
-        iv[0] -= fm(ZQ[0][0], Z[0][0], fm(ZQ[0][1], Z[0][1], ZQ[0][2] * Z[0][2]));
-        iv[1] -= fm(ZQ[0][0], Z[1][0], fm(ZQ[0][1], Z[1][1], ZQ[0][2] * Z[1][2]));
-        iv[2] -= fm(ZQ[1][0], Z[1][0], fm(ZQ[1][1], Z[1][1], ZQ[1][2] * Z[1][2]));
-        iv[7] += fm(ZQ[0][0], sum[6], fm(ZQ[0][1], sum[7], ZQ[0][2] * sum[8]));
-        iv[8] += fm(ZQ[1][0], sum[6], fm(ZQ[1][1], sum[7], ZQ[1][2] * sum[8]));
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < NK; ++a)
+#pragma unroll
+          for (int b = a; b < NK; ++b, ++q) iv[q] -= fm(ZQ[a][0], Z[b][0], fm(ZQ[a][1], Z[b][1], ZQ[a][2] * Z[b][2]));
+#pragma unroll
+        for (int a = 0; a < NK; ++a) iv[NS + 2 * NK + a] += fm(ZQ[a][0], sum[6], fm(ZQ[a][1], sum[7], ZQ[a][2] * sum[8]));
       }
     }
   }
@@ -752,7 +769,7 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
   if constexpr (INTR) {
     R* pp = reinterpret_cast<R*>(d.pt_part) + (size_t)(wgl * kWavesPerWG + wave) * kPtPartVals;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < NI; ++i) {
       const R t = wave_sum(iv[i]);
       if (lane == 0) pp[i] = t;
     }
@@ -785,7 +802,7 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) scam[i] = (R)d.cam[cur][i];
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  R* scr = scr_all + wave * 15 * kWave;
+  R* scr = scr_all + wave * (9 + 3 * kNk<SC>) * kWave;
   if constexpr (SC) point_pass<R, true, true>(d, c, scam, scr, wgl, wave, lane);
   else if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true, false>(d, c, scam, scr, wgl, wave, lane);
   else point_pass<R, false, false>(d, c, scam, scr, wgl, wave, lane);
@@ -811,8 +828,8 @@ __device__ __forceinline__ void load_cam(const double* __restrict__ src, R* dst)
 }
 
 // T = J_p Q (2 x 3) for the packed symmetric 3x3 Q.
-template <typename R>
-__device__ __forceinline__ void jp_q(const ObsJ<R>& o, const R* Q, R T[2][3]) {
+template <typename R, int NK>
+__device__ __forceinline__ void jp_q(const ObsJ<R, NK>& o, const R* Q, R T[2][3]) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -896,9 +913,11 @@ __device__ __forceinline__ void wave_store(float (&acc)[N], float* out, int lane
 
 // Camera task t of a cluster (one wavefront).  INTR: at least one of k1, k2
 // is estimated; both borders are then summed (the reduction writes only the
-// estimated ones).
+// estimated ones).  SC: the borders of all five intrinsics are summed (69
+// values: the 51 of the k1/k2 layout, then f, cx, cy).
 template <typename R, bool INTR, bool SC>
 __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& c, int t, int lane) {
+  constexpr int NK = kNk<SC>, NA = 39 + 6 * NK;
   const int4 tk = d.tasks[t];
   const int ka = (tk.x >> 12) & 0xfff, kb = tk.x & 0xfff;
   const int cur = c.cur;
@@ -907,19 +926,19 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
   const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
   const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
-  const int t0 = SC ? d.ktype0 : 0, t1 = SC ? d.ktype1 : 1;
   const bool mixed = sizeof(R) == 4;
   const R* __restrict__ ptv = reinterpret_cast<const R*>(d.ptv);
   R* part = reinterpret_cast<R*>(d.task_part) + (size_t)t * kTaskVals;
   R ca[kCamVals];
   load_cam(d.cam[cur] + kCamVals * ka, ca);
   (void)kb;
+  const gptr<const R> recz = gmem(reinterpret_cast<const R*>(d.ptz));
 
     const gptr<const int> cl_pt = gmem(d.cl_pt);
     const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.cl_uv64, d.cl_uv32), recs = gmem(ptv);
-    R acc[51];
+    R acc[NA];
 #pragma unroll
-    for (int i = 0; i < 51; ++i) acc[i] = R(0);
+    for (int i = 0; i < NA; ++i) acc[i] = R(0);
     // Loads are unconditional: padding lanes read point 0 (finite state and
     // record; their pixel is 0) and the observation model gives them weight
     // 0, which zeroes every term they add.  The next chunk's point index is
@@ -935,8 +954,10 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
       const R X0 = Xs[3 * ps], X1 = Xs[3 * ps + 1], X2 = Xs[3 * ps + 2], u = uvs[2 * idx], v = uvs[2 * idx + 1];
       R rec[kPtVals];
       rec_load<kPtVals>(recs + kPtVals * (size_t)ps, rec);
-      ObsJ<R> o;
-      obs_model<R, SC>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo, t0, t1);
+      R rz[SC ? kPtzVals : 1];
+      if constexpr (SC) rec_load<kPtzVals>(recz + kPtzVals * (size_t)ps, rz);
+      ObsJ<R, NK> o;
+      obs_model<R, SC>(ca, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
       const R* Q = rec;
       const R* gp = rec + 6;
       const R w = o.w;
@@ -954,11 +975,12 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
       const R ve0 = w * o.e[0], ve1 = w * o.e[1];
       const R vg0 = w * fm(T[0][2], gp[2], fm(T[0][1], gp[1], T[0][0] * gp[0]));
       const R vg1 = w * fm(T[1][2], gp[2], fm(T[1][1], gp[1], T[1][0] * gp[0]));
-      R vk[2][2] = {{0, 0}, {0, 0}};   // [intrinsic][row]
+      R vk[NK][2];   // [intrinsic][row]
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NK; ++q) {
+        vk[q][0] = vk[q][1] = R(0);
         if (!INTR) continue;
-        const R* z = rec + 9 + 3 * q;
+        const R* z = q < 2 ? rec + 9 + 3 * q : rz + 3 * (q - 2);
 #pragma unroll
         for (int a = 0; a < 2; ++a) vk[q][a] = w * (o.Jk[a][q] - fm(T[a][2], z[2], fm(T[a][1], z[1], T[a][0] * z[0])));
       }
@@ -979,12 +1001,24 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
         acc[27 + r] = fm(a0[r], vg0, fm(a1[r], vg1, acc[27 + r]));
         acc[33 + r] = fm(w * a0[r], a0[r], fm(w * a1[r], a1[r], acc[33 + r]));
         if (INTR) {
-          acc[39 + r] = fm(a0[r], vk[0][0], fm(a1[r], vk[0][1], acc[39 + r]));
-          acc[45 + r] = fm(a0[r], vk[1][0], fm(a1[r], vk[1][1], acc[45 + r]));
+#pragma unroll
+          for (int q = 0; q < NK; ++q)
+            acc[39 + 6 * q + r] = fm(a0[r], vk[q][0], fm(a1[r], vk[q][1], acc[39 + 6 * q + r]));
         }
       }
     }
-    wave_store(acc, part, lane);
+    if constexpr (SC) {
+      // a wavefront reduce-scatter takes at most 64 values: two of them
+      R lo[51], hi[NA - 51];
+#pragma unroll
+      for (int i = 0; i < 51; ++i) lo[i] = acc[i];
+#pragma unroll
+      for (int i = 51; i < NA; ++i) hi[i - 51] = acc[i];
+      wave_store(lo, part, lane);
+      wave_store(hi, part + 51, lane);
+    } else {
+      wave_store(acc, part, lane);
+    }
 }
 
 template <typename R, bool SC>
@@ -1035,7 +1069,7 @@ __device__ __forceinline__ void pairblk_task_k(const SlotDesc& d, const SlotCtl&
       // -Y_a W_b^T = J_ca^T M J_cb with the 2x2 M = -w_a w_b J_pa Q J_pb^T.
       R a0[6], a1[6], T[2][3], wa;
       {
-        ObsJ<R> oa;
+        ObsJ<R, kNk<SC>> oa;
         obs_model<R, SC>(ca, X0, X1, X2, ua, va, f, k1, k2, is, dt, valid, oa, cxo, cyo);
         jp_q(oa, Q, T);
 #pragma unroll
@@ -1045,7 +1079,7 @@ __device__ __forceinline__ void pairblk_task_k(const SlotDesc& d, const SlotCtl&
         }
         wa = oa.w;
       }
-      ObsJ<R> ob;
+      ObsJ<R, kNk<SC>> ob;
       obs_model<R, SC>(cb, X0, X1, X2, ub, vb, f, k1, k2, is, dt, valid, ob, cxo, cyo);
       const R ww = -wa * ob.w;
       R M[2][2];
@@ -1185,22 +1219,28 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
   const int4 tg = d.targets[bx - bt.tg_off[si]];
   const int kind = tg.x >> 24, ka = (tg.x >> 12) & 0xfff, kb = tg.x & 0xfff;
   const int v = threadIdx.x;
-  const int m = d.m, psize = d.psize, kc0 = d.kcol0, kc1 = d.kcol1;
+  const int m = d.m, psize = d.psize;
+  // intrinsic columns the kernels sum: k1, k2, and f, cx, cy when self-calibrating
+  const int nk = d.sc ? kIntr : 2;
   double* Sg = d.Sg;
   if (kind == TARGET_INTR) {
-    const double t = fixed_sum(reinterpret_cast<const R*>(d.pt_part), kPtPartVals, 9, tg.y, tg.z, sh, v);
-    if (v >= 9) return;
-    const int kk[9][2] = {{kc0, kc0}, {kc0, kc1}, {kc1, kc1}, {kc0, -2}, {kc1, -2}, {kc0, -3}, {kc1, -3},
-                          {kc0, -4}, {kc1, -4}};
-    const int a = kk[v][0], b = kk[v][1];
-    if (a < 0 || b == -1) return;
-    if (b >= 0) Sg[pidx(a < b ? a : b, a < b ? b : a)] = t;
-    else if (b == -2) Sg[psize + a] = t;
-    else if (b == -3) Sg[psize + 2 * m + a] = t;
-    else Sg[psize + m + a] = t;
+    // point-pass sums: S (packed upper triangle), g, diag U, Schur part of b
+    const int ns = nk * (nk + 1) / 2;
+    const double t = fixed_sum(reinterpret_cast<const R*>(d.pt_part), kPtPartVals, ns + 3 * nk, tg.y, tg.z, sh, v);
+    if (v >= ns + 3 * nk) return;
+    if (v < ns) {
+      int a = 0, r = v;
+      while (r >= nk - a) { r -= nk - a; ++a; }
+      const int ca = d.kcolt[a], cb = d.kcolt[a + r];
+      if (ca >= 0 && cb >= 0) Sg[pidx(min(ca, cb), max(ca, cb))] = t;
+      return;
+    }
+    const int q = (v - ns) / nk, col = d.kcolt[(v - ns) % nk];
+    if (col < 0) return;
+    Sg[psize + (q == 0 ? 0 : q == 1 ? 2 * m : m) + col] = t;
     return;
   }
-  const int nvals = kind == TASK_CAM ? 51 : 36;
+  const int nvals = kind == TASK_CAM ? 39 + 6 * nk : 36;
   const double t = fixed_sum(reinterpret_cast<const R*>(d.task_part), kTaskVals, nvals, tg.y, tg.z, sh, v);
   if (v >= nvals) return;
   const int fa = d.cam_col[ka];
@@ -1235,8 +1275,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
   } else if (v < 27) Sg[psize + fa + (v - 21)] = t;
   else if (v < 33) Sg[psize + m + fa + (v - 27)] = t;
   else if (v < 39) Sg[psize + 2 * m + fa + (v - 33)] = t;
-  else if (v < 45) { if (kc0 >= 0) Sg[pidx(fa + (v - 39), kc0)] = t; }
-  else if (kc1 >= 0) Sg[pidx(fa + (v - 45), kc1)] = t;
+  else {
+    const int col = d.kcolt[(v - 39) / 6];
+    if (col >= 0) Sg[pidx(fa + (v - 39) % 6, col)] = t;
+  }
 }
 
 // ---- damped reduced-camera-system solve (one workgroup per cluster) ------------
@@ -1257,7 +1299,7 @@ constexpr int kTbS = kSolveTb + 1;              // LDS row stride of a block (do
 constexpr int kTbV = kSolveTb * kTbS;           // doubles per block
 constexpr int kSolveWk = 2 * kSolveTb * kSolveTb + kSolveTb;   // factor scratch + solve vector
 constexpr size_t kSolveLdsCap = 150 * 1024;
-static_assert(kSolveTb * ((6 * kMaxFreeCams + 2 + kSolveTb - 1) / kSolveTb) <= kSolveWG,
+static_assert(kSolveTb * ((6 * kMaxFreeCams + kIntr + kSolveTb - 1) / kSolveTb) <= kSolveWG,
               "one thread per unknown of the padded system in the solve's load");
 
 // LDS doubles of the solve kernel for a batch whose largest system has nbm
@@ -1706,8 +1748,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     c.pred_c = predc;
     c.E_prior_trial = 0.5 * pc;
     for (int t = 0; t < 5; ++t)
-      c.k[nxt][t] = c.k[cur][t] + (d.kcol0 >= 0 && t == d.ktype0 ? xv[d.kcol0]
-                                   : (d.kcol1 >= 0 && t == d.ktype1 ? xv[d.kcol1] : 0.0));
+      c.k[nxt][t] = c.k[cur][t] + (d.kcolt[t] >= 0 ? xv[d.kcolt[t]] : 0.0);
   }
 }
 
@@ -2065,8 +2106,10 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
   const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
   const double* tki = c.k[nxt];   // trial intrinsics
-  const int kc0 = d.kcol0, kc1 = d.kcol1;
-  const R dk0 = kc0 >= 0 ? sdc[kc0] : R(0), dk1 = kc1 >= 0 ? sdc[kc1] : R(0);
+  constexpr int NK = kNk<SC>;
+  R dk[NK];   // intrinsic update (0 for fixed intrinsics)
+#pragma unroll
+  for (int t = 0; t < NK; ++t) dk[t] = d.kcolt[t] >= 0 ? sdc[d.kcolt[t]] : R(0);
   const gptr<const R> ptv = gmem(reinterpret_cast<const R*>(d.ptv)), ptd = gmem(reinterpret_cast<const R*>(d.ptd));
   const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
   const gptr<const double> Xc = gmem((const double*)d.X[cur]), uv64 = gmem((const double*)d.lane_uv64);
@@ -2102,9 +2145,8 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
     const double Xd[3] = {valid ? Xr[0] : 0.0, valid ? Xr[1] : 0.0, valid ? Xr[2] : 0.0};
     const double ud = valid ? ur : 0.0, vd = valid ? vr : 0.0;
     const R X0 = (R)Xd[0], X1 = (R)Xd[1], X2 = (R)Xd[2], u = (R)ud, v = (R)vd;
-    ObsJ<R> o;
-    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo,
-                     SC ? d.ktype0 : 0, SC ? d.ktype1 : 1);
+    ObsJ<R, NK> o;
+    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
     const int fi = valid ? scol[cam] : -1;
     // t = W_c^T dc + W_i^T dk, with W = w J_side^T J_p
     R tv[3] = {0, 0, 0};
@@ -2117,8 +2159,16 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
           jd[1] = fm(jc(o, 1, r), sdc[fi + r], jd[1]);
         }
       }
-      jd[0] = fm(o.Jk[0][0], dk0, fm(o.Jk[0][1], dk1, jd[0]));
-      jd[1] = fm(o.Jk[1][0], dk0, fm(o.Jk[1][1], dk1, jd[1]));
+      if constexpr (SC) {
+#pragma unroll
+        for (int q = NK - 1; q >= 0; --q) {
+          jd[0] = fm(o.Jk[0][q], dk[q], jd[0]);
+          jd[1] = fm(o.Jk[1][q], dk[q], jd[1]);
+        }
+      } else {
+        jd[0] = fm(o.Jk[0][0], dk[0], fm(o.Jk[0][1], dk[1], jd[0]));
+        jd[1] = fm(o.Jk[1][0], dk[0], fm(o.Jk[1][1], dk[1], jd[1]));
+      }
 #pragma unroll
       for (int t = 0; t < 3; ++t) tv[t] = o.w * fm(o.Jp[0][t], jd[0], o.Jp[1][t] * jd[1]);
     }
@@ -2254,9 +2304,9 @@ __global__ void k_export(Batch bt) {
   }
 }
 
-template <typename R>
+template <typename R, bool SC>
 size_t point_smem(const Batch& b) {
-  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * 15 * kWave);
+  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * (9 + 3 * kNk<SC>) * kWave);
 }
 
 template <typename R>
@@ -2330,7 +2380,8 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   hipError_t e;
   const size_t s_solve = solve_smem(b);
   if ((e = ensure_smem((const void*)k_solve, s_solve))) return e;
-  const size_t sp = mixed ? point_smem<float>(b) : point_smem<double>(b);
+  const size_t sp = mixed ? point_smem<float, false>(b) : point_smem<double, false>(b);
+  const size_t sps = mixed ? point_smem<float, true>(b) : point_smem<double, true>(b);
   const size_t sb = mixed ? backsub_smem<float>(b) : backsub_smem<double>(b);
   {
     const void* fn[4] = {mixed ? (const void*)k_backsub<float, false> : (const void*)k_backsub<double, false>,
@@ -2339,7 +2390,7 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
                          mixed ? (const void*)k_point<float, true> : (const void*)k_point<double, true>};
     for (int i = 0; i < 4; ++i)
       if ((i & 1) == 0 || b.any_sc)
-        if ((e = ensure_smem(fn[i], i < 2 ? sb : sp))) return e;
+        if ((e = ensure_smem(fn[i], i < 2 ? sb : (i == 2 ? sp : sps)))) return e;
   }
   const size_t s_pcg = pcg_smem(b);
   if ((e = ensure_smem((const void*)k_pcg, s_pcg))) return e;
@@ -2357,8 +2408,8 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
     const Batch& bb = b.total_wg > 0 ? b : nob;
     if (mixed) launch(k_point<float, false>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
     else launch(k_point<double, false>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
-    if (sc && mixed) launch(k_point<float, true>, g_pt, dim3(kWG), sp, st, nullptr, 0, bb);
-    if (sc && !mixed) launch(k_point<double, true>, g_pt, dim3(kWG), sp, st, nullptr, 0, bb);
+    if (sc && mixed) launch(k_point<float, true>, g_pt, dim3(kWG), sps, st, nullptr, 0, bb);
+    if (sc && !mixed) launch(k_point<double, true>, g_pt, dim3(kWG), sps, st, nullptr, 0, bb);
   }
   if (mixed) {
     // camera and pair tasks in one launch (slot 1); slot 2 marks an empty interval

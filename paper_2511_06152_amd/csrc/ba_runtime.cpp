@@ -76,7 +76,7 @@ class Arena {
 
 struct Staged {
   int C = 0, P = 0, O = 0, L = 0, n_chunks = 0, m = 0, n_free = 0, kcol0 = -1, kcol1 = -1;
-  int ktype0 = 0, ktype1 = 1, sc = 0;   // intrinsic of each intrinsic column; f, cx or cy estimated
+  int kcolt[kIntr] = {-1, -1, -1, -1, -1}, sc = 0;   // column of each intrinsic; f, cx or cy estimated
   int max_iters = 0, stop_on_ftol = 0;
   double f = 0, cx = 0, cy = 0, sigma = 1, delta = 1, lambda0 = 1e-4, ftol = 0, k[2] = {0, 0};
   std::vector<double> raw_cam;   // [C][30]
@@ -102,7 +102,7 @@ struct Staged {
 
 struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_meta, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
-      cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, pt_orig, task_part, pt_part, Sg, Sd, dc,
+      cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, out, total;
   int n_wg, psize, pstride;
@@ -140,6 +140,7 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.X321 = take(12 * (size_t)s.P);
   l.ptv = take(rs * kPtVals * (size_t)s.P);
   l.ptd = take(rs * 4 * (size_t)s.P);
+  l.ptz = take(s.sc ? rs * kPtzVals * (size_t)s.P : 0);
   l.pt_orig = take(4 * (size_t)s.P);
   l.task_part = take(rs * kTaskVals * s.tasks.size());
   l.pt_part = take(rs * kPtPartVals * (size_t)s.n_pt_part);
@@ -304,22 +305,14 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   else if (solver != BA_SOLVER_DENSE) { err = "unknown solver"; return BA_E_ARG; }
   if (!s.sparse && s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras for the dense solver"; return BA_E_ARG; }
   if (c->intr_mask & ~31) { err = "intr_mask has bits beyond k1, k2, f, cx, cy"; return BA_E_ARG; }
-  if (__builtin_popcount((unsigned)c->intr_mask) > 2) { err = "at most two estimated intrinsics"; return BA_E_ARG; }
   if (s.sparse && c->intr_mask) { err = "the PCG solver does not estimate intrinsics"; return BA_E_ARG; }
+  // the estimated intrinsics' columns follow the cameras', in bit order
   int col = 6 * s.n_free;
-  if ((c->intr_mask & ~3) == 0) {     // k1 and/or k2: column 0 is k1's, column 1 is k2's
-    if (c->intr_mask & 1) s.kcol0 = col++;
-    if (c->intr_mask & 2) s.kcol1 = col++;
-  } else {                            // f, cx or cy among them: the columns in bit order
-    s.sc = 1;
-    int slot = 0;
-    for (int b = 0; b < 5; ++b)
-      if (c->intr_mask & (1 << b)) {
-        if (slot == 0) { s.kcol0 = col++; s.ktype0 = b; }
-        else { s.kcol1 = col++; s.ktype1 = b; }
-        ++slot;
-      }
-  }
+  for (int b = 0; b < kIntr; ++b)
+    if (c->intr_mask & (1 << b)) s.kcolt[b] = col++;
+  s.kcol0 = s.kcolt[0];
+  s.kcol1 = s.kcolt[1];
+  s.sc = (c->intr_mask & ~3) != 0;
   s.m = col;
   s.raw_cam.resize(30 * (size_t)C);
   for (int k = 0; k < C; ++k) {
@@ -431,7 +424,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   }
   for (int i = 0; i < s.L; ++i) s.lane_meta[i] |= chunk_max[i / kWave] << 22;
   s.n_wg = (s.n_chunks + cpw - 1) / cpw;
-  const bool intr = s.kcol0 >= 0 || s.kcol1 >= 0;
+  const bool intr = s.m > 6 * s.n_free;   // an intrinsic is estimated
   s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
   s.nb = (s.m + kSolveTb - 1) / kSolveTb;
   const int F = s.n_free;
@@ -875,7 +868,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d = SlotDesc{};
   d.C = s.C; d.P = s.P; d.L = s.L; d.n_chunks = s.n_chunks; d.n_wg = lay.n_wg; d.cpw = c->opt.chunks_per_wg;
   d.m = s.m; d.n_free = s.n_free; d.kcol0 = s.kcol0; d.kcol1 = s.kcol1;
-  d.ktype0 = s.ktype0; d.ktype1 = s.ktype1; d.sc = s.sc;
+  for (int t = 0; t < kIntr; ++t) d.kcolt[t] = s.kcolt[t];
+  d.sc = s.sc;
   d.psize = lay.psize; d.pstride = lay.pstride;
   d.max_iters = s.max_iters; d.stop_on_ftol = s.stop_on_ftol; d.mixed = mixed ? 1 : 0; d.nb = s.nb;
   d.Lc = s.Lc; d.Lq = s.Lq; d.n_tasks = (int)s.tasks.size(); d.n_cam_tasks = s.n_cam_tasks;
@@ -910,6 +904,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.X32[1] = (float*)(base + lay.X321);
   d.ptv = base + lay.ptv;
   d.ptd = base + lay.ptd;
+  d.ptz = base + lay.ptz;
   d.pt_orig = (const int*)(base + lay.pt_orig);
   d.task_part = base + lay.task_part;
   d.pt_part = base + lay.pt_part;
