@@ -60,18 +60,18 @@ FLOP_PAIR = 246
 # (S, kernel)) and the same with `--batch-streams 1` (one launch covers the
 # batch: the kernel alone on the GPU), each scaled by what the same counter reads for a
 # plain copy of known size (`bench.py --copy-calibration 256`: FETCH_SIZE
-# reads 131084.8 KiB for 262144 KiB read, WRITE_SIZE 262144.0 KiB for 262144
+# reads 131084.9 KiB for 262144 KiB read, WRITE_SIZE 262144.0 KiB for 262144
 # KiB written).  Valid only for the kernel sources they were taken on (sha256
 # of csrc/ba_kernels.hip and csrc/ba_device.h); otherwise reported as null.
 TRAFFIC = {
-    "fetch_scale": 262144.0 / 131084.8, "write_scale": 262144.0 / 262144.0,
+    "fetch_scale": 262144.0 / 131084.9, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "blocks"): (91224.9, 2414.4),
-        (1, "blocks"): (174393.4, 4829.1),
+        (2, "blocks"): (91239.2, 2414.4),
+        (1, "blocks"): (174411.9, 4829.3),
     },
     "sources_sha256": {
-        "ba_kernels.hip": "2203985d9f5bcb825a91f563d0176df619f0e69a3b972511d95667027343aab6",
+        "ba_kernels.hip": "a7f89dde36d8bccaaa4605d592407dc1fd75839f6ff376bd0c0510698a76c74c",
         "ba_device.h": "451927cbab030830713cc888c0074ddd3651895ddafd31cba2231396d20a8d93",
     },
 }

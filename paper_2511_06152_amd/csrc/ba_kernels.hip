@@ -1123,9 +1123,11 @@ __device__ __forceinline__ int find_slot2(const int* __restrict__ off_a, const i
 // Camera and pair tasks of every cluster in one launch (the FP32 path): a
 // cluster's workgroups are contiguous, its camera tasks first, so its two
 // kinds of task run side by side on one XCD and read its points through one
-// L2, and the launch has one tail instead of two.
+// L2, and the launch has one tail instead of two.  The self-calibrating
+// instantiation (69 camera-task sums) is allowed more registers than four
+// waves per SIMD leave, so that it does not spill.
 template <typename R, bool SC>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_blocks(Batch bt) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(SC ? 2 : 4))) void k_blocks(Batch bt) {
   const int bx = xcd_block();
   if (bt.n_act == 0) return;   // empty dispatch that only carries timing events
   const int si = __builtin_amdgcn_readfirstlane(find_slot2(bt.tkc_off, bt.tkp_off, bt.n_act, bx));
