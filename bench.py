@@ -431,6 +431,34 @@ def run_global(args, Context, precision):
     return out, sc
 
 
+def run_selfcal(args, Context, ctx_kw, scenes, kw):
+    """The headline batch with all five intrinsics (k1, k2, f, cx, cy)
+    estimated, f submitted 0.1 % and the principal point 2 px off: the
+    self-calibrating kernel instantiations, timed like the headline steps."""
+    B = args.batch
+    sc5 = [dict(s, intr_mask=0b11111, f=s["f"] * 1.001, cx=s["cx"] + 2.0, cy=s["cy"] - 2.0) for s in scenes]
+    ctx = Context(batch_streams=args.batch_streams, **ctx_kw)
+    step_ms, iters = [], []
+    for rep in range(args.selfcal_reps + 1):
+        tickets = [ctx.submit(sc5[(rep * B + i) % len(sc5)], **kw) for i in range(B)]
+        for t in tickets:
+            ctx.ba_step(t, 0)
+        t0 = time.perf_counter()
+        ctx.ba_solve_batch(tickets)
+        t1 = time.perf_counter()
+        for t in tickets:
+            if rep > 0:
+                iters.append(ctx.ba_fetch(t)["iterations"])
+            ctx.ba_release(t)
+        if rep > 0:
+            step_ms.append((t1 - t0) * 1e3)
+        log(f"self-calibration rep {rep}{'' if rep else ' (warmup)'}: {(t1 - t0) * 1e3:.2f} ms for {B} clusters")
+    ctx.close()
+    ms = float(np.mean(step_ms))
+    return {"clusters": B, "reps": args.selfcal_reps, "intr_mask": "k1 k2 f cx cy", "m": 6 * 12 + 5,
+            "ms_per_batch": ms, "clusters_per_s": B / (ms / 1e3), "mean_iterations": float(np.mean(iters))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +490,8 @@ def main():
                     help="repetitions of the serving stream (4 strips x 40 images, one cluster per arriving "
                          "image, resident state; 0: skip)")
     ap.add_argument("--stream-window", type=int, default=2, help="stream clusters in flight (closed loop)")
+    ap.add_argument("--selfcal-reps", type=int, default=3,
+                    help="timed batches of the headline clusters with all five intrinsics estimated (0: skip)")
     ap.add_argument("--chain-reps", type=int, default=5,
                     help="repetitions of the chained 60-image flight (clusters of 12 reusing 3 images, Eq. 8 "
                          "fusion; 0: skip)")
@@ -540,12 +570,13 @@ def main():
                 "mfma_flop_per_launch": mfma_total / max(sv_n, 1), "avg_launch_us": sv_ms / max(sv_n, 1) * 1e3,
                 "achieved": (mfma_total / max(sv_n, 1)) / (sv_ms / max(sv_n, 1) / 1e3) / 1e12 if sv_n else None,
                 "note": "FP64 matrix-core work of the dense factorisation (16x16x16 panel and trailing block "
-                        "products) over the kernel's whole launch; the kernel is latency-bound (m <= 146)"}
+                        "products) over the kernel's whole launch; the kernel is latency-bound (m <= 149)"}
     solve_mc["frac"] = solve_mc["achieved"] / PEAK_MFMA_F64_TFLOPS if solve_mc["achieved"] else None
     ms_per_step = float(np.mean(step_ms))
     # the block kernels alone on the GPU: one more step on a single stream
     iso = measure_isolated(args, Context, ctx_kw, scenes, kw, flops) if args.batch_streams > 1 else None
     value = B / (ms_per_step / 1e3)
+    selfcal = run_selfcal(args, Context, ctx_kw, scenes, kw) if args.selfcal_reps > 0 else None
 
     dom = "blocks"
     asm_ms, asm_n = prof[dom]
@@ -748,6 +779,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_uneven": uneven,
         "serving_stream": stream,
+        "self_calibration": selfcal,
         "paper_chain": chain,
         "geo": geo,
         "global_ba": glob,
