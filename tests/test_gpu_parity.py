@@ -234,6 +234,36 @@ def test_self_calibration_mixed_within_tolerance(name):
     assert rms < 1e-3 and dT < 1e-3 and df < (5e-6 if name == "all_five" else 1e-6)
 
 
+def test_self_calibration_in_a_shared_batch():
+    """One batch solved by one launch sequence, both kernel instantiations in
+    each step: a cluster with all five intrinsics estimated, one with k1 and
+    k2, one with none, and one whose cameras are all fixed while f, cx and
+    cy are estimated (a reduced system of the three intrinsics alone).  Each
+    cluster's FP64 cost after every iteration within 1e-8 of the oracle."""
+    from paper_2511_06152_amd import Context
+    base = dict(A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=3, n_points=600), 147))
+    scs = [self_cal_scene("all_five"),
+           dict(base, intr_mask=0b00011),
+           dict(A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2, n_points=300), 148), intr_mask=0),
+           dict(base, intr_mask=0b11100, fixed=np.ones_like(base["fixed"]), f=base["f"] * 1.002,
+                cx=base["cx"] + 3.0, cy=base["cy"] - 2.0)]
+    iters = 10
+    with Context(precision=FP64) as ctx:
+        tickets = [ctx.submit(sc, max_iters=iters) for sc in scs]
+        for t in tickets:
+            ctx.ba_step(t, 0)
+        print("case shared batch: masks", [sc["intr_mask"] for sc in scs], flush=True)
+        ctx.ba_solve_batch(tickets)
+        got = [ctx.ba_fetch(t) for t in tickets]
+    for sc, g in zip(scs, got):
+        ref = oracle.solve(sc, max_iters=iters)
+        check_cost_log(g, ref)
+        if sc["intr_mask"] & 0b11100:
+            k5 = ref["state"][3]
+            assert abs(g["intr"][0] - k5[2]) < 1e-9 * k5[2]
+            assert np.abs(g["intr"][1:] - k5[3:]).max() < 1e-6
+
+
 def test_self_calibration_limits_rejected():
     from paper_2511_06152_amd import BAError, Context
     sc = dict(A.scene_tiny(1))
