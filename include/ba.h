@@ -198,20 +198,41 @@ typedef struct {
   int32_t fuse_resident;
 } ba_cluster;
 
-/* Results (ba_fetch).  Every pointer may be NULL (not written). */
+/* Results (ba_fetch).  Every pointer may be NULL (not written); the
+ * caller allocates each array.  The Levenberg-Marquardt quantities follow the
+ * minimisation of Eq. (7) (Sec. 3.2); the reprojection statistics are the
+ * ones Sec. 3.3 and Table 1 report (mean and standard deviation of the
+ * reprojection error norm). */
 typedef struct {
   double* R;                    /* [9C] */
   double* T;                    /* [3C] */
   double* X;                    /* [3P] */
   double* k;                    /* [2]  */
-  double* cost_log;             /* [max_iters + 1]: E before the first iteration and after each */
+  double* cost_log;             /* [max_iters + 1]: E before the first iteration and after each;
+                                   entries past the last iteration run are NaN */
   int32_t status;               /* enum ba_solve_status */
   int32_t iterations, accepted, rejected;
   double lambda;                /* damping after the last iteration */
   double initial_cost, final_cost;
-  double t_submit, t_admit, t_done;   /* seconds on the library's steady clock */
+  double t_submit, t_admit, t_done;   /* seconds on the library's steady clock: t_submit when
+                                         ba_submit_cluster(s) was entered, t_admit when the
+                                         cluster took its slot, t_done when the serving loop
+                                         retired it (0 outside the serving loop) */
   int64_t cg_iters;             /* conjugate-gradient iterations over all LM iterations (PCG solver; else 0) */
   double* intr;                 /* [3] f, cx, cy (estimated, or as submitted) */
+  double* lambda_log;           /* [max_iters]: the damping each iteration's step was solved with
+                                   (NaN past the last iteration run) */
+  int32_t* accepted_log;        /* [max_iters]: 1 if the iteration's trial was accepted, 0 if it was
+                                   rejected (a cost that did not decrease enough, a failed
+                                   factorisation, or a point at non-positive depth), -1 past the
+                                   last iteration run */
+  double nu;                    /* damping growth factor after the last iteration */
+  /* Reprojection error |p_obs - p^| (pixels, FP64, on the device) at the fetched state, over
+   * the observations at positive depth: count, RMS, mean, population standard deviation, and
+   * the same restricted to inliers |p_obs - p^| <= 3 huber_delta. */
+  int64_t n_reproj, n_inliers;
+  double reproj_rms, reproj_mean, reproj_std;
+  double inlier_mean, inlier_std;
 } ba_result;
 
 /* Limits enforced by ba_submit_cluster (BA_E_ARG beyond them). */

@@ -101,7 +101,10 @@ class ba_result(ct.Structure):
                 ("accepted", ct.c_int32), ("rejected", ct.c_int32), ("lambda_", ct.c_double),
                 ("initial_cost", ct.c_double), ("final_cost", ct.c_double),
                 ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double),
-                ("cg_iters", ct.c_int64), ("intr", ct.c_void_p)]
+                ("cg_iters", ct.c_int64), ("intr", ct.c_void_p), ("lambda_log", ct.c_void_p),
+                ("accepted_log", ct.c_void_p), ("nu", ct.c_double), ("n_reproj", ct.c_int64),
+                ("n_inliers", ct.c_int64), ("reproj_rms", ct.c_double), ("reproj_mean", ct.c_double),
+                ("reproj_std", ct.c_double), ("inlier_mean", ct.c_double), ("inlier_std", ct.c_double)]
 
 
 _lib = None
@@ -303,16 +306,23 @@ class Context:
     def ba_fetch(self, t: int) -> dict:
         C, P, it = self.meta[t]
         out = {"R": np.zeros((C, 3, 3)), "T": np.zeros((C, 3)), "X": np.zeros((max(P, 1), 3)), "k": np.zeros(2),
-               "cost_log": np.zeros(it + 1), "intr": np.zeros(3)}
+               "cost_log": np.zeros(it + 1), "intr": np.zeros(3), "lambda_log": np.zeros(max(it, 1)),
+               "accepted_log": np.zeros(max(it, 1), np.int32)}
         r = ba_result(_p(out["R"]), _p(out["T"]), _p(out["X"]), _p(out["k"]), _p(out["cost_log"]))
         r.intr = _p(out["intr"])
+        r.lambda_log = _p(out["lambda_log"])
+        r.accepted_log = _p(out["accepted_log"])
         self._chk(self.lib.ba_fetch(self.h, t, ct.byref(r)), "ba_fetch")
         out["X"] = out["X"][:P]
         n = r.iterations
         out.update(status=r.status, iterations=n, accepted=r.accepted, rejected=r.rejected, lambda_=r.lambda_,
-                   initial_cost=r.initial_cost, final_cost=r.final_cost, t_submit=r.t_submit, t_admit=r.t_admit,
-                   t_done=r.t_done, cg_iters=r.cg_iters)
+                   nu=r.nu, initial_cost=r.initial_cost, final_cost=r.final_cost, t_submit=r.t_submit,
+                   t_admit=r.t_admit, t_done=r.t_done, cg_iters=r.cg_iters, n_reproj=r.n_reproj,
+                   n_inliers=r.n_inliers, reproj_rms=r.reproj_rms, reproj_mean=r.reproj_mean,
+                   reproj_std=r.reproj_std, inlier_mean=r.inlier_mean, inlier_std=r.inlier_std)
         out["cost_log"] = out["cost_log"][: n + 1]
+        out["lambda_log"] = out["lambda_log"][:n]
+        out["accepted_log"] = out["accepted_log"][:n]
         out["state"] = (out["R"], out["T"], out["X"], out["k"])
         return out
 

@@ -22,6 +22,8 @@ constexpr int kTaskVals = 72;             // per block task partial: camera task
 constexpr int kPtPartVals = 32;           // per point-pass wavefront: intrinsic-intrinsic terms (9, or 30
                                           // when self-calibrating)
 constexpr int kPtzVals = 12;              // per point when self-calibrating: Z rows of f, cx, cy (9), pad (3)
+constexpr int kStatVals = 6;              // reprojection sums of one point-lane workgroup: observations,
+                                          // sum |e|, sum |e|^2, and the same over the inliers (|e| <= 3 delta)
 constexpr int kIntr = 5;                  // intrinsic state: k1, k2, f, principal-point offset x, y
 constexpr int kSolveTb = 16;              // block size of the dense reduced-system factorisation
 constexpr int kSolveTbVals = kSolveTb * (kSolveTb + 1);   // doubles per block (rows padded to 17)
@@ -104,7 +106,11 @@ struct SlotDesc {
   double* cost_part;                      // [n_wg][2] sum rho(s'), sum of point parts of the predicted reduction
   int* bad_part;                          // [n_wg] trial observations at non-positive depth
   double* cost_log;                       // [max_iters + 1]
-  double* out;                            // [12C + 3P + 5] export staging
+  double* lambda_log;                     // [max_iters] damping each iteration's step was solved with
+  int* acc_log;                           // [max_iters] 1: the iteration's trial was accepted
+  double* stat_part;                      // [n_wg][kStatVals] reprojection statistics of the exported state
+  double* out;                            // [12C + 3P + 5 + kStatVals] export staging: R, T, X, intrinsics,
+                                          //   then the cluster's reprojection sums at the exported state
 };
 
 // Levenberg-Marquardt control of one cluster, updated on the device.

@@ -2252,6 +2252,8 @@ __global__ void k_lm(Batch bt) {
     if (ok && pred > 0.0) rho = (c.E - E2) / pred;
   }
   const bool accept = ok && rho > kAcceptRatio;
+  d.lambda_log[c.iter] = c.lambda;
+  d.acc_log[c.iter] = accept ? 1 : 0;
   bool conv = false, stall = false;
   if (accept) {
     const double E = c.E;
@@ -2280,6 +2282,69 @@ __global__ void k_lm(Batch bt) {
   c.point_fail = 0;
 }
 
+// ---- reprojection statistics of the exported state --------------------------------
+//
+// Sec. 3.3 and Table 1 report the mean and standard deviation of the
+// reprojection error norm |p_kj - p^_kj| (pixels) over the observations.  One
+// lane per observation at the current state in FP64; per workgroup the sums
+// (observations, sum |e|, sum |e|^2, and the same over the inliers |e| <= 3
+// delta) in a fixed order.  Observations at non-positive depth are not counted.
+
+__global__ __launch_bounds__(kWG) void k_stats(Batch bt) {
+  const int bx = xcd_block();
+  extern __shared__ double sh_cam[];
+  const int si = find_slot(bt.wg_off, bt.n_act, bx);
+  const int s = bt.act[si];
+  const int wgl = bx - bt.wg_off[si];
+  const SlotDesc& d = bt.desc[s];
+  const SlotCtl& c = bt.ctl[s];
+  const int cur = c.cur;
+  for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) sh_cam[i] = d.cam[cur][i];
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const double* ki = c.k[cur];
+  const double lim = 3.0 * d.huber_dt / d.inv_sigma;   // 3 delta, pixels
+  double acc[kStatVals] = {0, 0, 0, 0, 0, 0};
+  const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
+  for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
+    const int idx = ch * kWave + lane;
+    const int pt = d.lane_pt[idx];
+    if (pt < 0) continue;
+    const double* cam = sh_cam + kCamVals * meta_cam(d.lane_meta[idx]);
+    const double X[3] = {d.X[cur][3 * pt], d.X[cur][3 * pt + 1], d.X[cur][3 * pt + 2]};
+    const double d0 = X[0] - cam[9], d1 = X[1] - cam[10], d2 = X[2] - cam[11];
+    const double x = cam[0] * d0 + cam[3] * d1 + cam[6] * d2;
+    const double y = cam[1] * d0 + cam[4] * d1 + cam[7] * d2;
+    const double z = cam[2] * d0 + cam[5] * d1 + cam[8] * d2;
+    if (!(z > 0.0)) continue;
+    const double a = x / z, b = y / z, r2 = a * a + b * b;
+    const double D = 1.0 + ki[0] * r2 + ki[1] * r2 * r2;
+    const double ex = ki[2] * D * a + ki[3] - d.lane_uv64[2 * idx];
+    const double ey = ki[2] * D * b + ki[4] - d.lane_uv64[2 * idx + 1];
+    const double e2 = ex * ex + ey * ey, e = sqrt(e2);
+    acc[0] += 1.0;
+    acc[1] += e;
+    acc[2] += e2;
+    if (e <= lim) {
+      acc[3] += 1.0;
+      acc[4] += e;
+      acc[5] += e2;
+    }
+  }
+  __shared__ double red[kWavesPerWG][kStatVals];
+#pragma unroll
+  for (int t = 0; t < kStatVals; ++t) {
+    const double v = wave_sum(acc[t]);
+    if (lane == 0) red[wave][t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatVals) {
+    double v = 0.0;
+    for (int w = 0; w < kWavesPerWG; ++w) v += red[w][threadIdx.x];
+    d.stat_part[kStatVals * (size_t)wgl + threadIdx.x] = v;
+  }
+}
+
 // ---- export: undo the origin shift --------------------------------------------------
 
 __global__ void k_export(Batch bt) {
@@ -2296,6 +2361,11 @@ __global__ void k_export(Batch bt) {
     const double* cm = d.cam[cur] + kCamVals * i;
     for (int t = 0; t < 9; ++t) d.out[9 * i + t] = cm[t];
     for (int t = 0; t < 3; ++t) d.out[9 * d.C + 3 * i + t] = cm[9 + t] + c.origin[t];
+  }
+  if (i < kStatVals) {   // the workgroups' reprojection sums, in workgroup order
+    double v = 0.0;
+    for (int w = 0; w < d.n_wg; ++w) v += d.stat_part[kStatVals * (size_t)w + i];
+    d.out[12 * d.C + 3 * d.P + 5 + i] = v;
   }
   if (i == 0) {
     d.out[12 * d.C + 3 * d.P] = c.k[cur][0];
@@ -2461,7 +2531,14 @@ hipError_t launch_writeback(const Batch& b, int max_rout, hipStream_t st) {
 
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st) {
   if (b.n_act == 0) return hipSuccess;
-  const int n = max_P > b.max_C ? max_P : (b.max_C > 0 ? b.max_C : 1);
+  if (b.total_wg > 0) {
+    const size_t sc = sizeof(double) * b.max_C * kCamVals;
+    hipError_t e = ensure_smem((const void*)k_stats, sc);
+    if (e) return e;
+    hipLaunchKernelGGL(k_stats, dim3(b.total_wg), dim3(kWG), sc, st, b);
+  }
+  int n = max_P > b.max_C ? max_P : (b.max_C > 0 ? b.max_C : 1);
+  if (n < kStatVals) n = kStatVals;
   hipLaunchKernelGGL(k_export, dim3((n + 255) / 256, b.n_act), dim3(256), 0, st, b);
   return hipGetLastError();
 }

@@ -104,7 +104,7 @@ struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_meta, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
-      bad_part, cost_log, out, total;
+      bad_part, cost_log, lambda_log, acc_log, stat_part, out, total;
   int n_wg, psize, pstride;
 };
 
@@ -162,7 +162,10 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.cost_part = take(16 * (size_t)l.n_wg);
   l.bad_part = take(4 * (size_t)l.n_wg);
   l.cost_log = take(8 * ((size_t)s.max_iters + 1));
-  l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 5));
+  l.lambda_log = take(8 * (size_t)s.max_iters);
+  l.acc_log = take(4 * (size_t)s.max_iters);
+  l.stat_part = take(8 * (size_t)kStatVals * l.n_wg);
+  l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 5 + kStatVals));
   l.total = o;
   return l;
 }
@@ -575,7 +578,8 @@ struct Ticket {
   int slot = -1;
   double t_submit = 0, t_admit = 0, t_done = 0;
   // results cached when the serving loop retires the cluster
-  std::vector<double> out, cost_log;
+  std::vector<double> out, cost_log, lambda_log;
+  std::vector<int> acc_log;
   SlotCtl ctl{};
   // resident state: rows of the store per camera and per point (caller order),
   // clusters that must write back first, and whether this one has finished
@@ -943,6 +947,9 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.cost_part = (double*)(base + lay.cost_part);
   d.bad_part = (int*)(base + lay.bad_part);
   d.cost_log = (double*)(base + lay.cost_log);
+  d.lambda_log = (double*)(base + lay.lambda_log);
+  d.acc_log = (int*)(base + lay.acc_log);
+  d.stat_part = (double*)(base + lay.stat_part);
   d.out = (double*)(base + lay.out);
   hipStream_t st = c->stream;
   HIPCHK(c, hipMemcpyAsync(base + lay.lane_pt, s.lane_pt.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
@@ -1128,10 +1135,15 @@ int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   for (int s : slots) {
     Slot& sl = c->slots[s];
     Ticket& t = *c->tickets[sl.ticket];
-    t.out.resize(12 * (size_t)sl.desc.C + 3 * (size_t)sl.desc.P + 5);
+    t.out.resize(12 * (size_t)sl.desc.C + 3 * (size_t)sl.desc.P + 5 + kStatVals);
     t.cost_log.resize((size_t)sl.desc.max_iters + 1);
+    t.lambda_log.resize((size_t)sl.desc.max_iters);
+    t.acc_log.resize((size_t)sl.desc.max_iters);
     HIPCHK(c, hipMemcpyAsync(t.out.data(), sl.desc.out, 8 * t.out.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(t.cost_log.data(), sl.desc.cost_log, 8 * t.cost_log.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(t.lambda_log.data(), sl.desc.lambda_log, 8 * t.lambda_log.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(t.acc_log.data(), sl.desc.acc_log, 4 * t.acc_log.size(), hipMemcpyDeviceToHost, c->stream));
   }
   // Finished resident clusters write their state back (once).
   std::vector<int> wb, done;
@@ -1298,7 +1310,7 @@ int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
 }  // namespace
 
 namespace {
-int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket);
+int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket, double t_submit);
 }  // namespace
 
 extern "C" {
@@ -1427,16 +1439,18 @@ size_t ba_footprint(ba_ctx* c, const ba_cluster* cl) {
 }
 
 int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
+  const double t_submit = now_s();   // latency runs from here: validation and layout included
   if (!c || !ticket) return BA_E_ARG;
   auto st = std::make_unique<Staged>();
   std::string err;
   int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
   std::lock_guard<std::mutex> g(c->mu);
   if (rc) return fail(c, rc, err);
-  return enqueue_staged(c, std::move(st), ticket);
+  return enqueue_staged(c, std::move(st), ticket, t_submit);
 }
 
 int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* tickets) {
+  const double t_submit = now_s();
   if (!c || n < 0 || (n > 0 && (!cl || !tickets))) return BA_E_ARG;
   for (int i = 0; i < n; ++i) tickets[i] = 0;
   std::vector<std::unique_ptr<Staged>> st(n);
@@ -1462,7 +1476,7 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
   for (int i = 0; i < n; ++i)
     if (rc[i]) return fail(c, rc[i], "cluster " + std::to_string(i) + ": " + err[i]);
   for (int i = 0; i < n; ++i) {
-    const int r = enqueue_staged(c, std::move(st[i]), &tickets[i]);
+    const int r = enqueue_staged(c, std::move(st[i]), &tickets[i], t_submit);
     if (r) return r;
   }
   return BA_OK;
@@ -1474,7 +1488,7 @@ namespace {
 
 // Queues a laid-out cluster (registering its resident IDs) and returns its
 // ticket.  Caller holds mu.
-int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket) {
+int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket, double t_submit) {
   int rc;
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
   const size_t bytes = make_layout(*st, c->opt.precision == BA_MIXED).total;
@@ -1488,7 +1502,7 @@ int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket) {
   t->P = st->P;
   t->max_iters = st->max_iters;
   t->bytes = bytes;
-  t->t_submit = now_s();
+  t->t_submit = t_submit;
   t->staged = std::move(st);
   const ba_ticket id = t->id;
   c->tickets[id] = std::move(t);
@@ -1612,6 +1626,23 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   if (r->cost_log) {
     for (int i = 0; i <= t->max_iters; ++i) r->cost_log[i] = i < n_log ? t->cost_log[i] : NAN;
   }
+  if (r->lambda_log)
+    for (int i = 0; i < t->max_iters; ++i) r->lambda_log[i] = i < n_log - 1 ? t->lambda_log[i] : NAN;
+  if (r->accepted_log)
+    for (int i = 0; i < t->max_iters; ++i) r->accepted_log[i] = i < n_log - 1 ? t->acc_log[i] : -1;
+  {
+    // reprojection statistics from the sums of the exported state
+    const double* st = o + 12 * C + 3 * (size_t)P + 5;
+    const double n = st[0], ni = st[3];
+    r->n_reproj = (int64_t)n;
+    r->reproj_rms = n > 0 ? std::sqrt(st[2] / n) : NAN;
+    r->reproj_mean = n > 0 ? st[1] / n : NAN;
+    r->reproj_std = n > 0 ? std::sqrt(std::max(0.0, st[2] / n - r->reproj_mean * r->reproj_mean)) : NAN;
+    r->n_inliers = (int64_t)ni;
+    r->inlier_mean = ni > 0 ? st[4] / ni : NAN;
+    r->inlier_std = ni > 0 ? std::sqrt(std::max(0.0, st[5] / ni - r->inlier_mean * r->inlier_mean)) : NAN;
+  }
+  r->nu = t->ctl.nu;
   r->status = ctl.status;
   r->iterations = ctl.iter;
   r->accepted = ctl.accepted;

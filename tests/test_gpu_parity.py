@@ -46,6 +46,33 @@ def check_cost_log(got, ref, tol=1e-8):
     assert np.all(err <= tol), err.max()
 
 
+def check_state(sc, got, ref, att_tol=1e-9, T_tol=1e-6, X_tol=1e-5, k_tol=1e-9):
+    """FP64 path: the state itself element by element against the oracle's
+    (attitude as the angle of R_gpu^T R_oracle, centres and points in metres,
+    intrinsics absolute), not only through the cost."""
+    R, T, X, k = ref["state"]
+    att = max((np.linalg.norm(Rotation.from_matrix(got["R"][c].T @ R[c]).as_rotvec()) for c in range(sc["n_cams"])),
+              default=0.0)
+    dT = float(np.abs(got["T"] - T).max()) if sc["n_cams"] else 0.0
+    dX = float(np.abs(got["X"] - X).max()) if sc["n_points"] else 0.0
+    dk = float(np.abs(got["k"] - np.asarray(k)[:2]).max())
+    print(f"state vs oracle: attitude {att:.2e} rad, centres {dT:.2e} m, points {dX:.2e} m, k {dk:.2e}", flush=True)
+    assert att <= att_tol and dT <= T_tol and dX <= X_tol and dk <= k_tol
+
+
+def check_stats(sc, got):
+    """ba_fetch's reprojection statistics (computed on the device) against
+    the same statistics of the oracle's predicted pixels at the fetched state."""
+    kk = np.concatenate([got["k"], got["intr"]])
+    uv = oracle.residuals(sc, (got["R"], got["T"], got["X"], kk))["uv"]
+    e = np.linalg.norm(uv - np.asarray(sc["obs_uv"]).reshape(-1, 2), axis=1)
+    inl = e <= 3.0 * sc["huber_delta"]
+    assert got["n_reproj"] == e.size and got["n_inliers"] == int(inl.sum())
+    for key, v in (("reproj_rms", np.sqrt((e * e).mean())), ("reproj_mean", e.mean()), ("reproj_std", e.std()),
+                   ("inlier_mean", e[inl].mean()), ("inlier_std", e[inl].std())):
+        assert got[key] == pytest.approx(v, rel=1e-9), key
+
+
 def final_errors(sc, got, ref):
     uv_g = A.project_obs(got["R"], got["T"], got["X"], got["k"], sc["obs_cam"], sc["obs_pt"])
     R, T, X, k = ref["state"]
@@ -63,9 +90,10 @@ def test_tiny_fp64_cost_per_iteration():
     ref = oracle.solve(sc, max_iters=10)
     got = gpu_run(sc, 10)
     check_cost_log(got, ref)
-    R, T, X, k = ref["state"]
-    assert np.abs(got["T"] - T).max() < 1e-6
-    assert np.abs(got["X"] - X).max() < 1e-5
+    check_state(sc, got, ref)
+    check_stats(sc, got)
+    assert got["accepted_log"].tolist() == ref["accepted_log"].tolist()
+    assert np.allclose(got["lambda_log"], ref["lambda_log"], rtol=1e-6, atol=0)
 
 
 def test_cluster12_fp64_cost_per_iteration():
@@ -75,7 +103,8 @@ def test_cluster12_fp64_cost_per_iteration():
     ref = oracle.solve(sc, max_iters=8)
     got = gpu_run(sc, 8)
     check_cost_log(got, ref)
-    assert np.abs(got["k"] - ref["state"][3]).max() < 1e-9
+    check_state(sc, got, ref)
+    check_stats(sc, got)
 
 
 @pytest.mark.parametrize("name,spec,seed", [
@@ -94,6 +123,7 @@ def test_variants_fp64_cost_per_iteration(name, spec, seed):
     ref = oracle.solve(sc, max_iters=6)
     got = gpu_run(sc, 6)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
 
 
 def test_prior_only_cluster():
@@ -115,6 +145,7 @@ def test_all_cameras_fixed_triangulation():
     ref = oracle.solve(sc, max_iters=5)
     got = gpu_run(sc, 5)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
 
 
 def test_point_with_64_observations():
@@ -146,6 +177,7 @@ def test_point_with_64_observations():
     ref = oracle.solve(sc, max_iters=5)
     got = gpu_run(sc, 5)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
 
 
 @pytest.mark.parametrize("which", ["tiny", "cluster12", "24_free_cams"])
@@ -206,6 +238,8 @@ def test_self_calibration_fp64_cost_per_iteration(name):
     ref = oracle.solve(sc, max_iters=10)
     got = gpu_run(sc, 10)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
+    check_stats(sc, got)
     k5 = ref["state"][3]
     print("f, cx, cy oracle", k5[2:], "gpu", got["intr"], flush=True)
     assert abs(got["intr"][0] - k5[2]) < 1e-9 * k5[2]
@@ -229,9 +263,12 @@ def test_self_calibration_mixed_within_tolerance(name):
     uv_o = oracle.residuals(sc, ref["state"])["uv"]
     rms = float(np.sqrt(((uv_g - uv_o) ** 2).sum(1).mean()))
     dT = float(np.abs(got["T"] - ref["state"][1]).max())
+    att = max(np.linalg.norm(Rotation.from_matrix(got["R"][c].T @ ref["state"][0][c]).as_rotvec())
+              for c in range(sc["n_cams"]))
     df = abs(got["intr"][0] - ref["state"][3][2]) / ref["state"][3][2]
-    print(f"self-calibration mixed {name}: rms {rms:.3e} px, centres {dT:.3e} m, f {df:.3e}", flush=True)
-    assert rms < 1e-3 and dT < 1e-3 and df < (5e-6 if name == "all_five" else 1e-6)
+    print(f"self-calibration mixed {name}: rms {rms:.3e} px, centres {dT:.3e} m, attitude {att:.3e} rad, "
+          f"f {df:.3e}", flush=True)
+    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6 and df < (5e-6 if name == "all_five" else 1e-6)
 
 
 def test_self_calibration_in_a_shared_batch():
