@@ -126,6 +126,30 @@ int ba_patch_transfer(ba_geo* ctx, int32_t n_img, const double* R, const double*
                       const double* uv0, int32_t n_pairs, const int32_t* pairs, const ba_pinhole* cam,
                       double* uv, int32_t* flags, double* lam);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the patch
+ * transfer of ba_patch_transfer with device-resident inputs and outputs, and
+ * no device allocation by the call.  R [9 n_img], T [3 n_img], uv0
+ * [2 n_patch], uv [n_pairs][n_patch][2] and flags [n_pairs][n_patch] are
+ * DEVICE pointers on the context's device, owned by the caller; pairs
+ * [2 n_pairs] and cam are host memory.  The results equal ba_patch_transfer's
+ * bit for bit (the same kernels); the depths (lam) are not returned, and a
+ * non-finite patch centre gives BA_GEO_MISS instead of an error.  The work
+ * buffers (the source list, the pairs grouped by source and the ground point
+ * of every source patch) live in a 16 MiB array inside the library that each
+ * device holds for the life of the process; a call that needs more
+ * (32 bytes per source image and patch, plus 4 bytes per source and 8 per
+ * pair, each part rounded up to 256 bytes) is refused with BA_E_ARG before
+ * anything runs.  Every call on a device shares that array: calls that
+ * overlap on one device (two threads, or two contexts) race.  The call is
+ * synchronous on the context's stream; ba_geo_last_ms times it.  It calls no
+ * hipMalloc, hipFree or other allocating routine.
+ * Errors: BA_E_ARG (NULL arrays with work to do, negative counts, an index
+ * out of range, bad camera, scratch too small), BA_E_DEVICE. */
+int ba_patch_transfer_noalloc(ba_geo* ctx, int32_t n_img, const double* R, const double* T, int32_t n_patch,
+                              const double* uv0, int32_t n_pairs, const int32_t* pairs, const ba_pinhole* cam,
+                              double* uv, int32_t* flags);
+
 /* Device time (ms) of the kernels of the last successful ba_footprints,
  * ba_footprint_overlaps or ba_patch_transfer call on the context, measured
  * by HIP events around its launches (transfers excluded): total_ms over all

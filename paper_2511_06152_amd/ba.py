@@ -25,7 +25,8 @@ BA_MAX_OBS_PER_POINT = 64
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_submit_clusters", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error", "ba_resident_poses", "ba_geo_create", "ba_geo_destroy", "ba_footprints",
-            "ba_footprint_overlaps", "ba_patch_transfer", "ba_geo_last_ms", "ba_geo_last_error"]
+            "ba_footprint_overlaps", "ba_patch_transfer", "ba_patch_transfer_noalloc", "ba_geo_last_ms",
+            "ba_geo_last_error"]
 # Kernel slots of ba_profile_enable / ba_profile_read.  "blocks" is the Schur
 # block launch: camera and pair tasks together in BA_MIXED, camera tasks
 # alone in BA_FP64 (whose pair tasks are "pairblk").
@@ -140,6 +141,8 @@ def load(path: str = LIB_PATH):
     L.ba_footprint_overlaps.argtypes = [P, ct.c_int32, P, P]
     L.ba_patch_transfer.argtypes = [P, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(ba_pinhole),
                                     P, P, P]
+    L.ba_patch_transfer_noalloc.argtypes = [P, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32, P,
+                                            ct.POINTER(ba_pinhole), P, P]
     L.ba_geo_last_ms.argtypes = [P, P, P]
     L.ba_geo_last_error.argtypes = [P]
     L.ba_geo_last_error.restype = ct.c_char_p
@@ -402,6 +405,19 @@ class Geo:
         self._chk(self.lib.ba_patch_transfer(self.h, n_img, _p(R), _p(T), n_patch, _p(uv0), n_pairs, _p(pairs),
                                              ct.byref(c), _p(uv), _p(flags), _p(lam)), "ba_patch_transfer")
         return uv, flags, lam
+
+    def ba_patch_transfer_noalloc(self, n_img: int, R_dev: int, T_dev: int, n_patch: int, uv0_dev: int, pairs,
+                                  cam: dict, uv_dev: int, flags_dev: int):
+        """The allocation-free transfer.  R_dev [n_img][9], T_dev [n_img][3],
+        uv0_dev [n_patch][2] (float64) and the outputs uv_dev
+        [n_pairs][n_patch][2] (float64), flags_dev [n_pairs][n_patch] (int32)
+        are device addresses (ints) on the context's device; pairs is host
+        data [n_pairs][2]."""
+        pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+        c = self._cam(cam)
+        self._chk(self.lib.ba_patch_transfer_noalloc(self.h, int(n_img), R_dev, T_dev, int(n_patch), uv0_dev,
+                                                     pairs.shape[0], _p(pairs), ct.byref(c), uv_dev, flags_dev),
+                  "ba_patch_transfer_noalloc")
 
     def ba_geo_last_ms(self, last_kernel: bool = False) -> float:
         """Device ms of the last call's kernels (or of its last kernel alone)."""

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -284,10 +285,41 @@ __global__ __launch_bounds__(kBlock) void k_project(Cam k, int n_patch, int slot
   }
 }
 
+// ---- scratch of the allocation-free patch transfer ---------------------------------
+//
+// ba_patch_transfer_noalloc keeps its work buffers (the source list, the
+// pairs grouped by source, the ground point of every source patch) in this
+// file-scope array instead of memory it allocates.  Each device the library
+// runs on holds its own copy until the process ends; in host code the name is
+// only a stand-in, so kernels get the device address that hipGetSymbolAddress
+// returns for the current device (resolved once per device at
+// ba_geo_create).  Every call on a device shares that device's copy: calls
+// that overlap on one device race.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;   // per device ordinal; nullptr until resolved
+
+// Device address of `scratch` on `device`, which must be the current device.
+hipError_t scratch_addr(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize(device + 1, nullptr);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct ba_geo {
   int device = 0;
+  void* scratch = nullptr;           // this device's address of the allocation-free transfer's scratch
   hipStream_t stream = nullptr;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // start, before the last kernel, end
   Dsm dsm{};
@@ -349,6 +381,59 @@ int finish(ba_geo* g, bool split) {
   return BA_OK;
 }
 
+// Validates the pairs and groups them by source image (stable in pair order):
+// src [n_src] the source images in order of first use, src_off [n_src + 1],
+// and per grouped pair e its pair index pidx[e] and destination pdst[e].
+int group_pairs(ba_geo* g, int32_t n_img, int32_t n_pairs, const int32_t* pairs, std::vector<int>& src,
+                std::vector<int>& src_off, std::vector<int>& pidx, std::vector<int>& pdst) {
+  std::vector<int> slot_of(n_img, -1);
+  src.clear();
+  for (int p = 0; p < n_pairs; ++p) {
+    const int a = pairs[2 * p], b = pairs[2 * p + 1];
+    if (a < 0 || a >= n_img || b < 0 || b >= n_img) return gfail(g, BA_E_ARG, "pair index out of range");
+    if (slot_of[a] < 0) {
+      slot_of[a] = (int)src.size();
+      src.push_back(a);
+    }
+  }
+  const int n_src = (int)src.size();
+  src_off.assign(n_src + 1, 0);
+  pidx.resize(n_pairs);
+  pdst.resize(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) ++src_off[slot_of[pairs[2 * p]] + 1];
+  for (int s = 0; s < n_src; ++s) src_off[s + 1] += src_off[s];
+  std::vector<int> fill(src_off.begin(), src_off.end() - 1);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int e = fill[slot_of[pairs[2 * p]]]++;
+    pidx[e] = p;
+    pdst[e] = pairs[2 * p + 1];
+  }
+  return BA_OK;
+}
+
+// The two kernels of a transfer on the context's stream, events around them:
+// the patch rays of every source image, then the projections.
+int launch_transfer(ba_geo* g, const Cam& k, int n_src, int n_patch, int n_pairs, const int* dSrc, const int* dOff,
+                    const int* dPidx, const int* dPdst, const double* dR, const double* dT, const double* dUv0,
+                    double4* dGp, double2* dUv, int* dFl) {
+  GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
+  const size_t rays = (size_t)n_src * n_patch;
+  hipLaunchKernelGGL(k_patch_rays, dim3((unsigned)((rays + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream, g->dsm,
+                     k, n_src, n_patch, dSrc, dR, dT, dUv0, dGp);
+  GEOCHK(g, hipGetLastError());
+  GEOCHK(g, hipEventRecord(g->ev[1], g->stream));
+  if (n_pairs > 0) {
+    const unsigned bx = (unsigned)((n_patch + kBlock - 1) / kBlock);
+    for (int s0 = 0; s0 < n_src; s0 += 65535) {
+      const unsigned by = (unsigned)std::min(65535, n_src - s0);
+      hipLaunchKernelGGL(k_project, dim3(bx, by), dim3(kBlock), 0, g->stream, k, n_patch, s0, dOff, dPidx, dPdst, dR,
+                         dT, (const double4*)dGp, dUv, dFl);
+      GEOCHK(g, hipGetLastError());
+    }
+  }
+  return finish(g, true);
+}
+
 }  // namespace
 
 extern "C" {
@@ -371,6 +456,7 @@ int ba_geo_create(int32_t device, const ba_dsm* dsm, ba_geo** out) {
     return code;
   };
   if (hipSetDevice(device) != hipSuccess) return bail(BA_E_DEVICE);
+  if (scratch_addr(device, &g->scratch) != hipSuccess) return bail(BA_E_DEVICE);
   if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) return bail(BA_E_DEVICE);
   for (hipEvent_t& e : g->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(BA_E_DEVICE);
@@ -458,35 +544,16 @@ int ba_patch_transfer(ba_geo* g, int32_t n_img, const double* R, const double* T
   if (!R || !T || !uv0 || (n_pairs > 0 && (!pairs || !uv || !flags))) return gfail(g, BA_E_ARG, "missing array");
   for (int i = 0; i < 2 * n_patch; ++i)
     if (!std::isfinite(uv0[i])) return gfail(g, BA_E_ARG, "non-finite patch centre");
-  std::vector<int> slot_of(n_img, -1), src;
-  for (int p = 0; p < n_pairs; ++p) {
-    const int a = pairs[2 * p], b = pairs[2 * p + 1];
-    if (a < 0 || a >= n_img || b < 0 || b >= n_img) return gfail(g, BA_E_ARG, "pair index out of range");
-    if (slot_of[a] < 0) {
-      slot_of[a] = (int)src.size();
-      src.push_back(a);
-    }
-  }
+  std::vector<int> src, src_off, pidx, pdst;
+  int rc = group_pairs(g, n_img, n_pairs, pairs, src, src_off, pidx, pdst);
+  if (rc) return rc;
   const int n_src = (int)src.size();
   if (lam)
     for (size_t i = 0; i < (size_t)n_img * n_patch; ++i) lam[i] = NAN;
   if (n_src == 0) return BA_OK;
-  // pairs grouped by source slot (counting sort, stable in pair order)
-  std::vector<int> src_off(n_src + 1, 0), pidx(n_pairs), pdst(n_pairs);
-  for (int p = 0; p < n_pairs; ++p) ++src_off[slot_of[pairs[2 * p]] + 1];
-  for (int s = 0; s < n_src; ++s) src_off[s + 1] += src_off[s];
-  {
-    std::vector<int> fill(src_off.begin(), src_off.end() - 1);
-    for (int p = 0; p < n_pairs; ++p) {
-      const int e = fill[slot_of[pairs[2 * p]]]++;
-      pidx[e] = p;
-      pdst[e] = pairs[2 * p + 1];
-    }
-  }
   const size_t rays = (size_t)n_src * n_patch, total = (size_t)n_pairs * n_patch;
   GEOCHK(g, hipSetDevice(g->device));
   void *dR, *dT, *dUv0, *dSrc, *dOff, *dPidx, *dPdst, *dGp, *dUv, *dFl;
-  int rc;
   if ((rc = buf(g, 0, 72 * (size_t)n_img, &dR)) || (rc = buf(g, 1, 24 * (size_t)n_img, &dT)) ||
       (rc = buf(g, 5, 16 * (size_t)n_patch, &dUv0)) || (rc = buf(g, 6, 4 * (size_t)n_src, &dSrc)) ||
       (rc = buf(g, 7, 4 * (size_t)(n_src + 1), &dOff)) || (rc = buf(g, 8, 4 * (size_t)n_pairs, &dPidx)) ||
@@ -500,24 +567,10 @@ int ba_patch_transfer(ba_geo* g, int32_t n_img, const double* R, const double* T
   GEOCHK(g, hipMemcpyAsync(dOff, src_off.data(), 4 * (size_t)(n_src + 1), hipMemcpyHostToDevice, g->stream));
   GEOCHK(g, hipMemcpyAsync(dPidx, pidx.data(), 4 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
   GEOCHK(g, hipMemcpyAsync(dPdst, pdst.data(), 4 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
-  GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
-  const Cam k = to_cam(cam);
-  hipLaunchKernelGGL(k_patch_rays, dim3((unsigned)((rays + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream, g->dsm, k,
-                     n_src, n_patch, (const int*)dSrc, (const double*)dR, (const double*)dT, (const double*)dUv0,
-                     (double4*)dGp);
-  GEOCHK(g, hipGetLastError());
-  GEOCHK(g, hipEventRecord(g->ev[1], g->stream));
-  if (total > 0) {
-    const unsigned bx = (unsigned)((n_patch + kBlock - 1) / kBlock);
-    for (int s0 = 0; s0 < n_src; s0 += 65535) {
-      const unsigned by = (unsigned)std::min(65535, n_src - s0);
-      hipLaunchKernelGGL(k_project, dim3(bx, by), dim3(kBlock), 0, g->stream, k, n_patch, s0, (const int*)dOff,
-                         (const int*)dPidx, (const int*)dPdst, (const double*)dR, (const double*)dT,
-                         (const double4*)dGp, (double2*)dUv, (int*)dFl);
-      GEOCHK(g, hipGetLastError());
-    }
-  }
-  if ((rc = finish(g, true))) return rc;
+  if ((rc = launch_transfer(g, to_cam(cam), n_src, n_patch, n_pairs, (const int*)dSrc, (const int*)dOff,
+                            (const int*)dPidx, (const int*)dPdst, (const double*)dR, (const double*)dT,
+                            (const double*)dUv0, (double4*)dGp, (double2*)dUv, (int*)dFl)))
+    return rc;
   if (total > 0) {
     GEOCHK(g, hipMemcpy(uv, dUv, 16 * total, hipMemcpyDeviceToHost));
     GEOCHK(g, hipMemcpy(flags, dFl, 4 * total, hipMemcpyDeviceToHost));
@@ -529,6 +582,40 @@ int ba_patch_transfer(ba_geo* g, int32_t n_img, const double* R, const double* T
       for (int q = 0; q < n_patch; ++q) lam[(size_t)src[s] * n_patch + q] = gp[4 * ((size_t)s * n_patch + q) + 3];
   }
   return BA_OK;
+}
+
+int ba_patch_transfer_noalloc(ba_geo* g, int32_t n_img, const double* R, const double* T, int32_t n_patch,
+                              const double* uv0, int32_t n_pairs, const int32_t* pairs, const ba_pinhole* cam,
+                              double* uv, int32_t* flags) {
+  if (!g) return BA_E_ARG;
+  if (n_img < 0 || n_patch < 0 || n_pairs < 0 || !cam_ok(cam)) return gfail(g, BA_E_ARG, "bad counts or camera");
+  if (n_img == 0 || n_patch == 0 || n_pairs == 0) {
+    if (n_pairs > 0 && n_img == 0) return gfail(g, BA_E_ARG, "pairs without images");
+    return BA_OK;
+  }
+  if (!R || !T || !uv0 || !pairs || !uv || !flags) return gfail(g, BA_E_ARG, "missing array");
+  if (!g->scratch) return gfail(g, BA_E_DEVICE, "scratch address not resolved");
+  std::vector<int> src, src_off, pidx, pdst;
+  int rc = group_pairs(g, n_img, n_pairs, pairs, src, src_off, pidx, pdst);
+  if (rc) return rc;
+  const int n_src = (int)src.size();
+  // scratch layout, each part 256-byte aligned: src, src_off, pidx, pdst, ground points
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_off = al(4 * (size_t)n_src), o_pidx = o_off + al(4 * (size_t)(n_src + 1));
+  const size_t o_pdst = o_pidx + al(4 * (size_t)n_pairs), o_gp = o_pdst + al(4 * (size_t)n_pairs);
+  const size_t need = o_gp + 32 * (size_t)n_src * n_patch;
+  if (need > kScratchBytes)
+    return gfail(g, BA_E_ARG, "transfer needs " + std::to_string(need) + " bytes of scratch (source images x patches x 32 "
+                 "bytes, plus the pair lists); the allocation-free entry point holds " + std::to_string(kScratchBytes));
+  GEOCHK(g, hipSetDevice(g->device));
+  char* sp = (char*)g->scratch;
+  GEOCHK(g, hipMemcpyAsync(sp, src.data(), 4 * (size_t)n_src, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(sp + o_off, src_off.data(), 4 * (size_t)(n_src + 1), hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(sp + o_pidx, pidx.data(), 4 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(sp + o_pdst, pdst.data(), 4 * (size_t)n_pairs, hipMemcpyHostToDevice, g->stream));
+  return launch_transfer(g, to_cam(cam), n_src, n_patch, n_pairs, (const int*)sp, (const int*)(sp + o_off),
+                         (const int*)(sp + o_pidx), (const int*)(sp + o_pdst), R, T, uv0, (double4*)(sp + o_gp),
+                         (double2*)uv, (int*)flags);
 }
 
 int ba_geo_last_ms(ba_geo* g, double* total_ms, double* last_ms) {
