@@ -37,8 +37,10 @@ sys.path.insert(0, ROOT)
 
 from synth import aerial as A  # noqa: E402
 
-PEAK_VALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-PEAK_MFMA_F64_TFLOPS = 78.6   # dense FP64 matrix cores (MI355X)
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed FP32: two FMAs per lane per clock)
+PEAK_VALU_TFLOPS = 78.6      # non-packed FP32 / FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz; the
+                             # ceiling of code built without packed FP32 instructions, as this library is
+PEAK_MFMA_F64_TFLOPS = 78.6  # dense FP64 matrix cores (MI355X)
 # Algorithmic work of the two Schur block kernels (flops; an FMA counts 2), in
 # the 2x2 / 2-vector formulation they use.  k_camblk, per observation of a free
 # camera: T = J_p Q (36), M = w I - w^2 T J_p^T (25), w e and w T g_p (16),
@@ -160,8 +162,9 @@ def measure_isolated(args, Context, ctx_kw, scenes, kw, flops):
     ms, n = prof[dom]
     avg = ms / max(n, 1)
     ach = fl / max(n, 1) / (avg / 1e3) / 1e12 if n else float("nan")
-    return {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": ach, "peak": PEAK_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TFLOPS, "traffic": traffic_bytes(dom, B, 1),
+    return {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "peak_nonpacked": PEAK_VALU_TFLOPS,
+            "frac_of_nonpacked": ach / PEAK_VALU_TFLOPS, "traffic": traffic_bytes(dom, B, 1),
             "traffic_unit": "bytes per launch", "avg_launch_us": avg * 1e3, "algorithmic_flop_per_launch": fl / max(n, 1),
             "batch_streams": 1,
             "note": "one more step of the same batch on one stream: each launch covers the batch, alone on the GPU"}
@@ -198,6 +201,10 @@ def run_uneven(args, Context, precision, kw):
     ctx = Context(precision=precision, max_slots=N, hbm_budget_bytes=budget, chunks_per_task=args.chunks_per_task,
                   batch_streams=args.batch_streams, iters_per_tick=args.iters_per_tick)
     times, iters, its_max = [], 0, 0
+    # the two smallest distinct clusters: their results are compared with the oracle's
+    sample = sorted(range(min(N, len(scs))), key=lambda i: scs[i]["n_obs"])[:2]
+    sample_res = {}
+    statuses = set()
     for step in range(1 + max(args.steps // 2, 1)):
         tickets = ctx.submit_many([scs[i % len(scs)] for i in range(N)], **kw)
         for t in tickets:
@@ -205,7 +212,11 @@ def run_uneven(args, Context, precision, kw):
         t0 = time.perf_counter()
         ctx.ba_solve_batch(tickets)
         dt = time.perf_counter() - t0
-        its = [ctx.ba_fetch(t)["iterations"] for t in tickets]
+        res = [ctx.ba_fetch(t) for t in tickets]
+        its = [r["iterations"] for r in res]
+        statuses |= {r["status"] for r in res}
+        if step == 0:
+            sample_res = {i: res[i] for i in sample}
         for t in tickets:
             ctx.ba_release(t)
         if step:
@@ -220,7 +231,9 @@ def run_uneven(args, Context, precision, kw):
     rep = {"clusters": N, "distinct": len(scs), "clusters_per_s": N / float(np.mean(times)),
            "ms_per_batch": 1e3 * float(np.mean(times)), "mean_iterations": iters / (N * len(times)),
            "max_iterations": its_max, "cams_range": [min(cams), max(cams)],
-           "points_range": [min(pts), max(pts)], "obs_total": int(sum(obs)), "hbm_budget_bytes": budget}
+           "points_range": [min(pts), max(pts)], "obs_total": int(sum(obs)), "hbm_budget_bytes": budget,
+           "statuses": sorted(int(x) for x in statuses)}
+    rep["_sample"] = [(scs[i], sample_res[i]) for i in sample]
     if not args.uneven_serve:
         return rep
     # the same clusters through the serving loop under a quarter of their total
@@ -257,17 +270,36 @@ def run_stream(args, Context, precision, kw):
     of Eq. (8)), closed loop with a fixed number in flight.  Latency =
     submit -> result available."""
     from collections import deque
+    from paper_2511_06152_amd import Geo
     from paper_2511_06152_amd.ba import Cluster
+    from synth import geo as SG
     t_gen = time.perf_counter()
-    st = A.make_stream(3)
-    cl = st["clusters"]
-    log(f"stream: {len(cl)} clusters from {st['flight']['n_cams']} images, "
-        f"{st['flight']['n_points']} pool points in {time.perf_counter() - t_gen:.1f}s")
+    sf = A.stream_flight(3)
+    fl = sf["flight"]
+    # cluster formation (Sec. 3.1-3.2) on the GPU: footprints of the GNSS/IMU
+    # poses on the flight's DSM, then the images each arriving image's
+    # footprint overlaps, within and across strips
+    cam = {"f": fl["f"], "cx": fl["cx"], "cy": fl["cy"], "width": A.IMG_W, "height": A.IMG_H}
+    rule = dict(max_back=7, free_back=3, max_cams=20, min_cams=8, min_overlap=0.05)
+    with Geo(SG.flight_dsm(fl)) as geo:
+        fp, _ = geo.ba_footprints(fl["R"], fl["T"], cam)
+        fp_ms = geo.ba_geo_last_ms()
+        members = geo.ba_cluster_membership(fp, fl["truth"]["strip"], **rule)
+        mem_ms = geo.ba_geo_last_ms()
+    cl = A.cut_clusters(sf, members)
+    formation = {"images": int(fl["n_cams"]), "clusters_formed": len(cl), "rule": rule,
+                 "footprints_ms": fp_ms, "membership_ms": mem_ms,
+                 "note": "each cluster's images from ba_footprints + ba_cluster_membership on the flight's "
+                         "GNSS/IMU poses and DSM"}
+    log(f"stream: {len(cl)} clusters formed from {fl['n_cams']} images' footprints "
+        f"({fp_ms * 1e3:.0f} + {mem_ms * 1e3:.0f} us), {fl['n_points']} pool points in "
+        f"{time.perf_counter() - t_gen:.1f}s")
     probe = Context(precision=precision, max_slots=2, hbm_budget_bytes=64 << 20)
     foot = max(probe.ba_footprint(Cluster(sc, **kw)) for sc in cl)
     probe.close()
     W = max(args.stream_window, 1)
     lat, walls = [], []
+    first = []          # results of the first clusters of repetition 0, in submission order
     for rep in range(args.stream_reps):
         ctx = Context(precision=precision, serve=True, max_slots=W + 2, hbm_budget_bytes=(W + 2) * foot + (64 << 20))
         pending = deque()
@@ -278,6 +310,8 @@ def run_stream(args, Context, precision, kw):
             ctx.ba_wait(t)
             r = ctx.ba_fetch(t)
             lat.append((r["t_done"] - r["t_submit"]) * 1e3)
+            if rep == 0 and len(first) < args.stream_oracle_clusters:
+                first.append(r)
             ctx.ba_release(t)
 
         for sc in cl:
@@ -291,13 +325,14 @@ def run_stream(args, Context, precision, kw):
         walls.append(time.perf_counter() - t0)
         ctx.close()
         log(f"stream rep {rep}: {len(cl)} clusters in {walls[-1] * 1e3:.0f} ms")
-    return {"clusters_per_rep": len(cl), "reps": args.stream_reps, "window": W,
+    return {"clusters_per_rep": len(cl), "reps": args.stream_reps, "window": W, "formation": formation,
             "cams_range": [min(c["n_cams"] for c in cl), max(c["n_cams"] for c in cl)],
             "points_range": [min(c["n_points"] for c in cl), max(c["n_points"] for c in cl)],
             "obs_range": [min(c["n_obs"] for c in cl), max(c["n_obs"] for c in cl)],
             "clusters_per_s": len(cl) * len(walls) / sum(walls), "latencies": len(lat),
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "budget_ms": 2080.0,
-            "p99_fraction_of_budget": pct(lat, 99) / 2080.0}
+            "p99_fraction_of_budget": pct(lat, 99) / 2080.0,
+            "_sample": list(zip(cl[:len(first)], first))}
 
 
 def run_chain(args, Context, precision, kw):
@@ -314,6 +349,7 @@ def run_chain(args, Context, precision, kw):
     cl = A.make_chain(9)["clusters"]
     log(f"chain: {len(cl)} clusters of {[c['n_cams'] for c in cl]} images in {time.perf_counter() - t_gen:.1f}s")
     walls, lat, errs = [], [], []
+    res0 = []
     for rep in range(args.chain_reps):
         ctx = Context(precision=precision, serve=True, max_slots=4, hbm_budget_bytes=1 << 30)
         t0 = time.perf_counter()
@@ -327,6 +363,7 @@ def run_chain(args, Context, precision, kw):
         walls.append(time.perf_counter() - t0)
         lat += [(r["t_done"] - r["t_submit"]) * 1e3 for r in res]
         if rep == 0:
+            res0 = res
             for sc, r in zip(cl, res):
                 e = A.project_obs(r["R"], r["T"], r["X"], r["k"], sc["obs_cam"], sc["obs_pt"]) - sc["obs_uv"]
                 errs.append(np.sqrt((e ** 2).sum(1)))
@@ -341,7 +378,8 @@ def run_chain(args, Context, precision, kw):
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
             "reproj_err_mean_px": float(e.mean()), "reproj_err_std_px": float(e.std()),
             "paper_context": "MATLAB on an i7 laptop CPU, 60 images: 66.45 s total with feature extraction and "
-                             "matching, 1.11 s per image pair (Table 1)"}, cl
+                             "matching, 1.11 s per image pair (Table 1)",
+            "_sample": list(zip(cl, res0))}, cl
 
 
 def run_geo(args):
@@ -391,6 +429,8 @@ def run_geo(args):
                                 "avg_launch_us": pr_ms * 1e3}}
     log(f"geo: footprints {rep['footprints_ms'] * 1e3:.1f} us, overlaps {rep['overlaps_ms'] * 1e3:.1f} us, "
         f"transfer {rep['transfer_ms'] * 1e3:.1f} us ({outputs} outputs; projection {pr_ms * 1e3:.1f} us)")
+    sel = list(range(0, len(pairs), max(1, len(pairs) // 8)))[:8]
+    rep["_sample"] = [(int(pairs[i][0]), int(pairs[i][1]), uv[i].copy(), fl[i].copy()) for i in sel]
     return rep, (g, cam, uv0, pairs)
 
 
@@ -406,7 +446,10 @@ def run_global(args, Context, precision):
     log(f"global: generated C={sc['n_cams']} P={sc['n_points']} O={sc['n_obs']} "
         f"in {time.perf_counter() - t_gen:.1f}s")
     n = args.global_iters
-    cl = Cluster(sc, max_iters=n + 1)
+    total = max(args.global_total_iters, n + 1)
+    # the timed iterations, then (untimed) on to `total` iterations for the
+    # comparison with the oracle's state after as many
+    cl = Cluster(sc, max_iters=total)
     probe = Context(precision=precision, max_slots=2, hbm_budget_bytes=64 << 20)
     foot = probe.ba_footprint(cl)
     probe.close()
@@ -420,15 +463,90 @@ def run_global(args, Context, precision):
     dt = time.perf_counter() - t0
     prof = ctx.ba_profile_read()
     r = ctx.ba_fetch(t)
-    ctx.close()
     out = {"cams": sc["n_cams"], "points": sc["n_points"], "obs": sc["n_obs"], "m": 6 * sc["n_cams"],
            "lm_iterations_timed": n, "ms_per_lm_iteration": 1e3 * dt / n,
            "cg_iterations_total": r["cg_iters"], "pcg_avg_ms": prof["pcg"][0] / max(prof["pcg"][1], 1),
            "kernel_avg_us": {k: 1e3 * v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
-           "cost_initial": float(r["cost_log"][0]), "cost_final": float(r["cost_log"][-1]),
+           "cost_initial": float(r["cost_log"][0]), "cost_after_timed": float(r["cost_log"][-1]),
            "hbm_footprint_bytes": foot}
+    if total > n + 1:
+        t0 = time.perf_counter()
+        ctx.ba_step(t, total - n - 1)
+        dt2 = time.perf_counter() - t0
+        r = ctx.ba_fetch(t)
+        out["continued"] = {"status": int(r["status"]), "iterations": int(r["iterations"]),
+                            "wall_s": dt2, "cost_final": float(r["cost_log"][-1]),
+                            "error_vs_oracle": global_error_vs_golden(sc, r)}
+        log(f"global: {r['iterations']} iterations (status {r['status']}); error vs the oracle's state after as "
+            f"many {out['continued']['error_vs_oracle']}")
+    ctx.close()
     log(f"global: {out['ms_per_lm_iteration']:.2f} ms per LM iteration, {r['cg_iters']} CG iterations")
     return out, sc
+
+
+GOLDEN_GLOBAL = os.path.join(ROOT, "tests", "golden", "global_400cams_seed5_iter150.txt")
+
+
+def read_golden_global(path=GOLDEN_GLOBAL):
+    """The oracle's converged solution of the 400-camera flight (written by
+    tests/golden/make_global_solution.py): cameras R [C,3,3], T [C,3], and
+    the sampled points' indices and positions; None when absent."""
+    if not os.path.exists(path):
+        return None
+    cams, pts = [], []
+    meta = {}
+    part = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                if line.startswith("# iterations"):
+                    tok = line[1:].split()
+                    meta = {tok[i]: float(tok[i + 1]) for i in range(0, len(tok) - 1, 2)}
+                part = "pts" if "points:" in line else ("cams" if "cameras:" in line else part)
+                continue
+            v = [float(x) for x in line.split()]
+            (cams if part == "cams" else pts).append(v)
+    cams, pts = np.array(cams), np.array(pts)
+    return {"R": cams[:, :9].reshape(-1, 3, 3), "T": cams[:, 9:12], "idx": pts[:, 0].astype(np.int64),
+            "X": pts[:, 1:4], "meta": meta}
+
+
+def state_errors(sc, R_a, T_a, X_a, R_b, T_b, X_b, k=(0.0, 0.0), k_b=None, obs_sel=None):
+    """RMS over observations of |p_a - p_b| (each state with its own radial
+    k1, k2; the generator's forward model), max camera-centre difference, max
+    attitude angle of R_a^T R_b."""
+    oc, op = sc["obs_cam"], sc["obs_pt"]
+    if obs_sel is not None:
+        oc, op = oc[obs_sel], op[obs_sel]
+    d = A.project_obs(R_a, T_a, X_a, k, oc, op) - A.project_obs(R_b, T_b, X_b, k if k_b is None else k_b, oc, op)
+    rms = float(np.sqrt((d ** 2).sum(1).mean())) if len(d) else 0.0
+    return {"rms_px": rms, "centres_m": float(np.abs(T_a - T_b).max()), "attitude_rad": max_angle(R_a, R_b)}
+
+
+def max_angle(R_a, R_b):
+    """Largest rotation angle of R_a[c]^T R_b[c] over the cameras, as
+    atan2(|sin|, cos) from the skew and trace parts (accurate for small
+    angles, where arccos of the trace loses half the digits)."""
+    M = np.einsum("cji,cjk->cik", np.asarray(R_a), np.asarray(R_b))
+    v = 0.5 * np.stack([M[:, 2, 1] - M[:, 1, 2], M[:, 0, 2] - M[:, 2, 0], M[:, 1, 0] - M[:, 0, 1]], 1)
+    c = 0.5 * (np.trace(M, axis1=1, axis2=2) - 1.0)
+    return float(np.max(np.arctan2(np.linalg.norm(v, axis=1), c))) if len(M) else 0.0
+
+
+def global_error_vs_golden(sc, r):
+    """The GPU's converged global solution against the oracle's (stored):
+    every camera, and the predicted pixels of every observation of the
+    stored sample of points."""
+    g = read_golden_global()
+    if g is None:
+        return None
+    sel = np.isin(sc["obs_pt"], g["idx"])
+    X_ref = np.array(r["X"], copy=True)
+    X_ref[g["idx"]] = g["X"]
+    e = state_errors(sc, r["R"], r["T"], r["X"], g["R"], g["T"], X_ref, obs_sel=sel)
+    e.update(observations_compared=int(sel.sum()), points_compared=int(len(g["idx"])),
+             oracle_iterations=int(g["meta"].get("iterations", 0)))
+    return e
 
 
 def run_selfcal(args, Context, ctx_kw, scenes, kw):
@@ -439,24 +557,170 @@ def run_selfcal(args, Context, ctx_kw, scenes, kw):
     sc5 = [dict(s, intr_mask=0b11111, f=s["f"] * 1.001, cx=s["cx"] + 2.0, cy=s["cy"] - 2.0) for s in scenes]
     ctx = Context(batch_streams=args.batch_streams, **ctx_kw)
     step_ms, iters = [], []
+    statuses, sample = set(), []
     for rep in range(args.selfcal_reps + 1):
-        tickets = [ctx.submit(sc5[(rep * B + i) % len(sc5)], **kw) for i in range(B)]
+        ids = [(rep * B + i) % len(sc5) for i in range(B)]
+        tickets = [ctx.submit(sc5[j], **kw) for j in ids]
         for t in tickets:
             ctx.ba_step(t, 0)
         t0 = time.perf_counter()
         ctx.ba_solve_batch(tickets)
         t1 = time.perf_counter()
-        for t in tickets:
+        for t, j in zip(tickets, ids):
+            r = ctx.ba_fetch(t)
+            statuses.add(int(r["status"]))
             if rep > 0:
-                iters.append(ctx.ba_fetch(t)["iterations"])
+                iters.append(r["iterations"])
+            if rep == 0 and j == 0 and not sample:
+                sample.append((sc5[0], r))
             ctx.ba_release(t)
         if rep > 0:
             step_ms.append((t1 - t0) * 1e3)
         log(f"self-calibration rep {rep}{'' if rep else ' (warmup)'}: {(t1 - t0) * 1e3:.2f} ms for {B} clusters")
     ctx.close()
     ms = float(np.mean(step_ms))
+    bad = statuses & {4, 5}
+    if bad:
+        raise RuntimeError(f"self-calibration leg: clusters ended stalled or with a bad initial state {bad}")
     return {"clusters": B, "reps": args.selfcal_reps, "intr_mask": "k1 k2 f cx cy", "m": 6 * 12 + 5,
-            "ms_per_batch": ms, "clusters_per_s": B / (ms / 1e3), "mean_iterations": float(np.mean(iters))}
+            "ms_per_batch": ms, "clusters_per_s": B / (ms / 1e3), "mean_iterations": float(np.mean(iters)),
+            "statuses": sorted(statuses), "_sample": sample}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_leg(args, scenes, mixed_final, plain_final, uneven, selfcal, stream, chain, geo, geo_in,
+                     glob_scene):
+    """The FP64 oracle on the host: throughput at one thread and at the
+    cores this process may use (clusters are independent, so the threads
+    solve different clusters), and the final error of each GPU leg's results
+    against the oracle's on the same inputs and rule."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build(force=False)
+    kw = dict(max_iters=args.max_iters, stop_on_ftol=True, ftol=args.ftol)
+
+    def errs(sc, got, ref):
+        """|p_gpu - p_oracle| RMS over every observation (each state with
+        its own intrinsics, the oracle's projection), centres, attitude."""
+        kg = np.concatenate([got["k"], got["intr"]])
+        uv_g = oracle.residuals(sc, (got["R"], got["T"], got["X"], kg))["uv"]
+        uv_o = oracle.residuals(sc, ref["state"])["uv"]
+        R_o, T_o = ref["state"][0], ref["state"][1]
+        att = max_angle(got["R"], R_o)
+        return {"rms_px": float(np.sqrt(((uv_g - uv_o) ** 2).sum(1).mean())) if len(uv_g) else 0.0,
+                "centres_m": float(np.abs(got["T"] - T_o).max()), "attitude_rad": att,
+                "iterations_gpu": int(got["iterations"]), "iterations_oracle": int(ref["iterations"])}
+
+    def worst(rows):
+        if not rows:
+            return None
+        out = {k: max(r[k] for r in rows) for k in ("rms_px", "centres_m", "attitude_rad")}
+        out["results_compared"] = len(rows)
+        out["iterations_equal"] = all(r["iterations_gpu"] == r["iterations_oracle"] for r in rows)
+        return out
+
+    # throughput: one thread, then the host's cores
+    n1 = args.cpu_clusters
+    t0 = time.perf_counter()
+    refs = [oracle.solve(scenes[i % len(scenes)], **kw) for i in range(n1)]
+    dt1 = time.perf_counter() - t0
+    nth = args.cpu_threads or min(len(os.sched_getaffinity(0)), 16)
+    n_par = 2 * nth
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nth) as ex:       # the oracle's ctypes calls release the GIL
+        list(ex.map(lambda i: oracle.solve(scenes[i % len(scenes)], **kw), range(n_par)))
+    dtn = time.perf_counter() - t0
+    cpu = {"value": n_par / dtn, "unit": "clusters/s", "cores": nth, "kind": "oracle",
+           "sample": f"{n_par} clusters of the headline workload, same termination rule, FP64 C++ oracle, "
+                     f"{nth} threads each solving whole clusters ({dtn:.1f} s)",
+           "cpu_model": cpu_model(), "cpus_visible": len(os.sched_getaffinity(0)),
+           "single_thread": {"value": n1 / dt1, "unit": "clusters/s", "cores": 1,
+                             "sample": f"{n1} clusters, one thread ({dt1:.1f} s)"}}
+    fe = {}
+    fe["headline_mixed"] = worst([errs(scenes[i % len(scenes)], mixed_final[i % len(scenes)], refs[i])
+                                  for i in range(n1) if i % len(scenes) in mixed_final])
+    fe["plain_fp64"] = worst([errs(scenes[i % len(scenes)], plain_final[i % len(scenes)], refs[i])
+                              for i in range(n1) if i % len(scenes) in plain_final])
+    if uneven is not None and uneven.get("_sample"):
+        fe["batched_uneven"] = worst([errs(sc, r, oracle.solve(sc, **kw)) for sc, r in uneven["_sample"]])
+    if selfcal is not None and selfcal.get("_sample"):
+        fe["self_calibration"] = worst([errs(sc, r, oracle.solve(sc, **kw)) for sc, r in selfcal["_sample"]])
+
+    def replay(clusters, results):
+        """Clusters chained by resident state, replayed on the host in
+        submission order: each starts from the values the clusters before it
+        left (fused poses by Eq. 8, solved points), and is solved by the oracle
+        with the same rule; returns the errors of the GPU's results."""
+        store_c, store_p, rows = {}, {}, []
+        for sc, got in zip(clusters, results):
+            R, T, X = sc["R"].copy(), sc["T"].copy(), sc["X"].copy()
+            for k, cid in enumerate(sc["cam_ids"]):
+                if cid in store_c:
+                    R[k], T[k] = store_c[cid][0], store_c[cid][1]
+            for j, pid in enumerate(sc["point_ids"]):
+                if pid in store_p:
+                    X[j] = store_p[pid]
+            sc2 = dict(sc, R=R, T=T, X=X)
+            ref = oracle.solve(sc2, **kw)
+            if got is not None:
+                rows.append(errs(sc2, got, ref))
+            Rf, Tf, Xf, _ = ref["state"]
+            n = np.bincount(sc["obs_cam"], minlength=sc["n_cams"]).astype(np.float64)
+            for k, cid in enumerate(sc["cam_ids"]):
+                if not sc["fixed"][k] and cid in store_c:
+                    store_c[cid] = oracle.fuse_pose(*store_c[cid], Rf[k], Tf[k], n[k])
+                else:
+                    store_c[cid] = (Rf[k], Tf[k], float(n[k]))
+            for j, pid in enumerate(sc["point_ids"]):
+                store_p[pid] = Xf[j]
+        return rows
+
+    if chain is not None and chain.get("_sample"):
+        cl = [c for c, _ in chain["_sample"]]
+        t0 = time.perf_counter()
+        rows = replay(cl, [r for _, r in chain["_sample"]])
+        cpu["chain_s_per_flight"] = time.perf_counter() - t0
+        cpu["chain_sample"] = f"the chained {len(cl)}-cluster flight once, same termination rule, single-threaded"
+        fe["paper_chain"] = worst(rows)
+    if stream is not None and stream.get("_sample"):
+        fe["serving_stream"] = worst(replay([c for c, _ in stream["_sample"]], [r for _, r in stream["_sample"]]))
+        if fe["serving_stream"]:
+            fe["serving_stream"]["note"] = "the stream's first clusters (repetition 0), replayed in submission order"
+    if geo_in is not None:
+        from oracle import geo as OG
+        g, cam, uv0, pairs = geo_in
+        t0 = time.perf_counter()
+        n_out, d_uv, fl_eq = 0, 0.0, True
+        for s_, d_, uv_g, fl_g in geo["_sample"]:
+            uv_o, _, fl_o = OG.transfer_eq3(g["dsm"], g["R"][s_], g["T"][s_], g["R"][d_], g["T"][d_], cam["f"],
+                                            cam["cx"], cam["cy"], cam["width"], cam["height"], uv0)
+            n_out += len(uv0)
+            ok = np.isfinite(uv_o).all(1) & np.isfinite(uv_g).all(1)
+            if ok.any():
+                d_uv = max(d_uv, float(np.abs(uv_g[ok] - uv_o[ok]).max()))
+            fl_eq = fl_eq and bool(np.array_equal(np.isfinite(uv_o).all(1), np.isfinite(uv_g).all(1)))
+        dt = time.perf_counter() - t0
+        cpu["geo_transfers_per_s"] = n_out / dt
+        cpu["geo_sample"] = f"{n_out} Eq. (3) transfers (8 pairs x {len(uv0)} patches), single-threaded numpy"
+        fe["geo_transfer"] = {"max_abs_px": d_uv, "hits_equal": fl_eq, "transfers_compared": n_out}
+    if glob_scene is not None and args.global_oracle_iters > 0:
+        t0 = time.perf_counter()
+        oracle.solve(glob_scene, max_iters=args.global_oracle_iters)
+        cpu["global_ba_s_per_lm_iteration"] = (time.perf_counter() - t0) / args.global_oracle_iters
+        cpu["global_ba_sample"] = (f"{args.global_oracle_iters} LM iteration(s) of the 400-camera flight "
+                                   "(dense FP64 Schur complement and Cholesky, m = 2400), single-threaded")
+    fe["bars"] = {"rms_px": 1e-3, "centres_m": 1e-3, "attitude_rad": 2e-6}
+    return cpu, fe
 
 
 def main():
@@ -497,6 +761,17 @@ def main():
                          "fusion; 0: skip)")
     ap.add_argument("--geo-reps", type=int, default=5,
                     help="timed repetitions of the footprint / overlap / Eq. (3) transfer leg (0: skip)")
+    ap.add_argument("--global-total-iters", type=int, default=150,
+                    help="after the timed global iterations, further ones (untimed) up to this many in all, "
+                         "for the comparison with the oracle's state after as many (stored by "
+                         "tests/golden/make_global_solution.py); at most the timed ones + 1: skip")
+    ap.add_argument("--stream-oracle-clusters", type=int, default=6,
+                    help="first serving-stream clusters replayed by the oracle for the final-error figures")
+    ap.add_argument("--batched-fp64", type=int, default=1,
+                    help="also time the headline batch through ba_solve_batch in plain FP64 (0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the multi-threaded oracle timing (0: the cores this process may "
+                         "use, at most 16)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -578,6 +853,32 @@ def main():
     value = B / (ms_per_step / 1e3)
     selfcal = run_selfcal(args, Context, ctx_kw, scenes, kw) if args.selfcal_reps > 0 else None
 
+    # ---- the same batch through ba_solve_batch in plain FP64: what FP32 assembly alone buys
+    batched_fp64 = None
+    if args.batched_fp64:
+        fctx = Context(batch_streams=args.batch_streams, **dict(ctx_kw, precision=BA_FP64))
+        f_ms, f_it = [], 0
+        for step in range(1 + max(args.steps // 2, 1)):
+            ids = [(step * B + i) % len(scenes) for i in range(B)]
+            tickets = [fctx.submit(scenes[j], **kw) for j in ids]
+            for t in tickets:
+                fctx.ba_step(t, 0)
+            t0 = time.perf_counter()
+            fctx.ba_solve_batch(tickets)
+            t1 = time.perf_counter()
+            for t in tickets:
+                if step:
+                    f_it += fctx.ba_fetch(t)["iterations"]
+                fctx.ba_release(t)
+            if step:
+                f_ms.append((t1 - t0) * 1e3)
+            log(f"batched FP64 step {step}{'' if step else ' (warmup)'}: {(t1 - t0) * 1e3:.2f} ms for {B} clusters")
+        fctx.close()
+        batched_fp64 = {"clusters_per_s": B / (float(np.mean(f_ms)) / 1e3), "ms_per_batch": float(np.mean(f_ms)),
+                        "mean_iterations": f_it / (B * len(f_ms)),
+                        "note": "ba_solve_batch with precision BA_FP64 on the same batch, context options and "
+                                "rule: FP64 assembly, everything else as the headline"}
+
     dom = "blocks"
     asm_ms, asm_n = prof[dom]
     asm_avg_ms = asm_ms / max(asm_n, 1)
@@ -587,7 +888,8 @@ def main():
                if k != "pairblk"}
 
     in_step = {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": achieved_tflops,
-               "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_VALU_TFLOPS,
+               "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+               "peak_nonpacked": PEAK_VALU_TFLOPS, "frac_of_nonpacked": achieved_tflops / PEAK_VALU_TFLOPS,
                "traffic": traffic_bytes(dom, B, args.batch_streams), "traffic_unit": "bytes per launch",
                "avg_launch_us": asm_avg_ms * 1e3, "algorithmic_flop_per_launch": fl_total[dom] / max(asm_n, 1),
                "batch_streams": args.batch_streams,
@@ -657,15 +959,21 @@ def main():
     rms = {}
     common = sorted(set(mixed_final) & set(plain_final))
     if common:
-        d = []
+        d, dp = [], []
         for j in common:
-            rm = rms_px(scenes[j], *mixed_final[j]["state"])
-            rp = rms_px(scenes[j], *plain_final[j]["state"])
+            rm = mixed_final[j]["reproj_rms"]
+            rp = plain_final[j]["reproj_rms"]
             d.append(abs(rm - rp))
+            # RMS over the observations of |p_mixed - p_plain| at the two final states
+            dp.append(state_errors(scenes[j], *mixed_final[j]["state"][:3], *plain_final[j]["state"][:3],
+                                   k=mixed_final[j]["k"], k_b=plain_final[j]["k"])["rms_px"])
             rms.setdefault("mixed_px", rm)
             rms.setdefault("plain_fp64_px", rp)
-        rms["max_abs_diff_px"] = float(max(d))
+        rms["max_abs_diff_of_rms_px"] = float(max(d))
+        rms["max_rms_of_prediction_diff_px"] = float(max(dp))
         rms["clusters_compared"] = len(common)
+        rms["note"] = ("reprojection RMS of each path from ba_fetch (device FP64); the prediction difference "
+                       "is the RMS over all observations of |p_mixed - p_plain|")
 
     # ---- uneven batched clusters: 6-24 cameras, 5k-60k points, one batch --------------------
     uneven = run_uneven(args, Context, BA_MIXED, kw) if args.uneven > 0 else None
@@ -682,63 +990,22 @@ def main():
     # ---- whole-flight global adjustment (PCG on the reduced camera system) ------------------
     glob, glob_scene = run_global(args, Context, BA_MIXED) if args.global_iters > 0 else (None, None)
 
-    # ---- CPU baseline: the FP64 oracle on the host cores ---------------------------------
-    cpu = None
+    # ---- CPU baseline: the FP64 oracle on the host cores, and the final error -----------------
+    # of every leg's results against the oracle's (the only place the oracle runs)
+    cpu, final_err = None, None
     if args.cpu_clusters > 0:
-        import oracle
-        oracle.build(force=False)
-        t0 = time.perf_counter()
-        for i in range(args.cpu_clusters):
-            oracle.solve(scenes[i % len(scenes)], max_iters=args.max_iters, stop_on_ftol=True, ftol=args.ftol)
-        dt = time.perf_counter() - t0
-        cpu = {"value": args.cpu_clusters / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_clusters} clusters of the same workload, same termination rule, "
-                         f"single-threaded FP64 C++ ({dt:.1f} s)"}
-        if chain_cl is not None:
-            # the same chain on the host: each cluster from the fused poses and
-            # points the clusters before it left
-            t0 = time.perf_counter()
-            store_c, store_p = {}, {}
-            for sc in chain_cl:
-                R, T, X = sc["R"].copy(), sc["T"].copy(), sc["X"].copy()
-                for k, cid in enumerate(sc["cam_ids"]):
-                    if cid in store_c:
-                        R[k], T[k] = store_c[cid][0], store_c[cid][1]
-                for j, pid in enumerate(sc["point_ids"]):
-                    if pid in store_p:
-                        X[j] = store_p[pid]
-                ref = oracle.solve(dict(sc, R=R, T=T, X=X), max_iters=args.max_iters, stop_on_ftol=True,
-                                   ftol=args.ftol)
-                Rf, Tf, Xf, _ = ref["state"]
-                n = np.bincount(sc["obs_cam"], minlength=sc["n_cams"]).astype(np.float64)
-                for k, cid in enumerate(sc["cam_ids"]):
-                    if not sc["fixed"][k] and cid in store_c:
-                        store_c[cid] = oracle.fuse_pose(*store_c[cid], Rf[k], Tf[k], n[k])
-                    else:
-                        store_c[cid] = (Rf[k], Tf[k], float(n[k]))
-                for j, pid in enumerate(sc["point_ids"]):
-                    store_p[pid] = Xf[j]
-            cpu["chain_s_per_flight"] = time.perf_counter() - t0
-            cpu["chain_sample"] = (f"the chained {len(chain_cl)}-cluster flight once, same termination rule, "
-                                   "single-threaded")
-        if geo_in is not None:
-            from oracle import geo as OG
-            g, cam, uv0, pairs = geo_in
-            t0 = time.perf_counter()
-            n_out = 0
-            for s_, d_ in pairs[:: max(1, len(pairs) // 8)][:8]:
-                OG.transfer_eq3(g["dsm"], g["R"][s_], g["T"][s_], g["R"][d_], g["T"][d_], cam["f"], cam["cx"],
-                                cam["cy"], cam["width"], cam["height"], uv0)
-                n_out += len(uv0)
-            dt = time.perf_counter() - t0
-            cpu["geo_transfers_per_s"] = n_out / dt
-            cpu["geo_sample"] = f"{n_out} Eq. (3) transfers (8 pairs x {len(uv0)} patches), single-threaded numpy"
-        if glob_scene is not None and args.global_oracle_iters > 0:
-            t0 = time.perf_counter()
-            oracle.solve(glob_scene, max_iters=args.global_oracle_iters)
-            cpu["global_ba_s_per_lm_iteration"] = (time.perf_counter() - t0) / args.global_oracle_iters
-            cpu["global_ba_sample"] = (f"{args.global_oracle_iters} LM iteration(s) of the 400-camera flight "
-                                       "(dense FP64 Schur complement and Cholesky, m = 2400), single-threaded")
+        cpu, final_err = cpu_baseline_leg(args, scenes, mixed_final, plain_final, uneven, selfcal, stream, chain,
+                                          geo, geo_in, glob_scene)
+    if glob is not None and glob.get("continued"):
+        final_err = final_err or {}
+        final_err["global_ba"] = dict(glob["continued"]["error_vs_oracle"] or {},
+                                      note="GPU state (mixed, PCG with the default forcing term) after 150 LM "
+                                           "iterations against the oracle's (exact steps) after 150, stored by "
+                                           "tests/golden/make_global_solution.py; every camera, and every "
+                                           "observation of 5000 sampled points")
+    for leg in (uneven, stream, chain, geo, selfcal):
+        if leg is not None:
+            leg.pop("_sample", None)
 
     O_mean = float(np.mean([s["n_obs"] for s in scenes]))
     P_mean = float(np.mean([s["n_points"] for s in scenes]))
@@ -777,6 +1044,9 @@ def main():
         "roofline_in_step": in_step,
         "solve_matrix_cores": solve_mc,
         "cpu_baseline": cpu,
+        "final_error_vs_oracle": final_err,
+        "batched_fp64": batched_fp64,
+        "speedup_vs_batched_fp64": value / batched_fp64["clusters_per_s"] if batched_fp64 else None,
         "batched_uneven": uneven,
         "serving_stream": stream,
         "self_calibration": selfcal,

@@ -108,6 +108,41 @@ int ba_footprints(ba_geo* ctx, int32_t n, const double* R, const double* T, cons
  * BA_E_DEVICE. */
 int ba_footprint_overlaps(ba_geo* ctx, int32_t n, const double* ground, double* area);
 
+/* How ba_cluster_membership forms a cluster (Sec. 3.1-3.2). */
+typedef struct {
+  int32_t max_back;             /* in-strip predecessors of the triggering image, at most (>= 0) */
+  int32_t free_back;            /* in-strip predecessors within this many steps stay free (>= 0) */
+  int32_t max_cams;             /* images per cluster, at most (1..64) */
+  int32_t min_cams;             /* a triggering image with fewer forms no cluster (1..max_cams) */
+  double min_overlap;           /* two footprints overlap when their intersection covers at least
+                                   this fraction of the smaller one (0..1) */
+} ba_cluster_rule;
+
+/* Cluster membership from footprints (Sec. 3.1: the images that overlap an
+ * image, within its strip and across strips, are found by comparing
+ * footprints; Sec. 3.2: each new image is adjusted in a cluster with its
+ * overlapping images, the part adjusted before held fixed).  n images in
+ * flight order with footprints ground [15n] (as ba_footprints writes them)
+ * and strip [n] (the strip of each image).  Two images overlap when both
+ * footprints exist (convex corner quadrilaterals, finite centre point) and
+ * the area of their intersection (as ba_footprint_overlaps computes it) is
+ * at least rule->min_overlap times the smaller footprint's area.  The
+ * cluster triggered by image i holds: i; its in-strip predecessors i-1,
+ * i-2, ... (at most max_back, each in i's strip and overlapping the image
+ * after it); then the earlier images (index < i) of other strips that
+ * overlap i, nearest first by the horizontal distance between footprint
+ * centres (ties: lower index); the list cut at max_cams.  With fewer than
+ * min_cams images image i forms no cluster.  The fixed images are the other
+ * strips' and the in-strip predecessors more than free_back steps back.
+ * Writes, for each image i, count [n] (its cluster's size, 0 for none),
+ * members [n][max_cams] (the cluster's images in ascending order, -1
+ * after the last) and fixed [n][max_cams] (1 = held fixed, aligned with
+ * members).  Integer results; calls are synchronous.
+ * Errors: BA_E_ARG (NULL arrays with n > 0, n outside 0..65536, a bad rule),
+ * BA_E_NOMEM, BA_E_DEVICE. */
+int ba_cluster_membership(ba_geo* ctx, int32_t n, const double* ground, const int32_t* strip,
+                          const ba_cluster_rule* rule, int32_t* members, uint8_t* fixed, int32_t* count);
+
 /* GNSS/IMU patch transfer, Eq. (3), with the patch depth from the DSM:
  * for each pair p = (src, dst) in pairs [2 n_pairs] (image indices into R, T)
  * and each patch centre q of uv0 [2 n_patch] (pixel coordinates in the source

@@ -204,3 +204,65 @@ def transfer_eq3(dsm: dict, R0, T0, Rk, Tk, f, cx, cy, width, height, uv0):
         uv[p] = (u, v)
         lam_out[p] = lam
     return uv, lam_out, flags
+
+
+def _quad_ok(q) -> bool:
+    q = np.asarray(q, np.float64)[:4, :2]
+    if not np.all(np.isfinite(q)):
+        return False
+    if polygon_area(q) < 0:
+        q = q[::-1]
+    return _is_convex_ccw(q)
+
+
+def cluster_membership(fp, strip, max_back=7, free_back=3, max_cams=20, min_cams=8, min_overlap=0.05):
+    """The images of the cluster each image triggers (Sec. 3.1: overlapping
+    images, within and across strips, are found by comparing footprints;
+    Sec. 3.2: the cluster of the current image and its overlapping images,
+    the part already adjusted held fixed).  fp [n][5][3] footprints in
+    flight order, strip [n] the strip of each image.
+
+    Two images overlap when both footprints exist (finite, convex corner
+    quadrilaterals and a finite centre point) and the area of their intersection is at least
+    min_overlap times the smaller of the two footprint areas.  The cluster
+    of image i: i; then its in-strip predecessors i-1, i-2, ... (at most
+    max_back, same strip, each overlapping the image after it); then the
+    earlier images of other strips that overlap image i, nearest first by
+    the horizontal distance of the footprint centres (ties: lower index);
+    the list cut at max_cams.  Fewer than min_cams images: no cluster.
+    Fixed: the earlier images of other strips and the in-strip predecessors
+    more than free_back steps back; free: i and the rest.
+
+    Returns, per image, None or (members ascending, fixed flags aligned)."""
+    n = len(fp)
+    strip = np.asarray(strip)
+    ok = [_quad_ok(fp[k]) and bool(np.all(np.isfinite(np.asarray(fp[k], np.float64)[4, :2]))) for k in range(n)]
+    area = [abs(polygon_area(np.asarray(fp[k], np.float64)[:4, :2])) if ok[k] else 0.0 for k in range(n)]
+
+    def overlapping(a, b):
+        if not (ok[a] and ok[b]):
+            return False
+        return overlap_area(fp[a][:4], fp[b][:4]) >= min_overlap * min(area[a], area[b])
+
+    out = []
+    for i in range(n):
+        own = []
+        j = i - 1
+        while j >= 0 and len(own) < max_back and strip[j] == strip[i] and overlapping(j, j + 1):
+            own.append(j)
+            j -= 1
+        cand = []
+        for j in range(i):
+            if strip[j] != strip[i] and overlapping(i, j):
+                dx = fp[j][4][0] - fp[i][4][0]
+                dy = fp[j][4][1] - fp[i][4][1]
+                cand.append((dx * dx + dy * dy, j))
+        cand.sort()
+        cams = ([i] + own + [j for _, j in cand])[:max_cams]
+        if len(cams) < min_cams:
+            out.append(None)
+            continue
+        cams = sorted(cams)
+        fixed = [0 if (k == i or (strip[k] == strip[i] and i - k <= free_back)) else 1 for k in cams]
+        out.append((np.array(cams, np.int32), np.array(fixed, np.uint8)))
+    return out

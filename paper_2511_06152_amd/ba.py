@@ -25,8 +25,8 @@ BA_MAX_OBS_PER_POINT = 64
 EXPORTED = ["ba_create", "ba_destroy", "ba_submit_cluster", "ba_submit_clusters", "ba_step", "ba_solve_batch", "ba_solve", "ba_wait",
             "ba_fetch", "ba_release", "ba_footprint", "ba_profile_enable", "ba_profile_read", "ba_strerror",
             "ba_last_error", "ba_resident_poses", "ba_geo_create", "ba_geo_destroy", "ba_footprints",
-            "ba_footprint_overlaps", "ba_patch_transfer", "ba_patch_transfer_noalloc", "ba_geo_last_ms",
-            "ba_geo_last_error"]
+            "ba_footprint_overlaps", "ba_cluster_membership", "ba_patch_transfer", "ba_patch_transfer_noalloc",
+            "ba_geo_last_ms", "ba_geo_last_error"]
 # Kernel slots of ba_profile_enable / ba_profile_read.  "blocks" is the Schur
 # block launch: camera and pair tasks together in BA_MIXED, camera tasks
 # alone in BA_FP64 (whose pair tasks are "pairblk").
@@ -96,6 +96,11 @@ class ba_pinhole(ct.Structure):
                 ("height", ct.c_int32)]
 
 
+class ba_cluster_rule(ct.Structure):
+    _fields_ = [("max_back", ct.c_int32), ("free_back", ct.c_int32), ("max_cams", ct.c_int32),
+                ("min_cams", ct.c_int32), ("min_overlap", ct.c_double)]
+
+
 class ba_result(ct.Structure):
     _fields_ = [("R", ct.c_void_p), ("T", ct.c_void_p), ("X", ct.c_void_p), ("k", ct.c_void_p),
                 ("cost_log", ct.c_void_p), ("status", ct.c_int32), ("iterations", ct.c_int32),
@@ -139,6 +144,7 @@ def load(path: str = LIB_PATH):
     L.ba_geo_destroy.argtypes = [P]
     L.ba_footprints.argtypes = [P, ct.c_int32, P, P, ct.POINTER(ba_pinhole), P, P]
     L.ba_footprint_overlaps.argtypes = [P, ct.c_int32, P, P]
+    L.ba_cluster_membership.argtypes = [P, ct.c_int32, P, P, ct.POINTER(ba_cluster_rule), P, P, P]
     L.ba_patch_transfer.argtypes = [P, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(ba_pinhole),
                                     P, P, P]
     L.ba_patch_transfer_noalloc.argtypes = [P, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32, P,
@@ -390,6 +396,20 @@ class Geo:
         area = np.zeros(max(n * (n - 1) // 2, 1))
         self._chk(self.lib.ba_footprint_overlaps(self.h, n, _p(ground), _p(area)), "ba_footprint_overlaps")
         return area[: n * (n - 1) // 2]
+
+    def ba_cluster_membership(self, ground, strip, max_back=7, free_back=3, max_cams=20, min_cams=8,
+                              min_overlap=0.05):
+        """Per image i: None (no cluster) or (members ascending, fixed flags)."""
+        ground = np.ascontiguousarray(np.asarray(ground, np.float64))
+        strip = np.ascontiguousarray(np.asarray(strip, np.int32).reshape(-1))
+        n = ground.shape[0]
+        rule = ba_cluster_rule(int(max_back), int(free_back), int(max_cams), int(min_cams), float(min_overlap))
+        mem = np.full((max(n, 1), max_cams), -1, np.int32)
+        fix = np.zeros((max(n, 1), max_cams), np.uint8)
+        cnt = np.zeros(max(n, 1), np.int32)
+        self._chk(self.lib.ba_cluster_membership(self.h, n, _p(ground), _p(strip), ct.byref(rule), _p(mem), _p(fix),
+                                                 _p(cnt)), "ba_cluster_membership")
+        return [None if cnt[i] == 0 else (mem[i, :cnt[i]].copy(), fix[i, :cnt[i]].copy()) for i in range(n)]
 
     def ba_patch_transfer(self, R, T, uv0, pairs, cam: dict, want_lam: bool = False):
         """(uv [n_pairs, n_patch, 2], flags [n_pairs, n_patch], lam [n_img, n_patch] or None)."""

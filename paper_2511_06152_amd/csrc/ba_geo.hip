@@ -242,6 +242,117 @@ __global__ __launch_bounds__(kBlock) void k_overlap(int n, const double* __restr
   }
 }
 
+// Cluster membership from footprints (Sec. 3.1: overlapping images, within
+// and across strips, are found by comparing footprints; Sec. 3.2: the
+// cluster of the current image and its overlapping images).  One thread per
+// triggering image i (flight order).  Images a, b overlap when both
+// footprints exist (convex corner quadrilaterals, finite centre) and their
+// intersection covers at least min_overlap of the smaller footprint.  The
+// cluster: i; its in-strip predecessors i-1, i-2, ... (at most max_back,
+// each overlapping the image after it); the earlier images of other strips
+// overlapping i, nearest first by footprint-centre distance (ties: lower
+// index); cut at max_cams; none below min_cams.  Members leave in ascending
+// order with their fixed flag (other strips, and in-strip predecessors more
+// than free_back steps back).  The candidate list of each thread is kept
+// sorted in LDS.
+constexpr int kMemberThreads = 64;
+constexpr int kMaxMembers = 64;
+
+struct MemberRule {
+  int max_back, free_back, max_cams, min_cams;
+  double min_overlap;
+};
+
+__device__ bool quad_area(const double* __restrict__ ground, int k, double x[4], double y[4], double* a) {
+  if (!load_quad(ground, k, x, y)) return false;
+  if (!(isfinite(ground[15 * (size_t)k + 12]) && isfinite(ground[15 * (size_t)k + 13]))) return false;
+  *a = fabs(signed_area(x, y, 4));
+  return true;
+}
+
+__global__ __launch_bounds__(kMemberThreads) void k_members(int n, const double* __restrict__ ground,
+                                                            const int* __restrict__ strip, MemberRule rule,
+                                                            int* __restrict__ members, unsigned char* __restrict__ fixed,
+                                                            int* __restrict__ count) {
+  __shared__ double s_d[kMemberThreads][kMaxMembers];
+  __shared__ int s_j[kMemberThreads][kMaxMembers];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* cd = s_d[threadIdx.x];
+  int* cj = s_j[threadIdx.x];
+  const int cap = rule.max_cams;
+  int* out = members + (size_t)i * cap;
+  unsigned char* fo = fixed + (size_t)i * cap;
+  for (int t = 0; t < cap; ++t) { out[t] = -1; fo[t] = 0; }
+  double xi[4], yi[4], ai = 0.0;
+  const bool oki = quad_area(ground, i, xi, yi, &ai);
+  // in-strip predecessors, each overlapping the image after it
+  int n_own = 0;
+  {
+    double xb[4], yb[4], ab = ai;
+    bool okb = oki;
+    for (int t = 0; t < 4; ++t) { xb[t] = xi[t]; yb[t] = yi[t]; }
+    for (int j = i - 1; j >= 0 && n_own < rule.max_back && strip[j] == strip[i]; --j) {
+      double xa[4], ya[4], aa;
+      const bool oka = quad_area(ground, j, xa, ya, &aa);
+      if (!(oka && okb) || !(clip_area(xa, ya, xb, yb) >= rule.min_overlap * fmin(aa, ab))) break;
+      cj[n_own++] = j;
+      for (int t = 0; t < 4; ++t) { xb[t] = xa[t]; yb[t] = ya[t]; }
+      ab = aa;
+    }
+  }
+  // earlier images of other strips overlapping i: the nearest (d2, j) first,
+  // kept in a sorted list of at most `room` entries after the in-strip ones
+  const int room = max(0, cap - 1 - n_own);
+  int n_x = 0;
+  if (oki && room > 0) {
+    const double cxi = ground[15 * (size_t)i + 12], cyi = ground[15 * (size_t)i + 13];
+    for (int j = 0; j < i; ++j) {
+      if (strip[j] == strip[i]) continue;
+      double xa[4], ya[4], aa;
+      if (!quad_area(ground, j, xa, ya, &aa)) continue;
+      if (!(clip_area(xi, yi, xa, ya) >= rule.min_overlap * fmin(ai, aa))) continue;
+      const double dx = ground[15 * (size_t)j + 12] - cxi, dy = ground[15 * (size_t)j + 13] - cyi;
+      const double d2 = dx * dx + dy * dy;
+      // insertion into the sorted list (ascending d2, then j; j rises, so an
+      // equal d2 goes after the entries already there)
+      int pos = n_x;
+      while (pos > 0 && cd[n_own + pos - 1] > d2) --pos;
+      if (pos >= room) continue;
+      const int last = min(n_x, room - 1);
+      for (int t = last; t > pos; --t) {
+        cd[n_own + t] = cd[n_own + t - 1];
+        cj[n_own + t] = cj[n_own + t - 1];
+      }
+      cd[n_own + pos] = d2;
+      cj[n_own + pos] = j;
+      if (n_x < room) ++n_x;
+    }
+  }
+  const int total = 1 + n_own + n_x;
+  if (total < rule.min_cams) {
+    count[i] = 0;
+    return;
+  }
+  // ascending order: i is larger than every other member
+  int m = 0;
+  for (int t = 0; t < n_own + n_x; ++t) {
+    const int j = cj[t];
+    int pos = m;
+    while (pos > 0 && out[pos - 1] > j) {
+      out[pos] = out[pos - 1];
+      fo[pos] = fo[pos - 1];
+      --pos;
+    }
+    out[pos] = j;
+    fo[pos] = (strip[j] == strip[i] && i - j <= rule.free_back) ? 0 : 1;
+    ++m;
+  }
+  out[m] = i;
+  fo[m] = 0;
+  count[i] = m + 1;
+}
+
 // Eq. (3): the ground point of source patch q projected into each image the
 // source is paired with, then wrapped into the image (re-initialisation at
 // the opposite edge).  One thread per (source, patch): the ground point is
@@ -616,6 +727,37 @@ int ba_patch_transfer_noalloc(ba_geo* g, int32_t n_img, const double* R, const d
   return launch_transfer(g, to_cam(cam), n_src, n_patch, n_pairs, (const int*)sp, (const int*)(sp + o_off),
                          (const int*)(sp + o_pidx), (const int*)(sp + o_pdst), R, T, uv0, (double4*)(sp + o_gp),
                          (double2*)uv, (int*)flags);
+}
+
+int ba_cluster_membership(ba_geo* g, int32_t n, const double* ground, const int32_t* strip,
+                          const ba_cluster_rule* rule, int32_t* members, uint8_t* fixed, int32_t* count) {
+  if (!g) return BA_E_ARG;
+  if (n < 0 || n > 65536) return gfail(g, BA_E_ARG, "image count out of range (0..65536)");
+  if (!rule || rule->max_back < 0 || rule->free_back < 0 || rule->max_cams < 1 || rule->max_cams > kMaxMembers ||
+      rule->min_cams < 1 || rule->min_cams > rule->max_cams || !(rule->min_overlap >= 0.0) ||
+      !(rule->min_overlap <= 1.0))
+    return gfail(g, BA_E_ARG, "bad cluster rule (1 <= min_cams <= max_cams <= 64, 0 <= min_overlap <= 1)");
+  if (n == 0) return BA_OK;
+  if (!ground || !strip || !members || !fixed || !count) return gfail(g, BA_E_ARG, "missing array");
+  GEOCHK(g, hipSetDevice(g->device));
+  const size_t cap = (size_t)rule->max_cams;
+  void *dG, *dS, *dM, *dF, *dC;
+  int rc;
+  if ((rc = buf(g, 2, 120 * (size_t)n, &dG)) || (rc = buf(g, 13, 4 * (size_t)n, &dS)) ||
+      (rc = buf(g, 14, 4 * cap * n, &dM)) || (rc = buf(g, 15, cap * n, &dF)) || (rc = buf(g, 3, 4 * (size_t)n, &dC)))
+    return rc;
+  GEOCHK(g, hipMemcpyAsync(dG, ground, 120 * (size_t)n, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipMemcpyAsync(dS, strip, 4 * (size_t)n, hipMemcpyHostToDevice, g->stream));
+  GEOCHK(g, hipEventRecord(g->ev[0], g->stream));
+  const MemberRule r{rule->max_back, rule->free_back, rule->max_cams, rule->min_cams, rule->min_overlap};
+  hipLaunchKernelGGL(k_members, dim3((n + kMemberThreads - 1) / kMemberThreads), dim3(kMemberThreads), 0, g->stream, n,
+                     (const double*)dG, (const int*)dS, r, (int*)dM, (unsigned char*)dF, (int*)dC);
+  GEOCHK(g, hipGetLastError());
+  if ((rc = finish(g, false))) return rc;
+  GEOCHK(g, hipMemcpy(members, dM, 4 * cap * n, hipMemcpyDeviceToHost));
+  GEOCHK(g, hipMemcpy(fixed, dF, cap * n, hipMemcpyDeviceToHost));
+  GEOCHK(g, hipMemcpy(count, dC, 4 * (size_t)n, hipMemcpyDeviceToHost));
+  return BA_OK;
 }
 
 int ba_geo_last_ms(ba_geo* g, double* total_ms, double* last_ms) {

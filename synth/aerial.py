@@ -218,7 +218,9 @@ def make_scene(spec: SceneSpec, seed: int) -> dict:
         X_true, obs_cam, obs_pt, uv_true = _spawn_points_blocked(spec, rng, R_t, T_t, terrain)
     else:
         X_true, obs_cam, obs_pt, uv_true = _spawn_points(spec, rng, R_t, T_t, terrain)
-    return _finish_scene(spec, rng, R_t, T_t, strip, X_true, obs_cam, obs_pt, uv_true)
+    sc = _finish_scene(spec, rng, R_t, T_t, strip, X_true, obs_cam, obs_pt, uv_true)
+    sc["truth"]["terrain"] = {"a": terrain.a.copy(), "s": terrain.s.copy(), "c": terrain.c.copy()}
+    return sc
 
 
 def _spawn_points(spec, rng, R_t, T_t, terrain):
@@ -526,6 +528,31 @@ def _cut_cluster(fl, order, starts, cams, fixed, image):
         "sigma_px": fl["sigma_px"], "huber_delta": fl["huber_delta"],
         "cam_ids": c(cams, np.int64), "point_ids": c(pts, np.int64),
     }
+
+
+def stream_flight(seed: int = 3, n_strips: int = 4, imgs_per_strip: int = 40, pts_per_image: int = 2000,
+                  obs_mean: float = 4.8) -> dict:
+    """The serving stream's flight: n_strips x imgs_per_strip images in flight
+    order over one global tie-point pool (~pts_per_image spawned per image).
+    Returns {"flight": scene of the whole block (truth["strip"], the strip of
+    each image; truth["terrain"], its hills), "order", "starts": the
+    observations grouped by camera}."""
+    fl, order, starts = _flight(seed, n_strips, imgs_per_strip, pts_per_image, obs_mean)
+    return {"flight": fl, "order": order, "starts": starts}
+
+
+def cut_clusters(sf: dict, membership) -> list:
+    """Cluster scenes of a stream flight for a given membership: membership[i]
+    is None (image i triggers no cluster) or (cameras, fixed flags), the
+    cameras as flight indices.  Scenes as make_stream's, "image" = i."""
+    fl, order, starts = sf["flight"], sf["order"], sf["starts"]
+    out = []
+    for i, m in enumerate(membership):
+        if m is None:
+            continue
+        cams = np.asarray(m[0], np.int64)
+        out.append(_cut_cluster(fl, order, starts, cams, np.asarray(m[1], np.uint8), i))
+    return out
 
 
 def make_stream(seed: int = 3, n_strips: int = 4, imgs_per_strip: int = 40, pts_per_image: int = 2000,

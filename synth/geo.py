@@ -41,6 +41,23 @@ def make_geo_flight(seed: int = 21, n_strips: int = 4, imgs_per_strip: int = 40,
             "f": A.F_PX, "cx": A.CX, "cy": A.CY, "width": A.IMG_W, "height": A.IMG_H}
 
 
+def flight_dsm(fl: dict, cell: float = 12.0) -> dict:
+    """The DSM raster of a generated flight's own terrain (fl["truth"]
+    ["terrain"], the hills its tie points lie on), covering its cameras with
+    one footprint of margin, heights as float32."""
+    T = np.asarray(fl["truth"]["T"])
+    lo = T[:, :2].min(0) - np.array([A.FOOT_ACROSS, A.FOOT_ALONG])
+    hi = T[:, :2].max(0) + np.array([A.FOOT_ACROSS, A.FOOT_ALONG])
+    terrain = A.Terrain.__new__(A.Terrain)
+    terrain.a, terrain.s, terrain.c = (np.asarray(fl["truth"]["terrain"][k]) for k in ("a", "s", "c"))
+    nx = int(math.ceil((hi[0] - lo[0]) / cell)) + 1
+    ny = int(math.ceil((hi[1] - lo[1]) / cell)) + 1
+    gx, gy = np.meshgrid(lo[0] + cell * np.arange(nx), lo[1] + cell * np.arange(ny))
+    h = terrain.height(np.stack([gx.ravel(), gy.ravel()], 1)).reshape(ny, nx).astype(np.float32)
+    return {"nx": nx, "ny": ny, "x0": float(lo[0]), "y0": float(lo[1]), "cell": float(cell),
+            "h": np.ascontiguousarray(h)}
+
+
 def patch_grid(width: int = A.IMG_W, height: int = A.IMG_H, size: int = A.CELL_PX) -> np.ndarray:
     """Centres (u, v) of the whole size x size px cells of the image, row by
     row: 53 x 40 = 2120 patches for 8000 x 6000 px at 150 px."""

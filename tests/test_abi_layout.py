@@ -12,7 +12,7 @@ import pytest
 from paper_2511_06152_amd import ba
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STRUCTS = [ba.ba_options, ba.ba_cluster, ba.ba_result, ba.ba_dsm, ba.ba_pinhole]
+STRUCTS = [ba.ba_options, ba.ba_cluster, ba.ba_result, ba.ba_dsm, ba.ba_pinhole, ba.ba_cluster_rule]
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="no host C compiler")

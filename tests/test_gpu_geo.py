@@ -216,3 +216,81 @@ def test_flat_nominal_depth_mode():
     shift = -(g["f"] / 300.0) * (R[0].T @ (T[1] - T[0]))[:2]
     inner = fl2[0] == 0
     assert inner.any() and np.abs(uv2[0][inner] - (uv0[inner] + shift)).max() < 1e-8
+
+
+# ---- cluster membership from footprints (Sec. 3.1-3.2) -----------------------------
+
+RULE = dict(max_back=7, free_back=3, max_cams=20, min_cams=8, min_overlap=0.05)
+
+
+def same_membership(got, ref):
+    assert len(got) == len(ref)
+    for i, (a, b) in enumerate(zip(got, ref)):
+        assert (a is None) == (b is None), i
+        if a is not None:
+            assert a[0].tolist() == b[0].tolist() and a[1].tolist() == b[1].tolist(), (i, a, b)
+
+
+def test_membership_on_hand_laid_footprints():
+    """The oracle pins' rectangle flights (ties in distance, the overlap
+    threshold, a chain break, a missing footprint), the same inputs to both
+    sides: integer results equal."""
+    from test_oracle_membership import rect, strip_flight
+    cases = []
+    fp, st = strip_flight(2, 8, 16.0, 60.0)
+    cases += [(fp, st, dict(RULE, max_back=1, max_cams=6, min_cams=1)), (fp, st, dict(RULE, max_cams=64, min_cams=1))]
+    fp, st = strip_flight(3, 12, 16.0, 60.0)
+    cases += [(fp, st, RULE), (fp, st, dict(RULE, min_overlap=0.5)), (fp, st, dict(RULE, max_cams=8, min_cams=3))]
+    fp2 = fp.copy()
+    fp2[14, 2] = np.nan
+    fp2[20:, :, 1] += 300.0
+    cases.append((fp2, st, dict(RULE, min_cams=1)))
+    cases.append((np.array([rect(0, 0, 100, 80), rect(96, 0, 100, 80)]), np.array([0, 1], np.int32),
+                  dict(RULE, min_cams=1, min_overlap=0.03)))
+    g = flight(n_strips=1, imgs_per_strip=2)
+    with geo_ctx(g) as geo:
+        for k, (fp_, st_, rule) in enumerate(cases):
+            print("case membership rectangles", k, rule, flush=True)
+            same_membership(geo.ba_cluster_membership(fp_, st_, **rule), G.cluster_membership(fp_, st_, **rule))
+
+
+def test_membership_of_the_flight_from_gpu_footprints():
+    """The 160-image flight: footprints, then membership, all on the GPU,
+    against the oracle's footprints and membership.  The decisions are
+    checked for margin on the oracle's values first (no overlap within 1e-9
+    of its threshold, no two candidate distances of one image within 1e-9),
+    so that rounding cannot flip one; the results are then equal."""
+    g = flight()
+    ref_fp, _ = oracle_footprints(g)
+    n = g["n_images"]
+    area = [abs(G.polygon_area(ref_fp[k][:4, :2])) for k in range(n)]
+    ov = G.overlaps(ref_fp)
+    iu, ju = np.triu_indices(n, 1)
+    thr = RULE["min_overlap"] * np.minimum(np.take(area, iu), np.take(area, ju))
+    near = np.abs(ov - thr) <= 1e-9 * thr
+    assert not near.any()
+    ref = G.cluster_membership(ref_fp, g["strip"], **RULE)
+    for i in range(n):
+        cand = [np.hypot(*(ref_fp[j][4, :2] - ref_fp[i][4, :2])) for j in range(i) if g["strip"][j] != g["strip"][i]]
+        c = np.sort(cand)
+        assert not np.any(np.diff(c) <= 1e-9 * c[1:]) if len(c) > 1 else True
+    with geo_ctx(g) as geo:
+        fp, st = geo.ba_footprints(g["R"], g["T"], cam_of(g))
+        got = geo.ba_cluster_membership(fp, g["strip"], **RULE)
+        print("membership kernel ms", geo.ba_geo_last_ms(), flush=True)
+    sizes = [len(m[0]) for m in ref if m is not None]
+    print("clusters", len(sizes), "sizes", min(sizes), "..", max(sizes), flush=True)
+    assert len(sizes) > 100 and max(sizes) <= 20 and min(sizes) >= 8
+    same_membership(got, ref)
+
+
+def test_membership_limits():
+    from paper_2511_06152_amd import BAError
+    g = flight(n_strips=1, imgs_per_strip=3)
+    with geo_ctx(g) as geo:
+        fp, _ = geo.ba_footprints(g["R"], g["T"], cam_of(g))
+        assert geo.ba_cluster_membership(fp[:0], np.zeros(0, np.int32)) == []
+        for bad in (dict(max_cams=65), dict(max_cams=0), dict(min_cams=30), dict(min_overlap=1.5), dict(max_back=-1)):
+            with pytest.raises(BAError) as e:
+                geo.ba_cluster_membership(fp, np.zeros(3, np.int32), **dict(RULE, **bad))
+            assert e.value.code == -1

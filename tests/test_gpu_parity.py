@@ -247,14 +247,55 @@ def test_self_calibration_fp64_cost_per_iteration(name):
     assert np.abs(got["k"] - k5[:2]).max() < 1e-9
 
 
+def sigma_f(sc, state):
+    """Standard error of the estimated f at a state: sqrt((H^-1)_ff) of the
+    FP64 normal equations H = sum w J~^T J~ + sum J_pr^T J_pr over every
+    unknown (cameras, estimated intrinsics, points), from the oracle's
+    Jacobians, weights and prior Jacobians, inverted densely by numpy."""
+    J = oracle.jacobians(sc, state)
+    w = oracle.residuals(sc, state)["w"]
+    _, Jw_pr = oracle.prior(sc, state)
+    C, P, O, mask = sc["n_cams"], sc["n_points"], sc["n_obs"], int(sc["intr_mask"])
+    free = [c for c in range(C) if not sc["fixed"][c]]
+    col = {c: 6 * i for i, c in enumerate(free)}
+    m = 6 * len(free)
+    kcol = {}
+    for b in range(5):
+        if mask & (1 << b):
+            kcol[b] = m
+            m += 1
+    H = np.zeros((m + 3 * P, m + 3 * P))
+    for o in range(O):
+        c, j = int(sc["obs_cam"][o]), int(sc["obs_pt"][o])
+        idx, A = [], []
+        if c in col:
+            idx += list(range(col[c], col[c] + 6))
+            A.append(np.hstack([J["Jw"][o], J["JT"][o]]))
+        for b, kc in kcol.items():
+            idx.append(kc)
+            A.append((J["Jk"][o][:, b] if b < 2 else J["Ji"][o][:, b - 2])[:, None])
+        idx += list(range(m + 3 * j, m + 3 * j + 3))
+        A.append(J["JX"][o])
+        A = np.hstack(A) / sc["sigma_px"]
+        H[np.ix_(idx, idx)] += w[o] * A.T @ A
+    for c in free:
+        sg = np.asarray(sc["prior_sigma"][c], np.float64)
+        Jp = np.zeros((6, 6))
+        Jp[:3, :3] = Jw_pr[c]
+        Jp[3:, 3:] = np.diag(np.where(sg[3:] > 0, 1.0 / np.where(sg[3:] > 0, sg[3:], 1.0), 0.0))
+        H[col[c]:col[c] + 6, col[c]:col[c] + 6] += Jp.T @ Jp
+    return float(np.sqrt(np.linalg.inv(H)[kcol[2], kcol[2]]))
+
+
 @pytest.mark.parametrize("name", ["f_k1", "all_five"])
 def test_self_calibration_mixed_within_tolerance(name):
     """Mixed path, f and k1 (or all five intrinsics) estimated, 40
     iterations: the predicted pixels of the two final states (each with its
-    own intrinsics) within 1e-3 px RMS, centres within 1 mm, f within 1e-6
-    relative (5e-6 with all five: f, k1 and k2 trade against each other
-    along a shallow direction of the cost, so the FP32 assembly moves f
-    further while the predicted pixels stay within the same bar)."""
+    own intrinsics) within 1e-3 px RMS, centres within 1 mm, attitude within
+    2e-6 rad, and f within 1e-3 of its standard error at the oracle's
+    solution (sigma_f from the FP64 normal equations: about 58 px on these
+    scenes, so the bar is about 0.06 px, 4e-6 of f; the precision of the
+    FP32 assembly is held to a thousandth of what the data determine)."""
     sc = self_cal_scene(name)
     ref = oracle.solve(sc, max_iters=40)
     got = gpu_run(sc, 40, precision=MIXED)
@@ -265,10 +306,11 @@ def test_self_calibration_mixed_within_tolerance(name):
     dT = float(np.abs(got["T"] - ref["state"][1]).max())
     att = max(np.linalg.norm(Rotation.from_matrix(got["R"][c].T @ ref["state"][0][c]).as_rotvec())
               for c in range(sc["n_cams"]))
-    df = abs(got["intr"][0] - ref["state"][3][2]) / ref["state"][3][2]
+    df = abs(got["intr"][0] - ref["state"][3][2])
+    sf = sigma_f(sc, ref["state"])
     print(f"self-calibration mixed {name}: rms {rms:.3e} px, centres {dT:.3e} m, attitude {att:.3e} rad, "
-          f"f {df:.3e}", flush=True)
-    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6 and df < (5e-6 if name == "all_five" else 1e-6)
+          f"f {df:.3e} px (sigma_f {sf:.3g} px, ratio {df / sf:.2e})", flush=True)
+    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6 and df < 1e-3 * sf
 
 
 def test_self_calibration_in_a_shared_batch():
