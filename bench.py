@@ -240,7 +240,7 @@ def run_uneven(args, Context, precision, kw):
     # footprint: admission by HBM budget, continuous batching
     total = sum(foot[i % len(scs)] for i in range(N))
     sctx = Context(precision=precision, serve=True, max_slots=N, hbm_budget_bytes=int(0.25 * total),
-                   chunks_per_task=args.chunks_per_task)
+                   chunks_per_task=args.chunks_per_task, stage_threads=args.stage_threads)
     t0 = time.perf_counter()
     # they arrive together: one batched submit lays them out on host threads
     tickets = sctx.submit_many([scs[i % len(scs)] for i in range(N)], **kw)
@@ -301,7 +301,8 @@ def run_stream(args, Context, precision, kw):
     lat, walls = [], []
     first = []          # results of the first clusters of repetition 0, in submission order
     for rep in range(args.stream_reps):
-        ctx = Context(precision=precision, serve=True, max_slots=W + 2, hbm_budget_bytes=(W + 2) * foot + (64 << 20))
+        ctx = Context(precision=precision, serve=True, max_slots=W + 2, hbm_budget_bytes=(W + 2) * foot + (64 << 20),
+                      stage_threads=args.stage_threads)
         pending = deque()
         t0 = time.perf_counter()
 
@@ -351,7 +352,8 @@ def run_chain(args, Context, precision, kw):
     walls, lat, errs = [], [], []
     res0 = []
     for rep in range(args.chain_reps):
-        ctx = Context(precision=precision, serve=True, max_slots=4, hbm_budget_bytes=1 << 30)
+        ctx = Context(precision=precision, serve=True, max_slots=4, hbm_budget_bytes=1 << 30,
+                      stage_threads=args.stage_threads)
         t0 = time.perf_counter()
         ts = ctx.submit_many(cl, use_resident=True, fuse_resident=True, **kw)
         for t in ts:
@@ -549,6 +551,35 @@ def global_error_vs_golden(sc, r):
     return e
 
 
+def run_tiny(args, Context, precisions):
+    """The tiny workload (6 cameras in 2 strips x 3, 2000 points, ~6k
+    observations, 10 LM iterations): latency of one cluster, submit to
+    result, in each precision (the FP64 path host-driven as the plain LM,
+    the mixed path through ba_solve_batch)."""
+    sc = A.scene_tiny(1)
+    out = {"cams": sc["n_cams"], "points": sc["n_points"], "obs": sc["n_obs"], "iterations": 10}
+    for name, prec in precisions:
+        ctx = Context(precision=prec, max_slots=4, hbm_budget_bytes=64 << 20)
+        lat = []
+        for i in range(args.tiny_reps + 1):
+            t0 = time.perf_counter()
+            t = ctx.submit(sc, max_iters=10)
+            if name == "plain_fp64":
+                ctx.ba_step(t, 10)
+            else:
+                ctx.ba_solve_batch([t])
+            r = ctx.ba_fetch(t)
+            t1 = time.perf_counter()
+            ctx.ba_release(t)
+            if i:
+                lat.append((t1 - t0) * 1e3)
+        ctx.close()
+        out[name] = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "runs": len(lat),
+                     "final_rms_px": r["reproj_rms"]}
+    out["note"] = "submit (validation, layout, upload) to fetched result, one cluster at a time"
+    return out
+
+
 def run_selfcal(args, Context, ctx_kw, scenes, kw):
     """The headline batch with all five intrinsics (k1, k2, f, cx, cy)
     estimated, f submitted 0.1 % and the principal point 2 px off: the
@@ -735,6 +766,8 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="clusters solved by the plain FP64 path")
     ap.add_argument("--serve", type=int, default=64, help="clusters through the serving loop (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--stage-threads", type=int, default=8,
+                    help="host threads laying out the clusters submitted to the serving loops (0: the caller's)")
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
     ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
     ap.add_argument("--batch-streams", type=int, default=2,
@@ -772,6 +805,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="host threads of the multi-threaded oracle timing (0: the cores this process may "
                          "use, at most 16)")
+    ap.add_argument("--tiny-reps", type=int, default=20,
+                    help="timed single-cluster runs of the tiny workload in each precision (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -896,21 +931,24 @@ def main():
                "note": "timed steps: launches of one part of the batch, beside the other parts' kernels"}
 
     # ---- plain FP64 GPU LM: one cluster at a time, host-driven ---------------------------
-    plain_lat, plain_final = [], {}
+    plain_lat, plain_e2e, plain_final = [], [], {}
     if args.plain > 0:
         pctx = Context(precision=BA_FP64, max_slots=4, hbm_budget_bytes=256 << 20)
         for i in range(args.plain + 1):
             j = i % len(scenes)
+            ts = time.perf_counter()
             t = pctx.submit(scenes[j], **kw)
             pctx.ba_step(t, 0)
             t0 = time.perf_counter()
             pctx.ba_step(t, args.max_iters)
             t1 = time.perf_counter()
             r = pctx.ba_fetch(t)
+            t2 = time.perf_counter()
             pctx.ba_release(t)
             if i == 0:
                 continue  # warmup
             plain_lat.append((t1 - t0) * 1e3)
+            plain_e2e.append((t2 - ts) * 1e3)
             plain_final.setdefault(j, r)
         pctx.close()
     plain_cps = 1e3 / float(np.mean(plain_lat)) if plain_lat else float("nan")
@@ -934,7 +972,7 @@ def main():
     serve = {}
     if args.serve > 0:
         sctx = Context(precision=BA_MIXED, serve=True, max_slots=args.serve_slots,
-                       hbm_budget_bytes=int(args.serve_slots * 16e6) + (256 << 20))
+                       hbm_budget_bytes=int(args.serve_slots * 16e6) + (256 << 20), stage_threads=args.stage_threads)
         inflight, lat, done = [], [], 0
         nxt = 0
         t_start = time.perf_counter()
@@ -952,8 +990,9 @@ def main():
             done += 1
         wall = time.perf_counter() - t_start
         sctx.close()
-        serve = {"clusters": done, "slots": args.serve_slots, "clusters_per_s": done / wall,
-                 "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)}
+        serve = {"clusters": done, "slots": args.serve_slots, "stage_threads": args.stage_threads,
+                 "clusters_per_s": done / wall, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                 "note": "closed loop, latency from ba_submit_cluster to the result (layout included)"}
 
     # ---- equal-RMS check -------------------------------------------------------------------
     rms = {}
@@ -974,6 +1013,9 @@ def main():
         rms["clusters_compared"] = len(common)
         rms["note"] = ("reprojection RMS of each path from ba_fetch (device FP64); the prediction difference "
                        "is the RMS over all observations of |p_mixed - p_plain|")
+
+    # ---- the tiny workload: one cluster's latency, submit to result ---------------------------
+    tiny = run_tiny(args, Context, [("plain_fp64", BA_FP64), ("mixed", BA_MIXED)]) if args.tiny_reps > 0 else None
 
     # ---- uneven batched clusters: 6-24 cameras, 5k-60k points, one batch --------------------
     uneven = run_uneven(args, Context, BA_MIXED, kw) if args.uneven > 0 else None
@@ -1032,7 +1074,11 @@ def main():
         "latency_ms": {"one_cluster_mixed_p50": pct(one_lat, 50), "one_cluster_mixed_p99": pct(one_lat, 99),
                        "serving": serve},
         "plain_fp64": {"clusters_per_s": plain_cps, "p50_ms": pct(plain_lat, 50), "p99_ms": pct(plain_lat, 99),
-                       "clusters": len(plain_lat)},
+                       "clusters": len(plain_lat),
+                       "submit_to_result_p50_ms": pct(plain_e2e, 50), "submit_to_result_p99_ms": pct(plain_e2e, 99),
+                       "note": "p50/p99: the LM iterations of an admitted cluster; submit_to_result: from "
+                               "ba_submit_cluster (validation, layout, upload, admission) to the fetched result, "
+                               "as the serving latencies"},
         "speedup_vs_plain_fp64": value / plain_cps if plain_lat else None,
         "rms": rms,
         "kernels": kernels,
@@ -1047,6 +1093,7 @@ def main():
         "final_error_vs_oracle": final_err,
         "batched_fp64": batched_fp64,
         "speedup_vs_batched_fp64": value / batched_fp64["clusters_per_s"] if batched_fp64 else None,
+        "tiny": tiny,
         "batched_uneven": uneven,
         "serving_stream": stream,
         "self_calibration": selfcal,

@@ -134,6 +134,18 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user);
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
+  /* Layout threads.  0: ba_submit_cluster(s) validate and lay a cluster out
+   * on the calling thread and report every invalid input at once.  n (1..64):
+   * a pool of n host threads lays submitted clusters out in the background,
+   * so that the caller and the serving loop are not held up by it;
+   * ba_submit_cluster(s) then check only what needs no layout (sizes, arrays
+   * present, resident IDs unique; BA_E_ARG), copy the cluster and return.  A
+   * cluster the pool refuses (the remaining checks of ba_submit_cluster, or
+   * a footprint larger than the arena) is dropped from the queue and
+   * reported by ba_wait, ba_step, ba_solve_batch and ba_fetch on its ticket
+   * (BA_E_ARG / BA_E_NOMEM with the message).  ba_step and ba_solve_batch
+   * wait for their clusters' layout.  Negative or above 64: BA_E_ARG. */
+  int32_t stage_threads;
 } ba_options;
 
 /* One cluster (ba_submit_cluster).  C = n_cams, P = n_points, O = n_obs. */

@@ -45,7 +45,7 @@ class ba_options(ct.Structure):
                 ("chunks_per_task", ct.c_int32), ("solver", ct.c_int32), ("pcg_max_iters", ct.c_int32),
                 ("pcg_tol", ct.c_double), ("resident_cams", ct.c_int32), ("resident_points", ct.c_int32),
                 ("batch_streams", ct.c_int32), ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE),
-                ("alloc_user", ct.c_void_p)]
+                ("alloc_user", ct.c_void_p), ("stage_threads", ct.c_int32)]
 
 
 class TorchAllocator:
@@ -210,12 +210,13 @@ class Context:
                  max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
                  chunks_per_wg: int = 16, chunks_per_task: int = 4, solver: int = BA_SOLVER_AUTO,
                  pcg_max_iters: int = 500, pcg_tol: float = 0.1, resident_cams: int = 0,
-                 resident_points: int = 0, batch_streams: int = 0, allocator=None):
+                 resident_points: int = 0, batch_streams: int = 0, allocator=None, stage_threads: int = 0):
         """allocator: None (hipMalloc) or "torch" (PyTorch's caching allocator)."""
         self.lib = load()
         opt = ba_options(device, stream, hbm_budget_bytes, max_slots, max_queue, precision, 1 if serve else 0,
                          iters_per_tick, chunks_per_wg, chunks_per_task, solver, pcg_max_iters, pcg_tol,
                          resident_cams, resident_points, batch_streams)
+        opt.stage_threads = int(stage_threads)
         self.allocator = None
         if allocator == "torch":
             self.allocator = TorchAllocator(device)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libba.so")
-SOURCES = ["ba_kernels.hip", "ba_runtime.cpp", "ba_geo.hip"]
+SOURCES = ["ba_kernels.hip", "ba_runtime.cpp", "ba_stage.cpp", "ba_geo.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

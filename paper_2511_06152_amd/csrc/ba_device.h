@@ -6,34 +6,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ba_consts.h"
+
 namespace bagpu {
 
-constexpr int kWave = 64;                 // CDNA wavefront
-constexpr int kWG = 256;                  // threads per workgroup of the chunk kernels
-constexpr int kWavesPerWG = kWG / kWave;
-constexpr int kMaxFreeCams = 24;          // reduced system m <= 6*24 + 5 = 149
-constexpr int kMaxCams = 512;             // camera table kept in LDS by the point-lane kernels
-constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
-constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
-constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
-constexpr int kPtVals = 16;               // per point: Q (6 packed symmetric), g (3), Z (6), pad (1)
-constexpr int kTaskVals = 72;             // per block task partial: camera task 51 values (69 when
-                                          // self-calibrating), pair task 36
-constexpr int kPtPartVals = 32;           // per point-pass wavefront: intrinsic-intrinsic terms (9, or 30
-                                          // when self-calibrating)
-constexpr int kPtzVals = 12;              // per point when self-calibrating: Z rows of f, cx, cy (9), pad (3)
-constexpr int kStatVals = 6;              // reprojection sums of one point-lane workgroup: observations,
-                                          // sum |e|, sum |e|^2, and the same over the inliers (|e| <= 3 delta)
-constexpr int kIntr = 5;                  // intrinsic state: k1, k2, f, principal-point offset x, y
-constexpr int kSolveTb = 16;              // block size of the dense reduced-system factorisation
-constexpr int kSolveTbVals = kSolveTb * (kSolveTb + 1);   // doubles per block (rows padded to 17)
-constexpr int kSbRow = 8;                 // sparse reduced-system block: 6 rows padded to 8 values
-constexpr int kSbVals = 6 * kSbRow;       //   (16-byte aligned rows for vector loads)
-// Work items of the block-assembly kernel (one wavefront each) and of its
-// reduction: int4 {kind << 24 | cam_a << 12 | cam_b, begin, end/count, 0}.
-enum TaskKind { TASK_CAM = 0, TASK_PAIR = 1, TARGET_INTR = 2 };
-
-enum SlotStatus { ST_QUEUED = 0, ST_RUNNING = 1, ST_MAXITER = 2, ST_CONVERGED = 3, ST_STALLED = 4, ST_BAD_INIT = 5 };
 
 // Read-only description of one resident cluster; written once at admission.
 struct SlotDesc {
@@ -91,7 +67,11 @@ struct SlotDesc {
   const int2* tslot;                      // [n_targets] block slots of a target: (a,b) and (b,a)
   double* Sblk;                           // [nnzb][6][kSbRow] FP64 blocks, row-major, rows padded
   float* Sblk32;                          // [nnzb][6][kSbRow] FP32 copy for the mixed-precision products
-  double* pcgw;                           // [2m] PCG work: gradient with priors, clamped diagonal
+  double* pcgw;                           // [5m + 8 kMaxCgWG] PCG work: gradient with priors, clamped
+                                          //   diagonal, z, p (two buffers), workgroup parts of the sums
+  const int* pcg_part;                    // [pcg_G + 1] first block row of each PCG workgroup
+  int pcg_G, pcg_rows_max;                // PCG workgroups; most block rows of one of them
+  int pcg_smem, pad3;                     // dynamic LDS bytes of the PCG launch
   // resident state keyed by global IDs (shared by the context's clusters)
   int n_rin_cam, n_rin_pt, n_rout_cam, n_rout_pt;
   double* res_cam;                        // [cap][12] world frame: R row-major (9), T (3)
@@ -140,6 +120,12 @@ struct Batch {
   int any_sparse, any_dense, any_sc, pad;   // any_sc: a self-calibrating cluster in the batch
 };
 
+// A cluster solved by conjugate gradients: its slot, workgroups and LDS bytes
+// (one cooperative launch each).
+struct SparseLaunch {
+  int slot, G, smem;
+};
+
 // max_rin: largest resident gather list of the batch (0: none).
 hipError_t launch_prep(const Batch& b, int max_P_L, int max_rin, hipStream_t st);
 hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
@@ -147,7 +133,11 @@ hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
 // of the iteration (point, camera blocks, pair blocks, reduce, dense solve,
 // back-substitution, LM, PCG solve), recorded by the dispatches themselves
 // for the kernels whose bit is set in `timed`.
-hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr, int timed = 0);
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr, int timed = 0,
+                            const SparseLaunch* sp = nullptr, int n_sp = 0);
+// Dynamic LDS bytes of the conjugate-gradient launch of a cluster: its
+// workgroups' largest block range (bytes), m and F.
+size_t pcg_lds_bytes(size_t block_bytes, int m, int F, int rows_max);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 // Writes the exported state of the batch's clusters back to the resident
 // store (after launch_export); max_rout: largest write-back list.

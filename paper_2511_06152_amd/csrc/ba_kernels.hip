@@ -32,6 +32,7 @@
 // cluster's result is the same alone or inside any batch.  Real is double
 // (plain path) or float (mixed path: FP32 residuals, Jacobians and Schur
 // accumulation; FP64 reduction, solve, cost and gain ratio).
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
 #include <math.h>
 
@@ -1759,94 +1760,55 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
 // For large reduced systems (a whole-flight adjustment: hundreds of cameras),
 // the Schur complement is kept as 6x6 blocks of the co-visible camera pairs
 // (block CSR, both orientations) and solved by conjugate gradients with the
-// inverse diagonal blocks as block-Jacobi preconditioner.  One workgroup of
-// 1024 threads per cluster.  Thread f owns block row f: its six entries of x
-// and r stay in registers and it applies its block of the preconditioner
-// (inverse Cholesky factor in LDS).  The direction p and the product S p live
-// in LDS; each thread computes whole rows of the product, several blocks at a
-// time.  In mixed mode the products are FP32 (FP32 copy of the blocks, FP32
-// accumulation); dot products, the preconditioner and the updates are FP64.
-// Every reduction has a fixed order.
+// inverse diagonal blocks as block-Jacobi preconditioner.  One cooperative
+// launch per such cluster: G workgroups, each owning a contiguous range of
+// block rows, whose blocks it copies into LDS once and keeps there for the
+// whole solve (in mixed mode the FP32 copy: FP32 products and accumulation;
+// dot products, the preconditioner and the updates are FP64).  Thread t of a
+// workgroup owns block row r0 + t (x, r in registers, its preconditioner
+// block in LDS).  Each CG step has two grid barriers:
+//   A: every workgroup has rebuilt the whole direction p = z + beta p_prev
+//      (from z and the previous p in global memory: each workgroup computes
+//      all of it the same way), multiplied its rows, and posted its part of
+//      p.Ap;
+//   B: every workgroup has updated its rows of x, r, z and posted its parts
+//      of r.r and r.z.
+// Every workgroup adds the G parts in workgroup order, so all of them take
+// the same decisions; sums inside a workgroup have a fixed order too.
 
-constexpr int kPcgThreads = 1024;
-constexpr int kPcgWaves = kPcgThreads / kWave;
+namespace cg = cooperative_groups;
+
+// entries of the direction each thread rebuilds: m <= 6 * kMaxCams
+constexpr int kCgPerThread = (6 * kMaxCams + kCgThreads - 1) / kCgThreads;
 
 // Sums over the workgroup in a fixed order (two values at once).
-__device__ __forceinline__ double2 block_sum2(double a, double b, double* red, int tid) {
+__device__ __forceinline__ double2 wg_sum2(double a, double b, double* red, int tid) {
   a = wave_sum(a);
   b = wave_sum(b);
   __syncthreads();
   if ((tid % kWave) == 0) {
     red[tid / kWave] = a;
-    red[kPcgWaves + tid / kWave] = b;
+    red[kCgWaves + tid / kWave] = b;
   }
   __syncthreads();
   double2 t = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int w = 0; w < kPcgWaves; ++w) {
+  for (int w = 0; w < kCgWaves; ++w) {
     t.x += red[w];
-    t.y += red[kPcgWaves + w];
+    t.y += red[kCgWaves + w];
   }
   return t;
 }
 
-// Rows of S p owned by one thread (q = tid, tid + 1024, ...); returns this
-// thread's part of p.Ap.  Row q = 6 bi + r reads row r of every block of
-// block row bi (16-byte vector loads of the padded row), NB blocks at a time
-// so that their loads are in flight together; out-of-range slots of a batch
-// re-read the row's first block and are multiplied by zero.  p is read from
-// LDS in the product's precision: FP32 copy [F][8] (mixed) or FP64 [m].
-__device__ __forceinline__ void row_load(const float* __restrict__ row, float v[6], const float* pp, float w[6]) {
-  const float4 a = *reinterpret_cast<const float4*>(row);
-  const float2 b = *reinterpret_cast<const float2*>(row + 4);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
-  const float4 c = *reinterpret_cast<const float4*>(pp);
-  const float2 e = *reinterpret_cast<const float2*>(pp + 4);
-  w[0] = c.x; w[1] = c.y; w[2] = c.z; w[3] = c.w; w[4] = e.x; w[5] = e.y;
-}
-__device__ __forceinline__ void row_load(const double* __restrict__ row, double v[6], const double* pp, double w[6]) {
-#pragma unroll
-  for (int h = 0; h < 3; ++h) {
-    const double2 a = *reinterpret_cast<const double2*>(row + 2 * h);
-    v[2 * h] = a.x;
-    v[2 * h + 1] = a.y;
-    const double2 c = *reinterpret_cast<const double2*>(pp + 2 * h);
-    w[2 * h] = c.x;
-    w[2 * h + 1] = c.y;
+// Parts of the G workgroups, added in workgroup order (every thread the same sums).
+__device__ __forceinline__ double2 grid_sum2(const double2* __restrict__ parts, int G) {
+  double2 t = make_double2(0.0, 0.0);
+  for (int w = 0; w < G; ++w) {
+    const double2 v = parts[w];
+    t.x += v.x;
+    t.y += v.y;
   }
-}
-
-template <typename B, int NB, int PS>
-__device__ __forceinline__ double pcg_spmv(const B* __restrict__ blk, const int* __restrict__ brow,
-                                           const int* __restrict__ bcol, const B* pB, const double* p, double* Ap,
-                                           int m, int tid) {
-  double pap = 0.0;
-  for (int q = tid; q < m; q += kPcgThreads) {
-    const int bi = q / 6, r = q % 6;
-    const int k0 = brow[bi], k1 = brow[bi + 1];
-    B acc = B(0);
-    for (int kb = k0; kb < k1; kb += NB) {
-      int cj[NB];
-#pragma unroll
-      for (int u = 0; u < NB; ++u) cj[u] = bcol[kb + u < k1 ? kb + u : k0];
-      B v[NB][6], w[NB][6];
-#pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        const int k = kb + u < k1 ? kb + u : k0;
-        row_load(blk + kSbVals * (size_t)k + kSbRow * r, v[u], pB + PS * cj[u], w[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        const B z = kb + u < k1 ? B(1) : B(0);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc = fm(v[u][c] * z, w[u][c], acc);
-      }
-    }
-    const double a = (double)acc;
-    Ap[q] = a;
-    pap = fm(a, p[q], pap);
-  }
-  return pap;
+  return t;
 }
 
 // z = Li^T Li r for one 6x6 block (Li: packed lower triangle, row-major).
@@ -1868,38 +1830,79 @@ __device__ __forceinline__ void pcg_precond(const double* Li, const double r[6],
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
-  extern __shared__ __attribute__((aligned(16))) double sv[];   // 16-byte vector reads of p
-  __shared__ int own_cam[kMaxCams];
-  __shared__ int ok;
-  const int s = bt.act[blockIdx.x];
+// Rows q of this workgroup's S p (q local: block row q / 6, row q % 6 of
+// it), blocks and p from LDS; returns this thread's part of p.Ap.  p is read
+// in the product's precision: FP32 copy [F][8] (mixed) or FP64 [m].
+template <typename B, int PS>
+__device__ __forceinline__ double cg_spmv(const B* __restrict__ Sl, const int* __restrict__ brow,
+                                          const int* __restrict__ bcol, int r0, int nr, int k0, const B* pB,
+                                          const double* pl, double* Apl, int tid) {
+  double pap = 0.0;
+  for (int q = tid; q < 6 * nr; q += kCgThreads) {
+    const int bl = q / 6, r = q % 6;
+    const int ka = brow[r0 + bl], kb = brow[r0 + bl + 1];
+    B acc = B(0);
+    for (int k = ka; k < kb; ++k) {
+      const B* row = Sl + kSbVals * (size_t)(k - k0) + kSbRow * r;
+      const B* pp = pB + PS * bcol[k];
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc) acc = fm(row[cc], pp[cc], acc);
+    }
+    const double a = (double)acc;
+    Apl[q] = a;
+    pap = fm(a, pl[6 * r0 + q], pap);
+  }
+  return pap;
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
+  extern __shared__ __attribute__((aligned(16))) double sv[];
+  __shared__ double red[2 * kCgWaves];
+  __shared__ int own_cam[kCgThreads];
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
+  // read by every workgroup before anything is written: the same decision everywhere
   if (c.status != ST_RUNNING || !d.sparse) return;
-  const int tid = threadIdx.x;
+  cg::grid_group grid = cg::this_grid();
+  const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
   const int F = d.n_free, m = d.m;
-  double* pv = sv;               // [m] search direction
-  double* Ap = pv + m;           // [m] S p; the solution at the end
-  double* Lf = Ap + m;           // [F][21] inverse Cholesky factors of the damped diagonal blocks
-  double* red = Lf + 21 * F;     // [2 * kPcgWaves]
-  // [F][8] FP32 copy of p (mixed), 16-byte aligned
-  float* p32 = reinterpret_cast<float*>(sv + ((2 * m + 21 * F + 2 * kPcgWaves + 1) & ~1));
-  double* gv = d.pcgw;           // [m] gradient of the camera side (with priors)
-  double* Dv = gv + m;           // [m] clamped diagonal
+  const int r0 = d.pcg_part[wg], r1 = d.pcg_part[wg + 1], nr = r1 - r0;
+  const int* const brow = d.brow;
+  const int* const bcol = d.bcol;
+  const int k0 = brow[r0], nblk = brow[r1] - k0;
+  const bool mixed = d.mixed != 0;
+  // global work: gradient with priors, clamped diagonal, z, p (two buffers),
+  // the workgroups' parts of the sums, FP32 copy of p
+  double* gv = d.pcgw;
+  double* Dv = gv + m;
+  double* zg = Dv + m;
+  double* pg = zg + m;
+  double2* part = reinterpret_cast<double2*>(pg + 2 * m);    // [4][kMaxCgWG]
+  // LDS: this workgroup's blocks, the whole p (FP64, and FP32 in mixed mode),
+  // its rows of S p, its preconditioner blocks
+  const size_t sbytes = (mixed ? sizeof(float) : sizeof(double)) * kSbVals * (size_t)nblk;
+  double* pl = sv + (sbytes + 7) / 8;
+  float* p32l = reinterpret_cast<float*>(pl + m);
+  double* Apl = pl + m + 4 * F;
+  double* Lf = Apl + 6 * d.pcg_rows_max;
+  const float* S32l = reinterpret_cast<const float*>(sv);
+  const double* S64l = sv;
   const double lambda = c.lambda;
   const int cur = c.cur;
-  if (tid == 0) ok = (c.point_fail == 0);
-  for (int k = tid; k < d.C; k += kPcgThreads) {
+  for (int k = tid; k < nr; k += kCgThreads) own_cam[k] = -1;
+  __syncthreads();
+  for (int k = tid; k < d.C; k += kCgThreads) {
     const int col = d.cam_col[k];
-    if (col >= 0) own_cam[col / 6] = k;
+    if (col >= 0 && col / 6 >= r0 && col / 6 < r1) own_cam[col / 6 - r0] = k;
   }
   __syncthreads();
-  // Owner set-up: priors, damping, preconditioner, right-hand side.
-  const bool own = tid < F;
+  // Owner set-up: priors and damping into the diagonal block, preconditioner,
+  // right-hand side, z = M^-1 r = p_0.
+  const bool own = tid < nr;
   double xr[6], rr[6];
-  double part_rr = 0.0, part_rz = 0.0;
+  double part_rr = 0.0, part_rz = 0.0, fails = 0.0;
   if (own) {
-    const int f = tid, k = own_cam[f], col = 6 * f;
+    const int f = r0 + tid, k = own_cam[tid], col = 6 * f;
     double g[6], Dg[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
@@ -1907,7 +1910,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
       rr[a] = d.Sg[m + col + a];      // bS for now
       Dg[a] = d.Sg[2 * m + col + a];  // diag U for now
     }
-    double* Ab = d.Sblk + kSbVals * (size_t)d.brow[f];
+    double* Ab = d.Sblk + kSbVals * (size_t)brow[f];
     double blkv[36];
 #pragma unroll
     for (int i = 0; i < 36; ++i) blkv[i] = Ab[kSbRow * (i / 6) + i % 6];
@@ -1937,15 +1940,15 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
       rr[a] = -g[a] + rr[a];
       xr[a] = 0.0;
     }
-    float* A32 = d.Sblk32 + kSbVals * (size_t)d.brow[f];
+    float* A32 = d.Sblk32 + kSbVals * (size_t)brow[f];
 #pragma unroll
     for (int i = 0; i < 36; ++i) {
       Ab[kSbRow * (i / 6) + i % 6] = blkv[i];
       A32[kSbRow * (i / 6) + i % 6] = (float)blkv[i];
     }
     double li[36];
-    if (!chol6_inv(blkv, li)) ok = 0;
-    double* L = Lf + 21 * f;
+    if (!chol6_inv(blkv, li)) fails = 1.0;
+    double* L = Lf + 21 * tid;
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -1954,25 +1957,40 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
     pcg_precond(L, rr, z);
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      pv[col + a] = z[a];
-      p32[kSbRow * f + a] = (float)z[a];
+      zg[col + a] = z[a];
+      pg[col + a] = z[a];
       part_rr = fm(rr[a], rr[a], part_rr);
       part_rz = fm(rr[a], z[a], part_rz);
     }
   }
-  const double2 s0 = block_sum2(part_rr, part_rz, red, tid);
-  if (!ok) {
-    if (tid == 0) c.solve_ok = 0;
+  // this workgroup's blocks into LDS (their diagonal blocks as just damped)
+  __syncthreads();
+  if (mixed) {
+    const float4* src = reinterpret_cast<const float4*>(d.Sblk32 + kSbVals * (size_t)k0);
+    float4* dst = reinterpret_cast<float4*>(sv);
+    for (int i = tid; i < nblk * kSbVals / 4; i += kCgThreads) dst[i] = src[i];
+  } else {
+    const double2* src = reinterpret_cast<const double2*>(d.Sblk + kSbVals * (size_t)k0);
+    double2* dst = reinterpret_cast<double2*>(sv);
+    for (int i = tid; i < nblk * kSbVals / 2; i += kCgThreads) dst[i] = src[i];
+  }
+  {
+    const double2 t = wg_sum2(part_rr, part_rz, red, tid);
+    const double fl = wg_sum2(fails, 0.0, red, tid).x;
+    if (tid == 0) {
+      part[wg] = t;
+      part[kMaxCgWG + wg] = make_double2(fl, 0.0);
+    }
+  }
+  grid.sync();
+  const double2 s0 = grid_sum2(part, G);
+  const double nfail = grid_sum2(part + kMaxCgWG, G).x;
+  if (nfail > 0.0 || c.point_fail) {
+    if (wg == 0 && tid == 0) c.solve_ok = 0;
     return;
   }
   const double bnorm = sqrt(s0.x);
-  double rz = s0.y;
-  const bool mixed = d.mixed != 0;
-  // loop invariants in registers (the barriers would otherwise reload them)
-  const int* const brow = d.brow;
-  const int* const bcol = d.bcol;
-  const float* const S32 = d.Sblk32;
-  const double* const S64 = d.Sblk;
+  double rz = s0.y, beta = 0.0;
   const int max_it = d.pcg_max_iters;
   // Forcing term of the inexact step: |r| <= eta |b| with
   // eta = min(pcg_tol, sqrt(|b| / |b_0|)), |b_0| the first solve's right-hand
@@ -1983,93 +2001,120 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(Batch bt) {
   bool good = true;
   int it = 0;
   for (; it < max_it && bnorm > 0.0;) {
-    const double pap_part = mixed ? pcg_spmv<float, 8, kSbRow>(S32, brow, bcol, p32, pv, Ap, m, tid)
-                                  : pcg_spmv<double, 4, 6>(S64, brow, bcol, pv, pv, Ap, m, tid);
-    const double pAp = block_sum2(pap_part, 0.0, red, tid).x;
+    // the whole direction p_it = z + beta p_(it-1) (p_0 = z), the same in every
+    // workgroup; all of a thread's loads are issued before any store (the
+    // stores could alias them as far as the compiler knows)
+    const double* pprev = pg + (size_t)((it + 1) & 1) * m;
+    double* pnew = pg + (size_t)(it & 1) * m;
+    {
+      double zv[kCgPerThread], pv[kCgPerThread];
+#pragma unroll
+      for (int u = 0; u < kCgPerThread; ++u) {
+        const int q = tid + u * kCgThreads;
+        zv[u] = q < m ? zg[q] : 0.0;
+        pv[u] = (q < m && it > 0) ? pprev[q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCgPerThread; ++u) {
+        const int q = tid + u * kCgThreads;
+        if (q < m) {
+          const double v = it == 0 ? zv[u] : fm(beta, pv[u], zv[u]);
+          pl[q] = v;
+          if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
+          if (it > 0 && q / 6 >= r0 && q / 6 < r1) pnew[q] = v;
+        }
+      }
+    }
+    __syncthreads();
+    const double pap_part = mixed ? cg_spmv<float, kSbRow>(S32l, brow, bcol, r0, nr, k0, p32l, pl, Apl, tid)
+                                  : cg_spmv<double, 6>(S64l, brow, bcol, r0, nr, k0, pl, pl, Apl, tid);
+    {
+      const double t = wg_sum2(pap_part, 0.0, red, tid).x;
+      if (tid == 0) part[2 * kMaxCgWG + wg] = make_double2(t, 0.0);
+    }
+    grid.sync();
+    const double pAp = grid_sum2(part + 2 * kMaxCgWG, G).x;
     ++it;
     if (!(pAp > 0.0) || !isfinite(pAp)) {
       good = false;
       break;
     }
     const double alpha = rz / pAp;
-    double z[6];
     part_rr = part_rz = 0.0;
     if (own) {
-      const int col = 6 * tid;
+      const int col = 6 * (r0 + tid);
+      double z[6];
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
-        xr[a] = fm(alpha, pv[col + a], xr[a]);
-        rr[a] = fm(-alpha, Ap[col + a], rr[a]);
+        xr[a] = fm(alpha, pl[col + a], xr[a]);
+        rr[a] = fm(-alpha, Apl[6 * tid + a], rr[a]);
       }
       pcg_precond(Lf + 21 * tid, rr, z);
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
+        zg[col + a] = z[a];
         part_rr = fm(rr[a], rr[a], part_rr);
         part_rz = fm(rr[a], z[a], part_rz);
       }
     }
-    const double2 s1 = block_sum2(part_rr, part_rz, red, tid);
-    if (sqrt(s1.x) <= tol * bnorm) break;
-    const double beta = s1.y / rz;
-    rz = s1.y;
-    if (own) {
-      const int col = 6 * tid;
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const double pn = fm(beta, pv[col + a], z[a]);
-        pv[col + a] = pn;
-        p32[kSbRow * tid + a] = (float)pn;
-      }
+    {
+      const double2 t = wg_sum2(part_rr, part_rz, red, tid);
+      if (tid == 0) part[3 * kMaxCgWG + wg] = t;
     }
-    __syncthreads();
+    grid.sync();
+    const double2 s1 = grid_sum2(part + 3 * kMaxCgWG, G);
+    if (sqrt(s1.x) <= tol * bnorm) break;
+    beta = s1.y / rz;
+    rz = s1.y;
   }
   if (!good) {
-    if (tid == 0) c.solve_ok = 0;
+    if (wg == 0 && tid == 0) c.solve_ok = 0;
     return;
   }
-  // Solution to LDS (over S p), predicted camera-side reduction.
-  double part_pred = 0.0;
-  __syncthreads();
+  // Solution, predicted camera-side reduction, trial cameras and their prior
+  // cost: owners for their cameras, workgroup 0 copies the fixed ones.
+  double part_pred = 0.0, pc = 0.0;
+  const int nxt = 1 - cur;
   if (own) {
-    const int col = 6 * tid;
+    const int col = 6 * (r0 + tid), k = own_cam[tid];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      Ap[col + a] = xr[a];
       d.dc[col + a] = xr[a];
       part_pred += xr[a] * (lambda * Dv[col + a] * xr[a] - gv[col + a]);
     }
-  }
-  const double predc = block_sum2(part_pred, 0.0, red, tid).x;
-  const double* x = Ap;
-  const int nxt = 1 - cur;
-  double pc = 0.0;
-  for (int k = tid; k < d.C; k += kPcgThreads) {
     const double* cm = d.cam[cur] + kCamVals * k;
     double* cn = d.cam[nxt] + kCamVals * k;
-    const int col = d.cam_col[k];
-    if (col < 0) {
-      for (int i = 0; i < kCamVals; ++i) cn[i] = cm[i];
-      continue;
-    }
-    const double wv[3] = {x[col], x[col + 1], x[col + 2]};
     double E[9];
-    so3_exp(wv, E);
+    so3_exp(xr, E);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) cn[3 * i + j] = cm[3 * i] * E[j] + cm[3 * i + 1] * E[3 + j] + cm[3 * i + 2] * E[6 + j];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + x[col + 3 + i];
+    for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + xr[3 + i];
     double e[6], J[9];
     prior_terms(cn, d.prior + kPriorVals * k, e, J);
 #pragma unroll
     for (int i = 0; i < 6; ++i) pc += e[i] * e[i];
   }
-  pc = block_sum2(pc, 0.0, red, tid).x;
-  if (tid == 0) {
-    c.pred_c = predc;
-    c.E_prior_trial = 0.5 * pc;
-    for (int t = 0; t < 5; ++t) c.k[nxt][t] = c.k[cur][t];
+  if (wg == 0) {
+    for (int k = tid; k < d.C; k += kCgThreads) {
+      if (d.cam_col[k] >= 0) continue;
+      const double* cm = d.cam[cur] + kCamVals * k;
+      double* cn = d.cam[nxt] + kCamVals * k;
+      for (int i = 0; i < kCamVals; ++i) cn[i] = cm[i];
+    }
+  }
+  {
+    const double2 t = wg_sum2(part_pred, pc, red, tid);
+    if (tid == 0) part[wg] = t;
+  }
+  grid.sync();
+  if (wg == 0 && tid == 0) {
+    const double2 t = grid_sum2(part, G);
+    c.pred_c = t.x;
+    c.E_prior_trial = 0.5 * t.y;
+    for (int q = 0; q < 5; ++q) c.k[nxt][q] = c.k[cur][q];
     c.cg_iters += it;
     if (!(c.cg_b0 > 0.0)) c.cg_b0 = bnorm;
   }
@@ -2388,10 +2433,6 @@ size_t backsub_smem(const Batch& b) {
          sizeof(int) * (size_t)b.max_C;
 }
 
-size_t pcg_smem(const Batch& b) {
-  const size_t m = (size_t)b.max_m;
-  return sizeof(double) * (2 * m + 21 * ((m + 5) / 6) + 2 * kPcgWaves + 1) + sizeof(float) * kSbRow * ((m + 5) / 6);
-}
 
 size_t solve_smem(const Batch& b) {
   const size_t nb = (size_t)b.max_nb, blk = nb * (nb + 1) / 2 * kTbV;
@@ -2447,7 +2488,12 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, hipEve
   else hipLaunchKernelGGL(kernel, grid, block, smem, st, b);
 }
 
-hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev_all, int timed) {
+size_t pcg_lds_bytes(size_t block_bytes, int m, int F, int rows_max) {
+  return (block_bytes + 7) / 8 * 8 + sizeof(double) * ((size_t)m + 4 * (size_t)F + 27 * (size_t)rows_max);
+}
+
+hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev_all, int timed,
+                            const SparseLaunch* spl, int n_sp) {
   if (b.n_act == 0) return hipSuccess;
   hipError_t e;
   const size_t s_solve = solve_smem(b);
@@ -2464,8 +2510,6 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
       if ((i & 1) == 0 || b.any_sc)
         if ((e = ensure_smem(fn[i], i < 2 ? sb : (i == 2 ? sp : sps)))) return e;
   }
-  const size_t s_pcg = pcg_smem(b);
-  if ((e = ensure_smem((const void*)k_pcg, s_pcg))) return e;
   // Events of kernel slot k, or none when it is not timed.
   auto evk = [&](int k) { return (ev_all && ((timed >> k) & 1)) ? ev_all : nullptr; };
   // Every timed kernel needs a dispatch to carry its events, also when a
@@ -2510,8 +2554,20 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   // events mark an empty interval.
   if (b.any_dense) launch(k_solve, dim3(b.n_act), dim3(kSolveWG), s_solve, st, evk(4), 4, b);
   else if (evk(4) && ((e = hipEventRecord(ev_all[8], st)) || (e = hipEventRecord(ev_all[9], st)))) return e;
-  if (b.any_sparse) launch(k_pcg, dim3(b.n_act), dim3(kPcgThreads), s_pcg, st, evk(7), 7, b);
-  else if (evk(7) && ((e = hipEventRecord(ev_all[14], st)) || (e = hipEventRecord(ev_all[15], st)))) return e;
+  // conjugate gradients: one cooperative launch per such cluster (its
+  // workgroups meet at grid barriers); timed from before the first to after
+  // the last
+  if (evk(7) && (e = hipEventRecord(ev_all[14], st))) return e;
+  for (int i = 0; i < n_sp; ++i) {
+    if ((e = ensure_smem((const void*)k_pcg, (size_t)spl[i].smem))) return e;
+    int slot = spl[i].slot;
+    Batch bb = b;
+    void* args[] = {&bb, &slot};
+    if ((e = hipLaunchCooperativeKernel((const void*)k_pcg, dim3(spl[i].G), dim3(kCgThreads), args,
+                                        (unsigned)spl[i].smem, st)))
+      return e;
+  }
+  if (evk(7) && (e = hipEventRecord(ev_all[15], st))) return e;
   if (b.total_wg > 0 || evk(5)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
     if (mixed) launch(k_backsub<float, false>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);

@@ -24,6 +24,7 @@
 
 #include "../../include/ba.h"
 #include "ba_device.h"
+#include "ba_stage.h"
 
 using namespace bagpu;
 
@@ -34,7 +35,7 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static_assert(sizeof(I4) == sizeof(int4) && sizeof(I2) == sizeof(int2), "layout tuples are uploaded as int4 / int2");
 
 // ---- arena: first-fit free list with coalescing -------------------------------------
 
@@ -72,40 +73,54 @@ class Arena {
   size_t size_ = 0, used_ = 0;
 };
 
-// ---- a submitted cluster, laid out for the device ------------------------------------
-
-struct Staged {
-  int C = 0, P = 0, O = 0, L = 0, n_chunks = 0, m = 0, n_free = 0, kcol0 = -1, kcol1 = -1;
-  int kcolt[kIntr] = {-1, -1, -1, -1, -1}, sc = 0;   // column of each intrinsic; f, cx or cy estimated
-  int max_iters = 0, stop_on_ftol = 0;
-  double f = 0, cx = 0, cy = 0, sigma = 1, delta = 1, lambda0 = 1e-4, ftol = 0, k[2] = {0, 0};
-  std::vector<double> raw_cam;   // [C][30]
-  std::vector<double> X;         // [3P] internal point order
-  std::vector<int> pt_orig;      // [P] caller index of each internal point
-  std::vector<int> cam_col;      // [C]
-  std::vector<int> lane_pt, lane_meta;
-  std::vector<double> lane_uv;   // [2L]
-  int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
-  std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
-  std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
-  std::vector<int4> tasks, targets;
-  // sparse (PCG) reduced system: block CSR over the free cameras, diagonal first
-  int sparse = 0;
-  std::vector<int> brow, bcol;   // [F + 1], [nnzb]
-  std::vector<int2> tslot;       // [n_targets] block slots (a,b), (b,a) of each target
-  // resident state: global IDs (caller order) when the cluster uses it;
-  // observations per camera (the match-count weights of Eq. 8 fusion)
-  bool resident = false, fuse = false;
-  std::vector<int64_t> cam_ids, point_ids;
-  std::vector<int> cam_nobs;
-};
+// Block rows of each conjugate-gradient workgroup: consecutive rows, at most
+// ceil(F / 16) per workgroup (about 16 workgroups: every conjugate-gradient
+// step pays two grid barriers whose cost grows with the workgroup count, and
+// on the 400-camera flight 16 beat 32, 64 and 128), and no more than keep the
+// workgroup's blocks, the whole direction p and its row work in 150 KB of
+// LDS.  False when a single block row does not fit or more than kMaxCgWG
+// workgroups would be needed.
+bool pcg_partition(const Staged& s, bool mixed, std::vector<int>& part, int& rows_max, size_t& smem) {
+  part.clear();
+  rows_max = 0;
+  smem = 0;
+  if (!s.sparse) return true;
+  const int F = s.n_free, m = s.m;
+  const size_t bb = (mixed ? 4 : 8) * (size_t)kSbVals, budget = 150 * 1024;
+  const size_t fixed = 8 * ((size_t)m + 4 * (size_t)F);
+  const int cap = std::max(1, std::min(kCgThreads, (F + 15) / 16));
+  part.push_back(0);
+  int rows = 0;
+  size_t bytes = 0;
+  for (int f = 0; f < F; ++f) {
+    const size_t rb = bb * (size_t)(s.brow[f + 1] - s.brow[f]);
+    if (rows > 0 && (rows == cap || fixed + bytes + rb + 216 * (size_t)(rows + 1) > budget)) {
+      part.push_back(f);
+      rows = 0;
+      bytes = 0;
+    }
+    if (fixed + rb + 216 > budget) return false;
+    bytes += rb;
+    ++rows;
+    rows_max = std::max(rows_max, rows);
+    smem = std::max(smem, pcg_lds_bytes(bytes, m, F, 0));
+  }
+  part.push_back(F);
+  if ((int)part.size() - 1 > kMaxCgWG) return false;
+  smem += 8 * 27 * (size_t)rows_max;
+  return true;
+}
 
 struct Layout {                  // byte offsets inside a slot block
   size_t lane_pt, lane_meta, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
-      brow, bcol, tslot, Sblk, Sblk32, pcgw, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
+      brow, bcol, tslot, Sblk, Sblk32, pcgw, pcg_part, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, lambda_log, acc_log, stat_part, out, total;
   int n_wg, psize, pstride;
+  std::vector<int> part;         // conjugate-gradient workgroups' first block rows
+  int pcg_rows_max;
+  size_t pcg_smem;
+  bool pcg_ok;
 };
 
 Layout make_layout(const Staged& s, bool mixed) {
@@ -153,7 +168,9 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.tslot = take(sizeof(int2) * s.tslot.size());
   l.Sblk = take(8 * (size_t)kSbVals * nnzb);
   l.Sblk32 = take(4 * (size_t)kSbVals * nnzb);
-  l.pcgw = take(8 * 2 * (size_t)(s.sparse ? s.m : 0));
+  l.pcg_ok = pcg_partition(s, mixed, l.part, l.pcg_rows_max, l.pcg_smem);
+  l.pcgw = take(s.sparse ? 8 * (5 * (size_t)s.m + 8 * (size_t)kMaxCgWG) : 0);
+  l.pcg_part = take(4 * l.part.size());
   const size_t rc = s.resident ? (size_t)s.C : 0, rp = s.resident ? (size_t)s.P : 0;
   l.rin_cam = take(sizeof(int2) * rc);
   l.rin_pt = take(sizeof(int2) * rp);
@@ -168,14 +185,6 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 5 + kStatVals));
   l.total = o;
   return l;
-}
-
-// splitmix64 finaliser: spreads IDs over a power-of-two table.
-inline uint64_t mix_id(int64_t id) {
-  uint64_t z = (uint64_t)id + 0x9e3779b97f4a7c15ull;
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  return z ^ (z >> 31);
 }
 
 // Global ID -> row, open addressing with linear probing (the resident store's
@@ -226,352 +235,44 @@ class IdMap {
   size_t mask_ = 0, n_ = 0;
 };
 
-// True when the n IDs are pairwise distinct.
-bool ids_unique(const int64_t* id, int n) {
-  size_t cap = 16;
-  while (cap < 2 * (size_t)n) cap <<= 1;
-  std::vector<int64_t> key(cap);
-  std::vector<uint8_t> used(cap, 0);
-  for (int i = 0; i < n; ++i) {
-    size_t h = mix_id(id[i]) & (cap - 1);
-    for (; used[h]; h = (h + 1) & (cap - 1))
-      if (key[h] == id[i]) return false;
-    used[h] = 1;
-    key[h] = id[i];
-  }
-  return true;
-}
+enum TicketState { TK_QUEUED, TK_RESIDENT, TK_DONE, TK_INVALID };
 
-bool finite_all(const double* p, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
-  return true;
-}
-
-int4 mk4(int kind, int a, int b, int y, int z) { return make_int4((kind << 24) | (a << 12) | b, y, z, 0); }
-
-// Validates the cluster and builds its work lists (integer bookkeeping only):
-//  * point lanes: observations sorted by (point, camera), packed greedily into
-//    64-lane chunks so that no point's observations straddle a chunk;
-//  * camera lanes: observations of each free camera in point order, each
-//    camera's run padded to whole chunks, cut into tasks of <= cpt chunks;
-//  * pair lanes: the observation pairs of each point whose two cameras are
-//    free, grouped by camera pair, padded and cut into tasks likewise;
-//  * reduction targets: each free camera, each camera pair, the intrinsics.
-int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, int solver) {
-  if (!c) { err = "cluster is NULL"; return BA_E_ARG; }
-  const int C = c->n_cams, P = c->n_points, O = c->n_obs;
-  if (C < 1 || C > kMaxCams || P < 0 || O < 0) { err = "sizes out of range (1 <= n_cams <= 512)"; return BA_E_ARG; }
-  if (!c->R || !c->T || !c->k || !c->prior_R || !c->prior_T || !c->prior_sigma || !c->fixed ||
-      (P > 0 && !c->X) || (O > 0 && (!c->obs_cam || !c->obs_pt || !c->obs_uv))) {
-    err = "missing input array"; return BA_E_ARG;
+// A submitted cluster's arrays, copied for background layout (stage_threads > 0).
+struct ClusterCopy {
+  ba_cluster c{};
+  std::vector<double> R, T, X, k, prior_R, prior_T, prior_sigma, obs_uv;
+  std::vector<uint8_t> fixed;
+  std::vector<int32_t> obs_cam, obs_pt;
+  std::vector<int64_t> cam_ids, point_ids;
+  explicit ClusterCopy(const ba_cluster& in) : c(in) {
+    const size_t C = (size_t)in.n_cams, P = (size_t)in.n_points, O = (size_t)in.n_obs;
+    auto cp = [](auto& v, const auto* src, size_t n) {
+      if (src) v.assign(src, src + n);
+      return src ? v.data() : nullptr;
+    };
+    c.R = cp(R, in.R, 9 * C);
+    c.T = cp(T, in.T, 3 * C);
+    c.X = cp(X, in.X, 3 * P);
+    c.k = cp(k, in.k, 2);
+    c.prior_R = cp(prior_R, in.prior_R, 9 * C);
+    c.prior_T = cp(prior_T, in.prior_T, 3 * C);
+    c.prior_sigma = cp(prior_sigma, in.prior_sigma, 6 * C);
+    c.fixed = cp(fixed, in.fixed, C);
+    c.obs_cam = cp(obs_cam, in.obs_cam, O);
+    c.obs_pt = cp(obs_pt, in.obs_pt, O);
+    c.obs_uv = cp(obs_uv, in.obs_uv, 2 * O);
+    c.cam_ids = cp(cam_ids, in.cam_ids, C);
+    c.point_ids = cp(point_ids, in.point_ids, P);
   }
-  if (c->max_iters < 1 || c->max_iters > 4096) { err = "max_iters must be in 1..4096"; return BA_E_ARG; }
-  if (!(c->sigma_px > 0) || !(c->huber_delta > 0) || !std::isfinite(c->sigma_px) || !std::isfinite(c->huber_delta) ||
-      !std::isfinite(c->f) || !std::isfinite(c->cx) || !std::isfinite(c->cy) || !(c->f > 0)) {
-    err = "bad camera or noise parameters"; return BA_E_ARG;
-  }
-  if (!finite_all(c->R, 9 * (size_t)C) || !finite_all(c->T, 3 * (size_t)C) || !finite_all(c->k, 2) ||
-      !finite_all(c->prior_R, 9 * (size_t)C) || !finite_all(c->prior_T, 3 * (size_t)C) ||
-      (P > 0 && !finite_all(c->X, 3 * (size_t)P)) || (O > 0 && !finite_all(c->obs_uv, 2 * (size_t)O))) {
-    err = "non-finite input"; return BA_E_ARG;
-  }
-  for (size_t i = 0; i < 6 * (size_t)C; ++i)
-    if (std::isnan(c->prior_sigma[i])) { err = "NaN prior sigma"; return BA_E_ARG; }
-  if (c->use_resident != 0 && c->use_resident != 1) { err = "use_resident must be 0 or 1"; return BA_E_ARG; }
-  if (c->fuse_resident != 0 && c->fuse_resident != 1) { err = "fuse_resident must be 0 or 1"; return BA_E_ARG; }
-  if (c->fuse_resident && !c->use_resident) { err = "fuse_resident needs use_resident"; return BA_E_ARG; }
-  if (c->use_resident) {
-    if (!c->cam_ids || (P > 0 && !c->point_ids)) { err = "use_resident needs cam_ids and point_ids"; return BA_E_ARG; }
-    if (!ids_unique(c->cam_ids, C)) { err = "duplicate camera ID in the cluster"; return BA_E_ARG; }
-    if (!ids_unique(c->point_ids, P)) { err = "duplicate point ID in the cluster"; return BA_E_ARG; }
-  }
-  s = Staged();
-  s.C = C; s.P = P; s.O = O;
-  if (c->use_resident) {
-    s.resident = true;
-    s.fuse = c->fuse_resident != 0;
-    s.cam_ids.assign(c->cam_ids, c->cam_ids + C);
-    s.point_ids.assign(c->point_ids, c->point_ids + P);
-    s.cam_nobs.assign(C, 0);
-    for (int o = 0; o < O; ++o)   // indices are range-checked below; count only valid ones here
-      if (c->obs_cam[o] >= 0 && c->obs_cam[o] < C) ++s.cam_nobs[c->obs_cam[o]];
-  }
-  s.max_iters = c->max_iters; s.stop_on_ftol = c->stop_on_ftol;
-  s.f = c->f; s.cx = c->cx; s.cy = c->cy; s.sigma = c->sigma_px; s.delta = c->huber_delta;
-  s.lambda0 = c->lambda0; s.ftol = c->ftol; s.k[0] = c->k[0]; s.k[1] = c->k[1];
-  s.cam_col.assign(C, -1);
-  for (int k = 0; k < C; ++k)
-    if (!c->fixed[k]) s.cam_col[k] = 6 * s.n_free++;
-  if (solver == BA_SOLVER_PCG) s.sparse = 1;
-  else if (solver == BA_SOLVER_AUTO) s.sparse = s.n_free > kMaxFreeCams;
-  else if (solver != BA_SOLVER_DENSE) { err = "unknown solver"; return BA_E_ARG; }
-  if (!s.sparse && s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras for the dense solver"; return BA_E_ARG; }
-  if (c->intr_mask & ~31) { err = "intr_mask has bits beyond k1, k2, f, cx, cy"; return BA_E_ARG; }
-  if (s.sparse && c->intr_mask) { err = "the PCG solver does not estimate intrinsics"; return BA_E_ARG; }
-  // the estimated intrinsics' columns follow the cameras', in bit order
-  int col = 6 * s.n_free;
-  for (int b = 0; b < kIntr; ++b)
-    if (c->intr_mask & (1 << b)) s.kcolt[b] = col++;
-  s.kcol0 = s.kcolt[0];
-  s.kcol1 = s.kcolt[1];
-  s.sc = (c->intr_mask & ~3) != 0;
-  s.m = col;
-  s.raw_cam.resize(30 * (size_t)C);
-  for (int k = 0; k < C; ++k) {
-    double* r = &s.raw_cam[30 * (size_t)k];
-    std::memcpy(r, c->R + 9 * k, 9 * sizeof(double));
-    std::memcpy(r + 9, c->T + 3 * k, 3 * sizeof(double));
-    std::memcpy(r + 12, c->prior_R + 9 * k, 9 * sizeof(double));
-    std::memcpy(r + 21, c->prior_T + 3 * k, 3 * sizeof(double));
-    std::memcpy(r + 24, c->prior_sigma + 6 * k, 6 * sizeof(double));
-  }
-  for (int o = 0; o < O; ++o) {
-    const int cam = c->obs_cam[o], pt = c->obs_pt[o];
-    if (cam < 0 || cam >= C || pt < 0 || pt >= P) { err = "observation index out of range"; return BA_E_ARG; }
-  }
-  // Internal point order: Morton (z-order) of the initial ground position, so
-  // that a camera's observations touch nearby point records.  Ties keep the
-  // caller's order (LSD radix sort of key << 32 | index on the key bits).
-  {
-    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
-    for (int j = 0; j < P; ++j)
-      for (int t = 0; t < 2; ++t) {
-        lo[t] = std::min(lo[t], c->X[3 * (size_t)j + t]);
-        hi[t] = std::max(hi[t], c->X[3 * (size_t)j + t]);
-      }
-    std::vector<uint64_t> kj(P), tmp(P);
-    for (int j = 0; j < P; ++j) {
-      uint32_t q[2];
-      for (int t = 0; t < 2; ++t) {
-        const double span = hi[t] - lo[t];
-        const double u = span > 0 ? (c->X[3 * (size_t)j + t] - lo[t]) / span : 0.0;
-        q[t] = (uint32_t)std::min(65535.0, std::max(0.0, u * 65535.0));
-      }
-      uint32_t k = 0;
-      for (int b = 0; b < 16; ++b) k |= ((q[0] >> b) & 1u) << (2 * b) | ((q[1] >> b) & 1u) << (2 * b + 1);
-      kj[j] = (uint64_t)k << 32 | (uint32_t)j;
-    }
-    for (int shift = 32; shift < 64; shift += 11) {
-      size_t cnt_d[2049] = {0};
-      for (int j = 0; j < P; ++j) ++cnt_d[((kj[j] >> shift) & 2047u) + 1];
-      for (int d = 0; d < 2048; ++d) cnt_d[d + 1] += cnt_d[d];
-      for (int j = 0; j < P; ++j) tmp[cnt_d[(kj[j] >> shift) & 2047u]++] = kj[j];
-      kj.swap(tmp);
-    }
-    s.pt_orig.resize(P);
-    for (int n = 0; n < P; ++n) s.pt_orig[n] = (int)(uint32_t)kj[n];
-  }
-  std::vector<int> inv(P), opt(O);
-  for (int n = 0; n < P; ++n) inv[s.pt_orig[n]] = n;
-  for (int o = 0; o < O; ++o) opt[o] = inv[c->obs_pt[o]];
-  s.X.resize(3 * (size_t)P);
-  for (int n = 0; n < P; ++n)
-    for (int t = 0; t < 3; ++t) s.X[3 * (size_t)n + t] = c->X[3 * (size_t)s.pt_orig[n] + t];
-  // observations per point
-  std::vector<int> cnt(P + 1, 0);
-  for (int o = 0; o < O; ++o)
-    if (++cnt[opt[o] + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
-  for (int j = 0; j < P; ++j) cnt[j + 1] += cnt[j];
-  // observations in (point, camera) order: a counting sort by camera, then a
-  // stable one by point; then their camera, pixel and point in that order
-  std::vector<int> order(O);
-  {
-    std::vector<int> by_cam(O), cc(C + 1, 0);
-    for (int o = 0; o < O; ++o) ++cc[c->obs_cam[o] + 1];
-    for (int k = 0; k < C; ++k) cc[k + 1] += cc[k];
-    for (int o = 0; o < O; ++o) by_cam[cc[c->obs_cam[o]]++] = o;
-    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-    for (int t = 0; t < O; ++t) order[fill[opt[by_cam[t]]]++] = by_cam[t];
-  }
-  std::vector<int> scam(O), spt(O);
-  std::vector<double> suv(2 * (size_t)O);
-  for (int j = 0; j < P; ++j)
-    for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
-      const int o = order[t];
-      scam[t] = c->obs_cam[o];
-      spt[t] = j;
-      suv[2 * (size_t)t] = c->obs_uv[2 * (size_t)o];
-      suv[2 * (size_t)t + 1] = c->obs_uv[2 * (size_t)o + 1];
-      if (t > cnt[j] && scam[t] == scam[t - 1]) { err = "a camera observes one point twice"; return BA_E_ARG; }
-    }
-  // greedy packing into 64-lane chunks
-  std::vector<int> start(P, 0);
-  int pos = 0;
-  for (int j = 0; j < P; ++j) {
-    const int n = cnt[j + 1] - cnt[j];
-    if (n == 0) continue;
-    if ((pos % kWave) + n > kWave) pos = (int)align_up(pos, kWave);
-    start[j] = pos;
-    pos += n;
-  }
-  s.L = (int)align_up(pos, kWave);
-  s.n_chunks = s.L / kWave;
-  s.lane_pt.assign(s.L, -1);
-  // lane word: camera (9 bits) | segment start in the chunk << 9 (6 bits) |
-  // segment length << 15 (7 bits) | the chunk's longest segment << 22 (7 bits)
-  s.lane_meta.resize(s.L);
-  s.lane_uv.assign(2 * (size_t)s.L, 0.0);
-  for (int i = 0; i < s.L; ++i) s.lane_meta[i] = ((i % kWave) << 9) | (1 << 15);
-  std::vector<int> chunk_max(s.n_chunks, 1);
-  for (int j = 0; j < P; ++j) {
-    const int n = cnt[j + 1] - cnt[j];
-    for (int t = 0; t < n; ++t) {
-      const int so = cnt[j] + t, lane = start[j] + t;
-      s.lane_pt[lane] = j;
-      s.lane_meta[lane] = scam[so] | ((start[j] % kWave) << 9) | (n << 15);
-      chunk_max[lane / kWave] = std::max(chunk_max[lane / kWave], n);
-      s.lane_uv[2 * (size_t)lane] = suv[2 * (size_t)so];
-      s.lane_uv[2 * (size_t)lane + 1] = suv[2 * (size_t)so + 1];
-    }
-  }
-  for (int i = 0; i < s.L; ++i) s.lane_meta[i] |= chunk_max[i / kWave] << 22;
-  s.n_wg = (s.n_chunks + cpw - 1) / cpw;
-  const bool intr = s.m > 6 * s.n_free;   // an intrinsic is estimated
-  s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
-  s.nb = (s.m + kSolveTb - 1) / kSolveTb;
-  const int F = s.n_free;
-  std::vector<int> free_cam(F);
-  for (int k = 0; k < C; ++k)
-    if (s.cam_col[k] >= 0) free_cam[s.cam_col[k] / 6] = k;
-  // camera lanes and tasks: each free camera's observations in point order
-  std::vector<int> coff(F + 1, 0);
-  for (int t = 0; t < O; ++t) {
-    const int col = s.cam_col[scam[t]];
-    if (col >= 0) ++coff[col / 6 + 1];
-  }
-  for (int fi = 0; fi < F; ++fi) coff[fi + 1] += coff[fi];
-  std::vector<int> cobs(coff[F]);
-  {
-    std::vector<int> fill(coff.begin(), coff.end() - 1);
-    for (int t = 0; t < O; ++t) {
-      const int col = s.cam_col[scam[t]];
-      if (col >= 0) cobs[fill[col / 6]++] = t;
-    }
-  }
-  for (int fi = 0; fi < F; ++fi) s.Lc += (int)align_up(coff[fi + 1] - coff[fi], kWave);
-  s.cl_pt.assign(s.Lc, -1);
-  s.cl_uv.assign(2 * (size_t)s.Lc, 0.0);
-  std::vector<int2> cam_range(F);
-  for (int fi = 0, base = 0; fi < F; ++fi) {
-    const int n = coff[fi + 1] - coff[fi];
-    for (int t = 0; t < n; ++t) {
-      const int so = cobs[coff[fi] + t];
-      const size_t lane = (size_t)base * kWave + t;
-      s.cl_pt[lane] = spt[so];
-      s.cl_uv[2 * lane] = suv[2 * (size_t)so];
-      s.cl_uv[2 * lane + 1] = suv[2 * (size_t)so + 1];
-    }
-    const int nch = (int)(align_up(n, kWave) / kWave);
-    cam_range[fi].x = (int)s.tasks.size();
-    for (int ch = 0; ch < nch; ch += cpt) s.tasks.push_back(mk4(TASK_CAM, free_cam[fi], 0, base + ch, std::min(cpt, nch - ch)));
-    cam_range[fi].y = (int)s.tasks.size();
-    base += nch;
-  }
-  s.n_cam_tasks = (int)s.tasks.size();
-  // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order;
-  // within a block the pairs (point, obs a, obs b) in point order
-  const int nblk = F * (F - 1) / 2;
-  auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
-  std::vector<int> poff(nblk + 1, 0);
-  for (int j = 0; j < P; ++j)
-    for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
-      const int ca = s.cam_col[scam[ta]];
-      if (ca < 0) continue;
-      for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
-        const int cb = s.cam_col[scam[tb]];
-        if (cb >= 0) ++poff[blk(ca / 6, cb / 6) + 1];
-      }
-    }
-  for (int b = 0; b < nblk; ++b) poff[b + 1] += poff[b];
-  std::vector<int3> pairs(poff[nblk]);
-  {
-    std::vector<int> fill(poff.begin(), poff.end() - 1);
-    for (int j = 0; j < P; ++j)
-      for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
-        const int ca = s.cam_col[scam[ta]];
-        if (ca < 0) continue;
-        for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
-          const int cb = s.cam_col[scam[tb]];
-          if (cb >= 0) pairs[fill[blk(ca / 6, cb / 6)]++] = make_int3(j, ta, tb);
-        }
-      }
-  }
-  auto blk_empty = [&](int b) { return poff[b + 1] == poff[b]; };
-  for (int b = 0; b < nblk; ++b) s.Lq += (int)align_up(poff[b + 1] - poff[b], kWave);
-  s.ql_pt.assign(s.Lq, -1);
-  s.ql_uv.assign(4 * (size_t)s.Lq, 0.0);
-  std::vector<int2> blk_range(nblk);
-  for (int fa = 0, base = 0; fa < F; ++fa)
-    for (int fb = fa + 1; fb < F; ++fb) {
-      const int b = blk(fa, fb), n = poff[b + 1] - poff[b];
-      for (int t = 0; t < n; ++t) {
-        const int3 pr = pairs[poff[b] + t];
-        const size_t lane = (size_t)base * kWave + t;
-        s.ql_pt[lane] = pr.x;
-        s.ql_uv[4 * lane] = suv[2 * (size_t)pr.y];
-        s.ql_uv[4 * lane + 1] = suv[2 * (size_t)pr.y + 1];
-        s.ql_uv[4 * lane + 2] = suv[2 * (size_t)pr.z];
-        s.ql_uv[4 * lane + 3] = suv[2 * (size_t)pr.z + 1];
-      }
-      const int nch = (int)(align_up(n, kWave) / kWave);
-      blk_range[b].x = (int)s.tasks.size();
-      for (int ch = 0; ch < nch; ch += cpt)
-        s.tasks.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], base + ch, std::min(cpt, nch - ch)));
-      blk_range[b].y = (int)s.tasks.size();
-      base += nch;
-    }
-  for (int fi = 0; fi < F; ++fi) s.targets.push_back(mk4(TASK_CAM, free_cam[fi], 0, cam_range[fi].x, cam_range[fi].y));
-  if (!s.sparse) {
-    for (int fa = 0; fa < F; ++fa)
-      for (int fb = fa + 1; fb < F; ++fb) {
-        const int2 r = blk_range[blk(fa, fb)];
-        s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
-      }
-    if (intr) s.targets.push_back(mk4(TARGET_INTR, 0, 0, 0, s.n_pt_part));
-    return BA_OK;
-  }
-  // Block CSR of the co-visible free-camera pairs.  Row fa lists its diagonal
-  // block, then the non-empty blocks (fa, fb) in increasing fb.  Each pair
-  // target writes its block and the transpose.
-  std::vector<std::vector<int>> nbr(F);
-  for (int fa = 0; fa < F; ++fa)
-    for (int fb = fa + 1; fb < F; ++fb)
-      if (!blk_empty(blk(fa, fb))) {
-        nbr[fa].push_back(fb);
-        nbr[fb].push_back(fa);
-      }
-  s.brow.assign(F + 1, 0);
-  std::vector<int> diag_slot(F);
-  std::map<std::pair<int, int>, int> slot_of;
-  for (int fa = 0; fa < F; ++fa) {
-    s.brow[fa] = (int)s.bcol.size();
-    diag_slot[fa] = (int)s.bcol.size();
-    s.bcol.push_back(fa);
-    std::sort(nbr[fa].begin(), nbr[fa].end());
-    for (int fb : nbr[fa]) {
-      slot_of[{fa, fb}] = (int)s.bcol.size();
-      s.bcol.push_back(fb);
-    }
-  }
-  s.brow[F] = (int)s.bcol.size();
-  for (int fi = 0; fi < F; ++fi) s.tslot.push_back(make_int2(diag_slot[fi], diag_slot[fi]));
-  for (int fa = 0; fa < F; ++fa)
-    for (int fb = fa + 1; fb < F; ++fb) {
-      if (blk_empty(blk(fa, fb))) continue;
-      const int2 r = blk_range[blk(fa, fb)];
-      s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
-      s.tslot.push_back(make_int2(slot_of[{fa, fb}], slot_of[{fb, fa}]));
-    }
-  return BA_OK;
-}
-
-enum TicketState { TK_QUEUED, TK_RESIDENT, TK_DONE };
+};
 
 struct Ticket {
   ba_ticket id = 0;
   TicketState state = TK_QUEUED;
   bool serving = false;           // owned by the serving loop until done
+  bool staging = false;           // laid out in the background; not admissible yet
+  int err_code = 0;               // TK_INVALID: why the background layout refused it
+  std::string err_msg;
   std::unique_ptr<Staged> staged; // until admission
   int C = 0, P = 0, max_iters = 0;
   size_t bytes = 0;
@@ -607,6 +308,7 @@ struct Launcher {
   hipEvent_t ev = nullptr;
   hipEvent_t copy_ev = nullptr;  // after the last upload from h_act
   bool copy_pending = false;
+  std::vector<SparseLaunch> sp;  // the batch's clusters solved by conjugate gradients
 };
 
 }  // namespace
@@ -655,6 +357,12 @@ struct ba_ctx {
   IdMap res_cam_row, res_pt_row;
   std::vector<ResRow> res_cam_meta, res_pt_meta;
   double res_lambda = NAN;        // damping the last written-back cluster ended with
+  // background layout (ba_options.stage_threads > 0)
+  std::vector<std::thread> stagers;
+  std::deque<std::pair<ba_ticket, std::unique_ptr<ClusterCopy>>> stage_jobs;
+  std::condition_variable stage_cv;       // wakes the layout threads
+  std::condition_variable staged_cv;      // a background layout finished
+  bool stage_stop = false;
 };
 
 namespace {
@@ -738,9 +446,11 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
   b.tkp_off = l.d_wgoff + 2 * (S + 1);
   b.tg_off = l.d_wgoff + 3 * (S + 1);
   b.n_act = (int)slots.size();
+  l.sp.clear();
   int tot = 0, tc = 0, tp = 0, tg = 0;
   for (int i = 0; i < b.n_act; ++i) {
     const Slot& sl = c->slots[slots[i]];
+    if (sl.desc.sparse) l.sp.push_back(SparseLaunch{slots[i], sl.desc.pcg_G, sl.desc.pcg_smem});
     act[i] = slots[i];
     off[i] = tot;
     tkc[i] = tc;
@@ -921,6 +631,10 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.Sblk = (double*)(base + lay.Sblk);
   d.Sblk32 = (float*)(base + lay.Sblk32);
   d.pcgw = (double*)(base + lay.pcgw);
+  d.pcg_part = (const int*)(base + lay.pcg_part);
+  d.pcg_G = lay.part.empty() ? 0 : (int)lay.part.size() - 1;
+  d.pcg_rows_max = lay.pcg_rows_max;
+  d.pcg_smem = (int)lay.pcg_smem;
   std::vector<int2> rin_c, rin_p, rout_p;
   std::vector<int4> rout_c;
   if (t.resident) {
@@ -973,6 +687,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
     HIPCHK(c, hipMemcpyAsync(base + lay.brow, s.brow.data(), 4 * s.brow.size(), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(base + lay.bcol, s.bcol.data(), 4 * s.bcol.size(), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(base + lay.tslot, s.tslot.data(), sizeof(int2) * s.tslot.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + lay.pcg_part, lay.part.data(), 4 * lay.part.size(), hipMemcpyHostToDevice, st));
   }
   HIPCHK(c, hipMemcpyAsync(base + lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C, hipMemcpyHostToDevice, st));
   if (s.P > 0) {
@@ -1054,7 +769,7 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
       c->prof_set_mask[c->prof_used] = c->prof;
       ev = c->prof_ev[c->prof_used++].data();
     }
-    HIPCHK(c, launch_iteration(b, mixed, c->stream, ev, c->prof));
+    HIPCHK(c, launch_iteration(b, mixed, c->stream, ev, c->prof, l.sp.data(), (int)l.sp.size()));
   }
   return BA_OK;
 }
@@ -1065,9 +780,11 @@ int run_iterations(ba_ctx* c, Launcher& l, const std::vector<int>& slots, int n_
 int run_iterations_parts(ba_ctx* c, bool serving, const std::vector<std::vector<int>>& parts, int n_iters) {
   const int P = (int)parts.size();
   Batch b[ba_ctx::kMaxParts];
+  Launcher* lp[ba_ctx::kMaxParts];
   int rc;
   for (int p = 0; p < P; ++p) {
     Launcher& l = p == 0 ? (serving ? c->srv : c->api) : (serving ? c->srv_p[p] : c->api_p[p]);
+    lp[p] = &l;
     if ((rc = make_batch(c, l, parts[p], b[p]))) return rc;   // uploads on the context's stream
   }
   HIPCHK(c, hipEventRecord(c->fork_ev, c->stream));
@@ -1086,7 +803,8 @@ int run_iterations_parts(ba_ctx* c, bool serving, const std::vector<std::vector<
         c->prof_set_mask[c->prof_used] = c->prof;
         ev = c->prof_ev[c->prof_used++].data();
       }
-      HIPCHK(c, launch_iteration(b[p], mixed, p ? c->stream_p[p] : c->stream, ev, c->prof));
+      HIPCHK(c, launch_iteration(b[p], mixed, p ? c->stream_p[p] : c->stream, ev, c->prof, lp[p]->sp.data(),
+                                 (int)lp[p]->sp.size()));
     }
   }
   for (int p = 1; p < P; ++p) {
@@ -1195,7 +913,7 @@ void free_slot(ba_ctx* c, int s) {
 int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only) {
   for (auto it = c->queue.begin(); it != c->queue.end();) {
     Ticket& t = *c->tickets[*it];
-    if ((serving_only && !t.serving) || !deps_done(c, t)) { ++it; continue; }
+    if (t.staging || (serving_only && !t.serving) || !deps_done(c, t)) { ++it; continue; }
     int rc = admit_one(c, t);
     if (rc == BA_E_AGAIN) break;
     if (rc) return rc;
@@ -1210,7 +928,7 @@ int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only) {
 bool serving_queued(ba_ctx* c) {
   for (ba_ticket id : c->queue) {
     const Ticket& t = *c->tickets[id];
-    if (t.serving && deps_done(c, t)) return true;
+    if (t.serving && !t.staging && deps_done(c, t)) return true;
   }
   return false;
 }
@@ -1311,6 +1029,9 @@ int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
 
 namespace {
 int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket, double t_submit);
+int enqueue_copy(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket, double t_submit);
+int wait_staged(ba_ctx* c, std::unique_lock<std::mutex>& lk, ba_ticket id);
+void stage_worker(ba_ctx* c);
 }  // namespace
 
 extern "C" {
@@ -1338,7 +1059,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   // 0 selects a field's default; a negative count is an error
   if (opt->max_slots < 0 || opt->max_queue < 0 || opt->iters_per_tick < 0 || opt->chunks_per_wg < 0 ||
       opt->chunks_per_task < 0 || opt->pcg_max_iters < 0 || opt->pcg_tol < 0 || opt->resident_cams < 0 ||
-      opt->resident_points < 0)
+      opt->resident_points < 0 || opt->stage_threads < 0 || opt->stage_threads > 64)
     return BA_E_ARG;
   auto c = std::make_unique<ba_ctx>();
   c->opt = *opt;
@@ -1391,6 +1112,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   for (int i = 0; i < c->opt.max_slots; ++i) c->srv.h_ctl[i] = SlotCtl{};
   if (hipDeviceSynchronize() != hipSuccess) return bail(BA_E_DEVICE);
   ba_ctx* raw = c.release();
+  for (int i = 0; i < raw->opt.stage_threads; ++i) raw->stagers.emplace_back(stage_worker, raw);
   if (opt->serve) raw->th = std::thread(serve_loop, raw);
   *out = raw;
   return BA_OK;
@@ -1401,8 +1123,12 @@ int ba_destroy(ba_ctx* c) {
   {
     std::lock_guard<std::mutex> g(c->mu);
     c->stop = true;
+    c->stage_stop = true;
   }
   c->cv.notify_all();
+  c->stage_cv.notify_all();
+  for (auto& th : c->stagers)
+    if (th.joinable()) th.join();
   if (c->th.joinable()) c->th.join();
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
@@ -1441,6 +1167,10 @@ size_t ba_footprint(ba_ctx* c, const ba_cluster* cl) {
 int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   const double t_submit = now_s();   // latency runs from here: validation and layout included
   if (!c || !ticket) return BA_E_ARG;
+  if (c->opt.stage_threads > 0) {
+    std::lock_guard<std::mutex> g(c->mu);
+    return enqueue_copy(c, cl, ticket, t_submit);
+  }
   auto st = std::make_unique<Staged>();
   std::string err;
   int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
@@ -1453,6 +1183,17 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
   const double t_submit = now_s();
   if (!c || n < 0 || (n > 0 && (!cl || !tickets))) return BA_E_ARG;
   for (int i = 0; i < n; ++i) tickets[i] = 0;
+  if (c->opt.stage_threads > 0) {   // background layout: queued in order, laid out by the pool
+    std::lock_guard<std::mutex> g(c->mu);
+    for (int i = 0; i < n; ++i) {
+      const int r = enqueue_copy(c, &cl[i], &tickets[i], t_submit);
+      if (r) {
+        c->last_error = "cluster " + std::to_string(i) + ": " + c->last_error;
+        return r;
+      }
+    }
+    return BA_OK;
+  }
   std::vector<std::unique_ptr<Staged>> st(n);
   std::vector<int> rc(n, BA_OK);
   std::vector<std::string> err(n);
@@ -1486,12 +1227,135 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
 
 namespace {
 
+// Releases the resident-store rows a ticket registered (it will never write
+// them back).  Caller holds mu.
+void res_abandon(ba_ctx* c, Ticket& t) {
+  for (int row : t.cam_rows)
+    if (c->res_cam_meta[row].pending == t.id) c->res_cam_meta[row].pending = 0;
+  for (int row : t.pt_rows)
+    if (c->res_pt_meta[row].pending == t.id) c->res_pt_meta[row].pending = 0;
+  t.res_done = true;
+}
+
+// A layout thread: lays out the queued copies in submission order of pickup;
+// the result (or the reason it was refused) goes to the ticket.
+void stage_worker(ba_ctx* c) {
+  std::unique_lock<std::mutex> lk(c->mu);
+  for (;;) {
+    c->stage_cv.wait(lk, [&] { return c->stage_stop || !c->stage_jobs.empty(); });
+    if (c->stage_stop) return;
+    auto job = std::move(c->stage_jobs.front());
+    c->stage_jobs.pop_front();
+    lk.unlock();
+    auto st = std::make_unique<Staged>();
+    std::string err;
+    const int rc = stage(&job.second->c, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
+    Layout lay;
+    if (!rc) lay = make_layout(*st, c->opt.precision == BA_MIXED);
+    lk.lock();
+    Ticket* t = nullptr;
+    auto it = c->tickets.find(job.first);
+    if (it != c->tickets.end()) t = it->second.get();
+    if (!t) {           // released meanwhile
+      c->staged_cv.notify_all();
+      continue;
+    }
+    int code = rc;
+    if (!code && !lay.pcg_ok) {
+      code = BA_E_ARG;
+      err = "reduced system too dense for the conjugate-gradient solve";
+    } else if (!code && lay.total > c->arena.size()) {
+      code = BA_E_NOMEM;
+      err = "cluster footprint exceeds the arena";
+    }
+    t->staging = false;
+    if (code) {
+      t->state = TK_INVALID;
+      t->err_code = code;
+      t->err_msg = err;
+      t->serving = false;
+      if (t->resident) res_abandon(c, *t);
+      c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), t->id), c->queue.end());
+      c->done_cv.notify_all();
+      c->cv.notify_all();
+    } else {
+      t->bytes = lay.total;
+      t->staged = std::move(st);
+      c->cv.notify_all();
+    }
+    c->staged_cv.notify_all();
+  }
+}
+
+// Waits (releasing mu) until the ticket's background layout has finished;
+// returns its refusal, if any.  Caller holds mu through lk.
+int wait_staged(ba_ctx* c, std::unique_lock<std::mutex>& lk, ba_ticket id) {
+  c->staged_cv.wait(lk, [&] {
+    auto it = c->tickets.find(id);
+    return it == c->tickets.end() || !it->second->staging;
+  });
+  auto it = c->tickets.find(id);
+  if (it == c->tickets.end()) return fail(c, BA_E_ARG, "unknown ticket");
+  if (it->second->state == TK_INVALID) return fail(c, it->second->err_code, it->second->err_msg);
+  return BA_OK;
+}
+
+// Queues a copy of the cluster for background layout: the checks that need no
+// layout now (sizes, arrays present, resident IDs unique), the rest on a
+// layout thread.  Caller holds mu.
+int enqueue_copy(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket, double t_submit) {
+  if (!cl) return fail(c, BA_E_ARG, "cluster is NULL");
+  const int C = cl->n_cams, P = cl->n_points, O = cl->n_obs;
+  if (C < 1 || C > kMaxCams || P < 0 || O < 0) return fail(c, BA_E_ARG, "sizes out of range (1 <= n_cams <= 512)");
+  if (!cl->R || !cl->T || !cl->k || !cl->prior_R || !cl->prior_T || !cl->prior_sigma || !cl->fixed ||
+      (P > 0 && !cl->X) || (O > 0 && (!cl->obs_cam || !cl->obs_pt || !cl->obs_uv)))
+    return fail(c, BA_E_ARG, "missing input array");
+  if (cl->max_iters < 1 || cl->max_iters > 4096) return fail(c, BA_E_ARG, "max_iters must be in 1..4096");
+  if (cl->use_resident != 0 && cl->use_resident != 1) return fail(c, BA_E_ARG, "use_resident must be 0 or 1");
+  if (cl->use_resident) {
+    if (!cl->cam_ids || (P > 0 && !cl->point_ids)) return fail(c, BA_E_ARG, "use_resident needs cam_ids and point_ids");
+    if (!ids_unique(cl->cam_ids, C)) return fail(c, BA_E_ARG, "duplicate camera ID in the cluster");
+    if (!ids_unique(cl->point_ids, P)) return fail(c, BA_E_ARG, "duplicate point ID in the cluster");
+  }
+  if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
+  if ((int)c->queue.size() >= c->opt.max_queue) return fail(c, BA_E_AGAIN, "admission queue full");
+  auto copy = std::make_unique<ClusterCopy>(*cl);
+  auto t = std::make_unique<Ticket>();
+  t->id = c->next_id;
+  if (cl->use_resident) {
+    Staged ids;   // the IDs alone: resident clusters are ordered at submission
+    ids.C = C;
+    ids.P = P;
+    ids.cam_ids = copy->cam_ids;
+    ids.point_ids = copy->point_ids;
+    const int rc = res_register(c, *t, ids);
+    if (rc) return rc;
+  }
+  c->next_id++;
+  t->C = C;
+  t->P = P;
+  t->max_iters = cl->max_iters;
+  t->t_submit = t_submit;
+  t->staging = true;
+  const ba_ticket id = t->id;
+  c->tickets[id] = std::move(t);
+  c->queue.push_back(id);
+  c->stage_jobs.emplace_back(id, std::move(copy));
+  c->stage_cv.notify_one();
+  *ticket = id;
+  return BA_OK;
+}
+
 // Queues a laid-out cluster (registering its resident IDs) and returns its
 // ticket.  Caller holds mu.
 int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket, double t_submit) {
   int rc;
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
-  const size_t bytes = make_layout(*st, c->opt.precision == BA_MIXED).total;
+  const Layout lay = make_layout(*st, c->opt.precision == BA_MIXED);
+  if (!lay.pcg_ok)
+    return fail(c, BA_E_ARG, "reduced system too dense for the conjugate-gradient solve (a block row's blocks must "
+                             "fit the LDS of one workgroup, at most 128 workgroups)");
+  const size_t bytes = lay.total;
   if (bytes > c->arena.size()) return fail(c, BA_E_NOMEM, "cluster footprint exceeds the arena");
   if ((int)c->queue.size() >= c->opt.max_queue) return fail(c, BA_E_AGAIN, "admission queue full");
   auto t = std::make_unique<Ticket>();
@@ -1517,10 +1381,16 @@ extern "C" {
 
 int ba_step(ba_ctx* c, ba_ticket id, int32_t n_iters) {
   if (!c) return BA_E_ARG;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::unique_lock<std::mutex> g(c->mu);
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (t->staging || t->state == TK_INVALID) {
+    const int rc = wait_staged(c, g, id);
+    if (rc) return rc;
+    t = find_ticket(c, id);
+    if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  }
   if (n_iters < 0) return fail(c, BA_E_ARG, "negative iteration count");
   HIPCHK(c, hipSetDevice(c->device));
   std::vector<int> adm;
@@ -1540,9 +1410,16 @@ int ba_step(ba_ctx* c, ba_ticket id, int32_t n_iters) {
 
 int ba_solve_batch(ba_ctx* c, const ba_ticket* ids, int32_t n) {
   if (!c || (n > 0 && !ids) || n < 0) return BA_E_ARG;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::unique_lock<std::mutex> g(c->mu);
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
   HIPCHK(c, hipSetDevice(c->device));
+  for (int i = 0; i < n; ++i) {
+    Ticket* t = find_ticket(c, ids[i]);
+    if (t && (t->staging || t->state == TK_INVALID)) {
+      const int rc = wait_staged(c, g, ids[i]);
+      if (rc) return rc;
+    }
+  }
   std::vector<int> adm, slots;
   for (int i = 0; i < n; ++i) {
     Ticket* t = find_ticket(c, ids[i]);
@@ -1575,6 +1452,7 @@ int ba_solve(ba_ctx* c, ba_ticket id) {
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
   if (!c->opt.serve) return fail(c, BA_E_STATE, "context has no serving loop");
+  if (t->state == TK_INVALID) return fail(c, t->err_code, t->err_msg);
   if (t->serving || t->state != TK_QUEUED) return fail(c, BA_E_STATE, "cluster is not queued");
   t->serving = true;
   c->cv.notify_all();
@@ -1586,16 +1464,18 @@ int ba_wait(ba_ctx* c, ba_ticket id, double timeout_s) {
   std::unique_lock<std::mutex> lk(c->mu);
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (t->state == TK_INVALID) return fail(c, t->err_code, t->err_msg);
   if (!t->serving && t->state != TK_DONE) return fail(c, BA_E_STATE, "cluster was not handed to ba_solve");
   // the ticket may be released (and removed) while this thread waits
   auto pred = [&] {
     Ticket* x = find_ticket(c, id);
-    return !x || x->state == TK_DONE || c->dead;
+    return !x || x->state == TK_DONE || x->state == TK_INVALID || c->dead;
   };
   if (timeout_s < 0) c->done_cv.wait(lk, pred);
   else if (!c->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return BA_E_TIMEOUT;
   t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_STATE, "cluster was released while waiting");
+  if (t->state == TK_INVALID) return fail(c, t->err_code, t->err_msg);
   if (c->dead && t->state != TK_DONE) return fail(c, BA_E_DEVICE, "serving loop stopped on a device error");
   return BA_OK;
 }
@@ -1605,6 +1485,7 @@ int ba_fetch(ba_ctx* c, ba_ticket id, ba_result* r) {
   std::lock_guard<std::mutex> g(c->mu);
   Ticket* t = find_ticket(c, id);
   if (!t) return fail(c, BA_E_ARG, "unknown ticket");
+  if (t->state == TK_INVALID) return fail(c, t->err_code, t->err_msg);
   if (t->serving) return fail(c, BA_E_STATE, "cluster is being solved by the serving loop");
   if (t->state == TK_QUEUED) return fail(c, BA_E_STATE, "cluster is still queued");
   if (t->state == TK_RESIDENT) {
@@ -1731,6 +1612,7 @@ int ba_release(ba_ctx* c, ba_ticket id) {
   }
   c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), id), c->queue.end());
   c->tickets.erase(id);
+  c->staged_cv.notify_all();   // a caller waiting for this cluster's layout
   return BA_OK;
 }
 

@@ -1,0 +1,355 @@
+// Host layout of a submitted cluster: validation and the work lists the
+// kernels read (ba_stage.h).  Plain C++: no HIP.
+#include "ba_stage.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+namespace bagpu {
+
+namespace {
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+I4 mk4(int kind, int a, int b, int y, int z) { return I4{(kind << 24) | (a << 12) | b, y, z, 0}; }
+
+}  // namespace
+
+uint64_t mix_id(int64_t id) {
+  uint64_t z = (uint64_t)id + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+bool ids_unique(const int64_t* id, int n) {
+  size_t cap = 16;
+  while (cap < 2 * (size_t)n) cap <<= 1;
+  std::vector<int64_t> key(cap);
+  std::vector<uint8_t> used(cap, 0);
+  for (int i = 0; i < n; ++i) {
+    size_t h = mix_id(id[i]) & (cap - 1);
+    for (; used[h]; h = (h + 1) & (cap - 1))
+      if (key[h] == id[i]) return false;
+    used[h] = 1;
+    key[h] = id[i];
+  }
+  return true;
+}
+
+
+int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, int solver) {
+  if (!c) { err = "cluster is NULL"; return BA_E_ARG; }
+  const int C = c->n_cams, P = c->n_points, O = c->n_obs;
+  if (C < 1 || C > kMaxCams || P < 0 || O < 0) { err = "sizes out of range (1 <= n_cams <= 512)"; return BA_E_ARG; }
+  if (!c->R || !c->T || !c->k || !c->prior_R || !c->prior_T || !c->prior_sigma || !c->fixed ||
+      (P > 0 && !c->X) || (O > 0 && (!c->obs_cam || !c->obs_pt || !c->obs_uv))) {
+    err = "missing input array"; return BA_E_ARG;
+  }
+  if (c->max_iters < 1 || c->max_iters > 4096) { err = "max_iters must be in 1..4096"; return BA_E_ARG; }
+  if (!(c->sigma_px > 0) || !(c->huber_delta > 0) || !std::isfinite(c->sigma_px) || !std::isfinite(c->huber_delta) ||
+      !std::isfinite(c->f) || !std::isfinite(c->cx) || !std::isfinite(c->cy) || !(c->f > 0)) {
+    err = "bad camera or noise parameters"; return BA_E_ARG;
+  }
+  if (!finite_all(c->R, 9 * (size_t)C) || !finite_all(c->T, 3 * (size_t)C) || !finite_all(c->k, 2) ||
+      !finite_all(c->prior_R, 9 * (size_t)C) || !finite_all(c->prior_T, 3 * (size_t)C) ||
+      (P > 0 && !finite_all(c->X, 3 * (size_t)P)) || (O > 0 && !finite_all(c->obs_uv, 2 * (size_t)O))) {
+    err = "non-finite input"; return BA_E_ARG;
+  }
+  for (size_t i = 0; i < 6 * (size_t)C; ++i)
+    if (std::isnan(c->prior_sigma[i])) { err = "NaN prior sigma"; return BA_E_ARG; }
+  if (c->use_resident != 0 && c->use_resident != 1) { err = "use_resident must be 0 or 1"; return BA_E_ARG; }
+  if (c->fuse_resident != 0 && c->fuse_resident != 1) { err = "fuse_resident must be 0 or 1"; return BA_E_ARG; }
+  if (c->fuse_resident && !c->use_resident) { err = "fuse_resident needs use_resident"; return BA_E_ARG; }
+  if (c->use_resident) {
+    if (!c->cam_ids || (P > 0 && !c->point_ids)) { err = "use_resident needs cam_ids and point_ids"; return BA_E_ARG; }
+    if (!ids_unique(c->cam_ids, C)) { err = "duplicate camera ID in the cluster"; return BA_E_ARG; }
+    if (!ids_unique(c->point_ids, P)) { err = "duplicate point ID in the cluster"; return BA_E_ARG; }
+  }
+  s = Staged();
+  s.C = C; s.P = P; s.O = O;
+  if (c->use_resident) {
+    s.resident = true;
+    s.fuse = c->fuse_resident != 0;
+    s.cam_ids.assign(c->cam_ids, c->cam_ids + C);
+    s.point_ids.assign(c->point_ids, c->point_ids + P);
+    s.cam_nobs.assign(C, 0);
+    for (int o = 0; o < O; ++o)   // indices are range-checked below; count only valid ones here
+      if (c->obs_cam[o] >= 0 && c->obs_cam[o] < C) ++s.cam_nobs[c->obs_cam[o]];
+  }
+  s.max_iters = c->max_iters; s.stop_on_ftol = c->stop_on_ftol;
+  s.f = c->f; s.cx = c->cx; s.cy = c->cy; s.sigma = c->sigma_px; s.delta = c->huber_delta;
+  s.lambda0 = c->lambda0; s.ftol = c->ftol; s.k[0] = c->k[0]; s.k[1] = c->k[1];
+  s.cam_col.assign(C, -1);
+  for (int k = 0; k < C; ++k)
+    if (!c->fixed[k]) s.cam_col[k] = 6 * s.n_free++;
+  if (solver == BA_SOLVER_PCG) s.sparse = 1;
+  else if (solver == BA_SOLVER_AUTO) s.sparse = s.n_free > kMaxFreeCams;
+  else if (solver != BA_SOLVER_DENSE) { err = "unknown solver"; return BA_E_ARG; }
+  if (!s.sparse && s.n_free > kMaxFreeCams) { err = "more than BA_MAX_FREE_CAMS free cameras for the dense solver"; return BA_E_ARG; }
+  if (c->intr_mask & ~31) { err = "intr_mask has bits beyond k1, k2, f, cx, cy"; return BA_E_ARG; }
+  if (s.sparse && c->intr_mask) { err = "the PCG solver does not estimate intrinsics"; return BA_E_ARG; }
+  // the estimated intrinsics' columns follow the cameras', in bit order
+  int col = 6 * s.n_free;
+  for (int b = 0; b < kIntr; ++b)
+    if (c->intr_mask & (1 << b)) s.kcolt[b] = col++;
+  s.kcol0 = s.kcolt[0];
+  s.kcol1 = s.kcolt[1];
+  s.sc = (c->intr_mask & ~3) != 0;
+  s.m = col;
+  s.raw_cam.resize(30 * (size_t)C);
+  for (int k = 0; k < C; ++k) {
+    double* r = &s.raw_cam[30 * (size_t)k];
+    std::memcpy(r, c->R + 9 * k, 9 * sizeof(double));
+    std::memcpy(r + 9, c->T + 3 * k, 3 * sizeof(double));
+    std::memcpy(r + 12, c->prior_R + 9 * k, 9 * sizeof(double));
+    std::memcpy(r + 21, c->prior_T + 3 * k, 3 * sizeof(double));
+    std::memcpy(r + 24, c->prior_sigma + 6 * k, 6 * sizeof(double));
+  }
+  for (int o = 0; o < O; ++o) {
+    const int cam = c->obs_cam[o], pt = c->obs_pt[o];
+    if (cam < 0 || cam >= C || pt < 0 || pt >= P) { err = "observation index out of range"; return BA_E_ARG; }
+  }
+  // Internal point order: Morton (z-order) of the initial ground position, so
+  // that a camera's observations touch nearby point records.  Ties keep the
+  // caller's order (LSD radix sort of key << 32 | index on the key bits).
+  {
+    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+    for (int j = 0; j < P; ++j)
+      for (int t = 0; t < 2; ++t) {
+        lo[t] = std::min(lo[t], c->X[3 * (size_t)j + t]);
+        hi[t] = std::max(hi[t], c->X[3 * (size_t)j + t]);
+      }
+    std::vector<uint64_t> kj(P), tmp(P);
+    for (int j = 0; j < P; ++j) {
+      uint32_t q[2];
+      for (int t = 0; t < 2; ++t) {
+        const double span = hi[t] - lo[t];
+        const double u = span > 0 ? (c->X[3 * (size_t)j + t] - lo[t]) / span : 0.0;
+        q[t] = (uint32_t)std::min(65535.0, std::max(0.0, u * 65535.0));
+      }
+      uint32_t k = 0;
+      for (int b = 0; b < 16; ++b) k |= ((q[0] >> b) & 1u) << (2 * b) | ((q[1] >> b) & 1u) << (2 * b + 1);
+      kj[j] = (uint64_t)k << 32 | (uint32_t)j;
+    }
+    for (int shift = 32; shift < 64; shift += 11) {
+      size_t cnt_d[2049] = {0};
+      for (int j = 0; j < P; ++j) ++cnt_d[((kj[j] >> shift) & 2047u) + 1];
+      for (int d = 0; d < 2048; ++d) cnt_d[d + 1] += cnt_d[d];
+      for (int j = 0; j < P; ++j) tmp[cnt_d[(kj[j] >> shift) & 2047u]++] = kj[j];
+      kj.swap(tmp);
+    }
+    s.pt_orig.resize(P);
+    for (int n = 0; n < P; ++n) s.pt_orig[n] = (int)(uint32_t)kj[n];
+  }
+  std::vector<int> inv(P), opt(O);
+  for (int n = 0; n < P; ++n) inv[s.pt_orig[n]] = n;
+  for (int o = 0; o < O; ++o) opt[o] = inv[c->obs_pt[o]];
+  s.X.resize(3 * (size_t)P);
+  for (int n = 0; n < P; ++n)
+    for (int t = 0; t < 3; ++t) s.X[3 * (size_t)n + t] = c->X[3 * (size_t)s.pt_orig[n] + t];
+  // observations per point
+  std::vector<int> cnt(P + 1, 0);
+  for (int o = 0; o < O; ++o)
+    if (++cnt[opt[o] + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
+  for (int j = 0; j < P; ++j) cnt[j + 1] += cnt[j];
+  // observations in (point, camera) order: a counting sort by camera, then a
+  // stable one by point; then their camera, pixel and point in that order
+  std::vector<int> order(O);
+  {
+    std::vector<int> by_cam(O), cc(C + 1, 0);
+    for (int o = 0; o < O; ++o) ++cc[c->obs_cam[o] + 1];
+    for (int k = 0; k < C; ++k) cc[k + 1] += cc[k];
+    for (int o = 0; o < O; ++o) by_cam[cc[c->obs_cam[o]]++] = o;
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int t = 0; t < O; ++t) order[fill[opt[by_cam[t]]]++] = by_cam[t];
+  }
+  std::vector<int> scam(O), spt(O);
+  std::vector<double> suv(2 * (size_t)O);
+  for (int j = 0; j < P; ++j)
+    for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
+      const int o = order[t];
+      scam[t] = c->obs_cam[o];
+      spt[t] = j;
+      suv[2 * (size_t)t] = c->obs_uv[2 * (size_t)o];
+      suv[2 * (size_t)t + 1] = c->obs_uv[2 * (size_t)o + 1];
+      if (t > cnt[j] && scam[t] == scam[t - 1]) { err = "a camera observes one point twice"; return BA_E_ARG; }
+    }
+  // greedy packing into 64-lane chunks
+  std::vector<int> start(P, 0);
+  int pos = 0;
+  for (int j = 0; j < P; ++j) {
+    const int n = cnt[j + 1] - cnt[j];
+    if (n == 0) continue;
+    if ((pos % kWave) + n > kWave) pos = (int)align_up(pos, kWave);
+    start[j] = pos;
+    pos += n;
+  }
+  s.L = (int)align_up(pos, kWave);
+  s.n_chunks = s.L / kWave;
+  s.lane_pt.assign(s.L, -1);
+  // lane word: camera (9 bits) | segment start in the chunk << 9 (6 bits) |
+  // segment length << 15 (7 bits) | the chunk's longest segment << 22 (7 bits)
+  s.lane_meta.resize(s.L);
+  s.lane_uv.assign(2 * (size_t)s.L, 0.0);
+  for (int i = 0; i < s.L; ++i) s.lane_meta[i] = ((i % kWave) << 9) | (1 << 15);
+  std::vector<int> chunk_max(s.n_chunks, 1);
+  for (int j = 0; j < P; ++j) {
+    const int n = cnt[j + 1] - cnt[j];
+    for (int t = 0; t < n; ++t) {
+      const int so = cnt[j] + t, lane = start[j] + t;
+      s.lane_pt[lane] = j;
+      s.lane_meta[lane] = scam[so] | ((start[j] % kWave) << 9) | (n << 15);
+      chunk_max[lane / kWave] = std::max(chunk_max[lane / kWave], n);
+      s.lane_uv[2 * (size_t)lane] = suv[2 * (size_t)so];
+      s.lane_uv[2 * (size_t)lane + 1] = suv[2 * (size_t)so + 1];
+    }
+  }
+  for (int i = 0; i < s.L; ++i) s.lane_meta[i] |= chunk_max[i / kWave] << 22;
+  s.n_wg = (s.n_chunks + cpw - 1) / cpw;
+  const bool intr = s.m > 6 * s.n_free;   // an intrinsic is estimated
+  s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
+  s.nb = (s.m + kSolveTb - 1) / kSolveTb;
+  const int F = s.n_free;
+  std::vector<int> free_cam(F);
+  for (int k = 0; k < C; ++k)
+    if (s.cam_col[k] >= 0) free_cam[s.cam_col[k] / 6] = k;
+  // camera lanes and tasks: each free camera's observations in point order
+  std::vector<int> coff(F + 1, 0);
+  for (int t = 0; t < O; ++t) {
+    const int col = s.cam_col[scam[t]];
+    if (col >= 0) ++coff[col / 6 + 1];
+  }
+  for (int fi = 0; fi < F; ++fi) coff[fi + 1] += coff[fi];
+  std::vector<int> cobs(coff[F]);
+  {
+    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    for (int t = 0; t < O; ++t) {
+      const int col = s.cam_col[scam[t]];
+      if (col >= 0) cobs[fill[col / 6]++] = t;
+    }
+  }
+  for (int fi = 0; fi < F; ++fi) s.Lc += (int)align_up(coff[fi + 1] - coff[fi], kWave);
+  s.cl_pt.assign(s.Lc, -1);
+  s.cl_uv.assign(2 * (size_t)s.Lc, 0.0);
+  std::vector<I2> cam_range(F);
+  for (int fi = 0, base = 0; fi < F; ++fi) {
+    const int n = coff[fi + 1] - coff[fi];
+    for (int t = 0; t < n; ++t) {
+      const int so = cobs[coff[fi] + t];
+      const size_t lane = (size_t)base * kWave + t;
+      s.cl_pt[lane] = spt[so];
+      s.cl_uv[2 * lane] = suv[2 * (size_t)so];
+      s.cl_uv[2 * lane + 1] = suv[2 * (size_t)so + 1];
+    }
+    const int nch = (int)(align_up(n, kWave) / kWave);
+    cam_range[fi].x = (int)s.tasks.size();
+    for (int ch = 0; ch < nch; ch += cpt) s.tasks.push_back(mk4(TASK_CAM, free_cam[fi], 0, base + ch, std::min(cpt, nch - ch)));
+    cam_range[fi].y = (int)s.tasks.size();
+    base += nch;
+  }
+  s.n_cam_tasks = (int)s.tasks.size();
+  // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order;
+  // within a block the pairs (point, obs a, obs b) in point order
+  const int nblk = F * (F - 1) / 2;
+  auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
+  std::vector<int> poff(nblk + 1, 0);
+  for (int j = 0; j < P; ++j)
+    for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
+      const int ca = s.cam_col[scam[ta]];
+      if (ca < 0) continue;
+      for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
+        const int cb = s.cam_col[scam[tb]];
+        if (cb >= 0) ++poff[blk(ca / 6, cb / 6) + 1];
+      }
+    }
+  for (int b = 0; b < nblk; ++b) poff[b + 1] += poff[b];
+  std::vector<I3> pairs(poff[nblk]);
+  {
+    std::vector<int> fill(poff.begin(), poff.end() - 1);
+    for (int j = 0; j < P; ++j)
+      for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
+        const int ca = s.cam_col[scam[ta]];
+        if (ca < 0) continue;
+        for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
+          const int cb = s.cam_col[scam[tb]];
+          if (cb >= 0) pairs[fill[blk(ca / 6, cb / 6)]++] = I3{j, ta, tb};
+        }
+      }
+  }
+  auto blk_empty = [&](int b) { return poff[b + 1] == poff[b]; };
+  for (int b = 0; b < nblk; ++b) s.Lq += (int)align_up(poff[b + 1] - poff[b], kWave);
+  s.ql_pt.assign(s.Lq, -1);
+  s.ql_uv.assign(4 * (size_t)s.Lq, 0.0);
+  std::vector<I2> blk_range(nblk);
+  for (int fa = 0, base = 0; fa < F; ++fa)
+    for (int fb = fa + 1; fb < F; ++fb) {
+      const int b = blk(fa, fb), n = poff[b + 1] - poff[b];
+      for (int t = 0; t < n; ++t) {
+        const I3 pr = pairs[poff[b] + t];
+        const size_t lane = (size_t)base * kWave + t;
+        s.ql_pt[lane] = pr.x;
+        s.ql_uv[4 * lane] = suv[2 * (size_t)pr.y];
+        s.ql_uv[4 * lane + 1] = suv[2 * (size_t)pr.y + 1];
+        s.ql_uv[4 * lane + 2] = suv[2 * (size_t)pr.z];
+        s.ql_uv[4 * lane + 3] = suv[2 * (size_t)pr.z + 1];
+      }
+      const int nch = (int)(align_up(n, kWave) / kWave);
+      blk_range[b].x = (int)s.tasks.size();
+      for (int ch = 0; ch < nch; ch += cpt)
+        s.tasks.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], base + ch, std::min(cpt, nch - ch)));
+      blk_range[b].y = (int)s.tasks.size();
+      base += nch;
+    }
+  for (int fi = 0; fi < F; ++fi) s.targets.push_back(mk4(TASK_CAM, free_cam[fi], 0, cam_range[fi].x, cam_range[fi].y));
+  if (!s.sparse) {
+    for (int fa = 0; fa < F; ++fa)
+      for (int fb = fa + 1; fb < F; ++fb) {
+        const I2 r = blk_range[blk(fa, fb)];
+        s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
+      }
+    if (intr) s.targets.push_back(mk4(TARGET_INTR, 0, 0, 0, s.n_pt_part));
+    return BA_OK;
+  }
+  // Block CSR of the co-visible free-camera pairs.  Row fa lists its diagonal
+  // block, then the non-empty blocks (fa, fb) in increasing fb.  Each pair
+  // target writes its block and the transpose.
+  std::vector<std::vector<int>> nbr(F);
+  for (int fa = 0; fa < F; ++fa)
+    for (int fb = fa + 1; fb < F; ++fb)
+      if (!blk_empty(blk(fa, fb))) {
+        nbr[fa].push_back(fb);
+        nbr[fb].push_back(fa);
+      }
+  s.brow.assign(F + 1, 0);
+  std::vector<int> diag_slot(F);
+  std::map<std::pair<int, int>, int> slot_of;
+  for (int fa = 0; fa < F; ++fa) {
+    s.brow[fa] = (int)s.bcol.size();
+    diag_slot[fa] = (int)s.bcol.size();
+    s.bcol.push_back(fa);
+    std::sort(nbr[fa].begin(), nbr[fa].end());
+    for (int fb : nbr[fa]) {
+      slot_of[{fa, fb}] = (int)s.bcol.size();
+      s.bcol.push_back(fb);
+    }
+  }
+  s.brow[F] = (int)s.bcol.size();
+  for (int fi = 0; fi < F; ++fi) s.tslot.push_back(I2{diag_slot[fi], diag_slot[fi]});
+  for (int fa = 0; fa < F; ++fa)
+    for (int fb = fa + 1; fb < F; ++fb) {
+      if (blk_empty(blk(fa, fb))) continue;
+      const I2 r = blk_range[blk(fa, fb)];
+      s.targets.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], r.x, r.y));
+      s.tslot.push_back(I2{slot_of[{fa, fb}], slot_of[{fb, fa}]});
+    }
+  return BA_OK;
+}
+
+}  // namespace bagpu

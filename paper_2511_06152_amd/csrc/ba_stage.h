@@ -1,0 +1,72 @@
+// Host layout of a submitted cluster (no HIP: also built alone for the host
+// tests under the sanitizers).  Validates a ba_cluster and builds the work
+// lists the kernels read: point lanes, camera lanes, pair lanes, tasks and
+// reduction targets, the Morton point order, and for the conjugate-gradient
+// solve the block-CSR structure of the reduced camera system.  Not part of
+// the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_consts.h"
+
+namespace bagpu {
+
+// Plain integer tuples with the layout of HIP's int2 / int3 / int4 (they are
+// uploaded as such).
+struct I2 { int x, y; };
+struct I3 { int x, y, z; };
+struct I4 { int x, y, z, w; };
+
+// A submitted cluster, laid out for the device.
+struct Staged {
+  int C = 0, P = 0, O = 0, L = 0, n_chunks = 0, m = 0, n_free = 0, kcol0 = -1, kcol1 = -1;
+  int kcolt[kIntr] = {-1, -1, -1, -1, -1}, sc = 0;   // column of each intrinsic; f, cx or cy estimated
+  int max_iters = 0, stop_on_ftol = 0;
+  double f = 0, cx = 0, cy = 0, sigma = 1, delta = 1, lambda0 = 1e-4, ftol = 0, k[2] = {0, 0};
+  std::vector<double> raw_cam;   // [C][30]
+  std::vector<double> X;         // [3P] internal point order
+  std::vector<int> pt_orig;      // [P] caller index of each internal point
+  std::vector<int> cam_col;      // [C]
+  std::vector<int> lane_pt, lane_meta;
+  std::vector<double> lane_uv;   // [2L]
+  int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
+  std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
+  std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
+  std::vector<I4> tasks, targets;
+  // sparse (PCG) reduced system: block CSR over the free cameras, diagonal first
+  int sparse = 0;
+  std::vector<int> brow, bcol;   // [F + 1], [nnzb]
+  std::vector<I2> tslot;         // [n_targets] block slots (a,b), (b,a) of each target
+  // resident state: global IDs (caller order) when the cluster uses it;
+  // observations per camera (the match-count weights of Eq. 8 fusion)
+  bool resident = false, fuse = false;
+  std::vector<int64_t> cam_ids, point_ids;
+  std::vector<int> cam_nobs;
+};
+
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// splitmix64 finaliser: spreads IDs over a power-of-two table.
+uint64_t mix_id(int64_t id);
+
+// True when the n IDs are pairwise distinct.
+bool ids_unique(const int64_t* id, int n);
+
+// Validates the cluster and builds its work lists (integer bookkeeping only):
+//  * point lanes: observations sorted by (point, camera), packed greedily into
+//    64-lane chunks so that no point's observations straddle a chunk;
+//  * camera lanes: observations of each free camera in point order, each
+//    camera's run padded to whole chunks, cut into tasks of <= cpt chunks;
+//  * pair lanes: the observation pairs of each point whose two cameras are
+//    free, grouped by camera pair, padded and cut into tasks likewise;
+//  * reduction targets: each free camera, each camera pair, the intrinsics.
+// Returns BA_OK, or BA_E_ARG with the reason in err.
+int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, int solver);
+
+}  // namespace bagpu

@@ -168,3 +168,87 @@ def test_global_400_cams_full_size():
     assert abs(log[-1] - e3) <= 1e-11 * e3
     assert np.all(np.diff(log) < 0)
     assert got["accepted"] == 3
+
+
+# ---- the whole flight at full size against the oracle's stored states -----------------
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def read_golden(iters):
+    """The oracle's state of scene_global(5) after `iters` iterations
+    (tests/golden/make_global_solution.py): R [C,3,3], T [C,3], sampled point
+    indices and positions, and the final cost."""
+    path = f"{GOLDEN}/global_400cams_seed5_iter{iters}.txt"
+    cams, pts, meta, part = [], [], {}, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                if line.startswith("# iterations"):
+                    tok = line[1:].split()
+                    meta = {tok[i]: float(tok[i + 1]) for i in range(0, len(tok) - 1, 2)}
+                part = "pts" if "points:" in line else ("cams" if "cameras:" in line else part)
+                continue
+            (cams if part == "cams" else pts).append([float(x) for x in line.split()])
+    cams, pts = np.array(cams), np.array(pts)
+    return {"R": cams[:, :9].reshape(-1, 3, 3), "T": cams[:, 9:12], "idx": pts[:, 0].astype(np.int64),
+            "X": pts[:, 1:4], "iterations": int(meta["iterations"]), "cost": meta["final_cost"]}
+
+
+_GLOBAL = {}
+
+
+def global_scene():
+    if "sc" not in _GLOBAL:
+        _GLOBAL["sc"] = A.scene_global(5)
+    return _GLOBAL["sc"]
+
+
+def errors_vs_golden(sc, got, g):
+    """Every camera, and the predicted pixels of every observation of the
+    stored sample of points (their observations' cameras and points)."""
+    sel = np.isin(sc["obs_pt"], g["idx"])
+    X = np.array(got["X"], copy=True)
+    X_ref = np.array(got["X"], copy=True)
+    X_ref[g["idx"]] = g["X"]
+    oc, op = sc["obs_cam"][sel], sc["obs_pt"][sel]
+    d = A.project_obs(got["R"], got["T"], X, (0.0, 0.0), oc, op) - A.project_obs(g["R"], g["T"], X_ref, (0.0, 0.0), oc, op)
+    rms = float(np.sqrt((d ** 2).sum(1).mean()))
+    M = np.einsum("cji,cjk->cik", got["R"], g["R"])
+    v = 0.5 * np.stack([M[:, 2, 1] - M[:, 1, 2], M[:, 0, 2] - M[:, 2, 0], M[:, 1, 0] - M[:, 0, 1]], 1)
+    att = float(np.max(np.arctan2(np.linalg.norm(v, axis=1), 0.5 * (np.trace(M, axis1=1, axis2=2) - 1.0))))
+    dT = float(np.abs(got["T"] - g["T"]).max())
+    dX = float(np.abs(got["X"][g["idx"]] - g["X"]).max())
+    return rms, dT, att, dX, int(sel.sum())
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-12), (MIXED, 1e-6)])
+def test_global_400_cams_tight_pcg_matches_oracle_state(precision, tol):
+    """Full size (400 cameras, 800k points, 3.5M observations), 20 LM
+    iterations with a tight PCG tolerance, so that the GPU follows the exact
+    LM's steps: against the oracle's state after 20 iterations (dense FP64
+    Schur complement and Cholesky, m = 2400).  FP64: cost within 1e-8,
+    cameras within 1e-8 rad and 1e-6 m, sampled points within 1e-5 m.
+    Mixed: the mixed-path bars (1e-3 px RMS over every observation of 5000
+    sampled points, 1 mm, 2e-6 rad)."""
+    from paper_2511_06152_amd import Context
+    from paper_2511_06152_amd.ba import Cluster
+    g = read_golden(20)
+    sc = global_scene()
+    print("case global full size tight PCG, precision", precision, flush=True)
+    with Context(precision=precision, max_slots=2, hbm_budget_bytes=3 << 30, pcg_tol=tol,
+                 pcg_max_iters=20000) as ctx:
+        t = ctx.ba_submit_cluster(Cluster(sc, max_iters=g["iterations"]))
+        ctx.ba_step(t, g["iterations"])
+        got = ctx.ba_fetch(t)
+    rms, dT, att, dX, n_obs = errors_vs_golden(sc, got, g)
+    e = got["cost_log"][-1]
+    print(f"global vs oracle after {g['iterations']}: rms {rms:.3e} px over {n_obs} observations, centres {dT:.3e} m, "
+          f"attitude {att:.3e} rad, points {dX:.3e} m; cost {e:.12g} vs {g['cost']:.12g}; cg {got['cg_iters']}",
+          flush=True)
+    assert got["iterations"] == g["iterations"] and got["accepted"] == g["iterations"]
+    if precision == FP64:
+        assert abs(e - g["cost"]) <= 1e-8 * g["cost"]
+        assert att < 1e-8 and dT < 1e-6 and dX < 1e-5
+    else:
+        assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
