@@ -341,6 +341,12 @@ size_t ba_footprint(ba_ctx* ctx, const ba_cluster* cluster);
  * the counters.  The Schur-block tasks are one launch in BA_MIXED (timed as
  * BA_PROF_BLOCKS; BA_PROF_PAIRBLK then marks an empty interval) and two in
  * BA_FP64 (camera tasks as BA_PROF_BLOCKS, pair tasks as BA_PROF_PAIRBLK).
+ * When the batch holds self-calibrating clusters, the point, block and
+ * back-substitution kernels run as two launches each (ordinary clusters,
+ * then self-calibrating ones); the slot's time then runs from the start of
+ * the first to the end of the second.  BA_PROF_PCG runs from before the first
+ * conjugate-gradient launch of the iteration to after the last (one
+ * cooperative launch per such cluster).
  * Errors: BA_E_ARG, BA_E_DEVICE. */
 enum ba_prof_kernel { BA_PROF_POINT = 0, BA_PROF_BLOCKS = 1, BA_PROF_PAIRBLK = 2, BA_PROF_REDUCE = 3,
                       BA_PROF_SOLVE = 4, BA_PROF_BACKSUB = 5, BA_PROF_LM = 6, BA_PROF_PCG = 7,

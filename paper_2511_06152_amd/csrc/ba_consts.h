@@ -27,6 +27,7 @@ constexpr int kSolveTbVals = kSolveTb * (kSolveTb + 1);   // doubles per block (
 constexpr int kCgThreads = 256;           // threads per workgroup of the conjugate-gradient solve
 constexpr int kCgWaves = kCgThreads / kWave;
 constexpr int kMaxCgWG = 128;             // workgroups of one cluster's conjugate-gradient solve, at most
+constexpr int kCgMaxRows = kCgThreads / 6;   // block rows of one conjugate-gradient workgroup, at most
 constexpr int kSbRow = 8;                 // sparse reduced-system block: 6 rows padded to 8 values
 constexpr int kSbVals = 6 * kSbRow;       //   (16-byte aligned rows for vector loads)
 // Work items of the block-assembly kernel (one wavefront each) and of its

@@ -67,8 +67,9 @@ struct SlotDesc {
   const int2* tslot;                      // [n_targets] block slots of a target: (a,b) and (b,a)
   double* Sblk;                           // [nnzb][6][kSbRow] FP64 blocks, row-major, rows padded
   float* Sblk32;                          // [nnzb][6][kSbRow] FP32 copy for the mixed-precision products
-  double* pcgw;                           // [5m + 8 kMaxCgWG] PCG work: gradient with priors, clamped
-                                          //   diagonal, z, p (two buffers), workgroup parts of the sums
+  double* pcgw;                           // [7m + 20 kMaxCgWG + 8] PCG work: gradient with priors, clamped
+                                          //   diagonal, z_0, u and z (two buffers each), workgroup parts of the sums
+                                          //   (set-up and final; CG steps, two buffers), barrier words
   const int* pcg_part;                    // [pcg_G + 1] first block row of each PCG workgroup
   int pcg_G, pcg_rows_max;                // PCG workgroups; most block rows of one of them
   int pcg_smem, pad3;                     // dynamic LDS bytes of the PCG launch
@@ -136,7 +137,8 @@ hipError_t launch_initial_cost(const Batch& b, hipStream_t st);
 hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent_t* ev = nullptr, int timed = 0,
                             const SparseLaunch* sp = nullptr, int n_sp = 0);
 // Dynamic LDS bytes of the conjugate-gradient launch of a cluster: its
-// workgroups' largest block range (bytes), m and F.
+// workgroups' largest block range (bytes: block values and block columns),
+// m and F.
 size_t pcg_lds_bytes(size_t block_bytes, int m, int F, int rows_max);
 hipError_t launch_export(const Batch& b, int max_P, hipStream_t st);
 // Writes the exported state of the batch's clusters back to the resident

@@ -1766,38 +1766,61 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
 // whole solve (in mixed mode the FP32 copy: FP32 products and accumulation;
 // dot products, the preconditioner and the updates are FP64).  Thread t of a
 // workgroup owns block row r0 + t (x, r in registers, its preconditioner
-// block in LDS).  Each CG step has two grid barriers:
-//   A: every workgroup has rebuilt the whole direction p = z + beta p_prev
-//      (from z and the previous p in global memory: each workgroup computes
-//      all of it the same way), multiplied its rows, and posted its part of
-//      p.Ap;
-//   B: every workgroup has updated its rows of x, r, z and posted its parts
-//      of r.r and r.z.
-// Every workgroup adds the G parts in workgroup order, so all of them take
-// the same decisions; sums inside a workgroup have a fixed order too.
+// block in LDS; at most kCgMaxRows rows, so the owners are in wavefront 0
+// and every scalar row of S p has a thread).  Every
+// workgroup keeps the entries of the direction p that its rows' blocks
+// multiply (its halo: the block columns of its blocks) in LDS, updated the
+// same way in every workgroup.
+//
+// One grid barrier per CG step.  With q = S p and u = M^-1 q, step i needs
+// p.q and r.z, and the next step's scalars follow from sums over vectors
+// that are known before the step's update x += alpha p, r -= alpha q,
+// z -= alpha u:
+//   r'.r' = r.r - 2 alpha r.q + alpha^2 q.q,
+//   r'.z' = r.z - 2 alpha q.z + alpha^2 q.u     (r.u = q.z: M symmetric).
+// So the owners post their parts of p.q, r.q, q.q, q.z, q.u, r.r, r.z
+// (summed over wavefront 0) and their rows of z = M^-1 r (recomputed from r
+// every step) and u, together; after the barrier every wavefront of every
+// workgroup adds the G parts by the same butterfly (all take the same
+// decisions), the owners update their rows of x and r, and every workgroup
+// forms its halo of the next p from z and u.  r.r and r.z are taken fresh
+// from the vectors each step and z is recomputed from r, so the expansions
+// only carry one step's rounding (of order eps times the step's r.r and
+// r.z), never an error accumulated from earlier steps.  The (z, u) pairs and
+// the parts are double-buffered by step parity: a workgroup posts step i + 1
+// only after the barrier of step i, which every workgroup reaches only after
+// reading what step i - 1 posted.
 
 namespace cg = cooperative_groups;
 
-// entries of the direction each thread rebuilds: m <= 6 * kMaxCams
-constexpr int kCgPerThread = (6 * kMaxCams + kCgThreads - 1) / kCgThreads;
+constexpr int kCgSums = 7;                // p.q, r.q, q.q, q.z, q.u, r.r, r.z
+constexpr int kCgPartStride = 8;          // doubles per workgroup part (7 used)
+constexpr long kCgSpinCap = 1L << 22;     // polls before a barrier wait gives up (seconds)
 
-// Sums over the workgroup in a fixed order (two values at once).
-__device__ __forceinline__ double2 wg_sum2(double a, double b, double* red, int tid) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  __syncthreads();
-  if ((tid % kWave) == 0) {
-    red[tid / kWave] = a;
-    red[kCgWaves + tid / kWave] = b;
-  }
-  __syncthreads();
-  double2 t = make_double2(0.0, 0.0);
+// Sums over the workgroup in a fixed order (N values at once); every thread
+// gets the sums.
+template <int N>
+__device__ __forceinline__ void wg_sum(double v[N], double* red, int tid) {
 #pragma unroll
-  for (int w = 0; w < kCgWaves; ++w) {
-    t.x += red[w];
-    t.y += red[kCgWaves + w];
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if ((tid % kWave) == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[i * kCgWaves + tid / kWave] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCgWaves; ++w) t += red[i * kCgWaves + w];
+    v[i] = t;
   }
-  return t;
+}
+
+__device__ __forceinline__ double2 wg_sum2(double a, double b, double* red, int tid) {
+  double v[2] = {a, b};
+  wg_sum<2>(v, red, tid);
+  return make_double2(v[0], v[1]);
 }
 
 // Parts of the G workgroups, added in workgroup order (every thread the same sums).
@@ -1809,6 +1832,37 @@ __device__ __forceinline__ double2 grid_sum2(const double2* __restrict__ parts, 
     t.y += v.y;
   }
   return t;
+}
+
+// Grid barrier of the conjugate-gradient launch: a counter that only grows
+// (across launches too, wrapping at 2^32).  A workgroup arrives by adding 1
+// (release at agent scope: its earlier global writes become visible to any
+// workgroup that then acquires) and waits, acquiring, until the counter has
+// passed `target` (the launch's base plus G per barrier).  Every workgroup of
+// a cooperative launch is resident and passes the same barriers, so every
+// wait ends.  As a guard all the same, a wait that has not ended after
+// kCgSpinCap polls raises the launch's abort word, and every wait returns
+// false as soon as it sees that word set: the whole grid then leaves early
+// (the solve is reported failed) instead of waiting on a missing workgroup.
+__device__ __forceinline__ bool cg_barrier(unsigned* ctr, unsigned target, unsigned* abort_word, int* ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long n = 0;
+    while ((int)(__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        *ok = 0;
+        break;
+      }
+      if (++n > kCgSpinCap) {
+        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *ok = 0;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  return *ok != 0;
 }
 
 // z = Li^T Li r for one 6x6 block (Li: packed lower triangle, row-major).
@@ -1830,58 +1884,74 @@ __device__ __forceinline__ void pcg_precond(const double* Li, const double r[6],
   }
 }
 
-// Rows q of this workgroup's S p (q local: block row q / 6, row q % 6 of
-// it), blocks and p from LDS; returns this thread's part of p.Ap.  p is read
-// in the product's precision: FP32 copy [F][8] (mixed) or FP64 [m].
+// This workgroup's rows of S p from LDS: its blocks Sl, its block-row
+// starts brl and block columns bcl (both relative to its first block), and p
+// (read in the product's precision: FP32 copy [F][8] in mixed mode, FP64 [m]
+// otherwise).  spt adjacent lanes (1, 2 or 4; 6 nr spt <= kCgThreads) share
+// a scalar row q (local: block row q / 6, row q % 6 of it), each taking every
+// spt-th block, and add their parts by a fixed butterfly; the first of them
+// writes Apl[q].
 template <typename B, int PS>
-__device__ __forceinline__ double cg_spmv(const B* __restrict__ Sl, const int* __restrict__ brow,
-                                          const int* __restrict__ bcol, int r0, int nr, int k0, const B* pB,
-                                          const double* pl, double* Apl, int tid) {
-  double pap = 0.0;
-  for (int q = tid; q < 6 * nr; q += kCgThreads) {
+__device__ __forceinline__ void cg_spmv(const B* __restrict__ Sl, const int* __restrict__ brl,
+                                        const int* __restrict__ bcl, int nr, int spt, const B* pB, double* Apl,
+                                        int tid) {
+  const int q = tid / spt, j = tid % spt;
+  B acc = B(0);
+  if (q < 6 * nr) {
     const int bl = q / 6, r = q % 6;
-    const int ka = brow[r0 + bl], kb = brow[r0 + bl + 1];
-    B acc = B(0);
-    for (int k = ka; k < kb; ++k) {
-      const B* row = Sl + kSbVals * (size_t)(k - k0) + kSbRow * r;
-      const B* pp = pB + PS * bcol[k];
+    const int ka = brl[bl], kb = brl[bl + 1];
+    for (int k = ka + j; k < kb; k += spt) {
+      const B* row = Sl + kSbVals * (size_t)k + kSbRow * r;
+      const B* pp = pB + PS * bcl[k];
 #pragma unroll
       for (int cc = 0; cc < 6; ++cc) acc = fm(row[cc], pp[cc], acc);
     }
-    const double a = (double)acc;
-    Apl[q] = a;
-    pap = fm(a, pl[6 * r0 + q], pap);
   }
-  return pap;
+  for (int off = 1; off < spt; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+  if (q < 6 * nr && j == 0) Apl[q] = (double)acc;
 }
 
 __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
   extern __shared__ __attribute__((aligned(16))) double sv[];
   __shared__ double red[2 * kCgWaves];
-  __shared__ int own_cam[kCgThreads];
+  __shared__ int own_cam[kWave];
+  __shared__ int brl[kWave + 1];
+  __shared__ int hmark[kMaxCams];
+  __shared__ int hcol[kMaxCams];
+  __shared__ int n_halo;
+  __shared__ unsigned bar_base;
+  __shared__ int bar_ok;
   const SlotDesc& d = bt.desc[s];
   SlotCtl& c = bt.ctl[s];
   // read by every workgroup before anything is written: the same decision everywhere
   if (c.status != ST_RUNNING || !d.sparse) return;
   cg::grid_group grid = cg::this_grid();
   const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
+  const int lane = tid % kWave;
   const int F = d.n_free, m = d.m;
-  const int r0 = d.pcg_part[wg], r1 = d.pcg_part[wg + 1], nr = r1 - r0;
+  const int r0 = d.pcg_part[wg], r1 = d.pcg_part[wg + 1], nr = r1 - r0;   // nr <= kCgMaxRows
   const int* const brow = d.brow;
   const int* const bcol = d.bcol;
   const int k0 = brow[r0], nblk = brow[r1] - k0;
   const bool mixed = d.mixed != 0;
-  // global work: gradient with priors, clamped diagonal, z, p (two buffers),
-  // the workgroups' parts of the sums, FP32 copy of p
+  const int spt = 6 * nr * 4 <= kCgThreads ? 4 : 6 * nr * 2 <= kCgThreads ? 2 : 1;
+  // global work: gradient with priors, clamped diagonal, z_0, (z, u) pairs
+  // (two buffers), the set-up and final parts, the CG parts (two buffers),
+  // the barrier words
   double* gv = d.pcgw;
   double* Dv = gv + m;
   double* zg = Dv + m;
-  double* pg = zg + m;
-  double2* part = reinterpret_cast<double2*>(pg + 2 * m);    // [4][kMaxCgWG]
-  // LDS: this workgroup's blocks, the whole p (FP64, and FP32 in mixed mode),
-  // its rows of S p, its preconditioner blocks
+  double2* zug = reinterpret_cast<double2*>(zg + m);               // [2][m]
+  double2* part = zug + 2 * m;                                      // [2][kMaxCgWG]
+  double* cgp = reinterpret_cast<double*>(part + 2 * kMaxCgWG);    // [2][kMaxCgWG][kCgPartStride]
+  unsigned* ctr = reinterpret_cast<unsigned*>(cgp + 2 * kMaxCgWG * kCgPartStride);
+  unsigned* abort_word = ctr + 1;
+  // LDS: this workgroup's blocks and their block columns, p (FP64, and FP32
+  // in mixed mode; only the halo entries are kept), its rows of S p, its
+  // preconditioner blocks
   const size_t sbytes = (mixed ? sizeof(float) : sizeof(double)) * kSbVals * (size_t)nblk;
-  double* pl = sv + (sbytes + 7) / 8;
+  int* bcl = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(sv) + sbytes);
+  double* pl = sv + (sbytes + sizeof(int) * (size_t)nblk + 7) / 8;
   float* p32l = reinterpret_cast<float*>(pl + m);
   double* Apl = pl + m + 4 * F;
   double* Lf = Apl + 6 * d.pcg_rows_max;
@@ -1889,15 +1959,41 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
   const double* S64l = sv;
   const double lambda = c.lambda;
   const int cur = c.cur;
+  if (tid == 0) {
+    // no workgroup arrives at a CG barrier or reads the abort word before the
+    // set-up grid barrier below
+    bar_base = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bar_ok = 1;
+    if (wg == 0) __hip_atomic_store(abort_word, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   for (int k = tid; k < nr; k += kCgThreads) own_cam[k] = -1;
+  for (int k = tid; k <= nr; k += kCgThreads) brl[k] = brow[r0 + k] - k0;
+  for (int k = tid; k < F; k += kCgThreads) hmark[k] = 0;
   __syncthreads();
+  for (int k = tid; k < nblk; k += kCgThreads) {
+    const int col = bcol[k0 + k];
+    bcl[k] = col;
+    hmark[col] = 1;
+  }
   for (int k = tid; k < d.C; k += kCgThreads) {
     const int col = d.cam_col[k];
     if (col >= 0 && col / 6 >= r0 && col / 6 < r1) own_cam[col / 6 - r0] = k;
   }
   __syncthreads();
+  // the halo, in increasing block column (wavefront 0 compacts the marks)
+  if (tid < kWave) {
+    int n = 0;
+    for (int f0 = 0; f0 < F; f0 += kWave) {
+      const int f = f0 + lane;
+      const bool on = f < F && hmark[f] != 0;
+      const unsigned long long bits = __ballot(on);
+      if (on) hcol[n + __popcll(bits & ((1ull << lane) - 1ull))] = f;
+      n += __popcll(bits);
+    }
+    if (lane == 0) n_halo = n;
+  }
   // Owner set-up: priors and damping into the diagonal block, preconditioner,
-  // right-hand side, z = M^-1 r = p_0.
+  // right-hand side, z_0 = M^-1 r_0 (= p_0).
   const bool own = tid < nr;
   double xr[6], rr[6];
   double part_rr = 0.0, part_rz = 0.0, fails = 0.0;
@@ -1958,7 +2054,6 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
       zg[col + a] = z[a];
-      pg[col + a] = z[a];
       part_rr = fm(rr[a], rr[a], part_rr);
       part_rz = fm(rr[a], z[a], part_rz);
     }
@@ -1989,8 +2084,15 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
     if (wg == 0 && tid == 0) c.solve_ok = 0;
     return;
   }
+  const int nh6 = 6 * n_halo;
+  // the halo of p_0 = z_0 into LDS
+  for (int e = tid; e < nh6; e += kCgThreads) {
+    const int q = 6 * hcol[e / 6] + e % 6;
+    const double v = zg[q];
+    pl[q] = v;
+    if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
+  }
   const double bnorm = sqrt(s0.x);
-  double rz = s0.y, beta = 0.0;
   const int max_it = d.pcg_max_iters;
   // Forcing term of the inexact step: |r| <= eta |b| with
   // eta = min(pcg_tol, sqrt(|b| / |b_0|)), |b_0| the first solve's right-hand
@@ -1998,77 +2100,108 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
   // while the early steps stay cheap.
   const double b0 = c.cg_b0 > 0.0 ? c.cg_b0 : bnorm;
   const double tol = b0 > 0.0 ? fmin(d.pcg_tol, sqrt(bnorm / b0)) : d.pcg_tol;
+  const unsigned base = bar_base;
   bool good = true;
   int it = 0;
   for (; it < max_it && bnorm > 0.0;) {
-    // the whole direction p_it = z + beta p_(it-1) (p_0 = z), the same in every
-    // workgroup; all of a thread's loads are issued before any store (the
-    // stores could alias them as far as the compiler knows)
-    const double* pprev = pg + (size_t)((it + 1) & 1) * m;
-    double* pnew = pg + (size_t)(it & 1) * m;
-    {
-      double zv[kCgPerThread], pv[kCgPerThread];
+    __syncthreads();
+    // q = S p for this workgroup's rows
+    if (mixed) cg_spmv<float, kSbRow>(S32l, brl, bcl, nr, spt, p32l, Apl, tid);
+    else cg_spmv<double, 6>(S64l, brl, bcl, nr, spt, pl, Apl, tid);
+    __syncthreads();
+    // owners (wavefront 0): z = M^-1 r, u = M^-1 q, their rows of (z, u),
+    // their parts of p.q, r.q, q.q, q.z, q.u, r.r, r.z summed over the wavefront
+    double2* zub = zug + (size_t)(it & 1) * m;
+    double* pb = cgp + (size_t)(it & 1) * kMaxCgWG * kCgPartStride;
+    double pown[6], qown[6];
+    if (tid < kWave) {
+      double sums[kCgSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (own) {
+        const int col = 6 * (r0 + tid);
+        double u[6], z[6];
 #pragma unroll
-      for (int u = 0; u < kCgPerThread; ++u) {
-        const int q = tid + u * kCgThreads;
-        zv[u] = q < m ? zg[q] : 0.0;
-        pv[u] = (q < m && it > 0) ? pprev[q] : 0.0;
-      }
+        for (int a = 0; a < 6; ++a) {
+          qown[a] = Apl[6 * tid + a];
+          pown[a] = pl[col + a];
+        }
+        pcg_precond(Lf + 21 * tid, qown, u);
+        pcg_precond(Lf + 21 * tid, rr, z);
 #pragma unroll
-      for (int u = 0; u < kCgPerThread; ++u) {
-        const int q = tid + u * kCgThreads;
-        if (q < m) {
-          const double v = it == 0 ? zv[u] : fm(beta, pv[u], zv[u]);
-          pl[q] = v;
-          if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
-          if (it > 0 && q / 6 >= r0 && q / 6 < r1) pnew[q] = v;
+        for (int a = 0; a < 6; ++a) {
+          zub[col + a] = make_double2(z[a], u[a]);
+          sums[0] = fm(pown[a], qown[a], sums[0]);
+          sums[1] = fm(rr[a], qown[a], sums[1]);
+          sums[2] = fm(qown[a], qown[a], sums[2]);
+          sums[3] = fm(qown[a], z[a], sums[3]);
+          sums[4] = fm(qown[a], u[a], sums[4]);
+          sums[5] = fm(rr[a], rr[a], sums[5]);
+          sums[6] = fm(rr[a], z[a], sums[6]);
         }
       }
+#pragma unroll
+      for (int i = 0; i < kCgSums; ++i) sums[i] = wave_sum(sums[i]);
+      if (lane == 0) {
+        double2* dst = reinterpret_cast<double2*>(pb + kCgPartStride * wg);
+        dst[0] = make_double2(sums[0], sums[1]);
+        dst[1] = make_double2(sums[2], sums[3]);
+        dst[2] = make_double2(sums[4], sums[5]);
+        dst[3] = make_double2(sums[6], 0.0);
+      }
     }
-    __syncthreads();
-    const double pap_part = mixed ? cg_spmv<float, kSbRow>(S32l, brow, bcol, r0, nr, k0, p32l, pl, Apl, tid)
-                                  : cg_spmv<double, 6>(S64l, brow, bcol, r0, nr, k0, pl, pl, Apl, tid);
-    {
-      const double t = wg_sum2(pap_part, 0.0, red, tid).x;
-      if (tid == 0) part[2 * kMaxCgWG + wg] = make_double2(t, 0.0);
-    }
-    grid.sync();
-    const double pAp = grid_sum2(part + 2 * kMaxCgWG, G).x;
     ++it;
+    if (!cg_barrier(ctr, base + (unsigned)it * (unsigned)G, abort_word, &bar_ok)) {
+      good = false;
+      break;
+    }
+    // every wavefront: the G parts, added by the same butterfly everywhere
+    // (lane l takes parts l and l + 64)
+    double t[kCgSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < kMaxCgWG / kWave; ++h) {
+      const int w = lane + h * kWave;
+      if (w < G) {
+        const double2* src = reinterpret_cast<const double2*>(pb + kCgPartStride * w);
+        const double2 v0 = src[0], v1 = src[1], v2 = src[2], v3 = src[3];
+        t[0] += v0.x;
+        t[1] += v0.y;
+        t[2] += v1.x;
+        t[3] += v1.y;
+        t[4] += v2.x;
+        t[5] += v2.y;
+        t[6] += v3.x;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kCgSums; ++i) t[i] = wave_sum(t[i]);
+    const double pAp = t[0], rz = t[6];
     if (!(pAp > 0.0) || !isfinite(pAp)) {
       good = false;
       break;
     }
     const double alpha = rz / pAp;
-    part_rr = part_rz = 0.0;
+    const double rr_new = fmax(fm(alpha * alpha, t[2], fm(-2.0 * alpha, t[1], t[5])), 0.0);
+    const double rz_new = fm(alpha * alpha, t[4], fm(-2.0 * alpha, t[3], rz));
     if (own) {
-      const int col = 6 * (r0 + tid);
-      double z[6];
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
-        xr[a] = fm(alpha, pl[col + a], xr[a]);
-        rr[a] = fm(-alpha, Apl[6 * tid + a], rr[a]);
-      }
-      pcg_precond(Lf + 21 * tid, rr, z);
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        zg[col + a] = z[a];
-        part_rr = fm(rr[a], rr[a], part_rr);
-        part_rz = fm(rr[a], z[a], part_rz);
+        xr[a] = fm(alpha, pown[a], xr[a]);
+        rr[a] = fm(-alpha, qown[a], rr[a]);
       }
     }
-    {
-      const double2 t = wg_sum2(part_rr, part_rz, red, tid);
-      if (tid == 0) part[3 * kMaxCgWG + wg] = t;
+    if (sqrt(rr_new) <= tol * bnorm) break;
+    const double beta = rz_new / rz;
+    // the halo of the next p = (z - alpha u) + beta p, the same in every workgroup
+    for (int e = tid; e < nh6; e += kCgThreads) {
+      const int q = 6 * hcol[e / 6] + e % 6;
+      const double2 zu = zub[q];
+      const double v = fm(beta, pl[q], fm(-alpha, zu.y, zu.x));
+      pl[q] = v;
+      if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
     }
-    grid.sync();
-    const double2 s1 = grid_sum2(part + 3 * kMaxCgWG, G);
-    if (sqrt(s1.x) <= tol * bnorm) break;
-    beta = s1.y / rz;
-    rz = s1.y;
   }
   if (!good) {
-    if (wg == 0 && tid == 0) c.solve_ok = 0;
+    // the same decision in every workgroup (a failed pAp), or an abandoned wait
+    if (tid == 0) c.solve_ok = 0;
     return;
   }
   // Solution, predicted camera-side reduction, trial cameras and their prior
@@ -2109,7 +2242,11 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
     const double2 t = wg_sum2(part_pred, pc, red, tid);
     if (tid == 0) part[wg] = t;
   }
-  grid.sync();
+  // every workgroup has passed the same `it` CG barriers
+  if (!cg_barrier(ctr, base + (unsigned)(it + 1) * (unsigned)G, abort_word, &bar_ok)) {
+    if (tid == 0) c.solve_ok = 0;
+    return;
+  }
   if (wg == 0 && tid == 0) {
     const double2 t = grid_sum2(part, G);
     c.pred_c = t.x;
@@ -2488,6 +2625,23 @@ void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, hipEve
   else hipLaunchKernelGGL(kernel, grid, block, smem, st, b);
 }
 
+// Launches the ordinary instantiation of a kernel and, when `sc`, the
+// self-calibrating one right after it (each skips the other kind of cluster).
+// With events, the slot spans both: the first dispatch records the start, the
+// last the end.
+template <typename K1, typename K2>
+void launch_both(K1 k1, K2 k2, bool sc, dim3 grid, dim3 block, size_t smem1, size_t smem2, hipStream_t st,
+                 hipEvent_t* ev, int slot, const Batch& b) {
+  if (!sc) return launch(k1, grid, block, smem1, st, ev, slot, b);
+  if (!ev) {
+    hipLaunchKernelGGL(k1, grid, block, smem1, st, b);
+    hipLaunchKernelGGL(k2, grid, block, smem2, st, b);
+    return;
+  }
+  hipExtLaunchKernelGGL(k1, grid, block, (uint32_t)smem1, st, ev[2 * slot], nullptr, 0, b);
+  hipExtLaunchKernelGGL(k2, grid, block, (uint32_t)smem2, st, nullptr, ev[2 * slot + 1], 0, b);
+}
+
 size_t pcg_lds_bytes(size_t block_bytes, int m, int F, int rows_max) {
   return (block_bytes + 7) / 8 * 8 + sizeof(double) * ((size_t)m + 4 * (size_t)F + 27 * (size_t)rows_max);
 }
@@ -2515,34 +2669,34 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   // Every timed kernel needs a dispatch to carry its events, also when a
   // batch has no work for it: a one-block launch that returns at once.
   // Self-calibrating clusters run in a second launch of the same kernel
-  // (each launch skips the other kind); it carries no events.
+  // (launch_both); a slot's events then span the two launches.
   const dim3 g_pt(b.total_wg > 0 ? b.total_wg : 1), g_tg(b.total_tg > 0 ? b.total_tg : 1);
   Batch nob = b;
   nob.n_act = 0;
   const bool sc = b.any_sc != 0;
   if (b.total_wg > 0 || evk(0)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_point<float, false>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
-    else launch(k_point<double, false>, g_pt, dim3(kWG), sp, st, evk(0), 0, bb);
-    if (sc && mixed) launch(k_point<float, true>, g_pt, dim3(kWG), sps, st, nullptr, 0, bb);
-    if (sc && !mixed) launch(k_point<double, true>, g_pt, dim3(kWG), sps, st, nullptr, 0, bb);
+    const bool s2 = sc && b.total_wg > 0;
+    if (mixed) launch_both(k_point<float, false>, k_point<float, true>, s2, g_pt, dim3(kWG), sp, sps, st, evk(0), 0, bb);
+    else launch_both(k_point<double, false>, k_point<double, true>, s2, g_pt, dim3(kWG), sp, sps, st, evk(0), 0, bb);
   }
   if (mixed) {
     // camera and pair tasks in one launch (slot 1); slot 2 marks an empty interval
     const int nwg = b.total_tkc_wg + b.total_tkp_wg;
-    if (nwg > 0 || evk(1)) launch(k_blocks<float, false>, dim3(nwg > 0 ? nwg : 1), dim3(kWG), 0, st, evk(1), 1, nwg > 0 ? b : nob);
-    if (sc && nwg > 0) launch(k_blocks<float, true>, dim3(nwg), dim3(kWG), 0, st, nullptr, 1, b);
+    if (nwg > 0 || evk(1))
+      launch_both(k_blocks<float, false>, k_blocks<float, true>, sc && nwg > 0, dim3(nwg > 0 ? nwg : 1), dim3(kWG), 0,
+                  0, st, evk(1), 1, nwg > 0 ? b : nob);
     if (evk(2) && ((e = hipEventRecord(ev_all[4], st)) || (e = hipEventRecord(ev_all[5], st)))) return e;
   } else {
     if (b.total_tkc_wg > 0 || evk(1)) {
-      const Batch& bb = b.total_tkc_wg > 0 ? b : nob;
-      launch(k_camblk<double, false>, dim3(b.total_tkc_wg > 0 ? b.total_tkc_wg : 1), dim3(kWG), 0, st, evk(1), 1, bb);
-      if (sc && b.total_tkc_wg > 0) launch(k_camblk<double, true>, dim3(b.total_tkc_wg), dim3(kWG), 0, st, nullptr, 1, b);
+      const int n = b.total_tkc_wg;
+      launch_both(k_camblk<double, false>, k_camblk<double, true>, sc && n > 0, dim3(n > 0 ? n : 1), dim3(kWG), 0, 0,
+                  st, evk(1), 1, n > 0 ? b : nob);
     }
     if (b.total_tkp_wg > 0 || evk(2)) {
-      const Batch& bb = b.total_tkp_wg > 0 ? b : nob;
-      launch(k_pairblk<double, false>, dim3(b.total_tkp_wg > 0 ? b.total_tkp_wg : 1), dim3(kWG), 0, st, evk(2), 2, bb);
-      if (sc && b.total_tkp_wg > 0) launch(k_pairblk<double, true>, dim3(b.total_tkp_wg), dim3(kWG), 0, st, nullptr, 2, b);
+      const int n = b.total_tkp_wg;
+      launch_both(k_pairblk<double, false>, k_pairblk<double, true>, sc && n > 0, dim3(n > 0 ? n : 1), dim3(kWG), 0,
+                  0, st, evk(2), 2, n > 0 ? b : nob);
     }
   }
   if (b.total_tg > 0 || evk(3)) {
@@ -2570,10 +2724,9 @@ hipError_t launch_iteration(const Batch& b, bool mixed, hipStream_t st, hipEvent
   if (evk(7) && (e = hipEventRecord(ev_all[15], st))) return e;
   if (b.total_wg > 0 || evk(5)) {
     const Batch& bb = b.total_wg > 0 ? b : nob;
-    if (mixed) launch(k_backsub<float, false>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
-    else launch(k_backsub<double, false>, g_pt, dim3(kWG), sb, st, evk(5), 5, bb);
-    if (sc && mixed) launch(k_backsub<float, true>, g_pt, dim3(kWG), sb, st, nullptr, 5, bb);
-    if (sc && !mixed) launch(k_backsub<double, true>, g_pt, dim3(kWG), sb, st, nullptr, 5, bb);
+    const bool s2 = sc && b.total_wg > 0;
+    if (mixed) launch_both(k_backsub<float, false>, k_backsub<float, true>, s2, g_pt, dim3(kWG), sb, sb, st, evk(5), 5, bb);
+    else launch_both(k_backsub<double, false>, k_backsub<double, true>, s2, g_pt, dim3(kWG), sb, sb, st, evk(5), 5, bb);
   }
   launch(k_lm, dim3(b.n_act), dim3(64), 0, st, evk(6), 6, b);
   return hipGetLastError();

@@ -74,32 +74,37 @@ class Arena {
 };
 
 // Block rows of each conjugate-gradient workgroup: consecutive rows, at most
-// ceil(F / 16) per workgroup (about 16 workgroups: every conjugate-gradient
-// step pays two grid barriers whose cost grows with the workgroup count, and
-// on the 400-camera flight 16 beat 32, 64 and 128), and no more than keep the
-// workgroup's blocks, the whole direction p and its row work in 150 KB of
-// LDS.  False when a single block row does not fit or more than kMaxCgWG
-// workgroups would be needed.
+// min(ceil(F / 16), kCgMaxRows) per workgroup (about 16 workgroups: every
+// conjugate-gradient step pays a grid barrier whose cost grows with the
+// workgroup count, and on the 400-camera flight 16 beat 32, 64 and 128), and
+// no more than keep the workgroup's blocks and block columns, the direction
+// p and the row work of the most rows any workgroup may get in 150 KB of
+// dynamic LDS (the kernel's static LDS, under 5 KB, fits in the rest of the
+// 160 KB).  False when a single block row does not fit or more than
+// kMaxCgWG workgroups would be needed.
 bool pcg_partition(const Staged& s, bool mixed, std::vector<int>& part, int& rows_max, size_t& smem) {
   part.clear();
   rows_max = 0;
   smem = 0;
   if (!s.sparse) return true;
   const int F = s.n_free, m = s.m;
-  const size_t bb = (mixed ? 4 : 8) * (size_t)kSbVals, budget = 150 * 1024;
-  const size_t fixed = 8 * ((size_t)m + 4 * (size_t)F);
-  const int cap = std::max(1, std::min(kCgThreads, (F + 15) / 16));
+  // bytes per block in LDS: its values and its block column
+  const size_t bb = (mixed ? 4 : 8) * (size_t)kSbVals + sizeof(int), budget = 150 * 1024;
+  const int cap = std::max(1, std::min(kCgMaxRows, (F + 15) / 16));
+  // p (FP64 and FP32 copy), and 27 values per row (S p rows, preconditioner)
+  // for up to cap rows
+  const size_t fixed = 8 * ((size_t)m + 4 * (size_t)F) + 216 * (size_t)cap;
   part.push_back(0);
   int rows = 0;
   size_t bytes = 0;
   for (int f = 0; f < F; ++f) {
     const size_t rb = bb * (size_t)(s.brow[f + 1] - s.brow[f]);
-    if (rows > 0 && (rows == cap || fixed + bytes + rb + 216 * (size_t)(rows + 1) > budget)) {
+    if (rows > 0 && (rows == cap || fixed + bytes + rb > budget)) {
       part.push_back(f);
       rows = 0;
       bytes = 0;
     }
-    if (fixed + rb + 216 > budget) return false;
+    if (fixed + rb > budget) return false;
     bytes += rb;
     ++rows;
     rows_max = std::max(rows_max, rows);
@@ -169,7 +174,7 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.Sblk = take(8 * (size_t)kSbVals * nnzb);
   l.Sblk32 = take(4 * (size_t)kSbVals * nnzb);
   l.pcg_ok = pcg_partition(s, mixed, l.part, l.pcg_rows_max, l.pcg_smem);
-  l.pcgw = take(s.sparse ? 8 * (5 * (size_t)s.m + 8 * (size_t)kMaxCgWG) : 0);
+  l.pcgw = take(s.sparse ? 8 * (7 * (size_t)s.m + 20 * (size_t)kMaxCgWG + 8) : 0);
   l.pcg_part = take(4 * l.part.size());
   const size_t rc = s.resident ? (size_t)s.C : 0, rp = s.resident ? (size_t)s.P : 0;
   l.rin_cam = take(sizeof(int2) * rc);

@@ -287,6 +287,16 @@ def sigma_f(sc, state):
     return float(np.sqrt(np.linalg.inv(H)[kcol[2], kcol[2]]))
 
 
+def f_bar(sc, state):
+    """Bar on |f_mixed - f_oracle|: the larger of a thousandth of f's standard
+    error at the oracle's solution (sigma_f above) and eight FP32 units in the
+    last place of f.  The second term matters only where the data pin f far
+    more tightly than usual (cameras all fixed: sigma_f of a few pixels): the
+    FP32 assembly cannot resolve f below a few of its own ulps."""
+    f = float(state[3][2])
+    return max(1e-3 * sigma_f(sc, state), 8.0 * float(np.spacing(np.float32(f))))
+
+
 @pytest.mark.parametrize("name", ["f_k1", "all_five"])
 def test_self_calibration_mixed_within_tolerance(name):
     """Mixed path, f and k1 (or all five intrinsics) estimated, 40
@@ -310,7 +320,7 @@ def test_self_calibration_mixed_within_tolerance(name):
     sf = sigma_f(sc, ref["state"])
     print(f"self-calibration mixed {name}: rms {rms:.3e} px, centres {dT:.3e} m, attitude {att:.3e} rad, "
           f"f {df:.3e} px (sigma_f {sf:.3g} px, ratio {df / sf:.2e})", flush=True)
-    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6 and df < 1e-3 * sf
+    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6 and df < f_bar(sc, ref["state"])
 
 
 def test_self_calibration_in_a_shared_batch():
@@ -341,6 +351,61 @@ def test_self_calibration_in_a_shared_batch():
             k5 = ref["state"][3]
             assert abs(g["intr"][0] - k5[2]) < 1e-9 * k5[2]
             assert np.abs(g["intr"][1:] - k5[3:]).max() < 1e-6
+
+
+def test_self_calibration_mixed_shared_batch_two_streams():
+    """Mixed path, ten clusters in one batch on two streams (five per stream
+    part): the five self-calibrating micro cases, a cluster whose cameras are
+    all fixed while f, cx and cy are estimated, and four ordinary clusters
+    (k1 and k2, or no intrinsic).  Each part's step launches both kernel
+    instantiations (ordinary and self-calibrating) over the same grid.  Every
+    cluster's 40-iteration result is bit-identical to the same cluster solved
+    alone, and within the mixed bars of the oracle: predicted pixels within
+    1e-3 px RMS, centres within 1 mm, attitude within 2e-6 rad, f within
+    f_bar."""
+    from paper_2511_06152_amd import Context
+    base = dict(A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=3, n_points=600), 147))
+    scs = [self_cal_scene(n) for n in ("f_k1", "cx_cy", "f_only", "f_cx_cy", "all_five")]
+    scs.append(dict(base, intr_mask=0b11100, fixed=np.ones_like(base["fixed"]), f=base["f"] * 1.002,
+                    cx=base["cx"] + 3.0, cy=base["cy"] - 2.0))
+    for i in range(4):
+        scs.append(dict(A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=2 + i % 3, n_points=300 + 200 * i,
+                                                  k_true=(-0.05, 0.02) if i % 2 else (0.0, 0.0)), 150 + i),
+                        intr_mask=3 if i % 2 else 0))
+    iters = 40
+    print("case mixed shared batch, two streams: masks", [sc["intr_mask"] for sc in scs], flush=True)
+    alone = []
+    with Context(precision=MIXED) as ctx:
+        for sc in scs:
+            t = ctx.submit(sc, max_iters=iters)
+            ctx.ba_solve_batch([t])
+            alone.append(ctx.ba_fetch(t))
+    with Context(precision=MIXED, batch_streams=2) as ctx:
+        ts = [ctx.submit(sc, max_iters=iters) for sc in scs]
+        ctx.ba_solve_batch(ts)
+        mix = [ctx.ba_fetch(t) for t in ts]
+    for sc, a, b in zip(scs, alone, mix):
+        assert a["iterations"] == b["iterations"]
+        assert np.array_equal(b["cost_log"], a["cost_log"])
+        for key in ("R", "T", "X", "k", "intr"):
+            assert np.array_equal(b[key], a[key]), key
+    for sc, g in zip(scs, mix):
+        ref = oracle.solve(sc, max_iters=iters)
+        kg = np.concatenate([g["k"], g["intr"]])
+        uv_g = oracle.residuals(sc, (g["R"], g["T"], g["X"], kg))["uv"]
+        uv_o = oracle.residuals(sc, ref["state"])["uv"]
+        rms = float(np.sqrt(((uv_g - uv_o) ** 2).sum(1).mean()))
+        dT = float(np.abs(g["T"] - ref["state"][1]).max())
+        att = max(np.linalg.norm(Rotation.from_matrix(g["R"][c].T @ ref["state"][0][c]).as_rotvec())
+                  for c in range(sc["n_cams"]))
+        msg = f"mask {sc['intr_mask']}: rms {rms:.3e} px, centres {dT:.3e} m, attitude {att:.3e} rad"
+        if sc["intr_mask"] & 0b00100:
+            df = abs(g["intr"][0] - ref["state"][3][2])
+            fb = f_bar(sc, ref["state"])
+            msg += f", f {df:.3e} px (bar {fb:.3g})"
+            assert df < fb, msg
+        print(msg, flush=True)
+        assert rms < 1e-3 and dT < 1e-3 and att < 2e-6, msg
 
 
 def test_self_calibration_limits_rejected():

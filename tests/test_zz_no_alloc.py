@@ -19,16 +19,13 @@ H2D, D2H = 1, 2
 
 
 def hip():
-    """The HIP runtime libba.so is linked against (the same instance)."""
+    """The HIP runtime libba.so is linked against (the same instance): its
+    symbols looked up through libba's own handle, which searches the
+    libraries libba was loaded with.  (In a process that imported torch
+    first, that is torch's copy of the runtime, not the one under /opt/rocm.)"""
     from paper_2511_06152_amd import ba
     lib = ba.load()
-    path = None
-    with open("/proc/self/maps") as fh:
-        for line in fh:
-            if "libamdhip64.so" in line and "/opt/rocm" in line:
-                path = line.split()[-1]
-                break
-    h = ct.CDLL(path or "/opt/rocm/lib/libamdhip64.so")
+    h = ct.CDLL(ba.LIB_PATH)
     h.hipMalloc.argtypes = [ct.POINTER(ct.c_void_p), ct.c_size_t]
     h.hipFree.argtypes = [ct.c_void_p]
     h.hipMemcpy.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_int]
