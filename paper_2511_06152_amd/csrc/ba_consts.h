@@ -24,10 +24,12 @@ constexpr int kStatVals = 6;              // reprojection sums of one point-lane
 constexpr int kIntr = 5;                  // intrinsic state: k1, k2, f, principal-point offset x, y
 constexpr int kSolveTb = 16;              // block size of the dense reduced-system factorisation
 constexpr int kSolveTbVals = kSolveTb * (kSolveTb + 1);   // doubles per block (rows padded to 17)
-constexpr int kCgThreads = 256;           // threads per workgroup of the conjugate-gradient solve
+constexpr int kCgThreads = 512;           // threads per workgroup of the conjugate-gradient solve
 constexpr int kCgWaves = kCgThreads / kWave;
 constexpr int kMaxCgWG = 128;             // workgroups of one cluster's conjugate-gradient solve, at most
-constexpr int kCgMaxRows = kCgThreads / 6;   // block rows of one conjugate-gradient workgroup, at most
+// block rows of one conjugate-gradient workgroup, at most: their owner
+// threads fit in wavefront 0, and each scalar row of S p has a thread
+constexpr int kCgMaxRows = kWave < kCgThreads / 6 ? kWave : kCgThreads / 6;
 constexpr int kSbRow = 8;                 // sparse reduced-system block: 6 rows padded to 8 values
 constexpr int kSbVals = 6 * kSbRow;       //   (16-byte aligned rows for vector loads)
 // Work items of the block-assembly kernel (one wavefront each) and of its

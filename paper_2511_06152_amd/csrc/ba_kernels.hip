@@ -1767,7 +1767,8 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
 // dot products, the preconditioner and the updates are FP64).  Thread t of a
 // workgroup owns block row r0 + t (x, r in registers, its preconditioner
 // block in LDS; at most kCgMaxRows rows, so the owners are in wavefront 0
-// and every scalar row of S p has a thread).  Every
+// and every scalar row of S p has a thread: up to four, each taking every
+// fourth block).  Every
 // workgroup keeps the entries of the direction p that its rows' blocks
 // multiply (its halo: the block columns of its blocks) in LDS, updated the
 // same way in every workgroup.
@@ -1796,6 +1797,8 @@ namespace cg = cooperative_groups;
 constexpr int kCgSums = 7;                // p.q, r.q, q.q, q.z, q.u, r.r, r.z
 constexpr int kCgPartStride = 8;          // doubles per workgroup part (7 used)
 constexpr long kCgSpinCap = 1L << 22;     // polls before a barrier wait gives up (seconds)
+// halo entries of p per thread, at most (the halo is at most all m <= 6 kMaxCams entries)
+constexpr int kCgHalo = (6 * kMaxCams + kCgThreads - 1) / kCgThreads;
 
 // Sums over the workgroup in a fixed order (N values at once); every thread
 // gets the sums.
@@ -2084,13 +2087,18 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
     if (wg == 0 && tid == 0) c.solve_ok = 0;
     return;
   }
+  // this thread's halo entries of p (index, or -1), and p_0 = z_0 there
   const int nh6 = 6 * n_halo;
-  // the halo of p_0 = z_0 into LDS
-  for (int e = tid; e < nh6; e += kCgThreads) {
-    const int q = 6 * hcol[e / 6] + e % 6;
-    const double v = zg[q];
-    pl[q] = v;
-    if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
+  int qh[kCgHalo];
+#pragma unroll
+  for (int u = 0; u < kCgHalo; ++u) {
+    const int e = tid + u * kCgThreads;
+    qh[u] = e < nh6 ? 6 * hcol[e / 6] + e % 6 : -1;
+    if (qh[u] >= 0) {
+      const double v = zg[qh[u]];
+      pl[qh[u]] = v;
+      if (mixed) p32l[kSbRow * (qh[u] / 6) + qh[u] % 6] = (float)v;
+    }
   }
   const double bnorm = sqrt(s0.x);
   const int max_it = d.pcg_max_iters;
@@ -2153,6 +2161,10 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
       good = false;
       break;
     }
+    // this thread's halo entries of (z, u), requested before the parts are added
+    double2 zu[kCgHalo];
+#pragma unroll
+    for (int u = 0; u < kCgHalo; ++u) zu[u] = qh[u] >= 0 ? zub[qh[u]] : make_double2(0.0, 0.0);
     // every wavefront: the G parts, added by the same butterfly everywhere
     // (lane l takes parts l and l + 64)
     double t[kCgSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -2191,12 +2203,14 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
     if (sqrt(rr_new) <= tol * bnorm) break;
     const double beta = rz_new / rz;
     // the halo of the next p = (z - alpha u) + beta p, the same in every workgroup
-    for (int e = tid; e < nh6; e += kCgThreads) {
-      const int q = 6 * hcol[e / 6] + e % 6;
-      const double2 zu = zub[q];
-      const double v = fm(beta, pl[q], fm(-alpha, zu.y, zu.x));
-      pl[q] = v;
-      if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
+#pragma unroll
+    for (int u = 0; u < kCgHalo; ++u) {
+      const int q = qh[u];
+      if (q >= 0) {
+        const double v = fm(beta, pl[q], fm(-alpha, zu[u].y, zu[u].x));
+        pl[q] = v;
+        if (mixed) p32l[kSbRow * (q / 6) + q % 6] = (float)v;
+      }
     }
   }
   if (!good) {
