@@ -528,14 +528,15 @@ __global__ void k_prep_points(Batch bt) {
     d.lane_uv32[2 * i] = (float)u;
     d.lane_uv32[2 * i + 1] = (float)v;
   }
-  if (i < d.Lc) {
+  // mixed mode: the camera- and pair-lane pixels arrive as FP32, already shifted
+  if (!d.mixed && i < d.Lc) {
     const double u = d.cl_uv64[2 * i] - d.cx, v = d.cl_uv64[2 * i + 1] - d.cy;
     d.cl_uv64[2 * i] = u;
     d.cl_uv64[2 * i + 1] = v;
     d.cl_uv32[2 * i] = (float)u;
     d.cl_uv32[2 * i + 1] = (float)v;
   }
-  if (i < 2 * d.Lq) {
+  if (!d.mixed && i < 2 * d.Lq) {
     const double u = d.ql_uv64[2 * i] - d.cx, v = d.ql_uv64[2 * i + 1] - d.cy;
     d.ql_uv64[2 * i] = u;
     d.ql_uv64[2 * i + 1] = v;

@@ -116,11 +116,16 @@ bool pcg_partition(const Staged& s, bool mixed, std::vector<int>& part, int& row
   return true;
 }
 
-struct Layout {                  // byte offsets inside a slot block
+constexpr size_t kAbsent = ~(size_t)0;   // an array the slot does not hold
+
+// Byte offsets inside a slot block.  The arrays taken from the host come
+// first, [0, upload_end), so that one copy of the cluster's upload image
+// fills them; the arrays the device computes follow.
+struct Layout {
   size_t lane_pt, lane_meta, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, pcg_part, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
-      bad_part, cost_log, lambda_log, acc_log, stat_part, out, total;
+      bad_part, cost_log, lambda_log, acc_log, stat_part, out, upload_end, total;
   int n_wg, psize, pstride;
   std::vector<int> part;         // conjugate-gradient workgroups' first block rows
   int pcg_rows_max;
@@ -137,45 +142,53 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.pstride = (int)align_up((size_t)l.psize + 3 * (size_t)s.m, 4);
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
+  l.pcg_ok = pcg_partition(s, mixed, l.part, l.pcg_rows_max, l.pcg_smem);
+  const size_t nnzb = s.bcol.size();
+  // from the host.  In mixed mode the camera- and pair-lane pixels come as
+  // FP32 (principal point already subtracted) and have no FP64 copy.
   l.lane_pt = take(4 * (size_t)s.L);
   l.lane_meta = take(4 * (size_t)s.L);
   l.uv64 = take(16 * (size_t)s.L);
-  l.uv32 = take(8 * (size_t)s.L);
   l.cl_pt = take(4 * (size_t)s.Lc);
-  l.cl_uv64 = take(16 * (size_t)s.Lc);
-  l.cl_uv32 = take(8 * (size_t)s.Lc);
+  l.cl_uv64 = mixed ? kAbsent : take(16 * (size_t)s.Lc);
+  l.cl_uv32 = mixed ? take(8 * (size_t)s.Lc) : kAbsent;
   l.ql_pt = take(4 * (size_t)s.Lq);
-  l.ql_uv64 = take(32 * (size_t)s.Lq);
-  l.ql_uv32 = take(16 * (size_t)s.Lq);
+  l.ql_uv64 = mixed ? kAbsent : take(32 * (size_t)s.Lq);
+  l.ql_uv32 = mixed ? take(16 * (size_t)s.Lq) : kAbsent;
   l.tasks = take(sizeof(int4) * s.tasks.size());
   l.targets = take(sizeof(int4) * s.targets.size());
-  l.cam0 = take(8 * (size_t)kCamVals * s.C);
-  l.cam1 = take(8 * (size_t)kCamVals * s.C);
-  l.prior = take(8 * (size_t)kPriorVals * s.C);
   l.cam_col = take(4 * (size_t)s.C);
   l.raw_cam = take(8 * 30 * (size_t)s.C);
   l.X0 = take(24 * (size_t)s.P);
+  l.pt_orig = take(4 * (size_t)s.P);
+  l.brow = take(4 * s.brow.size());
+  l.bcol = take(4 * nnzb);
+  l.tslot = take(sizeof(int2) * s.tslot.size());
+  l.pcg_part = take(4 * l.part.size());
+  l.upload_end = o;
+  // computed on the device
+  l.uv32 = take(8 * (size_t)s.L);
+  if (!mixed) {
+    l.cl_uv32 = take(8 * (size_t)s.Lc);
+    l.ql_uv32 = take(16 * (size_t)s.Lq);
+  }
+  l.cam0 = take(8 * (size_t)kCamVals * s.C);
+  l.cam1 = take(8 * (size_t)kCamVals * s.C);
+  l.prior = take(8 * (size_t)kPriorVals * s.C);
   l.X1 = take(24 * (size_t)s.P);
   l.X320 = take(12 * (size_t)s.P);
   l.X321 = take(12 * (size_t)s.P);
   l.ptv = take(rs * kPtVals * (size_t)s.P);
   l.ptd = take(rs * 4 * (size_t)s.P);
   l.ptz = take(s.sc ? rs * kPtzVals * (size_t)s.P : 0);
-  l.pt_orig = take(4 * (size_t)s.P);
   l.task_part = take(rs * kTaskVals * s.tasks.size());
   l.pt_part = take(rs * kPtPartVals * (size_t)s.n_pt_part);
   l.Sg = take(8 * (size_t)l.pstride);
   l.Sd = take(s.sparse ? 0 : 8 * kSolveTbVals * (size_t)s.nb * (s.nb + 1) / 2);
   l.dc = take(8 * (size_t)s.m);
-  const size_t nnzb = s.bcol.size();
-  l.brow = take(4 * s.brow.size());
-  l.bcol = take(4 * nnzb);
-  l.tslot = take(sizeof(int2) * s.tslot.size());
   l.Sblk = take(8 * (size_t)kSbVals * nnzb);
   l.Sblk32 = take(4 * (size_t)kSbVals * nnzb);
-  l.pcg_ok = pcg_partition(s, mixed, l.part, l.pcg_rows_max, l.pcg_smem);
   l.pcgw = take(s.sparse ? 8 * (7 * (size_t)s.m + 20 * (size_t)kMaxCgWG + 8) : 0);
-  l.pcg_part = take(4 * l.part.size());
   const size_t rc = s.resident ? (size_t)s.C : 0, rp = s.resident ? (size_t)s.P : 0;
   l.rin_cam = take(sizeof(int2) * rc);
   l.rin_pt = take(sizeof(int2) * rp);
@@ -190,6 +203,47 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.out = take(8 * (12 * (size_t)s.C + 3 * (size_t)s.P + 5 + kStatVals));
   l.total = o;
   return l;
+}
+
+// Writes the cluster's upload image: every array the slot block takes from
+// the host, at its offset below lay.upload_end (the alignment gaps are left
+// as they are).  In mixed mode the camera- and pair-lane pixels are written
+// relative to the principal point and rounded to FP32 from that FP64
+// difference (what the device's own conversion of the FP64 lanes gives).
+void pack_upload(const Staged& s, bool mixed, const Layout& lay, char* dst) {
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(dst + off, src, bytes);
+  };
+  put(lay.lane_pt, s.lane_pt.data(), 4 * (size_t)s.L);
+  put(lay.lane_meta, s.lane_meta.data(), 4 * (size_t)s.L);
+  put(lay.uv64, s.lane_uv.data(), 16 * (size_t)s.L);
+  put(lay.cl_pt, s.cl_pt.data(), 4 * (size_t)s.Lc);
+  put(lay.ql_pt, s.ql_pt.data(), 4 * (size_t)s.Lq);
+  if (mixed) {
+    float* cu = reinterpret_cast<float*>(dst + lay.cl_uv32);
+    for (size_t i = 0; i < 2 * (size_t)s.Lc; i += 2) {
+      cu[i] = (float)(s.cl_uv[i] - s.cx);
+      cu[i + 1] = (float)(s.cl_uv[i + 1] - s.cy);
+    }
+    float* qu = reinterpret_cast<float*>(dst + lay.ql_uv32);
+    for (size_t i = 0; i < 4 * (size_t)s.Lq; i += 2) {
+      qu[i] = (float)(s.ql_uv[i] - s.cx);
+      qu[i + 1] = (float)(s.ql_uv[i + 1] - s.cy);
+    }
+  } else {
+    put(lay.cl_uv64, s.cl_uv.data(), 16 * (size_t)s.Lc);
+    put(lay.ql_uv64, s.ql_uv.data(), 32 * (size_t)s.Lq);
+  }
+  put(lay.tasks, s.tasks.data(), sizeof(I4) * s.tasks.size());
+  put(lay.targets, s.targets.data(), sizeof(I4) * s.targets.size());
+  put(lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C);
+  put(lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C);
+  put(lay.X0, s.X.data(), 24 * (size_t)s.P);
+  put(lay.pt_orig, s.pt_orig.data(), 4 * (size_t)s.P);
+  put(lay.brow, s.brow.data(), 4 * s.brow.size());
+  put(lay.bcol, s.bcol.data(), 4 * s.bcol.size());
+  put(lay.tslot, s.tslot.data(), sizeof(I2) * s.tslot.size());
+  put(lay.pcg_part, lay.part.data(), 4 * lay.part.size());
 }
 
 // Global ID -> row, open addressing with linear probing (the resident store's
@@ -302,6 +356,10 @@ struct Slot {
   Layout lay{};
   SlotDesc desc{};
   bool mixed = false;
+  // sources of the admission's small uploads, kept until the slot is freed
+  SlotCtl ctl0{};
+  std::vector<int2> rin_c, rin_p, rout_p;
+  std::vector<int4> rout_c;
 };
 
 // Per-launcher device batch arrays and pinned mirrors.
@@ -368,6 +426,15 @@ struct ba_ctx {
   std::condition_variable stage_cv;       // wakes the layout threads
   std::condition_variable staged_cv;      // a background layout finished
   bool stage_stop = false;
+  // Pinned host buffers for the clusters' upload images (pin_mu): free ones
+  // (buffer, capacity), the bytes allocated, and the buffers of uploads in
+  // flight with the event that marks each upload's end.
+  std::mutex pin_mu;
+  std::vector<std::pair<char*, size_t>> pin_free;
+  size_t pin_bytes = 0;
+  struct PinFlight { std::shared_ptr<char> blob; hipEvent_t ev; };
+  std::vector<PinFlight> pin_flight;
+  std::vector<hipEvent_t> pin_events;     // idle events for pin_flight
 };
 
 namespace {
@@ -405,6 +472,71 @@ void dfree(ba_ctx* c, void* p) {
   if (!p) return;
   if (c->opt.dev_free) c->opt.dev_free(p, c->opt.alloc_user);
   else (void)hipFree(p);
+}
+
+// Pinned host memory for upload images: at most kPinnedPoolBytes in all, the
+// buffers reused across clusters (capacities rounded up to 2 MiB).
+constexpr size_t kPinnedPoolBytes = 256u << 20;
+
+// Returns the buffers of finished uploads to the free list.
+void pin_reap(ba_ctx* c) {
+  std::vector<std::shared_ptr<char>> done;   // dropped on return, after pin_mu is released
+  std::lock_guard<std::mutex> g(c->pin_mu);
+  for (size_t i = 0; i < c->pin_flight.size();) {
+    if (hipEventQuery(c->pin_flight[i].ev) == hipSuccess) {
+      c->pin_events.push_back(c->pin_flight[i].ev);
+      done.push_back(std::move(c->pin_flight[i].blob));
+      c->pin_flight[i] = std::move(c->pin_flight.back());
+      c->pin_flight.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+// A pinned buffer of at least `bytes` (returned to the pool when the last
+// pointer to it is dropped), or null when the pool is full.
+std::shared_ptr<char> pin_get(ba_ctx* c, size_t bytes) {
+  pin_reap(c);
+  char* p = nullptr;
+  size_t have = 0;
+  {
+    std::lock_guard<std::mutex> g(c->pin_mu);
+    int best = -1;
+    for (int i = 0; i < (int)c->pin_free.size(); ++i)
+      if (c->pin_free[i].second >= bytes && (best < 0 || c->pin_free[i].second < c->pin_free[best].second)) best = i;
+    if (best >= 0) {
+      p = c->pin_free[best].first;
+      have = c->pin_free[best].second;
+      c->pin_free.erase(c->pin_free.begin() + best);
+    } else {
+      have = align_up(std::max<size_t>(bytes, 1), 2u << 20);
+      if (c->pin_bytes + have > kPinnedPoolBytes) return nullptr;
+      c->pin_bytes += have;
+    }
+  }
+  if (!p && hipHostMalloc((void**)&p, have, hipHostMallocDefault) != hipSuccess) {
+    std::lock_guard<std::mutex> g(c->pin_mu);
+    c->pin_bytes -= have;
+    return nullptr;
+  }
+  return std::shared_ptr<char>(p, [c, have](char* q) {
+    std::lock_guard<std::mutex> g(c->pin_mu);
+    c->pin_free.emplace_back(q, have);
+  });
+}
+
+// Packs the cluster's upload image: into pinned memory when the pool has
+// room (its upload at admission is then asynchronous), else into ordinary
+// memory.
+void pack_staged(ba_ctx* c, Staged& s, const Layout& lay) {
+  std::shared_ptr<char> b;
+  if (lay.upload_end <= kPinnedPoolBytes / 4) b = pin_get(c, lay.upload_end);
+  s.blob_pinned = b != nullptr;
+  if (!b) b = std::shared_ptr<char>(new char[std::max<size_t>(lay.upload_end, 1)], std::default_delete<char[]>());
+  pack_upload(s, c->opt.precision == BA_MIXED, lay, b.get());
+  s.blob = std::move(b);
+  s.blob_bytes = lay.upload_end;
 }
 
 int init_launcher(ba_ctx* c, Launcher& l) {
@@ -570,7 +702,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   for (int i = 0; i < (int)c->slots.size(); ++i)
     if (!c->slots[i].used) { slot = i; break; }
   if (slot < 0) return BA_E_AGAIN;
-  const Staged& s = *t.staged;
+  Staged& s = *t.staged;
   const bool mixed = c->opt.precision == BA_MIXED;
   Layout lay = make_layout(s, mixed);
   size_t off = 0;
@@ -605,10 +737,10 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.lane_uv64 = (double*)(base + lay.uv64);
   d.lane_uv32 = (float*)(base + lay.uv32);
   d.cl_pt = (const int*)(base + lay.cl_pt);
-  d.cl_uv64 = (double*)(base + lay.cl_uv64);
+  d.cl_uv64 = lay.cl_uv64 == kAbsent ? nullptr : (double*)(base + lay.cl_uv64);
   d.cl_uv32 = (float*)(base + lay.cl_uv32);
   d.ql_pt = (const int*)(base + lay.ql_pt);
-  d.ql_uv64 = (double*)(base + lay.ql_uv64);
+  d.ql_uv64 = lay.ql_uv64 == kAbsent ? nullptr : (double*)(base + lay.ql_uv64);
   d.ql_uv32 = (float*)(base + lay.ql_uv32);
   d.tasks = (const int4*)(base + lay.tasks);
   d.targets = (const int4*)(base + lay.targets);
@@ -640,8 +772,10 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.pcg_G = lay.part.empty() ? 0 : (int)lay.part.size() - 1;
   d.pcg_rows_max = lay.pcg_rows_max;
   d.pcg_smem = (int)lay.pcg_smem;
-  std::vector<int2> rin_c, rin_p, rout_p;
-  std::vector<int4> rout_c;
+  std::vector<int2>& rin_c = sl.rin_c;
+  std::vector<int2>& rin_p = sl.rin_p;
+  std::vector<int2>& rout_p = sl.rout_p;
+  std::vector<int4>& rout_c = sl.rout_c;
   if (t.resident) {
     for (int k = 0; k < s.C; ++k) {
       const int row = t.cam_rows[k];
@@ -671,33 +805,23 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.stat_part = (double*)(base + lay.stat_part);
   d.out = (double*)(base + lay.out);
   hipStream_t st = c->stream;
-  HIPCHK(c, hipMemcpyAsync(base + lay.lane_pt, s.lane_pt.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
-  HIPCHK(c, hipMemcpyAsync(base + lay.lane_meta, s.lane_meta.data(), 4 * (size_t)s.L, hipMemcpyHostToDevice, st));
-  HIPCHK(c, hipMemcpyAsync(base + lay.uv64, s.lane_uv.data(), 16 * (size_t)s.L, hipMemcpyHostToDevice, st));
-  if (s.Lc) {
-    HIPCHK(c, hipMemcpyAsync(base + lay.cl_pt, s.cl_pt.data(), 4 * (size_t)s.Lc, hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(base + lay.cl_uv64, s.cl_uv.data(), 16 * (size_t)s.Lc, hipMemcpyHostToDevice, st));
-  }
-  if (s.Lq) {
-    HIPCHK(c, hipMemcpyAsync(base + lay.ql_pt, s.ql_pt.data(), 4 * (size_t)s.Lq, hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(base + lay.ql_uv64, s.ql_uv.data(), 32 * (size_t)s.Lq, hipMemcpyHostToDevice, st));
-  }
-  if (!s.tasks.empty())
-    HIPCHK(c, hipMemcpyAsync(base + lay.tasks, s.tasks.data(), sizeof(int4) * s.tasks.size(), hipMemcpyHostToDevice, st));
-  if (!s.targets.empty())
-    HIPCHK(c, hipMemcpyAsync(base + lay.targets, s.targets.data(), sizeof(int4) * s.targets.size(),
-                             hipMemcpyHostToDevice, st));
-  HIPCHK(c, hipMemcpyAsync(base + lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C, hipMemcpyHostToDevice, st));
-  if (s.sparse) {
-    HIPCHK(c, hipMemcpyAsync(base + lay.brow, s.brow.data(), 4 * s.brow.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(base + lay.bcol, s.bcol.data(), 4 * s.bcol.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(base + lay.tslot, s.tslot.data(), sizeof(int2) * s.tslot.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(base + lay.pcg_part, lay.part.data(), 4 * lay.part.size(), hipMemcpyHostToDevice, st));
-  }
-  HIPCHK(c, hipMemcpyAsync(base + lay.raw_cam, s.raw_cam.data(), 8 * 30 * (size_t)s.C, hipMemcpyHostToDevice, st));
-  if (s.P > 0) {
-    HIPCHK(c, hipMemcpyAsync(base + lay.X0, s.X.data(), 24 * (size_t)s.P, hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(base + lay.pt_orig, s.pt_orig.data(), 4 * (size_t)s.P, hipMemcpyHostToDevice, st));
+  // the upload image in one copy: asynchronous from pinned memory (the buffer
+  // goes back to the pool once the copy has run), else waited for below
+  if (!s.blob) pack_staged(c, s, lay);
+  if (s.blob_bytes) HIPCHK(c, hipMemcpyAsync(base, s.blob.get(), s.blob_bytes, hipMemcpyHostToDevice, st));
+  if (s.blob_pinned) {
+    hipEvent_t ev = nullptr;
+    {
+      std::lock_guard<std::mutex> g(c->pin_mu);
+      if (!c->pin_events.empty()) {
+        ev = c->pin_events.back();
+        c->pin_events.pop_back();
+      }
+    }
+    if (!ev) HIPCHK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(c, hipEventRecord(ev, st));
+    std::lock_guard<std::mutex> g(c->pin_mu);
+    c->pin_flight.push_back({std::move(s.blob), ev});
   }
   auto up2 = [&](size_t off, const std::vector<int2>& v) {
     return v.empty() ? hipSuccess : hipMemcpyAsync(base + off, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, st);
@@ -708,14 +832,16 @@ int admit_one(ba_ctx* c, Ticket& t) {
     HIPCHK(c, hipMemcpyAsync(base + lay.rout_cam, rout_c.data(), sizeof(int4) * rout_c.size(), hipMemcpyHostToDevice, st));
   HIPCHK(c, up2(lay.rout_pt, rout_p));
   HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
-  SlotCtl ctl{};
+  SlotCtl& ctl = sl.ctl0;
+  ctl = SlotCtl{};
   ctl.k[0][0] = s.k[0];
   ctl.k[0][1] = s.k[1];
   ctl.k[0][2] = s.f;      // principal-point offsets start at 0
   ctl.status = ST_RUNNING;
   HIPCHK(c, hipMemcpyAsync(c->d_ctl + slot, &ctl, sizeof(SlotCtl), hipMemcpyHostToDevice, st));
-  // The staged host data must stay alive until the copies above have run.
-  HIPCHK(c, hipStreamSynchronize(st));
+  // An image in ordinary memory must stay alive until its copy has run; the
+  // small sources above live in the slot until it is freed.
+  if (!s.blob_pinned) HIPCHK(c, hipStreamSynchronize(st));
   t.slot = slot;
   t.state = TK_RESIDENT;
   t.t_admit = now_s();
@@ -1148,6 +1274,19 @@ int ba_destroy(ba_ctx* c) {
   }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   free_launcher(c, c->srv);
+  // the tickets' upload images go back to the pool before it is freed
+  c->tickets.clear();
+  c->stage_jobs.clear();
+  {
+    std::vector<ba_ctx::PinFlight> fl;
+    {
+      std::lock_guard<std::mutex> g(c->pin_mu);
+      fl.swap(c->pin_flight);
+    }
+    for (auto& f : fl) (void)hipEventDestroy(f.ev);
+  }
+  for (auto& f : c->pin_free) (void)hipHostFree(f.first);
+  for (hipEvent_t e : c->pin_events) (void)hipEventDestroy(e);
   for (auto& set : c->prof_ev)
     for (auto& e : set) (void)hipEventDestroy(e);
   dfree(c, c->d_desc);
@@ -1179,6 +1318,10 @@ int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   auto st = std::make_unique<Staged>();
   std::string err;
   int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
+  if (!rc) {
+    const Layout lay = make_layout(*st, c->opt.precision == BA_MIXED);
+    if (lay.pcg_ok && lay.total <= c->arena.size()) pack_staged(c, *st, lay);
+  }
   std::lock_guard<std::mutex> g(c->mu);
   if (rc) return fail(c, rc, err);
   return enqueue_staged(c, std::move(st), ticket, t_submit);
@@ -1209,6 +1352,10 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
       for (int i; (i = next.fetch_add(1)) < n;) {
         st[i] = std::make_unique<Staged>();
         rc[i] = stage(&cl[i], *st[i], err[i], c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
+        if (!rc[i]) {
+          const Layout lay = make_layout(*st[i], c->opt.precision == BA_MIXED);
+          if (lay.pcg_ok && lay.total <= c->arena.size()) pack_staged(c, *st[i], lay);
+        }
       }
     };
     const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
@@ -1245,6 +1392,7 @@ void res_abandon(ba_ctx* c, Ticket& t) {
 // A layout thread: lays out the queued copies in submission order of pickup;
 // the result (or the reason it was refused) goes to the ticket.
 void stage_worker(ba_ctx* c) {
+  (void)hipSetDevice(c->device);   // for the pinned buffers of the upload images
   std::unique_lock<std::mutex> lk(c->mu);
   for (;;) {
     c->stage_cv.wait(lk, [&] { return c->stage_stop || !c->stage_jobs.empty(); });
@@ -1257,6 +1405,7 @@ void stage_worker(ba_ctx* c) {
     const int rc = stage(&job.second->c, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
     Layout lay;
     if (!rc) lay = make_layout(*st, c->opt.precision == BA_MIXED);
+    if (!rc && lay.pcg_ok && lay.total <= c->arena.size()) pack_staged(c, *st, lay);
     lk.lock();
     Ticket* t = nullptr;
     auto it = c->tickets.find(job.first);

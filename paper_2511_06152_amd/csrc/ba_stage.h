@@ -8,6 +8,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,13 @@ struct Staged {
   bool resident = false, fuse = false;
   std::vector<int64_t> cam_ids, point_ids;
   std::vector<int> cam_nobs;
+  // upload image: the arrays the slot block takes from the host, already at
+  // their offsets in the block, in a buffer the runtime provides (pinned
+  // host memory, returned to its pool when the pointer is dropped); empty
+  // when none was available (the arrays above are then copied one by one)
+  std::shared_ptr<char> blob;
+  size_t blob_bytes = 0;
+  bool blob_pinned = false;
 };
 
 

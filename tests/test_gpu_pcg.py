@@ -252,3 +252,35 @@ def test_global_400_cams_tight_pcg_matches_oracle_state(precision, tol):
         assert att < 1e-8 and dT < 1e-6 and dX < 1e-5
     else:
         assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
+
+
+def test_global_400_cams_bench_tolerance_matches_oracle_at_150():
+    """The bench's configuration of the whole-flight adjustment: mixed
+    precision, PCG forcing term min(1e-5, sqrt(|b|/|b_0|)), 150 LM
+    iterations, against the oracle's exact-LM state after 150 iterations,
+    within the mixed-path bars (1e-3 px RMS over every observation of the
+    5000 sampled points, 1 mm, 2e-6 rad).  The outlier points' IRLS weights
+    keep drifting (about 0.06 px per 10 iterations at 150), so the
+    comparison is at equal iteration count.  With the default cap of 0.1 the
+    FP32-assembled reduced gradient reaches its rounding floor early, the
+    forcing term stays at the cap, and the inexact steps drift along the flat
+    valley of the cost: at 150 iterations the cost agrees to 4e-7 but the
+    cameras sit centimetres from the oracle's; a cap of 1e-4 still leaves
+    3 mm."""
+    from paper_2511_06152_amd import Context
+    from paper_2511_06152_amd.ba import Cluster
+    g = read_golden(150)
+    sc = global_scene()
+    print("case global full size, mixed, pcg_tol 1e-5, 150 iterations", flush=True)
+    with Context(precision=MIXED, max_slots=2, hbm_budget_bytes=3 << 30, pcg_tol=1e-5,
+                 pcg_max_iters=20000) as ctx:
+        t = ctx.ba_submit_cluster(Cluster(sc, max_iters=g["iterations"]))
+        ctx.ba_step(t, g["iterations"])
+        got = ctx.ba_fetch(t)
+    rms, dT, att, dX, n_obs = errors_vs_golden(sc, got, g)
+    e = got["cost_log"][-1]
+    print(f"global pcg_tol 1e-5 vs oracle after {g['iterations']}: rms {rms:.3e} px over {n_obs} observations, "
+          f"centres {dT:.3e} m, attitude {att:.3e} rad, points {dX:.3e} m; cost {e:.12g} vs {g['cost']:.12g}; "
+          f"cg {got['cg_iters']}", flush=True)
+    assert got["iterations"] == g["iterations"]
+    assert rms < 1e-3 and dT < 1e-3 and att < 2e-6
