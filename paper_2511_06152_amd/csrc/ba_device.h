@@ -13,7 +13,7 @@ namespace bagpu {
 
 // Read-only description of one resident cluster; written once at admission.
 struct SlotDesc {
-  int C, P, L, n_chunks, n_wg, cpw;       // cameras, points, lanes, 64-lane chunks, workgroups, chunks/WG
+  int C, P, L, n_chunks, n_wg, pad0;      // cameras, points, observation lanes, point chunks, workgroups
   int m, n_free, kcol0, kcol1;            // reduced system size, free cameras, intrinsic columns (-1: fixed)
   int psize, pstride;                     // packed m(m+1)/2, reduced-system vector stride (psize + 3m)
   int max_iters, stop_on_ftol, mixed, nb;  // nb: 16x16 blocks per side of the dense reduced system
@@ -25,13 +25,14 @@ struct SlotDesc {
   int kcolt[kIntr], sc, pad2[2];
   double pcg_tol;
   double f, cx, cy, inv_sigma, huber_dt, ftol, lambda0;
-  // observation lanes, sorted by (point, camera); a point never straddles a 64-lane chunk
-  const int* lane_pt;                     // [L] point index, -1 for padding
-  const int* lane_meta;                   // [L] camera index (bits 0-8) | first lane of the point's
-                                          //     segment in the chunk << 9 | its length << 15 |
-                                          //     the chunk's longest segment << 22
-  double* lane_uv64;                      // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
-  float* lane_uv32;                       // [2L]
+  // point chunks: 64 consecutive internal points with the same observation
+  // count n; observation t (camera order) of the chunk's lane l sits in
+  // observation lane first + 64 t + l
+  const int4* pchunk;                     // [n_chunks] {first observation lane, n, first point, valid points}
+  const int* wg_chunk;                    // [n_wg + 1] first chunk of each point-pass workgroup
+  const int* ob_cam;                      // [L] camera of each observation lane (0 for padding)
+  double* ob_uv64;                        // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
+  float* ob_uv32;                         // [2L]
   // camera lanes: observations of free cameras sorted by (camera, point), each
   // camera's run padded to whole 64-lane chunks
   const int* cl_pt;                       // [Lc] point index, -1 for padding

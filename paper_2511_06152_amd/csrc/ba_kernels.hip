@@ -4,10 +4,10 @@
 // launches in the mixed path (seven in the plain FP64 path), each covering
 // every cluster of the batch:
 //
-//   k_point<Real>     per observation: residual of Eq. (5) with k1/k2 radial
-//                     terms, Huber IRLS weight (robust rho of Eq. 6/7), point
-//                     Jacobian; per point (wavefront-segmented sum): V_j, g_j
-//                     and the damped inverse
+//   k_point<Real>     one lane per point, over its observations: residual of
+//                     Eq. (5) with k1/k2 radial terms, Huber IRLS weight
+//                     (robust rho of Eq. 6/7), point Jacobian; V_j, g_j in
+//                     registers and the damped inverse
 //   k_blocks<float>   one wavefront per task: a free camera's diagonal Schur
 //   (k_camblk<double>, block (U_kk - sum W Q W^T, gradient, intrinsic border)
 //    k_pairblk<double>) over its observations, or one camera-pair block
@@ -63,14 +63,6 @@ __device__ __forceinline__ int xcd_block() {
   const int q = G >> 3, r = G & 7, x = b & 7, slot = b >> 3;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
 }
-
-// Observation lanes of chunk ch: one lane word holds the camera (bits 0-8),
-// the first lane of the point's segment (9-14), its length (15-21) and the
-// chunk's longest segment (22-28).
-__device__ __forceinline__ int meta_cam(int m) { return m & 511; }
-__device__ __forceinline__ int seg_first(int m) { return (m >> 9) & 63; }
-__device__ __forceinline__ int seg_len(int m) { return (m >> 15) & 127; }
-__device__ __forceinline__ int chunk_maxlen(int m) { return __builtin_amdgcn_readfirstlane((m >> 22) & 127); }
 
 // Packed storage of a symmetric matrix: element (r, c), r <= c.
 __device__ __forceinline__ int pidx(int r, int c) { return c * (c + 1) / 2 + r; }
@@ -522,11 +514,11 @@ __global__ void k_prep_points(Batch bt) {
     }
   }
   if (i < d.L) {
-    const double u = d.lane_uv64[2 * i] - d.cx, v = d.lane_uv64[2 * i + 1] - d.cy;
-    d.lane_uv64[2 * i] = u;
-    d.lane_uv64[2 * i + 1] = v;
-    d.lane_uv32[2 * i] = (float)u;
-    d.lane_uv32[2 * i + 1] = (float)v;
+    const double u = d.ob_uv64[2 * i] - d.cx, v = d.ob_uv64[2 * i + 1] - d.cy;
+    d.ob_uv64[2 * i] = u;
+    d.ob_uv64[2 * i + 1] = v;
+    d.ob_uv32[2 * i] = (float)u;
+    d.ob_uv32[2 * i + 1] = (float)v;
   }
   // mixed mode: the camera- and pair-lane pixels arrive as FP32, already shifted
   if (!d.mixed && i < d.Lc) {
@@ -563,15 +555,16 @@ __global__ __launch_bounds__(kWG) void k_cost0(Batch bt) {
   const double* ki = c.k[cur];
   double acc = 0.0;
   int bad = 0;
-  const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
-  for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
-    const int idx = ch * kWave + lane;
-    const int pt = d.lane_pt[idx];
-    if (pt >= 0) {
-      const int cam = meta_cam(d.lane_meta[idx]);
-      const double X[3] = {d.X[cur][3 * pt], d.X[cur][3 * pt + 1], d.X[cur][3 * pt + 2]};
+  // one lane per point of a chunk, over its observations
+  for (int ch = d.wg_chunk[wgl] + wave; ch < d.wg_chunk[wgl + 1]; ch += kWavesPerWG) {
+    const int4 pc = d.pchunk[ch];
+    if (lane >= pc.w) continue;
+    const int pt = pc.z + lane;
+    const double X[3] = {d.X[cur][3 * pt], d.X[cur][3 * pt + 1], d.X[cur][3 * pt + 2]};
+    for (int t = 0; t < pc.y; ++t) {
+      const int idx = pc.x + t * kWave + lane;
       double rho;
-      if (obs_rho(sh_cam + kCamVals * cam, X, d.lane_uv64[2 * idx], d.lane_uv64[2 * idx + 1], ki, d.inv_sigma,
+      if (obs_rho(sh_cam + kCamVals * d.ob_cam[idx], X, d.ob_uv64[2 * idx], d.ob_uv64[2 * idx + 1], ki, d.inv_sigma,
                   d.huber_dt, &rho)) acc += rho;
       else ++bad;
     }
@@ -624,13 +617,16 @@ __global__ void k_init(Batch bt) {
 
 // ---- point pass: damped point blocks --------------------------------------------
 //
-// One lane per observation, the observations of a point in consecutive lanes
-// of one wavefront.  Writes, per point, Q = (V + lambda D_V)^-1, g_p, D_V and
-// Z = sum of the intrinsic rows of W; per wavefront, the intrinsic-intrinsic
-// sums (U part of all observations, Schur part of all points).
+// One lane per point: the 64 points of a chunk have the same observation
+// count n, and the lane walks its point's observations in camera order (one
+// 64-lane row of the chunk's observation-major lanes each), so that the sums
+// V_j, g_j, Z_j stay in registers.  Writes, per point, Q = (V + lambda
+// D_V)^-1, g_p, D_V and Z = sum of the intrinsic rows of W; per wavefront,
+// the intrinsic-intrinsic sums (U part of all observations, Schur part of all
+// points).
 
 template <typename R, bool INTR, bool SC>
-__device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const R* scam, R* scr, int wgl, int wave,
+__device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const R* scam, int wgl, int wave,
                                            int lane) {
   constexpr int NK = kNk<SC>, NS = NK * (NK + 1) / 2, NI = NS + 3 * NK;
   constexpr int NV = INTR ? 9 + 3 * NK : 9;
@@ -642,71 +638,76 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
   const R cxo = SC ? (R)c.k[cur][3] : R(0), cyo = SC ? (R)c.k[cur][4] : R(0);
   const gptr<R> ptv = gmem(reinterpret_cast<R*>(d.ptv)), ptd = gmem(reinterpret_cast<R*>(d.ptd));
-  const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
-  const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.lane_uv64, d.lane_uv32);
+  const gptr<const int> ocam = gmem(d.ob_cam);
+  const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.ob_uv64, d.ob_uv32);
   // intrinsic sums: S (packed upper triangle, NS), g (NK), diag U (NK), Schur part of b (NK)
   R iv[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) iv[i] = R(0);
   bool fail = false;
-  const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
-  // The lane words of the next chunk are requested a chunk ahead; loads are
-  // unconditional (padding lanes read point 0, then zero what they read).
-  int pt_n = 0, meta_n = 0;
-  if (c0 + wave < c1) {
-    const int i0 = (c0 + wave) * kWave + lane;
-    pt_n = lpt[i0]; meta_n = lmeta[i0];
-  }
+  const int c0 = d.wg_chunk[wgl], c1 = d.wg_chunk[wgl + 1];
   for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
-    const int idx = ch * kWave + lane;
-    const int pt = pt_n, seg = meta_n, cam_l = meta_cam(seg);
-    if (ch + kWavesPerWG < c1) {
-      const int in = idx + kWavesPerWG * kWave;
-      pt_n = lpt[in]; meta_n = lmeta[in];
-    }
-    const bool valid = pt >= 0;
-    const int cam = valid ? cam_l : 0, ps = valid ? pt : 0;
-    const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
-    const bool head = valid && sb == lane;
-    const R X0r = Xs[3 * ps], X1r = Xs[3 * ps + 1], X2r = Xs[3 * ps + 2], ur = uvs[2 * idx], vr = uvs[2 * idx + 1];
+    const int4 pc = d.pchunk[ch];
+    const int n = pc.y;
+    // padding lanes read the chunk's first point and the padding lanes'
+    // camera 0 and pixel 0, then zero what they read
+    const bool valid = lane < pc.w;
+    const int pt = pc.z + (valid ? lane : 0);
+    const R X0r = Xs[3 * pt], X1r = Xs[3 * pt + 1], X2r = Xs[3 * pt + 2];
     const R X0 = valid ? X0r : R(0), X1 = valid ? X1r : R(0), X2 = valid ? X2r : R(0);
-    const R u = valid ? ur : R(0), v = valid ? vr : R(0);
-    ObsJ<R, NK> o;
-    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
-    const R w = o.w;
-    R wJp[2][3];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int t = 0; t < 3; ++t) wJp[i][t] = w * o.Jp[i][t];
-    R vals[NV];
-    vals[0] = fm(o.Jp[0][0], wJp[0][0], o.Jp[1][0] * wJp[1][0]);
-    vals[1] = fm(o.Jp[0][0], wJp[0][1], o.Jp[1][0] * wJp[1][1]);
-    vals[2] = fm(o.Jp[0][0], wJp[0][2], o.Jp[1][0] * wJp[1][2]);
-    vals[3] = fm(o.Jp[0][1], wJp[0][1], o.Jp[1][1] * wJp[1][1]);
-    vals[4] = fm(o.Jp[0][1], wJp[0][2], o.Jp[1][1] * wJp[1][2]);
-    vals[5] = fm(o.Jp[0][2], wJp[0][2], o.Jp[1][2] * wJp[1][2]);
-#pragma unroll
-    for (int t = 0; t < 3; ++t) vals[6 + t] = fm(wJp[0][t], o.e[0], wJp[1][t] * o.e[1]);
-    if constexpr (INTR) {
-#pragma unroll
-      for (int b = 0; b < NK; ++b)
-#pragma unroll
-        for (int t = 0; t < 3; ++t) vals[9 + 3 * b + t] = fm(o.Jk[0][b], wJp[0][t], o.Jk[1][b] * wJp[1][t]);
-    }
-    // segmented sums over the point's lanes (fixed order: first lane to last)
-    wave_sync();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) scr[i * kWave + lane] = vals[i];
-    wave_sync();
+    // the next observation's camera and pixel are requested one ahead
+    int idx = pc.x + lane;
+    int cam_n = ocam[idx];
+    R u_n = uvs[2 * idx], v_n = uvs[2 * idx + 1];
     R sum[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) sum[i] = R(0);
-    for (int t = 0; t < maxl; ++t) {
-      if (t < sl) {
-        const int src = sb + t;
+    for (int t = 0; t < n; ++t) {
+      const int cam = cam_n;
+      const R u = valid ? u_n : R(0), v = valid ? v_n : R(0);
+      if (t + 1 < n) {
+        idx += kWave;
+        cam_n = ocam[idx];
+        u_n = uvs[2 * idx];
+        v_n = uvs[2 * idx + 1];
+      }
+      ObsJ<R, NK> o;
+      obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
+      const R w = o.w;
+      R wJp[2][3];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) sum[i] += scr[i * kWave + src];
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) wJp[i][q] = w * o.Jp[i][q];
+      R vals[NV];
+      vals[0] = fm(o.Jp[0][0], wJp[0][0], o.Jp[1][0] * wJp[1][0]);
+      vals[1] = fm(o.Jp[0][0], wJp[0][1], o.Jp[1][0] * wJp[1][1]);
+      vals[2] = fm(o.Jp[0][0], wJp[0][2], o.Jp[1][0] * wJp[1][2]);
+      vals[3] = fm(o.Jp[0][1], wJp[0][1], o.Jp[1][1] * wJp[1][1]);
+      vals[4] = fm(o.Jp[0][1], wJp[0][2], o.Jp[1][1] * wJp[1][2]);
+      vals[5] = fm(o.Jp[0][2], wJp[0][2], o.Jp[1][2] * wJp[1][2]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) vals[6 + q] = fm(wJp[0][q], o.e[0], wJp[1][q] * o.e[1]);
+      if constexpr (INTR) {
+#pragma unroll
+        for (int b = 0; b < NK; ++b)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) vals[9 + 3 * b + q] = fm(o.Jk[0][b], wJp[0][q], o.Jk[1][b] * wJp[1][q]);
+      }
+      // the point's sums, in camera order
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sum[i] += vals[i];
+      if constexpr (INTR) {
+        int e = 0;
+#pragma unroll
+        for (int a = 0; a < NK; ++a) {
+          const R uaa = w * fm(o.Jk[0][a], o.Jk[0][a], o.Jk[1][a] * o.Jk[1][a]);
+          iv[e++] += uaa;
+#pragma unroll
+          for (int b = a + 1; b < NK; ++b) iv[e++] += w * fm(o.Jk[0][a], o.Jk[0][b], o.Jk[1][a] * o.Jk[1][b]);
+          iv[NS + a] += w * fm(o.Jk[0][a], o.e[0], o.Jk[1][a] * o.e[1]);
+          iv[NS + NK + a] += uaa;
+        }
       }
     }
     const R Dp[3] = {clampd(sum[0]), clampd(sum[3]), clampd(sum[5])};
@@ -717,7 +718,7 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
 #pragma unroll
       for (int i = 0; i < 6; ++i) Q[i] = R(0);
     }
-    if (head) {
+    if (valid) {
       R rec[kPtVals];
 #pragma unroll
       for (int i = 0; i < 6; ++i) rec[i] = Q[i];
@@ -735,33 +736,21 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
       }
       const R dr[4] = {Dp[0], Dp[1], Dp[2], R(0)};
       rec_store<4>(ptd + 4 * (size_t)pt, dr);
-    }
-    if constexpr (INTR) {
-      int e = 0;
-#pragma unroll
-      for (int a = 0; a < NK; ++a) {
-        const R uaa = w * fm(o.Jk[0][a], o.Jk[0][a], o.Jk[1][a] * o.Jk[1][a]);
-        iv[e++] += uaa;
-#pragma unroll
-        for (int b = a + 1; b < NK; ++b) iv[e++] += w * fm(o.Jk[0][a], o.Jk[0][b], o.Jk[1][a] * o.Jk[1][b]);
-        iv[NS + a] += w * fm(o.Jk[0][a], o.e[0], o.Jk[1][a] * o.e[1]);
-        iv[NS + NK + a] += uaa;
-      }
-      if (head) {
+      if constexpr (INTR) {
         R Z[NK][3], ZQ[NK][3];
 #pragma unroll
         for (int b = 0; b < NK; ++b)
 #pragma unroll
-          for (int t = 0; t < 3; ++t) Z[b][t] = sum[(9 + 3 * b + t) % NV];
+          for (int q = 0; q < 3; ++q) Z[b][q] = sum[(9 + 3 * b + q) % NV];
 #pragma unroll
         for (int b = 0; b < NK; ++b)
 #pragma unroll
-          for (int t = 0; t < 3; ++t) ZQ[b][t] = fm(Z[b][0], qel(Q, 0, t), fm(Z[b][1], qel(Q, 1, t), Z[b][2] * qel(Q, 2, t)));
-        int q = 0;
+          for (int q = 0; q < 3; ++q) ZQ[b][q] = fm(Z[b][0], qel(Q, 0, q), fm(Z[b][1], qel(Q, 1, q), Z[b][2] * qel(Q, 2, q)));
+        int e = 0;
 #pragma unroll
         for (int a = 0; a < NK; ++a)
 #pragma unroll
-          for (int b = a; b < NK; ++b, ++q) iv[q] -= fm(ZQ[a][0], Z[b][0], fm(ZQ[a][1], Z[b][1], ZQ[a][2] * Z[b][2]));
+          for (int b = a; b < NK; ++b, ++e) iv[e] -= fm(ZQ[a][0], Z[b][0], fm(ZQ[a][1], Z[b][1], ZQ[a][2] * Z[b][2]));
 #pragma unroll
         for (int a = 0; a < NK; ++a) iv[NS + 2 * NK + a] += fm(ZQ[a][0], sum[6], fm(ZQ[a][1], sum[7], ZQ[a][2] * sum[8]));
       }
@@ -778,15 +767,9 @@ __device__ __forceinline__ void point_pass(const SlotDesc& d, SlotCtl& c, const 
   }
 }
 
-// ---- point pass: damped point blocks --------------------------------------------
-//
-// One lane per observation, the observations of a point in consecutive lanes
-// of one wavefront.  Writes, per point, Q = (V + lambda D_V)^-1, g_p, Z = sum
-// of the intrinsic rows of W, and D_V; per wavefront, the intrinsic-intrinsic
-// sums (U part of all observations, Schur part of all points).
-// SC: the launch for self-calibrating clusters (f, cx or cy estimated); each
-// instantiation skips the other kind, so that the common one keeps its
-// register allocation.
+// The point pass over every cluster of the batch.  SC: the launch for
+// self-calibrating clusters (f, cx or cy estimated); each instantiation skips
+// the other kind, so that the common one keeps its register allocation.
 template <typename R, bool SC>
 __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   const int bx = xcd_block();
@@ -799,15 +782,13 @@ __global__ __launch_bounds__(kWG) void k_point(Batch bt) {
   SlotCtl& c = bt.ctl[s];
   if (c.status != ST_RUNNING || (d.sc != 0) != SC) return;
   R* scam = reinterpret_cast<R*>(smem);
-  R* scr_all = scam + bt.max_C * kCamVals;
   const int cur = c.cur;
   for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) scam[i] = (R)d.cam[cur][i];
   __syncthreads();
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  R* scr = scr_all + wave * (9 + 3 * kNk<SC>) * kWave;
-  if constexpr (SC) point_pass<R, true, true>(d, c, scam, scr, wgl, wave, lane);
-  else if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true, false>(d, c, scam, scr, wgl, wave, lane);
-  else point_pass<R, false, false>(d, c, scam, scr, wgl, wave, lane);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  if constexpr (SC) point_pass<R, true, true>(d, c, scam, wgl, wave, lane);
+  else if ((d.kcol0 >= 0) || (d.kcol1 >= 0)) point_pass<R, true, false>(d, c, scam, wgl, wave, lane);
+  else point_pass<R, false, false>(d, c, scam, wgl, wave, lane);
 }
 
 // ---- block passes: camera-diagonal and camera-pair blocks of the Schur complement ----
@@ -2288,8 +2269,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   double* tcam = reinterpret_cast<double*>(smem);               // trial cameras FP64
   R* scam = reinterpret_cast<R*>(tcam + bt.max_C * kCamVals);  // current cameras
   R* sdc = scam + bt.max_C * kCamVals;                         // camera update
-  R* scr_all = sdc + bt.max_m + 2;
-  int* scol = reinterpret_cast<int*>(scr_all + kWavesPerWG * 3 * kWave);
+  int* scol = reinterpret_cast<int*>(sdc + bt.max_m + 2);
   const int cur = c.cur, nxt = 1 - cur;
   for (int i = threadIdx.x; i < d.C * kCamVals; i += kWG) {
     tcam[i] = d.cam[nxt][i];
@@ -2298,8 +2278,7 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
   for (int i = threadIdx.x; i < d.m; i += kWG) sdc[i] = (R)d.dc[i];
   for (int i = threadIdx.x; i < d.C; i += kWG) scol[i] = d.cam_col[i];
   __syncthreads();
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  R* scr = scr_all + wave * 3 * kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const double lambda = c.lambda;
   const R f = SC ? (R)c.k[cur][2] : (R)d.f, is = (R)d.inv_sigma, dt = (R)d.huber_dt;
   const R k1 = (R)c.k[cur][0], k2 = (R)c.k[cur][1];
@@ -2310,46 +2289,48 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
 #pragma unroll
   for (int t = 0; t < NK; ++t) dk[t] = d.kcolt[t] >= 0 ? sdc[d.kcolt[t]] : R(0);
   const gptr<const R> ptv = gmem(reinterpret_cast<const R*>(d.ptv)), ptd = gmem(reinterpret_cast<const R*>(d.ptd));
-  const gptr<const int> lpt = gmem(d.lane_pt), lmeta = gmem(d.lane_meta);
-  const gptr<const double> Xc = gmem((const double*)d.X[cur]), uv64 = gmem((const double*)d.lane_uv64);
+  const gptr<const int> ocam = gmem(d.ob_cam);
+  const gptr<const double> Xc = gmem((const double*)d.X[cur]), uv64 = gmem((const double*)d.ob_uv64);
   const gptr<double> Xn64 = gmem(d.X[nxt]);
   const gptr<float> Xn32 = gmem(d.X32[nxt]);
   double rho_sum = 0.0, pred_sum = 0.0;
   int bad = 0;
-  const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
-  // The lane words of the next chunk are requested a chunk ahead; loads are
-  // unconditional (padding lanes read point 0 and do not use it).
-  int pt_n = 0, meta_n = 0;
-  if (c0 + wave < c1) {
-    const int i0 = (c0 + wave) * kWave + lane;
-    pt_n = lpt[i0]; meta_n = lmeta[i0];
-  }
+  const int c0 = d.wg_chunk[wgl], c1 = d.wg_chunk[wgl + 1];
+  // one lane per point of a chunk: its observations twice, first for
+  // t = sum_obs W^T dc (FP32), then for the FP64 trial residuals at the moved
+  // point.  Padding lanes read the chunk's first point and the padding
+  // lanes' camera 0 and pixel 0, and do not use them.
   for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
-    const int idx = ch * kWave + lane;
-    const int pt = pt_n, seg = meta_n, cam_l = meta_cam(seg);
-    if (ch + kWavesPerWG < c1) {
-      const int in = idx + kWavesPerWG * kWave;
-      pt_n = lpt[in]; meta_n = lmeta[in];
-    }
-    const bool valid = pt >= 0;
-    const int cam = valid ? cam_l : 0, ps = valid ? pt : 0;
-    const int sb = seg_first(seg), sl = seg_len(seg), maxl = chunk_maxlen(seg);
-    const bool head = valid && sb == lane;
+    const int4 pc = d.pchunk[ch];
+    const int n = pc.y;
+    const bool valid = lane < pc.w;
+    const int pt = pc.z + (valid ? lane : 0);
     // The FP64 point and pixel serve both models: their FP32 shadows are these
     // values rounded, so they are not read again.
-    const double Xr[3] = {Xc[3 * ps], Xc[3 * ps + 1], Xc[3 * ps + 2]}, ur = uv64[2 * idx], vr = uv64[2 * idx + 1];
+    const double Xr[3] = {Xc[3 * pt], Xc[3 * pt + 1], Xc[3 * pt + 2]};
     R pv[12], dv[4];
-    rec_load<sizeof(R) == 8 ? 10 : 12>(ptv + kPtVals * (size_t)ps, pv);
-    rec_load<4>(ptd + 4 * (size_t)ps, dv);
+    rec_load<sizeof(R) == 8 ? 10 : 12>(ptv + kPtVals * (size_t)pt, pv);
+    rec_load<4>(ptd + 4 * (size_t)pt, dv);
     const double Xd[3] = {valid ? Xr[0] : 0.0, valid ? Xr[1] : 0.0, valid ? Xr[2] : 0.0};
-    const double ud = valid ? ur : 0.0, vd = valid ? vr : 0.0;
-    const R X0 = (R)Xd[0], X1 = (R)Xd[1], X2 = (R)Xd[2], u = (R)ud, v = (R)vd;
-    ObsJ<R, NK> o;
-    obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
-    const int fi = valid ? scol[cam] : -1;
-    // t = W_c^T dc + W_i^T dk, with W = w J_side^T J_p
-    R tv[3] = {0, 0, 0};
-    {
+    const R X0 = (R)Xd[0], X1 = (R)Xd[1], X2 = (R)Xd[2];
+    int idx = pc.x + lane;
+    int cam_n = ocam[idx];
+    double u_n = uv64[2 * idx], v_n = uv64[2 * idx + 1];
+    R ts[3] = {0, 0, 0};
+    for (int t = 0; t < n; ++t) {
+      const int cam = cam_n;
+      const double ud = valid ? u_n : 0.0, vd = valid ? v_n : 0.0;
+      if (t + 1 < n) {
+        idx += kWave;
+        cam_n = ocam[idx];
+        u_n = uv64[2 * idx];
+        v_n = uv64[2 * idx + 1];
+      }
+      const R u = (R)ud, v = (R)vd;
+      ObsJ<R, NK> o;
+      obs_model<R, SC>(scam + kCamVals * cam, X0, X1, X2, u, v, f, k1, k2, is, dt, valid, o, cxo, cyo);
+      const int fi = valid ? scol[cam] : -1;
+      // t = W_c^T dc + W_i^T dk, with W = w J_side^T J_p
       R jd[2] = {0, 0};   // J_side * d (2-vector)
       if (fi >= 0) {
 #pragma unroll
@@ -2368,37 +2349,32 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
         jd[0] = fm(o.Jk[0][0], dk[0], fm(o.Jk[0][1], dk[1], jd[0]));
         jd[1] = fm(o.Jk[1][0], dk[0], fm(o.Jk[1][1], dk[1], jd[1]));
       }
+      // the point's sum, in camera order
 #pragma unroll
-      for (int t = 0; t < 3; ++t) tv[t] = o.w * fm(o.Jp[0][t], jd[0], o.Jp[1][t] * jd[1]);
+      for (int q = 0; q < 3; ++q) ts[q] += o.w * fm(o.Jp[0][q], jd[0], o.Jp[1][q] * jd[1]);
     }
-    wave_sync();
-    for (int t = 0; t < 3; ++t) scr[t * kWave + lane] = tv[t];
-    wave_sync();
-    R ts[3] = {0, 0, 0};
-    for (int t = 0; t < maxl; ++t) {
-      if (t < sl) {
-        const int src = sb + t;
-        for (int q = 0; q < 3; ++q) ts[q] += scr[q * kWave + src];
-      }
-    }
-    double Xn[3] = {Xd[0], Xd[1], Xd[2]};
-    if (valid) {
+    if (!valid) continue;
+    double Xn[3];
+    {
       const R* Q = pv;
       const R rr[3] = {-pv[6] - ts[0], -pv[7] - ts[1], -pv[8] - ts[2]};
       R dp[3];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) dp[t] = fm(qel(Q, t, 2), rr[2], fm(qel(Q, t, 1), rr[1], qel(Q, t, 0) * rr[0]));
-      for (int t = 0; t < 3; ++t) Xn[t] = Xd[t] + (double)dp[t];
-      if (head) {
-        for (int t = 0; t < 3; ++t) {
-          const double dd = (double)dp[t];
-          pred_sum += dd * (lambda * (double)dv[t] * dd - (double)pv[6 + t]);
-          Xn64[3 * pt + t] = Xn[t];
-          Xn32[3 * pt + t] = (float)Xn[t];
-        }
+      for (int q = 0; q < 3; ++q) dp[q] = fm(qel(Q, q, 2), rr[2], fm(qel(Q, q, 1), rr[1], qel(Q, q, 0) * rr[0]));
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double dd = (double)dp[q];
+        Xn[q] = Xd[q] + dd;
+        pred_sum += dd * (lambda * (double)dv[q] * dd - (double)pv[6 + q]);
+        Xn64[3 * pt + q] = Xn[q];
+        Xn32[3 * pt + q] = (float)Xn[q];
       }
+    }
+    for (int t = 0; t < n; ++t) {
+      const int i2 = pc.x + t * kWave + lane;
       double rho;
-      if (obs_rho(tcam + kCamVals * cam, Xn, ud, vd, tki, d.inv_sigma, d.huber_dt, &rho)) rho_sum += rho;
+      if (obs_rho(tcam + kCamVals * ocam[i2], Xn, uv64[2 * i2], uv64[2 * i2 + 1], tki, d.inv_sigma, d.huber_dt, &rho))
+        rho_sum += rho;
       else ++bad;
     }
   }
@@ -2502,30 +2478,32 @@ __global__ __launch_bounds__(kWG) void k_stats(Batch bt) {
   const double* ki = c.k[cur];
   const double lim = 3.0 * d.huber_dt / d.inv_sigma;   // 3 delta, pixels
   double acc[kStatVals] = {0, 0, 0, 0, 0, 0};
-  const int c0 = wgl * d.cpw, c1 = min(c0 + d.cpw, d.n_chunks);
-  for (int ch = c0 + wave; ch < c1; ch += kWavesPerWG) {
-    const int idx = ch * kWave + lane;
-    const int pt = d.lane_pt[idx];
-    if (pt < 0) continue;
-    const double* cam = sh_cam + kCamVals * meta_cam(d.lane_meta[idx]);
+  for (int ch = d.wg_chunk[wgl] + wave; ch < d.wg_chunk[wgl + 1]; ch += kWavesPerWG) {
+    const int4 pc = d.pchunk[ch];
+    if (lane >= pc.w) continue;
+    const int pt = pc.z + lane;
     const double X[3] = {d.X[cur][3 * pt], d.X[cur][3 * pt + 1], d.X[cur][3 * pt + 2]};
-    const double d0 = X[0] - cam[9], d1 = X[1] - cam[10], d2 = X[2] - cam[11];
-    const double x = cam[0] * d0 + cam[3] * d1 + cam[6] * d2;
-    const double y = cam[1] * d0 + cam[4] * d1 + cam[7] * d2;
-    const double z = cam[2] * d0 + cam[5] * d1 + cam[8] * d2;
-    if (!(z > 0.0)) continue;
-    const double a = x / z, b = y / z, r2 = a * a + b * b;
-    const double D = 1.0 + ki[0] * r2 + ki[1] * r2 * r2;
-    const double ex = ki[2] * D * a + ki[3] - d.lane_uv64[2 * idx];
-    const double ey = ki[2] * D * b + ki[4] - d.lane_uv64[2 * idx + 1];
-    const double e2 = ex * ex + ey * ey, e = sqrt(e2);
-    acc[0] += 1.0;
-    acc[1] += e;
-    acc[2] += e2;
-    if (e <= lim) {
-      acc[3] += 1.0;
-      acc[4] += e;
-      acc[5] += e2;
+    for (int t = 0; t < pc.y; ++t) {
+      const int idx = pc.x + t * kWave + lane;
+      const double* cam = sh_cam + kCamVals * d.ob_cam[idx];
+      const double d0 = X[0] - cam[9], d1 = X[1] - cam[10], d2 = X[2] - cam[11];
+      const double x = cam[0] * d0 + cam[3] * d1 + cam[6] * d2;
+      const double y = cam[1] * d0 + cam[4] * d1 + cam[7] * d2;
+      const double z = cam[2] * d0 + cam[5] * d1 + cam[8] * d2;
+      if (!(z > 0.0)) continue;
+      const double a = x / z, b = y / z, r2 = a * a + b * b;
+      const double D = 1.0 + ki[0] * r2 + ki[1] * r2 * r2;
+      const double ex = ki[2] * D * a + ki[3] - d.ob_uv64[2 * idx];
+      const double ey = ki[2] * D * b + ki[4] - d.ob_uv64[2 * idx + 1];
+      const double e2 = ex * ex + ey * ey, e = sqrt(e2);
+      acc[0] += 1.0;
+      acc[1] += e;
+      acc[2] += e2;
+      if (e <= lim) {
+        acc[3] += 1.0;
+        acc[4] += e;
+        acc[5] += e2;
+      }
     }
   }
   __shared__ double red[kWavesPerWG][kStatVals];
@@ -2575,13 +2553,12 @@ __global__ void k_export(Batch bt) {
 
 template <typename R, bool SC>
 size_t point_smem(const Batch& b) {
-  return sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)kWavesPerWG * (9 + 3 * kNk<SC>) * kWave);
+  return sizeof(R) * (size_t)b.max_C * kCamVals;
 }
 
 template <typename R>
 size_t backsub_smem(const Batch& b) {
-  return sizeof(double) * (size_t)b.max_C * kCamVals +
-         sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)b.max_m + 2 + (size_t)kWavesPerWG * 3 * kWave) +
+  return sizeof(double) * (size_t)b.max_C * kCamVals + sizeof(R) * ((size_t)b.max_C * kCamVals + (size_t)b.max_m + 2) +
          sizeof(int) * (size_t)b.max_C;
 }
 

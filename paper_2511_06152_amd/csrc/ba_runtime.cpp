@@ -122,7 +122,7 @@ constexpr size_t kAbsent = ~(size_t)0;   // an array the slot does not hold
 // first, [0, upload_end), so that one copy of the cluster's upload image
 // fills them; the arrays the device computes follow.
 struct Layout {
-  size_t lane_pt, lane_meta, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
+  size_t pchunk, wg_chunk, ob_cam, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
       cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, pcg_part, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, lambda_log, acc_log, stat_part, out, upload_end, total;
@@ -146,8 +146,9 @@ Layout make_layout(const Staged& s, bool mixed) {
   const size_t nnzb = s.bcol.size();
   // from the host.  In mixed mode the camera- and pair-lane pixels come as
   // FP32 (principal point already subtracted) and have no FP64 copy.
-  l.lane_pt = take(4 * (size_t)s.L);
-  l.lane_meta = take(4 * (size_t)s.L);
+  l.pchunk = take(sizeof(int4) * s.pchunk.size());
+  l.wg_chunk = take(4 * s.wg_chunk.size());
+  l.ob_cam = take(4 * (size_t)s.L);
   l.uv64 = take(16 * (size_t)s.L);
   l.cl_pt = take(4 * (size_t)s.Lc);
   l.cl_uv64 = mixed ? kAbsent : take(16 * (size_t)s.Lc);
@@ -214,9 +215,10 @@ void pack_upload(const Staged& s, bool mixed, const Layout& lay, char* dst) {
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(dst + off, src, bytes);
   };
-  put(lay.lane_pt, s.lane_pt.data(), 4 * (size_t)s.L);
-  put(lay.lane_meta, s.lane_meta.data(), 4 * (size_t)s.L);
-  put(lay.uv64, s.lane_uv.data(), 16 * (size_t)s.L);
+  put(lay.pchunk, s.pchunk.data(), sizeof(int4) * s.pchunk.size());
+  put(lay.wg_chunk, s.wg_chunk.data(), 4 * s.wg_chunk.size());
+  put(lay.ob_cam, s.ob_cam.data(), 4 * (size_t)s.L);
+  put(lay.uv64, s.ob_uv.data(), 16 * (size_t)s.L);
   put(lay.cl_pt, s.cl_pt.data(), 4 * (size_t)s.Lc);
   put(lay.ql_pt, s.ql_pt.data(), 4 * (size_t)s.Lq);
   if (mixed) {
@@ -717,7 +719,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   char* base = c->arena_base + off;
   SlotDesc& d = sl.desc;
   d = SlotDesc{};
-  d.C = s.C; d.P = s.P; d.L = s.L; d.n_chunks = s.n_chunks; d.n_wg = lay.n_wg; d.cpw = c->opt.chunks_per_wg;
+  d.C = s.C; d.P = s.P; d.L = s.L; d.n_chunks = s.n_chunks; d.n_wg = lay.n_wg;
   d.m = s.m; d.n_free = s.n_free; d.kcol0 = s.kcol0; d.kcol1 = s.kcol1;
   for (int t = 0; t < kIntr; ++t) d.kcolt[t] = s.kcolt[t];
   d.sc = s.sc;
@@ -732,10 +734,11 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.lambda0 = std::isnan(s.lambda0) ? (std::isnan(c->res_lambda) ? 1e-4 : c->res_lambda) : s.lambda0;
   d.sparse = s.sparse; d.nnzb = (int)s.bcol.size();
   d.pcg_max_iters = c->opt.pcg_max_iters; d.pcg_tol = c->opt.pcg_tol;
-  d.lane_pt = (const int*)(base + lay.lane_pt);
-  d.lane_meta = (const int*)(base + lay.lane_meta);
-  d.lane_uv64 = (double*)(base + lay.uv64);
-  d.lane_uv32 = (float*)(base + lay.uv32);
+  d.pchunk = (const int4*)(base + lay.pchunk);
+  d.wg_chunk = (const int*)(base + lay.wg_chunk);
+  d.ob_cam = (const int*)(base + lay.ob_cam);
+  d.ob_uv64 = (double*)(base + lay.uv64);
+  d.ob_uv32 = (float*)(base + lay.uv32);
   d.cl_pt = (const int*)(base + lay.cl_pt);
   d.cl_uv64 = lay.cl_uv64 == kAbsent ? nullptr : (double*)(base + lay.cl_uv64);
   d.cl_uv32 = (float*)(base + lay.cl_uv32);

@@ -116,9 +116,14 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
     const int cam = c->obs_cam[o], pt = c->obs_pt[o];
     if (cam < 0 || cam >= C || pt < 0 || pt >= P) { err = "observation index out of range"; return BA_E_ARG; }
   }
-  // Internal point order: Morton (z-order) of the initial ground position, so
-  // that a camera's observations touch nearby point records.  Ties keep the
-  // caller's order (LSD radix sort of key << 32 | index on the key bits).
+  // Internal point order: by the number of observations, then Morton (z-)
+  // order of the initial ground position, so that the 64 points of a
+  // point chunk have the same observation count and a camera's observations
+  // touch nearby point records.  Ties keep the caller's order (LSD radix sort
+  // of key << 32 | index on the key bits, then a stable counting sort by count).
+  std::vector<int> nobs(P, 0);
+  for (int o = 0; o < O; ++o)
+    if (++nobs[c->obs_pt[o]] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
   {
     double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
     for (int j = 0; j < P; ++j)
@@ -145,8 +150,14 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
       for (int j = 0; j < P; ++j) tmp[cnt_d[(kj[j] >> shift) & 2047u]++] = kj[j];
       kj.swap(tmp);
     }
+    int cls[BA_MAX_OBS_PER_POINT + 2] = {0};
+    for (int j = 0; j < P; ++j) ++cls[nobs[j] + 1];
+    for (int n = 0; n <= BA_MAX_OBS_PER_POINT; ++n) cls[n + 1] += cls[n];
     s.pt_orig.resize(P);
-    for (int n = 0; n < P; ++n) s.pt_orig[n] = (int)(uint32_t)kj[n];
+    for (int r = 0; r < P; ++r) {
+      const int j = (int)(uint32_t)kj[r];
+      s.pt_orig[cls[nobs[j]]++] = j;
+    }
   }
   std::vector<int> inv(P), opt(O);
   for (int n = 0; n < P; ++n) inv[s.pt_orig[n]] = n;
@@ -154,11 +165,9 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   s.X.resize(3 * (size_t)P);
   for (int n = 0; n < P; ++n)
     for (int t = 0; t < 3; ++t) s.X[3 * (size_t)n + t] = c->X[3 * (size_t)s.pt_orig[n] + t];
-  // observations per point
+  // observations per point (internal order)
   std::vector<int> cnt(P + 1, 0);
-  for (int o = 0; o < O; ++o)
-    if (++cnt[opt[o] + 1] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
-  for (int j = 0; j < P; ++j) cnt[j + 1] += cnt[j];
+  for (int n = 0; n < P; ++n) cnt[n + 1] = cnt[n] + nobs[s.pt_orig[n]];
   // observations in (point, camera) order: a counting sort by camera, then a
   // stable one by point; then their camera, pixel and point in that order
   std::vector<int> order(O);
@@ -181,38 +190,44 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
       suv[2 * (size_t)t + 1] = c->obs_uv[2 * (size_t)o + 1];
       if (t > cnt[j] && scam[t] == scam[t - 1]) { err = "a camera observes one point twice"; return BA_E_ARG; }
     }
-  // greedy packing into 64-lane chunks
-  std::vector<int> start(P, 0);
-  int pos = 0;
-  for (int j = 0; j < P; ++j) {
-    const int n = cnt[j + 1] - cnt[j];
-    if (n == 0) continue;
-    if ((pos % kWave) + n > kWave) pos = (int)align_up(pos, kWave);
-    start[j] = pos;
-    pos += n;
+  // point chunks: 64 consecutive points of one observation count n, their
+  // observations stored observation-major (observation t of the chunk's lane l
+  // at first + 64 t + l); the last chunk of a count is padded with lanes
+  // that hold camera 0 and pixel 0
+  for (int pb = 0; pb < P;) {
+    const int n = cnt[pb + 1] - cnt[pb];
+    int pe = pb + 1;
+    while (pe < P && cnt[pe + 1] - cnt[pe] == n) ++pe;
+    if (n > 0)
+      for (int p0 = pb; p0 < pe; p0 += kWave) {
+        s.pchunk.push_back(I4{s.L, n, p0, std::min(kWave, pe - p0)});
+        s.L += kWave * n;
+      }
+    pb = pe;
   }
-  s.L = (int)align_up(pos, kWave);
-  s.n_chunks = s.L / kWave;
-  s.lane_pt.assign(s.L, -1);
-  // lane word: camera (9 bits) | segment start in the chunk << 9 (6 bits) |
-  // segment length << 15 (7 bits) | the chunk's longest segment << 22 (7 bits)
-  s.lane_meta.resize(s.L);
-  s.lane_uv.assign(2 * (size_t)s.L, 0.0);
-  for (int i = 0; i < s.L; ++i) s.lane_meta[i] = ((i % kWave) << 9) | (1 << 15);
-  std::vector<int> chunk_max(s.n_chunks, 1);
-  for (int j = 0; j < P; ++j) {
-    const int n = cnt[j + 1] - cnt[j];
-    for (int t = 0; t < n; ++t) {
-      const int so = cnt[j] + t, lane = start[j] + t;
-      s.lane_pt[lane] = j;
-      s.lane_meta[lane] = scam[so] | ((start[j] % kWave) << 9) | (n << 15);
-      chunk_max[lane / kWave] = std::max(chunk_max[lane / kWave], n);
-      s.lane_uv[2 * (size_t)lane] = suv[2 * (size_t)so];
-      s.lane_uv[2 * (size_t)lane + 1] = suv[2 * (size_t)so + 1];
+  s.n_chunks = (int)s.pchunk.size();
+  s.ob_cam.assign(s.L, 0);
+  s.ob_uv.assign(2 * (size_t)s.L, 0.0);
+  for (const I4& ch : s.pchunk)
+    for (int l = 0; l < ch.w; ++l)
+      for (int t = 0; t < ch.y; ++t) {
+        const int so = cnt[ch.z + l] + t;
+        const size_t lane = (size_t)ch.x + (size_t)kWave * t + l;
+        s.ob_cam[lane] = scam[so];
+        s.ob_uv[2 * lane] = suv[2 * (size_t)so];
+        s.ob_uv[2 * lane + 1] = suv[2 * (size_t)so + 1];
+      }
+  // point-pass workgroups: runs of whole chunks holding at least cpw * 64
+  // observation lanes each
+  s.wg_chunk.assign(1, 0);
+  for (int ch = 0, lanes = 0; ch < s.n_chunks; ++ch) {
+    lanes += kWave * s.pchunk[ch].y;
+    if (lanes >= cpw * kWave || ch + 1 == s.n_chunks) {
+      s.wg_chunk.push_back(ch + 1);
+      lanes = 0;
     }
   }
-  for (int i = 0; i < s.L; ++i) s.lane_meta[i] |= chunk_max[i / kWave] << 22;
-  s.n_wg = (s.n_chunks + cpw - 1) / cpw;
+  s.n_wg = (int)s.wg_chunk.size() - 1;
   const bool intr = s.m > 6 * s.n_free;   // an intrinsic is estimated
   s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
   s.nb = (s.m + kSolveTb - 1) / kSolveTb;

@@ -1,7 +1,7 @@
 // Host layout of a submitted cluster (no HIP: also built alone for the host
 // tests under the sanitizers).  Validates a ba_cluster and builds the work
-// lists the kernels read: point lanes, camera lanes, pair lanes, tasks and
-// reduction targets, the Morton point order, and for the conjugate-gradient
+// lists the kernels read: point chunks, camera lanes, pair lanes, tasks and
+// reduction targets, the point order (observation count, then Morton), and for the conjugate-gradient
 // solve the block-CSR structure of the reduced camera system.  Not part of
 // the public ABI.
 #pragma once
@@ -33,8 +33,12 @@ struct Staged {
   std::vector<double> X;         // [3P] internal point order
   std::vector<int> pt_orig;      // [P] caller index of each internal point
   std::vector<int> cam_col;      // [C]
-  std::vector<int> lane_pt, lane_meta;
-  std::vector<double> lane_uv;   // [2L]
+  // point chunks: {first observation lane, observations per point n, first
+  // point, valid points}; observation t of lane l at first + 64 t + l
+  std::vector<I4> pchunk;        // [n_chunks]
+  std::vector<int> wg_chunk;     // [n_wg + 1] first chunk of each point-pass workgroup
+  std::vector<int> ob_cam;       // [L] camera of each observation lane (0 for padding)
+  std::vector<double> ob_uv;     // [2L] raw pixels (0 for padding)
   int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
   std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
   std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
@@ -67,8 +71,10 @@ uint64_t mix_id(int64_t id);
 bool ids_unique(const int64_t* id, int n);
 
 // Validates the cluster and builds its work lists (integer bookkeeping only):
-//  * point lanes: observations sorted by (point, camera), packed greedily into
-//    64-lane chunks so that no point's observations straddle a chunk;
+//  * point chunks: points sorted by observation count, then Morton order,
+//    cut into chunks of 64 points of one count n; the chunk's observations
+//    stored observation-major (the t-th of each point, in camera order, in
+//    one 64-lane row), and chunks grouped into point-pass workgroups;
 //  * camera lanes: observations of each free camera in point order, each
 //    camera's run padded to whole chunks, cut into tasks of <= cpt chunks;
 //  * pair lanes: the observation pairs of each point whose two cameras are

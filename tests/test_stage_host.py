@@ -4,10 +4,12 @@ UndefinedBehaviorSanitizer (and, for concurrent layouts, ThreadSanitizer),
 run on seeded scenes, and its output checked against the invariants the
 kernels rely on (CPU only):
 
-  * every observation sits in exactly one point lane, with its camera and
-    pixel; lanes of a point are consecutive and inside one 64-lane chunk;
-    the lane word's segment start, length and the chunk's longest segment
-    are right;
+  * points are ordered by observation count, then Morton order; each point
+    chunk holds up to 64 consecutive points of one count n, and observation
+    t (camera order) of its lane l sits at the chunk's first lane + 64 t + l,
+    with its camera and pixel: every observation exactly once, padding lanes
+    camera 0 and pixel 0; the point-pass workgroups cover the chunks in
+    order;
   * each free camera's lanes hold all its observations, in point order,
     its run padded to whole chunks;
   * the pair lanes hold every pair of observations of one point whose
@@ -84,21 +86,21 @@ def run(tools, sc, cpw=16, cpt=4, solver=0, threads=1, exe=None):
         buf = fh.read()
     hdr = np.frombuffer(buf[:48], np.int32)
     pos = 48
-    names = ["err", "pt_orig", "lane_pt", "lane_meta", "lane_uv", "cl_pt", "cl_uv", "ql_pt", "ql_uv", "tasks",
+    names = ["err", "pt_orig", "pchunk", "wg_chunk", "ob_cam", "ob_uv", "cl_pt", "cl_uv", "ql_pt", "ql_uv", "tasks",
              "targets", "cam_col", "brow", "bcol"]
-    types = [np.int8, np.int32, np.int32, np.int32, np.float64, np.int32, np.float64, np.int32, np.float64, np.int32,
+    types = [np.int8, np.int32, np.int32, np.int32, np.int32, np.float64, np.int32, np.float64, np.int32, np.float64, np.int32,
              np.int32, np.int32, np.int32, np.int32]
     out = dict(zip(["rc", "L", "n_chunks", "Lc", "Lq", "n_tasks", "n_targets", "m", "n_free", "sparse",
                     "n_cam_tasks", "n_wg"], hdr.tolist()))
     for name, dt in zip(names, types):
         if pos >= len(buf):
             break
-        n = int(np.frombuffer(buf[pos:pos + 8], np.int64)[0]) * (4 if name in ("tasks", "targets") else 1)
+        n = int(np.frombuffer(buf[pos:pos + 8], np.int64)[0]) * (4 if name in ("tasks", "targets", "pchunk") else 1)
         pos += 8
         out[name] = np.frombuffer(buf[pos:pos + n * np.dtype(dt).itemsize], dt).copy()
         pos += n * np.dtype(dt).itemsize
     out["err"] = bytes(out["err"].astype(np.uint8)).decode()
-    for key in ("tasks", "targets"):
+    for key in ("tasks", "targets", "pchunk"):
         if key in out:
             out[key] = out[key].reshape(-1, 4)
     return out
@@ -110,30 +112,42 @@ def check_layout(sc, lay):
     inv = np.empty(P, np.int64)
     inv[lay["pt_orig"]] = np.arange(P)                 # caller point -> internal point
     assert np.array_equal(np.sort(lay["pt_orig"]), np.arange(P))
-    # point lanes: every observation exactly once, with its camera and pixel
-    L = lay["L"]
-    assert L % WAVE == 0 and lay["n_chunks"] == L // WAVE
-    pt, meta, uv = lay["lane_pt"], lay["lane_meta"], lay["lane_uv"].reshape(-1, 2)
-    real = pt >= 0
-    assert real.sum() == O
-    got = sorted(zip(pt[real].tolist(), (meta[real] & 511).tolist(), uv[real, 0].tolist(), uv[real, 1].tolist()))
+    # point order: by observation count (never decreasing)
+    nobs = np.bincount(inv[sc["obs_pt"]], minlength=P)
+    assert np.all(np.diff(nobs) >= 0)
+    # point chunks: consecutive points of one count, 64 at most, lanes in order
+    L, pc = lay["L"], lay["pchunk"]
+    assert lay["n_chunks"] == len(pc)
+    first_pt = nobs.tolist().index(next((n for n in nobs if n > 0), 0)) if np.any(nobs > 0) else P
+    lane = 0
+    pnext = first_pt
+    for ch in pc:
+        off, n, p0, nv = (int(x) for x in ch)
+        assert off == lane and p0 == pnext and 1 <= nv <= WAVE and n >= 1
+        assert np.all(nobs[p0:p0 + nv] == n)
+        assert nv == WAVE or p0 + nv == P or nobs[p0 + nv] != n     # only a count's last chunk is partial
+        lane += WAVE * n
+        pnext = p0 + nv
+    assert lane == L and pnext == P
+    # every observation exactly once, with its camera and pixel, cameras
+    # ascending along a point's lanes; padding lanes hold camera 0 and pixel 0
+    cam, uv = lay["ob_cam"], lay["ob_uv"].reshape(-1, 2)
+    got, pad = [], []
+    for off, n, p0, nv in pc:
+        for l in range(WAVE):
+            idx = off + WAVE * np.arange(n) + l
+            if l < nv:
+                assert np.all(np.diff(cam[idx]) > 0)
+                got += [(p0 + l, int(cam[i]), float(uv[i, 0]), float(uv[i, 1])) for i in idx]
+            else:
+                pad += idx.tolist()
     want = sorted(zip(inv[sc["obs_pt"]].tolist(), sc["obs_cam"].tolist(), sc["obs_uv"][:, 0].tolist(),
                       sc["obs_uv"][:, 1].tolist()))
-    assert got == want
-    # a point's lanes are consecutive, inside one chunk, sorted by camera; the lane word's segment fields
-    lanes = np.nonzero(real)[0]
-    for j in np.unique(pt[real]):
-        idx = lanes[pt[lanes] == j]
-        assert np.array_equal(idx, np.arange(idx[0], idx[0] + idx.size))
-        assert idx[0] // WAVE == idx[-1] // WAVE
-        cams = meta[idx] & 511
-        assert np.all(np.diff(cams) > 0)
-        assert np.all(((meta[idx] >> 9) & 63) == idx[0] % WAVE) and np.all(((meta[idx] >> 15) & 127) == idx.size)
-    for ch in range(lay["n_chunks"]):
-        m = meta[ch * WAVE:(ch + 1) * WAVE]
-        p = pt[ch * WAVE:(ch + 1) * WAVE]
-        longest = max([int((x >> 15) & 127) for x, q in zip(m, p) if q >= 0], default=1)
-        assert np.all(((m >> 22) & 127) == longest)
+    assert sorted(got) == want
+    assert np.all(cam[pad] == 0) and np.all(uv[pad] == 0)
+    # point-pass workgroups: increasing chunk ranges covering every chunk
+    wg = lay["wg_chunk"]
+    assert wg[0] == 0 and wg[-1] == len(pc) and np.all(np.diff(wg) >= 1) and len(wg) == lay["n_wg"] + 1
     # camera lanes: each free camera's observations in point order, runs padded to chunks
     free = np.nonzero(sc["fixed"] == 0)[0]
     col = lay["cam_col"]
@@ -205,7 +219,7 @@ def test_layout_invariants_under_sanitizers(tools, name):
     check_layout(sc, run(tools, sc, cpw=3, cpt=1))       # other chunk and task sizes
 
 
-def test_point_with_64_observations_fills_a_chunk(tools):
+def test_points_with_64_observations_share_a_chunk(tools):
     rng = np.random.default_rng(5)
     C, P = 64, 40
     sc = A.make_scene(A.spec_micro(n_points=5), 3)
@@ -224,8 +238,8 @@ def test_point_with_64_observations_fills_a_chunk(tools):
               prior_sigma=np.ones((C, 6)), fixed=fixed, obs_cam=oc, obs_pt=op,
               obs_uv=A.project_obs(R, T, X, (0.0, 0.0), oc, op), intr_mask=0)
     lay = check_layout(sc, run(tools, sc))
-    full = [ch for ch in range(lay["n_chunks"]) if ((lay["lane_meta"][ch * WAVE] >> 15) & 127) == 64]
-    assert len(full) == P // 5
+    full = [ch for ch in lay["pchunk"] if ch[1] == 64]
+    assert len(full) == 1 and full[0][3] == P // 5
 
 
 def test_conjugate_gradient_block_structure(tools):
