@@ -774,6 +774,8 @@ def main():
                     help="host threads laying out the clusters submitted to the serving loops (0: the caller's)")
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
     ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
+    ap.add_argument("--chunks-per-wg", type=int, default=16,
+                    help="observation lanes of a point-pass workgroup, in units of 64 (batched context)")
     ap.add_argument("--batch-streams", type=int, default=2,
                     help="streams a batch is split across (1: one stream, no overlap)")
     ap.add_argument("--iters-per-tick", type=int, default=10,
@@ -839,7 +841,8 @@ def main():
     # ---- mixed, batched: the timed steps --------------------------------------------------
     B = args.batch
     ctx_kw = dict(precision=BA_MIXED, max_slots=max(B, 1), hbm_budget_bytes=int(B * 16e6) + (256 << 20),
-                  chunks_per_task=args.chunks_per_task, iters_per_tick=args.iters_per_tick)
+                  chunks_per_task=args.chunks_per_task, chunks_per_wg=args.chunks_per_wg,
+                  iters_per_tick=args.iters_per_tick)
     ctx = Context(batch_streams=args.batch_streams, **ctx_kw)
     step_ms, iters_total, mixed_final = [], 0, {}
     fl_total = {"blocks": 0.0}

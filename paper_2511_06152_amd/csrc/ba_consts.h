@@ -10,9 +10,9 @@ constexpr int kWG = 256;                  // threads per workgroup of the chunk 
 constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kMaxFreeCams = 24;          // reduced system m <= 6*24 + 5 = 149
 constexpr int kMaxCams = 512;             // camera table kept in LDS by the point-lane kernels
-constexpr int kScr = 18;                  // per-lane LDS scratch values (Real)
 constexpr int kCamVals = 12;              // R row-major (9), T - origin (3)
 constexpr int kPriorVals = 18;            // R_prior (9), T_prior - origin (3), 1/sigma (6)
+constexpr int kPtermVals = 16;            // cached prior terms of a camera: residual (6), Jacobian block (9), pad
 constexpr int kPtVals = 16;               // per point: Q (6 packed symmetric), g (3), Z (6), pad (1)
 constexpr int kTaskVals = 72;             // per block task partial: camera task 51 values (69 when
                                           // self-calibrating), pair task 36

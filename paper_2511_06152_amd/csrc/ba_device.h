@@ -48,6 +48,7 @@ struct SlotDesc {
   // cameras
   double* cam[2];                         // [C][12] state buffers
   double* prior;                          // [C][18]
+  double* pterm[2];                       // [C][16] prior terms (e 6, J 9, pad) of each state buffer's cameras
   const int* cam_col;                     // [C] first reduced-system column, -1 if fixed
   double* raw_cam;                        // [C][30] R (9), T (3), R_prior (9), T_prior (3), sigma (6)
   // points

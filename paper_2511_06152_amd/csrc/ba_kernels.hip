@@ -265,6 +265,22 @@ __device__ __forceinline__ void prior_terms(const double* __restrict__ cam, cons
   }
 }
 
+// Cached prior terms of one camera (e, J of prior_terms), kept per state
+// buffer: written when a state's cameras are formed (admission, trial
+// cameras), read by the solve of the iteration that starts from that state.
+__device__ __forceinline__ void pterm_store(double* __restrict__ p, const double e[6], const double J[9]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] = e[i];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) p[6 + i] = J[i];
+}
+__device__ __forceinline__ void pterm_load(const double* __restrict__ p, double e[6], double J[9]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) e[i] = p[i];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) J[i] = p[6 + i];
+}
+
 // ---- per-observation model ------------------------------------------------------
 
 template <typename R, int NK = 2>
@@ -600,6 +616,7 @@ __global__ void k_init(Batch bt) {
     if (d.cam_col[k] < 0) continue;
     double e[6], J[9];
     prior_terms(d.cam[c.cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
+    pterm_store(d.pterm[c.cur] + kPtermVals * k, e, J);
     #pragma unroll
     for (int i = 0; i < 6; ++i) pr += e[i] * e[i];
   }
@@ -1369,12 +1386,12 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// 1/sqrt(x) for x > 0: the hardware estimate and two Newton steps
-// y <- y + y (1 - x y^2) / 2 (each roughly doubles the correct bits).
+// 1/sqrt(x) for x > 0: the hardware estimate (about 23 correct bits) and one
+// Newton step y <- y + y (1 - x y^2) / 2, which doubles the correct bits.
 __device__ __forceinline__ double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < 1; ++it) {
     const double e = __builtin_fma(-x, y * y, 1.0);
     y = __builtin_fma(0.5 * y, e, y);
   }
@@ -1512,12 +1529,16 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
       if (b0 + u < ntri) A[(b0 + u) * kTbV + er * kTbS + ec] = val[u];
   };
   const int pk = min(tid, d.C - 1);
-  double pcam[kCamVals], ppr[kPriorVals];
-  const gdp gcam = (gdp)d.cam[cur] + kCamVals * pk, gpr = (gdp)d.prior + kPriorVals * pk;
+  // the prior terms of camera tid at the current state (cached when that
+  // state's cameras were formed), requested first
+  double pe[6], pJ[9];
+  {
+    const gdp gt = (gdp)d.pterm[cur] + kPtermVals * pk;
 #pragma unroll
-  for (int i = 0; i < kCamVals; ++i) pcam[i] = gcam[i];
+    for (int i = 0; i < 6; ++i) pe[i] = gt[i];
 #pragma unroll
-  for (int i = 0; i < kPriorVals; ++i) ppr[i] = gpr[i];
+    for (int i = 0; i < 9; ++i) pJ[i] = gt[6 + i];
+  }
   const int pcol = tid < d.C ? d.cam_col[tid] : -1;
   __asm__ volatile("" ::: "memory");
   fetch(0);
@@ -1525,8 +1546,6 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   const bool vreal = tid < m;
   const double g0 = vreal ? Sg[psize + tid] : 0.0, b0v = vreal ? Sg[psize + m + tid] : 0.0,
                d0 = vreal ? Sg[psize + 2 * m + tid] : 0.0;
-  double pe[6], pJ[9];
-  if (pcol >= 0) prior_terms(pcam, ppr, pe, pJ);
   put(0);
   for (int b0 = kLd; b0 < ntri; b0 += kLd) {
     fetch(b0);
@@ -1567,7 +1586,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     const int col = d.cam_col[k];
     if (col < 0) continue;
     double e[6], J[9];
-    prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
+    pterm_load(d.pterm[cur] + kPtermVals * k, e, J);
     add_prior(k, col, e, J);
   }
   __syncthreads();
@@ -1725,6 +1744,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + xv[col + 3 + i];
     double e[6], J[9];
     prior_terms(cn, d.prior + kPriorVals * k, e, J);
+    pterm_store(d.pterm[nxt] + kPtermVals * k, e, J);
     #pragma unroll
     for (int i = 0; i < 6; ++i) pc += e[i] * e[i];
   }
@@ -1996,7 +2016,7 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
 #pragma unroll
     for (int i = 0; i < 36; ++i) blkv[i] = Ab[kSbRow * (i / 6) + i % 6];
     double e[6], J[9];
-    prior_terms(d.cam[cur] + kCamVals * k, d.prior + kPriorVals * k, e, J);
+    pterm_load(d.pterm[cur] + kPtermVals * k, e, J);
     const double* pr = d.prior + kPriorVals * k;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -2223,6 +2243,7 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
     for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + xr[3 + i];
     double e[6], J[9];
     prior_terms(cn, d.prior + kPriorVals * k, e, J);
+    pterm_store(d.pterm[nxt] + kPtermVals * k, e, J);
 #pragma unroll
     for (int i = 0; i < 6; ++i) pc += e[i] * e[i];
   }
@@ -2370,11 +2391,22 @@ __global__ __launch_bounds__(kWG) void k_backsub(Batch bt) {
         Xn32[3 * pt + q] = (float)Xn[q];
       }
     }
+    // the observations again (cached), the next one requested one ahead
+    idx = pc.x + lane;
+    cam_n = ocam[idx];
+    u_n = uv64[2 * idx];
+    v_n = uv64[2 * idx + 1];
     for (int t = 0; t < n; ++t) {
-      const int i2 = pc.x + t * kWave + lane;
+      const int cam = cam_n;
+      const double u = u_n, v = v_n;
+      if (t + 1 < n) {
+        idx += kWave;
+        cam_n = ocam[idx];
+        u_n = uv64[2 * idx];
+        v_n = uv64[2 * idx + 1];
+      }
       double rho;
-      if (obs_rho(tcam + kCamVals * ocam[i2], Xn, uv64[2 * i2], uv64[2 * i2 + 1], tki, d.inv_sigma, d.huber_dt, &rho))
-        rho_sum += rho;
+      if (obs_rho(tcam + kCamVals * cam, Xn, u, v, tki, d.inv_sigma, d.huber_dt, &rho)) rho_sum += rho;
       else ++bad;
     }
   }

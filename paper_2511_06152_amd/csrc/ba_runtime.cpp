@@ -123,7 +123,7 @@ constexpr size_t kAbsent = ~(size_t)0;   // an array the slot does not hold
 // fills them; the arrays the device computes follow.
 struct Layout {
   size_t pchunk, wg_chunk, ob_cam, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
-      cam0, cam1, prior, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
+      cam0, cam1, prior, pterm0, pterm1, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, pcg_part, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, lambda_log, acc_log, stat_part, out, upload_end, total;
   int n_wg, psize, pstride;
@@ -176,6 +176,8 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.cam0 = take(8 * (size_t)kCamVals * s.C);
   l.cam1 = take(8 * (size_t)kCamVals * s.C);
   l.prior = take(8 * (size_t)kPriorVals * s.C);
+  l.pterm0 = take(8 * (size_t)kPtermVals * s.C);
+  l.pterm1 = take(8 * (size_t)kPtermVals * s.C);
   l.X1 = take(24 * (size_t)s.P);
   l.X320 = take(12 * (size_t)s.P);
   l.X321 = take(12 * (size_t)s.P);
@@ -750,6 +752,8 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.cam[0] = (double*)(base + lay.cam0);
   d.cam[1] = (double*)(base + lay.cam1);
   d.prior = (double*)(base + lay.prior);
+  d.pterm[0] = (double*)(base + lay.pterm0);
+  d.pterm[1] = (double*)(base + lay.pterm1);
   d.cam_col = (const int*)(base + lay.cam_col);
   d.raw_cam = (double*)(base + lay.raw_cam);
   d.X[0] = (double*)(base + lay.X0);
