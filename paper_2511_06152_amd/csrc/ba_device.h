@@ -15,7 +15,7 @@ namespace bagpu {
 struct SlotDesc {
   int C, P, L, n_chunks, n_wg, pad0;      // cameras, points, observation lanes, point chunks, workgroups
   int m, n_free, kcol0, kcol1;            // reduced system size, free cameras, intrinsic columns (-1: fixed)
-  int psize, pstride;                     // packed m(m+1)/2, reduced-system vector stride (psize + 3m)
+  int psize, pstride;                     // dense system doubles (16x16 blocks), vector stride (psize + 3m)
   int max_iters, stop_on_ftol, mixed, nb;  // nb: 16x16 blocks per side of the dense reduced system
   int Lc, Lq, n_tasks, n_cam_tasks, n_cam_task_wg, n_pair_task_wg, n_targets, n_pt_part;
   int sparse, nnzb, pcg_max_iters, pad1;  // sparse: block-CSR reduced system solved by PCG
@@ -61,7 +61,8 @@ struct SlotDesc {
   // reduced camera system
   void* task_part;                        // [n_tasks][72] Real: per-task block sums
   void* pt_part;                          // [n_pt_part][32] Real: per point-pass wavefront intrinsic sums
-  double* Sg;                             // [pstride] reduced: packed S_acc (psize), g, bS, diag U (m each)
+  double* Sg;                             // [pstride] reduced: S_acc in 16x16 blocks of the lower block
+                                          //   triangle, rows padded to 17 (psize), then g, bS, diag U (m each)
   double* Sd;                             // [nb(nb+1)/2][272] damped S in 16x16 blocks, for the refinement step
   // sparse reduced system (PCG): block rows of the free cameras, diagonal block first
   const int* brow;                        // [F + 1]

@@ -14,7 +14,7 @@
 //                     (- sum W_a Q W_b^T) over the observation pairs of that
 //                     pair of cameras; register sums, fixed-order reductions
 //   k_reduce<Real>    per target block: fixed-order sum of its task partials
-//                     into the packed reduced camera system, in FP64
+//                     into the reduced camera system (16x16 blocks), in FP64
 //   k_solve           one workgroup per cluster: pose priors, Marquardt
 //                     damping, FP64 Cholesky of the reduced camera system in
 //                     16x16 blocks (matrix-core panel and trailing updates),
@@ -66,6 +66,21 @@ __device__ __forceinline__ int xcd_block() {
 
 // Packed storage of a symmetric matrix: element (r, c), r <= c.
 __device__ __forceinline__ int pidx(int r, int c) { return c * (c + 1) / 2 + r; }
+
+// The dense reduced system in 16x16 FP64 blocks (the layout the reduction
+// writes and the dense solve loads, row stride 17): block (I, J), I >= J, of
+// the lower block triangle at tblk(I, J); diagonal blocks hold both triangles.
+constexpr int kTbS = kSolveTb + 1;              // row stride of a block (doubles)
+constexpr int kTbV = kSolveTb * kTbS;           // doubles per block
+__device__ __forceinline__ int tblk(int I, int J) { return (I * (I + 1) / 2 + J) * kTbV; }   // I >= J
+
+// Stores element (p, q) = (q, p) of the symmetric system into its blocked
+// place(s).
+__device__ __forceinline__ void sput(double* Sb, int p, int q, double t) {
+  const int P = p / kSolveTb, Q = q / kSolveTb;
+  if (P >= Q) Sb[tblk(P, Q) + (p % kSolveTb) * kTbS + q % kSolveTb] = t;
+  if (Q >= P) Sb[tblk(Q, P) + (q % kSolveTb) * kTbS + p % kSolveTb] = t;
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -185,12 +200,24 @@ __device__ __forceinline__ double uniform(double x) {
 
 // ---- SO(3) (FP64) -----------------------------------------------------------
 
+// Rotations below kSo3Series rad take the Taylor series of the SO(3) maps
+// (truncation below 1e-24 relative there, far under FP64 rounding), which
+// skips the transcendental functions on the common path: LM steps and prior
+// residuals are small rotations.
+constexpr double kSo3Series = 0.02;
+
 __device__ __forceinline__ void so3_exp(const double w[3], double R[9]) {
   const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-  const double th = sqrt(th2);
   double a, b;
-  if (th < 1e-8) { a = 1.0; b = 0.5; }
-  else { a = sin(th) / th; b = (1.0 - cos(th)) / th2; }
+  if (th2 < kSo3Series * kSo3Series) {
+    // a = sin(t)/t, b = (1 - cos t)/t^2
+    a = 1.0 + th2 * (-1.0 / 6.0 + th2 * (1.0 / 120.0 + th2 * (-1.0 / 5040.0 + th2 * (1.0 / 362880.0))));
+    b = 0.5 + th2 * (-1.0 / 24.0 + th2 * (1.0 / 720.0 + th2 * (-1.0 / 40320.0 + th2 * (1.0 / 3628800.0))));
+  } else {
+    const double th = sqrt(th2);
+    a = sin(th) / th;
+    b = (1.0 - cos(th)) / th2;
+  }
   const double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
   #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -206,8 +233,17 @@ __device__ __forceinline__ void so3_exp(const double w[3], double R[9]) {
 __device__ __forceinline__ void so3_log(const double R[9], double w[3]) {
   double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
   c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-  const double th = acos(c);
   const double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+  // v = 2 sin(t) axis: for a small angle, w = (t / (2 sin t)) v with
+  // t / sin t = asin(n) / n, n = sin t, in series
+  const double n2 = 0.25 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  if (c > 0.0 && n2 < kSo3Series * kSo3Series) {
+    const double r = 1.0 + n2 * (1.0 / 6.0 + n2 * (3.0 / 40.0 + n2 * (5.0 / 112.0 + n2 * (35.0 / 1152.0))));
+    #pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = 0.5 * r * v[i];
+    return;
+  }
+  const double th = acos(c);
   if (th < 1e-6) {
     const double s = 0.5 * (1.0 + th * th / 6.0);
     #pragma unroll
@@ -248,8 +284,14 @@ __device__ __forceinline__ void prior_terms(const double* __restrict__ cam, cons
   double phi[3];
   so3_log(M, phi);
   const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
-  const double th = sqrt(th2);
-  const double cc = th < 1e-4 ? 1.0 / 12.0 + th2 / 720.0 : 1.0 / th2 - (1.0 + cos(th)) / (2.0 * th * sin(th));
+  // cc = 1/t^2 - (1 + cos t) / (2 t sin t) = 1/12 + t^2/720 + t^4/30240 + t^6/1209600 + ...
+  double cc;
+  if (th2 < kSo3Series * kSo3Series) {
+    cc = 1.0 / 12.0 + th2 * (1.0 / 720.0 + th2 * (1.0 / 30240.0 + th2 * (1.0 / 1209600.0)));
+  } else {
+    const double th = sqrt(th2);
+    cc = 1.0 / th2 - (1.0 + cos(th)) / (2.0 * th * sin(th));
+  }
   const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
   #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -1177,7 +1219,7 @@ __global__ __launch_bounds__(kWG) void k_pairblk(Batch bt) {
   if (t < d.n_tasks) pairblk_task<R, SC>(d, c, t, threadIdx.x % kWave);
 }
 
-// ---- reduction of the task partials into the packed reduced system ----------------
+// ---- reduction of the task partials into the reduced system -----------------------
 //
 // One workgroup per target (a free camera's diagonal block and borders, a
 // camera-pair block, or the intrinsic block); sums its task range in order.
@@ -1234,7 +1276,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
       int a = 0, r = v;
       while (r >= nk - a) { r -= nk - a; ++a; }
       const int ca = d.kcolt[a], cb = d.kcolt[a + r];
-      if (ca >= 0 && cb >= 0) Sg[pidx(min(ca, cb), max(ca, cb))] = t;
+      if (ca >= 0 && cb >= 0) sput(Sg, ca, cb, t);
       return;
     }
     const int q = (v - ns) / nk, col = d.kcolt[(v - ns) % nk];
@@ -1267,19 +1309,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
   }
   if (kind == TASK_PAIR) {
     const int fb = d.cam_col[kb];
-    Sg[pidx(fa + v / 6, fb + v % 6)] = t;
+    sput(Sg, fa + v / 6, fb + v % 6, t);
     return;
   }
   if (v < 21) {
     int r, cc;
     tri6(v, &r, &cc);
-    Sg[pidx(fa + r, fa + cc)] = t;
+    sput(Sg, fa + r, fa + cc, t);
   } else if (v < 27) Sg[psize + fa + (v - 21)] = t;
   else if (v < 33) Sg[psize + m + fa + (v - 27)] = t;
   else if (v < 39) Sg[psize + 2 * m + fa + (v - 33)] = t;
   else {
     const int col = d.kcolt[(v - 39) / 6];
-    if (col >= 0) Sg[pidx(fa + (v - 39) % 6, col)] = t;
+    if (col >= 0) sput(Sg, fa + (v - 39) % 6, col, t);
   }
 }
 
@@ -1297,8 +1339,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Batch bt) {
 // global memory otherwise).
 
 constexpr int kSolveWG = 256;                   // four wavefronts
-constexpr int kTbS = kSolveTb + 1;              // LDS row stride of a block (doubles)
-constexpr int kTbV = kSolveTb * kTbS;           // doubles per block
 constexpr int kSolveWk = 2 * kSolveTb * kSolveTb + kSolveTb;   // factor scratch + solve vector
 constexpr size_t kSolveLdsCap = 150 * 1024;
 static_assert(kSolveTb * ((6 * kMaxFreeCams + kIntr + kSolveTb - 1) / kSolveTb) <= kSolveWG,
@@ -1316,7 +1356,6 @@ __host__ __device__ inline bool solve_lds_copy(int nbm) {
   return sizeof(double) * (solve_lds_base(nbm) + nb * (nb + 1) / 2 * kTbV) <= kSolveLdsCap;
 }
 
-__device__ __forceinline__ int tblk(int I, int J) { return (I * (I + 1) / 2 + J) * kTbV; }   // I >= J
 
 __device__ __forceinline__ void decode_tri(int e, int* ii, int* jj) {   // e -> (ii >= jj)
   int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
@@ -1500,11 +1539,11 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   __shared__ int ok;
   const double lambda = c.lambda;
   const int cur = c.cur;
-  // Load: packed reduced system -> blocks (diagonal blocks full, symmetric).
-  // Thread tid owns element (tid / 16, tid % 16) of every block; kLd blocks
-  // are requested at once.  The pose-prior terms of camera tid are computed
-  // while the first batch is in flight: its camera and prior are requested
-  // first, so that the prior math waits for them alone.
+  // Load: the reduced system's blocks (written in this layout by the
+  // reduction) with coalesced row reads; padding rows and columns beyond m
+  // are those of the identity.  Thread tid owns element (tid / 16, tid % 16)
+  // of every block; kLd blocks are requested at once.  The cached pose-prior
+  // terms of camera tid are requested first.
   constexpr int kLd = 16;
   // global (not generic) loads: they count on the vector-memory counter only,
   // so waits for scalar loads do not wait for them
@@ -1519,7 +1558,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     for (int u = 0; u < kLd; ++u) {
       const int p = kSolveTb * bi + er, q = kSolveTb * bj + ec;
       val[u] = (p == q) ? 1.0 : 0.0;
-      if (b0 + u < ntri && p < m && q < m) val[u] = Sg[p <= q ? pidx(p, q) : pidx(q, p)];
+      if (b0 + u < ntri && p < m && q < m) val[u] = Sg[(b0 + u) * kTbV + er * kTbS + ec];
       if (++bj > bi) { ++bi; bj = 0; }
     }
   };
@@ -1540,6 +1579,18 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     for (int i = 0; i < 9; ++i) pJ[i] = gt[6 + i];
   }
   const int pcol = tid < d.C ? d.cam_col[tid] : -1;
+  // what the closing wavefront needs (camera tid's state and prior, the
+  // intrinsics), requested now so that its loads are off the kernel's tail
+  double fcam[kCamVals], fpr[kPriorVals], kcur[kIntr];
+  if (tid < kWave) {
+    const gdp gc = (gdp)d.cam[cur] + kCamVals * pk, gp = (gdp)d.prior + kPriorVals * pk;
+#pragma unroll
+    for (int i = 0; i < kCamVals; ++i) fcam[i] = gc[i];
+#pragma unroll
+    for (int i = 0; i < kPriorVals; ++i) fpr[i] = gp[i];
+#pragma unroll
+    for (int t = 0; t < kIntr; ++t) kcur[t] = c.k[cur][t];
+  }
   __asm__ volatile("" ::: "memory");
   fetch(0);
   // gradient, bS and diag U of unknown tid (np <= 160 < kSolveWG), in the same batch
@@ -1726,24 +1777,32 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   const int nxt = 1 - cur;
   double pc = 0.0;
   for (int k = tid; k < d.C; k += kWave) {
-    const double* cm = d.cam[cur] + kCamVals * k;
+    // the first camera of each lane from the registers loaded at the start
+    double cm[kCamVals], pr[kPriorVals];
+    const bool pre = k == tid;
+#pragma unroll
+    for (int i = 0; i < kCamVals; ++i) cm[i] = pre ? fcam[i] : d.cam[cur][kCamVals * k + i];
     double* cn = d.cam[nxt] + kCamVals * k;
-    const int col = d.cam_col[k];
+    const int col = pre ? pcol : d.cam_col[k];
     if (col < 0) {
       for (int i = 0; i < kCamVals; ++i) cn[i] = cm[i];
       continue;
     }
+#pragma unroll
+    for (int i = 0; i < kPriorVals; ++i) pr[i] = pre ? fpr[i] : d.prior[kPriorVals * k + i];
     const double wv[3] = {xv[col], xv[col + 1], xv[col + 2]};
-    double E[9];
+    double E[9], cv[kCamVals];
     so3_exp(wv, E);
     #pragma unroll
     for (int i = 0; i < 3; ++i)
       #pragma unroll
-      for (int j = 0; j < 3; ++j) cn[3 * i + j] = cm[3 * i] * E[j] + cm[3 * i + 1] * E[3 + j] + cm[3 * i + 2] * E[6 + j];
+      for (int j = 0; j < 3; ++j) cv[3 * i + j] = cm[3 * i] * E[j] + cm[3 * i + 1] * E[3 + j] + cm[3 * i + 2] * E[6 + j];
     #pragma unroll
-    for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + xv[col + 3 + i];
+    for (int i = 0; i < 3; ++i) cv[9 + i] = cm[9 + i] + xv[col + 3 + i];
+    #pragma unroll
+    for (int i = 0; i < kCamVals; ++i) cn[i] = cv[i];
     double e[6], J[9];
-    prior_terms(cn, d.prior + kPriorVals * k, e, J);
+    prior_terms(cv, pr, e, J);
     pterm_store(d.pterm[nxt] + kPtermVals * k, e, J);
     #pragma unroll
     for (int i = 0; i < 6; ++i) pc += e[i] * e[i];
@@ -1752,8 +1811,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   if (tid == 0) {
     c.pred_c = predc;
     c.E_prior_trial = 0.5 * pc;
-    for (int t = 0; t < 5; ++t)
-      c.k[nxt][t] = c.k[cur][t] + (d.kcolt[t] >= 0 ? xv[d.kcolt[t]] : 0.0);
+    for (int t = 0; t < 5; ++t) c.k[nxt][t] = kcur[t] + (d.kcolt[t] >= 0 ? xv[d.kcolt[t]] : 0.0);
   }
 }
 
@@ -2233,16 +2291,18 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg(Batch bt, int s) {
     }
     const double* cm = d.cam[cur] + kCamVals * k;
     double* cn = d.cam[nxt] + kCamVals * k;
-    double E[9];
+    double E[9], cv[kCamVals];
     so3_exp(xr, E);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) cn[3 * i + j] = cm[3 * i] * E[j] + cm[3 * i + 1] * E[3 + j] + cm[3 * i + 2] * E[6 + j];
+      for (int j = 0; j < 3; ++j) cv[3 * i + j] = cm[3 * i] * E[j] + cm[3 * i + 1] * E[3 + j] + cm[3 * i + 2] * E[6 + j];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) cn[9 + i] = cm[9 + i] + xr[3 + i];
+    for (int i = 0; i < 3; ++i) cv[9 + i] = cm[9 + i] + xr[3 + i];
+#pragma unroll
+    for (int i = 0; i < kCamVals; ++i) cn[i] = cv[i];
     double e[6], J[9];
-    prior_terms(cn, d.prior + kPriorVals * k, e, J);
+    prior_terms(cv, d.prior + kPriorVals * k, e, J);
     pterm_store(d.pterm[nxt] + kPtermVals * k, e, J);
 #pragma unroll
     for (int i = 0; i < 6; ++i) pc += e[i] * e[i];

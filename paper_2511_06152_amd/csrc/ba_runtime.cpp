@@ -138,7 +138,8 @@ Layout make_layout(const Staged& s, bool mixed) {
   const size_t rs = real_size(mixed);
   l.n_wg = s.n_wg;
   // the sparse form keeps no packed triangle: Sg holds g, bS, diag U only
-  l.psize = s.sparse ? 0 : s.m * (s.m + 1) / 2;
+  // dense: the system in 16x16 blocks (lower block triangle, rows padded to 17)
+  l.psize = s.sparse ? 0 : s.nb * (s.nb + 1) / 2 * kSolveTb * (kSolveTb + 1);
   l.pstride = (int)align_up((size_t)l.psize + 3 * (size_t)s.m, 4);
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
