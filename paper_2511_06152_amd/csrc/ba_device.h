@@ -34,15 +34,14 @@ struct SlotDesc {
   double* ob_uv64;                        // [2L] u - cx, v - cy  (uploaded raw, shifted in place)
   float* ob_uv32;                         // [2L]
   // camera lanes: observations of free cameras sorted by (camera, point), each
-  // camera's run padded to whole 64-lane chunks
+  // camera's run padded to whole 64-lane chunks; pixels are read from the
+  // observation lanes
   const int* cl_pt;                       // [Lc] point index, -1 for padding
-  double* cl_uv64;                        // [2Lc]
-  float* cl_uv32;                         // [2Lc]
+  const int* cl_ob;                       // [Lc] observation lane, 0 for padding
   // pair lanes: observation pairs of one point with both cameras free, sorted
   // by camera-pair block, each block's run padded to whole chunks
-  const int* ql_pt;                       // [Lq]
-  double* ql_uv64;                        // [4Lq] (u_a, v_a, u_b, v_b)
-  float* ql_uv32;                         // [4Lq]
+  const int* ql_pt;                       // [Lq] point index, -1 for padding
+  const int2* ql_ob;                      // [Lq] observation lanes of camera a and b
   const int4* tasks;                      // [n_tasks] camera tasks (by camera), then pair tasks (by block)
   const int4* targets;                    // [n_targets] reduction targets with their task ranges
   // cameras

@@ -578,21 +578,6 @@ __global__ void k_prep_points(Batch bt) {
     d.ob_uv32[2 * i] = (float)u;
     d.ob_uv32[2 * i + 1] = (float)v;
   }
-  // mixed mode: the camera- and pair-lane pixels arrive as FP32, already shifted
-  if (!d.mixed && i < d.Lc) {
-    const double u = d.cl_uv64[2 * i] - d.cx, v = d.cl_uv64[2 * i + 1] - d.cy;
-    d.cl_uv64[2 * i] = u;
-    d.cl_uv64[2 * i + 1] = v;
-    d.cl_uv32[2 * i] = (float)u;
-    d.cl_uv32[2 * i + 1] = (float)v;
-  }
-  if (!d.mixed && i < 2 * d.Lq) {
-    const double u = d.ql_uv64[2 * i] - d.cx, v = d.ql_uv64[2 * i + 1] - d.cy;
-    d.ql_uv64[2 * i] = u;
-    d.ql_uv64[2 * i + 1] = v;
-    d.ql_uv32[2 * i] = (float)u;
-    d.ql_uv32[2 * i + 1] = (float)v;
-  }
 }
 
 // ---- FP64 cost of the current state (admission) -----------------------------------
@@ -976,24 +961,27 @@ __device__ __forceinline__ void camblk_task_k(const SlotDesc& d, const SlotCtl& 
   (void)kb;
   const gptr<const R> recz = gmem(reinterpret_cast<const R*>(d.ptz));
 
-    const gptr<const int> cl_pt = gmem(d.cl_pt);
-    const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.cl_uv64, d.cl_uv32), recs = gmem(ptv);
+    const gptr<const int> cl_pt = gmem(d.cl_pt), cl_ob = gmem(d.cl_ob);
+    const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.ob_uv64, d.ob_uv32), recs = gmem(ptv);
     R acc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = R(0);
-    // Loads are unconditional: padding lanes read point 0 (finite state and
-    // record; their pixel is 0) and the observation model gives them weight
-    // 0, which zeroes every term they add.  The next chunk's point index is
-    // requested a chunk ahead.
+    // Loads are unconditional: padding lanes read point 0 and observation
+    // lane 0 (finite state, record and pixel) and the observation model
+    // gives them weight 0, which zeroes every term they add.  The next
+    // chunk's point and observation lane are requested a chunk ahead.
     const int ch_end = tk.y + tk.z;
-    int pt_next = cl_pt[tk.y * kWave + lane];
+    int pt_next = cl_pt[tk.y * kWave + lane], ob_next = cl_ob[tk.y * kWave + lane];
     for (int ch = tk.y; ch < ch_end; ++ch) {
       const int idx = ch * kWave + lane;
-      const int pt = pt_next;
-      if (ch + 1 < ch_end) pt_next = cl_pt[idx + kWave];
+      const int pt = pt_next, ob = ob_next;
+      if (ch + 1 < ch_end) {
+        pt_next = cl_pt[idx + kWave];
+        ob_next = cl_ob[idx + kWave];
+      }
       const bool valid = pt >= 0;
       const int ps = valid ? pt : 0;
-      const R X0 = Xs[3 * ps], X1 = Xs[3 * ps + 1], X2 = Xs[3 * ps + 2], u = uvs[2 * idx], v = uvs[2 * idx + 1];
+      const R X0 = Xs[3 * ps], X1 = Xs[3 * ps + 1], X2 = Xs[3 * ps + 2], u = uvs[2 * ob], v = uvs[2 * ob + 1];
       R rec[kPtVals];
       rec_load<kPtVals>(recs + kPtVals * (size_t)ps, rec);
       R rz[SC ? kPtzVals : 1];
@@ -1088,24 +1076,31 @@ __device__ __forceinline__ void pairblk_task_k(const SlotDesc& d, const SlotCtl&
     R cb[kCamVals];
     load_cam(d.cam[cur] + kCamVals * kb, cb);
     const gptr<const int> ql_pt = gmem(d.ql_pt);
-    const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.ql_uv64, d.ql_uv32), recs = gmem(ptv);
+    const gptr<const int> ql_ob = gmem(reinterpret_cast<const int*>(d.ql_ob));
+    const gptr<const R> Xs = pts_of<R>(d, cur), uvs = uv_of<R>(d.ob_uv64, d.ob_uv32), recs = gmem(ptv);
     R acc[36];
 #pragma unroll
     for (int i = 0; i < 36; ++i) acc[i] = R(0);
-    // Loads are unconditional: padding lanes read point 0 (finite state and
-    // record; their pixels are 0) and the observation model gives them weight
-    // 0, which zeroes every term they add.  The next chunk's point index is
-    // requested a chunk ahead.
+    // Loads are unconditional: padding lanes read point 0 and observation
+    // lane 0 (finite state, record and pixels) and the observation model
+    // gives them weight 0, which zeroes every term they add.  The next
+    // chunk's point and observation lanes are requested a chunk ahead.
     const int ch_end = tk.y + tk.z;
     int pt_next = ql_pt[tk.y * kWave + lane];
+    int lo_next[2] = {ql_ob[2 * (tk.y * kWave + lane)], ql_ob[2 * (tk.y * kWave + lane) + 1]};
     for (int ch = tk.y; ch < ch_end; ++ch) {
       const int idx = ch * kWave + lane;
       const int pt = pt_next;
-      if (ch + 1 < ch_end) pt_next = ql_pt[idx + kWave];
+      const int lo[2] = {lo_next[0], lo_next[1]};   // observation lanes of the pair
+      if (ch + 1 < ch_end) {
+        pt_next = ql_pt[idx + kWave];
+        lo_next[0] = ql_ob[2 * (idx + kWave)];
+        lo_next[1] = ql_ob[2 * (idx + kWave) + 1];
+      }
       const bool valid = pt >= 0;
       const int ps = valid ? pt : 0;
       const R X0 = Xs[3 * ps], X1 = Xs[3 * ps + 1], X2 = Xs[3 * ps + 2];
-      const R ua = uvs[4 * idx], va = uvs[4 * idx + 1], ub = uvs[4 * idx + 2], vb = uvs[4 * idx + 3];
+      const R ua = uvs[2 * lo[0]], va = uvs[2 * lo[0] + 1], ub = uvs[2 * lo[1]], vb = uvs[2 * lo[1] + 1];
       R Q[8];
       rec_load<sizeof(R) == 8 ? 6 : 8>(recs + kPtVals * (size_t)ps, Q);
       // -Y_a W_b^T = J_ca^T M J_cb with the 2x2 M = -w_a w_b J_pa Q J_pb^T.

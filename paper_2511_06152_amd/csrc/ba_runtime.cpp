@@ -116,13 +116,12 @@ bool pcg_partition(const Staged& s, bool mixed, std::vector<int>& part, int& row
   return true;
 }
 
-constexpr size_t kAbsent = ~(size_t)0;   // an array the slot does not hold
 
 // Byte offsets inside a slot block.  The arrays taken from the host come
 // first, [0, upload_end), so that one copy of the cluster's upload image
 // fills them; the arrays the device computes follow.
 struct Layout {
-  size_t pchunk, wg_chunk, ob_cam, uv64, uv32, cl_pt, cl_uv64, cl_uv32, ql_pt, ql_uv64, ql_uv32, tasks, targets,
+  size_t pchunk, wg_chunk, ob_cam, uv64, uv32, cl_pt, cl_ob, ql_pt, ql_ob, tasks, targets,
       cam0, cam1, prior, pterm0, pterm1, cam_col, raw_cam, X0, X1, X320, X321, ptv, ptd, ptz, pt_orig, task_part, pt_part, Sg, Sd, dc,
       brow, bcol, tslot, Sblk, Sblk32, pcgw, pcg_part, rin_cam, rin_pt, rout_cam, rout_pt, cost_part,
       bad_part, cost_log, lambda_log, acc_log, stat_part, out, upload_end, total;
@@ -145,18 +144,16 @@ Layout make_layout(const Staged& s, bool mixed) {
   auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
   l.pcg_ok = pcg_partition(s, mixed, l.part, l.pcg_rows_max, l.pcg_smem);
   const size_t nnzb = s.bcol.size();
-  // from the host.  In mixed mode the camera- and pair-lane pixels come as
-  // FP32 (principal point already subtracted) and have no FP64 copy.
+  // from the host (the camera and pair lanes name observation lanes; their
+  // pixels are read from those)
   l.pchunk = take(sizeof(int4) * s.pchunk.size());
   l.wg_chunk = take(4 * s.wg_chunk.size());
   l.ob_cam = take(4 * (size_t)s.L);
   l.uv64 = take(16 * (size_t)s.L);
   l.cl_pt = take(4 * (size_t)s.Lc);
-  l.cl_uv64 = mixed ? kAbsent : take(16 * (size_t)s.Lc);
-  l.cl_uv32 = mixed ? take(8 * (size_t)s.Lc) : kAbsent;
+  l.cl_ob = take(4 * (size_t)s.Lc);
   l.ql_pt = take(4 * (size_t)s.Lq);
-  l.ql_uv64 = mixed ? kAbsent : take(32 * (size_t)s.Lq);
-  l.ql_uv32 = mixed ? take(16 * (size_t)s.Lq) : kAbsent;
+  l.ql_ob = take(8 * (size_t)s.Lq);
   l.tasks = take(sizeof(int4) * s.tasks.size());
   l.targets = take(sizeof(int4) * s.targets.size());
   l.cam_col = take(4 * (size_t)s.C);
@@ -170,10 +167,6 @@ Layout make_layout(const Staged& s, bool mixed) {
   l.upload_end = o;
   // computed on the device
   l.uv32 = take(8 * (size_t)s.L);
-  if (!mixed) {
-    l.cl_uv32 = take(8 * (size_t)s.Lc);
-    l.ql_uv32 = take(16 * (size_t)s.Lq);
-  }
   l.cam0 = take(8 * (size_t)kCamVals * s.C);
   l.cam1 = take(8 * (size_t)kCamVals * s.C);
   l.prior = take(8 * (size_t)kPriorVals * s.C);
@@ -211,10 +204,8 @@ Layout make_layout(const Staged& s, bool mixed) {
 
 // Writes the cluster's upload image: every array the slot block takes from
 // the host, at its offset below lay.upload_end (the alignment gaps are left
-// as they are).  In mixed mode the camera- and pair-lane pixels are written
-// relative to the principal point and rounded to FP32 from that FP64
-// difference (what the device's own conversion of the FP64 lanes gives).
-void pack_upload(const Staged& s, bool mixed, const Layout& lay, char* dst) {
+// as they are).
+void pack_upload(const Staged& s, const Layout& lay, char* dst) {
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(dst + off, src, bytes);
   };
@@ -223,22 +214,9 @@ void pack_upload(const Staged& s, bool mixed, const Layout& lay, char* dst) {
   put(lay.ob_cam, s.ob_cam.data(), 4 * (size_t)s.L);
   put(lay.uv64, s.ob_uv.data(), 16 * (size_t)s.L);
   put(lay.cl_pt, s.cl_pt.data(), 4 * (size_t)s.Lc);
+  put(lay.cl_ob, s.cl_ob.data(), 4 * (size_t)s.Lc);
   put(lay.ql_pt, s.ql_pt.data(), 4 * (size_t)s.Lq);
-  if (mixed) {
-    float* cu = reinterpret_cast<float*>(dst + lay.cl_uv32);
-    for (size_t i = 0; i < 2 * (size_t)s.Lc; i += 2) {
-      cu[i] = (float)(s.cl_uv[i] - s.cx);
-      cu[i + 1] = (float)(s.cl_uv[i + 1] - s.cy);
-    }
-    float* qu = reinterpret_cast<float*>(dst + lay.ql_uv32);
-    for (size_t i = 0; i < 4 * (size_t)s.Lq; i += 2) {
-      qu[i] = (float)(s.ql_uv[i] - s.cx);
-      qu[i + 1] = (float)(s.ql_uv[i + 1] - s.cy);
-    }
-  } else {
-    put(lay.cl_uv64, s.cl_uv.data(), 16 * (size_t)s.Lc);
-    put(lay.ql_uv64, s.ql_uv.data(), 32 * (size_t)s.Lq);
-  }
+  put(lay.ql_ob, s.ql_ob.data(), 8 * (size_t)s.Lq);
   put(lay.tasks, s.tasks.data(), sizeof(I4) * s.tasks.size());
   put(lay.targets, s.targets.data(), sizeof(I4) * s.targets.size());
   put(lay.cam_col, s.cam_col.data(), 4 * (size_t)s.C);
@@ -539,7 +517,7 @@ void pack_staged(ba_ctx* c, Staged& s, const Layout& lay) {
   if (lay.upload_end <= kPinnedPoolBytes / 4) b = pin_get(c, lay.upload_end);
   s.blob_pinned = b != nullptr;
   if (!b) b = std::shared_ptr<char>(new char[std::max<size_t>(lay.upload_end, 1)], std::default_delete<char[]>());
-  pack_upload(s, c->opt.precision == BA_MIXED, lay, b.get());
+  pack_upload(s, lay, b.get());
   s.blob = std::move(b);
   s.blob_bytes = lay.upload_end;
 }
@@ -743,11 +721,9 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.ob_uv64 = (double*)(base + lay.uv64);
   d.ob_uv32 = (float*)(base + lay.uv32);
   d.cl_pt = (const int*)(base + lay.cl_pt);
-  d.cl_uv64 = lay.cl_uv64 == kAbsent ? nullptr : (double*)(base + lay.cl_uv64);
-  d.cl_uv32 = (float*)(base + lay.cl_uv32);
+  d.cl_ob = (const int*)(base + lay.cl_ob);
   d.ql_pt = (const int*)(base + lay.ql_pt);
-  d.ql_uv64 = lay.ql_uv64 == kAbsent ? nullptr : (double*)(base + lay.ql_uv64);
-  d.ql_uv32 = (float*)(base + lay.ql_uv32);
+  d.ql_ob = (const int2*)(base + lay.ql_ob);
   d.tasks = (const int4*)(base + lay.tasks);
   d.targets = (const int4*)(base + lay.targets);
   d.cam[0] = (double*)(base + lay.cam0);
@@ -866,7 +842,7 @@ int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   int maxPL = 0, maxRin = 0;
   for (int s : slots) {
     const SlotDesc& d = c->slots[s].desc;
-    maxPL = std::max({maxPL, d.P, d.L, d.Lc, 2 * d.Lq});
+    maxPL = std::max({maxPL, d.P, d.L});
     maxRin = std::max({maxRin, d.n_rin_cam, d.n_rin_pt});
   }
   HIPCHK(c, launch_prep(b, maxPL, maxRin, c->stream));

@@ -208,14 +208,16 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   s.n_chunks = (int)s.pchunk.size();
   s.ob_cam.assign(s.L, 0);
   s.ob_uv.assign(2 * (size_t)s.L, 0.0);
+  std::vector<int> oblane(O);   // observation lane of each observation in (point, camera) order
   for (const I4& ch : s.pchunk)
     for (int l = 0; l < ch.w; ++l)
       for (int t = 0; t < ch.y; ++t) {
         const int so = cnt[ch.z + l] + t;
-        const size_t lane = (size_t)ch.x + (size_t)kWave * t + l;
+        const int lane = ch.x + kWave * t + l;
+        oblane[so] = lane;
         s.ob_cam[lane] = scam[so];
-        s.ob_uv[2 * lane] = suv[2 * (size_t)so];
-        s.ob_uv[2 * lane + 1] = suv[2 * (size_t)so + 1];
+        s.ob_uv[2 * (size_t)lane] = suv[2 * (size_t)so];
+        s.ob_uv[2 * (size_t)lane + 1] = suv[2 * (size_t)so + 1];
       }
   // point-pass workgroups: runs of whole chunks holding at least cpw * 64
   // observation lanes each
@@ -235,92 +237,81 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   std::vector<int> free_cam(F);
   for (int k = 0; k < C; ++k)
     if (s.cam_col[k] >= 0) free_cam[s.cam_col[k] / 6] = k;
-  // camera lanes and tasks: each free camera's observations in point order
+  // camera lanes and tasks: each free camera's observations in point order,
+  // each lane naming its point and its observation lane
   std::vector<int> coff(F + 1, 0);
   for (int t = 0; t < O; ++t) {
     const int col = s.cam_col[scam[t]];
     if (col >= 0) ++coff[col / 6 + 1];
   }
-  for (int fi = 0; fi < F; ++fi) coff[fi + 1] += coff[fi];
-  std::vector<int> cobs(coff[F]);
+  std::vector<int> cbase(F + 1, 0);   // first lane of each camera's run
+  for (int fi = 0; fi < F; ++fi) cbase[fi + 1] = cbase[fi] + (int)align_up(coff[fi + 1], kWave);
+  s.Lc = cbase[F];
+  s.cl_pt.assign(s.Lc, -1);
+  s.cl_ob.assign(s.Lc, 0);
   {
-    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    std::vector<int> fill(cbase.begin(), cbase.end() - 1);
     for (int t = 0; t < O; ++t) {
       const int col = s.cam_col[scam[t]];
-      if (col >= 0) cobs[fill[col / 6]++] = t;
+      if (col < 0) continue;
+      const int lane = fill[col / 6]++;
+      s.cl_pt[lane] = spt[t];
+      s.cl_ob[lane] = oblane[t];
     }
   }
-  for (int fi = 0; fi < F; ++fi) s.Lc += (int)align_up(coff[fi + 1] - coff[fi], kWave);
-  s.cl_pt.assign(s.Lc, -1);
-  s.cl_uv.assign(2 * (size_t)s.Lc, 0.0);
   std::vector<I2> cam_range(F);
-  for (int fi = 0, base = 0; fi < F; ++fi) {
-    const int n = coff[fi + 1] - coff[fi];
-    for (int t = 0; t < n; ++t) {
-      const int so = cobs[coff[fi] + t];
-      const size_t lane = (size_t)base * kWave + t;
-      s.cl_pt[lane] = spt[so];
-      s.cl_uv[2 * lane] = suv[2 * (size_t)so];
-      s.cl_uv[2 * lane + 1] = suv[2 * (size_t)so + 1];
-    }
-    const int nch = (int)(align_up(n, kWave) / kWave);
+  for (int fi = 0; fi < F; ++fi) {
+    const int base = cbase[fi] / kWave, nch = (cbase[fi + 1] - cbase[fi]) / kWave;
     cam_range[fi].x = (int)s.tasks.size();
     for (int ch = 0; ch < nch; ch += cpt) s.tasks.push_back(mk4(TASK_CAM, free_cam[fi], 0, base + ch, std::min(cpt, nch - ch)));
     cam_range[fi].y = (int)s.tasks.size();
-    base += nch;
   }
   s.n_cam_tasks = (int)s.tasks.size();
   // pair lanes and tasks, blocks (fa < fb) in row-major upper-triangle order;
-  // within a block the pairs (point, obs a, obs b) in point order
+  // within a block the pairs in point order, each lane naming its point and
+  // the observation lanes of its two observations
   const int nblk = F * (F - 1) / 2;
   auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
-  std::vector<int> poff(nblk + 1, 0);
+  std::vector<int> pcount(nblk, 0);
   for (int j = 0; j < P; ++j)
     for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
       const int ca = s.cam_col[scam[ta]];
       if (ca < 0) continue;
       for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
         const int cb = s.cam_col[scam[tb]];
-        if (cb >= 0) ++poff[blk(ca / 6, cb / 6) + 1];
+        if (cb >= 0) ++pcount[blk(ca / 6, cb / 6)];
       }
     }
-  for (int b = 0; b < nblk; ++b) poff[b + 1] += poff[b];
-  std::vector<I3> pairs(poff[nblk]);
+  std::vector<int> pbase(nblk + 1, 0);   // first lane of each block's run
+  for (int b = 0; b < nblk; ++b) pbase[b + 1] = pbase[b] + (int)align_up(pcount[b], kWave);
+  s.Lq = pbase[nblk];
+  s.ql_pt.assign(s.Lq, -1);
+  s.ql_ob.assign(s.Lq, I2{0, 0});
   {
-    std::vector<int> fill(poff.begin(), poff.end() - 1);
+    std::vector<int> fill(pbase.begin(), pbase.end() - 1);
     for (int j = 0; j < P; ++j)
       for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
         const int ca = s.cam_col[scam[ta]];
         if (ca < 0) continue;
         for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
           const int cb = s.cam_col[scam[tb]];
-          if (cb >= 0) pairs[fill[blk(ca / 6, cb / 6)]++] = I3{j, ta, tb};
+          if (cb < 0) continue;
+          const int lane = fill[blk(ca / 6, cb / 6)]++;
+          s.ql_pt[lane] = j;
+          s.ql_ob[lane] = I2{oblane[ta], oblane[tb]};
         }
       }
   }
-  auto blk_empty = [&](int b) { return poff[b + 1] == poff[b]; };
-  for (int b = 0; b < nblk; ++b) s.Lq += (int)align_up(poff[b + 1] - poff[b], kWave);
-  s.ql_pt.assign(s.Lq, -1);
-  s.ql_uv.assign(4 * (size_t)s.Lq, 0.0);
+  auto blk_empty = [&](int b) { return pcount[b] == 0; };
   std::vector<I2> blk_range(nblk);
-  for (int fa = 0, base = 0; fa < F; ++fa)
+  for (int fa = 0; fa < F; ++fa)
     for (int fb = fa + 1; fb < F; ++fb) {
-      const int b = blk(fa, fb), n = poff[b + 1] - poff[b];
-      for (int t = 0; t < n; ++t) {
-        const I3 pr = pairs[poff[b] + t];
-        const size_t lane = (size_t)base * kWave + t;
-        s.ql_pt[lane] = pr.x;
-        s.ql_uv[4 * lane] = suv[2 * (size_t)pr.y];
-        s.ql_uv[4 * lane + 1] = suv[2 * (size_t)pr.y + 1];
-        s.ql_uv[4 * lane + 2] = suv[2 * (size_t)pr.z];
-        s.ql_uv[4 * lane + 3] = suv[2 * (size_t)pr.z + 1];
-      }
-      const int nch = (int)(align_up(n, kWave) / kWave);
+      const int b = blk(fa, fb);
+      const int base = pbase[b] / kWave, nch = (pbase[b + 1] - pbase[b]) / kWave;
       blk_range[b].x = (int)s.tasks.size();
       for (int ch = 0; ch < nch; ch += cpt)
         s.tasks.push_back(mk4(TASK_PAIR, free_cam[fa], free_cam[fb], base + ch, std::min(cpt, nch - ch)));
       blk_range[b].y = (int)s.tasks.size();
-      base += nch;
     }
   for (int fi = 0; fi < F; ++fi) s.targets.push_back(mk4(TASK_CAM, free_cam[fi], 0, cam_range[fi].x, cam_range[fi].y));
   if (!s.sparse) {

@@ -40,8 +40,11 @@ struct Staged {
   std::vector<int> ob_cam;       // [L] camera of each observation lane (0 for padding)
   std::vector<double> ob_uv;     // [2L] raw pixels (0 for padding)
   int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
-  std::vector<int> cl_pt, ql_pt;               // camera lanes [Lc], pair lanes [Lq]
-  std::vector<double> cl_uv, ql_uv;            // [2Lc], [4Lq] raw pixels
+  // camera lanes [Lc]: point (-1 for padding) and observation lane (0 for
+  // padding); pair lanes [Lq]: point and the observation lanes of its two
+  // observations (camera a, camera b)
+  std::vector<int> cl_pt, cl_ob, ql_pt;
+  std::vector<I2> ql_ob;
   std::vector<I4> tasks, targets;
   // sparse (PCG) reduced system: block CSR over the free cameras, diagonal first
   int sparse = 0;
@@ -75,10 +78,12 @@ bool ids_unique(const int64_t* id, int n);
 //    cut into chunks of 64 points of one count n; the chunk's observations
 //    stored observation-major (the t-th of each point, in camera order, in
 //    one 64-lane row), and chunks grouped into point-pass workgroups;
-//  * camera lanes: observations of each free camera in point order, each
-//    camera's run padded to whole chunks, cut into tasks of <= cpt chunks;
+//  * camera lanes: observations of each free camera in point order (point and
+//    observation lane), each camera's run padded to whole chunks, cut into
+//    tasks of <= cpt chunks;
 //  * pair lanes: the observation pairs of each point whose two cameras are
-//    free, grouped by camera pair, padded and cut into tasks likewise;
+//    free (point and both observation lanes), grouped by camera pair,
+//    padded and cut into tasks likewise;
 //  * reduction targets: each free camera, each camera pair, the intrinsics.
 // Returns BA_OK, or BA_E_ARG with the reason in err.
 int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, int solver);

@@ -46,8 +46,8 @@ bool same(const Staged& a, const Staged& b) {
     return x.size() == y.size() && (x.empty() || !memcmp(x.data(), y.data(), sizeof(x[0]) * x.size()));
   };
   return a.L == b.L && a.Lc == b.Lc && a.Lq == b.Lq && eq(a.pchunk, b.pchunk) && eq(a.wg_chunk, b.wg_chunk) &&
-         eq(a.ob_cam, b.ob_cam) && eq(a.ob_uv, b.ob_uv) && eq(a.cl_pt, b.cl_pt) && eq(a.cl_uv, b.cl_uv) && eq(a.ql_pt, b.ql_pt) &&
-         eq(a.ql_uv, b.ql_uv) && eq(a.tasks, b.tasks) && eq(a.targets, b.targets) && eq(a.pt_orig, b.pt_orig) &&
+         eq(a.ob_cam, b.ob_cam) && eq(a.ob_uv, b.ob_uv) && eq(a.cl_pt, b.cl_pt) && eq(a.cl_ob, b.cl_ob) && eq(a.ql_pt, b.ql_pt) &&
+         eq(a.ql_ob, b.ql_ob) && eq(a.tasks, b.tasks) && eq(a.targets, b.targets) && eq(a.pt_orig, b.pt_orig) &&
          eq(a.brow, b.brow) && eq(a.bcol, b.bcol) && eq(a.tslot, b.tslot) && eq(a.X, b.X) && eq(a.raw_cam, b.raw_cam);
 }
 
@@ -116,9 +116,9 @@ int main(int argc, char** argv) {
     put(fo, s.ob_cam);
     put(fo, s.ob_uv);
     put(fo, s.cl_pt);
-    put(fo, s.cl_uv);
+    put(fo, s.cl_ob);
     put(fo, s.ql_pt);
-    put(fo, s.ql_uv);
+    put(fo, s.ql_ob);
     put(fo, s.tasks);
     put(fo, s.targets);
     put(fo, s.cam_col);

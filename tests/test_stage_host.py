@@ -10,11 +10,13 @@ kernels rely on (CPU only):
     with its camera and pixel: every observation exactly once, padding lanes
     camera 0 and pixel 0; the point-pass workgroups cover the chunks in
     order;
-  * each free camera's lanes hold all its observations, in point order,
-    its run padded to whole chunks;
+  * each free camera's lanes hold all its observations, in point order, each
+    naming its point and its observation lane (whose camera, point and pixel
+    are the observation's), its run padded to whole chunks;
   * the pair lanes hold every pair of observations of one point whose
-    cameras are both free, once, in camera-pair blocks: their number is
-    sum_j n_j (n_j - 1) / 2 over the free observations n_j of each point;
+    cameras are both free, once, in camera-pair blocks, naming both
+    observation lanes: their number is sum_j n_j (n_j - 1) / 2 over the free
+    observations n_j of each point;
   * tasks tile the camera and pair lanes; targets list every free camera and
     camera pair with their task ranges;
   * the conjugate-gradient layout's block rows list the diagonal block first
@@ -86,16 +88,16 @@ def run(tools, sc, cpw=16, cpt=4, solver=0, threads=1, exe=None):
         buf = fh.read()
     hdr = np.frombuffer(buf[:48], np.int32)
     pos = 48
-    names = ["err", "pt_orig", "pchunk", "wg_chunk", "ob_cam", "ob_uv", "cl_pt", "cl_uv", "ql_pt", "ql_uv", "tasks",
+    names = ["err", "pt_orig", "pchunk", "wg_chunk", "ob_cam", "ob_uv", "cl_pt", "cl_ob", "ql_pt", "ql_ob", "tasks",
              "targets", "cam_col", "brow", "bcol"]
-    types = [np.int8, np.int32, np.int32, np.int32, np.int32, np.float64, np.int32, np.float64, np.int32, np.float64, np.int32,
+    types = [np.int8, np.int32, np.int32, np.int32, np.int32, np.float64, np.int32, np.int32, np.int32, np.int32, np.int32,
              np.int32, np.int32, np.int32, np.int32]
     out = dict(zip(["rc", "L", "n_chunks", "Lc", "Lq", "n_tasks", "n_targets", "m", "n_free", "sparse",
                     "n_cam_tasks", "n_wg"], hdr.tolist()))
     for name, dt in zip(names, types):
         if pos >= len(buf):
             break
-        n = int(np.frombuffer(buf[pos:pos + 8], np.int64)[0]) * (4 if name in ("tasks", "targets", "pchunk") else 1)
+        n = int(np.frombuffer(buf[pos:pos + 8], np.int64)[0]) * {"tasks": 4, "targets": 4, "pchunk": 4, "ql_ob": 2}.get(name, 1)
         pos += 8
         out[name] = np.frombuffer(buf[pos:pos + n * np.dtype(dt).itemsize], dt).copy()
         pos += n * np.dtype(dt).itemsize
@@ -145,6 +147,10 @@ def check_layout(sc, lay):
                       sc["obs_uv"][:, 1].tolist()))
     assert sorted(got) == want
     assert np.all(cam[pad] == 0) and np.all(uv[pad] == 0)
+    lane_pt = np.full(L, -1, np.int64)                 # point of each observation lane
+    for off, n, p0, nv in pc:
+        for t in range(n):
+            lane_pt[off + WAVE * t: off + WAVE * t + nv] = p0 + np.arange(nv)
     # point-pass workgroups: increasing chunk ranges covering every chunk
     wg = lay["wg_chunk"]
     assert wg[0] == 0 and wg[-1] == len(pc) and np.all(np.diff(wg) >= 1) and len(wg) == lay["n_wg"] + 1
@@ -152,23 +158,28 @@ def check_layout(sc, lay):
     free = np.nonzero(sc["fixed"] == 0)[0]
     col = lay["cam_col"]
     assert np.array_equal(np.nonzero(col >= 0)[0], free) and np.array_equal(col[free], 6 * np.arange(free.size))
-    cl_pt, cl_uv = lay["cl_pt"], lay["cl_uv"].reshape(-1, 2)
+    # (each lane names its point and its observation lane, whose camera,
+    # point and pixel are the observation's)
+    cl_pt, cl_ob = lay["cl_pt"], lay["cl_ob"]
     base = 0
     for k in free:
         o = np.nonzero(sc["obs_cam"] == k)[0]
         order = np.argsort(inv[sc["obs_pt"][o]], kind="stable")
-        run = cl_pt[base * WAVE: base * WAVE + o.size]
-        assert np.array_equal(run, inv[sc["obs_pt"][o]][order])
-        assert np.array_equal(cl_uv[base * WAVE: base * WAVE + o.size], sc["obs_uv"][o][order])
+        sl = slice(base * WAVE, base * WAVE + o.size)
+        assert np.array_equal(cl_pt[sl], inv[sc["obs_pt"][o]][order])
+        ob = cl_ob[sl]
+        assert np.all(cam[ob] == k) and np.array_equal(lane_pt[ob], cl_pt[sl])
+        assert np.array_equal(uv[ob], sc["obs_uv"][o][order])
         n_ch = -(-o.size // WAVE)
-        assert np.all(cl_pt[base * WAVE + o.size:(base + n_ch) * WAVE] == -1)
+        pad_sl = slice(base * WAVE + o.size, (base + n_ch) * WAVE)
+        assert np.all(cl_pt[pad_sl] == -1) and np.all(cl_ob[pad_sl] == 0)
         base += n_ch
     assert base * WAVE == lay["Lc"]
     # pair lanes: every pair of free observations of a point, once
     isfree = sc["fixed"][sc["obs_cam"]] == 0
     nfree = np.bincount(inv[sc["obs_pt"][isfree]], minlength=P)
     n_pairs = int((nfree * (nfree - 1) // 2).sum())
-    ql, ql_uv = lay["ql_pt"], lay["ql_uv"].reshape(-1, 4)
+    ql, ql_ob = lay["ql_pt"], lay["ql_ob"].reshape(-1, 2)
     assert (ql >= 0).sum() == n_pairs and lay["Lq"] % WAVE == 0
     uv_of = {(int(inv[p]), int(c)): (float(u), float(v)) for p, c, (u, v) in
              zip(sc["obs_pt"], sc["obs_cam"], sc["obs_uv"])}
@@ -190,7 +201,11 @@ def check_layout(sc, lay):
             if j >= 0:
                 assert (j, a, b) not in seen
                 seen.add((j, a, b))
-                assert tuple(ql_uv[lane]) == uv_of[(j, a)] + uv_of[(j, b)]
+                la, lb = ql_ob[lane]
+                assert cam[la] == a and cam[lb] == b and lane_pt[la] == j and lane_pt[lb] == j
+                assert tuple(uv[la]) + tuple(uv[lb]) == uv_of[(j, a)] + uv_of[(j, b)]
+            else:
+                assert tuple(ql_ob[lane]) == (0, 0)
     assert len(seen) == n_pairs
     # targets: every free camera, then (dense) every camera pair, with contiguous task ranges
     tg = lay["targets"]
