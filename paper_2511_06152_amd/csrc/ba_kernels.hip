@@ -1682,65 +1682,83 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
     if (tid == 0) c.solve_ok = 0;
     return;
   }
-  double* yk = wk + 2 * kSolveTb * kSolveTb;   // [16]
-  // L L^T x = x in place, block by block with the inverted diagonal blocks;
-  // one wavefront (at most 144 rows below a block: three per lane).
-  auto solve = [&](double* x) {
-    for (int K = 0; K < nb; ++K) {            // forward: L y = x
-      if (lane < kSolveTb) {
-        const double* li = Li + K * kTbV + lane * kTbS;
-        double s0 = 0.0, s1 = 0.0;
+  // W = L^-1, block lower triangular, in place of L's off-diagonal blocks
+  // (its diagonal blocks are the inverted factor blocks Li), block row by
+  // block row: W_IJ = -Li_I sum_{K=J}^{I-1} L_IK W_KJ on the matrix cores,
+  // wavefront w taking the columns J = w, w + 4, w + 8.  The running sum
+  // stays in the product's accumulator, which is also the B operand layout
+  // of the product by Li_I.  Then every solve is two matrix-vector products,
+  // x = W^T (W b), all threads at once.
+  {
+    const int lo = lane & 15, hi = lane >> 4;
+    for (int I = 1; I < nb; ++I) {
+      double4_t res[3];
 #pragma unroll
-        for (int q = 0; q < kSolveTb; q += 2) {
-          s0 = __builtin_fma(li[q], x[kSolveTb * K + q], s0);
-          s1 = __builtin_fma(li[q + 1], x[kSolveTb * K + q + 1], s1);
-        }
-        yk[lane] = s0 + s1;
-      }
-      wave_sync();
-      for (int p = kSolveTb * (K + 1) + lane; p < np; p += kWave) {
-        const double* row = A + tblk(p / kSolveTb, K) + (p % kSolveTb) * kTbS;
-        double s0 = 0.0, s1 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const int J = wave + 4 * q;
+        res[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        if (J >= I) continue;
+        double4_t t = {0.0, 0.0, 0.0, 0.0};
+        for (int K = J; K < I; ++K) {
+          const double* P = A + tblk(I, K);
+          const double* Q = K == J ? Li + J * kTbV : A + tblk(K, J);
 #pragma unroll
-        for (int q = 0; q < kSolveTb; q += 2) {
-          s0 = __builtin_fma(row[q], yk[q], s0);
-          s1 = __builtin_fma(row[q + 1], yk[q + 1], s1);
+          for (int u = 0; u < 4; ++u)
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lo * kTbS + 4 * u + hi], Q[(4 * u + hi) * kTbS + lo], t, 0, 0,
+                                                      0);
         }
-        x[p] -= s0 + s1;
+        const double* L = Li + I * kTbV;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          res[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L[lo * kTbS + 4 * u + hi], t[u], res[q], 0, 0, 0);
       }
-      if (lane < kSolveTb) x[kSolveTb * K + lane] = yk[lane];
-      wave_sync();
+      __syncthreads();   // every wavefront has read block row I of L
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int J = wave + 4 * q;
+        if (J >= I) continue;
+        double* out = A + tblk(I, J);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(hi + 4 * r) * kTbS + lo] = res[q][r];
+      }
+      __syncthreads();
     }
-    for (int K = nb - 1; K >= 0; --K) {       // backward: L^T x = y
-      if (lane < kSolveTb) {
-        const double* li = Li + K * kTbV + lane;
-        double s0 = 0.0, s1 = 0.0;
+  }
+  double* yv = wk;   // [np]
+  // out = W^T (W in); out may be in
+  auto wsolve = [&](const double* in, double* out) {
+    for (int p = tid; p < np; p += kSolveWG) {   // y = W in, one row each
+      const int I = p / kSolveTb, r = p % kSolveTb;
+      double s0 = 0.0, s1 = 0.0;
+      for (int J = 0; J <= I; ++J) {
+        const double* row = (J == I ? Li + I * kTbV : A + tblk(I, J)) + r * kTbS;
 #pragma unroll
         for (int q = 0; q < kSolveTb; q += 2) {
-          s0 = __builtin_fma(li[q * kTbS], x[kSolveTb * K + q], s0);
-          s1 = __builtin_fma(li[(q + 1) * kTbS], x[kSolveTb * K + q + 1], s1);
+          s0 = __builtin_fma(row[q], in[kSolveTb * J + q], s0);
+          s1 = __builtin_fma(row[q + 1], in[kSolveTb * J + q + 1], s1);
         }
-        yk[lane] = s0 + s1;
       }
-      wave_sync();
-      for (int p = lane; p < kSolveTb * K; p += kWave) {
-        const double* colp = A + tblk(K, p / kSolveTb) + p % kSolveTb;
-        double s0 = 0.0, s1 = 0.0;
+      yv[p] = s0 + s1;
+    }
+    __syncthreads();
+    for (int p = tid; p < np; p += kSolveWG) {   // out = W^T y, one column each
+      const int J = p / kSolveTb, c = p % kSolveTb;
+      double s0 = 0.0, s1 = 0.0;
+      for (int I = J; I < nb; ++I) {
+        const double* col = (I == J ? Li + J * kTbV : A + tblk(I, J)) + c;
 #pragma unroll
         for (int r = 0; r < kSolveTb; r += 2) {
-          s0 = __builtin_fma(colp[r * kTbS], yk[r], s0);
-          s1 = __builtin_fma(colp[(r + 1) * kTbS], yk[r + 1], s1);
+          s0 = __builtin_fma(col[r * kTbS], yv[kSolveTb * I + r], s0);
+          s1 = __builtin_fma(col[(r + 1) * kTbS], yv[kSolveTb * I + r + 1], s1);
         }
-        x[p] -= s0 + s1;
       }
-      if (lane < kSolveTb) x[kSolveTb * K + lane] = yk[lane];
-      wave_sync();
+      out[p] = s0 + s1;
     }
-  };
-  if (wave == 0) solve(xv);
-  if (d.mixed) {
-    // one FP64 refinement step: r = b - S_damped x, then L L^T dx = r, x += dx
     __syncthreads();
+  };
+  wsolve(bv, xv);
+  if (d.mixed) {
+    // one FP64 refinement step: r = b - S_damped x, then dx = S^-1 r, x += dx
     const double* Sd = lds_copy ? Sl : d.Sd;
     for (int p = tid; p < np; p += kSolveWG) {
       const int P = p / kSolveTb, pr_ = p % kSolveTb;
@@ -1757,11 +1775,9 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
       rv[p] = t0 + t1;
     }
     __syncthreads();
-    if (wave == 0) {
-      solve(rv);
-      for (int p = lane; p < np; p += kWave) xv[p] += rv[p];
-      wave_sync();
-    }
+    wsolve(rv, rv);
+    for (int p = tid; p < np; p += kSolveWG) xv[p] += rv[p];
+    __syncthreads();
   }
   if (tid >= kWave) return;
   // From here on one wavefront: predicted decrease, trial cameras, prior cost.
