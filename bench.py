@@ -69,12 +69,12 @@ TRAFFIC = {
     "fetch_scale": 262144.0 / 131084.9, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "blocks"): (91239.2, 2414.4),
-        (1, "blocks"): (174411.9, 4829.3),
+        (2, "blocks"): (87466.7, 2415.0),
+        (1, "blocks"): (165006.4, 4830.1),
     },
     "sources_sha256": {
-        "ba_kernels.hip": "a7f89dde36d8bccaaa4605d592407dc1fd75839f6ff376bd0c0510698a76c74c",
-        "ba_device.h": "451927cbab030830713cc888c0074ddd3651895ddafd31cba2231396d20a8d93",
+        "ba_kernels.hip": "5526faf06abec9d21c3731d0eb4bcd517b129cb7b746c801fe8f23e96681fba4",
+        "ba_device.h": "45093471b96384b378a47b719b8dd54046152bcd82b097b1d9331eb892ddbd1f",
     },
 }
 
@@ -119,13 +119,17 @@ def block_flops(sc):
 
 
 def solve_mfma_flops(sc):
-    """FP64 matrix-core flops of one dense factorisation of the cluster's
-    reduced system: m = 6 free cameras + estimated intrinsics, nb = ceil(m/16)
-    blocks per side; block column K does nb-K-1 panel products and
-    (nb-K-1)(nb-K)/2 trailing products of 16x16x16 (8192 flops each)."""
-    m = 6 * int((sc["fixed"] == 0).sum()) + bin(int(sc["intr_mask"]) & 3).count("1")
+    """FP64 matrix-core flops of one dense solve of the cluster's reduced
+    system: m = 6 free cameras + estimated intrinsics, nb = ceil(m/16) blocks
+    per side.  The factorisation's block column K does nb-K-1 panel products
+    and (nb-K-1)(nb-K)/2 trailing products; the block inverse W = L^-1 then
+    takes, for each block (I, J) below the diagonal, I-J products for its sum
+    and one by the inverted diagonal block.  Each is a 16x16x16 product (8192
+    flops)."""
+    m = 6 * int((sc["fixed"] == 0).sum()) + bin(int(sc["intr_mask"]) & 31).count("1")
     nb = -(-m // 16)
     prods = sum((nb - K - 1) + (nb - K - 1) * (nb - K) // 2 for K in range(nb))
+    prods += sum((nb - d) * (d + 1) for d in range(1, nb))
     return 8192.0 * prods
 
 
@@ -889,8 +893,9 @@ def main():
     solve_mc = {"kernel": "k_solve", "unit": "TFLOP/s", "peak": PEAK_MFMA_F64_TFLOPS,
                 "mfma_flop_per_launch": mfma_total / max(sv_n, 1), "avg_launch_us": sv_ms / max(sv_n, 1) * 1e3,
                 "achieved": (mfma_total / max(sv_n, 1)) / (sv_ms / max(sv_n, 1) / 1e3) / 1e12 if sv_n else None,
-                "note": "FP64 matrix-core work of the dense factorisation (16x16x16 panel and trailing block "
-                        "products) over the kernel's whole launch; the kernel is latency-bound (m <= 149)"}
+                "note": "FP64 matrix-core work of the dense solve (16x16x16 panel and trailing block products "
+                        "of the factorisation, products of the block inverse W = L^-1) over the kernel's whole "
+                        "launch; the kernel is latency-bound (m <= 149)"}
     solve_mc["frac"] = solve_mc["achieved"] / PEAK_MFMA_F64_TFLOPS if solve_mc["achieved"] else None
     ms_per_step = float(np.mean(step_ms))
     # the block kernels alone on the GPU: one more step on a single stream

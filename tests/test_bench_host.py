@@ -46,9 +46,10 @@ def test_traffic_only_for_the_measured_configuration():
 
 
 def test_solve_mfma_flops_against_a_count_of_block_products():
-    """Panel and trailing products of the right-looking 16x16-block Cholesky,
-    counted by walking the loops, for systems of 1..10 blocks per side."""
-    for free, intr in [(1, 0), (2, 2), (5, 3), (11, 3), (12, 3), (16, 0), (24, 3), (24, 0)]:
+    """Panel and trailing products of the right-looking 16x16-block Cholesky
+    and the products of the block inverse W = L^-1, counted by walking the
+    loops, for systems of 1..10 blocks per side."""
+    for free, intr in [(1, 0), (2, 2), (5, 3), (11, 3), (12, 3), (16, 0), (24, 3), (24, 0), (24, 31), (12, 28)]:
         sc = {"fixed": np.array([0] * free + [1] * 3, np.uint8), "intr_mask": intr}
         m = 6 * free + bin(intr).count("1")
         nb = -(-m // 16)
@@ -56,4 +57,7 @@ def test_solve_mfma_flops_against_a_count_of_block_products():
         for K in range(nb):
             prods += sum(1 for I in range(K + 1, nb))                                   # L_IK = A_IK L_KK^-T
             prods += sum(1 for J in range(K + 1, nb) for I in range(J, nb))             # A_IJ -= L_IK L_JK^T
+        for I in range(1, nb):
+            for J in range(I):
+                prods += sum(1 for K in range(J, I)) + 1                                # W_IJ = -Li_I sum L_IK W_KJ
         assert bench.solve_mfma_flops(sc) == 2 * 16 ** 3 * prods

@@ -5,7 +5,7 @@ the FP64 oracle, which solves the same reduced system by dense Cholesky.
 Bars:
   * FP64 path with a tight PCG tolerance (1e-12 relative residual): cost after
     every LM iteration within 1e-8 relative of the oracle's, same accepted
-    steps;
+    steps, and the final state element by element (the dense path's bars);
   * mixed path (FP32 products) with a tight PCG tolerance (1e-6), so that it
     follows the exact LM's trajectory: after 60 iterations RMS
     |p_gpu - p_oracle| < 1e-3 px, camera centres < 1 mm, attitude < 2e-6 rad;
@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 from synth import aerial as A
-from test_gpu_parity import check_cost_log, final_errors
+from test_gpu_parity import check_cost_log, check_state, final_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,7 @@ def test_pcg_fp64_cost_per_iteration_small():
     ref = oracle.solve(sc, max_iters=8)
     got = run(sc, 8, pcg_tol=1e-12, pcg_max_iters=2000)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
 
 
 def test_pcg_fp64_cost_per_iteration_40_cams():
@@ -56,6 +57,7 @@ def test_pcg_fp64_cost_per_iteration_40_cams():
     ref = oracle.solve(sc, max_iters=8)
     got = run(sc, 8, pcg_tol=1e-12, pcg_max_iters=4000)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
 
 
 def test_pcg_fp64_with_fixed_cameras_and_prior_only_camera():
@@ -70,6 +72,7 @@ def test_pcg_fp64_with_fixed_cameras_and_prior_only_camera():
     ref = oracle.solve(sc, max_iters=6)
     got = run(sc, 6, pcg_tol=1e-12, pcg_max_iters=4000)
     check_cost_log(got, ref)
+    check_state(sc, got, ref)
 
 
 def test_pcg_mixed_tight_tolerance_40_cams():
