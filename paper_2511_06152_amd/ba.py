@@ -207,7 +207,7 @@ class Context:
     """Owns a ba_ctx.  Methods mirror the C ABI and raise BAError on failure."""
 
     def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 1 << 30, max_slots: int = 256,
-                 max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 2,
+                 max_queue: int = 4096, precision: int = BA_FP64, serve: bool = False, iters_per_tick: int = 10,
                  chunks_per_wg: int = 16, chunks_per_task: int = 4, solver: int = BA_SOLVER_AUTO,
                  pcg_max_iters: int = 500, pcg_tol: float = 0.1, resident_cams: int = 0,
                  resident_points: int = 0, batch_streams: int = 0, allocator=None, stage_threads: int = 0):

@@ -1565,13 +1565,16 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   const int pk = min(tid, d.C - 1);
   // the prior terms of camera tid at the current state (cached when that
   // state's cameras were formed), requested first
-  double pe[6], pJ[9];
+  double pe[6], pJ[9], pis[3];   // pis: 1/sigma of the position prior, three axes
   {
     const gdp gt = (gdp)d.pterm[cur] + kPtermVals * pk;
 #pragma unroll
     for (int i = 0; i < 6; ++i) pe[i] = gt[i];
 #pragma unroll
     for (int i = 0; i < 9; ++i) pJ[i] = gt[6 + i];
+    const gdp gs = (gdp)d.prior + kPriorVals * pk + 15;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pis[i] = gs[i];
   }
   const int pcol = tid < d.C ? d.cam_col[tid] : -1;
   // what the closing wavefront needs (camera tid's state and prior, the
@@ -1607,8 +1610,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
   // Pose priors of the free cameras, one thread per camera (disjoint entries).
   // Element (p, q) is stored when p's block row is at or below q's; the
   // diagonal blocks hold both triangles.
-  auto add_prior = [&](int k, int col, const double* e, const double* J) {
-    const double* pr = d.prior + kPriorVals * k;
+  auto add_prior = [&](int col, const double* e, const double* J, const double* is) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
@@ -1620,20 +1622,20 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(Batch bt) {
         if (q == r) Dv[col + r] += h;
       }
       gv[col + r] += J[r] * e[0] + J[3 + r] * e[1] + J[6 + r] * e[2];
-      const double it = pr[15 + r];
+      const double it = is[r];
       const int p3 = col + 3 + r;
       A[tblk(p3 / kSolveTb, p3 / kSolveTb) + (p3 % kSolveTb) * (kTbS + 1)] += it * it;
       Dv[col + 3 + r] += it * it;
       gv[col + 3 + r] += it * e[3 + r];
     }
   };
-  if (pcol >= 0) add_prior(tid, pcol, pe, pJ);
+  if (pcol >= 0) add_prior(pcol, pe, pJ, pis);
   for (int k = tid + kSolveWG; k < d.C; k += kSolveWG) {   // clusters of more than 256 cameras
     const int col = d.cam_col[k];
     if (col < 0) continue;
     double e[6], J[9];
     pterm_load(d.pterm[cur] + kPtermVals * k, e, J);
-    add_prior(k, col, e, J);
+    add_prior(col, e, J, d.prior + kPriorVals * k + 15);
   }
   __syncthreads();
   // Marquardt damping and the right-hand side.

@@ -353,6 +353,7 @@ struct Launcher {
   SlotCtl* h_ctl = nullptr; // pinned readback of all slots' control blocks
   hipEvent_t ev = nullptr;
   hipEvent_t copy_ev = nullptr;  // after the last upload from h_act
+  hipEvent_t exp_ev = nullptr;   // after the copies of the last export
   bool copy_pending = false;
   std::vector<SparseLaunch> sp;  // the batch's clusters solved by conjugate gradients
 };
@@ -404,6 +405,7 @@ struct ba_ctx {
   std::vector<ResRow> res_cam_meta, res_pt_meta;
   double res_lambda = NAN;        // damping the last written-back cluster ended with
   // background layout (ba_options.stage_threads > 0)
+  std::vector<std::unique_ptr<Staged>> staged_pool;   // admitted layouts kept for reuse (mu)
   std::vector<std::thread> stagers;
   std::deque<std::pair<ba_ticket, std::unique_ptr<ClusterCopy>>> stage_jobs;
   std::condition_variable stage_cv;       // wakes the layout threads
@@ -530,6 +532,7 @@ int init_launcher(ba_ctx* c, Launcher& l) {
   HIPCHK(c, hipHostMalloc(&l.h_ctl, sizeof(SlotCtl) * S, hipHostMallocDefault));
   HIPCHK(c, hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
   HIPCHK(c, hipEventCreateWithFlags(&l.copy_ev, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreateWithFlags(&l.exp_ev, hipEventDisableTiming));
   return BA_OK;
 }
 
@@ -540,6 +543,7 @@ void free_launcher(ba_ctx* c, Launcher& l) {
   if (l.h_ctl) (void)hipHostFree(l.h_ctl);
   if (l.ev) (void)hipEventDestroy(l.ev);
   if (l.copy_ev) (void)hipEventDestroy(l.copy_ev);
+  if (l.exp_ev) (void)hipEventDestroy(l.exp_ev);
   l = Launcher();
 }
 
@@ -676,6 +680,24 @@ int res_register(ba_ctx* c, Ticket& t, const Staged& s) {
   std::sort(t.deps.begin(), t.deps.end());
   t.resident = true;
   return BA_OK;
+}
+
+// A Staged for the next layout: a recycled one (its vectors keep their
+// storage) when the pool has one.  Caller holds mu.
+std::unique_ptr<Staged> take_staged(ba_ctx* c) {
+  if (c->staged_pool.empty()) return std::make_unique<Staged>();
+  auto s = std::move(c->staged_pool.back());
+  c->staged_pool.pop_back();
+  return s;
+}
+
+// Returns an admitted cluster's Staged to the pool (its upload image goes
+// back to the pinned pool now), unless the pool is full or the cluster was
+// very large.  Caller holds mu.
+void recycle_staged(ba_ctx* c, std::unique_ptr<Staged> s) {
+  if (!s || (size_t)s->O > kKeepObs || c->staged_pool.size() >= (size_t)c->opt.stage_threads + 2) return;
+  s->blob.reset();
+  c->staged_pool.push_back(std::move(s));
 }
 
 // Moves the ticket's staged data into a free slot and arena block.  Returns
@@ -829,7 +851,7 @@ int admit_one(ba_ctx* c, Ticket& t) {
   t.slot = slot;
   t.state = TK_RESIDENT;
   t.t_admit = now_s();
-  t.staged.reset();
+  recycle_staged(c, std::move(t.staged));
   return BA_OK;
 }
 
@@ -956,8 +978,29 @@ int run_tick(ba_ctx* c, bool serving, const std::vector<int>& act, int n_iters) 
   return run_iterations(c, serving ? c->srv : c->api, act, n_iters);
 }
 
-// Exports the listed slots' state into their ticket caches (synchronous).
-int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
+// An export in flight: each slot's result region (cost, damping and accept
+// logs, reprojection sums, exported state: the block's tail from the cost
+// log on) copied in stream order into pinned host memory, with what the
+// finish needs once the slot itself may have been reused.
+struct ExportJob {
+  struct Item {
+    ba_ticket ticket = 0;
+    int C = 0, P = 0, max_iters = 0;
+    size_t lam, acc, out;            // offsets in the region
+    bool res_finish = false;         // a resident cluster done with the store
+    SlotCtl ctl{};
+    std::shared_ptr<char> buf;       // pinned, or ordinary memory when the pool is full
+  };
+  std::vector<Item> items;
+};
+
+// Enqueues the export of the listed slots on the context's stream: the
+// export kernels, one copy per slot, the resident write-back of finished
+// clusters, then l.exp_ev.  l.h_ctl must hold the slots' current control
+// blocks.  Later work on the stream (uploads into a freed slot block)
+// comes after the copies.
+int export_begin(ba_ctx* c, Launcher& l, const std::vector<int>& slots, ExportJob& job) {
+  job.items.clear();
   if (slots.empty()) return BA_OK;
   Batch b;
   int rc = make_batch(c, l, slots, b);
@@ -965,27 +1008,31 @@ int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
   int maxP = 0;
   for (int s : slots) maxP = std::max(maxP, c->slots[s].desc.P);
   HIPCHK(c, launch_export(b, maxP, c->stream));
+  std::vector<int> wb;
   for (int s : slots) {
-    Slot& sl = c->slots[s];
-    Ticket& t = *c->tickets[sl.ticket];
-    t.out.resize(12 * (size_t)sl.desc.C + 3 * (size_t)sl.desc.P + 5 + kStatVals);
-    t.cost_log.resize((size_t)sl.desc.max_iters + 1);
-    t.lambda_log.resize((size_t)sl.desc.max_iters);
-    t.acc_log.resize((size_t)sl.desc.max_iters);
-    HIPCHK(c, hipMemcpyAsync(t.out.data(), sl.desc.out, 8 * t.out.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(t.cost_log.data(), sl.desc.cost_log, 8 * t.cost_log.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(t.lambda_log.data(), sl.desc.lambda_log, 8 * t.lambda_log.size(), hipMemcpyDeviceToHost,
+    const Slot& sl = c->slots[s];
+    const Ticket& t = *c->tickets[sl.ticket];
+    ExportJob::Item it;
+    it.ticket = t.id;
+    it.C = sl.desc.C;
+    it.P = sl.desc.P;
+    it.max_iters = sl.desc.max_iters;
+    it.lam = sl.lay.lambda_log - sl.lay.cost_log;
+    it.acc = sl.lay.acc_log - sl.lay.cost_log;
+    it.out = sl.lay.out - sl.lay.cost_log;
+    it.ctl = l.h_ctl[s];
+    const size_t bytes = sl.lay.total - sl.lay.cost_log;
+    it.buf = pin_get(c, bytes);
+    if (!it.buf) it.buf = std::shared_ptr<char>(new char[bytes], std::default_delete<char[]>());
+    HIPCHK(c, hipMemcpyAsync(it.buf.get(), c->arena_base + sl.off + sl.lay.cost_log, bytes, hipMemcpyDeviceToHost,
                              c->stream));
-    HIPCHK(c, hipMemcpyAsync(t.acc_log.data(), sl.desc.acc_log, 4 * t.acc_log.size(), hipMemcpyDeviceToHost, c->stream));
-  }
-  // Finished resident clusters write their state back (once).
-  std::vector<int> wb, done;
-  for (int s : slots) {
-    Ticket& t = *c->tickets[c->slots[s].ticket];
-    const int st = l.h_ctl[s].status;
-    if (!t.resident || t.res_done || !is_finished(st)) continue;
-    done.push_back(s);
-    if (st != ST_BAD_INIT) wb.push_back(s);
+    // finished resident clusters write their state back (once)
+    const int st = it.ctl.status;
+    if (t.resident && !t.res_done && is_finished(st)) {
+      it.res_finish = true;
+      if (st != ST_BAD_INIT) wb.push_back(s);
+    }
+    job.items.push_back(std::move(it));
   }
   if (!wb.empty()) {
     Batch bw;
@@ -994,15 +1041,35 @@ int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
     for (int s : wb) maxR = std::max({maxR, c->slots[s].desc.n_rout_cam, c->slots[s].desc.n_rout_pt});
     HIPCHK(c, launch_writeback(bw, maxR, c->stream));
   }
-  rc = read_ctl(c, l);
-  if (rc) return rc;
-  for (int s : slots) c->tickets[c->slots[s].ticket]->ctl = l.h_ctl[s];
-  for (int s : done) {
-    Ticket& t = *c->tickets[c->slots[s].ticket];
-    if (l.h_ctl[s].status != ST_BAD_INIT) {
+  HIPCHK(c, hipEventRecord(l.exp_ev, c->stream));
+  return BA_OK;
+}
+
+// Waits for an export's copies and moves the results into the ticket caches;
+// resident clusters that finished release their store rows.
+int export_finish(ba_ctx* c, Launcher& l, ExportJob& job) {
+  if (job.items.empty()) return BA_OK;
+  HIPCHK(c, hipEventSynchronize(l.exp_ev));
+  bool any_res = false;
+  for (ExportJob::Item& it : job.items) {
+    Ticket& t = *c->tickets[it.ticket];
+    const char* r = it.buf.get();
+    const double* lg = (const double*)r;
+    t.cost_log.assign(lg, lg + it.max_iters + 1);
+    const double* lm = (const double*)(r + it.lam);
+    t.lambda_log.assign(lm, lm + it.max_iters);
+    const int* ac = (const int*)(r + it.acc);
+    t.acc_log.assign(ac, ac + it.max_iters);
+    const double* o = (const double*)(r + it.out);
+    t.out.assign(o, o + 12 * (size_t)it.C + 3 * (size_t)it.P + 5 + kStatVals);
+    t.ctl = it.ctl;
+    it.buf.reset();
+    if (!it.res_finish) continue;
+    any_res = true;
+    if (it.ctl.status != ST_BAD_INIT) {
       for (int row : t.cam_rows) c->res_cam_meta[row].valid = true;
       for (int row : t.pt_rows) c->res_pt_meta[row].valid = true;
-      c->res_lambda = l.h_ctl[s].lambda;
+      c->res_lambda = it.ctl.lambda;
     }
     for (int row : t.cam_rows)
       if (c->res_cam_meta[row].pending == t.id) c->res_cam_meta[row].pending = 0;
@@ -1010,8 +1077,19 @@ int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
       if (c->res_pt_meta[row].pending == t.id) c->res_pt_meta[row].pending = 0;
     t.res_done = true;
   }
-  if (!done.empty()) c->cv.notify_all();
+  job.items.clear();
+  if (any_res) c->cv.notify_all();
   return BA_OK;
+}
+
+// Exports the listed slots' state into their ticket caches (synchronous).
+int export_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
+  if (slots.empty()) return BA_OK;
+  int rc = read_ctl(c, l);
+  if (rc) return rc;
+  ExportJob job;
+  if ((rc = export_begin(c, l, slots, job))) return rc;
+  return export_finish(c, l, job);
 }
 
 void free_slot(ba_ctx* c, int s) {
@@ -1048,6 +1126,28 @@ bool serving_queued(ba_ctx* c) {
   return false;
 }
 
+// LM iterations of the next serving tick: iters_per_tick, cut so that the
+// tick ends when the first running cluster reaches its iteration cap (it is
+// retired at once), and cut to a quarter while a free slot waits for a
+// cluster whose layout is still running (it is admitted sooner).  `adm`:
+// slots admitted for this tick (their read-back control is not theirs yet).
+int tick_iters(ba_ctx* c, const std::vector<int>& active, const std::vector<int>& adm) {
+  int n = c->opt.iters_per_tick;
+  for (int s : active) {
+    const bool fresh = std::find(adm.begin(), adm.end(), s) != adm.end();
+    const int rem = c->slots[s].desc.max_iters - (fresh ? 0 : c->srv.h_ctl[s].iter);
+    n = std::min(n, std::max(rem, 1));
+  }
+  if ((int)active.size() < c->opt.max_slots && n > 4) {
+    for (const auto& kv : c->tickets)
+      if (kv.second->serving && kv.second->staging) {
+        n = std::max(4, n / 4);
+        break;
+      }
+  }
+  return n;
+}
+
 // One serving tick: retire finished clusters, admit queued ones, iterate.
 Ticket* find_ticket(ba_ctx* c, ba_ticket id);
 
@@ -1074,25 +1174,23 @@ void serve_loop(ba_ctx* c) {
       c->cancel.clear();
       c->done_cv.notify_all();
     }
-    // retire
+    // retire: the export is enqueued and the finished slots are freed at
+    // once (uploads into their blocks come later on the stream); the next
+    // tick is launched before the host waits for the export's copies
     std::vector<int> fin;
     for (int s : active)
       if (is_finished(c->srv.h_ctl[s].status)) fin.push_back(s);
+    ExportJob job;
+    std::vector<ba_ticket> fin_t;
     if (!fin.empty()) {
-      if (export_slots(c, c->srv, fin)) break;
-      const double t_done = now_s();
+      if (export_begin(c, c->srv, fin, job)) break;
       for (int s : fin) {
-        Ticket& t = *c->tickets[c->slots[s].ticket];
-        t.state = TK_DONE;
-        t.serving = false;
-        t.slot = -1;
-        t.t_done = t_done;
+        fin_t.push_back(c->slots[s].ticket);
         free_slot(c, s);
       }
       active.erase(std::remove_if(active.begin(), active.end(),
                                   [&](int s) { return std::find(fin.begin(), fin.end(), s) != fin.end(); }),
                    active.end());
-      c->done_cv.notify_all();
     }
     // admit
     std::vector<int> adm;
@@ -1101,15 +1199,30 @@ void serve_loop(ba_ctx* c) {
       if (start_slots(c, c->srv, adm)) break;
       active.insert(active.end(), adm.begin(), adm.end());
     }
+    if (!active.empty()) {
+      if (run_tick(c, true, active, tick_iters(c, active, adm))) break;
+      if (hipMemcpyAsync(c->srv.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost,
+                         c->stream) ||
+          hipEventRecord(c->srv.ev, c->stream)) {
+        c->dead = true;
+        break;
+      }
+    }
+    if (!fin.empty()) {
+      if (export_finish(c, c->srv, job)) break;
+      const double t_done = now_s();
+      for (ba_ticket id : fin_t) {
+        Ticket& t = *c->tickets[id];
+        t.state = TK_DONE;
+        t.serving = false;
+        t.slot = -1;
+        t.t_done = t_done;
+      }
+      c->done_cv.notify_all();
+    }
     if (active.empty()) {
       c->cv.wait(lk, [&] { return c->stop || serving_queued(c) || !c->cancel.empty(); });
       continue;
-    }
-    if (run_tick(c, true, active, c->opt.iters_per_tick)) break;
-    if (hipMemcpyAsync(c->srv.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost, c->stream) ||
-        hipEventRecord(c->srv.ev, c->stream)) {
-      c->dead = true;
-      break;
     }
     lk.unlock();
     const hipError_t e = hipEventSynchronize(c->srv.ev);
@@ -1181,7 +1294,7 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (c->opt.hbm_budget_bytes == 0) c->opt.hbm_budget_bytes = (size_t)1 << 30;
   if (c->opt.max_slots <= 0) c->opt.max_slots = 256;
   if (c->opt.max_queue <= 0) c->opt.max_queue = 4096;
-  if (c->opt.iters_per_tick <= 0) c->opt.iters_per_tick = 2;
+  if (c->opt.iters_per_tick <= 0) c->opt.iters_per_tick = 10;
   if (c->opt.chunks_per_wg <= 0) c->opt.chunks_per_wg = 16;
   if (c->opt.chunks_per_task <= 0) c->opt.chunks_per_task = 4;
   if (c->opt.pcg_max_iters <= 0) c->opt.pcg_max_iters = 500;
@@ -1299,7 +1412,11 @@ int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
     std::lock_guard<std::mutex> g(c->mu);
     return enqueue_copy(c, cl, ticket, t_submit);
   }
-  auto st = std::make_unique<Staged>();
+  std::unique_ptr<Staged> st;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    st = take_staged(c);
+  }
   std::string err;
   int rc = stage(cl, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
   if (!rc) {
@@ -1327,6 +1444,10 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
     return BA_OK;
   }
   std::vector<std::unique_ptr<Staged>> st(n);
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    for (auto& p : st) p = take_staged(c);
+  }
   std::vector<int> rc(n, BA_OK);
   std::vector<std::string> err(n);
   {
@@ -1334,7 +1455,6 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
     std::atomic<int> next{0};
     auto work = [&]() {
       for (int i; (i = next.fetch_add(1)) < n;) {
-        st[i] = std::make_unique<Staged>();
         rc[i] = stage(&cl[i], *st[i], err[i], c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
         if (!rc[i]) {
           const Layout lay = make_layout(*st[i], c->opt.precision == BA_MIXED);
@@ -1383,8 +1503,8 @@ void stage_worker(ba_ctx* c) {
     if (c->stage_stop) return;
     auto job = std::move(c->stage_jobs.front());
     c->stage_jobs.pop_front();
+    auto st = take_staged(c);
     lk.unlock();
-    auto st = std::make_unique<Staged>();
     std::string err;
     const int rc = stage(&job.second->c, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
     Layout lay;

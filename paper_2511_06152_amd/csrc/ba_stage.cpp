@@ -19,7 +19,58 @@ bool finite_all(const double* p, size_t n) {
 
 I4 mk4(int kind, int a, int b, int y, int z) { return I4{(kind << 24) | (a << 12) | b, y, z, 0}; }
 
+// Spreads the 16 low bits of x to the even bit positions.
+uint32_t spread16(uint32_t x) {
+  x &= 0xffffu;
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+// Scratch arrays of one layout, kept per thread so that a thread that lays
+// out cluster after cluster reuses their storage.
+struct Work {
+  std::vector<int> nobs, inv, opt, cnt, order, by_cam, cc, fill, scam, spt, oblane, free_cam, coff, cbase, cend, pcount,
+      pbase, brow0, sfree;
+  std::vector<uint64_t> kj, tmp;
+  std::vector<double> suv;
+  std::vector<I2> cam_range, blk_range;
+};
+
+template <typename T, typename A>
+void keep_storage(std::vector<T, A>& dst, std::vector<T, A>& src) {
+  dst.swap(src);
+  dst.clear();
+}
+
 }  // namespace
+
+void reset_keep(Staged& s) {
+  Staged f;
+  keep_storage(f.raw_cam, s.raw_cam);
+  keep_storage(f.X, s.X);
+  keep_storage(f.pt_orig, s.pt_orig);
+  keep_storage(f.cam_col, s.cam_col);
+  keep_storage(f.pchunk, s.pchunk);
+  keep_storage(f.wg_chunk, s.wg_chunk);
+  keep_storage(f.ob_cam, s.ob_cam);
+  keep_storage(f.ob_uv, s.ob_uv);
+  keep_storage(f.cl_pt, s.cl_pt);
+  keep_storage(f.cl_ob, s.cl_ob);
+  keep_storage(f.ql_pt, s.ql_pt);
+  keep_storage(f.ql_ob, s.ql_ob);
+  keep_storage(f.tasks, s.tasks);
+  keep_storage(f.targets, s.targets);
+  keep_storage(f.brow, s.brow);
+  keep_storage(f.bcol, s.bcol);
+  keep_storage(f.tslot, s.tslot);
+  keep_storage(f.cam_ids, s.cam_ids);
+  keep_storage(f.point_ids, s.point_ids);
+  keep_storage(f.cam_nobs, s.cam_nobs);
+  s = std::move(f);
+}
 
 uint64_t mix_id(int64_t id) {
   uint64_t z = (uint64_t)id + 0x9e3779b97f4a7c15ull;
@@ -72,7 +123,14 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
     if (!ids_unique(c->cam_ids, C)) { err = "duplicate camera ID in the cluster"; return BA_E_ARG; }
     if (!ids_unique(c->point_ids, P)) { err = "duplicate point ID in the cluster"; return BA_E_ARG; }
   }
-  s = Staged();
+  reset_keep(s);
+  thread_local Work w;
+  // the scratch of a very large cluster (a whole flight) is not kept
+  struct Trim {
+    Work& w;
+    bool big;
+    ~Trim() { if (big) w = Work(); }
+  } trim{w, (size_t)O > kKeepObs};
   s.C = C; s.P = P; s.O = O;
   if (c->use_resident) {
     s.resident = true;
@@ -121,7 +179,8 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   // point chunk have the same observation count and a camera's observations
   // touch nearby point records.  Ties keep the caller's order (LSD radix sort
   // of key << 32 | index on the key bits, then a stable counting sort by count).
-  std::vector<int> nobs(P, 0);
+  std::vector<int>& nobs = w.nobs;
+  nobs.assign(P, 0);
   for (int o = 0; o < O; ++o)
     if (++nobs[c->obs_pt[o]] > BA_MAX_OBS_PER_POINT) { err = "more than 64 observations of one point"; return BA_E_ARG; }
   {
@@ -131,7 +190,10 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
         lo[t] = std::min(lo[t], c->X[3 * (size_t)j + t]);
         hi[t] = std::max(hi[t], c->X[3 * (size_t)j + t]);
       }
-    std::vector<uint64_t> kj(P), tmp(P);
+    std::vector<uint64_t>& kj = w.kj;
+    std::vector<uint64_t>& tmp = w.tmp;
+    kj.resize(P);
+    tmp.resize(P);
     for (int j = 0; j < P; ++j) {
       uint32_t q[2];
       for (int t = 0; t < 2; ++t) {
@@ -139,8 +201,7 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
         const double u = span > 0 ? (c->X[3 * (size_t)j + t] - lo[t]) / span : 0.0;
         q[t] = (uint32_t)std::min(65535.0, std::max(0.0, u * 65535.0));
       }
-      uint32_t k = 0;
-      for (int b = 0; b < 16; ++b) k |= ((q[0] >> b) & 1u) << (2 * b) | ((q[1] >> b) & 1u) << (2 * b + 1);
+      const uint32_t k = spread16(q[0]) | spread16(q[1]) << 1;   // x bits even, y bits odd
       kj[j] = (uint64_t)k << 32 | (uint32_t)j;
     }
     for (int shift = 32; shift < 64; shift += 11) {
@@ -159,28 +220,41 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
       s.pt_orig[cls[nobs[j]]++] = j;
     }
   }
-  std::vector<int> inv(P), opt(O);
+  std::vector<int>& inv = w.inv;
+  std::vector<int>& opt = w.opt;
+  inv.resize(P);
+  opt.resize(O);
   for (int n = 0; n < P; ++n) inv[s.pt_orig[n]] = n;
   for (int o = 0; o < O; ++o) opt[o] = inv[c->obs_pt[o]];
   s.X.resize(3 * (size_t)P);
   for (int n = 0; n < P; ++n)
     for (int t = 0; t < 3; ++t) s.X[3 * (size_t)n + t] = c->X[3 * (size_t)s.pt_orig[n] + t];
   // observations per point (internal order)
-  std::vector<int> cnt(P + 1, 0);
+  std::vector<int>& cnt = w.cnt;
+  cnt.assign(P + 1, 0);
   for (int n = 0; n < P; ++n) cnt[n + 1] = cnt[n] + nobs[s.pt_orig[n]];
   // observations in (point, camera) order: a counting sort by camera, then a
   // stable one by point; then their camera, pixel and point in that order
-  std::vector<int> order(O);
+  std::vector<int>& order = w.order;
+  order.resize(O);
   {
-    std::vector<int> by_cam(O), cc(C + 1, 0);
+    std::vector<int>& by_cam = w.by_cam;
+    std::vector<int>& cc = w.cc;
+    by_cam.resize(O);
+    cc.assign(C + 1, 0);
     for (int o = 0; o < O; ++o) ++cc[c->obs_cam[o] + 1];
     for (int k = 0; k < C; ++k) cc[k + 1] += cc[k];
     for (int o = 0; o < O; ++o) by_cam[cc[c->obs_cam[o]]++] = o;
-    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    std::vector<int>& fill = w.fill;
+    fill.assign(cnt.begin(), cnt.end() - 1);
     for (int t = 0; t < O; ++t) order[fill[opt[by_cam[t]]]++] = by_cam[t];
   }
-  std::vector<int> scam(O), spt(O);
-  std::vector<double> suv(2 * (size_t)O);
+  std::vector<int>& scam = w.scam;
+  std::vector<int>& spt = w.spt;
+  std::vector<double>& suv = w.suv;
+  scam.resize(O);
+  spt.resize(O);
+  suv.resize(2 * (size_t)O);
   for (int j = 0; j < P; ++j)
     for (int t = cnt[j]; t < cnt[j + 1]; ++t) {
       const int o = order[t];
@@ -206,10 +280,11 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
     pb = pe;
   }
   s.n_chunks = (int)s.pchunk.size();
-  s.ob_cam.assign(s.L, 0);
-  s.ob_uv.assign(2 * (size_t)s.L, 0.0);
-  std::vector<int> oblane(O);   // observation lane of each observation in (point, camera) order
-  for (const I4& ch : s.pchunk)
+  s.ob_cam.resize(s.L);
+  s.ob_uv.resize(2 * (size_t)s.L);
+  std::vector<int>& oblane = w.oblane;   // observation lane of each observation in (point, camera) order
+  oblane.resize(O);
+  for (const I4& ch : s.pchunk) {
     for (int l = 0; l < ch.w; ++l)
       for (int t = 0; t < ch.y; ++t) {
         const int so = cnt[ch.z + l] + t;
@@ -219,6 +294,14 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
         s.ob_uv[2 * (size_t)lane] = suv[2 * (size_t)so];
         s.ob_uv[2 * (size_t)lane + 1] = suv[2 * (size_t)so + 1];
       }
+    for (int l = ch.w; l < kWave; ++l)   // padding lanes
+      for (int t = 0; t < ch.y; ++t) {
+        const int lane = ch.x + kWave * t + l;
+        s.ob_cam[lane] = 0;
+        s.ob_uv[2 * (size_t)lane] = 0.0;
+        s.ob_uv[2 * (size_t)lane + 1] = 0.0;
+      }
+  }
   // point-pass workgroups: runs of whole chunks holding at least cpw * 64
   // observation lanes each
   s.wg_chunk.assign(1, 0);
@@ -234,32 +317,41 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   s.n_pt_part = intr ? s.n_wg * kWavesPerWG : 0;
   s.nb = (s.m + kSolveTb - 1) / kSolveTb;
   const int F = s.n_free;
-  std::vector<int> free_cam(F);
+  std::vector<int>& free_cam = w.free_cam;
+  free_cam.resize(F);
   for (int k = 0; k < C; ++k)
     if (s.cam_col[k] >= 0) free_cam[s.cam_col[k] / 6] = k;
   // camera lanes and tasks: each free camera's observations in point order,
   // each lane naming its point and its observation lane
-  std::vector<int> coff(F + 1, 0);
+  std::vector<int>& sfree = w.sfree;   // free-camera index of each observation, -1 for a fixed camera
+  sfree.resize(O);
+  std::vector<int>& coff = w.coff;
+  coff.assign(F + 1, 0);
   for (int t = 0; t < O; ++t) {
     const int col = s.cam_col[scam[t]];
+    sfree[t] = col < 0 ? -1 : col / 6;
     if (col >= 0) ++coff[col / 6 + 1];
   }
-  std::vector<int> cbase(F + 1, 0);   // first lane of each camera's run
+  std::vector<int>& cbase = w.cbase;   // first lane of each camera's run
+  cbase.assign(F + 1, 0);
   for (int fi = 0; fi < F; ++fi) cbase[fi + 1] = cbase[fi] + (int)align_up(coff[fi + 1], kWave);
   s.Lc = cbase[F];
-  s.cl_pt.assign(s.Lc, -1);
-  s.cl_ob.assign(s.Lc, 0);
+  s.cl_pt.resize(s.Lc);
+  s.cl_ob.resize(s.Lc);
   {
-    std::vector<int> fill(cbase.begin(), cbase.end() - 1);
+    std::vector<int>& fill = w.fill;
+    fill.assign(cbase.begin(), cbase.end() - 1);
     for (int t = 0; t < O; ++t) {
-      const int col = s.cam_col[scam[t]];
-      if (col < 0) continue;
-      const int lane = fill[col / 6]++;
+      if (sfree[t] < 0) continue;
+      const int lane = fill[sfree[t]]++;
       s.cl_pt[lane] = spt[t];
       s.cl_ob[lane] = oblane[t];
     }
+    for (int fi = 0; fi < F; ++fi)   // padding lanes: point -1, observation lane 0
+      for (int l = fill[fi]; l < cbase[fi + 1]; ++l) s.cl_pt[l] = -1, s.cl_ob[l] = 0;
   }
-  std::vector<I2> cam_range(F);
+  std::vector<I2>& cam_range = w.cam_range;
+  cam_range.resize(F);
   for (int fi = 0; fi < F; ++fi) {
     const int base = cbase[fi] / kWave, nch = (cbase[fi + 1] - cbase[fi]) / kWave;
     cam_range[fi].x = (int)s.tasks.size();
@@ -272,38 +364,46 @@ int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, in
   // the observation lanes of its two observations
   const int nblk = F * (F - 1) / 2;
   auto blk = [F](int fa, int fb) { return fa * F - fa * (fa + 1) / 2 + (fb - fa - 1); };
-  std::vector<int> pcount(nblk, 0);
+  std::vector<int>& brow0 = w.brow0;   // block of (fa, fb) = brow0[fa] + fb
+  brow0.resize(F);
+  for (int fa = 0; fa < F; ++fa) brow0[fa] = blk(fa, fa + 1) - (fa + 1);
+  std::vector<int>& pcount = w.pcount;
+  pcount.assign(nblk, 0);
   for (int j = 0; j < P; ++j)
     for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
-      const int ca = s.cam_col[scam[ta]];
-      if (ca < 0) continue;
-      for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
-        const int cb = s.cam_col[scam[tb]];
-        if (cb >= 0) ++pcount[blk(ca / 6, cb / 6)];
-      }
+      const int fa = sfree[ta];
+      if (fa < 0) continue;
+      for (int tb = ta + 1; tb < cnt[j + 1]; ++tb)
+        if (sfree[tb] >= 0) ++pcount[brow0[fa] + sfree[tb]];
     }
-  std::vector<int> pbase(nblk + 1, 0);   // first lane of each block's run
+  std::vector<int>& pbase = w.pbase;   // first lane of each block's run
+  pbase.assign(nblk + 1, 0);
   for (int b = 0; b < nblk; ++b) pbase[b + 1] = pbase[b] + (int)align_up(pcount[b], kWave);
   s.Lq = pbase[nblk];
-  s.ql_pt.assign(s.Lq, -1);
-  s.ql_ob.assign(s.Lq, I2{0, 0});
+  s.ql_pt.resize(s.Lq);
+  s.ql_ob.resize(s.Lq);
   {
-    std::vector<int> fill(pbase.begin(), pbase.end() - 1);
+    std::vector<int>& fill = w.fill;
+    fill.assign(pbase.begin(), pbase.end() - 1);
     for (int j = 0; j < P; ++j)
       for (int ta = cnt[j]; ta < cnt[j + 1]; ++ta) {
-        const int ca = s.cam_col[scam[ta]];
-        if (ca < 0) continue;
+        const int fa = sfree[ta];
+        if (fa < 0) continue;
+        int* row = fill.data() + brow0[fa];
         for (int tb = ta + 1; tb < cnt[j + 1]; ++tb) {
-          const int cb = s.cam_col[scam[tb]];
-          if (cb < 0) continue;
-          const int lane = fill[blk(ca / 6, cb / 6)]++;
+          const int fb = sfree[tb];
+          if (fb < 0) continue;
+          const int lane = row[fb]++;
           s.ql_pt[lane] = j;
           s.ql_ob[lane] = I2{oblane[ta], oblane[tb]};
         }
       }
+    for (int b = 0; b < nblk; ++b)   // padding lanes: point -1, observation lanes 0
+      for (int l = fill[b]; l < pbase[b + 1]; ++l) s.ql_pt[l] = -1, s.ql_ob[l] = I2{0, 0};
   }
   auto blk_empty = [&](int b) { return pcount[b] == 0; };
-  std::vector<I2> blk_range(nblk);
+  std::vector<I2>& blk_range = w.blk_range;
+  blk_range.resize(nblk);
   for (int fa = 0; fa < F; ++fa)
     for (int fb = fa + 1; fb < F; ++fb) {
       const int b = blk(fa, fb);

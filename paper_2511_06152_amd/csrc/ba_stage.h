@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/ba.h"
@@ -22,6 +23,30 @@ namespace bagpu {
 struct I2 { int x, y; };
 struct I3 { int x, y, z; };
 struct I4 { int x, y, z, w; };
+
+// Allocator that leaves trivially constructible values uninitialised on
+// resize(): the layout writes every lane of its lane arrays (padding
+// included), so zero-filling them first would only cost memory bandwidth.
+template <typename T>
+struct NoInit : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <typename U>
+  NoInit(const NoInit<U>&) {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+template <typename T>
+using lane_vec = std::vector<T, NoInit<T>>;
 
 // A submitted cluster, laid out for the device.
 struct Staged {
@@ -37,14 +62,14 @@ struct Staged {
   // point, valid points}; observation t of lane l at first + 64 t + l
   std::vector<I4> pchunk;        // [n_chunks]
   std::vector<int> wg_chunk;     // [n_wg + 1] first chunk of each point-pass workgroup
-  std::vector<int> ob_cam;       // [L] camera of each observation lane (0 for padding)
-  std::vector<double> ob_uv;     // [2L] raw pixels (0 for padding)
+  lane_vec<int> ob_cam;          // [L] camera of each observation lane (0 for padding)
+  lane_vec<double> ob_uv;        // [2L] raw pixels (0 for padding)
   int Lc = 0, Lq = 0, nb = 0, n_wg = 0, n_pt_part = 0, n_cam_tasks = 0;
   // camera lanes [Lc]: point (-1 for padding) and observation lane (0 for
   // padding); pair lanes [Lq]: point and the observation lanes of its two
   // observations (camera a, camera b)
-  std::vector<int> cl_pt, cl_ob, ql_pt;
-  std::vector<I2> ql_ob;
+  lane_vec<int> cl_pt, cl_ob, ql_pt;
+  lane_vec<I2> ql_ob;
   std::vector<I4> tasks, targets;
   // sparse (PCG) reduced system: block CSR over the free cameras, diagonal first
   int sparse = 0;
@@ -85,7 +110,16 @@ bool ids_unique(const int64_t* id, int n);
 //    free (point and both observation lanes), grouped by camera pair,
 //    padded and cut into tasks likewise;
 //  * reduction targets: each free camera, each camera pair, the intrinsics.
-// Returns BA_OK, or BA_E_ARG with the reason in err.
+// Returns BA_OK, or BA_E_ARG with the reason in err.  `s` is reset first;
+// the storage of its vectors is reused (a recycled Staged lays out the next
+// cluster without new allocations or page faults).
 int stage(const ba_cluster* c, Staged& s, std::string& err, int cpw, int cpt, int solver);
+
+// Resets every field of s to its default, keeping the vectors' storage.
+void reset_keep(Staged& s);
+
+// Layouts of clusters up to this many observations keep their storage for the
+// next one (per layout thread, and in the runtime's pool of Staged objects).
+constexpr size_t kKeepObs = size_t(1) << 20;
 
 }  // namespace bagpu

@@ -34,8 +34,8 @@ struct Reader {
   T one() { return vec<T>(1)[0]; }
 };
 
-template <typename T>
-void put(FILE* f, const std::vector<T>& v) {
+template <typename T, typename A>
+void put(FILE* f, const std::vector<T, A>& v) {
   const int64_t n = (int64_t)v.size();
   fwrite(&n, sizeof n, 1, f);
   if (n) fwrite(v.data(), sizeof(T), v.size(), f);
@@ -101,6 +101,16 @@ int main(int argc, char** argv) {
       }
   } else {
     rc[0] = stage(&c, st[0], err[0], cpw, cpt, solver);
+    if (rc[0] == 0) {
+      // again into the same Staged on the same thread: its storage and the
+      // thread's scratch are reused, and the layout must not change
+      const Staged first = st[0];
+      std::string e2;
+      if (stage(&c, st[0], e2, cpw, cpt, solver) != 0 || !same(first, st[0])) {
+        fprintf(stderr, "a reused layout differs\n");
+        return 5;
+      }
+    }
   }
   FILE* fo = fopen(argv[2], "wb");
   if (!fo) return 2;

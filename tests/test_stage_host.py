@@ -25,7 +25,8 @@ kernels rely on (CPU only):
     twice, an index out of range, a non-finite value, a point with more than
     64 observations);
   * several threads laying out the same cluster at once get identical
-    layouts, with no data race.
+    layouts, with no data race; a second layout into the same storage on the
+    same thread (reused vectors and scratch) is the same.
 """
 import os
 import shutil
@@ -300,3 +301,11 @@ def test_concurrent_layouts_identical_and_race_free(tools):
     for name in ("tiny", "uneven"):
         sc = SCENES[name]()
         check_layout(sc, run(tools, sc, threads=8, exe=tsan))
+
+
+def test_paper_scale_layout(tools):
+    """A paper-scale cluster (74k observations, 170k pair lanes); stage_check
+    also lays it out a second time into the same storage on the same thread
+    and requires the same layout."""
+    sc = A.scene_cluster12(2)
+    check_layout(sc, run(tools, sc))
