@@ -772,8 +772,8 @@ def main():
     ap.add_argument("--max-iters", type=int, default=20)
     ap.add_argument("--ftol", type=float, default=1e-6)
     ap.add_argument("--plain", type=int, default=8, help="clusters solved by the plain FP64 path")
-    ap.add_argument("--serve", type=int, default=64, help="clusters through the serving loop (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve", type=int, default=96, help="clusters timed at each serving load level (0: skip)")
+    ap.add_argument("--serve-slots", default="4,8,16", help="serving load levels: clusters kept in flight")
     ap.add_argument("--stage-threads", type=int, default=8,
                     help="host threads laying out the clusters submitted to the serving loops (0: the caller's)")
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
@@ -984,30 +984,45 @@ def main():
     octx.close()
 
     # ---- continuous-batching serving loop (closed loop, submit -> result) --------------
+    # Each load level: a context whose slots equal the clusters kept in flight,
+    # a warm-up of two rounds of the slots (pinned buffers, layout storage),
+    # then args.serve clusters timed from ba_submit_cluster to the result.
     serve = {}
     if args.serve > 0:
-        sctx = Context(precision=BA_MIXED, serve=True, max_slots=args.serve_slots,
-                       hbm_budget_bytes=int(args.serve_slots * 16e6) + (256 << 20), stage_threads=args.stage_threads)
-        inflight, lat, done = [], [], 0
-        nxt = 0
-        t_start = time.perf_counter()
-        while done < args.serve:
-            while len(inflight) < args.serve_slots and nxt < args.serve:
-                t = sctx.submit(scenes[nxt % len(scenes)], **kw)
-                sctx.ba_solve(t)
-                inflight.append(t)
-                nxt += 1
-            t = inflight.pop(0)
-            sctx.ba_wait(t)
-            r = sctx.ba_fetch(t)
-            lat.append((r["t_done"] - r["t_submit"]) * 1e3)
-            sctx.ba_release(t)
-            done += 1
-        wall = time.perf_counter() - t_start
-        sctx.close()
-        serve = {"clusters": done, "slots": args.serve_slots, "stage_threads": args.stage_threads,
-                 "clusters_per_s": done / wall, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-                 "note": "closed loop, latency from ba_submit_cluster to the result (layout included)"}
+        levels = []
+        for slots in sorted({int(x) for x in args.serve_slots.split(",") if x}):
+            sctx = Context(precision=BA_MIXED, serve=True, max_slots=slots,
+                           hbm_budget_bytes=int(slots * 16e6) + (256 << 20), stage_threads=args.stage_threads)
+            warm = 2 * slots
+            inflight, lat = [], []
+            nxt = done = 0
+            t_start = time.perf_counter()
+            while done < args.serve + warm:
+                while len(inflight) < slots and nxt < args.serve + warm:
+                    t = sctx.submit(scenes[nxt % len(scenes)], **kw)
+                    sctx.ba_solve(t)
+                    inflight.append(t)
+                    nxt += 1
+                t = inflight.pop(0)
+                sctx.ba_wait(t)
+                r = sctx.ba_fetch(t)
+                if done >= warm:
+                    lat.append((r["t_done"] - r["t_submit"]) * 1e3)
+                sctx.ba_release(t)
+                done += 1
+                if done == warm:
+                    t_start = time.perf_counter()
+            wall = time.perf_counter() - t_start
+            sctx.close()
+            levels.append({"slots": slots, "clusters": len(lat), "clusters_per_s": len(lat) / wall,
+                           "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)})
+        top = levels[-1]
+        serve = {"clusters": top["clusters"], "slots": top["slots"], "stage_threads": args.stage_threads,
+                 "clusters_per_s": top["clusters_per_s"], "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+                 "levels": levels,
+                 "note": "closed loop with `slots` clusters in flight, after a warm-up of two rounds; latency from "
+                         "ba_submit_cluster to the result (validation, background layout, upload and admission "
+                         "included); the top-level figures are the highest load level"}
 
     # ---- equal-RMS check -------------------------------------------------------------------
     rms = {}

@@ -334,6 +334,7 @@ struct Ticket {
 
 struct Slot {
   bool used = false;
+  bool early = false;        // admitted during a tick: uploaded on up_stream, started at the next boundary
   ba_ticket ticket = 0;
   size_t off = 0, bytes = 0;
   Layout lay{};
@@ -388,6 +389,10 @@ struct ba_ctx {
   static constexpr int kMaxParts = 4;
   Launcher api_p[kMaxParts], srv_p[kMaxParts];   // [0] unused
   hipStream_t stream_p[kMaxParts] = {};           // [0] unused
+  // serving loop: clusters admitted while a tick runs upload on their own
+  // stream (up_ev after the last such upload) and join at the next boundary
+  hipStream_t up_stream = nullptr;
+  hipEvent_t up_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev[kMaxParts] = {};
   // kernel timing (ba_profile_enable)
   int prof = 0;                   // bitmask of timed kernels
@@ -702,7 +707,7 @@ void recycle_staged(ba_ctx* c, std::unique_ptr<Staged> s) {
 
 // Moves the ticket's staged data into a free slot and arena block.  Returns
 // BA_E_AGAIN when no slot or memory is free.  Caller holds mu.
-int admit_one(ba_ctx* c, Ticket& t) {
+int admit_one(ba_ctx* c, Ticket& t, hipStream_t st) {
   int slot = -1;
   for (int i = 0; i < (int)c->slots.size(); ++i)
     if (!c->slots[i].used) { slot = i; break; }
@@ -810,7 +815,6 @@ int admit_one(ba_ctx* c, Ticket& t) {
   d.acc_log = (int*)(base + lay.acc_log);
   d.stat_part = (double*)(base + lay.stat_part);
   d.out = (double*)(base + lay.out);
-  hipStream_t st = c->stream;
   // the upload image in one copy: asynchronous from pinned memory (the buffer
   // goes back to the pool once the copy has run), else waited for below
   if (!s.blob) pack_staged(c, s, lay);
@@ -1103,16 +1107,21 @@ void free_slot(ba_ctx* c, int s) {
 // `serving_only`, only tickets handed to the serving loop are admitted.  A
 // ticket that waits for earlier clusters to write back resident state is
 // passed over (later tickets that do not depend on it go ahead).
-int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only) {
+int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only, bool early = false) {
+  hipStream_t st = early ? c->up_stream : c->stream;
+  bool any = false;
   for (auto it = c->queue.begin(); it != c->queue.end();) {
     Ticket& t = *c->tickets[*it];
     if (t.staging || (serving_only && !t.serving) || !deps_done(c, t)) { ++it; continue; }
-    int rc = admit_one(c, t);
+    int rc = admit_one(c, t, st);
     if (rc == BA_E_AGAIN) break;
     if (rc) return rc;
+    c->slots[t.slot].early = early;
+    any = true;
     admitted.push_back(t.slot);
     it = c->queue.erase(it);
   }
+  if (early && any) HIPCHK(c, hipEventRecord(c->up_ev, c->up_stream));
   return BA_OK;
 }
 
@@ -1154,8 +1163,19 @@ Ticket* find_ticket(ba_ctx* c, ba_ticket id);
 void serve_loop(ba_ctx* c) {
   (void)hipSetDevice(c->device);
   std::vector<int> active;
+  bool early_pending = false;   // uploads on up_stream since the last boundary
   std::unique_lock<std::mutex> lk(c->mu);
   while (!c->stop) {
+    // everything the compute stream does from here on comes after the
+    // uploads of clusters admitted during the last tick (a block freed
+    // below may have been theirs)
+    if (early_pending) {
+      if (hipStreamWaitEvent(c->stream, c->up_ev, 0) != hipSuccess) {
+        c->dead = true;
+        break;
+      }
+      early_pending = false;
+    }
     // cancel: clusters released while the loop owned them.  The previous
     // tick has completed on the device, so their slots can be freed; they
     // write nothing back, and a ticket that no longer exists holds back no
@@ -1192,8 +1212,13 @@ void serve_loop(ba_ctx* c) {
                                   [&](int s) { return std::find(fin.begin(), fin.end(), s) != fin.end(); }),
                    active.end());
     }
-    // admit
+    // admit: the clusters uploaded during the last tick, then the queue
     std::vector<int> adm;
+    for (int s = 0; s < (int)c->slots.size(); ++s)
+      if (c->slots[s].used && c->slots[s].early) {
+        c->slots[s].early = false;
+        adm.push_back(s);
+      }
     if (admit_queue(c, adm, true)) break;
     if (!adm.empty()) {
       if (start_slots(c, c->srv, adm)) break;
@@ -1224,9 +1249,23 @@ void serve_loop(ba_ctx* c) {
       c->cv.wait(lk, [&] { return c->stop || serving_queued(c) || !c->cancel.empty(); });
       continue;
     }
-    lk.unlock();
-    const hipError_t e = hipEventSynchronize(c->srv.ev);
-    lk.lock();
+    // Wait for the tick.  A cluster whose layout finishes meanwhile is
+    // admitted now, its upload running on up_stream beside the tick; it
+    // starts at the next boundary.
+    hipError_t e;
+    bool failed = false;
+    for (;;) {
+      e = hipEventQuery(c->srv.ev);
+      if (e != hipErrorNotReady) break;
+      if (!c->stop && serving_queued(c)) {
+        const size_t before = c->queue.size();
+        std::vector<int> early;
+        if (admit_queue(c, early, true, true)) { failed = true; break; }
+        if (c->queue.size() != before) early_pending = true;
+      }
+      c->cv.wait_for(lk, std::chrono::microseconds(50));
+    }
+    if (failed) break;
     if (e != hipSuccess) { c->dead = true; c->last_error = hipGetErrorString(e); break; }
     if (c->prof_used && harvest_prof(c)) break;
   }
@@ -1245,7 +1284,7 @@ int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
   if (t.state == TK_DONE) return fail(c, BA_E_STATE, "cluster already retired");
   if (!deps_done(c, t))
     return fail(c, BA_E_STATE, "cluster reads resident state that an unfinished earlier cluster has still to write");
-  int rc = admit_one(c, t);
+  int rc = admit_one(c, t, c->stream);
   if (rc == BA_E_AGAIN) return fail(c, BA_E_AGAIN, "no free slot or arena memory");
   if (rc) return rc;
   c->queue.erase(std::remove(c->queue.begin(), c->queue.end(), t.id), c->queue.end());
@@ -1331,6 +1370,9 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   c->slots.resize(c->opt.max_slots);
   if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return bail(BA_E_DEVICE);
   if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) return bail(BA_E_DEVICE);
+  if (c->opt.serve && (hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess))
+    return bail(BA_E_DEVICE);
   for (int p = 1; p < c->opt.batch_streams; ++p) {
     if (init_launcher(c.get(), c->api_p[p]) || init_launcher(c.get(), c->srv_p[p]) ||
         hipStreamCreateWithFlags(&c->stream_p[p], hipStreamNonBlocking) != hipSuccess ||
@@ -1360,6 +1402,7 @@ int ba_destroy(ba_ctx* c) {
   if (c->th.joinable()) c->th.join();
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->up_stream) (void)hipStreamSynchronize(c->up_stream);
   for (int p = 1; p < ba_ctx::kMaxParts; ++p)
     if (c->stream_p[p]) (void)hipStreamSynchronize(c->stream_p[p]);
   free_launcher(c, c->api);
@@ -1370,6 +1413,8 @@ int ba_destroy(ba_ctx* c) {
     if (c->join_ev[p]) (void)hipEventDestroy(c->join_ev[p]);
   }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->up_ev) (void)hipEventDestroy(c->up_ev);
+  if (c->up_stream) (void)hipStreamDestroy(c->up_stream);
   free_launcher(c, c->srv);
   // the tickets' upload images go back to the pool before it is freed
   c->tickets.clear();
