@@ -117,3 +117,39 @@ def test_stage_threads_option_limits():
         with pytest.raises(BAError) as e:
             Context(stage_threads=n)
         assert e.value.code == -1
+
+
+def test_clusters_arriving_during_a_tick_equal_alone():
+    """A long cluster keeps the serving loop in ticks of ten iterations while
+    small clusters arrive one by one: their layouts finish while a tick runs,
+    so the loop admits them at once (upload beside the tick) and starts them
+    at the next boundary.  Each result equals the one the cluster gets alone,
+    bit for bit, and so does the long cluster's."""
+    import time
+    from paper_2511_06152_amd import Context
+    long_sc = A.make_scene(A.spec_micro(n_strips=2, imgs_per_strip=4, n_points=3000), 411)
+    small = scenes(5, 420)
+    kw_long = dict(max_iters=150, stop_on_ftol=False)
+    kw = dict(max_iters=12, stop_on_ftol=False)
+    with Context(precision=MIXED) as ctx:
+        t = ctx.submit(long_sc, **kw_long)
+        ctx.ba_solve_batch([t])
+        ref_long = ctx.ba_fetch(t)
+        ts = [ctx.submit(sc, **kw) for sc in small]
+        ctx.ba_solve_batch(ts)
+        ref = [ctx.ba_fetch(t) for t in ts]
+    print("case arrivals during a tick", flush=True)
+    with Context(precision=MIXED, stage_threads=2, serve=True, max_slots=4, iters_per_tick=10) as ctx:
+        tl = ctx.submit(long_sc, **kw_long)
+        ctx.ba_solve(tl)
+        ts = []
+        for sc in small:
+            time.sleep(0.002)
+            t = ctx.submit(sc, **kw)
+            ctx.ba_solve(t)
+            ts.append(t)
+        for r, t in zip(ref, ts):
+            ctx.ba_wait(t, 60.0)
+            same(ctx.ba_fetch(t), r)
+        ctx.ba_wait(tl, 60.0)
+        same(ctx.ba_fetch(tl), ref_long)
