@@ -68,9 +68,10 @@ FLOP_PAIR = 246
 TRAFFIC = {
     "fetch_scale": 262144.0 / 131084.9, "write_scale": 262144.0 / 262144.0,
     "clusters": 64,
+    "chunks": (32, 10),   # (chunks_per_wg, chunks_per_task) of the measured launches
     "kib": {  # (streams, kernel): (FETCH_SIZE, WRITE_SIZE)
-        (2, "blocks"): (87291.9, 2415.0),
-        (1, "blocks"): (164859.9, 4830.1),
+        (2, "blocks"): (96011.7, 1961.7),
+        (1, "blocks"): (177742.1, 3923.3),
     },
     "sources_sha256": {
         "ba_kernels.hip": "be030a02ca766ad622db062abcc26acff0d8bee6f3d954287e0b87add4f0dea6",
@@ -79,12 +80,15 @@ TRAFFIC = {
 }
 
 
-def traffic_bytes(kernel: str, batch: int, streams: int):
+def traffic_bytes(kernel: str, batch: int, streams: int, chunks=None):
     """Measured HBM bytes per launch of `kernel`, or None when the counters
-    were taken on other kernel sources, another batch size or not at all."""
+    were taken on other kernel sources, another batch size, other chunk
+    sizes (chunks = (chunks_per_wg, chunks_per_task)) or not at all."""
     import hashlib
     key = (streams, kernel)
     if key not in TRAFFIC["kib"] or batch != TRAFFIC["clusters"]:
+        return None
+    if chunks is not None and tuple(chunks) != tuple(TRAFFIC["chunks"]):
         return None
     csrc = os.path.join(ROOT, "paper_2511_06152_amd", "csrc")
     for name, sha in TRAFFIC["sources_sha256"].items():
@@ -168,7 +172,8 @@ def measure_isolated(args, Context, ctx_kw, scenes, kw, flops):
     ach = fl / max(n, 1) / (avg / 1e3) / 1e12 if n else float("nan")
     return {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "peak_nonpacked": PEAK_VALU_TFLOPS,
-            "frac_of_nonpacked": ach / PEAK_VALU_TFLOPS, "traffic": traffic_bytes(dom, B, 1),
+            "frac_of_nonpacked": ach / PEAK_VALU_TFLOPS,
+            "traffic": traffic_bytes(dom, B, 1, (args.chunks_per_wg, args.chunks_per_task)),
             "traffic_unit": "bytes per launch", "avg_launch_us": avg * 1e3, "algorithmic_flop_per_launch": fl / max(n, 1),
             "batch_streams": 1,
             "note": "one more step of the same batch on one stream: each launch covers the batch, alone on the GPU"}
@@ -203,7 +208,7 @@ def run_uneven(args, Context, precision, kw):
     probe.close()
     budget = int(sum(foot[i % len(scs)] for i in range(N)) * 1.02) + (64 << 20)
     ctx = Context(precision=precision, max_slots=N, hbm_budget_bytes=budget, chunks_per_task=args.chunks_per_task,
-                  batch_streams=args.batch_streams, iters_per_tick=args.iters_per_tick)
+                  chunks_per_wg=args.chunks_per_wg, batch_streams=args.batch_streams, iters_per_tick=args.iters_per_tick)
     times, iters, its_max = [], 0, 0
     # the two smallest distinct clusters: their results are compared with the oracle's
     sample = sorted(range(min(N, len(scs))), key=lambda i: scs[i]["n_obs"])[:2]
@@ -790,8 +795,8 @@ def main():
     ap.add_argument("--stage-threads", type=int, default=8,
                     help="host threads laying out the clusters submitted to the serving loops (0: the caller's)")
     ap.add_argument("--cpu-clusters", type=int, default=3, help="clusters solved by the oracle (0: skip)")
-    ap.add_argument("--chunks-per-task", type=int, default=8, help="64-lane chunks per block task (batched context)")
-    ap.add_argument("--chunks-per-wg", type=int, default=16,
+    ap.add_argument("--chunks-per-task", type=int, default=10, help="64-lane chunks per block task (batched context)")
+    ap.add_argument("--chunks-per-wg", type=int, default=32,
                     help="observation lanes of a point-pass workgroup, in units of 64 (batched context)")
     ap.add_argument("--batch-streams", type=int, default=2,
                     help="streams a batch is split across (1: one stream, no overlap)")
@@ -953,7 +958,8 @@ def main():
     in_step = {"bound": "alu", "kernel": f"k_{dom}<float>", "achieved": achieved_tflops,
                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                "peak_nonpacked": PEAK_VALU_TFLOPS, "frac_of_nonpacked": achieved_tflops / PEAK_VALU_TFLOPS,
-               "traffic": traffic_bytes(dom, B, args.batch_streams), "traffic_unit": "bytes per launch",
+               "traffic": traffic_bytes(dom, B, args.batch_streams, (args.chunks_per_wg, args.chunks_per_task)),
+               "traffic_unit": "bytes per launch",
                "avg_launch_us": asm_avg_ms * 1e3, "algorithmic_flop_per_launch": fl_total[dom] / max(asm_n, 1),
                "batch_streams": args.batch_streams,
                "note": "timed steps: launches of one part of the batch, beside the other parts' kernels"}

@@ -43,6 +43,8 @@ def test_traffic_only_for_the_measured_configuration():
     assert bench.traffic_bytes(kernel, bench.TRAFFIC["clusters"] + 1, streams) is None
     assert bench.traffic_bytes(kernel, bench.TRAFFIC["clusters"], 7) is None
     assert bench.traffic_bytes("no_such_kernel", bench.TRAFFIC["clusters"], streams) is None
+    cpw, cpt = bench.TRAFFIC["chunks"]
+    assert bench.traffic_bytes(kernel, bench.TRAFFIC["clusters"], streams, (cpw + 1, cpt)) is None
 
 
 def test_solve_mfma_flops_against_a_count_of_block_products():
