@@ -104,8 +104,7 @@ typedef struct {
   int32_t serve;             /* 1: start the continuous-batching runtime thread */
   int32_t iters_per_tick;    /* LM iterations between control read-backs (batched solve,
                                 serving tick); 0 -> 10.  A serving tick is cut short
-                                when a cluster reaches its iteration cap, and while a
-                                free slot waits for a cluster's layout */
+                                when a cluster reaches its iteration cap */
   int32_t chunks_per_wg;     /* 64-observation chunks per workgroup of the point-major
                                 kernels; 0 -> 16 */
   int32_t chunks_per_task;   /* 64-lane chunks per wavefront task of the block kernel;

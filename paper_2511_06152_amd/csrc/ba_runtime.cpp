@@ -1137,22 +1137,14 @@ bool serving_queued(ba_ctx* c) {
 
 // LM iterations of the next serving tick: iters_per_tick, cut so that the
 // tick ends when the first running cluster reaches its iteration cap (it is
-// retired at once), and cut to a quarter while a free slot waits for a
-// cluster whose layout is still running (it is admitted sooner).  `adm`:
-// slots admitted for this tick (their read-back control is not theirs yet).
+// retired at once).  `adm`: slots admitted for this tick (their read-back
+// control is not theirs yet).
 int tick_iters(ba_ctx* c, const std::vector<int>& active, const std::vector<int>& adm) {
   int n = c->opt.iters_per_tick;
   for (int s : active) {
     const bool fresh = std::find(adm.begin(), adm.end(), s) != adm.end();
     const int rem = c->slots[s].desc.max_iters - (fresh ? 0 : c->srv.h_ctl[s].iter);
     n = std::min(n, std::max(rem, 1));
-  }
-  if ((int)active.size() < c->opt.max_slots && n > 4) {
-    for (const auto& kv : c->tickets)
-      if (kv.second->serving && kv.second->staging) {
-        n = std::max(4, n / 4);
-        break;
-      }
   }
   return n;
 }
