@@ -790,7 +790,7 @@ def main():
     ap.add_argument("--max-iters", type=int, default=20)
     ap.add_argument("--ftol", type=float, default=1e-6)
     ap.add_argument("--plain", type=int, default=8, help="clusters solved by the plain FP64 path")
-    ap.add_argument("--serve", type=int, default=96, help="clusters timed at each serving load level (0: skip)")
+    ap.add_argument("--serve", type=int, default=192, help="clusters timed at each serving load level (0: skip)")
     ap.add_argument("--serve-slots", default="4,8,16", help="serving load levels: clusters kept in flight")
     ap.add_argument("--stage-threads", type=int, default=8,
                     help="host threads laying out the clusters submitted to the serving loops (0: the caller's)")

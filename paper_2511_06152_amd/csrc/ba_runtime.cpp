@@ -316,6 +316,7 @@ struct Ticket {
   int err_code = 0;               // TK_INVALID: why the background layout refused it
   std::string err_msg;
   std::unique_ptr<Staged> staged; // until admission
+  int staged_home = -1;           // the layout thread whose pool the Staged returns to
   int C = 0, P = 0, max_iters = 0;
   size_t bytes = 0;
   int slot = -1;
@@ -411,6 +412,10 @@ struct ba_ctx {
   double res_lambda = NAN;        // damping the last written-back cluster ended with
   // background layout (ba_options.stage_threads > 0)
   std::vector<std::unique_ptr<Staged>> staged_pool;   // admitted layouts kept for reuse (mu)
+  // the same, per layout thread: a thread lays its next cluster out in
+  // storage it wrote last (measured: 1.66 -> 1.30 ms per paper-scale layout
+  // in the serving loop, against one shared pool)
+  std::vector<std::vector<std::unique_ptr<Staged>>> worker_pool;
   std::vector<std::thread> stagers;
   std::deque<std::pair<ba_ticket, std::unique_ptr<ClusterCopy>>> stage_jobs;
   std::condition_variable stage_cv;       // wakes the layout threads
@@ -688,21 +693,26 @@ int res_register(ba_ctx* c, Ticket& t, const Staged& s) {
 }
 
 // A Staged for the next layout: a recycled one (its vectors keep their
-// storage) when the pool has one.  Caller holds mu.
-std::unique_ptr<Staged> take_staged(ba_ctx* c) {
-  if (c->staged_pool.empty()) return std::make_unique<Staged>();
-  auto s = std::move(c->staged_pool.back());
-  c->staged_pool.pop_back();
+// storage) when the pool has one; `worker` >= 0: layout thread `worker`,
+// which takes from its own pool.  Caller holds mu.
+std::unique_ptr<Staged> take_staged(ba_ctx* c, int worker = -1) {
+  auto& pool = worker >= 0 ? c->worker_pool[worker] : c->staged_pool;
+  if (pool.empty()) return std::make_unique<Staged>();
+  auto s = std::move(pool.back());
+  pool.pop_back();
   return s;
 }
 
-// Returns an admitted cluster's Staged to the pool (its upload image goes
-// back to the pinned pool now), unless the pool is full or the cluster was
-// very large.  Caller holds mu.
-void recycle_staged(ba_ctx* c, std::unique_ptr<Staged> s) {
-  if (!s || (size_t)s->O > kKeepObs || c->staged_pool.size() >= (size_t)c->opt.stage_threads + 2) return;
+// Returns an admitted cluster's Staged to the pool it came from (its upload
+// image goes back to the pinned pool now), unless that pool is full or the
+// cluster was very large.  Caller holds mu.
+void recycle_staged(ba_ctx* c, std::unique_ptr<Staged> s, int home) {
+  if (!s || (size_t)s->O > kKeepObs) return;
+  auto& pool = home >= 0 ? c->worker_pool[home] : c->staged_pool;
+  const size_t cap = home >= 0 ? 2 : (size_t)c->opt.stage_threads + 2;
+  if (pool.size() >= cap) return;
   s->blob.reset();
-  c->staged_pool.push_back(std::move(s));
+  pool.push_back(std::move(s));
 }
 
 // Moves the ticket's staged data into a free slot and arena block.  Returns
@@ -855,7 +865,7 @@ int admit_one(ba_ctx* c, Ticket& t, hipStream_t st) {
   t.slot = slot;
   t.state = TK_RESIDENT;
   t.t_admit = now_s();
-  recycle_staged(c, std::move(t.staged));
+  recycle_staged(c, std::move(t.staged), t.staged_home);
   return BA_OK;
 }
 
@@ -1290,7 +1300,7 @@ namespace {
 int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket, double t_submit);
 int enqueue_copy(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket, double t_submit);
 int wait_staged(ba_ctx* c, std::unique_lock<std::mutex>& lk, ba_ticket id);
-void stage_worker(ba_ctx* c);
+void stage_worker(ba_ctx* c, int worker);
 }  // namespace
 
 extern "C" {
@@ -1374,7 +1384,8 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   for (int i = 0; i < c->opt.max_slots; ++i) c->srv.h_ctl[i] = SlotCtl{};
   if (hipDeviceSynchronize() != hipSuccess) return bail(BA_E_DEVICE);
   ba_ctx* raw = c.release();
-  for (int i = 0; i < raw->opt.stage_threads; ++i) raw->stagers.emplace_back(stage_worker, raw);
+  raw->worker_pool.resize(raw->opt.stage_threads);
+  for (int i = 0; i < raw->opt.stage_threads; ++i) raw->stagers.emplace_back(stage_worker, raw, i);
   if (opt->serve) raw->th = std::thread(serve_loop, raw);
   *out = raw;
   return BA_OK;
@@ -1532,7 +1543,7 @@ void res_abandon(ba_ctx* c, Ticket& t) {
 
 // A layout thread: lays out the queued copies in submission order of pickup;
 // the result (or the reason it was refused) goes to the ticket.
-void stage_worker(ba_ctx* c) {
+void stage_worker(ba_ctx* c, int worker) {
   (void)hipSetDevice(c->device);   // for the pinned buffers of the upload images
   std::unique_lock<std::mutex> lk(c->mu);
   for (;;) {
@@ -1540,7 +1551,7 @@ void stage_worker(ba_ctx* c) {
     if (c->stage_stop) return;
     auto job = std::move(c->stage_jobs.front());
     c->stage_jobs.pop_front();
-    auto st = take_staged(c);
+    auto st = take_staged(c, worker);
     lk.unlock();
     std::string err;
     const int rc = stage(&job.second->c, *st, err, c->opt.chunks_per_wg, c->opt.chunks_per_task, c->opt.solver);
@@ -1576,6 +1587,7 @@ void stage_worker(ba_ctx* c) {
     } else {
       t->bytes = lay.total;
       t->staged = std::move(st);
+      t->staged_home = worker;
       c->cv.notify_all();
     }
     c->staged_cv.notify_all();
