@@ -505,7 +505,11 @@ std::shared_ptr<char> pin_get(ba_ctx* c, size_t bytes) {
       have = c->pin_free[best].second;
       c->pin_free.erase(c->pin_free.begin() + best);
     } else {
-      have = align_up(std::max<size_t>(bytes, 1), 2u << 20);
+      // sizes in powers of two from 2 MiB, so that a freed buffer serves the
+      // next clusters of similar size (a new pinned allocation takes
+      // milliseconds)
+      have = size_t(2) << 20;
+      while (have < bytes) have <<= 1;
       if (c->pin_bytes + have > kPinnedPoolBytes) return nullptr;
       c->pin_bytes += have;
     }
