@@ -351,12 +351,17 @@ struct Slot {
 struct Launcher {
   int* d_act = nullptr;
   int* d_wgoff = nullptr;   // [4][max_slots + 1]: point-chunk, camera-task, pair-task, target workgroup prefixes
-  int* h_act = nullptr;     // pinned: [max_slots] act, then [4][max_slots + 1] prefixes
+  // pinned: kRing batch images, each [max_slots] act, then [4][max_slots + 1]
+  // prefixes; consecutive batches use consecutive images, so that building
+  // one seldom waits for the upload of the one before
+  static constexpr int kRing = 4;
+  int* h_act = nullptr;
   SlotCtl* h_ctl = nullptr; // pinned readback of all slots' control blocks
   hipEvent_t ev = nullptr;
-  hipEvent_t copy_ev = nullptr;  // after the last upload from h_act
-  hipEvent_t exp_ev = nullptr;   // after the copies of the last export
-  bool copy_pending = false;
+  hipEvent_t copy_ev[kRing] = {};   // after the last upload from each image
+  hipEvent_t exp_ev = nullptr;      // after the copies of the last export
+  bool copy_pending[kRing] = {};
+  int ring = 0;                     // the image the next batch is built in
   std::vector<SparseLaunch> sp;  // the batch's clusters solved by conjugate gradients
 };
 
@@ -542,10 +547,10 @@ int init_launcher(ba_ctx* c, Launcher& l) {
   const int S = c->opt.max_slots;
   HIPCHK(c, dmalloc(c, (void**)&l.d_act, sizeof(int) * S));
   HIPCHK(c, dmalloc(c, (void**)&l.d_wgoff, sizeof(int) * 4 * (S + 1)));
-  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (S + 4 * (S + 1)), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc(&l.h_act, sizeof(int) * (S + 4 * (S + 1)) * Launcher::kRing, hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc(&l.h_ctl, sizeof(SlotCtl) * S, hipHostMallocDefault));
   HIPCHK(c, hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
-  HIPCHK(c, hipEventCreateWithFlags(&l.copy_ev, hipEventDisableTiming));
+  for (hipEvent_t& e : l.copy_ev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPCHK(c, hipEventCreateWithFlags(&l.exp_ev, hipEventDisableTiming));
   return BA_OK;
 }
@@ -556,7 +561,8 @@ void free_launcher(ba_ctx* c, Launcher& l) {
   if (l.h_act) (void)hipHostFree(l.h_act);
   if (l.h_ctl) (void)hipHostFree(l.h_ctl);
   if (l.ev) (void)hipEventDestroy(l.ev);
-  if (l.copy_ev) (void)hipEventDestroy(l.copy_ev);
+  for (hipEvent_t e : l.copy_ev)
+    if (e) (void)hipEventDestroy(e);
   if (l.exp_ev) (void)hipEventDestroy(l.exp_ev);
   l = Launcher();
 }
@@ -564,13 +570,15 @@ void free_launcher(ba_ctx* c, Launcher& l) {
 // Builds and uploads the batch arrays of the given slots on launcher l.
 int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) {
   const int S = c->opt.max_slots;
-  int* act = l.h_act;
-  int* off = l.h_act + S;
-  // The pinned arrays are rewritten below: the previous upload from them must
-  // have been executed by the stream first.
-  if (l.copy_pending) {
-    HIPCHK(c, hipEventSynchronize(l.copy_ev));
-    l.copy_pending = false;
+  const int r = l.ring;
+  l.ring = (l.ring + 1) % Launcher::kRing;
+  int* act = l.h_act + (size_t)r * (S + 4 * (S + 1));
+  int* off = act + S;
+  // The image is rewritten below: the upload last made from it must have
+  // been executed by the stream first.
+  if (l.copy_pending[r]) {
+    HIPCHK(c, hipEventSynchronize(l.copy_ev[r]));
+    l.copy_pending[r] = false;
   }
   int* tkc = off + (S + 1);
   int* tkp = tkc + (S + 1);
@@ -617,8 +625,8 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
   if (b.n_act == 0) return BA_OK;
   HIPCHK(c, hipMemcpyAsync(l.d_act, act, sizeof(int) * b.n_act, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * 4 * (S + 1), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipEventRecord(l.copy_ev, c->stream));
-  l.copy_pending = true;
+  HIPCHK(c, hipEventRecord(l.copy_ev[r], c->stream));
+  l.copy_pending[r] = true;
   return BA_OK;
 }
 
@@ -1257,7 +1265,10 @@ void serve_loop(ba_ctx* c) {
     }
     // Wait for the tick.  A cluster whose layout finishes meanwhile is
     // admitted now, its upload running on up_stream beside the tick; it
-    // starts at the next boundary.
+    // starts at the next boundary.  The event is polled with mu released
+    // (submitters and layout threads take it meanwhile), so that the end of
+    // the tick is seen within microseconds rather than after a timed sleep:
+    // the device idles from there to the next tick's first launch.
     hipError_t e;
     bool failed = false;
     for (;;) {
@@ -1269,7 +1280,11 @@ void serve_loop(ba_ctx* c) {
         if (admit_queue(c, early, true, true)) { failed = true; break; }
         if (c->queue.size() != before) early_pending = true;
       }
-      c->cv.wait_for(lk, std::chrono::microseconds(50));
+      lk.unlock();
+      const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
+      while ((e = hipEventQuery(c->srv.ev)) == hipErrorNotReady && std::chrono::steady_clock::now() < until)
+        std::this_thread::yield();
+      lk.lock();
     }
     if (failed) break;
     if (e != hipSuccess) { c->dead = true; c->last_error = hipGetErrorString(e); break; }
@@ -1302,7 +1317,8 @@ int ensure_resident(ba_ctx* c, Ticket& t, std::vector<int>& admitted) {
 
 namespace {
 int enqueue_staged(ba_ctx* c, std::unique_ptr<Staged> st, ba_ticket* ticket, double t_submit);
-int enqueue_copy(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket, double t_submit);
+const char* copy_checks(const ba_cluster* cl);
+int enqueue_copy(ba_ctx* c, std::unique_ptr<ClusterCopy> copy, ba_ticket* ticket, double t_submit);
 int wait_staged(ba_ctx* c, std::unique_lock<std::mutex>& lk, ba_ticket id);
 void stage_worker(ba_ctx* c, int worker);
 }  // namespace
@@ -1460,9 +1476,13 @@ size_t ba_footprint(ba_ctx* c, const ba_cluster* cl) {
 int ba_submit_cluster(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket) {
   const double t_submit = now_s();   // latency runs from here: validation and layout included
   if (!c || !ticket) return BA_E_ARG;
-  if (c->opt.stage_threads > 0) {
+  if (c->opt.stage_threads > 0) {   // background layout: the copy is made before mu is taken
+    const char* why = copy_checks(cl);
+    std::unique_ptr<ClusterCopy> copy;
+    if (!why) copy = std::make_unique<ClusterCopy>(*cl);
     std::lock_guard<std::mutex> g(c->mu);
-    return enqueue_copy(c, cl, ticket, t_submit);
+    if (why) return fail(c, BA_E_ARG, why);
+    return enqueue_copy(c, std::move(copy), ticket, t_submit);
   }
   std::unique_ptr<Staged> st;
   {
@@ -1485,14 +1505,21 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
   if (!c || n < 0 || (n > 0 && (!cl || !tickets))) return BA_E_ARG;
   for (int i = 0; i < n; ++i) tickets[i] = 0;
   if (c->opt.stage_threads > 0) {   // background layout: queued in order, laid out by the pool
+    // the copies are made before mu is taken, up to the first cluster that
+    // fails its checks (the ones before it are queued, as one by one)
+    std::vector<std::unique_ptr<ClusterCopy>> copy(n);
+    const char* why = nullptr;
+    int n_ok = 0;
+    for (; n_ok < n && !(why = copy_checks(&cl[n_ok])); ++n_ok) copy[n_ok] = std::make_unique<ClusterCopy>(cl[n_ok]);
     std::lock_guard<std::mutex> g(c->mu);
-    for (int i = 0; i < n; ++i) {
-      const int r = enqueue_copy(c, &cl[i], &tickets[i], t_submit);
+    for (int i = 0; i < n_ok; ++i) {
+      const int r = enqueue_copy(c, std::move(copy[i]), &tickets[i], t_submit);
       if (r) {
         c->last_error = "cluster " + std::to_string(i) + ": " + c->last_error;
         return r;
       }
     }
+    if (why) return fail(c, BA_E_ARG, "cluster " + std::to_string(n_ok) + ": " + why);
     return BA_OK;
   }
   std::vector<std::unique_ptr<Staged>> st(n);
@@ -1611,26 +1638,35 @@ int wait_staged(ba_ctx* c, std::unique_lock<std::mutex>& lk, ba_ticket id) {
   return BA_OK;
 }
 
-// Queues a copy of the cluster for background layout: the checks that need no
-// layout now (sizes, arrays present, resident IDs unique), the rest on a
-// layout thread.  Caller holds mu.
-int enqueue_copy(ba_ctx* c, const ba_cluster* cl, ba_ticket* ticket, double t_submit) {
-  if (!cl) return fail(c, BA_E_ARG, "cluster is NULL");
+// The checks of a submitted cluster that need no layout (sizes, arrays
+// present, resident IDs unique); nullptr when it passes them.  The rest run
+// on a layout thread.
+const char* copy_checks(const ba_cluster* cl) {
+  if (!cl) return "cluster is NULL";
   const int C = cl->n_cams, P = cl->n_points, O = cl->n_obs;
-  if (C < 1 || C > kMaxCams || P < 0 || O < 0) return fail(c, BA_E_ARG, "sizes out of range (1 <= n_cams <= 512)");
+  if (C < 1 || C > kMaxCams || P < 0 || O < 0) return "sizes out of range (1 <= n_cams <= 512)";
   if (!cl->R || !cl->T || !cl->k || !cl->prior_R || !cl->prior_T || !cl->prior_sigma || !cl->fixed ||
       (P > 0 && !cl->X) || (O > 0 && (!cl->obs_cam || !cl->obs_pt || !cl->obs_uv)))
-    return fail(c, BA_E_ARG, "missing input array");
-  if (cl->max_iters < 1 || cl->max_iters > 4096) return fail(c, BA_E_ARG, "max_iters must be in 1..4096");
-  if (cl->use_resident != 0 && cl->use_resident != 1) return fail(c, BA_E_ARG, "use_resident must be 0 or 1");
+    return "missing input array";
+  if (cl->max_iters < 1 || cl->max_iters > 4096) return "max_iters must be in 1..4096";
+  if (cl->use_resident != 0 && cl->use_resident != 1) return "use_resident must be 0 or 1";
   if (cl->use_resident) {
-    if (!cl->cam_ids || (P > 0 && !cl->point_ids)) return fail(c, BA_E_ARG, "use_resident needs cam_ids and point_ids");
-    if (!ids_unique(cl->cam_ids, C)) return fail(c, BA_E_ARG, "duplicate camera ID in the cluster");
-    if (!ids_unique(cl->point_ids, P)) return fail(c, BA_E_ARG, "duplicate point ID in the cluster");
+    if (!cl->cam_ids || (P > 0 && !cl->point_ids)) return "use_resident needs cam_ids and point_ids";
+    if (!ids_unique(cl->cam_ids, C)) return "duplicate camera ID in the cluster";
+    if (!ids_unique(cl->point_ids, P)) return "duplicate point ID in the cluster";
   }
+  return nullptr;
+}
+
+// Queues a copy of a cluster that passed copy_checks for background layout.
+// The caller makes the copy before it takes mu (a paper-scale cluster is a
+// few MB: the serving thread and the layout threads do not wait for the
+// copying).  Caller holds mu.
+int enqueue_copy(ba_ctx* c, std::unique_ptr<ClusterCopy> copy, ba_ticket* ticket, double t_submit) {
+  const ba_cluster* cl = &copy->c;
+  const int C = cl->n_cams, P = cl->n_points;
   if (c->dead) return fail(c, BA_E_DEVICE, "context is unusable after a device error");
   if ((int)c->queue.size() >= c->opt.max_queue) return fail(c, BA_E_AGAIN, "admission queue full");
-  auto copy = std::make_unique<ClusterCopy>(*cl);
   auto t = std::make_unique<Ticket>();
   t->id = c->next_id;
   if (cl->use_resident) {
