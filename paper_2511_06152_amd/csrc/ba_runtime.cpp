@@ -399,6 +399,9 @@ struct ba_ctx {
   // stream (up_ev after the last such upload) and join at the next boundary
   hipStream_t up_stream = nullptr;
   hipEvent_t up_ev = nullptr;
+  // batch lists of the serving loop's work on up_stream: the set-up of
+  // clusters admitted during a tick and the export of finished ones
+  Launcher side;
   hipEvent_t fork_ev = nullptr, join_ev[kMaxParts] = {};
   // kernel timing (ba_profile_enable)
   int prof = 0;                   // bitmask of timed kernels
@@ -475,7 +478,7 @@ void dfree(ba_ctx* c, void* p) {
 }
 
 // Pinned host memory for upload images: at most kPinnedPoolBytes in all, the
-// buffers reused across clusters (capacities rounded up to 2 MiB).
+// buffers reused across clusters (capacities powers of two from 2 MiB).
 constexpr size_t kPinnedPoolBytes = 256u << 20;
 
 // Returns the buffers of finished uploads to the free list.
@@ -568,7 +571,8 @@ void free_launcher(ba_ctx* c, Launcher& l) {
 }
 
 // Builds and uploads the batch arrays of the given slots on launcher l.
-int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) {
+int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b, hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
   const int S = c->opt.max_slots;
   const int r = l.ring;
   l.ring = (l.ring + 1) % Launcher::kRing;
@@ -623,9 +627,9 @@ int make_batch(ba_ctx* c, Launcher& l, const std::vector<int>& slots, Batch& b) 
   b.total_tkp_wg = tp;
   b.total_tg = tg;
   if (b.n_act == 0) return BA_OK;
-  HIPCHK(c, hipMemcpyAsync(l.d_act, act, sizeof(int) * b.n_act, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * 4 * (S + 1), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipEventRecord(l.copy_ev[r], c->stream));
+  HIPCHK(c, hipMemcpyAsync(l.d_act, act, sizeof(int) * b.n_act, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(l.d_wgoff, off, sizeof(int) * 4 * (S + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipEventRecord(l.copy_ev[r], st));
   l.copy_pending[r] = true;
   return BA_OK;
 }
@@ -881,11 +885,13 @@ int admit_one(ba_ctx* c, Ticket& t, hipStream_t st) {
   return BA_OK;
 }
 
-// Runs prep and the initial FP64 cost for newly admitted slots.
-int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
+// Runs prep and the initial FP64 cost for newly admitted slots (on the
+// context's stream unless st is given).
+int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots, hipStream_t st = nullptr) {
   if (slots.empty()) return BA_OK;
+  if (!st) st = c->stream;
   Batch b;
-  int rc = make_batch(c, l, slots, b);
+  int rc = make_batch(c, l, slots, b, st);
   if (rc) return rc;
   int maxPL = 0, maxRin = 0;
   for (int s : slots) {
@@ -893,8 +899,8 @@ int start_slots(ba_ctx* c, Launcher& l, const std::vector<int>& slots) {
     maxPL = std::max({maxPL, d.P, d.L});
     maxRin = std::max({maxRin, d.n_rin_cam, d.n_rin_pt});
   }
-  HIPCHK(c, launch_prep(b, maxPL, maxRin, c->stream));
-  HIPCHK(c, launch_initial_cost(b, c->stream));
+  HIPCHK(c, launch_prep(b, maxPL, maxRin, st));
+  HIPCHK(c, launch_initial_cost(b, st));
   return BA_OK;
 }
 
@@ -1020,20 +1026,24 @@ struct ExportJob {
   std::vector<Item> items;
 };
 
-// Enqueues the export of the listed slots on the context's stream: the
-// export kernels, one copy per slot, the resident write-back of finished
-// clusters, then l.exp_ev.  l.h_ctl must hold the slots' current control
-// blocks.  Later work on the stream (uploads into a freed slot block)
-// comes after the copies.
-int export_begin(ba_ctx* c, Launcher& l, const std::vector<int>& slots, ExportJob& job) {
+// Enqueues the export of the listed slots: the export kernels, one copy per
+// slot, the resident write-back of finished clusters, then l.exp_ev.
+// l.h_ctl must hold the slots' current control blocks.  The work goes on
+// the context's stream with l's batch lists, or on st with bl's.  Later work
+// on that stream (uploads into a freed slot block) comes after the copies;
+// work on another stream that reuses a freed block must wait for l.exp_ev.
+int export_begin(ba_ctx* c, Launcher& l, const std::vector<int>& slots, ExportJob& job, Launcher* bl = nullptr,
+                 hipStream_t st = nullptr) {
   job.items.clear();
   if (slots.empty()) return BA_OK;
+  Launcher& bt = bl ? *bl : l;
+  if (!st) st = c->stream;
   Batch b;
-  int rc = make_batch(c, l, slots, b);
+  int rc = make_batch(c, bt, slots, b, st);
   if (rc) return rc;
   int maxP = 0;
   for (int s : slots) maxP = std::max(maxP, c->slots[s].desc.P);
-  HIPCHK(c, launch_export(b, maxP, c->stream));
+  HIPCHK(c, launch_export(b, maxP, st));
   std::vector<int> wb;
   for (int s : slots) {
     const Slot& sl = c->slots[s];
@@ -1051,23 +1061,23 @@ int export_begin(ba_ctx* c, Launcher& l, const std::vector<int>& slots, ExportJo
     it.buf = pin_get(c, bytes);
     if (!it.buf) it.buf = std::shared_ptr<char>(new char[bytes], std::default_delete<char[]>());
     HIPCHK(c, hipMemcpyAsync(it.buf.get(), c->arena_base + sl.off + sl.lay.cost_log, bytes, hipMemcpyDeviceToHost,
-                             c->stream));
+                             st));
     // finished resident clusters write their state back (once)
-    const int st = it.ctl.status;
-    if (t.resident && !t.res_done && is_finished(st)) {
+    const int status = it.ctl.status;
+    if (t.resident && !t.res_done && is_finished(status)) {
       it.res_finish = true;
-      if (st != ST_BAD_INIT) wb.push_back(s);
+      if (status != ST_BAD_INIT) wb.push_back(s);
     }
     job.items.push_back(std::move(it));
   }
   if (!wb.empty()) {
     Batch bw;
-    if ((rc = make_batch(c, l, wb, bw))) return rc;
+    if ((rc = make_batch(c, bt, wb, bw, st))) return rc;
     int maxR = 0;
     for (int s : wb) maxR = std::max({maxR, c->slots[s].desc.n_rout_cam, c->slots[s].desc.n_rout_pt});
-    HIPCHK(c, launch_writeback(bw, maxR, c->stream));
+    HIPCHK(c, launch_writeback(bw, maxR, st));
   }
-  HIPCHK(c, hipEventRecord(l.exp_ev, c->stream));
+  HIPCHK(c, hipEventRecord(l.exp_ev, st));
   return BA_OK;
 }
 
@@ -1129,12 +1139,17 @@ void free_slot(ba_ctx* c, int s) {
 // `serving_only`, only tickets handed to the serving loop are admitted.  A
 // ticket that waits for earlier clusters to write back resident state is
 // passed over (later tickets that do not depend on it go ahead).
-int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only, bool early = false) {
+int admit_queue(ba_ctx* c, std::vector<int>& admitted, bool serving_only, bool early = false,
+                hipEvent_t after = nullptr) {
   hipStream_t st = early ? c->up_stream : c->stream;
   bool any = false;
   for (auto it = c->queue.begin(); it != c->queue.end();) {
     Ticket& t = *c->tickets[*it];
     if (t.staging || (serving_only && !t.serving) || !deps_done(c, t)) { ++it; continue; }
+    if (after) {   // the uploads may go into blocks whose export `after` ends
+      HIPCHK(c, hipStreamWaitEvent(st, after, 0));
+      after = nullptr;
+    }
     int rc = admit_one(c, t, st);
     if (rc == BA_E_AGAIN) break;
     if (rc) return rc;
@@ -1208,16 +1223,17 @@ void serve_loop(ba_ctx* c) {
       c->cancel.clear();
       c->done_cv.notify_all();
     }
-    // retire: the export is enqueued and the finished slots are freed at
-    // once (uploads into their blocks come later on the stream); the next
-    // tick is launched before the host waits for the export's copies
+    // retire: the export is enqueued on up_stream, beside the next tick, and
+    // the finished slots are freed at once (uploads into their blocks come
+    // later on up_stream, or wait for the export); the next tick is launched
+    // before the host waits for the export's copies
     std::vector<int> fin;
     for (int s : active)
       if (is_finished(c->srv.h_ctl[s].status)) fin.push_back(s);
     ExportJob job;
     std::vector<ba_ticket> fin_t;
     if (!fin.empty()) {
-      if (export_begin(c, c->srv, fin, job)) break;
+      if (export_begin(c, c->srv, fin, job, &c->side, c->up_stream)) break;
       for (int s : fin) {
         fin_t.push_back(c->slots[s].ticket);
         free_slot(c, s);
@@ -1226,20 +1242,21 @@ void serve_loop(ba_ctx* c) {
                                   [&](int s) { return std::find(fin.begin(), fin.end(), s) != fin.end(); }),
                    active.end());
     }
-    // admit: the clusters uploaded during the last tick, then the queue
-    std::vector<int> adm;
+    // admit: the clusters uploaded and set up during the last tick, then the
+    // queue (uploaded and set up on the context's stream, after the export
+    // of a block they may reuse)
+    std::vector<int> fresh, adm;
     for (int s = 0; s < (int)c->slots.size(); ++s)
       if (c->slots[s].used && c->slots[s].early) {
         c->slots[s].early = false;
-        adm.push_back(s);
+        fresh.push_back(s);
       }
-    if (admit_queue(c, adm, true)) break;
-    if (!adm.empty()) {
-      if (start_slots(c, c->srv, adm)) break;
-      active.insert(active.end(), adm.begin(), adm.end());
-    }
+    if (admit_queue(c, adm, true, false, fin.empty() ? nullptr : c->srv.exp_ev)) break;
+    if (!adm.empty() && start_slots(c, c->srv, adm)) break;
+    fresh.insert(fresh.end(), adm.begin(), adm.end());
+    active.insert(active.end(), fresh.begin(), fresh.end());
     if (!active.empty()) {
-      if (run_tick(c, true, active, tick_iters(c, active, adm))) break;
+      if (run_tick(c, true, active, tick_iters(c, active, fresh))) break;
       if (hipMemcpyAsync(c->srv.h_ctl, c->d_ctl, sizeof(SlotCtl) * c->opt.max_slots, hipMemcpyDeviceToHost,
                          c->stream) ||
           hipEventRecord(c->srv.ev, c->stream)) {
@@ -1264,8 +1281,8 @@ void serve_loop(ba_ctx* c) {
       continue;
     }
     // Wait for the tick.  A cluster whose layout finishes meanwhile is
-    // admitted now, its upload running on up_stream beside the tick; it
-    // starts at the next boundary.  The event is polled with mu released
+    // admitted now, its upload and set-up running on up_stream beside the
+    // tick; it joins at the next boundary.  The event is polled with mu released
     // (submitters and layout threads take it meanwhile), so that the end of
     // the tick is seen within microseconds rather than after a timed sleep:
     // the device idles from there to the next tick's first launch.
@@ -1278,6 +1295,11 @@ void serve_loop(ba_ctx* c) {
         const size_t before = c->queue.size();
         std::vector<int> early;
         if (admit_queue(c, early, true, true)) { failed = true; break; }
+        if (!early.empty() &&
+            (start_slots(c, c->side, early, c->up_stream) || hipEventRecord(c->up_ev, c->up_stream) != hipSuccess)) {
+          failed = true;
+          break;
+        }
         if (c->queue.size() != before) early_pending = true;
       }
       lk.unlock();
@@ -1393,7 +1415,8 @@ int ba_create(const ba_options* opt, ba_ctx** out) {
   if (init_launcher(c.get(), c->api) || init_launcher(c.get(), c->srv)) return bail(BA_E_DEVICE);
   if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) return bail(BA_E_DEVICE);
   if (c->opt.serve && (hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking) != hipSuccess ||
-                       hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess))
+                       hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess ||
+                       init_launcher(c.get(), c->side)))
     return bail(BA_E_DEVICE);
   for (int p = 1; p < c->opt.batch_streams; ++p) {
     if (init_launcher(c.get(), c->api_p[p]) || init_launcher(c.get(), c->srv_p[p]) ||
@@ -1439,6 +1462,7 @@ int ba_destroy(ba_ctx* c) {
   if (c->up_ev) (void)hipEventDestroy(c->up_ev);
   if (c->up_stream) (void)hipStreamDestroy(c->up_stream);
   free_launcher(c, c->srv);
+  free_launcher(c, c->side);
   // the tickets' upload images go back to the pool before it is freed
   c->tickets.clear();
   c->stage_jobs.clear();
