@@ -533,14 +533,22 @@ std::shared_ptr<char> pin_get(ba_ctx* c, size_t bytes) {
   });
 }
 
+// Behind a cluster's upload image, at admission: the slot's descriptor and
+// initial control block, so that they too are copied from pinned memory
+// (an asynchronous copy; one from ordinary memory can hold the admitting
+// thread until the stream has drained).
+constexpr size_t kTailDesc = (sizeof(SlotDesc) + 63) / 64 * 64;
+constexpr size_t kTailBytes = 64 + kTailDesc + (sizeof(SlotCtl) + 63) / 64 * 64;
+size_t tail_off(size_t image_bytes) { return (image_bytes + 63) / 64 * 64; }
+
 // Packs the cluster's upload image: into pinned memory when the pool has
 // room (its upload at admission is then asynchronous), else into ordinary
 // memory.
 void pack_staged(ba_ctx* c, Staged& s, const Layout& lay) {
   std::shared_ptr<char> b;
-  if (lay.upload_end <= kPinnedPoolBytes / 4) b = pin_get(c, lay.upload_end);
+  if (lay.upload_end <= kPinnedPoolBytes / 4) b = pin_get(c, lay.upload_end + kTailBytes);
   s.blob_pinned = b != nullptr;
-  if (!b) b = std::shared_ptr<char>(new char[std::max<size_t>(lay.upload_end, 1)], std::default_delete<char[]>());
+  if (!b) b = std::shared_ptr<char>(new char[lay.upload_end + kTailBytes], std::default_delete<char[]>());
   pack_upload(s, lay, b.get());
   s.blob = std::move(b);
   s.blob_bytes = lay.upload_end;
@@ -842,9 +850,29 @@ int admit_one(ba_ctx* c, Ticket& t, hipStream_t st) {
   d.stat_part = (double*)(base + lay.stat_part);
   d.out = (double*)(base + lay.out);
   // the upload image in one copy: asynchronous from pinned memory (the buffer
-  // goes back to the pool once the copy has run), else waited for below
+  // goes back to the pool once the copies from it have run), else waited
+  // for below
   if (!s.blob) pack_staged(c, s, lay);
   if (s.blob_bytes) HIPCHK(c, hipMemcpyAsync(base, s.blob.get(), s.blob_bytes, hipMemcpyHostToDevice, st));
+  auto up2 = [&](size_t off, const std::vector<int2>& v) {
+    return v.empty() ? hipSuccess : hipMemcpyAsync(base + off, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, st);
+  };
+  HIPCHK(c, up2(lay.rin_cam, rin_c));
+  HIPCHK(c, up2(lay.rin_pt, rin_p));
+  if (!rout_c.empty())
+    HIPCHK(c, hipMemcpyAsync(base + lay.rout_cam, rout_c.data(), sizeof(int4) * rout_c.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(c, up2(lay.rout_pt, rout_p));
+  SlotCtl& ctl = sl.ctl0;
+  ctl = SlotCtl{};
+  ctl.k[0][0] = s.k[0];
+  ctl.k[0][1] = s.k[1];
+  ctl.k[0][2] = s.f;      // principal-point offsets start at 0
+  ctl.status = ST_RUNNING;
+  char* tail = s.blob.get() + tail_off(s.blob_bytes);
+  std::memcpy(tail, &d, sizeof(SlotDesc));
+  std::memcpy(tail + kTailDesc, &ctl, sizeof(SlotCtl));
+  HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, tail, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->d_ctl + slot, tail + kTailDesc, sizeof(SlotCtl), hipMemcpyHostToDevice, st));
   if (s.blob_pinned) {
     hipEvent_t ev = nullptr;
     {
@@ -859,22 +887,6 @@ int admit_one(ba_ctx* c, Ticket& t, hipStream_t st) {
     std::lock_guard<std::mutex> g(c->pin_mu);
     c->pin_flight.push_back({std::move(s.blob), ev});
   }
-  auto up2 = [&](size_t off, const std::vector<int2>& v) {
-    return v.empty() ? hipSuccess : hipMemcpyAsync(base + off, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, st);
-  };
-  HIPCHK(c, up2(lay.rin_cam, rin_c));
-  HIPCHK(c, up2(lay.rin_pt, rin_p));
-  if (!rout_c.empty())
-    HIPCHK(c, hipMemcpyAsync(base + lay.rout_cam, rout_c.data(), sizeof(int4) * rout_c.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(c, up2(lay.rout_pt, rout_p));
-  HIPCHK(c, hipMemcpyAsync(c->d_desc + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
-  SlotCtl& ctl = sl.ctl0;
-  ctl = SlotCtl{};
-  ctl.k[0][0] = s.k[0];
-  ctl.k[0][1] = s.k[1];
-  ctl.k[0][2] = s.f;      // principal-point offsets start at 0
-  ctl.status = ST_RUNNING;
-  HIPCHK(c, hipMemcpyAsync(c->d_ctl + slot, &ctl, sizeof(SlotCtl), hipMemcpyHostToDevice, st));
   // An image in ordinary memory must stay alive until its copy has run; the
   // small sources above live in the slot until it is freed.
   if (!s.blob_pinned) HIPCHK(c, hipStreamSynchronize(st));
