@@ -275,8 +275,9 @@ int ba_submit_cluster(ba_ctx* ctx, const ba_cluster* cluster, ba_ticket* ticket)
  * and laid out on up to 8 host threads at once, then queued in array order,
  * exactly as n calls of ba_submit_cluster in that order would (resident IDs
  * order them the same way).  Writes tickets [n].  A cluster that fails
- * validation fails the call before any is queued (BA_E_ARG, the message
- * names its index; every ticket 0).  A later error (BA_E_NOMEM: resident
+ * validation (with stage_threads > 0: the checks made at submission) fails
+ * the call before any is queued (BA_E_ARG, the message names its index;
+ * every ticket 0).  A later error (BA_E_NOMEM: resident
  * store full, BA_E_AGAIN: queue full, BA_E_DEVICE) leaves the clusters
  * before it queued with their tickets, and the rest with ticket 0. */
 int ba_submit_clusters(ba_ctx* ctx, int32_t n, const ba_cluster* clusters, ba_ticket* tickets);

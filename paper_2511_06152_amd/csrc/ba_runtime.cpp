@@ -1541,21 +1541,23 @@ int ba_submit_clusters(ba_ctx* c, int32_t n, const ba_cluster* cl, ba_ticket* ti
   if (!c || n < 0 || (n > 0 && (!cl || !tickets))) return BA_E_ARG;
   for (int i = 0; i < n; ++i) tickets[i] = 0;
   if (c->opt.stage_threads > 0) {   // background layout: queued in order, laid out by the pool
-    // the copies are made before mu is taken, up to the first cluster that
-    // fails its checks (the ones before it are queued, as one by one)
+    // a cluster that fails the checks made at submission fails the call
+    // before any is queued; the copies are made before mu is taken
+    for (int i = 0; i < n; ++i)
+      if (const char* why = copy_checks(&cl[i])) {
+        std::lock_guard<std::mutex> g(c->mu);
+        return fail(c, BA_E_ARG, "cluster " + std::to_string(i) + ": " + why);
+      }
     std::vector<std::unique_ptr<ClusterCopy>> copy(n);
-    const char* why = nullptr;
-    int n_ok = 0;
-    for (; n_ok < n && !(why = copy_checks(&cl[n_ok])); ++n_ok) copy[n_ok] = std::make_unique<ClusterCopy>(cl[n_ok]);
+    for (int i = 0; i < n; ++i) copy[i] = std::make_unique<ClusterCopy>(cl[i]);
     std::lock_guard<std::mutex> g(c->mu);
-    for (int i = 0; i < n_ok; ++i) {
+    for (int i = 0; i < n; ++i) {
       const int r = enqueue_copy(c, std::move(copy[i]), &tickets[i], t_submit);
       if (r) {
         c->last_error = "cluster " + std::to_string(i) + ": " + c->last_error;
         return r;
       }
     }
-    if (why) return fail(c, BA_E_ARG, "cluster " + std::to_string(n_ok) + ": " + why);
     return BA_OK;
   }
   std::vector<std::unique_ptr<Staged>> st(n);

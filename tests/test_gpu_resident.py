@@ -355,9 +355,12 @@ def test_batched_submit_equals_single():
         assert np.array_equal(a, g)
 
 
-def test_batched_submit_rejects_before_queueing():
+@pytest.mark.parametrize("stage_threads", [0, 2])
+def test_batched_submit_rejects_before_queueing(stage_threads):
     """One invalid cluster fails the whole call before any is queued: the
-    valid ones submitted afterwards run with no pending writers in the way."""
+    valid ones submitted afterwards run with no pending writers in the way.
+    With layout threads the duplicate ID is one of the checks made at
+    submission, before any cluster is copied or queued."""
     from paper_2511_06152_amd import BAError, Context
     from paper_2511_06152_amd.ba import Cluster
     cl = small_stream()["clusters"][:3]
@@ -365,7 +368,7 @@ def test_batched_submit_rejects_before_queueing():
     ids = bad["point_ids"].copy()
     ids[1] = ids[0]
     bad["point_ids"] = ids
-    with Context(precision=FP64) as ctx:
+    with Context(precision=FP64, stage_threads=stage_threads) as ctx:
         with pytest.raises(BAError) as e:
             ctx.ba_submit_clusters([Cluster(sc, max_iters=3, use_resident=True) for sc in (cl[0], bad, cl[2])])
         assert e.value.code == -1 and "cluster 1" in str(e.value)
