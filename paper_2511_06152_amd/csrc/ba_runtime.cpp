@@ -335,7 +335,7 @@ struct Ticket {
 
 struct Slot {
   bool used = false;
-  bool early = false;        // admitted during a tick: uploaded on up_stream, started at the next boundary
+  bool early = false;        // admitted during a tick: uploaded and set up on up_stream, joins at the next boundary
   ba_ticket ticket = 0;
   size_t off = 0, bytes = 0;
   Layout lay{};
@@ -395,8 +395,9 @@ struct ba_ctx {
   static constexpr int kMaxParts = 4;
   Launcher api_p[kMaxParts], srv_p[kMaxParts];   // [0] unused
   hipStream_t stream_p[kMaxParts] = {};           // [0] unused
-  // serving loop: clusters admitted while a tick runs upload on their own
-  // stream (up_ev after the last such upload) and join at the next boundary
+  // serving loop: clusters admitted while a tick runs are uploaded and set
+  // up on their own stream (up_ev after the last of that work) and join at
+  // the next boundary; exports of finished clusters run there too
   hipStream_t up_stream = nullptr;
   hipEvent_t up_ev = nullptr;
   // batch lists of the serving loop's work on up_stream: the set-up of
